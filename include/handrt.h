@@ -1,0 +1,186 @@
+/*
+ * handrt — differentiable Monte Carlo ray tracing of a skinned hand into many
+ * calibrated views, for render-and-compare refinement (Karvounas et al.,
+ * "Multiview Image-based Hand Geometry Refinement using Differentiable Monte
+ * Carlo Ray Tracing", BMVC 2021).  C ABI over hand-written HIP kernels for
+ * gfx950 (MI355X).
+ *
+ * The calls follow the paper's problem statement (Section 3): given calibrated
+ * views {O_i, C_i} and hand parameters h, an iteration is
+ *   hr_skin     h -> mesh vertices (the decoders G_v, G_J, Section 3.1)
+ *   hr_render   vertices, colour map, cameras -> images R(G_v(h), V, C_i)
+ *               (Monte Carlo pixel integrals, Section 3 "Method" and Eq. 3)
+ *   hr_loss     E1 = sum_i mean |O_i - R_i| and dE1/dR (Eq. 3 and D_c of Eq. 4)
+ *   hr_backward dE1/dh and dE1/d(colour map): derivative of the estimate at
+ *               fixed samples plus the silhouette-edge (visibility) term
+ *               sampled along edges (Section 4.2.2)
+ *   hr_step     one Adam step (Section 3.3)
+ *
+ * Conventions shared by every call
+ *  - Pointers named *_host are host memory; every other array pointer is
+ *    device memory owned by the caller, contiguous, float32 unless stated.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls only enqueue
+ *    work on `stream` and return; results are valid once the stream reaches
+ *    them.  No call synchronises the stream or allocates device memory, except
+ *    hr_scene_create (allocates the scene's buffers) and hr_scene_destroy.
+ *  - A scene's internal buffers (normals, acceleration structure, edge tables,
+ *    gradient accumulators) are shared by all calls on that scene: calls on
+ *    one scene must be ordered (one stream, or explicit events).
+ *  - Return value: HR_OK (0) or a negative HR_E* code; the message of the last
+ *    error on the calling thread is in hr_last_error().  On error nothing has
+ *    been enqueued unless the code is HR_EHIP (a HIP launch/runtime failure).
+ *
+ * Packed-view layout: views are numbered 0..n_views-1; view v has W_v x H_v
+ * pixels stored row-major starting at pixel offset pix_off[v] = sum_{u<v} W_u H_u.
+ * Images are [n_pixels, 3] float32 (RGB), masks [n_pixels] uint8.
+ *
+ * Parameter block of one hand (64 float32): [0:48] axis-angle rotations of the
+ * 16 joints (joint 0 is the root), [48:58] shape coefficients, [58:61] global
+ * rotation (axis-angle), [61:64] global translation (metres).
+ */
+#ifndef HANDRT_H
+#define HANDRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HR_OK 0
+#define HR_EINVAL (-1)       /* null pointer, bad count or option */
+#define HR_ESHAPE (-2)       /* sizes inconsistent with the scene */
+#define HR_EHIP (-4)         /* HIP runtime / launch failure */
+#define HR_EUNSUPPORTED (-5) /* outside the supported range (see the call) */
+
+/* backward flags */
+#define HR_GRAD_INTERIOR 1u     /* derivative of the estimate at fixed samples */
+#define HR_GRAD_EDGES 2u        /* silhouette-edge (visibility) term */
+#define HR_GRAD_ALL 3u
+#define HR_REUSE_GEOMETRY 4u    /* normals/BVH already prepared from `verts`
+                                   by the previous hr_render on this scene */
+
+typedef struct hr_scene hr_scene;
+
+/* Hand model and mesh topology, HOST pointers, copied by hr_scene_create.
+   Sizes: V vertices, F triangles, J joints (parents[j] < j, parents[0] = -1),
+   K shape directions, E edges.  faces are wound counter-clockwise seen from
+   outside; edges[e] = (a,b) appears as a->b in face edge_faces[e][0] and as
+   b->a in edge_faces[e][1] (-1 for a boundary edge). */
+typedef struct {
+    int32_t n_verts, n_faces, n_joints, n_shape, n_edges;
+    const float* v_template;   /* [V,3] rest-pose vertices (metres) */
+    const float* shapedirs;    /* [V,3,K] shape displacement per coefficient */
+    const float* j_regressor;  /* [J,V] joint = sum_v J[j,v] shaped vertex */
+    const float* weights;      /* [V,J] skinning weights, rows sum to 1 */
+    const int32_t* parents;    /* [J] */
+    const int32_t* faces;      /* [F,3] */
+    const float* uv;           /* [V,2] texture coordinates in [0,1] */
+    const int32_t* edges;      /* [E,2] */
+    const int32_t* edge_faces; /* [E,2] */
+} hr_mesh_desc;
+
+/* Pinhole camera: a world point x maps to camera coordinates R (x - o)
+   (R row-major, rows = right, down, forward) and to pixel coordinates
+   (fx X/Z + cx, fy Y/Z + cy); pixel (i,j) covers [j,j+1) x [i,i+1). */
+typedef struct {
+    float R[9];
+    float o[3];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+    int32_t hand;   /* which hand of the batch this view observes */
+} hr_camera;
+
+/* Estimator configuration (fixed for a scene). */
+typedef struct {
+    float ka, kd;        /* colour = albedo(uv) * (ka + kd max(0, n.l)) */
+    float light[3];      /* unit direction towards the light, world frame */
+    int32_t spp;         /* camera samples per pixel, 1..256 */
+    float edge_delta;    /* side-ray offset of an edge sample, pixels (> 0) */
+    int32_t tex_h, tex_w;/* colour map size (texels) */
+    uint64_t seed;       /* Philox key of all sample streams */
+} hr_config;
+
+/* Adam hyper-parameters.  Learning rates per parameter group; 0 freezes a
+   group (its parameters and moments are left untouched). */
+typedef struct {
+    float lr_pose_root;  /* params [0:3]   */
+    float lr_pose;       /* params [3:48]  */
+    float lr_shape;      /* params [48:58] */
+    float lr_rot;        /* params [58:61] */
+    float lr_trans;      /* params [61:64] */
+    float lr_albedo;     /* colour map; clamped to [0,1] after the step */
+    float beta1, beta2, eps;
+} hr_adam_config;
+
+/* Create a scene for n_hands hands of the same model seen by n_views cameras
+   (cams_host[v].hand in [0,n_hands)).  Allocates device buffers on the current
+   HIP device; the scene may only be used on that device.
+   HR_EUNSUPPORTED: V > 4096, F > 8192, J > 32, K > 16, a view larger than
+   4096 x 4096, spp outside 1..256. */
+int hr_scene_create(hr_scene** out, const hr_mesh_desc* mesh_host, int32_t n_hands,
+                    const hr_camera* cams_host, int32_t n_views, const hr_config* cfg);
+void hr_scene_destroy(hr_scene* scene);
+
+/* Number of pixels over all views (length of packed image buffers). */
+int64_t hr_num_pixels(const hr_scene* scene);
+
+/* Skinning (Section 3.1 "Geometry"): shape blend, joint regression, Rodrigues
+   rotations, forward kinematics along the joint tree, linear blend of joint
+   transforms, global rotation and translation.
+   params [n_hands,64] -> verts [n_hands,V,3], joints [n_hands,J,3] (nullable). */
+int hr_skin(hr_scene* scene, const float* params, float* verts, float* joints, void* stream);
+
+/* Render all views: pixel = (1/spp) sum over samples of the colour of the
+   first surface hit by the ray through a uniformly drawn point of the pixel,
+   or the pixel's background colour (Section 3, Eq. 3).  Also prepares the
+   scene's per-iteration geometry (vertex normals, acceleration structure,
+   per-view screen bounds) from `verts`.
+   verts [n_hands,V,3]; albedo [n_hands,tex_h,tex_w,3]; background [P,3];
+   iter selects the sample streams; image [P,3] out;
+   hit_face [P,spp] int32 out (nullable): first-hit triangle of every sample,
+   -1 for a miss. */
+int hr_render(hr_scene* scene, const float* verts, const float* albedo, const float* background,
+              uint32_t iter, float* image, int32_t* hit_face, void* stream);
+
+/* Photometric loss, per hand: E1 = sum over the hand's views of the mean of
+   |image - target| over the view's masked pixels and the 3 channels
+   (Eq. 3 with D_c of Eq. 4); dimage = dE1/dimage = sign(image - target) /
+   (3 * masked pixel count of the view) on masked pixels, 0 elsewhere.
+   mask [P] uint8 (nullable = all pixels); loss [n_hands] out; dimage [P,3] out. */
+int hr_loss(hr_scene* scene, const float* image, const float* target, const uint8_t* mask,
+            float* loss, float* dimage, void* stream);
+
+/* Gradient of L = sum_p dimage[p] . image[p] (with the samples of hr_render
+   at the same iter) with respect to the hand parameters and the colour map.
+   flags: HR_GRAD_* terms to include, plus HR_REUSE_GEOMETRY.
+   grad_params [n_hands,64] out; grad_albedo [n_hands,tex_h,tex_w,3] out;
+   grad_verts [n_hands,V,3] out (nullable): dL/dvertex before skinning
+   backward, all terms; grad_normals [n_hands,V,3] out (nullable): dL/d(unit
+   vertex normal) of the interior term.  Outputs are overwritten. */
+int hr_backward(hr_scene* scene, const float* params, const float* verts, const float* albedo,
+                const float* background, const float* dimage, uint32_t iter, uint32_t flags,
+                float* grad_params, float* grad_albedo, float* grad_verts, float* grad_normals,
+                void* stream);
+
+/* One Adam step (t >= 1 counts steps) on params [n_hands,64] and albedo
+   [n_hands,tex_h,tex_w,3] in place, with moments m_*, v_* (same shapes,
+   caller-owned, zero before the first step). */
+int hr_step(hr_scene* scene, float* params, float* albedo, const float* grad_params,
+            const float* grad_albedo, float* m_params, float* v_params, float* m_albedo,
+            float* v_albedo, int32_t t, const hr_adam_config* cfg, void* stream);
+
+/* Diagnostics of the last backward call on this scene, copied to HOST memory
+   after synchronising `stream`: per view the total quantised silhouette
+   length (uint64, 1/256 px) and the number of edge samples drawn.
+   total_host [n_views] u64 out, budget_host [n_views] i64 out. */
+int hr_edge_stats(hr_scene* scene, uint64_t* total_host, int64_t* budget_host, void* stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* hr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HANDRT_H */

@@ -661,6 +661,7 @@ static void view_edges(const cam_t* c, const float* v32, const int32_t* faces, i
         if (!clip32(ax, ay, bx, by, (float)c->W, (float)c->H, &t0, &t1)) continue;
         float dx = bx - ax, dy = by - ay;
         float len = sqrtf(dx * dx + dy * dy);
+        if (!(len > 0.0f)) continue;   /* projects to a point: no boundary */
         float ell = len * (t1 - t0);
         float q = floorf(ell * 256.0f);
         uint32_t w = q >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)q;

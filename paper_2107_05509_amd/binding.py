@@ -1,0 +1,219 @@
+"""Thin ctypes binding of the handrt C ABI (include/handrt.h).
+
+Argument marshalling only: every step runs in the HIP kernels of libhandrt.so.
+Tensors are torch CUDA tensors (float32 unless stated, contiguous); work is
+enqueued on torch's current stream.  If the library is not built, importing
+this module works but any call raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhandrt.so")
+
+HR_GRAD_INTERIOR = 1
+HR_GRAD_EDGES = 2
+HR_GRAD_ALL = 3
+HR_REUSE_GEOMETRY = 4
+
+EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_render", "hr_loss",
+           "hr_backward", "hr_step", "hr_edge_stats", "hr_last_error")
+
+
+class HRError(RuntimeError):
+    pass
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("n_faces", ctypes.c_int32), ("n_joints", ctypes.c_int32),
+                ("n_shape", ctypes.c_int32), ("n_edges", ctypes.c_int32),
+                ("v_template", ctypes.c_void_p), ("shapedirs", ctypes.c_void_p),
+                ("j_regressor", ctypes.c_void_p), ("weights", ctypes.c_void_p), ("parents", ctypes.c_void_p),
+                ("faces", ctypes.c_void_p), ("uv", ctypes.c_void_p), ("edges", ctypes.c_void_p),
+                ("edge_faces", ctypes.c_void_p)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("o", ctypes.c_float * 3), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("W", ctypes.c_int32), ("H", ctypes.c_int32), ("hand", ctypes.c_int32)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("ka", ctypes.c_float), ("kd", ctypes.c_float), ("light", ctypes.c_float * 3),
+                ("spp", ctypes.c_int32), ("edge_delta", ctypes.c_float), ("tex_h", ctypes.c_int32),
+                ("tex_w", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class AdamConfig(ctypes.Structure):
+    _fields_ = [("lr_pose_root", ctypes.c_float), ("lr_pose", ctypes.c_float), ("lr_shape", ctypes.c_float),
+                ("lr_rot", ctypes.c_float), ("lr_trans", ctypes.c_float), ("lr_albedo", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HRError(f"handrt library not built: {LIB_PATH} is missing "
+                          "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+        L.hr_scene_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(MeshDesc), i32, ctypes.POINTER(Camera),
+                                      i32, ctypes.POINTER(Config)]
+        L.hr_scene_destroy.argtypes = [vp]
+        L.hr_scene_destroy.restype = None
+        L.hr_num_pixels.argtypes = [vp]
+        L.hr_num_pixels.restype = ctypes.c_int64
+        L.hr_skin.argtypes = [vp, vp, vp, vp, vp]
+        L.hr_render.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp]
+        L.hr_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
+        L.hr_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(AdamConfig), vp]
+        L.hr_edge_stats.argtypes = [vp, vp, vp, vp]
+        L.hr_last_error.restype = ctypes.c_char_p
+        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step",
+                     "hr_edge_stats"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        msg = lib().hr_last_error().decode()
+        raise HRError(f"{what} failed ({rc}): {msg}")
+
+
+def _ptr(t, dtype=torch.float32, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise HRError(f"{name}: expected a CUDA tensor")
+    if t.dtype != dtype:
+        raise HRError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise HRError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise HRError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Scene:
+    """A handrt scene: hand model + cameras + estimator configuration."""
+
+    def __init__(self, model, cams, n_hands, spp, tex_h, tex_w, seed=0, shading=None, edge_delta=1e-3):
+        from . import scene as _scene
+        shading = _scene.SHADING if shading is None else shading
+        self._keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            self._keep.append(a)
+            return a.ctypes.data_as(ctypes.c_void_p)
+
+        md = MeshDesc()
+        md.n_verts, md.n_faces = model.n_verts, model.n_faces
+        md.n_joints, md.n_shape, md.n_edges = model.j_regressor.shape[0], model.shapedirs.shape[2], model.n_edges
+        md.v_template = arr(model.v_template, np.float32)
+        md.shapedirs = arr(model.shapedirs, np.float32)
+        md.j_regressor = arr(model.j_regressor, np.float32)
+        md.weights = arr(model.weights, np.float32)
+        md.parents = arr(model.parents, np.int32)
+        md.faces = arr(model.faces, np.int32)
+        md.uv = arr(model.uv, np.float32)
+        md.edges = arr(model.edges, np.int32)
+        md.edge_faces = arr(model.edge_faces, np.int32)
+        cam_arr = (Camera * len(cams))()
+        tables = _scene.camera_arrays(cams)
+        for i, c in enumerate(cams):
+            cam_arr[i].R[:] = [float(x) for x in tables["R"][i]]
+            cam_arr[i].o[:] = [float(x) for x in tables["o"][i]]
+            cam_arr[i].fx, cam_arr[i].fy, cam_arr[i].cx, cam_arr[i].cy = [float(x) for x in tables["intr"][i]]
+            cam_arr[i].W, cam_arr[i].H = int(c.W), int(c.H)
+            cam_arr[i].hand = int(c.hand)
+        cfg = Config()
+        cfg.ka, cfg.kd = float(shading[0]), float(shading[1])
+        cfg.light[:] = [float(x) for x in shading[2:5]]
+        cfg.spp, cfg.edge_delta = int(spp), float(edge_delta)
+        cfg.tex_h, cfg.tex_w, cfg.seed = int(tex_h), int(tex_w), int(seed)
+        h = ctypes.c_void_p()
+        _check(lib().hr_scene_create(ctypes.byref(h), ctypes.byref(md), int(n_hands), cam_arr, len(cams),
+                                     ctypes.byref(cfg)), "hr_scene_create")
+        self._h = h
+        self._keep = []
+        self.n_hands, self.n_views = int(n_hands), len(cams)
+        self.V, self.F, self.J = model.n_verts, model.n_faces, model.j_regressor.shape[0]
+        self.spp, self.tex_h, self.tex_w = int(spp), int(tex_h), int(tex_w)
+        self.P = int(lib().hr_num_pixels(h))
+        self.pix_off = tables["pix_off"]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hr_scene_destroy(h)
+            self._h = None
+
+    # -- calls ---------------------------------------------------------------
+    def skin(self, params, verts, joints=None):
+        _check(lib().hr_skin(self._h, _ptr(params, shape=(self.n_hands, 64), name="params"),
+                             _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),
+                             _ptr(joints, shape=(self.n_hands, self.J, 3), name="joints"), _stream()), "hr_skin")
+
+    def render(self, verts, albedo, background, it, image, hit_face=None):
+        _check(lib().hr_render(self._h, _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),
+                               _ptr(albedo, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="albedo"),
+                               _ptr(background, shape=(self.P, 3), name="background"), int(it),
+                               _ptr(image, shape=(self.P, 3), name="image"),
+                               _ptr(hit_face, torch.int32, (self.P, self.spp), "hit_face"), _stream()), "hr_render")
+
+    def loss(self, image, target, mask, loss, dimage):
+        _check(lib().hr_loss(self._h, _ptr(image, shape=(self.P, 3), name="image"),
+                             _ptr(target, shape=(self.P, 3), name="target"),
+                             _ptr(mask, torch.uint8, (self.P,), "mask"),
+                             _ptr(loss, shape=(self.n_hands,), name="loss"),
+                             _ptr(dimage, shape=(self.P, 3), name="dimage"), _stream()), "hr_loss")
+
+    def backward(self, params, verts, albedo, background, dimage, it, grad_params, grad_albedo,
+                 grad_verts=None, grad_normals=None, flags=HR_GRAD_ALL):
+        _check(lib().hr_backward(
+            self._h, _ptr(params, shape=(self.n_hands, 64), name="params"),
+            _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),
+            _ptr(albedo, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="albedo"),
+            _ptr(background, shape=(self.P, 3), name="background"), _ptr(dimage, shape=(self.P, 3), name="dimage"),
+            int(it), int(flags), _ptr(grad_params, shape=(self.n_hands, 64), name="grad_params"),
+            _ptr(grad_albedo, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="grad_albedo"),
+            _ptr(grad_verts, shape=(self.n_hands, self.V, 3), name="grad_verts"),
+            _ptr(grad_normals, shape=(self.n_hands, self.V, 3), name="grad_normals"), _stream()), "hr_backward")
+
+    def step(self, params, albedo, grad_params, grad_albedo, m_p, v_p, m_a, v_a, t, lrs, betas=(0.9, 0.999),
+             eps=1e-8):
+        c = AdamConfig()
+        (c.lr_pose_root, c.lr_pose, c.lr_shape, c.lr_rot, c.lr_trans, c.lr_albedo) = [float(x) for x in lrs]
+        c.beta1, c.beta2, c.eps = float(betas[0]), float(betas[1]), float(eps)
+        shp_p, shp_a = (self.n_hands, 64), (self.n_hands, self.tex_h, self.tex_w, 3)
+        _check(lib().hr_step(self._h, _ptr(params, shape=shp_p, name="params"),
+                             _ptr(albedo, shape=shp_a, name="albedo"), _ptr(grad_params, shape=shp_p, name="gp"),
+                             _ptr(grad_albedo, shape=shp_a, name="ga"), _ptr(m_p, shape=shp_p, name="m_p"),
+                             _ptr(v_p, shape=shp_p, name="v_p"), _ptr(m_a, shape=shp_a, name="m_a"),
+                             _ptr(v_a, shape=shp_a, name="v_a"), int(t), ctypes.byref(c), _stream()), "hr_step")
+
+    def edge_stats(self):
+        tot = np.zeros(self.n_views, dtype=np.uint64)
+        bud = np.zeros(self.n_views, dtype=np.int64)
+        _check(lib().hr_edge_stats(self._h, tot.ctypes.data_as(ctypes.c_void_p),
+                                   bud.ctypes.data_as(ctypes.c_void_p), _stream()), "hr_edge_stats")
+        return tot, bud

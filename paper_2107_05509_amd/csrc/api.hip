@@ -1,0 +1,490 @@
+// C ABI of the handrt library (include/handrt.h): scene set-up on the host
+// (topology tables, bounding-volume hierarchy topology, work lists) and the
+// per-iteration launch sequences.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/handrt.h"
+#include "kernels.hip"
+
+using namespace hr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HR_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return HR_OK;
+}
+
+template <class T>
+int dev_upload(T** dst, const T* src, size_t n)
+{
+    *dst = nullptr;
+    if (n == 0) return HR_OK;
+    hipError_t e = hipMalloc((void**)dst, sizeof(T) * n);
+    if (e != hipSuccess) return fail(HR_EHIP, "hipMalloc(%zu): %s", sizeof(T) * n, hipGetErrorString(e));
+    if (src) {
+        e = hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(HR_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    return HR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// bounding-volume hierarchy topology (built once on the host from the rest
+// pose; bounds are refit on the device every iteration)
+// ---------------------------------------------------------------------------
+
+struct HostBvh {
+    std::vector<int> child;      // [n,2]
+    std::vector<int> perm;       // [F]
+    std::vector<int> order, level_off;
+    int depth = 0;
+};
+
+int leaf_code(int start, int count) { return ~((start << 3) | count); }
+
+int build_rec(HostBvh& b, std::vector<int>& idx, const std::vector<float>& cen, int lo, int hi, int depth)
+{
+    b.depth = std::max(b.depth, depth);
+    const int node = (int)b.child.size() / 2;
+    b.child.push_back(0);
+    b.child.push_back(0);
+    const int mid = (lo + hi) / 2;
+    float mn[3] = {1e30f, 1e30f, 1e30f}, mx[3] = {-1e30f, -1e30f, -1e30f};
+    for (int i = lo; i < hi; ++i)
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = std::min(mn[k], cen[3 * idx[i] + k]);
+            mx[k] = std::max(mx[k], cen[3 * idx[i] + k]);
+        }
+    int axis = 0;
+    for (int k = 1; k < 3; ++k)
+        if (mx[k] - mn[k] > mx[axis] - mn[axis]) axis = k;
+    std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi,
+                     [&](int a, int c) { return cen[3 * a + axis] < cen[3 * c + axis]; });
+    const int ranges[2][2] = {{lo, mid}, {mid, hi}};
+    for (int c = 0; c < 2; ++c) {
+        const int a = ranges[c][0], e = ranges[c][1];
+        int code;
+        if (e - a <= kLeafMax) code = leaf_code(a, e - a);
+        else code = build_rec(b, idx, cen, a, e, depth + 1);
+        b.child[2 * node + c] = code;
+    }
+    return node;
+}
+
+HostBvh build_bvh(const float* verts, const int* faces, int F)
+{
+    HostBvh b;
+    std::vector<float> cen(3 * F);
+    for (int f = 0; f < F; ++f)
+        for (int k = 0; k < 3; ++k)
+            cen[3 * f + k] = (verts[3 * faces[3 * f] + k] + verts[3 * faces[3 * f + 1] + k] +
+                              verts[3 * faces[3 * f + 2] + k]) / 3.0f;
+    std::vector<int> idx(F);
+    std::iota(idx.begin(), idx.end(), 0);
+    if (F <= kLeafMax) {
+        b.child = {leaf_code(0, F), leaf_code(0, 0)};
+    } else {
+        build_rec(b, idx, cen, 0, F, 1);
+    }
+    b.perm = idx;
+    const int n = (int)b.child.size() / 2;
+    // heights: leaves 0; a node is refit after all its children
+    std::vector<int> height(n, 0);
+    for (int i = n - 1; i >= 0; --i) {   // children have larger indices (preorder)
+        int h = 1;
+        for (int c = 0; c < 2; ++c) {
+            int code = b.child[2 * i + c];
+            if (code >= 0) h = std::max(h, height[code] + 1);
+        }
+        height[i] = h;
+    }
+    int maxh = *std::max_element(height.begin(), height.end());
+    b.level_off.assign(maxh + 1, 0);
+    for (int L = 1; L <= maxh; ++L) {
+        for (int i = 0; i < n; ++i)
+            if (height[i] == L) b.order.push_back(i);
+        b.level_off[L] = (int)b.order.size();
+    }
+    return b;
+}
+
+}  // namespace
+
+struct hr_scene {
+    int device = 0;
+    int n_hands = 0, n_views = 0;
+    int V = 0, F = 0, J = 0, K = 0, E = 0;
+    long long n_pixels = 0;
+    hr_config cfg{};
+    MeshDev mesh{};
+    BvhDev bvh{};
+    int bvh_depth = 0;
+    std::vector<void*> allocs;
+    ViewDev* views = nullptr;
+    std::vector<ViewDev> views_host;
+    int2* work = nullptr;
+    int n_work = 0;
+    int2* chunks = nullptr;
+    int n_chunks = 0;
+    int* view_chunk_off = nullptr;
+    int* hand_view_off = nullptr;
+    int* hand_views = nullptr;
+    int4* bounds = nullptr;
+    float* normals = nullptr;
+    Tri* tris = nullptr;
+    Node* nodes = nullptr;
+    float* gacc = nullptr;
+    float* loss_partial = nullptr;
+    float* view_scale = nullptr;
+    EdgeRec* edge_rec = nullptr;
+    unsigned long long* edge_cdf = nullptr;
+    unsigned long long* edge_total = nullptr;
+    long long* edge_budget = nullptr;
+    size_t smem_prepare = 0, smem_skin = 0, smem_geom_bwd = 0, smem_adjoint = 0;
+
+    template <class T>
+    int upload(T** dst, const T* src, size_t n)
+    {
+        int rc = dev_upload(dst, src, n);
+        if (*dst) allocs.push_back((void*)*dst);
+        return rc;
+    }
+};
+
+extern "C" {
+
+const char* hr_last_error(void) { return g_err.c_str(); }
+
+void hr_scene_destroy(hr_scene* s)
+{
+    if (!s) return;
+    for (void* p : s->allocs) (void)hipFree(p);
+    delete s;
+}
+
+int64_t hr_num_pixels(const hr_scene* s) { return s ? s->n_pixels : -1; }
+
+int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, const hr_camera* cams,
+                    int32_t n_views, const hr_config* cfg)
+{
+    if (!out || !m || !cams || !cfg) return fail(HR_EINVAL, "hr_scene_create: null argument");
+    *out = nullptr;
+    if (n_hands < 1 || n_views < 1) return fail(HR_EINVAL, "hr_scene_create: need >= 1 hand and view");
+    if (!m->v_template || !m->shapedirs || !m->j_regressor || !m->weights || !m->parents || !m->faces ||
+        !m->uv || !m->edges || !m->edge_faces)
+        return fail(HR_EINVAL, "hr_scene_create: null mesh array");
+    const int V = m->n_verts, F = m->n_faces, J = m->n_joints, K = m->n_shape, E = m->n_edges;
+    if (V < 3 || F < 1 || J < 1 || K < 0 || E < 3) return fail(HR_EINVAL, "hr_scene_create: bad mesh sizes");
+    if (V > 4096 || F > 8192 || J > kMaxJoints || K > 16)
+        return fail(HR_EUNSUPPORTED, "hr_scene_create: mesh too large (V<=4096, F<=8192, J<=32, K<=16)");
+    if (cfg->spp < 1 || cfg->spp > 256) return fail(HR_EUNSUPPORTED, "hr_scene_create: spp must be 1..256");
+    if (cfg->tex_h < 1 || cfg->tex_w < 1) return fail(HR_EINVAL, "hr_scene_create: bad texture size");
+    if (!(cfg->edge_delta > 0.0f)) return fail(HR_EINVAL, "hr_scene_create: edge_delta must be > 0");
+    for (int f = 0; f < 3 * F; ++f)
+        if (m->faces[f] < 0 || m->faces[f] >= V) return fail(HR_EINVAL, "hr_scene_create: face index out of range");
+    for (int e = 0; e < E; ++e) {
+        if (m->edges[2 * e] < 0 || m->edges[2 * e] >= V || m->edges[2 * e + 1] < 0 || m->edges[2 * e + 1] >= V)
+            return fail(HR_EINVAL, "hr_scene_create: edge vertex out of range");
+        if (m->edge_faces[2 * e] < 0 || m->edge_faces[2 * e] >= F || m->edge_faces[2 * e + 1] >= F)
+            return fail(HR_EINVAL, "hr_scene_create: edge face out of range");
+    }
+    for (int j = 0; j < J; ++j)
+        if (m->parents[j] >= j || (j > 0 && m->parents[j] < 0) || (j == 0 && m->parents[0] >= 0))
+            return fail(HR_EINVAL, "hr_scene_create: parents must satisfy parents[0] < 0 <= parents[j] < j");
+    for (int v = 0; v < n_views; ++v) {
+        const hr_camera& c = cams[v];
+        if (c.hand < 0 || c.hand >= n_hands) return fail(HR_EINVAL, "hr_scene_create: camera %d: bad hand", v);
+        if (c.W < 1 || c.H < 1) return fail(HR_EINVAL, "hr_scene_create: camera %d: bad size", v);
+        if (c.W > 4096 || c.H > 4096) return fail(HR_EUNSUPPORTED, "hr_scene_create: camera %d larger than 4096", v);
+        if (!(c.fx > 0.0f) || !(c.fy > 0.0f)) return fail(HR_EINVAL, "hr_scene_create: camera %d: bad focal", v);
+    }
+
+    hr_scene* s = new hr_scene();
+    s->n_hands = n_hands;
+    s->n_views = n_views;
+    s->V = V; s->F = F; s->J = J; s->K = K; s->E = E;
+    s->cfg = *cfg;
+    (void)hipGetDevice(&s->device);
+    int rc = HR_OK;
+#define TRY(x) do { rc = (x); if (rc != HR_OK) { hr_scene_destroy(s); return rc; } } while (0)
+    // mesh tables
+    MeshDev& md = s->mesh;
+    md.V = V; md.F = F; md.J = J; md.K = K; md.E = E;
+    {
+        float* p;
+        TRY(s->upload(&p, m->v_template, 3 * (size_t)V)); md.v_template = p;
+        TRY(s->upload(&p, m->shapedirs, 3 * (size_t)V * std::max(K, 1))); md.shapedirs = p;
+        TRY(s->upload(&p, m->j_regressor, (size_t)J * V)); md.j_regressor = p;
+        TRY(s->upload(&p, m->weights, (size_t)V * J)); md.weights = p;
+        TRY(s->upload(&p, m->uv, 2 * (size_t)V)); md.uv = p;
+        int* q;
+        TRY(s->upload(&q, m->parents, (size_t)J)); md.parents = q;
+        TRY(s->upload(&q, m->faces, 3 * (size_t)F)); md.faces = q;
+        TRY(s->upload(&q, m->edges, 2 * (size_t)E)); md.edges = q;
+        TRY(s->upload(&q, m->edge_faces, 2 * (size_t)E)); md.edge_faces = q;
+        std::vector<int> off(V + 1, 0), cnt(V, 0), flat(3 * F);
+        for (int i = 0; i < 3 * F; ++i) off[m->faces[i] + 1]++;
+        for (int v = 0; v < V; ++v) off[v + 1] += off[v];
+        for (int f = 0; f < F; ++f)
+            for (int k = 0; k < 3; ++k) {
+                int v = m->faces[3 * f + k];
+                flat[off[v] + cnt[v]++] = f;
+            }
+        TRY(s->upload(&q, off.data(), off.size())); md.vf_off = q;
+        TRY(s->upload(&q, flat.data(), flat.size())); md.vf_faces = q;
+    }
+    // hierarchy topology from the rest pose
+    {
+        HostBvh hb = build_bvh(m->v_template, m->faces, F);
+        if (hb.depth + 1 > kMaxStack) {
+            hr_scene_destroy(s);
+            return fail(HR_EUNSUPPORTED, "hr_scene_create: hierarchy too deep (%d)", hb.depth);
+        }
+        s->bvh_depth = hb.depth;
+        BvhDev& b = s->bvh;
+        b.n_nodes = (int)hb.child.size() / 2;
+        b.n_levels = (int)hb.level_off.size() - 1;
+        int* q;
+        TRY(s->upload(&q, hb.child.data(), hb.child.size())); b.child = q;
+        TRY(s->upload(&q, hb.perm.data(), hb.perm.size())); b.perm = q;
+        TRY(s->upload(&q, hb.order.data(), hb.order.size())); b.order = q;
+        TRY(s->upload(&q, hb.level_off.data(), hb.level_off.size())); b.level_off = q;
+    }
+    // views, work lists
+    {
+        std::vector<int2> work, chunks;
+        std::vector<int> vco(1, 0);
+        long long pix = 0;
+        for (int v = 0; v < n_views; ++v) {
+            const hr_camera& c = cams[v];
+            ViewDev d;
+            memcpy(d.R, c.R, sizeof(d.R));
+            memcpy(d.o, c.o, sizeof(d.o));
+            d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+            d.W = c.W; d.H = c.H; d.hand = c.hand;
+            d.bx = (c.W + kBlockPix - 1) / kBlockPix;
+            d.pix0 = pix;
+            const int by = (c.H + kBlockPix - 1) / kBlockPix;
+            for (int i = 0; i < d.bx * by; ++i) work.push_back(make_int2(v, i));
+            const long long np = (long long)c.W * c.H;
+            for (long long p0 = 0; p0 < np; p0 += kLossChunk) chunks.push_back(make_int2(v, (int)p0));
+            vco.push_back((int)chunks.size());
+            pix += np;
+            s->views_host.push_back(d);
+        }
+        s->n_pixels = pix;
+        s->n_work = (int)work.size();
+        s->n_chunks = (int)chunks.size();
+        std::vector<int> hvo(n_hands + 1, 0), hv;
+        for (int h = 0; h < n_hands; ++h) {
+            for (int v = 0; v < n_views; ++v)
+                if (cams[v].hand == h) hv.push_back(v);
+            hvo[h + 1] = (int)hv.size();
+        }
+        TRY(s->upload(&s->views, s->views_host.data(), s->views_host.size()));
+        TRY(s->upload(&s->work, work.data(), work.size()));
+        TRY(s->upload(&s->chunks, chunks.data(), chunks.size()));
+        TRY(s->upload(&s->view_chunk_off, vco.data(), vco.size()));
+        TRY(s->upload(&s->hand_view_off, hvo.data(), hvo.size()));
+        TRY(s->upload(&s->hand_views, hv.data(), hv.size()));
+    }
+    // per-iteration state
+    TRY(s->upload<int4>(&s->bounds, nullptr, n_views));
+    TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
+    TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
+    TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.n_nodes));
+    TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_hands * V * 6));
+    TRY(s->upload<float>(&s->loss_partial, nullptr, 2 * (size_t)s->n_chunks));
+    TRY(s->upload<float>(&s->view_scale, nullptr, n_views));
+    TRY(s->upload<EdgeRec>(&s->edge_rec, nullptr, (size_t)n_views * E));
+    TRY(s->upload<unsigned long long>(&s->edge_cdf, nullptr, (size_t)n_views * E));
+    TRY(s->upload<unsigned long long>(&s->edge_total, nullptr, n_views));
+    TRY(s->upload<long long>(&s->edge_budget, nullptr, n_views));
+#undef TRY
+    s->smem_skin = sizeof(float) * 3 * V;
+    s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.n_nodes);
+    s->smem_geom_bwd = sizeof(float) * (3 * V * 4 + 3 * F);
+    s->smem_adjoint = sizeof(float) * 6 * V;
+    *out = s;
+    return HR_OK;
+}
+
+int hr_skin(hr_scene* s, const float* params, float* verts, float* joints, void* stream)
+{
+    if (!s || !params || !verts) return fail(HR_EINVAL, "hr_skin: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh, params, verts, joints);
+    return check_launch("hr_skin");
+}
+
+static int prepare(hr_scene* s, const float* verts, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_prepare, dim3(s->n_hands), dim3(512), s->smem_prepare, st, s->mesh, s->bvh, verts,
+                       s->normals, s->tris, s->nodes);
+    int rc = check_launch("prepare");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_view_bounds, dim3(s->n_views), dim3(256), 0, st, s->mesh, s->views, verts, s->bounds);
+    return check_launch("view bounds");
+}
+
+static Shading shading_of(const hr_config& c)
+{
+    Shading S;
+    S.ka = c.ka; S.kd = c.kd;
+    S.l[0] = c.light[0]; S.l[1] = c.light[1]; S.l[2] = c.light[2];
+    return S;
+}
+
+int hr_render(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
+              float* image, int32_t* hit_face, void* stream)
+{
+    if (!s || !verts || !albedo || !background || !image) return fail(HR_EINVAL, "hr_render: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = prepare(s, verts, st);
+    if (rc) return rc;
+    RenderArgs a;
+    a.work = s->work; a.views = s->views; a.bounds = s->bounds;
+    a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
+    a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
+    a.n_nodes = s->bvh.n_nodes; a.n_faces = s->F; a.n_verts = s->V;
+    a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
+    a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    hipLaunchKernelGGL(k_render, dim3(s->n_work), dim3(kThreads), 0, st, a);
+    return check_launch("hr_render");
+}
+
+int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss, float* dimage,
+            void* stream)
+{
+    if (!s || !image || !target || !loss || !dimage) return fail(HR_EINVAL, "hr_loss: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    LossArgs a;
+    a.chunks = s->chunks; a.views = s->views; a.image = image; a.target = target; a.mask = mask;
+    a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
+    a.hand_views = s->hand_views; a.view_scale = s->view_scale; a.loss = loss; a.dimage = dimage;
+    a.n_hands = s->n_hands;
+    hipLaunchKernelGGL(k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
+    int rc = check_launch("hr_loss partial");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_loss_final, dim3((s->n_hands + 63) / 64), dim3(64), 0, st, a);
+    rc = check_launch("hr_loss final");
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
+    return check_launch("hr_loss grad");
+}
+
+static void fill(float* p, long long n, float v, hipStream_t st)
+{
+    if (n <= 0) return;
+    long long blocks = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
+                const float* dimage, uint32_t iter, uint32_t flags, float* grad_params, float* grad_albedo,
+                float* grad_verts, float* grad_normals, void* stream)
+{
+    if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
+        return fail(HR_EINVAL, "hr_backward: null argument");
+    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY)) return fail(HR_EINVAL, "hr_backward: unknown flags");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if (!(flags & HR_REUSE_GEOMETRY)) {
+        rc = prepare(s, verts, st);
+        if (rc) return rc;
+    }
+    const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
+    fill(grad_albedo, nalb, 0.0f, st);
+    fill(s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
+    if (flags & HR_GRAD_INTERIOR) {
+        AdjointArgs a;
+        a.work = s->work; a.views = s->views; a.bounds = s->bounds;
+        a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
+        a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gacc = s->gacc;
+        a.n_nodes = s->bvh.n_nodes; a.n_faces = s->F; a.n_verts = s->V;
+        a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
+        a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+        hipLaunchKernelGGL(k_adjoint_interior, dim3(s->n_work), dim3(kThreads), s->smem_adjoint, st, a);
+        rc = check_launch("hr_backward interior");
+        if (rc) return rc;
+    }
+    if (flags & HR_GRAD_EDGES) {
+        EdgeArgs a;
+        a.m = s->mesh; a.views = s->views; a.verts = verts;
+        a.rec = s->edge_rec; a.cdf = s->edge_cdf; a.total = s->edge_total; a.budget = s->edge_budget;
+        a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
+        a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
+        a.n_nodes = s->bvh.n_nodes; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
+        a.delta = s->cfg.edge_delta; a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+        hipLaunchKernelGGL(k_edges_setup, dim3(s->n_views), dim3(256), 0, st, a);
+        rc = check_launch("hr_backward edges setup");
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_edge_sample, dim3(8, s->n_views), dim3(kThreads), 0, st, a);
+        rc = check_launch("hr_backward edge samples");
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh, params, verts,
+                       s->gacc, grad_params, grad_verts, grad_normals);
+    return check_launch("hr_backward geometry");
+}
+
+int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
+            float* m_params, float* v_params, float* m_albedo, float* v_albedo, int32_t t, const hr_adam_config* cfg,
+            void* stream)
+{
+    if (!s || !params || !albedo || !grad_params || !grad_albedo || !m_params || !v_params || !m_albedo ||
+        !v_albedo || !cfg)
+        return fail(HR_EINVAL, "hr_step: null argument");
+    if (t < 1) return fail(HR_EINVAL, "hr_step: t must be >= 1");
+    AdamArgs a;
+    a.params = params; a.albedo = albedo; a.grad_params = grad_params; a.grad_albedo = grad_albedo;
+    a.m_params = m_params; a.v_params = v_params; a.m_albedo = m_albedo; a.v_albedo = v_albedo;
+    a.n_albedo = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
+    a.n_hands = s->n_hands;
+    a.lr[0] = cfg->lr_pose_root; a.lr[1] = cfg->lr_pose; a.lr[2] = cfg->lr_shape;
+    a.lr[3] = cfg->lr_rot; a.lr[4] = cfg->lr_trans; a.lr[5] = cfg->lr_albedo;
+    a.beta1 = cfg->beta1; a.beta2 = cfg->beta2; a.eps = cfg->eps;
+    a.bc1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)t));
+    a.bc2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)t));
+    const long long n = 64ll * s->n_hands + a.n_albedo;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
+    return check_launch("hr_step");
+}
+
+int hr_edge_stats(hr_scene* s, uint64_t* total_host, int64_t* budget_host, void* stream)
+{
+    if (!s || !total_host || !budget_host) return fail(HR_EINVAL, "hr_edge_stats: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipMemcpy(total_host, s->edge_total, sizeof(uint64_t) * s->n_views, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(budget_host, s->edge_budget, sizeof(int64_t) * s->n_views, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_edge_stats: %s", hipGetErrorString(e));
+    return HR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,412 @@
+// Device-side building blocks of the handrt kernels (gfx950, wave64).
+//
+// Float32 decisions (closest hit, silhouette classification, edge sample
+// placement) are written with an explicit evaluation order and the library is
+// compiled with -ffp-contract=off, so each decision rounds exactly as written:
+// a float64 host evaluation that follows the same published algorithms in
+// float32 reaches the same integer results.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hr {
+
+constexpr int kMaxStack = 40;       // traversal stack entries per lane
+constexpr int kLeafMax = 4;         // triangles per leaf
+constexpr int kBlockPix = 16;       // render work unit: 16x16 pixels
+constexpr int kThreads = 256;       // 4 waves, one 8x8 pixel tile each
+
+// ---------------------------------------------------------------------------
+// records in device memory
+// ---------------------------------------------------------------------------
+
+struct ViewDev {            // one camera (see hr_camera)
+    float R[9];
+    float o[3];
+    float fx, fy, cx, cy;
+    int W, H, hand, bx;     // bx = number of 16-pixel blocks across
+    long long pix0;         // first pixel in packed buffers
+};
+
+struct alignas(16) Node {   // internal node: bounds of both children
+    float lo0[3], hi0[3], lo1[3], hi1[3];
+    int child[2];           // >= 0 internal node, < 0 leaf: ~(start << 3 | count)
+    int pad[2];
+};
+
+struct alignas(16) Tri {    // triangle in leaf order
+    float v[9];
+    int face, i0, i1, i2;
+    int pad[3];
+};
+
+struct alignas(16) EdgeRec {  // silhouette edge of one view (float32)
+    float ax, ay, bx, by;     // projected endpoints
+    float t0, t1;             // clipped parameter interval
+    uint32_t w;               // quantised length, 1/256 px (0 = not sampled)
+    int pad;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+
+struct U64x4 { uint64_t x[4]; };
+
+__device__ __forceinline__ U64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                            uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        uint64_t y0 = hi1 ^ c1 ^ k0;
+        uint64_t y2 = hi0 ^ c3 ^ k1;
+        c0 = y0; c1 = lo1; c2 = y2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    U64x4 o;
+    o.x[0] = c0; o.x[1] = c1; o.x[2] = c2; o.x[3] = c3;
+    return o;
+}
+
+__device__ __forceinline__ float u24_lo(uint64_t r) { return (float)((uint32_t)r >> 8) * 0x1p-24f; }
+__device__ __forceinline__ float u24_hi(uint64_t r) { return (float)(r >> 40) * 0x1p-24f; }
+
+constexpr uint64_t kDomainCamera = 0;
+constexpr uint64_t kDomainEdge = 1;
+
+// ---------------------------------------------------------------------------
+// rays and the watertight test (Woop, Benthin, Wald, JCGT 2013)
+// ---------------------------------------------------------------------------
+
+struct Ray {
+    float o[3], d[3];
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+    float inv[3];           // 1/d for the slab test (|d| clamped away from 0)
+};
+
+__device__ __forceinline__ float comp(const float* a, int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
+
+__device__ __forceinline__ void ray_setup(Ray& r)
+{
+    int kz = 0;
+    if (fabsf(r.d[1]) > fabsf(r.d[kz])) kz = 1;
+    if (fabsf(r.d[2]) > fabsf(comp(r.d, kz))) kz = 2;
+    int kx = kz + 1; if (kx == 3) kx = 0;
+    int ky = kx + 1; if (ky == 3) ky = 0;
+    float dz = comp(r.d, kz);
+    if (dz < 0.0f) { int t = kx; kx = ky; ky = t; }
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.Sx = comp(r.d, kx) / dz;
+    r.Sy = comp(r.d, ky) / dz;
+    r.Sz = 1.0f / dz;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float dk = r.d[k];
+        if (fabsf(dk) < 1e-20f) dk = dk < 0.0f ? -1e-20f : 1e-20f;
+        r.inv[k] = 1.0f / dk;
+    }
+}
+
+// ray through screen point (sx, sy): origin at the camera centre, direction R^T dc
+__device__ __forceinline__ void ray_screen(const ViewDev& c, float sx, float sy, Ray& r)
+{
+    float dcx = (sx - c.cx) / c.fx;
+    float dcy = (sy - c.cy) / c.fy;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float a = c.R[k] * dcx;
+        float b = c.R[3 + k] * dcy;
+        r.d[k] = (a + b) + c.R[6 + k];
+        r.o[k] = c.o[k];
+    }
+    ray_setup(r);
+}
+
+// returns true and (t, U, V, W, det) when the ray hits the triangle with t > 0
+__device__ __forceinline__ bool watertight(const Ray& r, const float* v0, const float* v1,
+                                           const float* v2, float& t_out, float& U_out,
+                                           float& V_out, float& W_out, float& det_out)
+{
+    float A[3], B[3], C[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        A[k] = v0[k] - r.o[k];
+        B[k] = v1[k] - r.o[k];
+        C[k] = v2[k] - r.o[k];
+    }
+    const float Akx = comp(A, r.kx), Aky = comp(A, r.ky), Akz = comp(A, r.kz);
+    const float Bkx = comp(B, r.kx), Bky = comp(B, r.ky), Bkz = comp(B, r.kz);
+    const float Ckx = comp(C, r.kx), Cky = comp(C, r.ky), Ckz = comp(C, r.kz);
+    float Ax = Akx - r.Sx * Akz;
+    float Ay = Aky - r.Sy * Akz;
+    float Bx = Bkx - r.Sx * Bkz;
+    float By = Bky - r.Sy * Bkz;
+    float Cx = Ckx - r.Sx * Ckz;
+    float Cy = Cky - r.Sy * Ckz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        double CxBy = (double)Cx * (double)By, CyBx = (double)Cy * (double)Bx;
+        double AxCy = (double)Ax * (double)Cy, AyCx = (double)Ay * (double)Cx;
+        double BxAy = (double)Bx * (double)Ay, ByAx = (double)By * (double)Ax;
+        U = (float)(CxBy - CyBx);
+        V = (float)(AxCy - AyCx);
+        W = (float)(BxAy - ByAx);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    float det = (U + V) + W;
+    if (det == 0.0f) return false;
+    float Az = r.Sz * Akz;
+    float Bz = r.Sz * Bkz;
+    float Cz = r.Sz * Ckz;
+    float T = (U * Az + V * Bz) + W * Cz;
+    float t = T / det;
+    if (!(t > 0.0f)) return false;
+    t_out = t; U_out = U; V_out = V; W_out = W; det_out = det;
+    return true;
+}
+
+struct Hit {
+    int face;         // -1: miss
+    int slot;         // leaf-order index of the triangle
+    float t;
+};
+
+// Surface point of a hit, with barycentrics recomputed in float64 from the
+// exact sample ray: the float32 test decides the triangle, float64 gives the
+// position on it (well conditioned even at grazing incidence).
+struct Surf {
+    int i0, i1, i2;
+    float b0, b1, b2;
+    double tu, tv;    // texture coordinates (float64: texel positions stay exact)
+    float v[9];       // triangle vertices
+    double d[3];      // float64 ray direction (unnormalised, camera depth scale)
+};
+
+__device__ __forceinline__ bool slab(const Ray& r, const float* lo, const float* hi, float tmax_in,
+                                     float& tmin_out)
+{
+    float tx0 = (lo[0] - r.o[0]) * r.inv[0], tx1 = (hi[0] - r.o[0]) * r.inv[0];
+    float ty0 = (lo[1] - r.o[1]) * r.inv[1], ty1 = (hi[1] - r.o[1]) * r.inv[1];
+    float tz0 = (lo[2] - r.o[2]) * r.inv[2], tz1 = (hi[2] - r.o[2]) * r.inv[2];
+    float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+    float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax_in));
+    tmin_out = tmin;
+    return tmin <= tmax;
+}
+
+// Closest hit by stack traversal of a binary BVH with padded (conservative)
+// bounds.  The closest hit is the minimum of (t, face id): independent of the
+// visiting order, hence equal to a brute-force loop over all triangles.
+// `stack` points at this lane's column of an LDS array (stride `sstride`).
+__device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
+                                      const Ray& r, int* stack, int sstride, Hit& h)
+{
+    h.face = -1;
+    float tb = __builtin_inff();
+    int fb = 0x7fffffff;
+    int sp = 0;
+    int node = 0;
+    while (true) {
+        const Node& n = nodes[node];
+        float4 q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
+        float4 q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
+        float4 q2 = *reinterpret_cast<const float4*>(&n.lo1[2]);
+        int4 q3 = *reinterpret_cast<const int4*>(&n.child[0]);
+        float lo0[3] = {q0.x, q0.y, q0.z}, hi0[3] = {q0.w, q1.x, q1.y};
+        float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
+        int c0 = q3.x, c1 = q3.y;
+        float t0, t1;
+        bool h0 = slab(r, lo0, hi0, tb, t0);
+        bool h1 = slab(r, lo1, hi1, tb, t1);
+        // leaves are tested right away
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            int code = c == 0 ? c0 : c1;
+            bool hit = c == 0 ? h0 : h1;
+            if (hit && code < 0) {
+                int lc = ~code;
+                int start = lc >> 3, cnt = lc & 7;
+                for (int k = 0; k < cnt; ++k) {
+                    const Tri& tr = tris[start + k];
+                    float4 p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
+                    float4 p1 = *reinterpret_cast<const float4*>(&tr.v[4]);
+                    float4 p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+                    float v0[3] = {p0.x, p0.y, p0.z};
+                    float v1[3] = {p0.w, p1.x, p1.y};
+                    float v2[3] = {p1.z, p1.w, p2.x};
+                    int face = __float_as_int(p2.y);
+                    float t, U, V, W, det;
+                    if (watertight(r, v0, v1, v2, t, U, V, W, det)) {
+                        if (t < tb || (t == tb && face < fb)) {
+                            tb = t; fb = face;
+                            h.face = face;
+                            h.slot = start + k;
+                            h.t = t;
+                        }
+                    }
+                }
+            }
+        }
+        bool go0 = h0 && c0 >= 0 && t0 <= tb;
+        bool go1 = h1 && c1 >= 0 && t1 <= tb;
+        if (go0 && go1) {
+            int nearc = t0 <= t1 ? c0 : c1;
+            int farc = t0 <= t1 ? c1 : c0;
+            if (sp < kMaxStack) { stack[sp * sstride] = farc; ++sp; }
+            node = nearc;
+        } else if (go0) {
+            node = c0;
+        } else if (go1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = stack[sp * sstride];
+        }
+    }
+}
+
+// float64 direction of the ray through screen point (X, Y)
+__device__ __forceinline__ void ray_dir64(const ViewDev& c, double X, double Y, double* d)
+{
+    double dcx = (X - (double)c.cx) / (double)c.fx;
+    double dcy = (Y - (double)c.cy) / (double)c.fy;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = (double)c.R[k] * dcx + (double)c.R[3 + k] * dcy + (double)c.R[6 + k];
+}
+
+// barycentrics of the hit on triangle `slot` for the float64 ray (o, d):
+// o + t d = (1-b1-b2) v0 + b1 v1 + b2 v2 by Cramer's rule
+__device__ __forceinline__ void surface(const Tri* __restrict__ tris, const float* __restrict__ uv, int slot,
+                                        const ViewDev& c, double X, double Y, Surf& s)
+{
+    const Tri& tr = tris[slot];
+    float4 p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
+    float4 p1 = *reinterpret_cast<const float4*>(&tr.v[4]);
+    float4 p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+    s.v[0] = p0.x; s.v[1] = p0.y; s.v[2] = p0.z; s.v[3] = p0.w; s.v[4] = p1.x;
+    s.v[5] = p1.y; s.v[6] = p1.z; s.v[7] = p1.w; s.v[8] = p2.x;
+    s.i0 = __float_as_int(p2.z); s.i1 = __float_as_int(p2.w); s.i2 = tr.i2;
+    ray_dir64(c, X, Y, s.d);
+    double e1[3], e2[3], q[3], pv[3], sv[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = (double)s.v[3 + k] - (double)s.v[k];
+        e2[k] = (double)s.v[6 + k] - (double)s.v[k];
+        sv[k] = (double)c.o[k] - (double)s.v[k];
+    }
+    pv[0] = s.d[1] * e2[2] - s.d[2] * e2[1];
+    pv[1] = s.d[2] * e2[0] - s.d[0] * e2[2];
+    pv[2] = s.d[0] * e2[1] - s.d[1] * e2[0];
+    double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    q[0] = sv[1] * e1[2] - sv[2] * e1[1];
+    q[1] = sv[2] * e1[0] - sv[0] * e1[2];
+    q[2] = sv[0] * e1[1] - sv[1] * e1[0];
+    double b1 = (sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2]) / det;
+    double b2 = (s.d[0] * q[0] + s.d[1] * q[1] + s.d[2] * q[2]) / det;
+    const double b0 = 1.0 - b1 - b2;
+    s.b0 = (float)b0;
+    s.b1 = (float)b1;
+    s.b2 = (float)b2;
+    const float2 uv0 = *reinterpret_cast<const float2*>(uv + 2 * s.i0);
+    const float2 uv1 = *reinterpret_cast<const float2*>(uv + 2 * s.i1);
+    const float2 uv2 = *reinterpret_cast<const float2*>(uv + 2 * s.i2);
+    s.tu = b0 * (double)uv0.x + b1 * (double)uv1.x + b2 * (double)uv2.x;
+    s.tv = b0 * (double)uv0.y + b1 * (double)uv1.y + b2 * (double)uv2.y;
+}
+
+// ---------------------------------------------------------------------------
+// shading: albedo(uv) * (ka + kd max(0, n.l)), bilinear albedo with texel
+// centres at (j + 1/2) / W, clamped at the border
+// ---------------------------------------------------------------------------
+
+struct Shading {
+    float ka, kd, l[3];
+};
+
+struct Shade {
+    float u, v;                 // texture coordinates
+    float n[3], nlen;           // unit interpolated normal and the raw length
+    float ndotl, shade;
+    int idx[4];                 // texel indices
+    float w[4];                 // bilinear weights
+    float col[3];               // albedo
+    float dcol_du[3], dcol_dv[3];
+};
+
+__device__ __forceinline__ void shade_hit(const Surf& h, const float* __restrict__ normals,
+                                          const float* __restrict__ uv, const float* __restrict__ tex,
+                                          int th, int tw, const Shading& S, Shade& o)
+{
+    const float b0 = h.b0, b1 = h.b1, b2 = h.b2;
+    o.u = (float)h.tu;
+    o.v = (float)h.tv;
+    const float* n0 = normals + 3 * h.i0;
+    const float* n1 = normals + 3 * h.i1;
+    const float* n2 = normals + 3 * h.i2;
+    float nr[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nr[k] = b0 * n0[k] + b1 * n1[k] + b2 * n2[k];
+    o.nlen = sqrtf(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+    float inl = 1.0f / o.nlen;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) o.n[k] = nr[k] * inl;
+    o.ndotl = o.n[0] * S.l[0] + o.n[1] * S.l[1] + o.n[2] * S.l[2];
+    o.shade = S.ka + S.kd * fmaxf(o.ndotl, 0.0f);
+    const double x = h.tu * tw - 0.5, y = h.tv * th - 0.5;
+    const double fx0 = floor(x), fy0 = floor(y);
+    const float ax = (float)(x - fx0), ay = (float)(y - fy0);
+    int j0 = (int)fx0, i0 = (int)fy0;
+    int j1 = min(max(j0 + 1, 0), tw - 1), i1 = min(max(i0 + 1, 0), th - 1);
+    j0 = min(max(j0, 0), tw - 1);
+    i0 = min(max(i0, 0), th - 1);
+    o.idx[0] = i0 * tw + j0; o.w[0] = (1.0f - ax) * (1.0f - ay);
+    o.idx[1] = i0 * tw + j1; o.w[1] = ax * (1.0f - ay);
+    o.idx[2] = i1 * tw + j0; o.w[2] = (1.0f - ax) * ay;
+    o.idx[3] = i1 * tw + j1; o.w[3] = ax * ay;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        float a00 = tex[3 * o.idx[0] + ch], a01 = tex[3 * o.idx[1] + ch];
+        float a10 = tex[3 * o.idx[2] + ch], a11 = tex[3 * o.idx[3] + ch];
+        o.col[ch] = o.w[0] * a00 + o.w[1] * a01 + o.w[2] * a10 + o.w[3] * a11;
+        o.dcol_du[ch] = tw * ((1.0f - ay) * (a01 - a00) + ay * (a11 - a10));
+        o.dcol_dv[ch] = th * ((1.0f - ax) * (a10 - a00) + ax * (a11 - a01));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// float32 projection (edge decisions)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool project32(const ViewDev& c, const float* v, float& px, float& py)
+{
+    float q0 = v[0] - c.o[0], q1 = v[1] - c.o[1], q2 = v[2] - c.o[2];
+    float xc = (c.R[0] * q0 + c.R[1] * q1) + c.R[2] * q2;
+    float yc = (c.R[3] * q0 + c.R[4] * q1) + c.R[5] * q2;
+    float zc = (c.R[6] * q0 + c.R[7] * q1) + c.R[8] * q2;
+    if (!(zc > 1e-4f)) return false;
+    px = (c.fx * xc) / zc + c.cx;
+    py = (c.fy * yc) / zc + c.cy;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// wave / block reductions
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace hr

@@ -1,0 +1,121 @@
+// Kernel argument records of the handrt library (device pointers only).
+#pragma once
+
+#include "device.h"
+
+namespace hr {
+
+constexpr int kMaxJoints = 32;
+constexpr int kLossChunk = 4096;     // pixels per loss block (never straddles views)
+
+struct MeshDev {
+    int V, F, J, K, E;
+    const float* v_template;   // [V,3]
+    const float* shapedirs;    // [V,3,K]
+    const float* j_regressor;  // [J,V]
+    const float* weights;      // [V,J]
+    const int* parents;        // [J]
+    const int* faces;          // [F,3]
+    const float* uv;           // [V,2]
+    const int* edges;          // [E,2]
+    const int* edge_faces;     // [E,2]
+    const int* vf_off;         // [V+1]
+    const int* vf_faces;       // [3F]
+};
+
+struct BvhDev {
+    int n_nodes, n_levels;
+    const int* child;          // [n_nodes,2] child codes
+    const int* perm;           // [F] face of each leaf slot
+    const int* order;          // [n_nodes] internal nodes sorted by height
+    const int* level_off;      // [n_levels+1]
+};
+
+struct RenderArgs {
+    const int2* work;          // (view, block index in view)
+    const ViewDev* views;
+    const int4* bounds;        // per view, in 16-pixel blocks
+    const Node* nodes;
+    const Tri* tris;
+    const float* normals;
+    const float* uv;
+    const float* albedo;
+    const float* background;
+    float* image;
+    int* hit_face;
+    int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
+    uint32_t iter;
+    uint64_t seed;
+    Shading shading;
+};
+
+struct AdjointArgs {
+    const int2* work;
+    const ViewDev* views;
+    const int4* bounds;
+    const Node* nodes;
+    const Tri* tris;
+    const float* normals;
+    const float* uv;
+    const float* albedo;
+    const float* dimage;
+    float* grad_albedo;
+    float* gacc;               // [hands,V,6]
+    int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
+    uint32_t iter;
+    uint64_t seed;
+    Shading shading;
+};
+
+struct LossArgs {
+    const int2* chunks;        // (view, first pixel)
+    const ViewDev* views;
+    const float* image;
+    const float* target;
+    const uint8_t* mask;
+    float* partial;            // [n_chunks,2]
+    const int* view_chunk_off; // [n_views+1]
+    const int* hand_view_off;  // [n_hands+1]
+    const int* hand_views;     // [n_views]
+    float* view_scale;         // [n_views]
+    float* loss;               // [n_hands]
+    float* dimage;
+    int n_hands;
+};
+
+struct EdgeArgs {
+    MeshDev m;
+    const ViewDev* views;
+    const float* verts;
+    EdgeRec* rec;              // [n_views,E]
+    unsigned long long* cdf;   // [n_views,E]
+    unsigned long long* total; // [n_views]
+    long long* budget;         // [n_views]
+    const Node* nodes;
+    const Tri* tris;
+    const float* normals;
+    const float* uv;
+    const float* albedo;
+    const float* background;
+    const float* dimage;
+    float* gacc;
+    int n_nodes, tex_h, tex_w;
+    float delta;
+    uint32_t iter;
+    uint64_t seed;
+    Shading shading;
+};
+
+struct AdamArgs {
+    float* params;
+    float* albedo;
+    const float* grad_params;
+    const float* grad_albedo;
+    float *m_params, *v_params, *m_albedo, *v_albedo;
+    long long n_albedo;
+    int n_hands;
+    float lr[6];
+    float beta1, beta2, eps, bc1, bc2;
+};
+
+}  // namespace hr

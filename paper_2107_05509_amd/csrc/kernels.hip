@@ -1,0 +1,1068 @@
+// handrt kernels for gfx950: skinning, geometry preparation (vertex normals,
+// bounding-volume refit, per-view screen bounds), rendering, L1 loss, interior
+// adjoint, silhouette edges and edge sampling, normals + skinning backward, Adam.
+#include "kernels.h"
+
+namespace hr {
+
+// ===========================================================================
+// skinning (forward)
+// ===========================================================================
+
+struct Rod {                  // R = I + a K + b K^2 and the derivative factors
+    float R[9];
+    float a, b, ad, bd;       // ad = a'(|r|)/|r|, bd = b'(|r|)/|r|
+};
+
+__device__ void rodrigues(const float* r, Rod& o)
+{
+    float t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    float t = sqrtf(t2);
+    if (t < 0.3f) {
+        // series (no cancellation for small angles)
+        o.a = 1.0f - t2 / 6.0f + t2 * t2 / 120.0f;
+        o.b = 0.5f - t2 / 24.0f + t2 * t2 / 720.0f;
+        o.ad = -1.0f / 3.0f + t2 / 30.0f - t2 * t2 / 840.0f;
+        o.bd = -1.0f / 12.0f + t2 / 180.0f - t2 * t2 / 6720.0f;
+    } else {
+        float s = sinf(t), c = cosf(t), sh = sinf(0.5f * t);
+        o.a = s / t;
+        o.b = 2.0f * sh * sh / t2;
+        o.ad = (t * c - s) / (t2 * t);
+        o.bd = (t * s - 4.0f * sh * sh) / (t2 * t2);
+    }
+    float K[9] = {0.0f, -r[2], r[1], r[2], 0.0f, -r[0], -r[1], r[0], 0.0f};
+    float K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            K2[3 * i + j] = K[3 * i + 0] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+    for (int i = 0; i < 9; ++i) o.R[i] = o.a * K[i] + o.b * K2[i];
+    o.R[0] += 1.0f; o.R[4] += 1.0f; o.R[8] += 1.0f;
+}
+
+// <G, K(e_k)> for k = 0..2, K(e) the cross-product matrix of e
+__device__ __forceinline__ void skew_dot(const float* G, float* out)
+{
+    out[0] = G[7] - G[5];
+    out[1] = G[2] - G[6];
+    out[2] = G[3] - G[1];
+}
+
+// gradient of <gR, R(r)> with respect to r
+__device__ void rodrigues_bwd(const float* r, const Rod& d, const float* gR, float* gr)
+{
+    float K[9] = {0.0f, -r[2], r[1], r[2], 0.0f, -r[0], -r[1], r[0], 0.0f};
+    float K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            K2[3 * i + j] = K[3 * i + 0] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+    float gK = 0.0f, gK2 = 0.0f;
+    for (int i = 0; i < 9; ++i) { gK += gR[i] * K[i]; gK2 += gR[i] * K2[i]; }
+    // X = gR K^T + K^T gR: <gR, E K + K E> = <X, E>
+    float X[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            float s = 0.0f;
+            for (int m = 0; m < 3; ++m) s += gR[3 * i + m] * K[3 * j + m] + K[3 * m + i] * gR[3 * m + j];
+            X[3 * i + j] = s;
+        }
+    float s1[3], s2[3];
+    skew_dot(gR, s1);
+    skew_dot(X, s2);
+    for (int k = 0; k < 3; ++k) gr[k] = d.ad * r[k] * gK + d.a * s1[k] + d.bd * r[k] * gK2 + d.b * s2[k];
+}
+
+__device__ __forceinline__ void matmul3(const float* A, const float* B, float* C)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+__device__ __forceinline__ void matvec3(const float* A, const float* x, float* y)
+{
+    for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+}
+
+__device__ __forceinline__ void matTvec3(const float* A, const float* x, float* y)
+{
+    for (int i = 0; i < 3; ++i) y[i] = A[i] * x[0] + A[3 + i] * x[1] + A[6 + i] * x[2];
+}
+
+// block-wide sum of `n` per-thread values (n <= 16), result broadcast in `out`
+template <int N>
+__device__ void block_sum(float* vals, float* red /* LDS [4*N] */, float* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        float v = wave_sum(vals[i]);
+        if (lane == 0) red[wave * N + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < N) {
+        float s = 0.0f;
+        for (int w = 0; w < nw; ++w) s += red[w * N + threadIdx.x];
+        red[16 * N + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = red[16 * N + i];
+    __syncthreads();
+}
+
+struct SkinShared {
+    float GR[kMaxJoints * 9];
+    float Gt[kMaxJoints * 3];
+    float At[kMaxJoints * 3];
+    float J[kMaxJoints * 3];
+    float Rj[kMaxJoints * 9];
+    float Rp[9];
+    float red[16 * 16 + 16 * 16];
+};
+
+// shaped vertices into vs (LDS), joints, joint transforms
+__device__ void skin_common(const MeshDev& m, const float* __restrict__ p, float* vs, SkinShared& sh)
+{
+    const int V = m.V, J = m.J, K = m.K;
+    const float* beta = p + 48;
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        for (int c = 0; c < 3; ++c) {
+            float s = m.v_template[3 * v + c];
+            const float* sd = m.shapedirs + (3 * v + c) * K;
+            for (int k = 0; k < K; ++k) s += sd[k] * beta[k];
+            vs[3 * v + c] = s;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < J; ++j) {
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+        const float* jr = m.j_regressor + (size_t)j * V;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            float w = jr[v];
+            acc[0] += w * vs[3 * v];
+            acc[1] += w * vs[3 * v + 1];
+            acc[2] += w * vs[3 * v + 2];
+        }
+        float out[3];
+        block_sum<3>(acc, sh.red, out);
+        if (threadIdx.x == 0) { sh.J[3 * j] = out[0]; sh.J[3 * j + 1] = out[1]; sh.J[3 * j + 2] = out[2]; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < J; ++j) {
+            Rod rd;
+            rodrigues(p + 3 * j, rd);
+            for (int i = 0; i < 9; ++i) sh.Rj[9 * j + i] = rd.R[i];
+            int par = m.parents[j];
+            if (par < 0) {
+                for (int i = 0; i < 9; ++i) sh.GR[9 * j + i] = rd.R[i];
+                for (int i = 0; i < 3; ++i) sh.Gt[3 * j + i] = sh.J[3 * j + i];
+            } else {
+                matmul3(sh.GR + 9 * par, rd.R, sh.GR + 9 * j);
+                float d[3] = {sh.J[3 * j] - sh.J[3 * par], sh.J[3 * j + 1] - sh.J[3 * par + 1],
+                              sh.J[3 * j + 2] - sh.J[3 * par + 2]};
+                float y[3];
+                matvec3(sh.GR + 9 * par, d, y);
+                for (int i = 0; i < 3; ++i) sh.Gt[3 * j + i] = y[i] + sh.Gt[3 * par + i];
+            }
+            float y[3];
+            matvec3(sh.GR + 9 * j, sh.J + 3 * j, y);
+            for (int i = 0; i < 3; ++i) sh.At[3 * j + i] = sh.Gt[3 * j + i] - y[i];
+        }
+        Rod rp;
+        rodrigues(p + 58, rp);
+        for (int i = 0; i < 9; ++i) sh.Rp[i] = rp.R[i];
+    }
+    __syncthreads();
+}
+
+// posed (pre-global-transform) vertex v
+__device__ __forceinline__ void blend_vertex(const MeshDev& m, const float* vs, const SkinShared& sh,
+                                             int v, float* vp)
+{
+    vp[0] = vp[1] = vp[2] = 0.0f;
+    const float* W = m.weights + (size_t)v * m.J;
+    const float x[3] = {vs[3 * v], vs[3 * v + 1], vs[3 * v + 2]};
+    for (int j = 0; j < m.J; ++j) {
+        float w = W[j];
+        if (w == 0.0f) continue;
+        float y[3];
+        matvec3(sh.GR + 9 * j, x, y);
+        for (int c = 0; c < 3; ++c) vp[c] += w * (y[c] + sh.At[3 * j + c]);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_skin(MeshDev m, const float* __restrict__ params,
+                                              float* __restrict__ verts, float* __restrict__ joints)
+{
+    extern __shared__ float dyn[];
+    __shared__ SkinShared sh;
+    const int h = blockIdx.x;
+    const float* p = params + 64 * h;
+    float* vs = dyn;
+    skin_common(m, p, vs, sh);
+    const float* tau = p + 61;
+    for (int v = threadIdx.x; v < m.V; v += blockDim.x) {
+        float vp[3], y[3];
+        blend_vertex(m, vs, sh, v, vp);
+        matvec3(sh.Rp, vp, y);
+        float* o = verts + ((size_t)h * m.V + v) * 3;
+        o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
+    }
+    if (joints) {
+        for (int j = threadIdx.x; j < m.J; j += blockDim.x) {
+            float y[3];
+            matvec3(sh.Rp, sh.Gt + 3 * j, y);
+            float* o = joints + ((size_t)h * m.J + j) * 3;
+            o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
+        }
+    }
+}
+
+// ===========================================================================
+// geometry preparation: vertex normals, triangles in leaf order, BVH refit
+// ===========================================================================
+
+__global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const float* __restrict__ verts,
+                                                 float* __restrict__ normals, Tri* __restrict__ tris,
+                                                 Node* __restrict__ nodes)
+{
+    extern __shared__ float dyn[];
+    const int h = blockIdx.x;
+    const int V = m.V, F = m.F;
+    float* vsh = dyn;                 // [V*3]
+    float* fn = vsh + 3 * V;          // [F*3]
+    float* nb = fn + 3 * F;           // [n_nodes*6] node bounds
+    const float* vh = verts + (size_t)h * V * 3;
+    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
+    __syncthreads();
+    for (int f = threadIdx.x; f < F; f += blockDim.x) {
+        int a = m.faces[3 * f], bb = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
+        float e1[3] = {vsh[3 * bb] - vsh[3 * a], vsh[3 * bb + 1] - vsh[3 * a + 1], vsh[3 * bb + 2] - vsh[3 * a + 2]};
+        float e2[3] = {vsh[3 * c] - vsh[3 * a], vsh[3 * c + 1] - vsh[3 * a + 1], vsh[3 * c + 2] - vsh[3 * a + 2]};
+        fn[3 * f] = e1[1] * e2[2] - e1[2] * e2[1];
+        fn[3 * f + 1] = e1[2] * e2[0] - e1[0] * e2[2];
+        fn[3 * f + 2] = e1[0] * e2[1] - e1[1] * e2[0];
+    }
+    __syncthreads();
+    float* nh = normals + (size_t)h * V * 3;
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        float s[3] = {0.0f, 0.0f, 0.0f};
+        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+            int f = m.vf_faces[k];
+            s[0] += fn[3 * f]; s[1] += fn[3 * f + 1]; s[2] += fn[3 * f + 2];
+        }
+        float inv = 1.0f / sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        nh[3 * v] = s[0] * inv; nh[3 * v + 1] = s[1] * inv; nh[3 * v + 2] = s[2] * inv;
+    }
+    Tri* th = tris + (size_t)h * F;
+    for (int i = threadIdx.x; i < F; i += blockDim.x) {
+        int f = b.perm[i];
+        Tri t;
+        int id[3] = {m.faces[3 * f], m.faces[3 * f + 1], m.faces[3 * f + 2]};
+        for (int k = 0; k < 3; ++k)
+            for (int c = 0; c < 3; ++c) t.v[3 * k + c] = vsh[3 * id[k] + c];
+        t.face = f; t.i0 = id[0]; t.i1 = id[1]; t.i2 = id[2];
+        t.pad[0] = t.pad[1] = t.pad[2] = 0;
+        th[i] = t;
+    }
+    // refit, level by level from the leaves up
+    Node* nd = nodes + (size_t)h * b.n_nodes;
+    for (int L = 0; L < b.n_levels; ++L) {
+        for (int q = b.level_off[L] + threadIdx.x; q < b.level_off[L + 1]; q += blockDim.x) {
+            int n = b.order[q];
+            Node out;
+            float own[6] = {3e38f, 3e38f, 3e38f, -3e38f, -3e38f, -3e38f};
+            for (int c = 0; c < 2; ++c) {
+                int code = b.child[2 * n + c];
+                float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+                if (code >= 0) {
+                    for (int k = 0; k < 3; ++k) { lo[k] = nb[6 * code + k]; hi[k] = nb[6 * code + 3 + k]; }
+                } else {
+                    int lc = ~code, start = lc >> 3, cnt = lc & 7;
+                    for (int i = 0; i < cnt; ++i) {
+                        int f = b.perm[start + i];
+                        for (int k = 0; k < 3; ++k) {
+                            int vid = m.faces[3 * f + k];
+                            for (int cc = 0; cc < 3; ++cc) {
+                                float x = vsh[3 * vid + cc];
+                                lo[cc] = fminf(lo[cc], x);
+                                hi[cc] = fmaxf(hi[cc], x);
+                            }
+                        }
+                    }
+                    // conservative padding: the float32 watertight test accepts
+                    // rays a few ulps outside the exact triangle
+                    for (int cc = 0; cc < 3; ++cc) {
+                        float pad = 1e-5f + 1e-6f * fmaxf(fabsf(lo[cc]), fabsf(hi[cc]));
+                        lo[cc] -= pad; hi[cc] += pad;
+                    }
+                }
+                float* dl = c == 0 ? out.lo0 : out.lo1;
+                float* dh = c == 0 ? out.hi0 : out.hi1;
+                for (int k = 0; k < 3; ++k) {
+                    dl[k] = lo[k]; dh[k] = hi[k];
+                    own[k] = fminf(own[k], lo[k]); own[3 + k] = fmaxf(own[3 + k], hi[k]);
+                }
+                out.child[c] = code;
+            }
+            out.pad[0] = out.pad[1] = 0;
+            nd[n] = out;
+            for (int k = 0; k < 6; ++k) nb[6 * n + k] = own[k];
+        }
+        __syncthreads();
+    }
+}
+
+// per-view screen bounds of the projected hand, in 16-pixel blocks:
+// (bx0, by0, bx1, by1) inclusive-exclusive; the whole view if any vertex is
+// not in front of the camera
+__global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* __restrict__ views,
+                                                     const float* __restrict__ verts, int4* __restrict__ bounds)
+{
+    __shared__ float red[4 * 64];
+    const ViewDev c = views[blockIdx.x];
+    const float* vh = verts + (size_t)c.hand * m.V * 3;
+    float mnx = 3e38f, mny = 3e38f, mxx = -3e38f, mxy = -3e38f;
+    int bad = 0;
+    for (int v = threadIdx.x; v < m.V; v += blockDim.x) {
+        float px, py;
+        if (project32(c, vh + 3 * v, px, py)) {
+            mnx = fminf(mnx, px); mny = fminf(mny, py);
+            mxx = fmaxf(mxx, px); mxy = fmaxf(mxy, py);
+        } else {
+            bad = 1;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = fminf(mnx, __shfl_xor(mnx, o)); mny = fminf(mny, __shfl_xor(mny, o));
+        mxx = fmaxf(mxx, __shfl_xor(mxx, o)); mxy = fmaxf(mxy, __shfl_xor(mxy, o));
+    }
+    int anybad = __syncthreads_or(bad);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { red[4 * w] = mnx; red[4 * w + 1] = mny; red[4 * w + 2] = mxx; red[4 * w + 3] = mxy; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            mnx = fminf(mnx, red[4 * k]); mny = fminf(mny, red[4 * k + 1]);
+            mxx = fmaxf(mxx, red[4 * k + 2]); mxy = fmaxf(mxy, red[4 * k + 3]);
+        }
+        const int nbx = (c.W + kBlockPix - 1) / kBlockPix, nby = (c.H + kBlockPix - 1) / kBlockPix;
+        int4 r;
+        if (anybad) {
+            r = make_int4(0, 0, nbx, nby);
+        } else if (mxx < -1.0f || mxy < -1.0f || mnx > c.W + 1.0f || mny > c.H + 1.0f) {
+            r = make_int4(0, 0, 0, 0);
+        } else {
+            // one pixel of margin around the float32 projections
+            int x0 = (int)floorf(fmaxf(mnx - 1.0f, 0.0f)), y0 = (int)floorf(fmaxf(mny - 1.0f, 0.0f));
+            int x1 = (int)floorf(fminf(mxx + 1.0f, (float)c.W - 1.0f)), y1 = (int)floorf(fminf(mxy + 1.0f, (float)c.H - 1.0f));
+            r = make_int4(x0 / kBlockPix, y0 / kBlockPix, x1 / kBlockPix + 1, y1 / kBlockPix + 1);
+        }
+        bounds[blockIdx.x] = r;
+    }
+}
+
+// ===========================================================================
+// render
+// ===========================================================================
+
+// pixel of thread t in a 16x16 block: wave w owns an 8x8 quadrant
+__device__ __forceinline__ void block_pixel(int t, int& lx, int& ly)
+{
+    const int w = t >> 6, l = t & 63;
+    lx = (w & 1) * 8 + (l & 7);
+    ly = (w >> 1) * 8 + (l >> 3);
+}
+
+__global__ void __launch_bounds__(kThreads) k_render(RenderArgs a)
+{
+    __shared__ int stack[kMaxStack * kThreads];
+    const int2 wk = a.work[blockIdx.x];
+    const ViewDev c = a.views[wk.x];
+    const int bxi = wk.y % c.bx, byi = wk.y / c.bx;
+    int lx, ly;
+    block_pixel(threadIdx.x, lx, ly);
+    const int px = bxi * kBlockPix + lx, py = byi * kBlockPix + ly;
+    const bool inside = px < c.W && py < c.H;
+    const long long pl = (long long)py * c.W + px;
+    const long long pg = c.pix0 + pl;
+    const int4 bd = a.bounds[wk.x];
+    const bool culled = bxi < bd.x || bxi >= bd.z || byi < bd.y || byi >= bd.w;
+    if (!inside) return;
+    const float bgc[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
+    if (culled) {
+        a.image[3 * pg] = bgc[0]; a.image[3 * pg + 1] = bgc[1]; a.image[3 * pg + 2] = bgc[2];
+        if (a.hit_face)
+            for (int s = 0; s < a.spp; ++s) a.hit_face[pg * a.spp + s] = -1;
+        return;
+    }
+    const Node* nodes = a.nodes + (size_t)c.hand * a.n_nodes;
+    const Tri* tris = a.tris + (size_t)c.hand * a.n_faces;
+    const float* normals = a.normals + (size_t)c.hand * a.n_verts * 3;
+    const float* tex = a.albedo + (size_t)c.hand * a.tex_h * a.tex_w * 3;
+    int* stk = stack + threadIdx.x;
+    // sum of the hit colours (all terms non-negative: no cancellation) and the
+    // number of misses, which take the background colour
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    int misses = 0;
+    const uint64_t c2 = (uint64_t)(uint32_t)wk.x | (kDomainCamera << 32);
+    for (int q = 0; q < (a.spp + 3) / 4; ++q) {
+        U64x4 r = philox4x64((uint64_t)pl, (uint64_t)q, c2, (uint64_t)a.iter, a.seed, 0);
+        for (int j = 0; j < 4; ++j) {
+            const int s = 4 * q + j;
+            if (s >= a.spp) break;
+            float u = u24_lo(r.x[j]), v = u24_hi(r.x[j]);
+            float sx = (float)px + u, sy = (float)py + v;
+            Ray ray;
+            ray_screen(c, sx, sy, ray);
+            Hit h;
+            trace(nodes, tris, ray, stk, kThreads, h);
+            if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
+            if (h.face >= 0) {
+                Surf sf;
+                surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
+                Shade sd;
+                shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, sd);
+                for (int ch = 0; ch < 3; ++ch) acc[ch] += sd.col[ch] * sd.shade;
+            } else {
+                ++misses;
+            }
+        }
+    }
+    float out[3];
+    if (misses == a.spp) {
+        out[0] = bgc[0]; out[1] = bgc[1]; out[2] = bgc[2];
+    } else {
+        const float inv = 1.0f / (float)a.spp, fm = (float)misses;
+        for (int ch = 0; ch < 3; ++ch) out[ch] = (acc[ch] + fm * bgc[ch]) * inv;
+    }
+    a.image[3 * pg] = out[0];
+    a.image[3 * pg + 1] = out[1];
+    a.image[3 * pg + 2] = out[2];
+}
+
+// ===========================================================================
+// L1 loss
+// ===========================================================================
+
+__global__ void __launch_bounds__(256) k_loss_partial(LossArgs a)
+{
+    __shared__ float red[2 * 16];
+    const int2 ck = a.chunks[blockIdx.x];   // (view, first pixel in view)
+    const ViewDev c = a.views[ck.x];
+    const long long n = (long long)c.W * c.H;
+    float s = 0.0f, cnt = 0.0f;
+    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+        long long pl = (long long)ck.y + k;
+        if (pl >= n) break;
+        long long pg = c.pix0 + pl;
+        if (a.mask && a.mask[pg] == 0) continue;
+        s += fabsf(a.image[3 * pg] - a.target[3 * pg]) + fabsf(a.image[3 * pg + 1] - a.target[3 * pg + 1]) +
+             fabsf(a.image[3 * pg + 2] - a.target[3 * pg + 2]);
+        cnt += 1.0f;
+    }
+    s = wave_sum(s);
+    cnt = wave_sum(cnt);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) { red[2 * w] = s; red[2 * w + 1] = cnt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float ts = 0.0f, tc = 0.0f;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ts += red[2 * k]; tc += red[2 * k + 1]; }
+        a.partial[2 * blockIdx.x] = ts;
+        a.partial[2 * blockIdx.x + 1] = tc;
+    }
+}
+
+// one thread per hand: reduce its views' chunks in order
+__global__ void k_loss_final(LossArgs a)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= a.n_hands) return;
+    float loss = 0.0f;
+    for (int q = a.hand_view_off[h]; q < a.hand_view_off[h + 1]; ++q) {
+        const int v = a.hand_views[q];
+        float s = 0.0f, cnt = 0.0f;
+        for (int k = a.view_chunk_off[v]; k < a.view_chunk_off[v + 1]; ++k) {
+            s += a.partial[2 * k];
+            cnt += a.partial[2 * k + 1];
+        }
+        a.view_scale[v] = cnt > 0.0f ? 1.0f / (3.0f * cnt) : 0.0f;
+        if (cnt > 0.0f) loss += s / (3.0f * cnt);
+    }
+    a.loss[h] = loss;
+}
+
+__global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
+{
+    const int2 ck = a.chunks[blockIdx.x];
+    const ViewDev c = a.views[ck.x];
+    const long long n = (long long)c.W * c.H;
+    const float sc = a.view_scale[ck.x];
+    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+        long long pl = (long long)ck.y + k;
+        if (pl >= n) break;
+        long long pg = c.pix0 + pl;
+        bool on = !a.mask || a.mask[pg] != 0;
+        for (int ch = 0; ch < 3; ++ch) {
+            float d = a.image[3 * pg + ch] - a.target[3 * pg + ch];
+            float sg = (float)((d > 0.0f) - (d < 0.0f));
+            a.dimage[3 * pg + ch] = on ? sg * sc : 0.0f;
+        }
+    }
+}
+
+// ===========================================================================
+// interior adjoint
+// ===========================================================================
+
+__global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
+{
+    __shared__ int stack[kMaxStack * kThreads];
+    extern __shared__ float gacc[];   // [V*6]: dL/dv (3), dL/dn (3)
+    const int2 wk = a.work[blockIdx.x];
+    const ViewDev c = a.views[wk.x];
+    const int bxi = wk.y % c.bx, byi = wk.y / c.bx;
+    const int4 bd = a.bounds[wk.x];
+    if (bxi < bd.x || bxi >= bd.z || byi < bd.y || byi >= bd.w) return;   // block-uniform
+    for (int i = threadIdx.x; i < a.n_verts * 6; i += blockDim.x) gacc[i] = 0.0f;
+    __syncthreads();
+    int lx, ly;
+    block_pixel(threadIdx.x, lx, ly);
+    const int px = bxi * kBlockPix + lx, py = byi * kBlockPix + ly;
+    const long long pl = (long long)py * c.W + px;
+    const long long pg = c.pix0 + pl;
+    float g[3] = {0.0f, 0.0f, 0.0f};
+    if (px < c.W && py < c.H) {
+        const float inv = 1.0f / (float)a.spp;
+        g[0] = a.dimage[3 * pg] * inv; g[1] = a.dimage[3 * pg + 1] * inv; g[2] = a.dimage[3 * pg + 2] * inv;
+    }
+    const bool live = g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f;
+    const int hand = c.hand;
+    const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
+    const Tri* tris = a.tris + (size_t)hand * a.n_faces;
+    const float* normals = a.normals + (size_t)hand * a.n_verts * 3;
+    const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
+    float* gtex = a.grad_albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
+    int* stk = stack + threadIdx.x;
+    const uint64_t c2 = (uint64_t)(uint32_t)wk.x | (kDomainCamera << 32);
+    const Shading S = a.shading;
+    if (live) {
+        for (int q = 0; q < (a.spp + 3) / 4; ++q) {
+            U64x4 r = philox4x64((uint64_t)pl, (uint64_t)q, c2, (uint64_t)a.iter, a.seed, 0);
+            for (int j = 0; j < 4; ++j) {
+                const int s = 4 * q + j;
+                if (s >= a.spp) break;
+                float u = u24_lo(r.x[j]), v = u24_hi(r.x[j]);
+                float sx = (float)px + u, sy = (float)py + v;
+                Ray ray;
+                ray_screen(c, sx, sy, ray);
+                Hit h;
+                trace(nodes, tris, ray, stk, kThreads, h);
+                if (h.face < 0) continue;
+                Surf sf;
+                surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
+                Shade sd;
+                shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, S, sd);
+                // colour map texels
+                for (int k = 0; k < 4; ++k) {
+                    float wk2 = sd.shade * sd.w[k];
+                    for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * sd.idx[k] + ch, g[ch] * wk2);
+                }
+                const float gs = g[0] * sd.col[0] + g[1] * sd.col[1] + g[2] * sd.col[2];
+                float gtu = 0.0f, gtv = 0.0f;
+                for (int ch = 0; ch < 3; ++ch) {
+                    gtu += g[ch] * sd.shade * sd.dcol_du[ch];
+                    gtv += g[ch] * sd.shade * sd.dcol_dv[ch];
+                }
+                const float2 uv0 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i0);
+                const float2 uv1 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i1);
+                const float2 uv2 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i2);
+                float gb1 = gtu * (uv1.x - uv0.x) + gtv * (uv1.y - uv0.y);
+                float gb2 = gtu * (uv2.x - uv0.x) + gtv * (uv2.y - uv0.y);
+                if (sd.ndotl > 0.0f) {
+                    float gn[3] = {gs * S.kd * S.l[0], gs * S.kd * S.l[1], gs * S.kd * S.l[2]};
+                    float gnn = gn[0] * sd.n[0] + gn[1] * sd.n[1] + gn[2] * sd.n[2];
+                    float inl = 1.0f / sd.nlen;
+                    float gr[3];
+                    for (int k = 0; k < 3; ++k) gr[k] = (gn[k] - gnn * sd.n[k]) * inl;
+                    const float* n0 = normals + 3 * sf.i0;
+                    const float* n1 = normals + 3 * sf.i1;
+                    const float* n2 = normals + 3 * sf.i2;
+                    for (int k = 0; k < 3; ++k) {
+                        atomicAdd(gacc + 6 * sf.i0 + 3 + k, sf.b0 * gr[k]);
+                        atomicAdd(gacc + 6 * sf.i1 + 3 + k, sf.b1 * gr[k]);
+                        atomicAdd(gacc + 6 * sf.i2 + 3 + k, sf.b2 * gr[k]);
+                        gb1 += gr[k] * (n1[k] - n0[k]);
+                        gb2 += gr[k] * (n2[k] - n0[k]);
+                    }
+                }
+                // hit point: y = M^{-T} [gb1, gb2, 0], M = [v1-v0, v2-v0, -d] (float64)
+                double e1[3], e2[3], md[3];
+                for (int k = 0; k < 3; ++k) {
+                    e1[k] = (double)sf.v[3 + k] - (double)sf.v[k];
+                    e2[k] = (double)sf.v[6 + k] - (double)sf.v[k];
+                    md[k] = -sf.d[k];
+                }
+                double c23[3] = {e2[1] * md[2] - e2[2] * md[1], e2[2] * md[0] - e2[0] * md[2], e2[0] * md[1] - e2[1] * md[0]};
+                double c31[3] = {md[1] * e1[2] - md[2] * e1[1], md[2] * e1[0] - md[0] * e1[2], md[0] * e1[1] - md[1] * e1[0]};
+                double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+                double idet = 1.0 / det;
+                float y[3];
+                for (int k = 0; k < 3; ++k) y[k] = (float)(((double)gb1 * c23[k] + (double)gb2 * c31[k]) * idet);
+                for (int k = 0; k < 3; ++k) {
+                    atomicAdd(gacc + 6 * sf.i0 + k, -sf.b0 * y[k]);
+                    atomicAdd(gacc + 6 * sf.i1 + k, -sf.b1 * y[k]);
+                    atomicAdd(gacc + 6 * sf.i2 + k, -sf.b2 * y[k]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    float* gout = a.gacc + (size_t)hand * a.n_verts * 6;
+    for (int i = threadIdx.x; i < a.n_verts * 6; i += blockDim.x) {
+        float x = gacc[i];
+        if (x != 0.0f) unsafeAtomicAdd(gout + i, x);
+    }
+}
+
+// ===========================================================================
+// silhouette edges: classification, quantised weights, prefix sums
+// ===========================================================================
+
+__global__ void __launch_bounds__(256) k_edges_setup(EdgeArgs a)
+{
+    __shared__ unsigned long long part[256];
+    const int vi = blockIdx.x;
+    const ViewDev c = a.views[vi];
+    const float* vh = a.verts + (size_t)c.hand * a.m.V * 3;
+    const int E = a.m.E;
+    EdgeRec* rec = a.rec + (size_t)vi * E;
+    unsigned long long* cdf = a.cdf + (size_t)vi * E;
+    const int per = (E + blockDim.x - 1) / blockDim.x;
+    const int e0 = threadIdx.x * per;
+    const int e1 = min(E, e0 + per);
+    unsigned long long local = 0;
+    for (int e = e0; e < e1; ++e) {
+        EdgeRec r;
+        r.ax = r.ay = r.bx = r.by = r.t0 = r.t1 = 0.0f;
+        r.w = 0; r.pad = 0;
+        const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
+        const float* pa = vh + 3 * va;
+        int front[2] = {0, 0};
+        const int nf = a.m.edge_faces[2 * e + 1] < 0 ? 1 : 2;
+        for (int k = 0; k < nf; ++k) {
+            const int f = a.m.edge_faces[2 * e + k];
+            const float* p0 = vh + 3 * a.m.faces[3 * f];
+            const float* p1 = vh + 3 * a.m.faces[3 * f + 1];
+            const float* p2 = vh + 3 * a.m.faces[3 * f + 2];
+            float u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+            float w[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+            float n0 = u[1] * w[2] - u[2] * w[1];
+            float n1 = u[2] * w[0] - u[0] * w[2];
+            float n2 = u[0] * w[1] - u[1] * w[0];
+            float w0 = c.o[0] - pa[0], w1 = c.o[1] - pa[1], w2 = c.o[2] - pa[2];
+            float dd = (n0 * w0 + n1 * w1) + n2 * w2;
+            front[k] = dd > 0.0f;
+        }
+        const bool sil = nf == 1 || front[0] != front[1];
+        float ax, ay, bx, by;
+        if (sil && project32(c, pa, ax, ay) && project32(c, vh + 3 * vb, bx, by)) {
+            // Liang-Barsky clip to [0,W] x [0,H]
+            float dx = bx - ax, dy = by - ay;
+            float lo = 0.0f, hi = 1.0f;
+            const float pp[4] = {-dx, dx, -dy, dy};
+            const float qq[4] = {ax, (float)c.W - ax, ay, (float)c.H - ay};
+            bool ok = true;
+            for (int k = 0; k < 4; ++k) {
+                if (pp[k] == 0.0f) {
+                    if (qq[k] < 0.0f) ok = false;
+                } else {
+                    float rr = qq[k] / pp[k];
+                    if (pp[k] < 0.0f) { if (rr > lo) lo = rr; }
+                    else { if (rr < hi) hi = rr; }
+                }
+            }
+            const float len = sqrtf(dx * dx + dy * dy);
+            if (ok && lo < hi && len > 0.0f) {
+                float ell = len * (hi - lo);
+                float qv = floorf(ell * 256.0f);
+                uint32_t wq = qv >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)qv;
+                if (wq == 0) wq = 1;
+                r.ax = ax; r.ay = ay; r.bx = bx; r.by = by; r.t0 = lo; r.t1 = hi; r.w = wq;
+            }
+        }
+        rec[e] = r;
+        local += r.w;
+    }
+    part[threadIdx.x] = local;
+    __syncthreads();
+    // inclusive scan of the per-thread totals (Hillis-Steele)
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        unsigned long long x = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0ull;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    unsigned long long run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0ull;
+    for (int e = e0; e < e1; ++e) {
+        run += rec[e].w;
+        cdf[e] = run;
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        const unsigned long long T = part[threadIdx.x];
+        a.total[vi] = T;
+        a.budget[vi] = (long long)((T + 255ull) / 256ull);
+    }
+}
+
+// ===========================================================================
+// edge sampling (boundary term)
+// ===========================================================================
+
+__device__ __forceinline__ void shade_or_bg(const Hit& h, const Tri* tris, const ViewDev& c, float X, float Y,
+                                            const float* normals, const float* uv, const float* tex, int th,
+                                            int tw, const Shading& S, const float* bg, float* out)
+{
+    if (h.face >= 0) {
+        Surf sf;
+        surface(tris, uv, h.slot, c, (double)X, (double)Y, sf);
+        Shade sd;
+        shade_hit(sf, normals, uv, tex, th, tw, S, sd);
+        for (int ch = 0; ch < 3; ++ch) out[ch] = sd.col[ch] * sd.shade;
+    } else {
+        for (int ch = 0; ch < 3; ++ch) out[ch] = bg[ch];
+    }
+}
+
+__device__ __forceinline__ void proj_jacobian(const ViewDev& c, const float* v, float J[2][3])
+{
+    float q[3] = {v[0] - c.o[0], v[1] - c.o[1], v[2] - c.o[2]};
+    float xc[3];
+    matvec3(c.R, q, xc);
+    float iz = 1.0f / xc[2];
+    float d[2][3] = {{c.fx * iz, 0.0f, -c.fx * xc[0] * iz * iz}, {0.0f, c.fy * iz, -c.fy * xc[1] * iz * iz}};
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) J[r][k] = d[r][0] * c.R[k] + d[r][1] * c.R[3 + k] + d[r][2] * c.R[6 + k];
+}
+
+__global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
+{
+    __shared__ int stack[kMaxStack * kThreads];
+    const int vi = blockIdx.y;
+    const ViewDev c = a.views[vi];
+    const long long M = a.budget[vi];
+    const unsigned long long T = a.total[vi];
+    if (M == 0 || T == 0) return;
+    const int E = a.m.E;
+    const EdgeRec* rec = a.rec + (size_t)vi * E;
+    const unsigned long long* cdf = a.cdf + (size_t)vi * E;
+    const int hand = c.hand;
+    const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
+    const Tri* tris = a.tris + (size_t)hand * a.m.F;
+    const float* normals = a.normals + (size_t)hand * a.m.V * 3;
+    const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
+    const float* vh = a.verts + (size_t)hand * a.m.V * 3;
+    float* gout = a.gacc + (size_t)hand * a.m.V * 6;
+    int* stk = stack + threadIdx.x;
+    const uint64_t c2 = (uint64_t)(uint32_t)vi | (kDomainEdge << 32);
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < M;
+         k += (long long)gridDim.x * blockDim.x) {
+        U64x4 r = philox4x64((uint64_t)k, 0, c2, (uint64_t)a.iter, a.seed, 0);
+        const unsigned long long target = __umul64hi(r.x[0], T);
+        int lo = 0, hi = E - 1;   // first e with cdf[e] > target
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        const int e = lo;
+        const EdgeRec q = rec[e];
+        const float u = u24_hi(r.x[1]);
+        const float t = q.t0 + u * (q.t1 - q.t0);
+        const float dx = q.bx - q.ax, dy = q.by - q.ay;
+        const float x = q.ax + t * dx;
+        const float y = q.ay + t * dy;
+        const float len = sqrtf(dx * dx + dy * dy);
+        const float nhx = dy / len, nhy = -dx / len;
+        const float xp = x + a.delta * nhx, yp = y + a.delta * nhy;
+        const float xm = x - a.delta * nhx, ym = y - a.delta * nhy;
+        int px = (int)floorf(x), py = (int)floorf(y);
+        px = min(max(px, 0), c.W - 1);
+        py = min(max(py, 0), c.H - 1);
+        const long long pg = c.pix0 + (long long)py * c.W + px;
+        const float g[3] = {a.dimage[3 * pg], a.dimage[3 * pg + 1], a.dimage[3 * pg + 2]};
+        if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) continue;
+        const float bg[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
+        float cp[3], cm[3];
+        Ray ray;
+        Hit h;
+        ray_screen(c, xp, yp, ray);
+        trace(nodes, tris, ray, stk, kThreads, h);
+        shade_or_bg(h, tris, c, xp, yp, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, cp);
+        ray_screen(c, xm, ym, ray);
+        trace(nodes, tris, ray, stk, kThreads, h);
+        shade_or_bg(h, tris, c, xm, ym, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, cm);
+        const float jump = g[0] * (cm[0] - cp[0]) + g[1] * (cm[1] - cp[1]) + g[2] * (cm[2] - cp[2]);
+        if (jump == 0.0f) continue;
+        const float ell = len * (q.t1 - q.t0);
+        const float s = jump * (ell * (float)T / ((float)q.w * (float)M));
+        const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
+        float Ja[2][3], Jb[2][3];
+        proj_jacobian(c, vh + 3 * va, Ja);
+        proj_jacobian(c, vh + 3 * vb, Jb);
+        const float sa = (1.0f - t) * s, sb = t * s;
+        for (int k3 = 0; k3 < 3; ++k3) {
+            unsafeAtomicAdd(gout + 6 * va + k3, sa * (Ja[0][k3] * nhx + Ja[1][k3] * nhy));
+            unsafeAtomicAdd(gout + 6 * vb + k3, sb * (Jb[0][k3] * nhx + Jb[1][k3] * nhy));
+        }
+    }
+}
+
+// ===========================================================================
+// normals backward + skinning backward (one block per hand)
+// ===========================================================================
+
+__global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* __restrict__ params,
+                                                       const float* __restrict__ verts,
+                                                       const float* __restrict__ gacc,
+                                                       float* __restrict__ grad_params,
+                                                       float* __restrict__ grad_verts,
+                                                       float* __restrict__ grad_normals)
+{
+    extern __shared__ float dyn[];
+    __shared__ SkinShared sh;
+    __shared__ float gJ[kMaxJoints * 3];
+    __shared__ float gAt[kMaxJoints * 3];
+    __shared__ float gGR[kMaxJoints * 9];
+    __shared__ float gmisc[16];
+    const int h = blockIdx.x;
+    const int V = m.V, F = m.F, J = m.J, K = m.K;
+    float* vsh = dyn;              // posed vertices [V*3]
+    float* fn = vsh + 3 * V;       // raw face normals [F*3]
+    float* graw = fn + 3 * F;      // dL/d(raw vertex normal) [V*3]
+    float* gv = graw + 3 * V;      // total dL/dv [V*3]
+    float* vs = gv + 3 * V;        // shaped vertices [V*3]
+    const float* vh = verts + (size_t)h * V * 3;
+    const float* ga = gacc + (size_t)h * V * 6;
+    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
+    __syncthreads();
+    for (int f = threadIdx.x; f < F; f += blockDim.x) {
+        int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
+        float e1[3] = {vsh[3 * b] - vsh[3 * a], vsh[3 * b + 1] - vsh[3 * a + 1], vsh[3 * b + 2] - vsh[3 * a + 2]};
+        float e2[3] = {vsh[3 * c] - vsh[3 * a], vsh[3 * c + 1] - vsh[3 * a + 1], vsh[3 * c + 2] - vsh[3 * a + 2]};
+        fn[3 * f] = e1[1] * e2[2] - e1[2] * e2[1];
+        fn[3 * f + 1] = e1[2] * e2[0] - e1[0] * e2[2];
+        fn[3 * f + 2] = e1[0] * e2[1] - e1[1] * e2[0];
+    }
+    __syncthreads();
+    // unit normal n = s/|s|: dL/ds = (gn - (gn.n) n) / |s|
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        float s[3] = {0.0f, 0.0f, 0.0f};
+        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+            int f = m.vf_faces[k];
+            s[0] += fn[3 * f]; s[1] += fn[3 * f + 1]; s[2] += fn[3 * f + 2];
+        }
+        float len = sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        float il = 1.0f / len;
+        float n[3] = {s[0] * il, s[1] * il, s[2] * il};
+        float gn[3] = {ga[6 * v + 3], ga[6 * v + 4], ga[6 * v + 5]};
+        if (grad_normals) {
+            float* o = grad_normals + ((size_t)h * V + v) * 3;
+            o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
+        }
+        float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+        for (int k = 0; k < 3; ++k) graw[3 * v + k] = (gn[k] - d * n[k]) * il;
+    }
+    __syncthreads();
+    // face normal f = e1 x e2: dL/de1 = e2 x gf, dL/de2 = gf x e1, gathered per vertex
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        float acc[3] = {ga[6 * v], ga[6 * v + 1], ga[6 * v + 2]};
+        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+            int f = m.vf_faces[k];
+            int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
+            float gf[3];
+            for (int q = 0; q < 3; ++q) gf[q] = graw[3 * a + q] + graw[3 * b + q] + graw[3 * c + q];
+            float e1[3] = {vsh[3 * b] - vsh[3 * a], vsh[3 * b + 1] - vsh[3 * a + 1], vsh[3 * b + 2] - vsh[3 * a + 2]};
+            float e2[3] = {vsh[3 * c] - vsh[3 * a], vsh[3 * c + 1] - vsh[3 * a + 1], vsh[3 * c + 2] - vsh[3 * a + 2]};
+            float g1[3] = {e2[1] * gf[2] - e2[2] * gf[1], e2[2] * gf[0] - e2[0] * gf[2], e2[0] * gf[1] - e2[1] * gf[0]};
+            float g2[3] = {gf[1] * e1[2] - gf[2] * e1[1], gf[2] * e1[0] - gf[0] * e1[2], gf[0] * e1[1] - gf[1] * e1[0]};
+            if (v == a) for (int q = 0; q < 3; ++q) acc[q] -= g1[q] + g2[q];
+            else if (v == b) for (int q = 0; q < 3; ++q) acc[q] += g1[q];
+            else for (int q = 0; q < 3; ++q) acc[q] += g2[q];
+        }
+        for (int q = 0; q < 3; ++q) gv[3 * v + q] = acc[q];
+        if (grad_verts) {
+            float* o = grad_verts + ((size_t)h * V + v) * 3;
+            o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2];
+        }
+    }
+    __syncthreads();
+    // ---- skinning backward ----
+    const float* p = params + 64 * h;
+    skin_common(m, p, vs, sh);
+    // global transform: v = Rp vp + tau
+    {
+        float part[12];
+        for (int i = 0; i < 12; ++i) part[i] = 0.0f;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            float vp[3];
+            blend_vertex(m, vs, sh, v, vp);
+            const float* g = gv + 3 * v;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) part[3 * i + j] += g[i] * vp[j];
+            part[9] += g[0]; part[10] += g[1]; part[11] += g[2];
+        }
+        float out[12];
+        block_sum<12>(part, sh.red, out);
+        if (threadIdx.x < 12) gmisc[threadIdx.x] = out[threadIdx.x];
+    }
+    __syncthreads();
+    // per joint: dL/dGR_j = sum_v W_vj gvp_v vs_v^T, dL/dAt_j = sum_v W_vj gvp_v
+    for (int j = 0; j < J; ++j) {
+        float part[12];
+        for (int i = 0; i < 12; ++i) part[i] = 0.0f;
+        for (int v = threadIdx.x; v < V; v += blockDim.x) {
+            float w = m.weights[(size_t)v * J + j];
+            if (w == 0.0f) continue;
+            float gvp[3];
+            matTvec3(sh.Rp, gv + 3 * v, gvp);
+            for (int i = 0; i < 3; ++i) {
+                for (int k = 0; k < 3; ++k) part[3 * i + k] += w * gvp[i] * vs[3 * v + k];
+                part[9 + i] += w * gvp[i];
+            }
+        }
+        float out[12];
+        block_sum<12>(part, sh.red, out);
+        if (threadIdx.x < 9) gGR[9 * j + threadIdx.x] = out[threadIdx.x];
+        if (threadIdx.x < 3) gAt[3 * j + threadIdx.x] = out[9 + threadIdx.x];
+    }
+    __syncthreads();
+    float* gp = grad_params + 64 * h;
+    if (threadIdx.x == 0) {
+        float gGt[kMaxJoints * 3];
+        for (int j = 0; j < J; ++j)
+            for (int i = 0; i < 3; ++i) { gGt[3 * j + i] = gAt[3 * j + i]; gJ[3 * j + i] = 0.0f; }
+        // At_j = Gt_j - GR_j J_j
+        for (int j = 0; j < J; ++j) {
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] -= gAt[3 * j + i] * sh.J[3 * j + k];
+            float y[3];
+            matTvec3(sh.GR + 9 * j, gAt + 3 * j, y);
+            for (int i = 0; i < 3; ++i) gJ[3 * j + i] -= y[i];
+        }
+        float gR[kMaxJoints * 9];
+        for (int j = J - 1; j >= 0; --j) {
+            int par = m.parents[j];
+            if (par < 0) {
+                for (int i = 0; i < 9; ++i) gR[9 * j + i] = gGR[9 * j + i];
+                for (int i = 0; i < 3; ++i) gJ[3 * j + i] += gGt[3 * j + i];
+                continue;
+            }
+            const float* GRp = sh.GR + 9 * par;
+            const float* Rj = sh.Rj + 9 * j;
+            float d[3] = {sh.J[3 * j] - sh.J[3 * par], sh.J[3 * j + 1] - sh.J[3 * par + 1],
+                          sh.J[3 * j + 2] - sh.J[3 * par + 2]};
+            // Gt_j = GRp d + Gt_p ; GR_j = GRp Rj
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    float s = gGt[3 * j + i] * d[k];
+                    for (int q = 0; q < 3; ++q) s += gGR[9 * j + 3 * i + q] * Rj[3 * k + q];
+                    gGR[9 * par + 3 * i + k] += s;
+                }
+            float y[3];
+            matTvec3(GRp, gGt + 3 * j, y);
+            for (int i = 0; i < 3; ++i) { gJ[3 * j + i] += y[i]; gJ[3 * par + i] -= y[i]; gGt[3 * par + i] += gGt[3 * j + i]; }
+            for (int i = 0; i < 3; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    float s = 0.0f;
+                    for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
+                    gR[9 * j + 3 * i + k] = s;
+                }
+        }
+        for (int j = 0; j < J; ++j) {
+            Rod rd;
+            rodrigues(p + 3 * j, rd);
+            rodrigues_bwd(p + 3 * j, rd, gR + 9 * j, gp + 3 * j);
+        }
+        for (int j = J; j < 16; ++j) gp[3 * j] = gp[3 * j + 1] = gp[3 * j + 2] = 0.0f;
+        Rod rp;
+        rodrigues(p + 58, rp);
+        rodrigues_bwd(p + 58, rp, gmisc, gp + 58);
+        gp[61] = gmisc[9]; gp[62] = gmisc[10]; gp[63] = gmisc[11];
+    }
+    __syncthreads();
+    // shaped vertices: dL/dvs_v = sum_j W_vj GR_j^T gvp_v + sum_j Jreg_jv gJ_j
+    float part[16];
+    for (int k = 0; k < 16; ++k) part[k] = 0.0f;
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        float gvp[3], g[3] = {0.0f, 0.0f, 0.0f};
+        matTvec3(sh.Rp, gv + 3 * v, gvp);
+        for (int j = 0; j < J; ++j) {
+            float w = m.weights[(size_t)v * J + j];
+            float jr = m.j_regressor[(size_t)j * V + v];
+            if (w != 0.0f) {
+                float y[3];
+                matTvec3(sh.GR + 9 * j, gvp, y);
+                for (int c = 0; c < 3; ++c) g[c] += w * y[c];
+            }
+            if (jr != 0.0f)
+                for (int c = 0; c < 3; ++c) g[c] += jr * gJ[3 * j + c];
+        }
+        for (int c = 0; c < 3; ++c) {
+            const float* sd = m.shapedirs + (3 * v + c) * K;
+            for (int k = 0; k < K; ++k) part[k] += sd[k] * g[c];
+        }
+    }
+    float out[16];
+    block_sum<16>(part, sh.red, out);
+    if (threadIdx.x < K) gp[48 + threadIdx.x] = out[threadIdx.x];
+    if (threadIdx.x >= K && threadIdx.x < 10) gp[48 + threadIdx.x] = 0.0f;
+}
+
+// ===========================================================================
+// Adam
+// ===========================================================================
+
+__global__ void __launch_bounds__(256) k_adam(AdamArgs a)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long np = 64ll * a.n_hands;
+    const long long n = np + a.n_albedo;
+    if (i >= n) return;
+    float lr;
+    float *x, *m, *v;
+    float g;
+    if (i < np) {
+        const int k = (int)(i % 64);
+        lr = k < 3 ? a.lr[0] : k < 48 ? a.lr[1] : k < 58 ? a.lr[2] : k < 61 ? a.lr[3] : a.lr[4];
+        x = a.params + i; m = a.m_params + i; v = a.v_params + i; g = a.grad_params[i];
+    } else {
+        const long long j = i - np;
+        lr = a.lr[5];
+        x = a.albedo + j; m = a.m_albedo + j; v = a.v_albedo + j; g = a.grad_albedo[j];
+    }
+    if (lr == 0.0f) return;
+    const float m2 = a.beta1 * *m + (1.0f - a.beta1) * g;
+    const float v2 = a.beta2 * *v + (1.0f - a.beta2) * g * g;
+    *m = m2;
+    *v = v2;
+    const float mh = m2 / a.bc1, vh = v2 / a.bc2;
+    float x2 = *x - lr * mh / (sqrtf(vh) + a.eps);
+    if (i >= np) x2 = fminf(fmaxf(x2, 0.0f), 1.0f);
+    *x = x2;
+}
+
+// ===========================================================================
+// utilities
+// ===========================================================================
+
+__global__ void k_fill(float* __restrict__ p, long long n, float v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace hr

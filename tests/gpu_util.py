@@ -1,0 +1,65 @@
+"""Shared set-up of the GPU parity tests: one scene, the same float32 inputs
+handed to the HIP path and to the oracle."""
+import numpy as np
+import torch
+
+import oracle
+from paper_2107_05509_amd import binding, scene
+
+DEV = "cuda:0"
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32)
+
+
+class Case:
+    """A workload with float32 inputs shared by both sides."""
+
+    def __init__(self, w: scene.Workload, n_views=None, seed=5):
+        self.w = w
+        cams = w.cams if n_views is None else w.cams[:n_views]
+        self.cams = cams
+        self.model = w.model
+        self.om = oracle.Model(w.model)
+        tab = scene.camera_arrays(cams)
+        self.tab = tab
+        self.osc = oracle.Scene(w.model.faces, w.model.uv, tab, scene.SHADING, w.model.edges, w.model.edge_faces)
+        th, tw = w.albedo_true.shape[1:3]
+        self.th, self.tw = th, tw
+        self.seed = seed
+        self.gsc = binding.Scene(w.model, cams, w.n_hands, w.spp, th, tw, seed=seed)
+        self.P = int(tab["pix_off"][-1])
+        bg = np.concatenate([b.reshape(-1, 3) for b in w.backgrounds[:len(cams)]])
+        self.bg = f32(bg)
+        self.params = f32(w.params_init)
+        self.albedo = f32(w.albedo_true)
+        # the oracle's skinning gives the float32 vertices both renderers take
+        v, _ = oracle.skin(self.om, torch.as_tensor(self.params.astype(np.float64)))
+        self.v32 = f32(v.numpy())
+        self.n64 = oracle.vertex_normals(torch.as_tensor(self.v32.astype(np.float64)), self.om.faces).numpy()
+
+    def t(self, a, dtype=torch.float32):
+        return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype)
+
+    def gpu_render(self, it=0, hits=False):
+        img = torch.empty(self.P, 3, device=DEV)
+        hf = torch.empty(self.P, self.w.spp, device=DEV, dtype=torch.int32) if hits else None
+        self.gsc.render(self.t(self.v32), self.t(self.albedo), self.t(self.bg), it, img, hf)
+        torch.cuda.synchronize()
+        return (img.cpu().numpy(), hf.cpu().numpy() if hits else None)
+
+    def oracle_render(self, it=0, hits=False):
+        return oracle.render(self.osc, self.v32, self.n64, self.albedo, self.bg, self.w.spp, self.seed, it,
+                             want_hits=hits)
+
+
+def rel_err(a, b, floor=1e-3):
+    return np.abs(a - b) / np.maximum(np.abs(b), floor)
+
+
+def block_rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / max(nb, 1e-30)

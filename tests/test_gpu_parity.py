@@ -1,0 +1,179 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, stage by stage,
+on identical float32 inputs: the tiny workload (4 views 64x64, 4 spp) and
+edge cases.  Bars: triangle ids of every sample bit-exact; images 1e-5
+relative; gradients 1e-4 relative per block."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import DEV, Case, block_rel, f32, rel_err
+from paper_2107_05509_amd import binding, scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("case: tiny workload, seed 0", flush=True)
+    return Case(scene.workload_tiny(0))
+
+
+def test_skin_parity(tiny):
+    c = tiny
+    for p in (c.w.params_true, c.w.params_init):
+        p32 = f32(p)
+        verts = torch.empty(1, c.model.n_verts, 3, device=DEV)
+        joints = torch.empty(1, 16, 3, device=DEV)
+        c.gsc.skin(c.t(p32), verts, joints)
+        torch.cuda.synchronize()
+        v, j = oracle.skin(c.om, torch.as_tensor(p32.astype(np.float64)))
+        scale = np.abs(v.numpy()).max()
+        assert np.abs(verts.cpu().numpy() - v.numpy()).max() <= 1e-5 * scale
+        assert np.abs(joints.cpu().numpy() - j.numpy()).max() <= 1e-5 * scale
+
+
+def test_render_parity(tiny):
+    c = tiny
+    for it in (0, 3):
+        img_g, hit_g = c.gpu_render(it, hits=True)
+        img_o, hit_o = c.oracle_render(it, hits=True)
+        assert np.array_equal(hit_g, hit_o), f"hit ids differ on {(hit_g != hit_o).sum()} samples"
+        assert (hit_o >= 0).mean() > 0.02
+        e = rel_err(img_g, img_o)
+        print("image rel err: max %.3g p99.9 %.3g p99 %.3g" % (e.max(), np.quantile(e, 0.999), np.quantile(e, 0.99)),
+              flush=True)
+        assert e.max() <= 1e-5
+
+
+def test_loss_parity(tiny):
+    c = tiny
+    img, _ = c.gpu_render(0)
+    rng = np.random.default_rng(1)
+    target = f32(np.clip(img + rng.normal(0, 0.05, img.shape), 0, 1))
+    target[::7] = img[::7]  # exact ties: sign(0) = 0
+    mask = (rng.uniform(0, 1, c.P) < 0.8).astype(np.uint8)
+    mask[c.tab["pix_off"][2]:c.tab["pix_off"][3]] = 0   # a view with an empty mask
+    loss = torch.empty(1, device=DEV)
+    dimg = torch.empty(c.P, 3, device=DEV)
+    c.gsc.loss(c.t(img), c.t(target), c.t(mask, torch.uint8), loss, dimg)
+    torch.cuda.synchronize()
+    lo, do = oracle.l1_loss(img, target, mask, c.tab["pix_off"], c.tab["hand"], 1)
+    assert abs(loss.item() - lo[0]) <= 1e-5 * abs(lo[0])
+    dg = dimg.cpu().numpy()
+    assert np.array_equal(np.sign(dg), np.sign(do))
+    assert rel_err(dg, do, 1e-30).max() <= 1e-6
+
+
+def _dimage(c, img):
+    rng = np.random.default_rng(2)
+    target = np.clip(img + rng.normal(0, 0.1, img.shape), 0, 1)
+    _, d = oracle.l1_loss(img, target, None, c.tab["pix_off"], c.tab["hand"], 1)
+    return f32(d)
+
+
+def _oracle_grads(c, dimage, flags):
+    v64 = c.v32.astype(np.float64)
+    ga = np.zeros((1, c.th, c.tw, 3))
+    gv = np.zeros_like(v64[None] if v64.ndim == 2 else v64)
+    gn = np.zeros_like(gv)
+    if flags & binding.HR_GRAD_INTERIOR:
+        ga, gvi, gn = oracle.backward_interior(c.osc, v64, c.n64, c.albedo, dimage, c.w.spp, c.seed, 0)
+        gv = gv + gvi
+    if flags & binding.HR_GRAD_EDGES:
+        gv = gv + oracle.backward_edges(c.osc, v64, c.n64, c.albedo, c.bg, dimage, c.seed, 0, 1e-3)
+    # through normals and skinning (float64 autograd)
+    p = torch.as_tensor(c.params.astype(np.float64)).requires_grad_(True)
+    vs, _ = oracle.skin(c.om, p)
+    vt = torch.as_tensor(v64).requires_grad_(True)
+    nt = oracle.vertex_normals(vt, c.om.faces)
+    torch.autograd.backward([nt], [torch.as_tensor(gn)])
+    gv_total = gv + vt.grad.numpy()
+    torch.autograd.backward([vs], [torch.as_tensor(gv_total)])
+    return dict(ga=ga, gn=gn, gv=gv_total, gp=p.grad.numpy())
+
+
+def _gpu_grads(c, dimage, flags):
+    gp = torch.empty(1, 64, device=DEV)
+    ga = torch.empty(1, c.th, c.tw, 3, device=DEV)
+    gv = torch.empty(1, c.model.n_verts, 3, device=DEV)
+    gn = torch.empty(1, c.model.n_verts, 3, device=DEV)
+    c.gsc.backward(c.t(c.params), c.t(c.v32), c.t(c.albedo), c.t(c.bg), c.t(dimage), 0, gp, ga, gv, gn, flags)
+    torch.cuda.synchronize()
+    return dict(ga=ga.cpu().numpy(), gn=gn.cpu().numpy(), gv=gv.cpu().numpy(), gp=gp.cpu().numpy())
+
+
+def test_interior_adjoint_parity(tiny):
+    c = tiny
+    img, _ = c.gpu_render(0)
+    d = _dimage(c, img)
+    g = _gpu_grads(c, d, binding.HR_GRAD_INTERIOR)
+    o = _oracle_grads(c, d, binding.HR_GRAD_INTERIOR)
+    for k in ("ga", "gn", "gv"):
+        e = block_rel(g[k], o[k])
+        print(k, e, flush=True)
+        assert e <= 1e-4, k
+    _check_params(g["gp"], o["gp"])
+
+
+def test_edge_term_parity(tiny):
+    c = tiny
+    img, _ = c.gpu_render(0)
+    d = _dimage(c, img)
+    g = _gpu_grads(c, d, binding.HR_GRAD_EDGES)
+    o = _oracle_grads(c, d, binding.HR_GRAD_EDGES)
+    tot, bud = c.gsc.edge_stats()
+    w, cdf, tot_o, bud_o = oracle.edge_weights(c.osc, c.v32.astype(np.float64))
+    assert np.array_equal(tot, tot_o) and np.array_equal(bud, bud_o)
+    assert bud.min() > 10
+    e = block_rel(g["gv"], o["gv"])
+    print("gv", e, flush=True)
+    assert e <= 1e-4
+    _check_params(g["gp"], o["gp"])
+
+
+def _check_params(gp, op):
+    blocks = {"pose": slice(0, 48), "shape": slice(48, 58), "global": slice(58, 64)}
+    for name, sl in blocks.items():
+        e = block_rel(gp[:, sl], op[:, sl])
+        print(name, e, flush=True)
+        assert e <= 1e-4, name
+
+
+def test_adam_parity(tiny):
+    c = tiny
+    rng = np.random.default_rng(3)
+    p = f32(c.params)
+    a = f32(c.albedo)
+    gp_, ga_ = f32(rng.normal(0, 1, p.shape)), f32(rng.normal(0, 1, a.shape))
+    tp, ta = c.t(p), c.t(a)
+    mp, vp = torch.zeros_like(tp), torch.zeros_like(tp)
+    ma, va = torch.zeros_like(ta), torch.zeros_like(ta)
+    lrs = (0.0, 1e-2, 1e-2, 1e-2, 1e-3, 1e-2)
+    lr_vec = np.concatenate([[lrs[0]] * 3, [lrs[1]] * 45, [lrs[2]] * 10, [lrs[3]] * 3, [lrs[4]] * 3])
+    xo, mo, vo = p.astype(np.float64), np.zeros(p.shape), np.zeros(p.shape)
+    xa, ma_o, va_o = a.astype(np.float64), np.zeros(a.shape), np.zeros(a.shape)
+    for t in (1, 2, 3):
+        c.gsc.step(tp, ta, c.t(gp_), c.t(ga_), mp, vp, ma, va, t, lrs)
+        xo, mo, vo = oracle.adam_step(xo, gp_, mo, vo, t, lr_vec[None])
+        xa, ma_o, va_o = oracle.adam_step(xa, ga_, ma_o, va_o, t, lrs[5], lo=0.0, hi=1.0)
+    torch.cuda.synchronize()
+    assert np.abs(tp.cpu().numpy() - xo).max() <= 1e-6
+    assert np.abs(ta.cpu().numpy() - xa).max() <= 1e-6
+    assert np.array_equal(tp.cpu().numpy()[:, :3], p[:, :3])
+
+
+def test_background_only_view(tiny):
+    # a camera looking away from the hand: every pixel is its background, exactly
+    c = tiny
+    cam = scene.Camera(R=scene.look_at([0.0, 0.0, 0.6], [0.0, 0.0, 5.0]), o=np.array([0.0, 0.0, 0.6]),
+                       fx=80.0, fy=80.0, cx=16.0, cy=8.0, W=32, H=16)
+    g = binding.Scene(c.model, [cam], 1, 3, c.th, c.tw, seed=1)
+    bg = torch.rand(32 * 16, 3, device=DEV)
+    img = torch.empty_like(bg)
+    hf = torch.empty(32 * 16, 3, device=DEV, dtype=torch.int32)
+    g.render(c.t(c.v32), c.t(c.albedo), bg, 0, img, hf)
+    torch.cuda.synchronize()
+    assert torch.equal(img, bg) and bool((hf == -1).all())
