@@ -1,0 +1,234 @@
+#!/usr/bin/env python
+"""Throughput of one render-and-compare refinement iteration on one MI355X.
+
+Workload (synthetic stand-in for an InterHand2.6M-like multiframe): one
+procedural skinned hand seen by 8 calibrated cameras of 334x512 pixels on a
+0.6-0.9 m shell, 16 camera samples per pixel, a 512x512 RGB colour map, target
+images rendered from the true parameters at 64 samples per pixel, L1 loss over
+hand masks, Adam on the 64 hand parameters and the colour map.
+
+A step is one full iteration: skin -> render (vertex normals, BVH refit, screen
+bounds, ray tracing) -> L1 loss -> backward (interior adjoint, silhouette edge
+sampling, normals + skinning backward) -> Adam.  Inputs are resident in HBM
+before the timed region.  Steps 0..49 optimise the colour map only (warm-up
+phase of the paper's schedule); the timed steps follow with all variables.
+
+Prints one JSON line (see the design doc for the metric and roofline definitions).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2107_05509_amd import binding, scene  # noqa: E402
+
+METRIC = "fwd+bwd diff-render Mrays/s + refine iters/s (8 views 334x512, 16 spp)"
+PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 128 lanes x 2 x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic operations per unit of traversal work (FP32-equivalent)
+OPS_PER_RAY = 90       # ray generation (Philox share + camera transform) and set-up
+OPS_PER_NODE = 50      # two slab tests and the near/far order
+OPS_PER_TRI = 47       # watertight ray/triangle test
+OPS_PER_HIT = {"k_render": 150, "k_adjoint_interior": 300, "k_edge_sample": 150}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2107_05509_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def lr_schedule(it, warm=50):
+    """(root pose, pose, shape, global rotation, translation, albedo)."""
+    if it < warm:
+        return (0.0, 0.0, 0.0, 0.0, 0.0, 1e-2)
+    return (1e-2, 1e-2, 1e-2, 1e-2, 1e-3, 1e-2)
+
+
+class Refiner:
+    def __init__(self, w, dev="cuda:0", seed=0):
+        self.w = w
+        th, tw = w.albedo_true.shape[1:3]
+        self.g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=1000 + seed)
+        P = self.g.P
+        t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+        self.bg = t(w.packed_background().astype(np.float32))
+        # targets: true parameters, 64 samples per pixel, an independent sample key
+        gt = binding.Scene(w.model, w.cams, w.n_hands, 64, th, tw, seed=7000 + seed)
+        vt = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
+        gt.skin(t(w.params_true.astype(np.float32)), vt)
+        self.target = torch.empty(P, 3, device=dev)
+        hits = torch.empty(P, 64, device=dev, dtype=torch.int32)
+        gt.render(vt, t(w.albedo_true.astype(np.float32)), self.bg, 0, self.target, hits)
+        cover = (hits >= 0).any(1).float()
+        masks = []
+        off = w.pixel_offsets()
+        for i, c in enumerate(w.cams):
+            m = cover[off[i]:off[i + 1]].view(1, 1, c.H, c.W)
+            masks.append(torch.nn.functional.max_pool2d(m, 9, 1, 4).reshape(-1))
+        self.mask = (torch.cat(masks) > 0).to(torch.uint8).contiguous()
+        del hits, gt
+        self.params = t(w.params_init.astype(np.float32))
+        self.albedo = t(w.albedo_init.astype(np.float32))
+        self.mp, self.vp = torch.zeros_like(self.params), torch.zeros_like(self.params)
+        self.ma, self.va = torch.zeros_like(self.albedo), torch.zeros_like(self.albedo)
+        self.verts = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
+        self.image = torch.empty(P, 3, device=dev)
+        self.dimage = torch.empty(P, 3, device=dev)
+        self.loss = torch.empty(w.n_hands, device=dev)
+        self.gp = torch.empty_like(self.params)
+        self.ga = torch.empty_like(self.albedo)
+
+    def step(self, it):
+        g = self.g
+        g.skin(self.params, self.verts)
+        g.render(self.verts, self.albedo, self.bg, it, self.image)
+        g.loss(self.image, self.target, self.mask, self.loss, self.dimage)
+        g.backward(self.params, self.verts, self.albedo, self.bg, self.dimage, it, self.gp, self.ga,
+                   flags=binding.HR_GRAD_ALL | binding.HR_REUSE_GEOMETRY)
+        g.step(self.params, self.albedo, self.gp, self.ga, self.mp, self.vp, self.ma, self.va, it + 1,
+               lr_schedule(it))
+
+
+def cpu_baseline(w, ref, views=1):
+    """The oracle (float64, brute force, OpenMP) on the first `views` views of the
+    same workload: forward render + loss + interior adjoint + edge term."""
+    import oracle
+    oracle.build(force=False)
+    cams = w.cams[:views]
+    tab = scene.camera_arrays(cams)
+    osc = oracle.Scene(w.model.faces, w.model.uv, tab, scene.SHADING, w.model.edges, w.model.edge_faces)
+    om = oracle.Model(w.model)
+    P = int(tab["pix_off"][-1])
+    p = torch.as_tensor(w.params_init.astype(np.float32).astype(np.float64))
+    bg = ref.bg[:P].cpu().numpy().astype(np.float64)
+    alb = w.albedo_init.astype(np.float64)
+    target = ref.target[:P].cpu().numpy().astype(np.float64)
+    mask = ref.mask[:P].cpu().numpy()
+    t0 = time.perf_counter()
+    v, _ = oracle.skin(om, p)
+    n = oracle.vertex_normals(v, om.faces)
+    v, n = v.numpy(), n.numpy()
+    img = oracle.render(osc, v, n, alb, bg, w.spp, 1000, 60)
+    _, dimg = oracle.l1_loss(img, target, mask, tab["pix_off"], tab["hand"], 1)
+    oracle.backward_interior(osc, v, n, alb, dimg, w.spp, 1000, 60)
+    oracle.backward_edges(osc, v, n, alb, bg, dimg, 1000, 60)
+    dt = time.perf_counter() - t0
+    samples = P * w.spp
+    return {"value": samples / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{views} of {len(w.cams)} views ({cams[0].W}x{cams[0].H}), {w.spp} spp: forward render, "
+                      f"loss, interior adjoint and edge term, float64 brute force; {dt:.1f} s",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(DESIGN.md describes how the workload would shard)", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = scene.workload_realistic(args.seed)
+    print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
+    ref = Refiner(w, seed=args.seed)
+    it = 0
+    for _ in range(args.warmup):
+        ref.step(it)
+        it += 1
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    ref.g.timing_enable(True)
+    ref.g.timing_read()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        ref.step(it)
+        it += 1
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    kern = ref.g.timing_read()
+    ref.g.timing_enable(False)
+    ms = total_ms / args.steps
+    print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step, loss {ref.loss.item():.5f}", file=sys.stderr,
+          flush=True)
+    # work counts of one more iteration (untimed)
+    ref.g.set_counting(True)
+    ref.step(it)
+    counts = ref.g.read_counts()
+    ref.g.set_counting(False)
+    tot, bud = ref.g.edge_stats()
+    torch.cuda.synchronize()
+
+    cam_samples = sum(c.W * c.H for c in w.cams) * w.spp
+    traced = sum(int(counts[k][0]) for k in counts)
+    per_kernel = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "ms_per_step": v[0] / args.steps}
+                  for k, v in kern.items()}
+    for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        print(f"[bench]   {k:22s} {v['ms_per_launch'] * 1e3:9.1f} us/launch", file=sys.stderr)
+    # roofline of the dominant ray-tracing kernel
+    dom = max(("k_render", "k_adjoint_interior"), key=lambda k: per_kernel[k]["ms_per_step"])
+    rays, nodes, tris, hits = counts[dom]
+    ops = rays * OPS_PER_RAY + nodes * OPS_PER_NODE + tris * OPS_PER_TRI + hits * OPS_PER_HIT[dom]
+    ach = ops / (per_kernel[dom]["ms_per_launch"] * 1e-3) / 1e12
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tfile):
+        tj = json.load(open(tfile))
+        if tj.get("source_hash") == kernel_source_hash() and dom in tj.get("kernels", {}):
+            traffic = tj["kernels"][dom]
+    roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "kernel": dom,
+            "ops_per_launch": int(ops), "rays": int(rays), "node_visits": int(nodes), "tri_tests": int(tris),
+            "hits": int(hits)}
+    out = {
+        "metric": METRIC,
+        "value": round(cam_samples / (ms * 1e-3) / 1e6, 2),
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "realistic: 1 hand (778 verts, 1538 tris), 8 views 334x512, 16 spp, "
+                               "512x512 albedo, L1 over hand masks, Adam on 64 params + albedo",
+                   "views": len(w.cams), "W": 334, "H": 512, "spp": w.spp, "tex": 512,
+                   "camera_samples_per_step": cam_samples},
+        "refine_iters_per_s": round(1e3 / ms, 2),
+        "traced_mrays_per_s": round(traced / (ms * 1e-3) / 1e6, 2),
+        "edge_samples_per_step": int(bud.sum()),
+        "kernels": {k: round(v["ms_per_launch"] * 1e3, 2) for k, v in per_kernel.items()},
+        "kernels_unit": "us per launch",
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, ref, args.cpu_views)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

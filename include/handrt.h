@@ -176,6 +176,23 @@ int hr_step(hr_scene* scene, float* params, float* albedo, const float* grad_par
    total_host [n_views] u64 out, budget_host [n_views] i64 out. */
 int hr_edge_stats(hr_scene* scene, uint64_t* total_host, int64_t* budget_host, void* stream);
 
+/* Work counting (profiling aid).  While enabled, hr_render and hr_backward
+   launch variants of their ray-tracing kernels that count their work.
+   hr_read_counts synchronises `stream`, copies 12 uint64 to counts_host
+   (HOST) and resets them: for the render, interior-adjoint and edge-sampling
+   kernels in turn, (rays traced, BVH nodes visited, ray/triangle tests, rays
+   that hit). */
+int hr_set_counting(hr_scene* scene, int32_t enable);
+int hr_read_counts(hr_scene* scene, uint64_t* counts_host, void* stream);
+
+/* Per-kernel timing (profiling aid).  While enabled, every kernel the scene
+   launches is bracketed by HIP events on its stream.  hr_timing_read
+   synchronises `stream`, returns per kernel name (names: n x 32 chars, HOST)
+   the summed milliseconds and launch counts, and clears the record. */
+int hr_timing_enable(hr_scene* scene, int32_t enable);
+int hr_timing_read(hr_scene* scene, char* names, double* ms, int64_t* count, int32_t max_n, int32_t* n_out,
+                   void* stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* hr_last_error(void);
 

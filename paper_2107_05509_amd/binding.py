@@ -22,7 +22,8 @@ HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_render", "hr_loss",
-           "hr_backward", "hr_step", "hr_edge_stats", "hr_last_error")
+           "hr_backward", "hr_step", "hr_edge_stats", "hr_set_counting", "hr_read_counts", "hr_timing_enable",
+           "hr_timing_read", "hr_last_error")
 
 
 class HRError(RuntimeError):
@@ -80,9 +81,13 @@ def lib():
         L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
         L.hr_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(AdamConfig), vp]
         L.hr_edge_stats.argtypes = [vp, vp, vp, vp]
+        L.hr_set_counting.argtypes = [vp, i32]
+        L.hr_read_counts.argtypes = [vp, vp, vp]
+        L.hr_timing_enable.argtypes = [vp, i32]
+        L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.hr_last_error.restype = ctypes.c_char_p
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step",
-                     "hr_edge_stats"):
+                     "hr_edge_stats", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -217,3 +222,34 @@ class Scene:
         _check(lib().hr_edge_stats(self._h, tot.ctypes.data_as(ctypes.c_void_p),
                                    bud.ctypes.data_as(ctypes.c_void_p), _stream()), "hr_edge_stats")
         return tot, bud
+
+    # -- profiling aids --------------------------------------------------------
+    def set_counting(self, enable):
+        _check(lib().hr_set_counting(self._h, int(bool(enable))), "hr_set_counting")
+
+    def read_counts(self):
+        """{kernel: (rays, nodes, triangle tests, hits)} since the last read."""
+        c = np.zeros(12, dtype=np.uint64)
+        _check(lib().hr_read_counts(self._h, c.ctypes.data_as(ctypes.c_void_p), _stream()), "hr_read_counts")
+        c = c.reshape(3, 4).astype(np.int64)
+        return {"k_render": tuple(c[0]), "k_adjoint_interior": tuple(c[1]), "k_edge_sample": tuple(c[2])}
+
+    def timing_enable(self, enable):
+        _check(lib().hr_timing_enable(self._h, int(bool(enable))), "hr_timing_enable")
+
+    def timing_read(self):
+        """{kernel name: (total ms, launches)} since the last read."""
+        n_max = 64
+        names = ctypes.create_string_buffer(32 * n_max)
+        ms = np.zeros(n_max, dtype=np.float64)
+        cnt = np.zeros(n_max, dtype=np.int64)
+        n = ctypes.c_int32(0)
+        _check(lib().hr_timing_read(self._h, names, ms.ctypes.data_as(ctypes.c_void_p),
+                                    cnt.ctypes.data_as(ctypes.c_void_p), n_max, ctypes.byref(n), _stream()),
+               "hr_timing_read")
+        raw = names.raw
+        out = {}
+        for i in range(n.value):
+            nm = raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[i]), int(cnt[i]))
+        return out

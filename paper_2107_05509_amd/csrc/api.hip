@@ -145,14 +145,16 @@ struct hr_scene {
     std::vector<void*> allocs;
     ViewDev* views = nullptr;
     std::vector<ViewDev> views_host;
-    int2* work = nullptr;
-    int n_work = 0;
+    TileShape ts{};
+    int2* tiles = nullptr;        // wave tiles inside the per-view screen bounds
+    long long tile_cap = 0;
+    int* tile_count = nullptr;
+    int trace_blocks = 0;         // persistent grid of the ray-tracing kernels
     int2* chunks = nullptr;
     int n_chunks = 0;
     int* view_chunk_off = nullptr;
     int* hand_view_off = nullptr;
     int* hand_views = nullptr;
-    int4* bounds = nullptr;
     float* normals = nullptr;
     Tri* tris = nullptr;
     Node* nodes = nullptr;
@@ -163,7 +165,15 @@ struct hr_scene {
     unsigned long long* edge_cdf = nullptr;
     unsigned long long* edge_total = nullptr;
     long long* edge_budget = nullptr;
-    size_t smem_prepare = 0, smem_skin = 0, smem_geom_bwd = 0, smem_adjoint = 0;
+    long long* edge_prefix = nullptr;
+    size_t smem_prepare = 0, smem_skin = 0, smem_geom_bwd = 0;
+    unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
+    bool counting = false;
+    // per-kernel timing (profiling aid)
+    bool timing = false;
+    struct TimedLaunch { const char* name; hipEvent_t a, b; };
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
 
     template <class T>
     int upload(T** dst, const T* src, size_t n)
@@ -174,6 +184,28 @@ struct hr_scene {
     }
 };
 
+// Launch a kernel; with timing enabled, bracket it by events on its stream.
+template <class... KArgs, class... Args>
+static int launch(hr_scene* s, const char* name, void (*kern)(KArgs...), dim3 grid, dim3 block, size_t smem,
+                  hipStream_t st, Args... args)
+{
+    hr_scene::TimedLaunch tl{name, nullptr, nullptr};
+    if (s->timing) {
+        for (hipEvent_t* ev : {&tl.a, &tl.b}) {
+            if (!s->event_pool.empty()) { *ev = s->event_pool.back(); s->event_pool.pop_back(); }
+            else if (hipEventCreate(ev) != hipSuccess) return fail(HR_EHIP, "%s: hipEventCreate failed", name);
+        }
+        (void)hipEventRecord(tl.a, st);
+    }
+    hipLaunchKernelGGL(kern, grid, block, smem, st, args...);
+    int rc = check_launch(name);
+    if (s->timing) {
+        (void)hipEventRecord(tl.b, st);
+        s->timed.push_back(tl);
+    }
+    return rc;
+}
+
 extern "C" {
 
 const char* hr_last_error(void) { return g_err.c_str(); }
@@ -181,6 +213,8 @@ const char* hr_last_error(void) { return g_err.c_str(); }
 void hr_scene_destroy(hr_scene* s)
 {
     if (!s) return;
+    for (auto& t : s->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     for (void* p : s->allocs) (void)hipFree(p);
     delete s;
 }
@@ -275,7 +309,16 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     }
     // views, work lists
     {
-        std::vector<int2> work, chunks;
+        // wave tile shape: all samples of a pixel in one wave
+        TileShape& ts = s->ts;
+        int spp_r = 1, lg = 0;
+        while (spp_r < cfg->spp && spp_r < 64) { spp_r <<= 1; ++lg; }
+        ts.spp_log2 = lg;
+        const int ppw_log2 = 6 - lg;
+        ts.tw_log2 = (ppw_log2 + 1) / 2;
+        ts.th_log2 = ppw_log2 - ts.tw_log2;
+        ts.rounds = (cfg->spp + 63) / 64;
+        std::vector<int2> chunks;
         std::vector<int> vco(1, 0);
         long long pix = 0;
         for (int v = 0; v < n_views; ++v) {
@@ -285,10 +328,10 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             memcpy(d.o, c.o, sizeof(d.o));
             d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
             d.W = c.W; d.H = c.H; d.hand = c.hand;
-            d.bx = (c.W + kBlockPix - 1) / kBlockPix;
+            d.bx = 0;
             d.pix0 = pix;
-            const int by = (c.H + kBlockPix - 1) / kBlockPix;
-            for (int i = 0; i < d.bx * by; ++i) work.push_back(make_int2(v, i));
+            s->tile_cap += (long long)((c.W + (1 << ts.tw_log2) - 1) >> ts.tw_log2) *
+                           ((c.H + (1 << ts.th_log2) - 1) >> ts.th_log2);
             const long long np = (long long)c.W * c.H;
             for (long long p0 = 0; p0 < np; p0 += kLossChunk) chunks.push_back(make_int2(v, (int)p0));
             vco.push_back((int)chunks.size());
@@ -296,8 +339,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             s->views_host.push_back(d);
         }
         s->n_pixels = pix;
-        s->n_work = (int)work.size();
         s->n_chunks = (int)chunks.size();
+        s->trace_blocks = (int)std::max<long long>(1, std::min<long long>(2048, (s->tile_cap + 3) / 4));
         std::vector<int> hvo(n_hands + 1, 0), hv;
         for (int h = 0; h < n_hands; ++h) {
             for (int v = 0; v < n_views; ++v)
@@ -305,14 +348,15 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             hvo[h + 1] = (int)hv.size();
         }
         TRY(s->upload(&s->views, s->views_host.data(), s->views_host.size()));
-        TRY(s->upload(&s->work, work.data(), work.size()));
         TRY(s->upload(&s->chunks, chunks.data(), chunks.size()));
         TRY(s->upload(&s->view_chunk_off, vco.data(), vco.size()));
         TRY(s->upload(&s->hand_view_off, hvo.data(), hvo.size()));
         TRY(s->upload(&s->hand_views, hv.data(), hv.size()));
     }
     // per-iteration state
-    TRY(s->upload<int4>(&s->bounds, nullptr, n_views));
+    TRY(s->upload<int2>(&s->tiles, nullptr, (size_t)s->tile_cap));
+    TRY(s->upload<int>(&s->tile_count, nullptr, 4));
+    TRY(s->upload<long long>(&s->edge_prefix, nullptr, (size_t)n_views + 1));
     TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
     TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
     TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.n_nodes));
@@ -323,11 +367,13 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<unsigned long long>(&s->edge_cdf, nullptr, (size_t)n_views * E));
     TRY(s->upload<unsigned long long>(&s->edge_total, nullptr, n_views));
     TRY(s->upload<long long>(&s->edge_budget, nullptr, n_views));
+    TRY(s->upload<unsigned long long>(&s->counts, nullptr, 12));
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)0, s->counts, 12);
+    if (hipDeviceSynchronize() != hipSuccess) { hr_scene_destroy(s); return fail(HR_EHIP, "scene init failed"); }
 #undef TRY
     s->smem_skin = sizeof(float) * 3 * V;
     s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.n_nodes);
     s->smem_geom_bwd = sizeof(float) * (3 * V * 4 + 3 * F);
-    s->smem_adjoint = sizeof(float) * 6 * V;
     *out = s;
     return HR_OK;
 }
@@ -336,18 +382,19 @@ int hr_skin(hr_scene* s, const float* params, float* verts, float* joints, void*
 {
     if (!s || !params || !verts) return fail(HR_EINVAL, "hr_skin: null argument");
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh, params, verts, joints);
-    return check_launch("hr_skin");
+    return launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh, params, verts,
+                  joints);
 }
 
 static int prepare(hr_scene* s, const float* verts, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_prepare, dim3(s->n_hands), dim3(512), s->smem_prepare, st, s->mesh, s->bvh, verts,
-                       s->normals, s->tris, s->nodes);
-    int rc = check_launch("prepare");
+    int rc = launch(s, "k_prepare", k_prepare, dim3(s->n_hands), dim3(512), s->smem_prepare, st, s->mesh, s->bvh,
+                    verts, s->normals, s->tris, s->nodes);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_view_bounds, dim3(s->n_views), dim3(256), 0, st, s->mesh, s->views, verts, s->bounds);
-    return check_launch("view bounds");
+    rc = launch(s, "k_set_i32", k_set_i32, dim3(1), dim3(64), 0, st, s->tile_count, 4, 0);
+    if (rc) return rc;
+    return launch(s, "k_view_bounds", k_view_bounds, dim3(s->n_views), dim3(256), 0, st, s->mesh,
+                  (const ViewDev*)s->views, verts, s->ts, s->tiles, s->tile_count);
 }
 
 static Shading shading_of(const hr_config& c)
@@ -365,15 +412,83 @@ int hr_render(hr_scene* s, const float* verts, const float* albedo, const float*
     hipStream_t st = (hipStream_t)stream;
     int rc = prepare(s, verts, st);
     if (rc) return rc;
+    const long long P = s->n_pixels;
+    rc = launch(s, "k_copy", k_copy, dim3((unsigned)std::min<long long>(4096, (3 * P + 255) / 256)), dim3(256), 0,
+                st, background, image, 3 * P);
+    if (rc) return rc;
+    if (hit_face) {
+        rc = launch(s, "k_fill_i32", k_fill_i32, dim3((unsigned)std::min<long long>(4096, (P * s->cfg.spp + 255) / 256)),
+                    dim3(256), 0, st, (int*)hit_face, P * s->cfg.spp, -1);
+        if (rc) return rc;
+    }
     RenderArgs a;
-    a.work = s->work; a.views = s->views; a.bounds = s->bounds;
+    a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
     a.n_nodes = s->bvh.n_nodes; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-    hipLaunchKernelGGL(k_render, dim3(s->n_work), dim3(kThreads), 0, st, a);
-    return check_launch("hr_render");
+    a.counts = s->counts;
+    if (s->counting)
+        return launch(s, "k_render", k_render<true>, dim3(s->trace_blocks), dim3(kThreads), 0, st, a);
+    return launch(s, "k_render", k_render<false>, dim3(s->trace_blocks), dim3(kThreads), 0, st, a);
+}
+
+int hr_set_counting(hr_scene* s, int32_t enable)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_counting: null scene");
+    s->counting = enable != 0;
+    return HR_OK;
+}
+
+int hr_read_counts(hr_scene* s, uint64_t* counts_host, void* stream)
+{
+    if (!s || !counts_host) return fail(HR_EINVAL, "hr_read_counts: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(counts_host, s->counts, 12 * sizeof(uint64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_read_counts: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, s->counts, 12);
+    return check_launch("hr_read_counts");
+}
+
+int hr_timing_enable(hr_scene* s, int32_t enable)
+{
+    if (!s) return fail(HR_EINVAL, "hr_timing_enable: null scene");
+    s->timing = enable != 0;
+    return HR_OK;
+}
+
+int hr_timing_read(hr_scene* s, char* names, double* ms, int64_t* count, int32_t max_n, int32_t* n_out, void* stream)
+{
+    if (!s || !names || !ms || !count || !n_out || max_n < 1) return fail(HR_EINVAL, "hr_timing_read: bad argument");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_timing_read: %s", hipGetErrorString(e));
+    std::vector<std::string> keys;
+    std::vector<double> tot;
+    std::vector<int64_t> cnt;
+    for (auto& t : s->timed) {
+        (void)hipEventSynchronize(t.b);
+        float x = 0.0f;
+        (void)hipEventElapsedTime(&x, t.a, t.b);
+        size_t k = 0;
+        while (k < keys.size() && keys[k] != t.name) ++k;
+        if (k == keys.size()) { keys.push_back(t.name); tot.push_back(0.0); cnt.push_back(0); }
+        tot[k] += x;
+        cnt[k] += 1;
+        s->event_pool.push_back(t.a);
+        s->event_pool.push_back(t.b);
+    }
+    s->timed.clear();
+    int n = (int)std::min<size_t>(keys.size(), (size_t)max_n);
+    for (int i = 0; i < n; ++i) {
+        memset(names + 32 * i, 0, 32);
+        strncpy(names + 32 * i, keys[i].c_str(), 31);
+        ms[i] = tot[i];
+        count[i] = cnt[i];
+    }
+    *n_out = n;
+    return HR_OK;
 }
 
 int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss, float* dimage,
@@ -386,14 +501,11 @@ int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t*
     a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
     a.hand_views = s->hand_views; a.view_scale = s->view_scale; a.loss = loss; a.dimage = dimage;
     a.n_hands = s->n_hands;
-    hipLaunchKernelGGL(k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
-    int rc = check_launch("hr_loss partial");
+    int rc = launch(s, "k_loss_partial", k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_loss_final, dim3((s->n_hands + 63) / 64), dim3(64), 0, st, a);
-    rc = check_launch("hr_loss final");
+    rc = launch(s, "k_loss_final", k_loss_final, dim3((s->n_hands + 63) / 64), dim3(64), 0, st, a);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
-    return check_launch("hr_loss grad");
+    return launch(s, "k_loss_grad", k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
 }
 
 static void fill(float* p, long long n, float v, hipStream_t st)
@@ -421,34 +533,45 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
     fill(s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
     if (flags & HR_GRAD_INTERIOR) {
         AdjointArgs a;
-        a.work = s->work; a.views = s->views; a.bounds = s->bounds;
+        a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
+        a.faces = s->mesh.faces;
         a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
         a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gacc = s->gacc;
         a.n_nodes = s->bvh.n_nodes; a.n_faces = s->F; a.n_verts = s->V;
         a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
         a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-        hipLaunchKernelGGL(k_adjoint_interior, dim3(s->n_work), dim3(kThreads), s->smem_adjoint, st, a);
-        rc = check_launch("hr_backward interior");
+        a.counts = s->counts + 4;
+        if (s->counting)
+            rc = launch(s, "k_adjoint_interior", k_adjoint_interior<true>, dim3(s->trace_blocks), dim3(kThreads), 0,
+                        st, a);
+        else
+            rc = launch(s, "k_adjoint_interior", k_adjoint_interior<false>, dim3(s->trace_blocks), dim3(kThreads), 0,
+                        st, a);
         if (rc) return rc;
     }
     if (flags & HR_GRAD_EDGES) {
         EdgeArgs a;
         a.m = s->mesh; a.views = s->views; a.verts = verts;
         a.rec = s->edge_rec; a.cdf = s->edge_cdf; a.total = s->edge_total; a.budget = s->edge_budget;
+        a.prefix = s->edge_prefix; a.n_views = s->n_views;
         a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
         a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
         a.n_nodes = s->bvh.n_nodes; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
         a.delta = s->cfg.edge_delta; a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-        hipLaunchKernelGGL(k_edges_setup, dim3(s->n_views), dim3(256), 0, st, a);
-        rc = check_launch("hr_backward edges setup");
+        rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(256), 0, st, a);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_edge_sample, dim3(8, s->n_views), dim3(kThreads), 0, st, a);
-        rc = check_launch("hr_backward edge samples");
+        a.counts = s->counts + 8;
+        rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
+                    s->n_views, s->edge_prefix);
+        if (rc) return rc;
+        if (s->counting)
+            rc = launch(s, "k_edge_sample", k_edge_sample<true>, dim3(1024), dim3(kThreads), 0, st, a);
+        else
+            rc = launch(s, "k_edge_sample", k_edge_sample<false>, dim3(1024), dim3(kThreads), 0, st, a);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh, params, verts,
-                       s->gacc, grad_params, grad_verts, grad_normals);
-    return check_launch("hr_backward geometry");
+    return launch(s, "k_geom_backward", k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh,
+                  params, verts, (const float*)s->gacc, grad_params, grad_verts, grad_normals);
 }
 
 int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
@@ -470,8 +593,7 @@ int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params,
     a.bc1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)t));
     a.bc2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)t));
     const long long n = 64ll * s->n_hands + a.n_albedo;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
-    return check_launch("hr_step");
+    return launch(s, "k_adam", k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
 }
 
 int hr_edge_stats(hr_scene* s, uint64_t* total_host, int64_t* budget_host, void* stream)

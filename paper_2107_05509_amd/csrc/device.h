@@ -12,10 +12,9 @@
 
 namespace hr {
 
-constexpr int kMaxStack = 40;       // traversal stack entries per lane
+constexpr int kMaxStack = 24;       // traversal stack entries per lane
 constexpr int kLeafMax = 4;         // triangles per leaf
-constexpr int kBlockPix = 16;       // render work unit: 16x16 pixels
-constexpr int kThreads = 256;       // 4 waves, one 8x8 pixel tile each
+constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
 
 // ---------------------------------------------------------------------------
 // records in device memory
@@ -206,8 +205,14 @@ __device__ __forceinline__ bool slab(const Ray& r, const float* lo, const float*
 // bounds.  The closest hit is the minimum of (t, face id): independent of the
 // visiting order, hence equal to a brute-force loop over all triangles.
 // `stack` points at this lane's column of an LDS array (stride `sstride`).
+// Work counters of one traversal (only maintained when COUNT is true).
+struct TraceCount {
+    unsigned nodes = 0, tris = 0;
+};
+
+template <bool COUNT = false>
 __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
-                                      const Ray& r, int* stack, int sstride, Hit& h)
+                                      const Ray& r, int* stack, int sstride, Hit& h, TraceCount* cnt = nullptr)
 {
     h.face = -1;
     float tb = __builtin_inff();
@@ -215,6 +220,7 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
     int sp = 0;
     int node = 0;
     while (true) {
+        if (COUNT) cnt->nodes++;
         const Node& n = nodes[node];
         float4 q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
         float4 q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
@@ -233,8 +239,9 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
             bool hit = c == 0 ? h0 : h1;
             if (hit && code < 0) {
                 int lc = ~code;
-                int start = lc >> 3, cnt = lc & 7;
-                for (int k = 0; k < cnt; ++k) {
+                int start = lc >> 3, ncnt = lc & 7;
+                if (COUNT) cnt->tris += ncnt;
+                for (int k = 0; k < ncnt; ++k) {
                     const Tri& tr = tris[start + k];
                     float4 p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
                     float4 p1 = *reinterpret_cast<const float4*>(&tr.v[4]);

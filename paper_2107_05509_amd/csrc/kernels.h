@@ -31,10 +31,17 @@ struct BvhDev {
     const int* level_off;      // [n_levels+1]
 };
 
+// wave tiles: a tile of 2^tw_log2 x 2^th_log2 pixels, 2^spp_log2 lanes per
+// pixel (64 lanes per wave); spp > 64 takes `rounds` passes of 64 samples
+struct TileShape {
+    int spp_log2, tw_log2, th_log2, rounds;
+};
+
 struct RenderArgs {
-    const int2* work;          // (view, block index in view)
+    const int2* tiles;         // (view, tx | ty << 16)
+    const int* tile_count;
+    TileShape ts;
     const ViewDev* views;
-    const int4* bounds;        // per view, in 16-pixel blocks
     const Node* nodes;
     const Tri* tris;
     const float* normals;
@@ -43,6 +50,7 @@ struct RenderArgs {
     const float* background;
     float* image;
     int* hit_face;
+    unsigned long long* counts;   // [4] rays traced, node visits, triangle tests, hits (counting variant)
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
     uint64_t seed;
@@ -50,9 +58,11 @@ struct RenderArgs {
 };
 
 struct AdjointArgs {
-    const int2* work;
+    const int2* tiles;
+    const int* tile_count;
+    TileShape ts;
     const ViewDev* views;
-    const int4* bounds;
+    const int* faces;
     const Node* nodes;
     const Tri* tris;
     const float* normals;
@@ -61,6 +71,7 @@ struct AdjointArgs {
     const float* dimage;
     float* grad_albedo;
     float* gacc;               // [hands,V,6]
+    unsigned long long* counts;
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
     uint64_t seed;
@@ -91,6 +102,8 @@ struct EdgeArgs {
     unsigned long long* cdf;   // [n_views,E]
     unsigned long long* total; // [n_views]
     long long* budget;         // [n_views]
+    long long* prefix;         // [n_views+1] exclusive prefix of budgets
+    int n_views;
     const Node* nodes;
     const Tri* tris;
     const float* normals;
@@ -99,6 +112,7 @@ struct EdgeArgs {
     const float* background;
     const float* dimage;
     float* gacc;
+    unsigned long long* counts;
     int n_nodes, tex_h, tex_w;
     float delta;
     uint32_t iter;

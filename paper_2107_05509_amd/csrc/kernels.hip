@@ -316,13 +316,16 @@ __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const floa
     }
 }
 
-// per-view screen bounds of the projected hand, in 16-pixel blocks:
-// (bx0, by0, bx1, by1) inclusive-exclusive; the whole view if any vertex is
-// not in front of the camera
+// Per-view screen bounds of the projected hand, turned into a list of wave
+// tiles (tw x th pixels, all samples of a pixel in one wave) appended to
+// `tiles` (order across views is arbitrary).  The whole view is listed if any
+// vertex is not in front of the camera.
 __global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* __restrict__ views,
-                                                     const float* __restrict__ verts, int4* __restrict__ bounds)
+                                                     const float* __restrict__ verts, TileShape ts,
+                                                     int2* __restrict__ tiles, int* __restrict__ tile_count)
 {
-    __shared__ float red[4 * 64];
+    __shared__ float red[4 * 4];
+    __shared__ int base;
     const ViewDev c = views[blockIdx.x];
     const float* vh = verts + (size_t)c.hand * m.V * 3;
     float mnx = 3e38f, mny = 3e38f, mxx = -3e38f, mxy = -3e38f;
@@ -340,108 +343,135 @@ __global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* _
         mnx = fminf(mnx, __shfl_xor(mnx, o)); mny = fminf(mny, __shfl_xor(mny, o));
         mxx = fmaxf(mxx, __shfl_xor(mxx, o)); mxy = fmaxf(mxy, __shfl_xor(mxy, o));
     }
-    int anybad = __syncthreads_or(bad);
+    const int anybad = __syncthreads_or(bad);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) { red[4 * w] = mnx; red[4 * w + 1] = mny; red[4 * w + 2] = mxx; red[4 * w + 3] = mxy; }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+    int tx0 = 0, ty0 = 0, nx = 0, ny = 0;
+    {
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
             mnx = fminf(mnx, red[4 * k]); mny = fminf(mny, red[4 * k + 1]);
             mxx = fmaxf(mxx, red[4 * k + 2]); mxy = fmaxf(mxy, red[4 * k + 3]);
         }
-        const int nbx = (c.W + kBlockPix - 1) / kBlockPix, nby = (c.H + kBlockPix - 1) / kBlockPix;
-        int4 r;
+        const int ntx = (c.W + (1 << ts.tw_log2) - 1) >> ts.tw_log2;
+        const int nty = (c.H + (1 << ts.th_log2) - 1) >> ts.th_log2;
         if (anybad) {
-            r = make_int4(0, 0, nbx, nby);
-        } else if (mxx < -1.0f || mxy < -1.0f || mnx > c.W + 1.0f || mny > c.H + 1.0f) {
-            r = make_int4(0, 0, 0, 0);
-        } else {
+            nx = ntx; ny = nty;
+        } else if (!(mxx < -1.0f || mxy < -1.0f || mnx > c.W + 1.0f || mny > c.H + 1.0f)) {
             // one pixel of margin around the float32 projections
             int x0 = (int)floorf(fmaxf(mnx - 1.0f, 0.0f)), y0 = (int)floorf(fmaxf(mny - 1.0f, 0.0f));
-            int x1 = (int)floorf(fminf(mxx + 1.0f, (float)c.W - 1.0f)), y1 = (int)floorf(fminf(mxy + 1.0f, (float)c.H - 1.0f));
-            r = make_int4(x0 / kBlockPix, y0 / kBlockPix, x1 / kBlockPix + 1, y1 / kBlockPix + 1);
+            int x1 = (int)floorf(fminf(mxx + 1.0f, (float)c.W - 1.0f));
+            int y1 = (int)floorf(fminf(mxy + 1.0f, (float)c.H - 1.0f));
+            tx0 = x0 >> ts.tw_log2; ty0 = y0 >> ts.th_log2;
+            nx = (x1 >> ts.tw_log2) + 1 - tx0; ny = (y1 >> ts.th_log2) + 1 - ty0;
         }
-        bounds[blockIdx.x] = r;
     }
+    const int count = (nx > 0 && ny > 0) ? nx * ny : 0;
+    if (threadIdx.x == 0) base = count > 0 ? atomicAdd(tile_count, count) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+        tiles[base + i] = make_int2(blockIdx.x, (tx0 + i % nx) | ((ty0 + i / nx) << 16));
 }
 
 // ===========================================================================
 // render
 // ===========================================================================
 
-// pixel of thread t in a 16x16 block: wave w owns an 8x8 quadrant
-__device__ __forceinline__ void block_pixel(int t, int& lx, int& ly)
+__device__ __forceinline__ uint64_t pick(const U64x4& r, int j)
 {
-    const int w = t >> 6, l = t & 63;
-    lx = (w & 1) * 8 + (l & 7);
-    ly = (w >> 1) * 8 + (l >> 3);
+    return j == 0 ? r.x[0] : j == 1 ? r.x[1] : j == 2 ? r.x[2] : r.x[3];
 }
 
+// Lane layout of a wave tile: lane = (pixel in tile) * G + sample, G = 2^spp_log2
+// lanes per pixel; tiles of tw x th pixels.  Returns the lane's pixel.
+__device__ __forceinline__ void tile_pixel(const TileShape& ts, int2 e, int lane, int& px, int& py)
+{
+    const int pit = lane >> ts.spp_log2;
+    const int tx = e.y & 0xffff, ty = e.y >> 16;
+    px = (tx << ts.tw_log2) + (pit & ((1 << ts.tw_log2) - 1));
+    py = (ty << ts.th_log2) + (pit >> ts.tw_log2);
+}
+
+template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_render(RenderArgs a)
 {
     __shared__ int stack[kMaxStack * kThreads];
-    const int2 wk = a.work[blockIdx.x];
-    const ViewDev c = a.views[wk.x];
-    const int bxi = wk.y % c.bx, byi = wk.y / c.bx;
-    int lx, ly;
-    block_pixel(threadIdx.x, lx, ly);
-    const int px = bxi * kBlockPix + lx, py = byi * kBlockPix + ly;
-    const bool inside = px < c.W && py < c.H;
-    const long long pl = (long long)py * c.W + px;
-    const long long pg = c.pix0 + pl;
-    const int4 bd = a.bounds[wk.x];
-    const bool culled = bxi < bd.x || bxi >= bd.z || byi < bd.y || byi >= bd.w;
-    if (!inside) return;
-    const float bgc[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
-    if (culled) {
-        a.image[3 * pg] = bgc[0]; a.image[3 * pg + 1] = bgc[1]; a.image[3 * pg + 2] = bgc[2];
-        if (a.hit_face)
-            for (int s = 0; s < a.spp; ++s) a.hit_face[pg * a.spp + s] = -1;
-        return;
-    }
-    const Node* nodes = a.nodes + (size_t)c.hand * a.n_nodes;
-    const Tri* tris = a.tris + (size_t)c.hand * a.n_faces;
-    const float* normals = a.normals + (size_t)c.hand * a.n_verts * 3;
-    const float* tex = a.albedo + (size_t)c.hand * a.tex_h * a.tex_w * 3;
     int* stk = stack + threadIdx.x;
-    // sum of the hit colours (all terms non-negative: no cancellation) and the
-    // number of misses, which take the background colour
-    float acc[3] = {0.0f, 0.0f, 0.0f};
-    int misses = 0;
-    const uint64_t c2 = (uint64_t)(uint32_t)wk.x | (kDomainCamera << 32);
-    for (int q = 0; q < (a.spp + 3) / 4; ++q) {
-        U64x4 r = philox4x64((uint64_t)pl, (uint64_t)q, c2, (uint64_t)a.iter, a.seed, 0);
-        for (int j = 0; j < 4; ++j) {
-            const int s = 4 * q + j;
-            if (s >= a.spp) break;
-            float u = u24_lo(r.x[j]), v = u24_hi(r.x[j]);
-            float sx = (float)px + u, sy = (float)py + v;
-            Ray ray;
-            ray_screen(c, sx, sy, ray);
-            Hit h;
-            trace(nodes, tris, ray, stk, kThreads, h);
-            if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
-            if (h.face >= 0) {
-                Surf sf;
-                surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
-                Shade sd;
-                shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, sd);
-                for (int ch = 0; ch < 3; ++ch) acc[ch] += sd.col[ch] * sd.shade;
-            } else {
-                ++misses;
+    const int lane = threadIdx.x & 63;
+    const int G = 1 << a.ts.spp_log2;
+    const int s_lane = lane & (G - 1);
+    const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kThreads + threadIdx.x) >> 6));
+    const int nw = (int)((gridDim.x * kThreads) >> 6);
+    const int n_tiles = *a.tile_count;
+    const float inv_spp = 1.0f / (float)a.spp;
+    TraceCount tc;
+    unsigned long long n_rays = 0, n_hit = 0;
+    for (int t = gw; t < n_tiles; t += nw) {
+        const int2 e = a.tiles[t];
+        const ViewDev& c = a.views[e.x];
+        int px, py;
+        tile_pixel(a.ts, e, lane, px, py);
+        const bool pix_ok = px < c.W && py < c.H;
+        const long long pl = (long long)py * c.W + px;
+        const long long pg = c.pix0 + pl;
+        const Node* nodes = a.nodes + (size_t)c.hand * a.n_nodes;
+        const Tri* tris = a.tris + (size_t)c.hand * a.n_faces;
+        const float* normals = a.normals + (size_t)c.hand * a.n_verts * 3;
+        const float* tex = a.albedo + (size_t)c.hand * a.tex_h * a.tex_w * 3;
+        const uint64_t c2 = (uint64_t)(uint32_t)e.x | (kDomainCamera << 32);
+        float acc[3] = {0.0f, 0.0f, 0.0f};
+        int misses = 0;
+        for (int r = 0; r < a.ts.rounds; ++r) {
+            const int s = s_lane + 64 * r;
+            if (pix_ok && s < a.spp) {
+                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, (uint64_t)a.iter, a.seed, 0);
+                const uint64_t wd = pick(rr, s & 3);
+                const float u = u24_lo(wd), v = u24_hi(wd);
+                Ray ray;
+                ray_screen(c, (float)px + u, (float)py + v, ray);
+                Hit h;
+                trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+                if (COUNT) ++n_rays;
+                if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
+                if (h.face >= 0) {
+                    if (COUNT) ++n_hit;
+                    Surf sf;
+                    surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
+                    Shade sd;
+                    shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, sd);
+                    for (int ch = 0; ch < 3; ++ch) acc[ch] += sd.col[ch] * sd.shade;
+                } else {
+                    ++misses;
+                }
             }
         }
+        // sum over the G lanes of the pixel (fixed butterfly order)
+        for (int o = G >> 1; o > 0; o >>= 1) {
+            acc[0] += __shfl_xor(acc[0], o);
+            acc[1] += __shfl_xor(acc[1], o);
+            acc[2] += __shfl_xor(acc[2], o);
+            misses += __shfl_xor(misses, o);
+        }
+        if (s_lane == 0 && pix_ok) {
+            const float* bg = a.background + 3 * pg;
+            float out[3];
+            if (misses == a.spp) {
+                out[0] = bg[0]; out[1] = bg[1]; out[2] = bg[2];
+            } else {
+                const float fm = (float)misses;
+                for (int ch = 0; ch < 3; ++ch) out[ch] = (acc[ch] + fm * bg[ch]) * inv_spp;
+            }
+            a.image[3 * pg] = out[0];
+            a.image[3 * pg + 1] = out[1];
+            a.image[3 * pg + 2] = out[2];
+        }
     }
-    float out[3];
-    if (misses == a.spp) {
-        out[0] = bgc[0]; out[1] = bgc[1]; out[2] = bgc[2];
-    } else {
-        const float inv = 1.0f / (float)a.spp, fm = (float)misses;
-        for (int ch = 0; ch < 3; ++ch) out[ch] = (acc[ch] + fm * bgc[ch]) * inv;
+    if (COUNT) {
+        atomicAdd(a.counts + 0, n_rays);
+        atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
+        atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
+        atomicAdd(a.counts + 3, n_hit);
     }
-    a.image[3 * pg] = out[0];
-    a.image[3 * pg + 1] = out[1];
-    a.image[3 * pg + 2] = out[2];
 }
 
 // ===========================================================================
@@ -519,113 +549,154 @@ __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
 // interior adjoint
 // ===========================================================================
 
+template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
 {
     __shared__ int stack[kMaxStack * kThreads];
-    extern __shared__ float gacc[];   // [V*6]: dL/dv (3), dL/dn (3)
-    const int2 wk = a.work[blockIdx.x];
-    const ViewDev c = a.views[wk.x];
-    const int bxi = wk.y % c.bx, byi = wk.y / c.bx;
-    const int4 bd = a.bounds[wk.x];
-    if (bxi < bd.x || bxi >= bd.z || byi < bd.y || byi >= bd.w) return;   // block-uniform
-    for (int i = threadIdx.x; i < a.n_verts * 6; i += blockDim.x) gacc[i] = 0.0f;
-    __syncthreads();
-    int lx, ly;
-    block_pixel(threadIdx.x, lx, ly);
-    const int px = bxi * kBlockPix + lx, py = byi * kBlockPix + ly;
-    const long long pl = (long long)py * c.W + px;
-    const long long pg = c.pix0 + pl;
-    float g[3] = {0.0f, 0.0f, 0.0f};
-    if (px < c.W && py < c.H) {
-        const float inv = 1.0f / (float)a.spp;
-        g[0] = a.dimage[3 * pg] * inv; g[1] = a.dimage[3 * pg + 1] * inv; g[2] = a.dimage[3 * pg + 2] * inv;
-    }
-    const bool live = g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f;
-    const int hand = c.hand;
-    const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
-    const Tri* tris = a.tris + (size_t)hand * a.n_faces;
-    const float* normals = a.normals + (size_t)hand * a.n_verts * 3;
-    const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
-    float* gtex = a.grad_albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
     int* stk = stack + threadIdx.x;
-    const uint64_t c2 = (uint64_t)(uint32_t)wk.x | (kDomainCamera << 32);
+    const int lane = threadIdx.x & 63;
+    const int G = 1 << a.ts.spp_log2;
+    const int s_lane = lane & (G - 1);
+    const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kThreads + threadIdx.x) >> 6));
+    const int nw = (int)((gridDim.x * kThreads) >> 6);
+    const int n_tiles = *a.tile_count;
+    const float inv_spp = 1.0f / (float)a.spp;
     const Shading S = a.shading;
-    if (live) {
-        for (int q = 0; q < (a.spp + 3) / 4; ++q) {
-            U64x4 r = philox4x64((uint64_t)pl, (uint64_t)q, c2, (uint64_t)a.iter, a.seed, 0);
-            for (int j = 0; j < 4; ++j) {
-                const int s = 4 * q + j;
-                if (s >= a.spp) break;
-                float u = u24_lo(r.x[j]), v = u24_hi(r.x[j]);
-                float sx = (float)px + u, sy = (float)py + v;
+    TraceCount tc;
+    unsigned long long n_rays = 0, n_hit = 0;
+    for (int t = gw; t < n_tiles; t += nw) {
+        const int2 e = a.tiles[t];
+        const ViewDev& c = a.views[e.x];
+        int px, py;
+        tile_pixel(a.ts, e, lane, px, py);
+        const bool pix_ok = px < c.W && py < c.H;
+        const long long pl = (long long)py * c.W + px;
+        const long long pg = c.pix0 + pl;
+        float g[3] = {0.0f, 0.0f, 0.0f};
+        if (pix_ok) {
+            g[0] = a.dimage[3 * pg] * inv_spp;
+            g[1] = a.dimage[3 * pg + 1] * inv_spp;
+            g[2] = a.dimage[3 * pg + 2] * inv_spp;
+        }
+        const bool live = g[0] != 0.0f || g[1] != 0.0f || g[2] != 0.0f;
+        if (!__any(live)) continue;   // wave-uniform
+        const int hand = c.hand;
+        const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
+        const Tri* tris = a.tris + (size_t)hand * a.n_faces;
+        const float* normals = a.normals + (size_t)hand * a.n_verts * 3;
+        const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
+        float* gtex = a.grad_albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
+        float* gout = a.gacc + (size_t)hand * a.n_verts * 6;
+        const uint64_t c2 = (uint64_t)(uint32_t)e.x | (kDomainCamera << 32);
+        for (int r = 0; r < a.ts.rounds; ++r) {
+            const int s = s_lane + 64 * r;
+            // per-sample contributions to the triangle's three vertices:
+            // [k*3 + c] position gradient, [9 + k*3 + c] normal gradient
+            float gv[18];
+            for (int k = 0; k < 18; ++k) gv[k] = 0.0f;
+            int face = -1;
+            if (live && s < a.spp) {
+                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, (uint64_t)a.iter, a.seed, 0);
+                const uint64_t wd = pick(rr, s & 3);
+                const float u = u24_lo(wd), v = u24_hi(wd);
                 Ray ray;
-                ray_screen(c, sx, sy, ray);
+                ray_screen(c, (float)px + u, (float)py + v, ray);
                 Hit h;
-                trace(nodes, tris, ray, stk, kThreads, h);
-                if (h.face < 0) continue;
-                Surf sf;
-                surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
-                Shade sd;
-                shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, S, sd);
-                // colour map texels
-                for (int k = 0; k < 4; ++k) {
-                    float wk2 = sd.shade * sd.w[k];
-                    for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * sd.idx[k] + ch, g[ch] * wk2);
-                }
-                const float gs = g[0] * sd.col[0] + g[1] * sd.col[1] + g[2] * sd.col[2];
-                float gtu = 0.0f, gtv = 0.0f;
-                for (int ch = 0; ch < 3; ++ch) {
-                    gtu += g[ch] * sd.shade * sd.dcol_du[ch];
-                    gtv += g[ch] * sd.shade * sd.dcol_dv[ch];
-                }
-                const float2 uv0 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i0);
-                const float2 uv1 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i1);
-                const float2 uv2 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i2);
-                float gb1 = gtu * (uv1.x - uv0.x) + gtv * (uv1.y - uv0.y);
-                float gb2 = gtu * (uv2.x - uv0.x) + gtv * (uv2.y - uv0.y);
-                if (sd.ndotl > 0.0f) {
-                    float gn[3] = {gs * S.kd * S.l[0], gs * S.kd * S.l[1], gs * S.kd * S.l[2]};
-                    float gnn = gn[0] * sd.n[0] + gn[1] * sd.n[1] + gn[2] * sd.n[2];
-                    float inl = 1.0f / sd.nlen;
-                    float gr[3];
-                    for (int k = 0; k < 3; ++k) gr[k] = (gn[k] - gnn * sd.n[k]) * inl;
-                    const float* n0 = normals + 3 * sf.i0;
-                    const float* n1 = normals + 3 * sf.i1;
-                    const float* n2 = normals + 3 * sf.i2;
+                trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+                if (COUNT) ++n_rays;
+                if (h.face >= 0) {
+                    if (COUNT) ++n_hit;
+                    face = h.face;
+                    Surf sf;
+                    surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
+                    Shade sd;
+                    shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, S, sd);
+                    // colour map texels
+                    for (int k = 0; k < 4; ++k) {
+                        const float wk = sd.shade * sd.w[k];
+                        for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * sd.idx[k] + ch, g[ch] * wk);
+                    }
+                    const float gs = g[0] * sd.col[0] + g[1] * sd.col[1] + g[2] * sd.col[2];
+                    float gtu = 0.0f, gtv = 0.0f;
+                    for (int ch = 0; ch < 3; ++ch) {
+                        gtu += g[ch] * sd.shade * sd.dcol_du[ch];
+                        gtv += g[ch] * sd.shade * sd.dcol_dv[ch];
+                    }
+                    const float2 uv0 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i0);
+                    const float2 uv1 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i1);
+                    const float2 uv2 = *reinterpret_cast<const float2*>(a.uv + 2 * sf.i2);
+                    float gb1 = gtu * (uv1.x - uv0.x) + gtv * (uv1.y - uv0.y);
+                    float gb2 = gtu * (uv2.x - uv0.x) + gtv * (uv2.y - uv0.y);
+                    if (sd.ndotl > 0.0f) {
+                        float gn[3] = {gs * S.kd * S.l[0], gs * S.kd * S.l[1], gs * S.kd * S.l[2]};
+                        const float gnn = gn[0] * sd.n[0] + gn[1] * sd.n[1] + gn[2] * sd.n[2];
+                        const float inl = 1.0f / sd.nlen;
+                        const float* n0 = normals + 3 * sf.i0;
+                        const float* n1 = normals + 3 * sf.i1;
+                        const float* n2 = normals + 3 * sf.i2;
+                        for (int k = 0; k < 3; ++k) {
+                            const float gr = (gn[k] - gnn * sd.n[k]) * inl;
+                            gv[9 + k] = sf.b0 * gr;
+                            gv[12 + k] = sf.b1 * gr;
+                            gv[15 + k] = sf.b2 * gr;
+                            gb1 += gr * (n1[k] - n0[k]);
+                            gb2 += gr * (n2[k] - n0[k]);
+                        }
+                    }
+                    // hit point: y = M^{-T} [gb1, gb2, 0], M = [v1-v0, v2-v0, -d] (float64)
+                    double e1[3], e2[3], md[3];
                     for (int k = 0; k < 3; ++k) {
-                        atomicAdd(gacc + 6 * sf.i0 + 3 + k, sf.b0 * gr[k]);
-                        atomicAdd(gacc + 6 * sf.i1 + 3 + k, sf.b1 * gr[k]);
-                        atomicAdd(gacc + 6 * sf.i2 + 3 + k, sf.b2 * gr[k]);
-                        gb1 += gr[k] * (n1[k] - n0[k]);
-                        gb2 += gr[k] * (n2[k] - n0[k]);
+                        e1[k] = (double)sf.v[3 + k] - (double)sf.v[k];
+                        e2[k] = (double)sf.v[6 + k] - (double)sf.v[k];
+                        md[k] = -sf.d[k];
+                    }
+                    const double c23[3] = {e2[1] * md[2] - e2[2] * md[1], e2[2] * md[0] - e2[0] * md[2],
+                                           e2[0] * md[1] - e2[1] * md[0]};
+                    const double c31[3] = {md[1] * e1[2] - md[2] * e1[1], md[2] * e1[0] - md[0] * e1[2],
+                                           md[0] * e1[1] - md[1] * e1[0]};
+                    const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
+                    const double idet = 1.0 / det;
+                    for (int k = 0; k < 3; ++k) {
+                        const float y = (float)(((double)gb1 * c23[k] + (double)gb2 * c31[k]) * idet);
+                        gv[k] = -sf.b0 * y;
+                        gv[3 + k] = -sf.b1 * y;
+                        gv[6 + k] = -sf.b2 * y;
                     }
                 }
-                // hit point: y = M^{-T} [gb1, gb2, 0], M = [v1-v0, v2-v0, -d] (float64)
-                double e1[3], e2[3], md[3];
-                for (int k = 0; k < 3; ++k) {
-                    e1[k] = (double)sf.v[3 + k] - (double)sf.v[k];
-                    e2[k] = (double)sf.v[6 + k] - (double)sf.v[k];
-                    md[k] = -sf.d[k];
+            }
+            // Samples of a pixel mostly hit the same triangle: when all hitting
+            // lanes of the group agree, sum over the group and let one lane
+            // scatter; otherwise every hitting lane scatters its own values.
+            int fmin = face < 0 ? 0x7fffffff : face, fmax = face;
+            for (int o = G >> 1; o > 0; o >>= 1) {
+                fmin = min(fmin, __shfl_xor(fmin, o));
+                fmax = max(fmax, __shfl_xor(fmax, o));
+            }
+            const bool uniform = fmax >= 0 && fmin == fmax;
+            if (__any(uniform)) {
+                for (int k = 0; k < 18; ++k) {
+                    float x = gv[k];
+                    for (int o = G >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o);
+                    if (uniform) gv[k] = x;
                 }
-                double c23[3] = {e2[1] * md[2] - e2[2] * md[1], e2[2] * md[0] - e2[0] * md[2], e2[0] * md[1] - e2[1] * md[0]};
-                double c31[3] = {md[1] * e1[2] - md[2] * e1[1], md[2] * e1[0] - md[0] * e1[2], md[0] * e1[1] - md[1] * e1[0]};
-                double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
-                double idet = 1.0 / det;
-                float y[3];
-                for (int k = 0; k < 3; ++k) y[k] = (float)(((double)gb1 * c23[k] + (double)gb2 * c31[k]) * idet);
-                for (int k = 0; k < 3; ++k) {
-                    atomicAdd(gacc + 6 * sf.i0 + k, -sf.b0 * y[k]);
-                    atomicAdd(gacc + 6 * sf.i1 + k, -sf.b1 * y[k]);
-                    atomicAdd(gacc + 6 * sf.i2 + k, -sf.b2 * y[k]);
-                }
+            }
+            const bool scatter = uniform ? (s_lane == 0) : (face >= 0);
+            if (scatter) {
+                const int f = uniform ? fmax : face;
+                const int vid[3] = {a.faces[3 * f], a.faces[3 * f + 1], a.faces[3 * f + 2]};
+                for (int k = 0; k < 3; ++k)
+                    for (int q = 0; q < 3; ++q) {
+                        unsafeAtomicAdd(gout + 6 * vid[k] + q, gv[3 * k + q]);
+                        unsafeAtomicAdd(gout + 6 * vid[k] + 3 + q, gv[9 + 3 * k + q]);
+                    }
             }
         }
     }
-    __syncthreads();
-    float* gout = a.gacc + (size_t)hand * a.n_verts * 6;
-    for (int i = threadIdx.x; i < a.n_verts * 6; i += blockDim.x) {
-        float x = gacc[i];
-        if (x != 0.0f) unsafeAtomicAdd(gout + i, x);
+    if (COUNT) {
+        atomicAdd(a.counts + 0, n_rays);
+        atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
+        atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
+        atomicAdd(a.counts + 3, n_hit);
     }
 }
 
@@ -749,36 +820,68 @@ __device__ __forceinline__ void proj_jacobian(const ViewDev& c, const float* v, 
         for (int k = 0; k < 3; ++k) J[r][k] = d[r][0] * c.R[k] + d[r][1] * c.R[3 + k] + d[r][2] * c.R[6 + k];
 }
 
+// exclusive prefix of the per-view edge-sample budgets (one block)
+__global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict__ budget, int n_views,
+                                                     long long* __restrict__ prefix)
+{
+    __shared__ long long part[256];
+    const int per = (n_views + blockDim.x - 1) / blockDim.x;
+    const int v0 = threadIdx.x * per, v1 = min(n_views, v0 + per);
+    long long s = 0;
+    for (int v = v0; v < v1; ++v) s += budget[v];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        long long x = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0ll;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    long long run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0ll;
+    for (int v = v0; v < v1; ++v) {
+        prefix[v] = run;
+        run += budget[v];
+    }
+    if (threadIdx.x == blockDim.x - 1) prefix[n_views] = part[threadIdx.x];
+}
+
+// One edge sample per lane pair: the even lane traces the ray at x + delta n,
+// the odd lane the ray at x - delta n.
+template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
 {
     __shared__ int stack[kMaxStack * kThreads];
-    const int vi = blockIdx.y;
-    const ViewDev c = a.views[vi];
-    const long long M = a.budget[vi];
-    const unsigned long long T = a.total[vi];
-    if (M == 0 || T == 0) return;
-    const int E = a.m.E;
-    const EdgeRec* rec = a.rec + (size_t)vi * E;
-    const unsigned long long* cdf = a.cdf + (size_t)vi * E;
-    const int hand = c.hand;
-    const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
-    const Tri* tris = a.tris + (size_t)hand * a.m.F;
-    const float* normals = a.normals + (size_t)hand * a.m.V * 3;
-    const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
-    const float* vh = a.verts + (size_t)hand * a.m.V * 3;
-    float* gout = a.gacc + (size_t)hand * a.m.V * 6;
     int* stk = stack + threadIdx.x;
-    const uint64_t c2 = (uint64_t)(uint32_t)vi | (kDomainEdge << 32);
-    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < M;
-         k += (long long)gridDim.x * blockDim.x) {
-        U64x4 r = philox4x64((uint64_t)k, 0, c2, (uint64_t)a.iter, a.seed, 0);
-        const unsigned long long target = __umul64hi(r.x[0], T);
-        int lo = 0, hi = E - 1;   // first e with cdf[e] > target
+    const long long total = a.prefix[a.n_views];
+    const int side = threadIdx.x & 1;
+    const long long npairs = ((long long)gridDim.x * blockDim.x) >> 1;
+    const int E = a.m.E;
+    TraceCount tc;
+    unsigned long long n_rays = 0, n_hit = 0;
+    for (long long kg = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 1; kg < total; kg += npairs) {
+        // view of global sample kg: last v with prefix[v] <= kg
+        int lo = 0, hi = a.n_views - 1;
         while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+            int mid = (lo + hi + 1) >> 1;
+            if (a.prefix[mid] <= kg) lo = mid; else hi = mid - 1;
         }
-        const int e = lo;
+        const int vi = lo;
+        const long long k = kg - a.prefix[vi];
+        const ViewDev& c = a.views[vi];
+        const long long M = a.budget[vi];
+        const unsigned long long T = a.total[vi];
+        const EdgeRec* rec = a.rec + (size_t)vi * E;
+        const unsigned long long* cdf = a.cdf + (size_t)vi * E;
+        const int hand = c.hand;
+        const uint64_t c2 = (uint64_t)(uint32_t)vi | (kDomainEdge << 32);
+        const U64x4 r = philox4x64((uint64_t)k, 0, c2, (uint64_t)a.iter, a.seed, 0);
+        const unsigned long long target = __umul64hi(r.x[0], T);
+        int elo = 0, ehi = E - 1;   // first e with cdf[e] > target
+        while (elo < ehi) {
+            int mid = (elo + ehi) >> 1;
+            if (cdf[mid] > target) ehi = mid; else elo = mid + 1;
+        }
+        const int e = elo;
         const EdgeRec q = rec[e];
         const float u = u24_hi(r.x[1]);
         const float t = q.t0 + u * (q.t1 - q.t0);
@@ -787,37 +890,50 @@ __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
         const float y = q.ay + t * dy;
         const float len = sqrtf(dx * dx + dy * dy);
         const float nhx = dy / len, nhy = -dx / len;
-        const float xp = x + a.delta * nhx, yp = y + a.delta * nhy;
-        const float xm = x - a.delta * nhx, ym = y - a.delta * nhy;
+        const float xs = side == 0 ? x + a.delta * nhx : x - a.delta * nhx;
+        const float ys = side == 0 ? y + a.delta * nhy : y - a.delta * nhy;
         int px = (int)floorf(x), py = (int)floorf(y);
         px = min(max(px, 0), c.W - 1);
         py = min(max(py, 0), c.H - 1);
         const long long pg = c.pix0 + (long long)py * c.W + px;
         const float g[3] = {a.dimage[3 * pg], a.dimage[3 * pg + 1], a.dimage[3 * pg + 2]};
-        if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) continue;
+        if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) continue;   // same for both lanes of the pair
         const float bg[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
-        float cp[3], cm[3];
+        const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
+        const Tri* tris = a.tris + (size_t)hand * a.m.F;
+        const float* normals = a.normals + (size_t)hand * a.m.V * 3;
+        const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
         Ray ray;
         Hit h;
-        ray_screen(c, xp, yp, ray);
-        trace(nodes, tris, ray, stk, kThreads, h);
-        shade_or_bg(h, tris, c, xp, yp, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, cp);
-        ray_screen(c, xm, ym, ray);
-        trace(nodes, tris, ray, stk, kThreads, h);
-        shade_or_bg(h, tris, c, xm, ym, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, cm);
-        const float jump = g[0] * (cm[0] - cp[0]) + g[1] * (cm[1] - cp[1]) + g[2] * (cm[2] - cp[2]);
+        ray_screen(c, xs, ys, ray);
+        trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+        if (COUNT) { ++n_rays; n_hit += h.face >= 0; }
+        float col[3];
+        shade_or_bg(h, tris, c, xs, ys, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, col);
+        const float o0 = __shfl_xor(col[0], 1), o1 = __shfl_xor(col[1], 1), o2 = __shfl_xor(col[2], 1);
+        if (side != 0) continue;
+        // c(x - delta n) - c(x + delta n)
+        const float jump = g[0] * (o0 - col[0]) + g[1] * (o1 - col[1]) + g[2] * (o2 - col[2]);
         if (jump == 0.0f) continue;
         const float ell = len * (q.t1 - q.t0);
-        const float s = jump * (ell * (float)T / ((float)q.w * (float)M));
+        const float sc = jump * (ell * (float)T / ((float)q.w * (float)M));
         const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
+        const float* vh = a.verts + (size_t)hand * a.m.V * 3;
+        float* gout = a.gacc + (size_t)hand * a.m.V * 6;
         float Ja[2][3], Jb[2][3];
         proj_jacobian(c, vh + 3 * va, Ja);
         proj_jacobian(c, vh + 3 * vb, Jb);
-        const float sa = (1.0f - t) * s, sb = t * s;
+        const float sa = (1.0f - t) * sc, sb = t * sc;
         for (int k3 = 0; k3 < 3; ++k3) {
             unsafeAtomicAdd(gout + 6 * va + k3, sa * (Ja[0][k3] * nhx + Ja[1][k3] * nhy));
             unsafeAtomicAdd(gout + 6 * vb + k3, sb * (Jb[0][k3] * nhx + Jb[1][k3] * nhy));
         }
+    }
+    if (COUNT) {
+        atomicAdd(a.counts + 0, n_rays);
+        atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
+        atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
+        atomicAdd(a.counts + 3, n_hit);
     }
 }
 
@@ -1058,6 +1174,28 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 // ===========================================================================
 // utilities
 // ===========================================================================
+
+__global__ void k_set_i32(int* p, int n, int v)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = v;
+}
+
+__global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_fill_i32(int* __restrict__ p, long long n, int v)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
 
 __global__ void k_fill(float* __restrict__ p, long long n, float v)
 {
