@@ -69,6 +69,7 @@ class Refiner:
         gt = binding.Scene(w.model, w.cams, w.n_hands, 64, th, tw, seed=7000 + seed)
         vt = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
         gt.skin(t(w.params_true.astype(np.float32)), vt)
+        gt.build_hierarchy(vt)
         self.target = torch.empty(P, 3, device=dev)
         hits = torch.empty(P, 64, device=dev, dtype=torch.int32)
         gt.render(vt, t(w.albedo_true.astype(np.float32)), self.bg, 0, self.target, hits)
@@ -85,6 +86,9 @@ class Refiner:
         self.mp, self.vp = torch.zeros_like(self.params), torch.zeros_like(self.params)
         self.ma, self.va = torch.zeros_like(self.albedo), torch.zeros_like(self.albedo)
         self.verts = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
+        # hierarchy topology around the initial pose (set-up, untimed)
+        self.g.skin(self.params, self.verts)
+        self.g.build_hierarchy(self.verts)
         self.image = torch.empty(P, 3, device=dev)
         self.dimage = torch.empty(P, 3, device=dev)
         self.loss = torch.empty(w.n_hands, device=dev)

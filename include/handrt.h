@@ -131,6 +131,14 @@ int64_t hr_num_pixels(const hr_scene* scene);
    params [n_hands,64] -> verts [n_hands,V,3], joints [n_hands,J,3] (nullable). */
 int hr_skin(hr_scene* scene, const float* params, float* verts, float* joints, void* stream);
 
+/* Rebuild the topology of each hand's bounding-volume hierarchy (binned
+   surface-area heuristic) around the given vertices [n_hands,V,3].  Bounds
+   are refit every iteration by hr_render; the topology only affects speed,
+   never results.  Call it once the pose is roughly known (e.g. after the
+   first hr_skin).  Synchronises `stream`; host-side work, not for use under
+   graph capture.  The scene starts with a hierarchy of the rest pose. */
+int hr_build_hierarchy(hr_scene* scene, const float* verts, void* stream);
+
 /* Render all views: pixel = (1/spp) sum over samples of the colour of the
    first surface hit by the ray through a uniformly drawn point of the pixel,
    or the pixel's background colour (Section 3, Eq. 3).  Also prepares the

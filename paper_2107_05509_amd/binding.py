@@ -22,7 +22,7 @@ HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_render", "hr_loss",
-           "hr_backward", "hr_step", "hr_edge_stats", "hr_set_counting", "hr_read_counts", "hr_timing_enable",
+           "hr_backward", "hr_step", "hr_edge_stats", "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable",
            "hr_timing_read", "hr_last_error")
 
 
@@ -81,13 +81,14 @@ def lib():
         L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
         L.hr_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(AdamConfig), vp]
         L.hr_edge_stats.argtypes = [vp, vp, vp, vp]
+        L.hr_build_hierarchy.argtypes = [vp, vp, vp]
         L.hr_set_counting.argtypes = [vp, i32]
         L.hr_read_counts.argtypes = [vp, vp, vp]
         L.hr_timing_enable.argtypes = [vp, i32]
         L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.hr_last_error.restype = ctypes.c_char_p
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step",
-                     "hr_edge_stats", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read"):
+                     "hr_edge_stats", "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -177,6 +178,10 @@ class Scene:
         _check(lib().hr_skin(self._h, _ptr(params, shape=(self.n_hands, 64), name="params"),
                              _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),
                              _ptr(joints, shape=(self.n_hands, self.J, 3), name="joints"), _stream()), "hr_skin")
+
+    def build_hierarchy(self, verts):
+        _check(lib().hr_build_hierarchy(self._h, _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),
+                                        _stream()), "hr_build_hierarchy")
 
     def render(self, verts, albedo, background, it, image, hit_face=None):
         _check(lib().hr_render(self._h, _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),

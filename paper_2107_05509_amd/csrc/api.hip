@@ -12,6 +12,7 @@
 
 #include "../../include/handrt.h"
 #include "kernels.hip"
+#include "bvh_build.h"
 
 using namespace hr;
 
@@ -51,86 +52,6 @@ int dev_upload(T** dst, const T* src, size_t n)
     return HR_OK;
 }
 
-// ---------------------------------------------------------------------------
-// bounding-volume hierarchy topology (built once on the host from the rest
-// pose; bounds are refit on the device every iteration)
-// ---------------------------------------------------------------------------
-
-struct HostBvh {
-    std::vector<int> child;      // [n,2]
-    std::vector<int> perm;       // [F]
-    std::vector<int> order, level_off;
-    int depth = 0;
-};
-
-int leaf_code(int start, int count) { return ~((start << 3) | count); }
-
-int build_rec(HostBvh& b, std::vector<int>& idx, const std::vector<float>& cen, int lo, int hi, int depth)
-{
-    b.depth = std::max(b.depth, depth);
-    const int node = (int)b.child.size() / 2;
-    b.child.push_back(0);
-    b.child.push_back(0);
-    const int mid = (lo + hi) / 2;
-    float mn[3] = {1e30f, 1e30f, 1e30f}, mx[3] = {-1e30f, -1e30f, -1e30f};
-    for (int i = lo; i < hi; ++i)
-        for (int k = 0; k < 3; ++k) {
-            mn[k] = std::min(mn[k], cen[3 * idx[i] + k]);
-            mx[k] = std::max(mx[k], cen[3 * idx[i] + k]);
-        }
-    int axis = 0;
-    for (int k = 1; k < 3; ++k)
-        if (mx[k] - mn[k] > mx[axis] - mn[axis]) axis = k;
-    std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi,
-                     [&](int a, int c) { return cen[3 * a + axis] < cen[3 * c + axis]; });
-    const int ranges[2][2] = {{lo, mid}, {mid, hi}};
-    for (int c = 0; c < 2; ++c) {
-        const int a = ranges[c][0], e = ranges[c][1];
-        int code;
-        if (e - a <= kLeafMax) code = leaf_code(a, e - a);
-        else code = build_rec(b, idx, cen, a, e, depth + 1);
-        b.child[2 * node + c] = code;
-    }
-    return node;
-}
-
-HostBvh build_bvh(const float* verts, const int* faces, int F)
-{
-    HostBvh b;
-    std::vector<float> cen(3 * F);
-    for (int f = 0; f < F; ++f)
-        for (int k = 0; k < 3; ++k)
-            cen[3 * f + k] = (verts[3 * faces[3 * f] + k] + verts[3 * faces[3 * f + 1] + k] +
-                              verts[3 * faces[3 * f + 2] + k]) / 3.0f;
-    std::vector<int> idx(F);
-    std::iota(idx.begin(), idx.end(), 0);
-    if (F <= kLeafMax) {
-        b.child = {leaf_code(0, F), leaf_code(0, 0)};
-    } else {
-        build_rec(b, idx, cen, 0, F, 1);
-    }
-    b.perm = idx;
-    const int n = (int)b.child.size() / 2;
-    // heights: leaves 0; a node is refit after all its children
-    std::vector<int> height(n, 0);
-    for (int i = n - 1; i >= 0; --i) {   // children have larger indices (preorder)
-        int h = 1;
-        for (int c = 0; c < 2; ++c) {
-            int code = b.child[2 * i + c];
-            if (code >= 0) h = std::max(h, height[code] + 1);
-        }
-        height[i] = h;
-    }
-    int maxh = *std::max_element(height.begin(), height.end());
-    b.level_off.assign(maxh + 1, 0);
-    for (int L = 1; L <= maxh; ++L) {
-        for (int i = 0; i < n; ++i)
-            if (height[i] == L) b.order.push_back(i);
-        b.level_off[L] = (int)b.order.size();
-    }
-    return b;
-}
-
 }  // namespace
 
 struct hr_scene {
@@ -158,7 +79,8 @@ struct hr_scene {
     float* normals = nullptr;
     Tri* tris = nullptr;
     Node* nodes = nullptr;
-    float* gacc = nullptr;
+    float* gacc = nullptr;        // [hands,V,6] vertex gradient slots (edge term)
+    float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
     float* loss_partial = nullptr;
     float* view_scale = nullptr;
     EdgeRec* edge_rec = nullptr;
@@ -183,6 +105,31 @@ struct hr_scene {
         return rc;
     }
 };
+
+// Copy one hand's hierarchy topology to the device (synchronous).
+static int upload_hierarchy(hr_scene* s, int h, const HostBvh& hb)
+{
+    BvhDev& b = s->bvh;
+    const int n = (int)hb.child.size() / 2;
+    const int nl = (int)hb.level_off.size() - 1;
+    if (hb.depth + 1 > kMaxStack || nl + 1 > b.level_stride)
+        return fail(HR_EUNSUPPORTED, "hierarchy too deep (%d levels)", hb.depth);
+    if (n > b.node_stride) return fail(HR_EUNSUPPORTED, "hierarchy too large (%d nodes)", n);
+    hipError_t e = hipMemcpy((int*)b.child + (size_t)h * b.node_stride * 2, hb.child.data(),
+                             sizeof(int) * hb.child.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((int*)b.perm + (size_t)h * s->F, hb.perm.data(), sizeof(int) * hb.perm.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((int*)b.order + (size_t)h * b.node_stride, hb.order.data(), sizeof(int) * hb.order.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((int*)b.level_off + (size_t)h * b.level_stride, hb.level_off.data(),
+                      sizeof(int) * hb.level_off.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((int*)b.n_levels + h, &nl, sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(HR_EHIP, "hierarchy upload: %s", hipGetErrorString(e));
+    return HR_OK;
+}
 
 // Launch a kernel; with timing enabled, bracket it by events on its stream.
 template <class... KArgs, class... Args>
@@ -290,22 +237,19 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload(&q, off.data(), off.size())); md.vf_off = q;
         TRY(s->upload(&q, flat.data(), flat.size())); md.vf_faces = q;
     }
-    // hierarchy topology from the rest pose
+    // hierarchy topology: from the rest pose until hr_build_hierarchy is called
     {
-        HostBvh hb = build_bvh(m->v_template, m->faces, F);
-        if (hb.depth + 1 > kMaxStack) {
-            hr_scene_destroy(s);
-            return fail(HR_EUNSUPPORTED, "hr_scene_create: hierarchy too deep (%d)", hb.depth);
-        }
-        s->bvh_depth = hb.depth;
         BvhDev& b = s->bvh;
-        b.n_nodes = (int)hb.child.size() / 2;
-        b.n_levels = (int)hb.level_off.size() - 1;
+        b.node_stride = std::max(F - 1, 1);
+        b.level_stride = kMaxStack + 2;
         int* q;
-        TRY(s->upload(&q, hb.child.data(), hb.child.size())); b.child = q;
-        TRY(s->upload(&q, hb.perm.data(), hb.perm.size())); b.perm = q;
-        TRY(s->upload(&q, hb.order.data(), hb.order.size())); b.order = q;
-        TRY(s->upload(&q, hb.level_off.data(), hb.level_off.size())); b.level_off = q;
+        TRY(s->upload<int>(&q, nullptr, (size_t)n_hands)); b.n_levels = q;
+        TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.node_stride * 2)); b.child = q;
+        TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * F)); b.perm = q;
+        TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.node_stride)); b.order = q;
+        TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.level_stride)); b.level_off = q;
+        HostBvh hb = build_bvh(m->v_template, m->faces, F, kLeafMax);
+        for (int h = 0; h < n_hands; ++h) TRY(upload_hierarchy(s, h, hb));
     }
     // views, work lists
     {
@@ -359,8 +303,9 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<long long>(&s->edge_prefix, nullptr, (size_t)n_views + 1));
     TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
     TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
-    TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.n_nodes));
+    TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.node_stride));
     TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_hands * V * 6));
+    TRY(s->upload<float>(&s->gface, nullptr, (size_t)n_hands * F * 18));
     TRY(s->upload<float>(&s->loss_partial, nullptr, 2 * (size_t)s->n_chunks));
     TRY(s->upload<float>(&s->view_scale, nullptr, n_views));
     TRY(s->upload<EdgeRec>(&s->edge_rec, nullptr, (size_t)n_views * E));
@@ -372,8 +317,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     if (hipDeviceSynchronize() != hipSuccess) { hr_scene_destroy(s); return fail(HR_EHIP, "scene init failed"); }
 #undef TRY
     s->smem_skin = sizeof(float) * 3 * V;
-    s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.n_nodes);
-    s->smem_geom_bwd = sizeof(float) * (3 * V * 4 + 3 * F);
+    s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.node_stride);
+    s->smem_geom_bwd = sizeof(float) * (3 * V * 3 + 3 * F);
     *out = s;
     return HR_OK;
 }
@@ -384,6 +329,27 @@ int hr_skin(hr_scene* s, const float* params, float* verts, float* joints, void*
     hipStream_t st = (hipStream_t)stream;
     return launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh, params, verts,
                   joints);
+}
+
+int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
+{
+    if (!s || !verts) return fail(HR_EINVAL, "hr_build_hierarchy: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> hv((size_t)s->n_hands * s->V * 3);
+    std::vector<int> faces((size_t)s->F * 3);
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipMemcpy(hv.data(), verts, sizeof(float) * hv.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = hipMemcpy(faces.data(), s->mesh.faces, sizeof(int) * faces.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_build_hierarchy: %s", hipGetErrorString(e));
+    for (size_t i = 0; i < hv.size(); ++i)
+        if (!std::isfinite(hv[i])) return fail(HR_EINVAL, "hr_build_hierarchy: non-finite vertex");
+    for (int h = 0; h < s->n_hands; ++h) {
+        HostBvh hb = build_bvh(hv.data() + (size_t)h * s->V * 3, faces.data(), s->F, kLeafMax);
+        int rc = upload_hierarchy(s, h, hb);
+        if (rc) return rc;
+    }
+    return HR_OK;
 }
 
 static int prepare(hr_scene* s, const float* verts, hipStream_t st)
@@ -425,7 +391,7 @@ int hr_render(hr_scene* s, const float* verts, const float* albedo, const float*
     a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
-    a.n_nodes = s->bvh.n_nodes; a.n_faces = s->F; a.n_verts = s->V;
+    a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
@@ -503,16 +469,16 @@ int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t*
     a.n_hands = s->n_hands;
     int rc = launch(s, "k_loss_partial", k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
     if (rc) return rc;
-    rc = launch(s, "k_loss_final", k_loss_final, dim3((s->n_hands + 63) / 64), dim3(64), 0, st, a);
+    rc = launch(s, "k_loss_final", k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
     if (rc) return rc;
     return launch(s, "k_loss_grad", k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
 }
 
-static void fill(float* p, long long n, float v, hipStream_t st)
+static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
 {
-    if (n <= 0) return;
+    if (n <= 0) return HR_OK;
     long long blocks = std::min<long long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+    return launch(s, "k_fill", k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
 }
 
 int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
@@ -529,15 +495,17 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
         if (rc) return rc;
     }
     const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
-    fill(grad_albedo, nalb, 0.0f, st);
-    fill(s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
+    rc = fill(s, grad_albedo, nalb, 0.0f, st);
+    if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
+    if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
+    if (rc) return rc;
     if (flags & HR_GRAD_INTERIOR) {
         AdjointArgs a;
         a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
         a.faces = s->mesh.faces;
         a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
-        a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gacc = s->gacc;
-        a.n_nodes = s->bvh.n_nodes; a.n_faces = s->F; a.n_verts = s->V;
+        a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
+        a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
         a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
         a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
         a.counts = s->counts + 4;
@@ -556,7 +524,7 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
         a.prefix = s->edge_prefix; a.n_views = s->n_views;
         a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
         a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
-        a.n_nodes = s->bvh.n_nodes; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
+        a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
         a.delta = s->cfg.edge_delta; a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
         rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(256), 0, st, a);
         if (rc) return rc;
@@ -571,7 +539,8 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
         if (rc) return rc;
     }
     return launch(s, "k_geom_backward", k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh,
-                  params, verts, (const float*)s->gacc, grad_params, grad_verts, grad_normals);
+                  params, verts, (const float*)s->gacc, (const float*)s->gface, grad_params, grad_verts,
+                  grad_normals);
 }
 
 int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,

@@ -23,12 +23,16 @@ struct MeshDev {
     const int* vf_faces;       // [3F]
 };
 
+// Topology of each hand's hierarchy (bounds are refit every iteration).
+// Arrays are per hand with fixed strides.
 struct BvhDev {
-    int n_nodes, n_levels;
-    const int* child;          // [n_nodes,2] child codes
-    const int* perm;           // [F] face of each leaf slot
-    const int* order;          // [n_nodes] internal nodes sorted by height
-    const int* level_off;      // [n_levels+1]
+    int node_stride;           // >= internal nodes of any hand
+    int level_stride;          // >= levels + 1 of any hand
+    const int* n_levels;       // [H]
+    const int* child;          // [H, node_stride, 2] child codes
+    const int* perm;           // [H, F] face of each leaf slot
+    const int* order;          // [H, node_stride] internal nodes sorted by height
+    const int* level_off;      // [H, level_stride] offsets into order per height
 };
 
 // wave tiles: a tile of 2^tw_log2 x 2^th_log2 pixels, 2^spp_log2 lanes per
@@ -70,7 +74,7 @@ struct AdjointArgs {
     const float* albedo;
     const float* dimage;
     float* grad_albedo;
-    float* gacc;               // [hands,V,6]
+    float* gface;              // [hands,F,18] per-triangle corner gradients
     unsigned long long* counts;
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;

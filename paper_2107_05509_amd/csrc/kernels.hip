@@ -118,9 +118,20 @@ struct SkinShared {
     float At[kMaxJoints * 3];
     float J[kMaxJoints * 3];
     float Rj[kMaxJoints * 9];
+    Rod rod[kMaxJoints + 1];     // joint rotations and the global rotation
     float Rp[9];
+    int depth[kMaxJoints];
+    int max_depth;
     float red[16 * 16 + 16 * 16];
 };
+
+// depth of joint j in the tree (root = 0)
+__device__ __forceinline__ int joint_depth(const int* parents, int j)
+{
+    int d = 0;
+    while (parents[j] >= 0) { j = parents[j]; ++d; }
+    return d;
+}
 
 // shaped vertices into vs (LDS), joints, joint transforms
 __device__ void skin_common(const MeshDev& m, const float* __restrict__ p, float* vs, SkinShared& sh)
@@ -135,32 +146,44 @@ __device__ void skin_common(const MeshDev& m, const float* __restrict__ p, float
             vs[3 * v + c] = s;
         }
     }
-    __syncthreads();
-    for (int j = 0; j < J; ++j) {
-        float acc[3] = {0.0f, 0.0f, 0.0f};
-        const float* jr = m.j_regressor + (size_t)j * V;
-        for (int v = threadIdx.x; v < V; v += blockDim.x) {
-            float w = jr[v];
-            acc[0] += w * vs[3 * v];
-            acc[1] += w * vs[3 * v + 1];
-            acc[2] += w * vs[3 * v + 2];
-        }
-        float out[3];
-        block_sum<3>(acc, sh.red, out);
-        if (threadIdx.x == 0) { sh.J[3 * j] = out[0]; sh.J[3 * j + 1] = out[1]; sh.J[3 * j + 2] = out[2]; }
+    // rotations of all joints and of the global transform, in parallel
+    if ((int)threadIdx.x <= J) {
+        const int j = threadIdx.x;
+        rodrigues(j < J ? p + 3 * j : p + 58, sh.rod[j]);
+        if (j < J) sh.depth[j] = joint_depth(m.parents, j);
     }
     __syncthreads();
+    // joint regression: one wave per joint, fixed reduction order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    for (int j = wave; j < J; j += nwv) {
+        const float* jr = m.j_regressor + (size_t)j * V;
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        for (int v = lane; v < V; v += 64) {
+            const float w = jr[v];
+            a0 += w * vs[3 * v]; a1 += w * vs[3 * v + 1]; a2 += w * vs[3 * v + 2];
+        }
+        a0 = wave_sum(a0); a1 = wave_sum(a1); a2 = wave_sum(a2);
+        if (lane == 0) { sh.J[3 * j] = a0; sh.J[3 * j + 1] = a1; sh.J[3 * j + 2] = a2; }
+    }
     if (threadIdx.x == 0) {
-        for (int j = 0; j < J; ++j) {
-            Rod rd;
-            rodrigues(p + 3 * j, rd);
-            for (int i = 0; i < 9; ++i) sh.Rj[9 * j + i] = rd.R[i];
-            int par = m.parents[j];
+        int md = 0;
+        for (int j = 0; j < J; ++j) md = max(md, sh.depth[j]);
+        sh.max_depth = md;
+        for (int i = 0; i < 9; ++i) sh.Rp[i] = sh.rod[J].R[i];
+    }
+    for (int j = threadIdx.x; j < J; j += blockDim.x)
+        for (int i = 0; i < 9; ++i) sh.Rj[9 * j + i] = sh.rod[j].R[i];
+    __syncthreads();
+    // forward kinematics, one tree level at a time
+    for (int L = 0; L <= sh.max_depth; ++L) {
+        const int j = threadIdx.x;
+        if (j < J && sh.depth[j] == L) {
+            const int par = m.parents[j];
             if (par < 0) {
-                for (int i = 0; i < 9; ++i) sh.GR[9 * j + i] = rd.R[i];
+                for (int i = 0; i < 9; ++i) sh.GR[9 * j + i] = sh.Rj[9 * j + i];
                 for (int i = 0; i < 3; ++i) sh.Gt[3 * j + i] = sh.J[3 * j + i];
             } else {
-                matmul3(sh.GR + 9 * par, rd.R, sh.GR + 9 * j);
+                matmul3(sh.GR + 9 * par, sh.Rj + 9 * j, sh.GR + 9 * j);
                 float d[3] = {sh.J[3 * j] - sh.J[3 * par], sh.J[3 * j + 1] - sh.J[3 * par + 1],
                               sh.J[3 * j + 2] - sh.J[3 * par + 2]};
                 float y[3];
@@ -171,11 +194,8 @@ __device__ void skin_common(const MeshDev& m, const float* __restrict__ p, float
             matvec3(sh.GR + 9 * j, sh.J + 3 * j, y);
             for (int i = 0; i < 3; ++i) sh.At[3 * j + i] = sh.Gt[3 * j + i] - y[i];
         }
-        Rod rp;
-        rodrigues(p + 58, rp);
-        for (int i = 0; i < 9; ++i) sh.Rp[i] = rp.R[i];
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // posed (pre-global-transform) vertex v
@@ -234,7 +254,12 @@ __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const floa
     const int V = m.V, F = m.F;
     float* vsh = dyn;                 // [V*3]
     float* fn = vsh + 3 * V;          // [F*3]
-    float* nb = fn + 3 * F;           // [n_nodes*6] node bounds
+    float* nb = fn + 3 * F;           // [node_stride*6] node bounds
+    const int* child = b.child + (size_t)h * b.node_stride * 2;
+    const int* perm = b.perm + (size_t)h * F;
+    const int* order = b.order + (size_t)h * b.node_stride;
+    const int* level_off = b.level_off + (size_t)h * b.level_stride;
+    const int n_levels = b.n_levels[h];
     const float* vh = verts + (size_t)h * V * 3;
     for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
     __syncthreads();
@@ -259,7 +284,7 @@ __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const floa
     }
     Tri* th = tris + (size_t)h * F;
     for (int i = threadIdx.x; i < F; i += blockDim.x) {
-        int f = b.perm[i];
+        int f = perm[i];
         Tri t;
         int id[3] = {m.faces[3 * f], m.faces[3 * f + 1], m.faces[3 * f + 2]};
         for (int k = 0; k < 3; ++k)
@@ -269,21 +294,21 @@ __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const floa
         th[i] = t;
     }
     // refit, level by level from the leaves up
-    Node* nd = nodes + (size_t)h * b.n_nodes;
-    for (int L = 0; L < b.n_levels; ++L) {
-        for (int q = b.level_off[L] + threadIdx.x; q < b.level_off[L + 1]; q += blockDim.x) {
-            int n = b.order[q];
+    Node* nd = nodes + (size_t)h * b.node_stride;
+    for (int L = 0; L < n_levels; ++L) {
+        for (int q = level_off[L] + threadIdx.x; q < level_off[L + 1]; q += blockDim.x) {
+            int n = order[q];
             Node out;
             float own[6] = {3e38f, 3e38f, 3e38f, -3e38f, -3e38f, -3e38f};
             for (int c = 0; c < 2; ++c) {
-                int code = b.child[2 * n + c];
+                int code = child[2 * n + c];
                 float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
                 if (code >= 0) {
                     for (int k = 0; k < 3; ++k) { lo[k] = nb[6 * code + k]; hi[k] = nb[6 * code + 3 + k]; }
                 } else {
                     int lc = ~code, start = lc >> 3, cnt = lc & 7;
                     for (int i = 0; i < cnt; ++i) {
-                        int f = b.perm[start + i];
+                        int f = perm[start + i];
                         for (int k = 0; k < 3; ++k) {
                             int vid = m.faces[3 * f + k];
                             for (int cc = 0; cc < 3; ++cc) {
@@ -507,23 +532,33 @@ __global__ void __launch_bounds__(256) k_loss_partial(LossArgs a)
     }
 }
 
-// one thread per hand: reduce its views' chunks in order
-__global__ void k_loss_final(LossArgs a)
+// one block per hand: per view, the chunk partials are summed in a fixed order
+__global__ void __launch_bounds__(256) k_loss_final(LossArgs a)
 {
-    const int h = blockIdx.x * blockDim.x + threadIdx.x;
-    if (h >= a.n_hands) return;
+    __shared__ float red[2 * 4];
+    const int h = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     float loss = 0.0f;
     for (int q = a.hand_view_off[h]; q < a.hand_view_off[h + 1]; ++q) {
         const int v = a.hand_views[q];
         float s = 0.0f, cnt = 0.0f;
-        for (int k = a.view_chunk_off[v]; k < a.view_chunk_off[v + 1]; ++k) {
+        for (int k = a.view_chunk_off[v] + threadIdx.x; k < a.view_chunk_off[v + 1]; k += blockDim.x) {
             s += a.partial[2 * k];
             cnt += a.partial[2 * k + 1];
         }
-        a.view_scale[v] = cnt > 0.0f ? 1.0f / (3.0f * cnt) : 0.0f;
-        if (cnt > 0.0f) loss += s / (3.0f * cnt);
+        s = wave_sum(s);
+        cnt = wave_sum(cnt);
+        if (lane == 0) { red[2 * w] = s; red[2 * w + 1] = cnt; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float ts = 0.0f, tc = 0.0f;
+            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ts += red[2 * k]; tc += red[2 * k + 1]; }
+            a.view_scale[v] = tc > 0.0f ? 1.0f / (3.0f * tc) : 0.0f;
+            if (tc > 0.0f) loss += ts / (3.0f * tc);
+        }
+        __syncthreads();
     }
-    a.loss[h] = loss;
+    if (threadIdx.x == 0) a.loss[h] = loss;
 }
 
 __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
@@ -586,7 +621,6 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
         const float* normals = a.normals + (size_t)hand * a.n_verts * 3;
         const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
         float* gtex = a.grad_albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
-        float* gout = a.gacc + (size_t)hand * a.n_verts * 6;
         const uint64_t c2 = (uint64_t)(uint32_t)e.x | (kDomainCamera << 32);
         for (int r = 0; r < a.ts.rounds; ++r) {
             const int s = s_lane + 64 * r;
@@ -595,6 +629,9 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
             float gv[18];
             for (int k = 0; k < 18; ++k) gv[k] = 0.0f;
             int face = -1;
+            int tidx[4] = {0, 0, 0, 0};   // texels of the bilinear footprint
+            float twt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            int tmask = 0;
             if (live && s < a.spp) {
                 const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, (uint64_t)a.iter, a.seed, 0);
                 const uint64_t wd = pick(rr, s & 3);
@@ -611,11 +648,11 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
                     surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
                     Shade sd;
                     shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, S, sd);
-                    // colour map texels
                     for (int k = 0; k < 4; ++k) {
-                        const float wk = sd.shade * sd.w[k];
-                        for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * sd.idx[k] + ch, g[ch] * wk);
+                        tidx[k] = sd.idx[k];
+                        twt[k] = sd.shade * sd.w[k];
                     }
+                    tmask = 0xF;
                     const float gs = g[0] * sd.col[0] + g[1] * sd.col[1] + g[2] * sd.col[2];
                     float gtu = 0.0f, gtv = 0.0f;
                     for (int ch = 0; ch < 3; ++ch) {
@@ -664,31 +701,48 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
                     }
                 }
             }
-            // Samples of a pixel mostly hit the same triangle: when all hitting
-            // lanes of the group agree, sum over the group and let one lane
-            // scatter; otherwise every hitting lane scatters its own values.
-            int fmin = face < 0 ? 0x7fffffff : face, fmax = face;
-            for (int o = G >> 1; o > 0; o >>= 1) {
-                fmin = min(fmin, __shfl_xor(fmin, o));
-                fmax = max(fmax, __shfl_xor(fmax, o));
-            }
-            const bool uniform = fmax >= 0 && fmin == fmax;
-            if (__any(uniform)) {
-                for (int k = 0; k < 18; ++k) {
-                    float x = gv[k];
-                    for (int o = G >> 1; o > 0; o >>= 1) x += __shfl_xor(x, o);
-                    if (uniform) gv[k] = x;
+            // Colour map: all lanes of a pixel share dL/dI, so the gradient of
+            // texel j is dL/dI * sum of (shade * bilinear weight) over the
+            // pixel's samples touching j.  Sum per texel within the pixel's
+            // lanes; one lane per (pixel, texel) scatters.
+            {
+                const int gbase = lane & ~(G - 1);
+                const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
+                while (__any(tmask != 0)) {
+                    const unsigned long long b = __ballot(tmask != 0);
+                    const unsigned long long seg = (b >> gbase) & gmask;
+                    const int first = tmask ? tidx[__ffs(tmask) - 1] : -1;
+                    const int leader = seg ? gbase + __ffsll((long long)seg) - 1 : lane;
+                    const int tau = __shfl(first, leader);
+                    float wsum = 0.0f;
+                    if (seg) {
+                        for (int k = 0; k < 4; ++k)
+                            if (((tmask >> k) & 1) && tidx[k] == tau) { wsum += twt[k]; tmask &= ~(1 << k); }
+                    }
+                    for (int o = G >> 1; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
+                    if (seg && lane == leader)
+                        for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * tau + ch, g[ch] * wsum);
                 }
             }
-            const bool scatter = uniform ? (s_lane == 0) : (face >= 0);
-            if (scatter) {
-                const int f = uniform ? fmax : face;
-                const int vid[3] = {a.faces[3 * f], a.faces[3 * f + 1], a.faces[3 * f + 2]};
-                for (int k = 0; k < 3; ++k)
-                    for (int q = 0; q < 3; ++q) {
-                        unsafeAtomicAdd(gout + 6 * vid[k] + q, gv[3 * k + q]);
-                        unsafeAtomicAdd(gout + 6 * vid[k] + 3 + q, gv[9 + 3 * k + q]);
-                    }
+            // Sum the lanes' contributions per triangle (a wave's samples hit a
+            // few triangles) and let one lane scatter each sum into the
+            // triangle's slot: [corner k][dL/dv (3), dL/dn (3)].
+            unsigned long long pending = __ballot(face >= 0);
+            while (pending) {
+                const int leader = __ffsll((long long)pending) - 1;
+                const int f = __shfl(face, leader);
+                const bool mine = face == f;
+                pending &= ~__ballot(mine);
+                float sum[18];
+                for (int k = 0; k < 18; ++k) sum[k] = wave_sum(mine ? gv[k] : 0.0f);
+                if (lane == leader) {
+                    float* slot = a.gface + ((size_t)hand * a.n_faces + f) * 18;
+                    for (int k = 0; k < 3; ++k)
+                        for (int q = 0; q < 3; ++q) {
+                            unsafeAtomicAdd(slot + 6 * k + q, sum[3 * k + q]);
+                            unsafeAtomicAdd(slot + 6 * k + 3 + q, sum[9 + 3 * k + q]);
+                        }
+                }
             }
         }
     }
@@ -941,9 +995,24 @@ __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
 // normals backward + skinning backward (one block per hand)
 // ===========================================================================
 
+// gradient of vertex v (q0 = 0: position, 3: normal): its own slot plus the
+// slots of the triangle corners it occupies, in CSR order
+__device__ __forceinline__ void vertex_grad(const MeshDev& m, const float* gvtx, const float* gf, int v, int q0,
+                                            float* out)
+{
+    out[0] = gvtx[6 * v + q0]; out[1] = gvtx[6 * v + q0 + 1]; out[2] = gvtx[6 * v + q0 + 2];
+    for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+        const int f = m.vf_faces[k];
+        const int corner = m.faces[3 * f] == v ? 0 : (m.faces[3 * f + 1] == v ? 1 : 2);
+        const float* sl = gf + 18 * f + 6 * corner + q0;
+        out[0] += sl[0]; out[1] += sl[1]; out[2] += sl[2];
+    }
+}
+
 __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* __restrict__ params,
                                                        const float* __restrict__ verts,
                                                        const float* __restrict__ gacc,
+                                                       const float* __restrict__ gface,
                                                        float* __restrict__ grad_params,
                                                        float* __restrict__ grad_verts,
                                                        float* __restrict__ grad_normals)
@@ -952,7 +1021,9 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
     __shared__ SkinShared sh;
     __shared__ float gJ[kMaxJoints * 3];
     __shared__ float gAt[kMaxJoints * 3];
+    __shared__ float gGt[kMaxJoints * 3];
     __shared__ float gGR[kMaxJoints * 9];
+    __shared__ float gR[kMaxJoints * 9];
     __shared__ float gmisc[16];
     const int h = blockIdx.x;
     const int V = m.V, F = m.F, J = m.J, K = m.K;
@@ -960,9 +1031,10 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
     float* fn = vsh + 3 * V;       // raw face normals [F*3]
     float* graw = fn + 3 * F;      // dL/d(raw vertex normal) [V*3]
     float* gv = graw + 3 * V;      // total dL/dv [V*3]
-    float* vs = gv + 3 * V;        // shaped vertices [V*3]
+    float* vs = vsh;               // shaped vertices [V*3], once the posed ones are no longer needed
     const float* vh = verts + (size_t)h * V * 3;
-    const float* ga = gacc + (size_t)h * V * 6;
+    const float* gvtx = gacc + (size_t)h * V * 6;
+    const float* gf = gface + (size_t)h * F * 18;
     for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
     __syncthreads();
     for (int f = threadIdx.x; f < F; f += blockDim.x) {
@@ -984,7 +1056,8 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
         float len = sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
         float il = 1.0f / len;
         float n[3] = {s[0] * il, s[1] * il, s[2] * il};
-        float gn[3] = {ga[6 * v + 3], ga[6 * v + 4], ga[6 * v + 5]};
+        float gn[3];
+        vertex_grad(m, gvtx, gf, v, 3, gn);
         if (grad_normals) {
             float* o = grad_normals + ((size_t)h * V + v) * 3;
             o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
@@ -995,7 +1068,8 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
     __syncthreads();
     // face normal f = e1 x e2: dL/de1 = e2 x gf, dL/de2 = gf x e1, gathered per vertex
     for (int v = threadIdx.x; v < V; v += blockDim.x) {
-        float acc[3] = {ga[6 * v], ga[6 * v + 1], ga[6 * v + 2]};
+        float acc[3];
+        vertex_grad(m, gvtx, gf, v, 0, acc);
         for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
             int f = m.vf_faces[k];
             int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
@@ -1019,7 +1093,8 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
     // ---- skinning backward ----
     const float* p = params + 64 * h;
     skin_common(m, p, vs, sh);
-    // global transform: v = Rp vp + tau
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    // global transform v = Rp vp + tau: dL/dRp = sum_v g_v vp_v^T, dL/dtau = sum_v g_v
     {
         float part[12];
         for (int i = 0; i < 12; ++i) part[i] = 0.0f;
@@ -1035,13 +1110,12 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
         block_sum<12>(part, sh.red, out);
         if (threadIdx.x < 12) gmisc[threadIdx.x] = out[threadIdx.x];
     }
-    __syncthreads();
-    // per joint: dL/dGR_j = sum_v W_vj gvp_v vs_v^T, dL/dAt_j = sum_v W_vj gvp_v
-    for (int j = 0; j < J; ++j) {
+    // per joint (one wave each): dL/dGR_j = sum_v W_vj gvp_v vs_v^T, dL/dAt_j = sum_v W_vj gvp_v
+    for (int j = wave; j < J; j += nwv) {
         float part[12];
         for (int i = 0; i < 12; ++i) part[i] = 0.0f;
-        for (int v = threadIdx.x; v < V; v += blockDim.x) {
-            float w = m.weights[(size_t)v * J + j];
+        for (int v = lane; v < V; v += 64) {
+            const float w = m.weights[(size_t)v * J + j];
             if (w == 0.0f) continue;
             float gvp[3];
             matTvec3(sh.Rp, gv + 3 * v, gvp);
@@ -1050,75 +1124,90 @@ __global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* _
                 part[9 + i] += w * gvp[i];
             }
         }
-        float out[12];
-        block_sum<12>(part, sh.red, out);
-        if (threadIdx.x < 9) gGR[9 * j + threadIdx.x] = out[threadIdx.x];
-        if (threadIdx.x < 3) gAt[3 * j + threadIdx.x] = out[9 + threadIdx.x];
+        for (int i = 0; i < 12; ++i) part[i] = wave_sum(part[i]);
+        if (lane == 0) {
+            for (int i = 0; i < 9; ++i) gGR[9 * j + i] = part[i];
+            for (int i = 0; i < 3; ++i) gAt[3 * j + i] = part[9 + i];
+        }
     }
     __syncthreads();
     float* gp = grad_params + 64 * h;
-    if (threadIdx.x == 0) {
-        float gGt[kMaxJoints * 3];
-        for (int j = 0; j < J; ++j)
-            for (int i = 0; i < 3; ++i) { gGt[3 * j + i] = gAt[3 * j + i]; gJ[3 * j + i] = 0.0f; }
-        // At_j = Gt_j - GR_j J_j
-        for (int j = 0; j < J; ++j) {
-            for (int i = 0; i < 3; ++i)
-                for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] -= gAt[3 * j + i] * sh.J[3 * j + k];
-            float y[3];
-            matTvec3(sh.GR + 9 * j, gAt + 3 * j, y);
-            for (int i = 0; i < 3; ++i) gJ[3 * j + i] -= y[i];
+    // At_j = Gt_j - GR_j J_j (per joint, parallel)
+    for (int j = threadIdx.x; j < J; j += blockDim.x) {
+        for (int i = 0; i < 3; ++i) {
+            gGt[3 * j + i] = gAt[3 * j + i];
+            for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] -= gAt[3 * j + i] * sh.J[3 * j + k];
         }
-        float gR[kMaxJoints * 9];
-        for (int j = J - 1; j >= 0; --j) {
-            int par = m.parents[j];
+        float y[3];
+        matTvec3(sh.GR + 9 * j, gAt + 3 * j, y);
+        for (int i = 0; i < 3; ++i) gJ[3 * j + i] = -y[i];
+    }
+    __syncthreads();
+    // forward kinematics in reverse, one tree level at a time (deepest first):
+    // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j.  Joints of level L
+    // finish their own terms while their parents (level L-1) pull the
+    // children's contributions.
+    for (int L = sh.max_depth; L >= 0; --L) {
+        const int j = threadIdx.x;
+        if (j < J && sh.depth[j] == L) {
+            const int par = m.parents[j];
             if (par < 0) {
                 for (int i = 0; i < 9; ++i) gR[9 * j + i] = gGR[9 * j + i];
                 for (int i = 0; i < 3; ++i) gJ[3 * j + i] += gGt[3 * j + i];
-                continue;
+            } else {
+                const float* GRp = sh.GR + 9 * par;
+                float y[3];
+                matTvec3(GRp, gGt + 3 * j, y);
+                for (int i = 0; i < 3; ++i) gJ[3 * j + i] += y[i];
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) {
+                        float acc = 0.0f;
+                        for (int q = 0; q < 3; ++q) acc += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
+                        gR[9 * j + 3 * i + k] = acc;
+                    }
             }
-            const float* GRp = sh.GR + 9 * par;
-            const float* Rj = sh.Rj + 9 * j;
-            float d[3] = {sh.J[3 * j] - sh.J[3 * par], sh.J[3 * j + 1] - sh.J[3 * par + 1],
-                          sh.J[3 * j + 2] - sh.J[3 * par + 2]};
-            // Gt_j = GRp d + Gt_p ; GR_j = GRp Rj
-            for (int i = 0; i < 3; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    float s = gGt[3 * j + i] * d[k];
-                    for (int q = 0; q < 3; ++q) s += gGR[9 * j + 3 * i + q] * Rj[3 * k + q];
-                    gGR[9 * par + 3 * i + k] += s;
-                }
-            float y[3];
-            matTvec3(GRp, gGt + 3 * j, y);
-            for (int i = 0; i < 3; ++i) { gJ[3 * j + i] += y[i]; gJ[3 * par + i] -= y[i]; gGt[3 * par + i] += gGt[3 * j + i]; }
-            for (int i = 0; i < 3; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    float s = 0.0f;
-                    for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
-                    gR[9 * j + 3 * i + k] = s;
-                }
         }
-        for (int j = 0; j < J; ++j) {
-            Rod rd;
-            rodrigues(p + 3 * j, rd);
-            rodrigues_bwd(p + 3 * j, rd, gR + 9 * j, gp + 3 * j);
+        const int pj = threadIdx.x - 64;   // a second wave handles the parents
+        if (pj >= 0 && pj < J && sh.depth[pj] == L - 1) {
+            const float* GRp = sh.GR + 9 * pj;
+            for (int c = pj + 1; c < J; ++c) {
+                if (m.parents[c] != pj) continue;
+                const float* Rc = sh.Rj + 9 * c;
+                const float d[3] = {sh.J[3 * c] - sh.J[3 * pj], sh.J[3 * c + 1] - sh.J[3 * pj + 1],
+                                    sh.J[3 * c + 2] - sh.J[3 * pj + 2]};
+                for (int i = 0; i < 3; ++i)
+                    for (int k = 0; k < 3; ++k) {
+                        float acc = gGt[3 * c + i] * d[k];
+                        for (int q = 0; q < 3; ++q) acc += gGR[9 * c + 3 * i + q] * Rc[3 * k + q];
+                        gGR[9 * pj + 3 * i + k] += acc;
+                    }
+                float y[3];
+                matTvec3(GRp, gGt + 3 * c, y);
+                for (int i = 0; i < 3; ++i) {
+                    gJ[3 * pj + i] -= y[i];
+                    gGt[3 * pj + i] += gGt[3 * c + i];
+                }
+            }
         }
-        for (int j = J; j < 16; ++j) gp[3 * j] = gp[3 * j + 1] = gp[3 * j + 2] = 0.0f;
-        Rod rp;
-        rodrigues(p + 58, rp);
-        rodrigues_bwd(p + 58, rp, gmisc, gp + 58);
-        gp[61] = gmisc[9]; gp[62] = gmisc[10]; gp[63] = gmisc[11];
+        __syncthreads();
     }
-    __syncthreads();
-    // shaped vertices: dL/dvs_v = sum_j W_vj GR_j^T gvp_v + sum_j Jreg_jv gJ_j
+    // axis-angle gradients of the joint rotations and the global rotation (parallel)
+    if ((int)threadIdx.x <= J) {
+        const int j = threadIdx.x;
+        if (j < J) rodrigues_bwd(p + 3 * j, sh.rod[j], gR + 9 * j, gp + 3 * j);
+        else rodrigues_bwd(p + 58, sh.rod[J], gmisc, gp + 58);
+    }
+    for (int j = J + threadIdx.x; j < 16; j += blockDim.x) gp[3 * j] = gp[3 * j + 1] = gp[3 * j + 2] = 0.0f;
+    if (threadIdx.x == 0) { gp[61] = gmisc[9]; gp[62] = gmisc[10]; gp[63] = gmisc[11]; }
+    // shaped vertices: dL/dvs_v = sum_j W_vj GR_j^T gvp_v + sum_j Jreg_jv gJ_j; dL/dbeta
     float part[16];
     for (int k = 0; k < 16; ++k) part[k] = 0.0f;
     for (int v = threadIdx.x; v < V; v += blockDim.x) {
         float gvp[3], g[3] = {0.0f, 0.0f, 0.0f};
         matTvec3(sh.Rp, gv + 3 * v, gvp);
         for (int j = 0; j < J; ++j) {
-            float w = m.weights[(size_t)v * J + j];
-            float jr = m.j_regressor[(size_t)j * V + v];
+            const float w = m.weights[(size_t)v * J + j];
+            const float jr = m.j_regressor[(size_t)j * V + v];
             if (w != 0.0f) {
                 float y[3];
                 matTvec3(sh.GR + 9 * j, gvp, y);

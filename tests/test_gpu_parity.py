@@ -177,3 +177,19 @@ def test_background_only_view(tiny):
     g.render(c.t(c.v32), c.t(c.albedo), bg, 0, img, hf)
     torch.cuda.synchronize()
     assert torch.equal(img, bg) and bool((hf == -1).all())
+
+
+def test_hierarchy_topology_does_not_change_results(tiny):
+    # the rebuilt (surface-area heuristic) hierarchy changes only the visiting
+    # order: images and hit ids stay bit-identical
+    c = tiny
+    img0, hit0 = c.gpu_render(2, hits=True)
+    g = binding.Scene(c.model, c.cams, 1, c.w.spp, c.th, c.tw, seed=c.seed)
+    v = c.t(c.v32)
+    g.build_hierarchy(v)
+    img = torch.empty(c.P, 3, device=DEV)
+    hf = torch.empty(c.P, c.w.spp, device=DEV, dtype=torch.int32)
+    g.render(v, c.t(c.albedo), c.t(c.bg), 2, img, hf)
+    torch.cuda.synchronize()
+    assert np.array_equal(hf.cpu().numpy(), hit0)
+    assert np.array_equal(img.cpu().numpy(), img0)
