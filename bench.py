@@ -225,6 +225,8 @@ def main():
         "traced_mrays_per_s": round(traced / (ms * 1e-3) / 1e6, 2),
         "edge_samples_per_step": int(bud.sum()),
         "kernels": {k: round(v["ms_per_launch"] * 1e3, 2) for k, v in per_kernel.items()},
+        "work_counts": {k: {"rays": int(v[0]), "node_visits": int(v[1]), "tri_tests": int(v[2]), "hits": int(v[3])}
+                        for k, v in counts.items()},
         "kernels_unit": "us per launch",
         "roofline": roof,
     }

@@ -704,11 +704,15 @@ void ora_edge_weights(int n_hands, int V, int F, const double* verts, const int3
 
 /*
  * ora_backward_edges: boundary term of the gradient of sum_p dimage[p] . I_p.
- * For each view, `budget` samples are drawn along silhouette edges with
- * probability proportional to the quantised length weight, uniformly along
- * the chosen edge.  A sample at x on an edge with screen
- * normal n contributes g_p . (c(x - delta n) - c(x + delta n)) / (pdf(x) M)
- * times the normal velocity of the edge, split linearly between its endpoints.
+ * For each view, `budget` M samples are drawn along silhouette edges: the
+ * quantised length weights form an integer CDF of total T; sample k takes a
+ * uniform target in the k-th of M strata [k T/M, (k+1) T/M) of it (stratified
+ * sampling), picks the edge whose CDF interval holds the target, and a
+ * uniform point along the chosen edge.  With stratum width n_k and density
+ * (w_e/T)/len_e per unit length, a sample at x on an edge with screen normal n
+ * contributes g_p . (c(x - delta n) - c(x + delta n)) * len_e * n_k / w_e
+ * times the normal velocity of the edge, split linearly between its endpoints
+ * (an unbiased estimate of the boundary integral).
  *   g_verts [n_hands,V,3] f64 accumulated into.
  *   budget_override [n_views] i64 (nullable): number of samples per view.
  *   edge_stats [n_views,E] f64 (nullable): accumulates |g.(c- - c+)| / (pdf M)
@@ -740,12 +744,18 @@ void ora_backward_edges(int n_hands, int V, int F, const double* verts, const do
         if (T == 0) continue;
         int64_t Mv = (int64_t)((T + 255) / 256);
         if (budget_override) Mv = budget_override[vi];
+        if (Mv <= 0) continue;
         for (int64_t k = 0; k < Mv; ++k) {
             uint64_t ctr[4] = {(uint64_t)k, 0, (uint64_t)(uint32_t)vi | (DOMAIN_EDGE << 32), (uint64_t)iter};
             uint64_t key[2] = {seed, 0};
             uint64_t r[4];
             philox4x64_10(ctr, key, r);
-            uint64_t target = (uint64_t)(((unsigned __int128)r[0] * T) >> 64);
+            /* stratum k of the quantised-length CDF: targets [k T / M, (k+1) T / M) */
+            uint64_t lo = (uint64_t)(((unsigned __int128)k * T) / (uint64_t)Mv);
+            uint64_t hi = (uint64_t)(((unsigned __int128)(k + 1) * T) / (uint64_t)Mv);
+            uint64_t width = hi - lo;
+            if (width == 0) continue;
+            uint64_t target = lo + (uint64_t)(((unsigned __int128)r[0] * width) >> 64);
             /* first edge whose inclusive prefix sum exceeds the target */
             int e = 0;
             while (cdf[e] <= target) ++e;
@@ -789,8 +799,8 @@ void ora_backward_edges(int n_hands, int V, int F, const double* verts, const do
             double len64 = sqrt(ddx * ddx + ddy * ddy);
             double nx = ddy / len64, ny = -ddx / len64;
             double ell = len64 * ((double)q->t1 - (double)q->t0);
-            /* 1/(pdf M) with pdf = (w_e/T)/ell per unit length */
-            double inv_pdf_m = ell * (double)T / ((double)q->w * (double)Mv);
+            /* sample weight: (stratum probability width/T) / (pdf (w_e/T)/ell) */
+            double inv_pdf_m = ell * (double)width / (double)q->w;
             double jump = g[0] * (cm[0] - cp[0]) + g[1] * (cm[1] - cp[1]) + g[2] * (cm[2] - cp[2]);
             double s = jump * inv_pdf_m;
             if (edge_stats) edge_stats[(size_t)vi * E + e] += fabs(s);

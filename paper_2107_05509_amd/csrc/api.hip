@@ -300,7 +300,6 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     // per-iteration state
     TRY(s->upload<int2>(&s->tiles, nullptr, (size_t)s->tile_cap));
     TRY(s->upload<int>(&s->tile_count, nullptr, 4));
-    TRY(s->upload<long long>(&s->edge_prefix, nullptr, (size_t)n_views + 1));
     TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
     TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
     TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.node_stride));
@@ -312,6 +311,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<unsigned long long>(&s->edge_cdf, nullptr, (size_t)n_views * E));
     TRY(s->upload<unsigned long long>(&s->edge_total, nullptr, n_views));
     TRY(s->upload<long long>(&s->edge_budget, nullptr, n_views));
+    TRY(s->upload<long long>(&s->edge_prefix, nullptr, (size_t)n_views + 1));
     TRY(s->upload<unsigned long long>(&s->counts, nullptr, 12));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)0, s->counts, 12);
     if (hipDeviceSynchronize() != hipSuccess) { hr_scene_destroy(s); return fail(HR_EHIP, "scene init failed"); }
@@ -522,6 +522,7 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
         a.m = s->mesh; a.views = s->views; a.verts = verts;
         a.rec = s->edge_rec; a.cdf = s->edge_cdf; a.total = s->edge_total; a.budget = s->edge_budget;
         a.prefix = s->edge_prefix; a.n_views = s->n_views;
+
         a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
         a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
         a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
@@ -532,10 +533,11 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
         rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
                     s->n_views, s->edge_prefix);
         if (rc) return rc;
+        const dim3 eg(1024);
         if (s->counting)
-            rc = launch(s, "k_edge_sample", k_edge_sample<true>, dim3(1024), dim3(kThreads), 0, st, a);
+            rc = launch(s, "k_edge_sample", k_edge_sample<true>, eg, dim3(kThreads), 0, st, a);
         else
-            rc = launch(s, "k_edge_sample", k_edge_sample<false>, dim3(1024), dim3(kThreads), 0, st, a);
+            rc = launch(s, "k_edge_sample", k_edge_sample<false>, eg, dim3(kThreads), 0, st, a);
         if (rc) return rc;
     }
     return launch(s, "k_geom_backward", k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh,

@@ -108,6 +108,7 @@ struct EdgeArgs {
     long long* budget;         // [n_views]
     long long* prefix;         // [n_views+1] exclusive prefix of budgets
     int n_views;
+
     const Node* nodes;
     const Tri* tris;
     const float* normals;

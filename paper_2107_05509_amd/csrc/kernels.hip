@@ -900,7 +900,9 @@ __global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict
 }
 
 // One edge sample per lane pair: the even lane traces the ray at x + delta n,
-// the odd lane the ray at x - delta n.
+// the odd lane the ray at x - delta n.  Consecutive global sample indices are
+// consecutive strata of one view's CDF, so the lanes of a wave work on
+// neighbouring edges.
 template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
 {
@@ -908,40 +910,51 @@ __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
     int* stk = stack + threadIdx.x;
     const long long total = a.prefix[a.n_views];
     const int side = threadIdx.x & 1;
-    const long long npairs = ((long long)gridDim.x * blockDim.x) >> 1;
     const int E = a.m.E;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
+    const long long npairs = ((long long)gridDim.x * blockDim.x) >> 1;
     for (long long kg = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 1; kg < total; kg += npairs) {
         // view of global sample kg: last v with prefix[v] <= kg
-        int lo = 0, hi = a.n_views - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (a.prefix[mid] <= kg) lo = mid; else hi = mid - 1;
+        int vlo = 0, vhi = a.n_views - 1;
+        while (vlo < vhi) {
+            const int mid = (vlo + vhi + 1) >> 1;
+            if (a.prefix[mid] <= kg) vlo = mid; else vhi = mid - 1;
         }
-        const int vi = lo;
+        const int vi = vlo;
         const long long k = kg - a.prefix[vi];
-        const ViewDev& c = a.views[vi];
         const long long M = a.budget[vi];
         const unsigned long long T = a.total[vi];
+        const ViewDev& c = a.views[vi];
         const EdgeRec* rec = a.rec + (size_t)vi * E;
         const unsigned long long* cdf = a.cdf + (size_t)vi * E;
         const int hand = c.hand;
+        const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
+        const Tri* tris = a.tris + (size_t)hand * a.m.F;
+        const float* normals = a.normals + (size_t)hand * a.m.V * 3;
+        const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
         const uint64_t c2 = (uint64_t)(uint32_t)vi | (kDomainEdge << 32);
-        const U64x4 r = philox4x64((uint64_t)k, 0, c2, (uint64_t)a.iter, a.seed, 0);
-        const unsigned long long target = __umul64hi(r.x[0], T);
+        // floor(k T / M) = k q + floor(k r / M) with q = T / M, r = T % M (k r < M^2 fits 64 bits)
+        const unsigned long long um = (unsigned long long)M, q = T / um, rm = T % um;
+        const unsigned long long uk = (unsigned long long)k;
+        const unsigned long long lo = uk * q + (uk * rm) / um;
+        const unsigned long long hi = (uk + 1) * q + ((uk + 1) * rm) / um;
+        const unsigned long long width = hi - lo;
+        if (width == 0) continue;   // same for both lanes of the pair
+        const U64x4 r = philox4x64(uk, 0, c2, (uint64_t)a.iter, a.seed, 0);
+        const unsigned long long target = lo + __umul64hi(r.x[0], width);
         int elo = 0, ehi = E - 1;   // first e with cdf[e] > target
         while (elo < ehi) {
             int mid = (elo + ehi) >> 1;
             if (cdf[mid] > target) ehi = mid; else elo = mid + 1;
         }
         const int e = elo;
-        const EdgeRec q = rec[e];
+        const EdgeRec qe = rec[e];
         const float u = u24_hi(r.x[1]);
-        const float t = q.t0 + u * (q.t1 - q.t0);
-        const float dx = q.bx - q.ax, dy = q.by - q.ay;
-        const float x = q.ax + t * dx;
-        const float y = q.ay + t * dy;
+        const float t = qe.t0 + u * (qe.t1 - qe.t0);
+        const float dx = qe.bx - qe.ax, dy = qe.by - qe.ay;
+        const float x = qe.ax + t * dx;
+        const float y = qe.ay + t * dy;
         const float len = sqrtf(dx * dx + dy * dy);
         const float nhx = dy / len, nhy = -dx / len;
         const float xs = side == 0 ? x + a.delta * nhx : x - a.delta * nhx;
@@ -953,10 +966,6 @@ __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
         const float g[3] = {a.dimage[3 * pg], a.dimage[3 * pg + 1], a.dimage[3 * pg + 2]};
         if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) continue;   // same for both lanes of the pair
         const float bg[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
-        const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
-        const Tri* tris = a.tris + (size_t)hand * a.m.F;
-        const float* normals = a.normals + (size_t)hand * a.m.V * 3;
-        const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
         Ray ray;
         Hit h;
         ray_screen(c, xs, ys, ray);
@@ -969,8 +978,9 @@ __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
         // c(x - delta n) - c(x + delta n)
         const float jump = g[0] * (o0 - col[0]) + g[1] * (o1 - col[1]) + g[2] * (o2 - col[2]);
         if (jump == 0.0f) continue;
-        const float ell = len * (q.t1 - q.t0);
-        const float sc = jump * (ell * (float)T / ((float)q.w * (float)M));
+        // weight: (stratum probability width/T) / (density (w_e/T)/len per unit length)
+        const float ell = len * (qe.t1 - qe.t0);
+        const float sc = jump * (ell * (float)width / (float)qe.w);
         const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
         const float* vh = a.verts + (size_t)hand * a.m.V * 3;
         float* gout = a.gacc + (size_t)hand * a.m.V * 6;
