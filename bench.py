@@ -194,10 +194,16 @@ def main():
                   for k, v in kern.items()}
     for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"]):
         print(f"[bench]   {k:22s} {v['ms_per_launch'] * 1e3:9.1f} us/launch", file=sys.stderr)
-    # roofline of the dominant ray-tracing kernel
-    dom = max(("k_render", "k_adjoint_interior"), key=lambda k: per_kernel[k]["ms_per_step"])
-    rays, nodes, tris, hits = counts[dom]
-    ops = rays * OPS_PER_RAY + nodes * OPS_PER_NODE + tris * OPS_PER_TRI + hits * OPS_PER_HIT[dom]
+    # roofline of the dominant ray-tracing kernel (the backward launch carries
+    # both the interior adjoint and the edge samples)
+    dom = max(("k_render", "k_backward_trace"), key=lambda k: per_kernel[k]["ms_per_step"])
+    parts = ["k_render"] if dom == "k_render" else ["k_adjoint_interior", "k_edge_sample"]
+    rays = sum(counts[p][0] for p in parts)
+    nodes = sum(counts[p][1] for p in parts)
+    tris = sum(counts[p][2] for p in parts)
+    hits = sum(counts[p][3] for p in parts)
+    ops = sum(counts[p][0] * OPS_PER_RAY + counts[p][1] * OPS_PER_NODE + counts[p][2] * OPS_PER_TRI
+              + counts[p][3] * OPS_PER_HIT[p] for p in parts)
     ach = ops / (per_kernel[dom]["ms_per_launch"] * 1e-3) / 1e12
     traffic = None
     tfile = os.path.join(ROOT, "profiles", "traffic.json")

@@ -363,6 +363,9 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st)
                   (const ViewDev*)s->views, verts, s->ts, s->tiles, s->tile_count);
 }
 
+static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
+                          const float* dimage, uint32_t iter);
+
 static Shading shading_of(const hr_config& c)
 {
     Shading S;
@@ -395,9 +398,26 @@ int hr_render(hr_scene* s, const float* verts, const float* albedo, const float*
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
-    if (s->counting)
-        return launch(s, "k_render", k_render<true>, dim3(s->trace_blocks), dim3(kThreads), 0, st, a);
-    return launch(s, "k_render", k_render<false>, dim3(s->trace_blocks), dim3(kThreads), 0, st, a);
+    // the silhouette tables of these vertices are built alongside
+    const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter);
+    const dim3 grid(s->n_views + s->trace_blocks);
+    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, s->n_views);
+    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, s->n_views);
+}
+
+static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
+                          const float* dimage, uint32_t iter)
+{
+    EdgeArgs a;
+    a.m = s->mesh; a.views = s->views; a.verts = verts;
+    a.rec = s->edge_rec; a.cdf = s->edge_cdf; a.total = s->edge_total; a.budget = s->edge_budget;
+    a.prefix = s->edge_prefix; a.n_views = s->n_views;
+    a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
+    a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
+    a.counts = s->counts + 8;
+    a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
+    a.delta = s->cfg.edge_delta; a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    return a;
 }
 
 int hr_set_counting(hr_scene* s, int32_t enable)
@@ -499,45 +519,34 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
     if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
     if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
     if (rc) return rc;
-    if (flags & HR_GRAD_INTERIOR) {
-        AdjointArgs a;
-        a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
-        a.faces = s->mesh.faces;
-        a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
-        a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
-        a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
-        a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
-        a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-        a.counts = s->counts + 4;
-        if (s->counting)
-            rc = launch(s, "k_adjoint_interior", k_adjoint_interior<true>, dim3(s->trace_blocks), dim3(kThreads), 0,
-                        st, a);
-        else
-            rc = launch(s, "k_adjoint_interior", k_adjoint_interior<false>, dim3(s->trace_blocks), dim3(kThreads), 0,
-                        st, a);
-        if (rc) return rc;
-    }
+    const EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter);
+    int n_edge = 0, n_adj = 0;
     if (flags & HR_GRAD_EDGES) {
-        EdgeArgs a;
-        a.m = s->mesh; a.views = s->views; a.verts = verts;
-        a.rec = s->edge_rec; a.cdf = s->edge_cdf; a.total = s->edge_total; a.budget = s->edge_budget;
-        a.prefix = s->edge_prefix; a.n_views = s->n_views;
-
-        a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
-        a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
-        a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
-        a.delta = s->cfg.edge_delta; a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-        rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(256), 0, st, a);
-        if (rc) return rc;
-        a.counts = s->counts + 8;
+        if (!(flags & HR_REUSE_GEOMETRY)) {
+            rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kThreads), 0, st, e);
+            if (rc) return rc;
+        }
         rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
                     s->n_views, s->edge_prefix);
         if (rc) return rc;
-        const dim3 eg(1024);
+        n_edge = kEdgeBlocks;
+    }
+    AdjointArgs a;
+    a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
+    a.faces = s->mesh.faces;
+    a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
+    a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
+    a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
+    a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
+    a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    a.counts = s->counts + 4;
+    if (flags & HR_GRAD_INTERIOR) n_adj = s->trace_blocks;
+    if (n_edge + n_adj > 0) {
+        const dim3 grid(n_edge + n_adj);
         if (s->counting)
-            rc = launch(s, "k_edge_sample", k_edge_sample<true>, eg, dim3(kThreads), 0, st, a);
+            rc = launch(s, "k_backward_trace", k_backward_trace<true>, grid, dim3(kThreads), 0, st, a, e, n_edge);
         else
-            rc = launch(s, "k_edge_sample", k_edge_sample<false>, eg, dim3(kThreads), 0, st, a);
+            rc = launch(s, "k_backward_trace", k_backward_trace<false>, grid, dim3(kThreads), 0, st, a, e, n_edge);
         if (rc) return rc;
     }
     return launch(s, "k_geom_backward", k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh,

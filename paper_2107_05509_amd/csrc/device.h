@@ -15,6 +15,7 @@ namespace hr {
 constexpr int kMaxStack = 24;       // traversal stack entries per lane
 constexpr int kLeafMax = 4;         // triangles per leaf
 constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
+constexpr int kEdgeBlocks = 256;    // blocks of edge samples in the backward launch
 
 // ---------------------------------------------------------------------------
 // records in device memory

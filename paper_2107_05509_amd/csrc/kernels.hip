@@ -417,16 +417,16 @@ __device__ __forceinline__ void tile_pixel(const TileShape& ts, int2 e, int lane
     py = (ty << ts.th_log2) + (pit >> ts.tw_log2);
 }
 
+// Render the listed wave tiles; this block is `bid` of `nb` blocks sharing them.
 template <bool COUNT>
-__global__ void __launch_bounds__(kThreads) k_render(RenderArgs a)
+__device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
 {
-    __shared__ int stack[kMaxStack * kThreads];
     int* stk = stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
     const int s_lane = lane & (G - 1);
-    const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kThreads + threadIdx.x) >> 6));
-    const int nw = (int)((gridDim.x * kThreads) >> 6);
+    const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
+    const int nw = (int)((nb * kThreads) >> 6);
     const int n_tiles = *a.tile_count;
     const float inv_spp = 1.0f / (float)a.spp;
     TraceCount tc;
@@ -584,16 +584,16 @@ __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
 // interior adjoint
 // ===========================================================================
 
+// Interior adjoint over the listed wave tiles; block `bid` of `nb`.
 template <bool COUNT>
-__global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
+__device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack)
 {
-    __shared__ int stack[kMaxStack * kThreads];
     int* stk = stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
     const int s_lane = lane & (G - 1);
-    const int gw = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * kThreads + threadIdx.x) >> 6));
-    const int nw = (int)((gridDim.x * kThreads) >> 6);
+    const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
+    const int nw = (int)((nb * kThreads) >> 6);
     const int n_tiles = *a.tile_count;
     const float inv_spp = 1.0f / (float)a.spp;
     const Shading S = a.shading;
@@ -758,10 +758,9 @@ __global__ void __launch_bounds__(kThreads) k_adjoint_interior(AdjointArgs a)
 // silhouette edges: classification, quantised weights, prefix sums
 // ===========================================================================
 
-__global__ void __launch_bounds__(256) k_edges_setup(EdgeArgs a)
+// Silhouette table of view `vi` (one block of 256 threads; `part` is LDS [256]).
+__device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* part)
 {
-    __shared__ unsigned long long part[256];
-    const int vi = blockIdx.x;
     const ViewDev c = a.views[vi];
     const float* vh = a.verts + (size_t)c.hand * a.m.V * 3;
     const int E = a.m.E;
@@ -903,18 +902,18 @@ __global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict
 // the odd lane the ray at x - delta n.  Consecutive global sample indices are
 // consecutive strata of one view's CDF, so the lanes of a wave work on
 // neighbouring edges.
+// Edge samples of all views; block `bid` of `nb`.
 template <bool COUNT>
-__global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
+__device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
 {
-    __shared__ int stack[kMaxStack * kThreads];
     int* stk = stack + threadIdx.x;
     const long long total = a.prefix[a.n_views];
     const int side = threadIdx.x & 1;
     const int E = a.m.E;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
-    const long long npairs = ((long long)gridDim.x * blockDim.x) >> 1;
-    for (long long kg = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 1; kg < total; kg += npairs) {
+    const long long npairs = ((long long)nb * kThreads) >> 1;
+    for (long long kg = ((long long)bid * kThreads + threadIdx.x) >> 1; kg < total; kg += npairs) {
         // view of global sample kg: last v with prefix[v] <= kg
         int vlo = 0, vhi = a.n_views - 1;
         while (vlo < vhi) {
@@ -999,6 +998,43 @@ __global__ void __launch_bounds__(kThreads) k_edge_sample(EdgeArgs a)
         atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
         atomicAdd(a.counts + 3, n_hit);
     }
+}
+
+// ===========================================================================
+// launches of the ray-tracing work
+// ===========================================================================
+
+// Render; the first `n_setup` blocks build the silhouette tables of the views
+// (they need only the geometry) alongside the render blocks.
+template <bool COUNT>
+__global__ void __launch_bounds__(kThreads) k_render(RenderArgs a, EdgeArgs e, int n_setup)
+{
+    __shared__ int stack[kMaxStack * kThreads];
+    if ((int)blockIdx.x < n_setup) {
+        edges_setup_view(e, blockIdx.x, reinterpret_cast<unsigned long long*>(stack));
+        return;
+    }
+    render_tiles<COUNT>(a, (int)blockIdx.x - n_setup, (int)gridDim.x - n_setup, stack);
+}
+
+__global__ void __launch_bounds__(kThreads) k_edges_setup(EdgeArgs e)
+{
+    __shared__ unsigned long long part[kThreads];
+    edges_setup_view(e, blockIdx.x, part);
+}
+
+// Backward ray tracing: the first `n_edge` blocks draw the edge samples, the
+// rest run the interior adjoint; in one launch the latency-bound edge
+// samples overlap with the adjoint's arithmetic.
+template <bool COUNT>
+__global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge)
+{
+    __shared__ int stack[kMaxStack * kThreads];
+    if ((int)blockIdx.x < n_edge) {
+        edge_samples<COUNT>(e, blockIdx.x, n_edge, stack);
+        return;
+    }
+    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, stack);
 }
 
 // ===========================================================================
