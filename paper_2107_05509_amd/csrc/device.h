@@ -16,6 +16,7 @@ constexpr int kMaxStack = 24;       // traversal stack entries per lane
 constexpr int kLeafMax = 4;         // triangles per leaf
 constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
 constexpr int kEdgeBlocks = 256;    // blocks of edge samples in the backward launch
+constexpr int kPatch = 16;          // texel patch (per wave) of the colour-map gradient
 
 // ---------------------------------------------------------------------------
 // records in device memory
@@ -345,6 +346,7 @@ struct Shade {
     float n[3], nlen;           // unit interpolated normal and the raw length
     float ndotl, shade;
     int idx[4];                 // texel indices
+    int ti0, ti1, tj0, tj1;     // texel rows / columns of the bilinear footprint
     float w[4];                 // bilinear weights
     float col[3];               // albedo
     float dcol_du[3], dcol_dv[3];
@@ -376,6 +378,7 @@ __device__ __forceinline__ void shade_hit(const Surf& h, const float* __restrict
     int j1 = min(max(j0 + 1, 0), tw - 1), i1 = min(max(i0 + 1, 0), th - 1);
     j0 = min(max(j0, 0), tw - 1);
     i0 = min(max(i0, 0), th - 1);
+    o.ti0 = i0; o.ti1 = i1; o.tj0 = j0; o.tj1 = j1;
     o.idx[0] = i0 * tw + j0; o.w[0] = (1.0f - ax) * (1.0f - ay);
     o.idx[1] = i0 * tw + j1; o.w[1] = ax * (1.0f - ay);
     o.idx[2] = i1 * tw + j0; o.w[2] = (1.0f - ax) * ay;
@@ -415,6 +418,28 @@ __device__ __forceinline__ float wave_sum(float v)
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// order the wave's LDS accesses across lanes (no block barrier: waves of a
+// block run independently in the persistent loops)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 }  // namespace hr

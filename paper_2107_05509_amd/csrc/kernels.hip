@@ -586,8 +586,9 @@ __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
 
 // Interior adjoint over the listed wave tiles; block `bid` of `nb`.
 template <bool COUNT>
-__device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack)
+__device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack, float* patch_base)
 {
+    float* patch = patch_base + 3 * kPatch * kPatch * (threadIdx.x >> 6);
     int* stk = stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
@@ -632,6 +633,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack)
             int tidx[4] = {0, 0, 0, 0};   // texels of the bilinear footprint
             float twt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             int tmask = 0;
+            int fi0 = 0x7fffffff, fi1 = -1, fj0 = 0x7fffffff, fj1 = -1;   // footprint rows / columns
             if (live && s < a.spp) {
                 const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, (uint64_t)a.iter, a.seed, 0);
                 const uint64_t wd = pick(rr, s & 3);
@@ -653,6 +655,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack)
                         twt[k] = sd.shade * sd.w[k];
                     }
                     tmask = 0xF;
+                    fi0 = sd.ti0; fi1 = sd.ti1; fj0 = sd.tj0; fj1 = sd.tj1;
                     const float gs = g[0] * sd.col[0] + g[1] * sd.col[1] + g[2] * sd.col[2];
                     float gtu = 0.0f, gtv = 0.0f;
                     for (int ch = 0; ch < 3; ++ch) {
@@ -701,7 +704,37 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack)
                     }
                 }
             }
-            // Colour map: all lanes of a pixel share dL/dI, so the gradient of
+            // Colour map.  Usually the wave's samples touch at most 16x16 texels:
+            // sum them in an LDS patch and add the patch to the gradient row
+            // by row, consecutive lanes on consecutive floats (a few memory
+            // transactions per row instead of one per texel and channel).
+            const int pi0 = wave_min(fi0), pi1 = wave_max(fi1);
+            const int pj0 = wave_min(fj0), pj1 = wave_max(fj1);
+            const bool use_patch = pi1 >= pi0 && pi1 - pi0 < kPatch && pj1 - pj0 < kPatch;
+            if (use_patch) {
+                float* pch = patch;   // this wave's [kPatch][kPatch][3]
+                const int nrow = pi1 - pi0 + 1, ncol = 3 * (pj1 - pj0 + 1);
+                for (int f = lane; f < 3 * kPatch * kPatch; f += 64) pch[f] = 0.0f;
+                wave_lds_sync();
+                if (tmask) {
+                    const int ri[4] = {fi0, fi0, fi1, fi1}, rj[4] = {fj0, fj1, fj0, fj1};
+                    for (int k = 0; k < 4; ++k) {
+                        float* dst = pch + ((ri[k] - pi0) * kPatch + (rj[k] - pj0)) * 3;
+                        for (int ch = 0; ch < 3; ++ch) atomicAdd(dst + ch, g[ch] * twt[k]);
+                    }
+                    tmask = 0;
+                }
+                wave_lds_sync();
+                for (int f = lane; f < nrow * 3 * kPatch; f += 64) {
+                    const int row = f / (3 * kPatch), o = f - 3 * kPatch * row;
+                    if (o < ncol) {
+                        const float x = pch[f];
+                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * ((pi0 + row) * a.tex_w + pj0) + o, x);
+                    }
+                }
+                wave_lds_sync();
+            }
+            // Otherwise: all lanes of a pixel share dL/dI, so the gradient of
             // texel j is dL/dI * sum of (shade * bilinear weight) over the
             // pixel's samples touching j.  Sum per texel within the pixel's
             // lanes; one lane per (pixel, texel) scatters.
@@ -733,16 +766,16 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack)
                 const int f = __shfl(face, leader);
                 const bool mine = face == f;
                 pending &= ~__ballot(mine);
-                float sum[18];
-                for (int k = 0; k < 18; ++k) sum[k] = wave_sum(mine ? gv[k] : 0.0f);
-                if (lane == leader) {
-                    float* slot = a.gface + ((size_t)hand * a.n_faces + f) * 18;
-                    for (int k = 0; k < 3; ++k)
-                        for (int q = 0; q < 3; ++q) {
-                            unsafeAtomicAdd(slot + 6 * k + q, sum[3 * k + q]);
-                            unsafeAtomicAdd(slot + 6 * k + 3 + q, sum[9 + 3 * k + q]);
-                        }
+                // slot entry l (corner l/6, position or normal part) from lane l:
+                // one instruction over 18 consecutive floats
+                float mine_val = 0.0f;
+                for (int k = 0; k < 18; ++k) {
+                    const float x = wave_sum(mine ? gv[k] : 0.0f);
+                    const int corner = k < 9 ? k / 3 : (k - 9) / 3;
+                    const int entry = 6 * corner + (k < 9 ? k % 3 : 3 + (k - 9) % 3);
+                    if (lane == entry) mine_val = x;
                 }
+                if (lane < 18) unsafeAtomicAdd(a.gface + ((size_t)hand * a.n_faces + f) * 18 + lane, mine_val);
             }
         }
     }
@@ -1030,11 +1063,12 @@ template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge)
 {
     __shared__ int stack[kMaxStack * kThreads];
+    __shared__ float patch[3 * kPatch * kPatch * (kThreads / 64)];
     if ((int)blockIdx.x < n_edge) {
         edge_samples<COUNT>(e, blockIdx.x, n_edge, stack);
         return;
     }
-    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, stack);
+    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, stack, patch);
 }
 
 // ===========================================================================
