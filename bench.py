@@ -28,7 +28,7 @@ import torch
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-from paper_2107_05509_amd import binding, scene  # noqa: E402
+from paper_2107_05509_amd import binding, refine, scene  # noqa: E402
 
 METRIC = "fwd+bwd diff-render Mrays/s + refine iters/s (8 views 334x512, 16 spp)"
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 128 lanes x 2 x 2.4 GHz)
@@ -50,60 +50,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def lr_schedule(it, warm=50):
-    """(root pose, pose, shape, global rotation, translation, albedo)."""
-    if it < warm:
-        return (0.0, 0.0, 0.0, 0.0, 0.0, 1e-2)
-    return (1e-2, 1e-2, 1e-2, 1e-2, 1e-3, 1e-2)
-
-
-class Refiner:
-    def __init__(self, w, dev="cuda:0", seed=0):
-        self.w = w
-        th, tw = w.albedo_true.shape[1:3]
-        self.g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=1000 + seed)
-        P = self.g.P
-        t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
-        self.bg = t(w.packed_background().astype(np.float32))
-        # targets: true parameters, 64 samples per pixel, an independent sample key
-        gt = binding.Scene(w.model, w.cams, w.n_hands, 64, th, tw, seed=7000 + seed)
-        vt = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
-        gt.skin(t(w.params_true.astype(np.float32)), vt)
-        gt.build_hierarchy(vt)
-        self.target = torch.empty(P, 3, device=dev)
-        hits = torch.empty(P, 64, device=dev, dtype=torch.int32)
-        gt.render(vt, t(w.albedo_true.astype(np.float32)), self.bg, 0, self.target, hits)
-        cover = (hits >= 0).any(1).float()
-        masks = []
-        off = w.pixel_offsets()
-        for i, c in enumerate(w.cams):
-            m = cover[off[i]:off[i + 1]].view(1, 1, c.H, c.W)
-            masks.append(torch.nn.functional.max_pool2d(m, 9, 1, 4).reshape(-1))
-        self.mask = (torch.cat(masks) > 0).to(torch.uint8).contiguous()
-        del hits, gt
-        self.params = t(w.params_init.astype(np.float32))
-        self.albedo = t(w.albedo_init.astype(np.float32))
-        self.mp, self.vp = torch.zeros_like(self.params), torch.zeros_like(self.params)
-        self.ma, self.va = torch.zeros_like(self.albedo), torch.zeros_like(self.albedo)
-        self.verts = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
-        # hierarchy topology around the initial pose (set-up, untimed)
-        self.g.skin(self.params, self.verts)
-        self.g.build_hierarchy(self.verts)
-        self.image = torch.empty(P, 3, device=dev)
-        self.dimage = torch.empty(P, 3, device=dev)
-        self.loss = torch.empty(w.n_hands, device=dev)
-        self.gp = torch.empty_like(self.params)
-        self.ga = torch.empty_like(self.albedo)
-
-    def step(self, it):
-        g = self.g
-        g.skin(self.params, self.verts)
-        g.render(self.verts, self.albedo, self.bg, it, self.image)
-        g.loss(self.image, self.target, self.mask, self.loss, self.dimage)
-        g.backward(self.params, self.verts, self.albedo, self.bg, self.dimage, it, self.gp, self.ga,
-                   flags=binding.HR_GRAD_ALL | binding.HR_REUSE_GEOMETRY)
-        g.step(self.params, self.albedo, self.gp, self.ga, self.mp, self.vp, self.ma, self.va, it + 1,
-               lr_schedule(it))
+def make_refiner(w, dev="cuda:0", seed=0, tune=True):
+    """Scene, synthetic targets (true parameters, 64 samples per pixel, an
+    independent sample key), coverage masks and the loop buffers; hierarchy
+    built at the initial pose; launch grids tuned.  Set-up, never timed."""
+    th, tw = w.albedo_true.shape[1:3]
+    g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=1000 + seed)
+    t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    bg = t(w.packed_background().astype(np.float32))
+    gt = binding.Scene(w.model, w.cams, w.n_hands, 64, th, tw, seed=7000 + seed)
+    vt = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
+    gt.skin(t(w.params_true.astype(np.float32)), vt)
+    gt.build_hierarchy(vt)
+    target = torch.empty(g.P, 3, device=dev)
+    hits = torch.empty(g.P, 64, device=dev, dtype=torch.int32)
+    gt.render(vt, t(w.albedo_true.astype(np.float32)), bg, 0, target, hits)
+    mask = refine.coverage_mask(hits, w.cams, w.pixel_offsets(), 9)
+    del hits, gt
+    r = refine.Refiner(g, t(w.params_init.astype(np.float32)), t(w.albedo_init.astype(np.float32)), bg, target,
+                       mask, warm=50, graph_chunk=10)
+    r.build_hierarchy()
+    if tune:
+        r.tune(reps=3)
+    return r
 
 
 def cpu_baseline(w, ref, views=1):
@@ -117,10 +86,10 @@ def cpu_baseline(w, ref, views=1):
     om = oracle.Model(w.model)
     P = int(tab["pix_off"][-1])
     p = torch.as_tensor(w.params_init.astype(np.float32).astype(np.float64))
-    bg = ref.bg[:P].cpu().numpy().astype(np.float64)
+    bg = ref.state.background[:P].cpu().numpy().astype(np.float64)
     alb = w.albedo_init.astype(np.float64)
-    target = ref.target[:P].cpu().numpy().astype(np.float64)
-    mask = ref.mask[:P].cpu().numpy()
+    target = ref.state.target[:P].cpu().numpy().astype(np.float64)
+    mask = ref.state.mask[:P].cpu().numpy()
     t0 = time.perf_counter()
     v, _ = oracle.skin(om, p)
     n = oracle.vertex_normals(v, om.faces)
@@ -137,12 +106,27 @@ def cpu_baseline(w, ref, views=1):
             "seconds": dt}
 
 
+def timed(fn):
+    """Milliseconds of the work fn enqueues, bracketed by synchronisations."""
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=150)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", choices=("graph", "eager"), default="graph",
+                    help="graph: replay captured iterations (hr_graph); eager: one hr_iterate per iteration")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2)
     args = ap.parse_args()
@@ -156,41 +140,43 @@ def main():
     torch.cuda.set_device(0)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
-    ref = Refiner(w, seed=args.seed)
-    it = 0
-    for _ in range(args.warmup):
-        ref.step(it)
-        it += 1
+    ref = make_refiner(w, seed=args.seed, tune=not args.no_tune)
+    g = ref.scene
+    print(f"[bench] launch grids (render, adjoint): {g.grids()}", file=sys.stderr, flush=True)
+    graph = args.mode == "graph"
+    ref.run(args.warmup, graph=graph)
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    ref.g.timing_enable(True)
-    ref.g.timing_read()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        ref.step(it)
-        it += 1
-    stop.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    kern = ref.g.timing_read()
-    ref.g.timing_enable(False)
+    if graph:
+        ref.prepare_graphs(args.steps)   # capture before the timed region
+    if not graph:
+        g.timing_enable(True)
+        g.timing_read()
+    total_ms = timed(lambda: ref.run(args.steps, graph=graph))
     ms = total_ms / args.steps
-    print(f"[bench] timed {args.steps} steps: {ms:.4f} ms/step, loss {ref.loss.item():.5f}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] timed {args.steps} steps ({args.mode}): {ms:.4f} ms/step, loss {ref.loss.item():.5f}",
+          file=sys.stderr, flush=True)
+    eager_ms = None
+    if graph:
+        # per-kernel durations: HIP events around every launch of the same
+        # number of iterations, enqueued one by one right after the timed region
+        g.timing_enable(True)
+        g.timing_read()
+        eager_ms = timed(lambda: ref.run(args.steps, graph=False)) / args.steps
+    kern = g.timing_read()
+    g.timing_enable(False)
     # work counts of one more iteration (untimed)
-    ref.g.set_counting(True)
-    ref.step(it)
-    counts = ref.g.read_counts()
-    ref.g.set_counting(False)
-    tot, bud = ref.g.edge_stats()
+    g.set_counting(True)
+    ref.step()
+    counts = g.read_counts()
+    g.set_counting(False)
+    tot, bud = g.edge_stats()
     torch.cuda.synchronize()
 
     cam_samples = sum(c.W * c.H for c in w.cams) * w.spp
     traced = sum(int(counts[k][0]) for k in counts)
-    per_kernel = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "ms_per_step": v[0] / args.steps}
+    n_it = args.steps
+    per_kernel = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "ms_per_step": v[0] / n_it}
                   for k, v in kern.items()}
     for k, v in sorted(per_kernel.items(), key=lambda kv: -kv[1]["ms_per_step"]):
         print(f"[bench]   {k:22s} {v['ms_per_launch'] * 1e3:9.1f} us/launch", file=sys.stderr)
@@ -213,6 +199,7 @@ def main():
             traffic = tj["kernels"][dom]
     roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "kernel": dom,
+            "kernel_us": round(per_kernel[dom]["ms_per_launch"] * 1e3, 2),
             "ops_per_launch": int(ops), "rays": int(rays), "node_visits": int(nodes), "tri_tests": int(tris),
             "hits": int(hits)}
     out = {
@@ -227,9 +214,12 @@ def main():
                                "512x512 albedo, L1 over hand masks, Adam on 64 params + albedo",
                    "views": len(w.cams), "W": 334, "H": 512, "spp": w.spp, "tex": 512,
                    "camera_samples_per_step": cam_samples},
+        "mode": args.mode,
+        "launch_grids": list(g.grids()),
         "refine_iters_per_s": round(1e3 / ms, 2),
         "traced_mrays_per_s": round(traced / (ms * 1e-3) / 1e6, 2),
         "edge_samples_per_step": int(bud.sum()),
+        "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernels": {k: round(v["ms_per_launch"] * 1e3, 2) for k, v in per_kernel.items()},
         "work_counts": {k: {"rays": int(v[0]), "node_visits": int(v[1]), "tri_tests": int(v[2]), "hits": int(v[3])}
                         for k, v in counts.items()},

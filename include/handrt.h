@@ -61,6 +61,7 @@ extern "C" {
                                    by the previous hr_render on this scene */
 
 typedef struct hr_scene hr_scene;
+typedef struct hr_graph hr_graph;
 
 /* Hand model and mesh topology, HOST pointers, copied by hr_scene_create.
    Sizes: V vertices, F triangles, J joints (parents[j] < j, parents[0] = -1),
@@ -99,6 +100,10 @@ typedef struct {
     float edge_delta;    /* side-ray offset of an edge sample, pixels (> 0) */
     int32_t tex_h, tex_w;/* colour map size (texels) */
     uint64_t seed;       /* Philox key of all sample streams */
+    uint32_t view_base;  /* sample-stream id of view 0; view v draws the streams
+                            of id view_base + v, so a scene holding views
+                            k..k+n-1 of a larger set (with view_base = k)
+                            reproduces their samples exactly */
 } hr_config;
 
 /* Adam hyper-parameters.  Learning rates per parameter group; 0 freezes a
@@ -177,6 +182,63 @@ int hr_backward(hr_scene* scene, const float* params, const float* verts, const 
 int hr_step(hr_scene* scene, float* params, float* albedo, const float* grad_params,
             const float* grad_albedo, float* m_params, float* v_params, float* m_albedo,
             float* v_albedo, int32_t t, const hr_adam_config* cfg, void* stream);
+
+/* Buffers of a refinement loop, all DEVICE pointers owned by the caller
+   (shapes as in the calls above; P = hr_num_pixels). */
+typedef struct {
+    float* params;            /* [n_hands,64] updated in place */
+    float* albedo;            /* [n_hands,tex_h,tex_w,3] updated in place */
+    float* m_params;          /* Adam moments, zero before the first step */
+    float* v_params;
+    float* m_albedo;
+    float* v_albedo;
+    const float* background;  /* [P,3] */
+    const float* target;      /* [P,3] observed images */
+    const uint8_t* mask;      /* [P] nullable = all pixels */
+    float* verts;             /* [n_hands,V,3] out: vertices of the iteration */
+    float* image;             /* [P,3] out: rendered images */
+    float* dimage;            /* [P,3] out: dE1/dimage */
+    float* loss;              /* [n_hands] out: E1 of the iteration (before its step) */
+    float* grad_params;       /* [n_hands,64] out */
+    float* grad_albedo;       /* [n_hands,tex_h,tex_w,3] out */
+    int32_t* iter;            /* [1] int32 iteration index, read when the work
+                                 runs and incremented by one at its end */
+} hr_state;
+
+/* One whole refinement iteration (Section 3.3): hr_skin, hr_render, hr_loss,
+   hr_backward (terms in `flags`, HR_GRAD_*) and hr_step, with the iteration
+   index i = *state->iter taken from device memory: samples of iteration i and
+   Adam step count t = i + 1.  Equivalent to the five calls with iter = i,
+   t = i + 1, followed by ++*state->iter.  Enqueues kernels only (no host
+   synchronisation, no allocation), so it can be captured into a graph. */
+int hr_iterate(hr_scene* scene, const hr_state* state, const hr_adam_config* cfg, uint32_t flags, void* stream);
+
+/* A HIP graph of n_iters (1..1024) consecutive hr_iterate calls on `state`'s
+   buffers (the pointers and cfg are fixed at creation; buffer contents are
+   read when the graph runs).  hr_graph_launch enqueues it on `stream`; each
+   launch advances *state->iter by n_iters.  The graph uses the scene's internal
+   buffers: launches must be ordered with every other call on the scene.
+   hr_graph_create captures on an internal stream and runs nothing. */
+int hr_graph_create(hr_graph** out, hr_scene* scene, const hr_state* state, const hr_adam_config* cfg,
+                    uint32_t flags, int32_t n_iters);
+int hr_graph_launch(hr_graph* graph, void* stream);
+void hr_graph_destroy(hr_graph* graph);
+
+/* Launch tuning.  The render and interior-adjoint launches are persistent
+   grids that walk the wave-tile list; their block counts change speed only:
+   images are identical for any choice (each pixel sums its samples in a fixed
+   order), gradients agree up to the order of floating-point atomic sums.
+   hr_set_grid sets them (0 keeps a value; values are capped at one block per
+   four wave tiles of the views), hr_get_grid reads them.  hr_tune times candidate grids on `state`'s
+   buffers (it runs skin, render, loss and the interior adjoint `reps` times
+   per candidate, overwriting verts, image, dimage, loss and the gradient
+   outputs, never params, albedo, moments or iter), keeps the fastest and
+   writes (render blocks, adjoint blocks) to blocks_host (HOST, nullable).
+   Synchronises `stream`; not for use under graph capture.  Graphs created
+   before a change keep the grids they were captured with. */
+int hr_set_grid(hr_scene* scene, int32_t render_blocks, int32_t adjoint_blocks);
+int hr_get_grid(const hr_scene* scene, int32_t* blocks_host);   /* (render, adjoint) */
+int hr_tune(hr_scene* scene, const hr_state* state, int32_t reps, int32_t* blocks_host, void* stream);
 
 /* Diagnostics of the last backward call on this scene, copied to HOST memory
    after synchronising `stream`: per view the total quantised silhouette

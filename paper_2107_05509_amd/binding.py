@@ -21,9 +21,10 @@ HR_GRAD_EDGES = 2
 HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
 
-EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_render", "hr_loss",
-           "hr_backward", "hr_step", "hr_edge_stats", "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable",
-           "hr_timing_read", "hr_last_error")
+EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
+           "hr_loss", "hr_backward", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
+           "hr_graph_destroy", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
+           "hr_timing_enable", "hr_timing_read", "hr_last_error")
 
 
 class HRError(RuntimeError):
@@ -48,13 +49,19 @@ class Camera(ctypes.Structure):
 class Config(ctypes.Structure):
     _fields_ = [("ka", ctypes.c_float), ("kd", ctypes.c_float), ("light", ctypes.c_float * 3),
                 ("spp", ctypes.c_int32), ("edge_delta", ctypes.c_float), ("tex_h", ctypes.c_int32),
-                ("tex_w", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("tex_w", ctypes.c_int32), ("seed", ctypes.c_uint64), ("view_base", ctypes.c_uint32)]
 
 
 class AdamConfig(ctypes.Structure):
     _fields_ = [("lr_pose_root", ctypes.c_float), ("lr_pose", ctypes.c_float), ("lr_shape", ctypes.c_float),
                 ("lr_rot", ctypes.c_float), ("lr_trans", ctypes.c_float), ("lr_albedo", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in (
+        "params", "albedo", "m_params", "v_params", "m_albedo", "v_albedo", "background", "target", "mask", "verts",
+        "image", "dimage", "loss", "grad_params", "grad_albedo", "iter")]
 
 
 _lib = None
@@ -80,6 +87,15 @@ def lib():
         L.hr_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
         L.hr_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(AdamConfig), vp]
+        L.hr_iterate.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(AdamConfig), u32, vp]
+        L.hr_graph_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(State), ctypes.POINTER(AdamConfig), u32,
+                                      i32]
+        L.hr_graph_launch.argtypes = [vp, vp]
+        L.hr_graph_destroy.argtypes = [vp]
+        L.hr_graph_destroy.restype = None
+        L.hr_set_grid.argtypes = [vp, i32, i32]
+        L.hr_get_grid.argtypes = [vp, vp]
+        L.hr_tune.argtypes = [vp, ctypes.POINTER(State), i32, vp, vp]
         L.hr_edge_stats.argtypes = [vp, vp, vp, vp]
         L.hr_build_hierarchy.argtypes = [vp, vp, vp]
         L.hr_set_counting.argtypes = [vp, i32]
@@ -87,8 +103,9 @@ def lib():
         L.hr_timing_enable.argtypes = [vp, i32]
         L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.hr_last_error.restype = ctypes.c_char_p
-        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step",
-                     "hr_edge_stats", "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read"):
+        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step", "hr_iterate",
+                     "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats",
+                     "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -121,7 +138,7 @@ def _stream():
 class Scene:
     """A handrt scene: hand model + cameras + estimator configuration."""
 
-    def __init__(self, model, cams, n_hands, spp, tex_h, tex_w, seed=0, shading=None, edge_delta=1e-3):
+    def __init__(self, model, cams, n_hands, spp, tex_h, tex_w, seed=0, shading=None, edge_delta=1e-3, view_base=0):
         from . import scene as _scene
         shading = _scene.SHADING if shading is None else shading
         self._keep = []
@@ -156,6 +173,7 @@ class Scene:
         cfg.light[:] = [float(x) for x in shading[2:5]]
         cfg.spp, cfg.edge_delta = int(spp), float(edge_delta)
         cfg.tex_h, cfg.tex_w, cfg.seed = int(tex_h), int(tex_w), int(seed)
+        cfg.view_base = int(view_base)
         h = ctypes.c_void_p()
         _check(lib().hr_scene_create(ctypes.byref(h), ctypes.byref(md), int(n_hands), cam_arr, len(cams),
                                      ctypes.byref(cfg)), "hr_scene_create")
@@ -211,15 +229,42 @@ class Scene:
 
     def step(self, params, albedo, grad_params, grad_albedo, m_p, v_p, m_a, v_a, t, lrs, betas=(0.9, 0.999),
              eps=1e-8):
-        c = AdamConfig()
-        (c.lr_pose_root, c.lr_pose, c.lr_shape, c.lr_rot, c.lr_trans, c.lr_albedo) = [float(x) for x in lrs]
-        c.beta1, c.beta2, c.eps = float(betas[0]), float(betas[1]), float(eps)
+        c = adam_config(lrs, betas, eps)
         shp_p, shp_a = (self.n_hands, 64), (self.n_hands, self.tex_h, self.tex_w, 3)
         _check(lib().hr_step(self._h, _ptr(params, shape=shp_p, name="params"),
                              _ptr(albedo, shape=shp_a, name="albedo"), _ptr(grad_params, shape=shp_p, name="gp"),
                              _ptr(grad_albedo, shape=shp_a, name="ga"), _ptr(m_p, shape=shp_p, name="m_p"),
                              _ptr(v_p, shape=shp_p, name="v_p"), _ptr(m_a, shape=shp_a, name="m_a"),
                              _ptr(v_a, shape=shp_a, name="v_a"), int(t), ctypes.byref(c), _stream()), "hr_step")
+
+    # -- whole iterations ----------------------------------------------------
+    def make_state(self, params, albedo, background, target, mask=None, iter0=0):
+        """Allocate the buffers of a refinement loop around the given tensors (which
+        it owns from now on: params/albedo are updated in place)."""
+        return LoopState(self, params, albedo, background, target, mask, iter0)
+
+    def iterate(self, state, lrs, flags=HR_GRAD_ALL, betas=(0.9, 0.999), eps=1e-8):
+        _check(lib().hr_iterate(self._h, ctypes.byref(state.c), ctypes.byref(adam_config(lrs, betas, eps)),
+                                int(flags), _stream()), "hr_iterate")
+
+    def graph(self, state, lrs, n_iters=1, flags=HR_GRAD_ALL, betas=(0.9, 0.999), eps=1e-8):
+        return Graph(self, state, adam_config(lrs, betas, eps), int(flags), int(n_iters))
+
+    def set_grid(self, render_blocks=0, adjoint_blocks=0):
+        _check(lib().hr_set_grid(self._h, int(render_blocks), int(adjoint_blocks)), "hr_set_grid")
+
+    def grids(self):
+        """(render blocks, adjoint blocks) of the persistent ray-tracing grids."""
+        out = np.zeros(2, dtype=np.int32)
+        _check(lib().hr_get_grid(self._h, out.ctypes.data_as(ctypes.c_void_p)), "hr_get_grid")
+        return int(out[0]), int(out[1])
+
+    def tune(self, state, reps=3):
+        """Time candidate persistent grids; returns (render blocks, adjoint blocks)."""
+        out = np.zeros(2, dtype=np.int32)
+        _check(lib().hr_tune(self._h, ctypes.byref(state.c), int(reps), out.ctypes.data_as(ctypes.c_void_p),
+                             _stream()), "hr_tune")
+        return int(out[0]), int(out[1])
 
     def edge_stats(self):
         tot = np.zeros(self.n_views, dtype=np.uint64)
@@ -258,3 +303,63 @@ class Scene:
             nm = raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
             out[nm] = (float(ms[i]), int(cnt[i]))
         return out
+
+
+def adam_config(lrs, betas=(0.9, 0.999), eps=1e-8):
+    """hr_adam_config from (root pose, pose, shape, rotation, translation, albedo) rates."""
+    c = AdamConfig()
+    (c.lr_pose_root, c.lr_pose, c.lr_shape, c.lr_rot, c.lr_trans, c.lr_albedo) = [float(x) for x in lrs]
+    c.beta1, c.beta2, c.eps = float(betas[0]), float(betas[1]), float(eps)
+    return c
+
+
+class LoopState:
+    """Device buffers of a refinement loop (hr_state)."""
+
+    def __init__(self, scene, params, albedo, background, target, mask=None, iter0=0):
+        dev = params.device
+        H, V, P = scene.n_hands, scene.V, scene.P
+        shp_a = (H, scene.tex_h, scene.tex_w, 3)
+        self.params, self.albedo = params, albedo
+        self.m_params, self.v_params = torch.zeros_like(params), torch.zeros_like(params)
+        self.m_albedo, self.v_albedo = torch.zeros_like(albedo), torch.zeros_like(albedo)
+        self.background, self.target, self.mask = background, target, mask
+        self.verts = torch.empty(H, V, 3, device=dev)
+        self.image = torch.empty(P, 3, device=dev)
+        self.dimage = torch.empty(P, 3, device=dev)
+        self.loss = torch.empty(H, device=dev)
+        self.grad_params = torch.empty_like(params)
+        self.grad_albedo = torch.empty_like(albedo)
+        self.iter = torch.full((1,), int(iter0), dtype=torch.int32, device=dev)
+        c = State()
+        c.params = _ptr(params, shape=(H, 64), name="params")
+        c.albedo = _ptr(albedo, shape=shp_a, name="albedo")
+        c.m_params, c.v_params = _ptr(self.m_params), _ptr(self.v_params)
+        c.m_albedo, c.v_albedo = _ptr(self.m_albedo), _ptr(self.v_albedo)
+        c.background = _ptr(background, shape=(P, 3), name="background")
+        c.target = _ptr(target, shape=(P, 3), name="target")
+        c.mask = _ptr(mask, torch.uint8, (P,), "mask")
+        c.verts, c.image, c.dimage, c.loss = _ptr(self.verts), _ptr(self.image), _ptr(self.dimage), _ptr(self.loss)
+        c.grad_params, c.grad_albedo = _ptr(self.grad_params), _ptr(self.grad_albedo)
+        c.iter = _ptr(self.iter, torch.int32, (1,), "iter")
+        self.c = c
+
+
+class Graph:
+    """n_iters captured iterations (hr_graph); launch() enqueues them."""
+
+    def __init__(self, scene, state, cfg, flags, n_iters):
+        self.scene, self.state, self.n_iters = scene, state, n_iters   # keep the buffers alive
+        h = ctypes.c_void_p()
+        _check(lib().hr_graph_create(ctypes.byref(h), scene._h, ctypes.byref(state.c), ctypes.byref(cfg), flags,
+                                     n_iters), "hr_graph_create")
+        self._h = h
+
+    def launch(self):
+        _check(lib().hr_graph_launch(self._h, _stream()), "hr_graph_launch")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.hr_graph_destroy(h)
+            self._h = None

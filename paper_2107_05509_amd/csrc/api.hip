@@ -70,7 +70,9 @@ struct hr_scene {
     int2* tiles = nullptr;        // wave tiles inside the per-view screen bounds
     long long tile_cap = 0;
     int* tile_count = nullptr;
-    int trace_blocks = 0;         // persistent grid of the ray-tracing kernels
+    int render_blocks = 0;        // persistent grids of the ray-tracing kernels (hr_tune)
+    int adjoint_blocks = 0;
+    int max_blocks = 0;           // one block per 4 wave tiles of the full views
     int2* chunks = nullptr;
     int n_chunks = 0;
     int* view_chunk_off = nullptr;
@@ -104,6 +106,12 @@ struct hr_scene {
         if (*dst) allocs.push_back((void*)*dst);
         return rc;
     }
+};
+
+struct hr_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int n_iters = 0;
 };
 
 // Copy one hand's hierarchy topology to the device (synchronous).
@@ -272,7 +280,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             memcpy(d.o, c.o, sizeof(d.o));
             d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
             d.W = c.W; d.H = c.H; d.hand = c.hand;
-            d.bx = 0;
+            d.sid = cfg->view_base + (uint32_t)v;
             d.pix0 = pix;
             s->tile_cap += (long long)((c.W + (1 << ts.tw_log2) - 1) >> ts.tw_log2) *
                            ((c.H + (1 << ts.th_log2) - 1) >> ts.th_log2);
@@ -284,7 +292,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         }
         s->n_pixels = pix;
         s->n_chunks = (int)chunks.size();
-        s->trace_blocks = (int)std::max<long long>(1, std::min<long long>(2048, (s->tile_cap + 3) / 4));
+        s->max_blocks = (int)std::max<long long>(1, std::min<long long>(kMaxTraceBlocks, (s->tile_cap + 3) / 4));
+        s->render_blocks = s->adjoint_blocks = std::min(2048, s->max_blocks);
         std::vector<int> hvo(n_hands + 1, 0), hv;
         for (int h = 0; h < n_hands; ++h) {
             for (int v = 0; v < n_views; ++v)
@@ -364,7 +373,7 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st)
 }
 
 static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
-                          const float* dimage, uint32_t iter);
+                          const float* dimage, uint32_t iter, const int* iter_dev);
 
 static Shading shading_of(const hr_config& c)
 {
@@ -374,11 +383,9 @@ static Shading shading_of(const hr_config& c)
     return S;
 }
 
-int hr_render(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
-              float* image, int32_t* hit_face, void* stream)
+static int render_impl(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
+                       const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st)
 {
-    if (!s || !verts || !albedo || !background || !image) return fail(HR_EINVAL, "hr_render: null argument");
-    hipStream_t st = (hipStream_t)stream;
     int rc = prepare(s, verts, st);
     if (rc) return rc;
     const long long P = s->n_pixels;
@@ -396,17 +403,24 @@ int hr_render(hr_scene* s, const float* verts, const float* albedo, const float*
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
-    a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
     // the silhouette tables of these vertices are built alongside
-    const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter);
-    const dim3 grid(s->n_views + s->trace_blocks);
+    const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
+    const dim3 grid(s->n_views + s->render_blocks);
     if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, s->n_views);
     return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, s->n_views);
 }
 
+int hr_render(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
+              float* image, int32_t* hit_face, void* stream)
+{
+    if (!s || !verts || !albedo || !background || !image) return fail(HR_EINVAL, "hr_render: null argument");
+    return render_impl(s, verts, albedo, background, iter, nullptr, image, hit_face, (hipStream_t)stream);
+}
+
 static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
-                          const float* dimage, uint32_t iter)
+                          const float* dimage, uint32_t iter, const int* iter_dev)
 {
     EdgeArgs a;
     a.m = s->mesh; a.views = s->views; a.verts = verts;
@@ -416,7 +430,8 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
     a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
     a.counts = s->counts + 8;
     a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
-    a.delta = s->cfg.edge_delta; a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    a.delta = s->cfg.edge_delta; a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed;
+    a.shading = shading_of(s->cfg);
     return a;
 }
 
@@ -477,11 +492,9 @@ int hr_timing_read(hr_scene* s, char* names, double* ms, int64_t* count, int32_t
     return HR_OK;
 }
 
-int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss, float* dimage,
-            void* stream)
+static int loss_impl(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss,
+                     float* dimage, hipStream_t st)
 {
-    if (!s || !image || !target || !loss || !dimage) return fail(HR_EINVAL, "hr_loss: null argument");
-    hipStream_t st = (hipStream_t)stream;
     LossArgs a;
     a.chunks = s->chunks; a.views = s->views; a.image = image; a.target = target; a.mask = mask;
     a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
@@ -494,6 +507,13 @@ int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t*
     return launch(s, "k_loss_grad", k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
 }
 
+int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss, float* dimage,
+            void* stream)
+{
+    if (!s || !image || !target || !loss || !dimage) return fail(HR_EINVAL, "hr_loss: null argument");
+    return loss_impl(s, image, target, mask, loss, dimage, (hipStream_t)stream);
+}
+
 static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
 {
     if (n <= 0) return HR_OK;
@@ -501,14 +521,11 @@ static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
     return launch(s, "k_fill", k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
 }
 
-int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
-                const float* dimage, uint32_t iter, uint32_t flags, float* grad_params, float* grad_albedo,
-                float* grad_verts, float* grad_normals, void* stream)
+static int backward_impl(hr_scene* s, const float* params, const float* verts, const float* albedo,
+                         const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
+                         uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
+                         float* grad_normals, hipStream_t st)
 {
-    if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
-        return fail(HR_EINVAL, "hr_backward: null argument");
-    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY)) return fail(HR_EINVAL, "hr_backward: unknown flags");
-    hipStream_t st = (hipStream_t)stream;
     int rc;
     if (!(flags & HR_REUSE_GEOMETRY)) {
         rc = prepare(s, verts, st);
@@ -519,7 +536,7 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
     if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
     if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
     if (rc) return rc;
-    const EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter);
+    const EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
     int n_edge = 0, n_adj = 0;
     if (flags & HR_GRAD_EDGES) {
         if (!(flags & HR_REUSE_GEOMETRY)) {
@@ -538,9 +555,9 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
     a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
-    a.iter = iter; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts + 4;
-    if (flags & HR_GRAD_INTERIOR) n_adj = s->trace_blocks;
+    if (flags & HR_GRAD_INTERIOR) n_adj = s->adjoint_blocks;
     if (n_edge + n_adj > 0) {
         const dim3 grid(n_edge + n_adj);
         if (s->counting)
@@ -554,14 +571,21 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
                   grad_normals);
 }
 
-int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
-            float* m_params, float* v_params, float* m_albedo, float* v_albedo, int32_t t, const hr_adam_config* cfg,
-            void* stream)
+int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
+                const float* dimage, uint32_t iter, uint32_t flags, float* grad_params, float* grad_albedo,
+                float* grad_verts, float* grad_normals, void* stream)
 {
-    if (!s || !params || !albedo || !grad_params || !grad_albedo || !m_params || !v_params || !m_albedo ||
-        !v_albedo || !cfg)
-        return fail(HR_EINVAL, "hr_step: null argument");
-    if (t < 1) return fail(HR_EINVAL, "hr_step: t must be >= 1");
+    if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
+        return fail(HR_EINVAL, "hr_backward: null argument");
+    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY)) return fail(HR_EINVAL, "hr_backward: unknown flags");
+    return backward_impl(s, params, verts, albedo, background, dimage, iter, nullptr, flags, grad_params, grad_albedo,
+                         grad_verts, grad_normals, (hipStream_t)stream);
+}
+
+static int step_impl(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
+                     float* m_params, float* v_params, float* m_albedo, float* v_albedo, int32_t t, const int* iter_dev,
+                     const hr_adam_config* cfg, hipStream_t st)
+{
     AdamArgs a;
     a.params = params; a.albedo = albedo; a.grad_params = grad_params; a.grad_albedo = grad_albedo;
     a.m_params = m_params; a.v_params = v_params; a.m_albedo = m_albedo; a.v_albedo = v_albedo;
@@ -572,8 +596,198 @@ int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params,
     a.beta1 = cfg->beta1; a.beta2 = cfg->beta2; a.eps = cfg->eps;
     a.bc1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)t));
     a.bc2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)t));
+    a.iter_dev = iter_dev;
     const long long n = 64ll * s->n_hands + a.n_albedo;
-    return launch(s, "k_adam", k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
+    return launch(s, "k_adam", k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+}
+
+int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
+            float* m_params, float* v_params, float* m_albedo, float* v_albedo, int32_t t, const hr_adam_config* cfg,
+            void* stream)
+{
+    if (!s || !params || !albedo || !grad_params || !grad_albedo || !m_params || !v_params || !m_albedo ||
+        !v_albedo || !cfg)
+        return fail(HR_EINVAL, "hr_step: null argument");
+    if (t < 1) return fail(HR_EINVAL, "hr_step: t must be >= 1");
+    return step_impl(s, params, albedo, grad_params, grad_albedo, m_params, v_params, m_albedo, v_albedo, t, nullptr,
+                     cfg, (hipStream_t)stream);
+}
+
+static int check_state(const hr_state* q, const char* who)
+{
+    if (!q) return fail(HR_EINVAL, "%s: null state", who);
+    if (!q->params || !q->albedo || !q->m_params || !q->v_params || !q->m_albedo || !q->v_albedo ||
+        !q->background || !q->target || !q->verts || !q->image || !q->dimage || !q->loss || !q->grad_params ||
+        !q->grad_albedo || !q->iter)
+        return fail(HR_EINVAL, "%s: null state buffer (only mask may be null)", who);
+    return HR_OK;
+}
+
+// One refinement iteration with the iteration index in device memory.
+static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cfg, uint32_t flags, hipStream_t st)
+{
+    const int* it = q->iter;
+    int rc = launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh,
+                    (const float*)q->params, q->verts, (float*)nullptr);
+    if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st);
+    if (!rc) rc = loss_impl(s, q->image, q->target, q->mask, q->loss, q->dimage, st);
+    if (!rc)
+        rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
+                           (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
+                           nullptr, st);
+    if (!rc)
+        rc = step_impl(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
+                       q->m_albedo, q->v_albedo, 1, it, cfg, st);
+    if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
+    return rc;
+}
+
+int hr_iterate(hr_scene* s, const hr_state* state, const hr_adam_config* cfg, uint32_t flags, void* stream)
+{
+    if (!s || !cfg) return fail(HR_EINVAL, "hr_iterate: null argument");
+    int rc = check_state(state, "hr_iterate");
+    if (rc) return rc;
+    if (flags & ~HR_GRAD_ALL) return fail(HR_EINVAL, "hr_iterate: unknown flags");
+    return iterate_impl(s, state, cfg, flags, (hipStream_t)stream);
+}
+
+int hr_graph_create(hr_graph** out, hr_scene* s, const hr_state* state, const hr_adam_config* cfg, uint32_t flags,
+                    int32_t n_iters)
+{
+    if (!out || !s || !cfg) return fail(HR_EINVAL, "hr_graph_create: null argument");
+    *out = nullptr;
+    int rc = check_state(state, "hr_graph_create");
+    if (rc) return rc;
+    if (flags & ~HR_GRAD_ALL) return fail(HR_EINVAL, "hr_graph_create: unknown flags");
+    if (n_iters < 1 || n_iters > 1024) return fail(HR_EINVAL, "hr_graph_create: n_iters must be 1..1024");
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_graph_create: %s", hipGetErrorString(e));
+    const bool timing = s->timing;
+    s->timing = false;    // no event nodes in the graph
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) rc = fail(HR_EHIP, "hr_graph_create: begin capture: %s", hipGetErrorString(e));
+    for (int i = 0; i < n_iters && !rc; ++i) rc = iterate_impl(s, state, cfg, flags, cs);
+    if (e == hipSuccess) {
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (!rc && e2 != hipSuccess) rc = fail(HR_EHIP, "hr_graph_create: end capture: %s", hipGetErrorString(e2));
+    }
+    s->timing = timing;
+    (void)hipStreamDestroy(cs);
+    hipGraphExec_t x = nullptr;
+    if (!rc) {
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(HR_EHIP, "hr_graph_create: instantiate: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    hr_graph* h = new hr_graph();
+    h->graph = g;
+    h->exec = x;
+    h->n_iters = n_iters;
+    *out = h;
+    return HR_OK;
+}
+
+int hr_graph_launch(hr_graph* g, void* stream)
+{
+    if (!g) return fail(HR_EINVAL, "hr_graph_launch: null graph");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_graph_launch: %s", hipGetErrorString(e));
+    return HR_OK;
+}
+
+void hr_graph_destroy(hr_graph* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+int hr_set_grid(hr_scene* s, int32_t render_blocks, int32_t adjoint_blocks)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_grid: null scene");
+    if (render_blocks < 0 || adjoint_blocks < 0) return fail(HR_EINVAL, "hr_set_grid: negative block count");
+    if (render_blocks) s->render_blocks = std::min(render_blocks, s->max_blocks);
+    if (adjoint_blocks) s->adjoint_blocks = std::min(adjoint_blocks, s->max_blocks);
+    return HR_OK;
+}
+
+int hr_get_grid(const hr_scene* s, int32_t* blocks_host)
+{
+    if (!s || !blocks_host) return fail(HR_EINVAL, "hr_get_grid: null argument");
+    blocks_host[0] = s->render_blocks;
+    blocks_host[1] = s->adjoint_blocks;
+    return HR_OK;
+}
+
+int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_host, void* stream)
+{
+    if (!s) return fail(HR_EINVAL, "hr_tune: null scene");
+    int rc = check_state(state, "hr_tune");
+    if (rc) return rc;
+    if (reps < 1 || reps > 100) return fail(HR_EINVAL, "hr_tune: reps must be 1..100");
+    hipStream_t st = (hipStream_t)stream;
+    const hr_state& q = *state;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(HR_EHIP, "hr_tune: hipEventCreate failed");
+    const bool timing = s->timing;
+    s->timing = false;
+    // the candidates' results are discarded; the iteration index stays on the host
+    auto run = [&](bool adjoint) -> int {
+        int r = launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh,
+                       (const float*)q.params, q.verts, (float*)nullptr);
+        if (!r) r = render_impl(s, q.verts, q.albedo, q.background, 0, nullptr, q.image, nullptr, st);
+        if (!r && adjoint) {
+            r = loss_impl(s, q.image, q.target, q.mask, q.loss, q.dimage, st);
+            if (!r)
+                r = backward_impl(s, q.params, q.verts, q.albedo, q.background, q.dimage, 0, nullptr,
+                                  HR_GRAD_INTERIOR | HR_REUSE_GEOMETRY, q.grad_params, q.grad_albedo, nullptr,
+                                  nullptr, st);
+        }
+        return r;
+    };
+    auto measure = [&](bool adjoint, float* ms) -> int {
+        int r = run(adjoint);   // warm
+        if (!r && hipEventRecord(e0, st) != hipSuccess) r = fail(HR_EHIP, "hr_tune: event");
+        for (int i = 0; i < reps && !r; ++i) r = run(adjoint);
+        if (!r && hipEventRecord(e1, st) != hipSuccess) r = fail(HR_EHIP, "hr_tune: event");
+        if (!r && hipEventSynchronize(e1) != hipSuccess) r = fail(HR_EHIP, "hr_tune: sync");
+        if (!r) (void)hipEventElapsedTime(ms, e0, e1);
+        return r;
+    };
+    static const int kCand[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096};
+    float best = 0.0f;
+    int best_r = s->render_blocks, best_a = s->adjoint_blocks;
+    for (int pass = 0; pass < 2 && !rc; ++pass) {
+        const bool adjoint = pass == 1;
+        best = 3.4e38f;
+        int last = -1;
+        for (int c : kCand) {
+            const int b = std::min(c, s->max_blocks);
+            if (b == last) continue;
+            last = b;
+            if (adjoint) s->adjoint_blocks = b; else s->render_blocks = b;
+            float ms = 0.0f;
+            rc = measure(adjoint, &ms);
+            if (rc) break;
+            if (ms < best) { best = ms; if (adjoint) best_a = b; else best_r = b; }
+        }
+        // the adjoint pass times render + adjoint with the chosen render grid
+        s->render_blocks = best_r;
+        s->adjoint_blocks = best_a;
+    }
+    s->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (blocks_host) { blocks_host[0] = s->render_blocks; blocks_host[1] = s->adjoint_blocks; }
+    return HR_OK;
 }
 
 int hr_edge_stats(hr_scene* s, uint64_t* total_host, int64_t* budget_host, void* stream)

@@ -16,6 +16,7 @@ constexpr int kMaxStack = 24;       // traversal stack entries per lane
 constexpr int kLeafMax = 4;         // triangles per leaf
 constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
 constexpr int kEdgeBlocks = 256;    // blocks of edge samples in the backward launch
+constexpr int kMaxTraceBlocks = 4096;   // largest persistent ray-tracing grid
 constexpr int kPatch = 16;          // texel patch (per wave) of the colour-map gradient
 
 // ---------------------------------------------------------------------------
@@ -26,7 +27,8 @@ struct ViewDev {            // one camera (see hr_camera)
     float R[9];
     float o[3];
     float fx, fy, cx, cy;
-    int W, H, hand, bx;     // bx = number of 16-pixel blocks across
+    int W, H, hand;
+    uint32_t sid;           // sample-stream id (Philox counter word of the view)
     long long pix0;         // first pixel in packed buffers
 };
 

@@ -57,6 +57,7 @@ struct RenderArgs {
     unsigned long long* counts;   // [4] rays traced, node visits, triangle tests, hits (counting variant)
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
+    const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`
     uint64_t seed;
     Shading shading;
 };
@@ -78,6 +79,7 @@ struct AdjointArgs {
     unsigned long long* counts;
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
+    const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`
     uint64_t seed;
     Shading shading;
 };
@@ -121,6 +123,7 @@ struct EdgeArgs {
     int n_nodes, tex_h, tex_w;
     float delta;
     uint32_t iter;
+    const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`
     uint64_t seed;
     Shading shading;
 };
@@ -135,6 +138,7 @@ struct AdamArgs {
     int n_hands;
     float lr[6];
     float beta1, beta2, eps, bc1, bc2;
+    const int* iter_dev;       // nullable: step count = *iter_dev + 1, bias corrections on the device
 };
 
 }  // namespace hr

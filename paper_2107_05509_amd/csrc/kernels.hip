@@ -402,6 +402,13 @@ __global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* _
 // render
 // ===========================================================================
 
+// iteration index of the sample streams: from device memory when the launch
+// belongs to a device-counted (graph-replayable) iteration
+__device__ __forceinline__ uint64_t iteration(const int* iter_dev, uint32_t iter)
+{
+    return iter_dev ? (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(*iter_dev) : (uint64_t)iter;
+}
+
 __device__ __forceinline__ uint64_t pick(const U64x4& r, int j)
 {
     return j == 0 ? r.x[0] : j == 1 ? r.x[1] : j == 2 ? r.x[2] : r.x[3];
@@ -421,6 +428,7 @@ __device__ __forceinline__ void tile_pixel(const TileShape& ts, int2 e, int lane
 template <bool COUNT>
 __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
 {
+    const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* stk = stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
@@ -443,13 +451,13 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
         const Tri* tris = a.tris + (size_t)c.hand * a.n_faces;
         const float* normals = a.normals + (size_t)c.hand * a.n_verts * 3;
         const float* tex = a.albedo + (size_t)c.hand * a.tex_h * a.tex_w * 3;
-        const uint64_t c2 = (uint64_t)(uint32_t)e.x | (kDomainCamera << 32);
+        const uint64_t c2 = (uint64_t)c.sid | (kDomainCamera << 32);
         float acc[3] = {0.0f, 0.0f, 0.0f};
         int misses = 0;
         for (int r = 0; r < a.ts.rounds; ++r) {
             const int s = s_lane + 64 * r;
             if (pix_ok && s < a.spp) {
-                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, (uint64_t)a.iter, a.seed, 0);
+                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
                 const uint64_t wd = pick(rr, s & 3);
                 const float u = u24_lo(wd), v = u24_hi(wd);
                 Ray ray;
@@ -588,6 +596,7 @@ __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
 template <bool COUNT>
 __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack, float* patch_base)
 {
+    const uint64_t iter = iteration(a.iter_dev, a.iter);
     float* patch = patch_base + 3 * kPatch * kPatch * (threadIdx.x >> 6);
     int* stk = stack + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -622,7 +631,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
         const float* normals = a.normals + (size_t)hand * a.n_verts * 3;
         const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
         float* gtex = a.grad_albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
-        const uint64_t c2 = (uint64_t)(uint32_t)e.x | (kDomainCamera << 32);
+        const uint64_t c2 = (uint64_t)c.sid | (kDomainCamera << 32);
         for (int r = 0; r < a.ts.rounds; ++r) {
             const int s = s_lane + 64 * r;
             // per-sample contributions to the triangle's three vertices:
@@ -635,7 +644,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             int tmask = 0;
             int fi0 = 0x7fffffff, fi1 = -1, fj0 = 0x7fffffff, fj1 = -1;   // footprint rows / columns
             if (live && s < a.spp) {
-                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, (uint64_t)a.iter, a.seed, 0);
+                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
                 const uint64_t wd = pick(rr, s & 3);
                 const float u = u24_lo(wd), v = u24_hi(wd);
                 Ray ray;
@@ -939,6 +948,7 @@ __global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict
 template <bool COUNT>
 __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
 {
+    const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* stk = stack + threadIdx.x;
     const long long total = a.prefix[a.n_views];
     const int side = threadIdx.x & 1;
@@ -965,7 +975,7 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
         const Tri* tris = a.tris + (size_t)hand * a.m.F;
         const float* normals = a.normals + (size_t)hand * a.m.V * 3;
         const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
-        const uint64_t c2 = (uint64_t)(uint32_t)vi | (kDomainEdge << 32);
+        const uint64_t c2 = (uint64_t)c.sid | (kDomainEdge << 32);
         // floor(k T / M) = k q + floor(k r / M) with q = T / M, r = T % M (k r < M^2 fits 64 bits)
         const unsigned long long um = (unsigned long long)M, q = T / um, rm = T % um;
         const unsigned long long uk = (unsigned long long)k;
@@ -973,7 +983,7 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
         const unsigned long long hi = (uk + 1) * q + ((uk + 1) * rm) / um;
         const unsigned long long width = hi - lo;
         if (width == 0) continue;   // same for both lanes of the pair
-        const U64x4 r = philox4x64(uk, 0, c2, (uint64_t)a.iter, a.seed, 0);
+        const U64x4 r = philox4x64(uk, 0, c2, iter, a.seed, 0);
         const unsigned long long target = lo + __umul64hi(r.x[0], width);
         int elo = 0, ehi = E - 1;   // first e with cdf[e] > target
         while (elo < ehi) {
@@ -1334,7 +1344,13 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
     const float v2 = a.beta2 * *v + (1.0f - a.beta2) * g * g;
     *m = m2;
     *v = v2;
-    const float mh = m2 / a.bc1, vh = v2 / a.bc2;
+    float bc1 = a.bc1, bc2 = a.bc2;
+    if (a.iter_dev) {
+        const double t = (double)(*a.iter_dev) + 1.0;
+        bc1 = (float)(1.0 - pow((double)a.beta1, t));
+        bc2 = (float)(1.0 - pow((double)a.beta2, t));
+    }
+    const float mh = m2 / bc1, vh = v2 / bc2;
     float x2 = *x - lr * mh / (sqrtf(vh) + a.eps);
     if (i >= np) x2 = fminf(fmaxf(x2, 0.0f), 1.0f);
     *x = x2;
@@ -1343,6 +1359,11 @@ __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 // ===========================================================================
 // utilities
 // ===========================================================================
+
+__global__ void k_advance(int* p)
+{
+    if (threadIdx.x == 0) *p += 1;
+}
 
 __global__ void k_set_i32(int* p, int n, int v)
 {

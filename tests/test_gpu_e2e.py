@@ -1,0 +1,85 @@
+"""End to end: ten refinement iterations (skin, render, L1 loss, interior and
+edge gradients, Adam with the root rotation frozen) on the tiny workload, run
+independently by the HIP path and by the oracle from the same float32 inputs
+(target images rendered by the oracle from the true parameters at 64 samples
+per pixel with an independent key).  The two trajectories must stay together
+(loss 1e-4 relative per iteration, parameters within a quarter of a
+learning rate after ten steps) and
+the loss must fall on both."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import DEV, f32
+from paper_2107_05509_amd import binding, scene
+
+pytestmark = pytest.mark.gpu
+
+LRS = (0.0, 1e-2, 1e-2, 1e-2, 1e-3, 1e-2)   # root pose frozen; all else free
+N_IT = 10
+SEED = 5
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def _param_lr(lrs):
+    lr = np.empty(64)
+    lr[0:3], lr[3:48], lr[48:58], lr[58:61], lr[61:64] = lrs[:5]
+    return lr
+
+
+def test_refinement_trajectory():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = scene.workload_tiny(0)
+    print("case: tiny workload, 10 iterations GPU vs oracle", flush=True)
+    tab = scene.camera_arrays(w.cams)
+    osc = oracle.Scene(w.model.faces, w.model.uv, tab, scene.SHADING, w.model.edges, w.model.edge_faces)
+    om = oracle.Model(w.model)
+    bg = f32(w.packed_background())
+    alb0 = f32(w.albedo_init)
+    p0 = f32(w.params_init)
+    vt, _ = oracle.skin(om, torch.as_tensor(f32(w.params_true).astype(np.float64)))
+    nt = oracle.vertex_normals(vt, om.faces)
+    target = f32(oracle.render(osc, vt.numpy(), nt.numpy(), f32(w.albedo_true), bg, 64, 777, 0))
+
+    # oracle trajectory (float64)
+    p = p0.astype(np.float64)[None] if p0.ndim == 1 else p0.astype(np.float64)
+    a = alb0.astype(np.float64)
+    mp, vp, ma, va = np.zeros_like(p), np.zeros_like(p), np.zeros_like(a), np.zeros_like(a)
+    lr_p = _param_lr(LRS)
+    o_loss, o_params = [], []
+    for it in range(N_IT):
+        r = oracle.gradient(om, osc, p, a, bg, target, None, w.spp, SEED, it)
+        o_loss.append(float(r["loss"][0]))
+        p, mp, vp = oracle.adam_step(p, r["grad_params"], mp, vp, it + 1, lr_p)
+        a, ma, va = oracle.adam_step(a, r["grad_albedo"], ma, va, it + 1, LRS[5], lo=0.0, hi=1.0)
+        o_params.append(p.copy())
+
+    # HIP trajectory (float32) through the C ABI
+    th, tw = w.albedo_true.shape[1:3]
+    g = binding.Scene(w.model, w.cams, 1, w.spp, th, tw, seed=SEED)
+    st = g.make_state(_t(p0), _t(alb0), _t(bg), _t(target))
+    g_loss, g_params = [], []
+    for it in range(N_IT):
+        g.iterate(st, LRS)
+        torch.cuda.synchronize()
+        g_loss.append(float(st.loss.item()))
+        g_params.append(st.params.cpu().numpy().astype(np.float64))
+
+    for it in range(N_IT):
+        dl = abs(g_loss[it] - o_loss[it]) / o_loss[it]
+        dp = np.abs(g_params[it] - o_params[it]).max()
+        print(f"iter {it}: loss gpu {g_loss[it]:.6f} oracle {o_loss[it]:.6f} rel {dl:.2e}; max |dparam| {dp:.2e}",
+              flush=True)
+        assert dl <= 1e-4, it
+    # a wrong gradient term moves parameters by about one learning rate (1e-2)
+    # per step; float32 against float64 rounding, amplified by Adam's
+    # normalisation of small gradient components, stays far below that
+    drift = np.abs(g_params[-1] - o_params[-1])
+    print("largest final drift at parameter %d: %.2e" % (int(drift.argmax()), drift.max()), flush=True)
+    assert drift.max() <= 2.5e-3
+    assert g_loss[-1] < g_loss[0] and o_loss[-1] < o_loss[0]

@@ -1,0 +1,174 @@
+"""The refinement loop entry points: hr_iterate and captured graphs against the
+separate calls, launch-grid invariance (the tuner's knob), sample-stream
+offsets (view_base) and the batched multi-hand scene against one scene per
+hand.  Images must agree bit for bit wherever the samples are the same;
+gradients and updated parameters within the atomic-order tolerance (1e-5
+relative per block for a few iterations, 1e-4 after ten)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, block_rel, f32
+from paper_2107_05509_amd import binding, refine, scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+class Loop:
+    """A tiny workload's loop buffers, fresh for each call."""
+
+    def __init__(self, w, seed=3, spp=None):
+        self.w = w
+        th, tw = w.albedo_true.shape[1:3]
+        self.g = binding.Scene(w.model, w.cams, w.n_hands, spp or w.spp, th, tw, seed=seed)
+        self.bg = _t(f32(w.packed_background()))
+        img = torch.empty(self.g.P, 3, device=DEV)
+        v = torch.empty(w.n_hands, w.model.n_verts, 3, device=DEV)
+        self.g.skin(_t(f32(w.params_true)), v)
+        self.g.render(v, _t(f32(w.albedo_true)), self.bg, 99, img)
+        self.target = img
+        rng = np.random.default_rng(0)
+        self.mask = _t((rng.uniform(size=self.g.P) < 0.9).astype(np.uint8), torch.uint8)
+
+    def refiner(self, warm=2):
+        return refine.Refiner(self.g, _t(f32(self.w.params_init)), _t(f32(self.w.albedo_init)), self.bg,
+                              self.target, self.mask, warm=warm, graph_chunk=3)
+
+
+@pytest.fixture(scope="module")
+def loop():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("case: tiny workload, loop entry points", flush=True)
+    return Loop(scene.workload_tiny(0))
+
+
+def _snap(r):
+    q = r.state
+    torch.cuda.synchronize()
+    return {k: getattr(q, k).detach().cpu().numpy().copy() for k in
+            ("params", "albedo", "loss", "image", "grad_params", "grad_albedo", "iter")}
+
+
+def test_iterate_matches_calls(loop):
+    a, b = loop.refiner(), loop.refiner()
+    for k in range(5):           # crosses the warm-up boundary (2)
+        a.step_eager()
+        b.step()
+        sa, sb = _snap(a), _snap(b)
+        assert int(sb["iter"][0]) == k + 1 == int(sa["iter"][0])
+        if k == 0:
+            assert np.array_equal(sa["image"], sb["image"])
+        for key in ("params", "albedo", "loss", "grad_params", "grad_albedo"):
+            assert block_rel(sb[key], sa[key]) <= 1e-5, (k, key, block_rel(sb[key], sa[key]))
+
+
+def test_graph_matches_iterate(loop):
+    a, b = loop.refiner(), loop.refiner()
+    a.run(7, graph=False)        # hr_iterate one by one
+    b.run(7, graph=True)         # graphs: warm-up chunk of 2, then chunks of 3, 2
+    sa, sb = _snap(a), _snap(b)
+    assert int(sb["iter"][0]) == 7
+    for key in ("params", "albedo", "loss", "grad_params"):
+        assert block_rel(sb[key], sa[key]) <= 1e-5, (key, block_rel(sb[key], sa[key]))
+    # replaying a captured graph again continues from the device counter
+    a.run(3, graph=False)
+    b.run(3, graph=True)
+    sa, sb = _snap(a), _snap(b)
+    assert int(sb["iter"][0]) == 10
+    # ten Adam steps amplify the last-bit differences of atomic sums
+    assert block_rel(sb["params"], sa["params"]) <= 1e-4
+
+
+def test_grid_does_not_change_images(loop):
+    g = loop.g
+    w = loop.w
+    v = torch.empty(1, w.model.n_verts, 3, device=DEV)
+    g.skin(_t(f32(w.params_init)), v)
+    alb = _t(f32(w.albedo_true))
+    d = _t(np.random.default_rng(2).normal(size=(g.P, 3)).astype(np.float32))
+    outs = []
+    for blocks in ((1, 1), (7, 5), (4096, 4096)):
+        g.set_grid(*blocks)
+        img = torch.empty(g.P, 3, device=DEV)
+        g.render(v, alb, loop.bg, 4, img)
+        gp = torch.empty(1, 64, device=DEV)
+        ga = torch.empty_like(alb)
+        g.backward(_t(f32(w.params_init)), v, alb, loop.bg, d, 4, gp, ga)
+        torch.cuda.synchronize()
+        outs.append((img.cpu().numpy(), gp.cpu().numpy(), ga.cpu().numpy()))
+    r = loop.refiner()
+    chosen = r.tune(reps=1)
+    print("tuned grids", chosen, flush=True)
+    assert all(c >= 1 for c in chosen)
+    for img, gp, ga in outs[1:]:
+        assert np.array_equal(img, outs[0][0])
+        assert block_rel(gp, outs[0][1]) <= 1e-5
+        assert block_rel(ga, outs[0][2]) <= 1e-5
+
+
+def test_view_base_reproduces_streams():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = scene.workload_tiny(1)
+    th, tw = w.albedo_true.shape[1:3]
+    full = binding.Scene(w.model, w.cams, 1, w.spp, th, tw, seed=11)
+    part = binding.Scene(w.model, w.cams[2:], 1, w.spp, th, tw, seed=11, view_base=2)
+    v = torch.empty(1, w.model.n_verts, 3, device=DEV)
+    full.skin(_t(f32(w.params_init)), v)
+    bg = _t(f32(w.packed_background()))
+    off = w.pixel_offsets()
+    a = torch.empty(full.P, 3, device=DEV)
+    b = torch.empty(part.P, 3, device=DEV)
+    full.render(v, _t(f32(w.albedo_true)), bg, 5, a)
+    part.render(v, _t(f32(w.albedo_true)), bg[off[2]:].contiguous(), 5, b)
+    torch.cuda.synchronize()
+    assert np.array_equal(a[off[2]:].cpu().numpy(), b.cpu().numpy())
+
+
+def test_batched_matches_per_hand():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = scene.workload_batched(0, n_hands=3, spp=4)
+    print("case: batched 3 hands,", len(w.cams), "views", flush=True)
+    th, tw = w.albedo_true.shape[1:3]
+    seed = 21
+    g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=seed)
+    off = w.pixel_offsets()
+    bg = _t(f32(w.packed_background()))
+    p = _t(f32(w.params_init))
+    alb = _t(f32(w.albedo_true))
+    v = torch.empty(w.n_hands, w.model.n_verts, 3, device=DEV)
+    g.skin(p, v)
+    img = torch.empty(g.P, 3, device=DEV)
+    g.render(v, alb, bg, 2, img)
+    d = _t(np.random.default_rng(4).normal(size=(g.P, 3)).astype(np.float32) * 1e-3)
+    gp = torch.empty_like(p)
+    ga = torch.empty_like(alb)
+    g.backward(p, v, alb, bg, d, 2, gp, ga)
+    torch.cuda.synchronize()
+    hands = np.array([c.hand for c in w.cams])
+    for h in range(w.n_hands):
+        idx = np.nonzero(hands == h)[0]
+        v0, v1 = int(idx[0]), int(idx[-1]) + 1
+        assert np.array_equal(idx, np.arange(v0, v1))
+        cams = [dataclasses.replace(c, hand=0) for c in w.cams[v0:v1]]
+        gh = binding.Scene(w.model, cams, 1, w.spp, th, tw, seed=seed, view_base=v0)
+        vh = v[h:h + 1].contiguous()
+        ih = torch.empty(gh.P, 3, device=DEV)
+        gh.skin(p[h:h + 1].contiguous(), vh)
+        gh.render(vh, alb[h:h + 1].contiguous(), bg[off[v0]:off[v1]].contiguous(), 2, ih)
+        gph = torch.empty(1, 64, device=DEV)
+        gah = torch.empty_like(alb[h:h + 1])
+        gh.backward(p[h:h + 1].contiguous(), vh, alb[h:h + 1].contiguous(), bg[off[v0]:off[v1]].contiguous(),
+                    d[off[v0]:off[v1]].contiguous(), 2, gph, gah)
+        torch.cuda.synchronize()
+        assert np.array_equal(ih.cpu().numpy(), img[off[v0]:off[v1]].cpu().numpy()), h
+        assert block_rel(gph.cpu().numpy(), gp[h:h + 1].cpu().numpy()) <= 1e-5, h
+        assert block_rel(gah.cpu().numpy(), ga[h:h + 1].cpu().numpy()) <= 1e-5, h
