@@ -50,10 +50,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def make_refiner(w, dev="cuda:0", seed=0, tune=True):
+def make_refiner(w, dev="cuda:0", seed=0, tune=True, cover_spp=64):
     """Scene, synthetic targets (true parameters, 64 samples per pixel, an
-    independent sample key), coverage masks and the loop buffers; hierarchy
-    built at the initial pose; launch grids tuned.  Set-up, never timed."""
+    independent sample key), coverage masks (samples of a cover_spp render of
+    the true pose) and the loop buffers; hierarchy built at the initial pose;
+    launch grids tuned.  Set-up, never timed."""
     th, tw = w.albedo_true.shape[1:3]
     g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=1000 + seed)
     t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
@@ -63,10 +64,20 @@ def make_refiner(w, dev="cuda:0", seed=0, tune=True):
     gt.skin(t(w.params_true.astype(np.float32)), vt)
     gt.build_hierarchy(vt)
     target = torch.empty(g.P, 3, device=dev)
-    hits = torch.empty(g.P, 64, device=dev, dtype=torch.int32)
-    gt.render(vt, t(w.albedo_true.astype(np.float32)), bg, 0, target, hits)
+    alb_true = t(w.albedo_true.astype(np.float32))
+    if cover_spp >= 64:
+        hits = torch.empty(g.P, 64, device=dev, dtype=torch.int32)
+        gt.render(vt, alb_true, bg, 0, target, hits)
+    else:
+        gt.render(vt, alb_true, bg, 0, target)
+        gc = binding.Scene(w.model, w.cams, w.n_hands, cover_spp, th, tw, seed=7500 + seed)
+        gc.skin(t(w.params_true.astype(np.float32)), vt)
+        gc.build_hierarchy(vt)
+        hits = torch.empty(g.P, cover_spp, device=dev, dtype=torch.int32)
+        gc.render(vt, alb_true, bg, 0, torch.empty_like(target), hits)
+        del gc
     mask = refine.coverage_mask(hits, w.cams, w.pixel_offsets(), 9)
-    del hits, gt
+    del hits, gt, alb_true
     r = refine.Refiner(g, t(w.params_init.astype(np.float32)), t(w.albedo_init.astype(np.float32)), bg, target,
                        mask, warm=50, graph_chunk=10)
     r.build_hierarchy()
@@ -118,6 +129,52 @@ def timed(fn):
     return start.elapsed_time(stop)
 
 
+def bench_batched(args):
+    """Many hands per launch: per-iteration latency percentiles of graph-replayed
+    iterations (one graph launch per iteration, events between launches)."""
+    w = scene.workload_batched(args.seed)
+    print(f"[bench] workload: {w.name}, {len(w.cams)} views, {w.n_pixels} pixels", file=sys.stderr, flush=True)
+    ref = make_refiner(w, seed=args.seed, tune=not args.no_tune, cover_spp=4)
+    ref.chunk = 1
+    g = ref.scene
+    warm, steps = min(args.warmup, 5), min(args.steps, 30)
+    ref.warm = 0                      # all variables from the first iteration
+    ref.run(warm)
+    ref.prepare_graphs(steps)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
+        ref.run(1)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    ms = float(lat.mean())
+    cam_samples = w.n_pixels * w.spp
+    g.set_counting(True)
+    ref.step()
+    counts = g.read_counts()
+    g.set_counting(False)
+    traced = sum(int(counts[k][0]) for k in counts)
+    out = {
+        "metric": "batched refine: camera samples/s and per-iteration latency (64 hands, 8 spp)",
+        "value": round(cam_samples / (ms * 1e-3) / 1e6, 2), "unit": "Mrays/s", "n_gpus": 1,
+        "steps": steps, "warmup": warm, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name + ": views U{4..40} per hand, 128x128/256x256/334x512, 256x256 albedo",
+                   "hands": w.n_hands, "views": len(w.cams), "pixels": int(w.n_pixels), "spp": w.spp,
+                   "camera_samples_per_step": int(cam_samples)},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3),
+                       "max": round(float(lat.max()), 3)},
+        "refine_iters_per_s": round(1e3 / ms, 3),
+        "hand_iters_per_s": round(w.n_hands * 1e3 / ms, 1),
+        "traced_mrays_per_s": round(traced / (ms * 1e-3) / 1e6, 2),
+        "launch_grids": list(g.grids()),
+        "loss_mean": round(float(ref.loss.mean().item()), 5),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,8 +184,13 @@ def main():
     ap.add_argument("--mode", choices=("graph", "eager"), default="graph",
                     help="graph: replay captured iterations (hr_graph); eager: one hr_iterate per iteration")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--grids", default=None,
+                    help="R,A: persistent render/adjoint grid sizes to use instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2)
+    ap.add_argument("--workload", choices=("realistic", "batched"), default="realistic",
+                    help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
+                         "(per-iteration latency percentiles; not the headline metric)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -138,10 +200,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batched":
+        return bench_batched(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
-    ref = make_refiner(w, seed=args.seed, tune=not args.no_tune)
+    ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))
     g = ref.scene
+    if args.grids:
+        g.set_grid(*[int(x) for x in args.grids.split(",")])
     print(f"[bench] launch grids (render, adjoint): {g.grids()}", file=sys.stderr, flush=True)
     graph = args.mode == "graph"
     ref.run(args.warmup, graph=graph)
