@@ -142,24 +142,29 @@ def backward_interior(sc: Scene, verts, normals, albedo, dimage, spp, seed, it):
     return ga, gv, gn
 
 
-def edge_weights(sc: Scene, verts):
+def edge_weights(sc: Scene, verts, want_rec=False):
     """Per (view, edge): quantised weights w (u32), inclusive prefix sums (u64),
-    per-view totals and sample budgets."""
+    per-view totals and sample budgets (and, with want_rec, the float32 edge
+    records [n_views,E,6]: projected endpoints and clipped interval)."""
     verts = _c(verts, np.float64).reshape(-1, sc.V, 3)
     E = sc.edges.shape[0]
     w = np.zeros((sc.n_views, E), dtype=np.uint32)
     cdf = np.zeros((sc.n_views, E), dtype=np.uint64)
     tot = np.zeros(sc.n_views, dtype=np.uint64)
     bud = np.zeros(sc.n_views, dtype=np.int64)
+    rec = np.zeros((sc.n_views, E, 6), dtype=np.float32) if want_rec else None
     lib().ora_edge_weights(ctypes.c_int(verts.shape[0]), ctypes.c_int(sc.V), ctypes.c_int(sc.F),
                            _p(verts), _p(sc.faces), ctypes.c_int(E), _p(sc.edges), _p(sc.edge_faces),
-                           *sc._cam_args(), _p(w), _p(cdf), _p(tot), _p(bud))
-    return w, cdf, tot, bud
+                           *sc._cam_args(), _p(w), _p(cdf), _p(tot), _p(bud), _p(rec) if want_rec else None)
+    return (w, cdf, tot, bud, rec) if want_rec else (w, cdf, tot, bud)
 
 
 def backward_edges(sc: Scene, verts, normals, albedo, background, dimage, seed, it,
-                   delta=1e-3, budget=None, want_stats=False):
-    """Boundary-term vertex gradient [H,V,3] (and per-edge |contribution| sums)."""
+                   delta=1e-3, budget=None, want_stats=False, wq=None, want_dc=False):
+    """Boundary-term vertex gradient [H,V,3]; with want_stats also the per-edge
+    |contribution| sums [n_views,E]; with want_dc the per-edge colour-jump sums
+    and counts [n_views,E,4].  wq [n_views,E] (u32, optional): sampling weights
+    replacing the length weights on silhouette edges."""
     verts = _c(verts, np.float64).reshape(-1, sc.V, 3)
     normals = _c(normals, np.float64).reshape(-1, sc.V, 3)
     albedo = _c(albedo, np.float64)
@@ -171,14 +176,18 @@ def backward_edges(sc: Scene, verts, normals, albedo, background, dimage, seed, 
     gv = np.zeros_like(verts)
     stats = np.zeros((sc.n_views, E)) if want_stats else None
     bud = None if budget is None else _c(np.broadcast_to(budget, (sc.n_views,)), np.int64)
+    wq = None if wq is None else _c(wq, np.uint32).reshape(sc.n_views, E)
+    dc = np.zeros((sc.n_views, E, 4)) if want_dc else None
     lib().ora_backward_edges(ctypes.c_int(verts.shape[0]), ctypes.c_int(sc.V), ctypes.c_int(sc.F),
                              _p(verts), _p(normals), _p(sc.faces), _p(sc.uv), ctypes.c_int(th),
                              ctypes.c_int(tw), _p(albedo), _p(background), ctypes.c_int(E),
                              _p(sc.edges), _p(sc.edge_faces), *sc._cam_args(), _p(sc.shading),
                              ctypes.c_float(delta), ctypes.c_uint64(seed), ctypes.c_uint32(it),
                              _p(dimage), _p(bud) if bud is not None else None, _p(gv),
-                             _p(stats) if want_stats else None)
-    return (gv, stats) if want_stats else gv
+                             _p(stats) if want_stats else None, _p(wq) if wq is not None else None,
+                             _p(dc) if want_dc else None)
+    out = [gv] + ([stats] if want_stats else []) + ([dc] if want_dc else [])
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def trace_rays32(org, dirs, v32, faces):

@@ -675,13 +675,15 @@ static void view_edges(const cam_t* c, const float* v32, const int32_t* faces, i
 /*
  * ora_edge_weights: per (view, edge) quantised weights and inclusive prefix sums.
  *   w [n_views,E] u32 out, cdf [n_views,E] u64 out, total [n_views] u64 out,
- *   budget [n_views] i64 out = ceil(total / 256)  (one sample per silhouette pixel).
+ *   budget [n_views] i64 out = ceil(total / 256)  (one sample per silhouette pixel),
+ *   rec [n_views,E,6] f32 out (nullable): projected endpoints ax, ay, bx, by and
+ *   the clipped parameter interval t0, t1 (zeros where w = 0).
  */
 void ora_edge_weights(int n_hands, int V, int F, const double* verts, const int32_t* faces, int E,
                       const int32_t* edges, const int32_t* edge_faces, int n_views, const float* R,
                       const float* o, const float* intr, const int32_t* wh, const int32_t* hand,
                       const int64_t* pix_off, uint32_t* w, uint64_t* cdf, uint64_t* total,
-                      int64_t* budget)
+                      int64_t* budget, float* rec)
 {
     float* v32 = round_verts(verts, n_hands * V);
     edge32_t* ed = (edge32_t*)malloc(sizeof(edge32_t) * (size_t)E);
@@ -693,6 +695,11 @@ void ora_edge_weights(int n_hands, int V, int F, const double* verts, const int3
             acc += ed[e].w;
             w[(size_t)vi * E + e] = ed[e].w;
             cdf[(size_t)vi * E + e] = acc;
+            if (rec) {
+                float* r = rec + ((size_t)vi * E + e) * 6;
+                r[0] = ed[e].ax; r[1] = ed[e].ay; r[2] = ed[e].bx; r[3] = ed[e].by;
+                r[4] = ed[e].t0; r[5] = ed[e].t1;
+            }
         }
         total[vi] = acc;
         budget[vi] = (int64_t)((acc + 255) / 256);
@@ -717,6 +724,12 @@ void ora_edge_weights(int n_hands, int V, int F, const double* verts, const int3
  *   budget_override [n_views] i64 (nullable): number of samples per view.
  *   edge_stats [n_views,E] f64 (nullable): accumulates |g.(c- - c+)| / (pdf M)
  *   per edge (an estimate of each edge's share of the boundary integral).
+ *   wq [n_views,E] u32 (nullable): sampling weights replacing the length
+ *   weights w_e on silhouette edges (w_e > 0; entries elsewhere are ignored;
+ *   each used entry must be >= 1).  The sample budget still follows the
+ *   length weights.  Any positive weights give an unbiased estimate.
+ *   dc_stats [n_views,E,4] f64 (nullable): accumulates, over the samples whose
+ *   pixel has a non-zero dimage, |c- - c+| per channel and the sample count.
  */
 void ora_backward_edges(int n_hands, int V, int F, const double* verts, const double* normals,
                         const int32_t* faces, const double* uv, int th, int tw, const double* albedo,
@@ -725,7 +738,7 @@ void ora_backward_edges(int n_hands, int V, int F, const double* verts, const do
                         const float* intr, const int32_t* wh, const int32_t* hand,
                         const int64_t* pix_off, const double* shading, float delta, uint64_t seed,
                         uint32_t iter, const double* dimage, const int64_t* budget_override,
-                        double* g_verts, double* edge_stats)
+                        double* g_verts, double* edge_stats, const uint32_t* wq, double* dc_stats)
 {
     mesh_t m = {V, F, faces, uv, th, tw, shading[0], shading[1], {shading[2], shading[3], shading[4]}};
     float* v32 = round_verts(verts, n_hands * V);
@@ -739,10 +752,15 @@ void ora_backward_edges(int n_hands, int V, int F, const double* verts, const do
         const double* tex = albedo + (size_t)3 * th * tw * c.hand;
         double* gv = g_verts + (size_t)3 * V * c.hand;
         view_edges(&c, hv32, faces, E, edges, edge_faces, ed);
+        uint64_t Tlen = 0;
+        for (int e = 0; e < E; ++e) Tlen += ed[e].w;
+        if (Tlen == 0) continue;
+        if (wq)   /* sampling weights: length weights replaced where sampled */
+            for (int e = 0; e < E; ++e)
+                if (ed[e].w > 0) ed[e].w = wq[(size_t)vi * E + e];
         uint64_t T = 0;
         for (int e = 0; e < E; ++e) { T += ed[e].w; cdf[e] = T; }
-        if (T == 0) continue;
-        int64_t Mv = (int64_t)((T + 255) / 256);
+        int64_t Mv = (int64_t)((Tlen + 255) / 256);
         if (budget_override) Mv = budget_override[vi];
         if (Mv <= 0) continue;
         for (int64_t k = 0; k < Mv; ++k) {
@@ -804,6 +822,11 @@ void ora_backward_edges(int n_hands, int V, int F, const double* verts, const do
             double jump = g[0] * (cm[0] - cp[0]) + g[1] * (cm[1] - cp[1]) + g[2] * (cm[2] - cp[2]);
             double s = jump * inv_pdf_m;
             if (edge_stats) edge_stats[(size_t)vi * E + e] += fabs(s);
+            if (dc_stats && (g[0] != 0.0 || g[1] != 0.0 || g[2] != 0.0)) {
+                double* d = dc_stats + ((size_t)vi * E + e) * 4;
+                for (int ch = 0; ch < 3; ++ch) d[ch] += fabs(cm[ch] - cp[ch]);
+                d[3] += 1.0;
+            }
             double td = (double)t;
             double dpa[2] = {(1.0 - td) * s * nx, (1.0 - td) * s * ny};
             double dpb[2] = {td * s * nx, td * s * ny};
