@@ -240,6 +240,78 @@ int hr_set_grid(hr_scene* scene, int32_t render_blocks, int32_t adjoint_blocks);
 int hr_get_grid(const hr_scene* scene, int32_t* blocks_host);   /* (render, adjoint) */
 int hr_tune(hr_scene* scene, const hr_state* state, int32_t reps, int32_t* blocks_host, void* stream);
 
+/* ---- learned edge-sampling proposal (project addition) -----------------
+   The silhouette term (Section 4.2.2) samples edges in proportion to their
+   clipped screen length.  With a learned proposal, a network
+   16 -> 64 -> 64 -> 1 (erf-GELU; bfloat16 operands on the matrix cores,
+   float32 accumulation) maps features of each (view, silhouette edge) to a
+   logit z_e, and the edge CDF uses the integer weights
+     W_e = max(1, floor(w_e (1 + (1 - eps)(E_e / Ebar - 1))))
+   with w_e the length weight, E_e = exp(z_e - max z), Ebar = sum w E / sum w:
+   equal logits keep the length weights exactly, and every edge keeps at
+   least eps of its length-proportional share.  The sample budget per view is
+   unchanged and each sample is divided by its own probability, so the
+   estimate stays unbiased for any network.  hr_backward draws with these
+   weights and records, per (view, edge), the sum of |sample contribution| and
+   of |c- - c+| per channel; hr_proposal_train (also run by hr_iterate) takes
+   one Adam step on KL(target || q), target = the recorded |contribution|
+   sums normalised per view, q_e = w_e exp(z_e) / sum_f w_f exp(z_f), updates
+   the per-edge colour-jump averages (features 7-9) and clears the records.
+
+   Features of a row (view v, edge e), in order: the clipped projected
+   endpoints over (W, H) (4), the clipped length over the image diagonal, the
+   larger and the smaller of n_f . vhat over the edge's faces (unit face
+   normals; vhat the unit direction from the edge midpoint to the camera; 0
+   for a missing face), the colour jump across the edge (3: the running
+   average of measured |c- - c+|, or before any measurement |shade -
+   background| at the edge midpoint), 6 zeros.
+
+   Parameter vector (HR_MLP_PARAMS float32): W1 [16][64] (input-major), b1 [64],
+   W2 [64][64], b2 [64], w3 [64], b3. */
+#define HR_PROPOSAL_LENGTH 0
+#define HR_PROPOSAL_LEARNED 1
+#define HR_MLP_PARAMS 5313
+
+typedef struct {
+    int32_t kind;        /* HR_PROPOSAL_* */
+    float eps;           /* floor share of the length-proportional weights, (0,1] */
+    float ema;           /* decay of the colour-jump averages, [0,1) */
+    float lr;            /* Adam learning rate of the network (0 = no training) */
+    float beta1, beta2, adam_eps;
+} hr_proposal_config;
+
+/* Select the proposal.  Allocates the proposal's device state on the first
+   call (HR_EUNSUPPORTED above 8192 edges); resets the optimiser, the records
+   and the colour-jump averages; theta_host (HOST, HR_MLP_PARAMS, nullable =
+   keep the current parameters, zero at first) sets the network.  Synchronises
+   the device. */
+int hr_proposal_set(hr_scene* scene, const hr_proposal_config* cfg, const float* theta_host);
+/* Current network parameters to HOST memory (synchronises `stream`). */
+int hr_proposal_get(hr_scene* scene, float* theta_host, void* stream);
+/* Use the given logits z [n_views,E] (DEVICE, nullable = the network's)
+   instead of the network's; training is skipped while set. */
+int hr_proposal_override(hr_scene* scene, const float* z);
+/* One training step on the records of the backward passes since the last
+   call (see above). */
+int hr_proposal_train(hr_scene* scene, void* stream);
+/* Inputs the last backward pass gave the network, DEVICE [n_views,E,16]
+   float32 (the bfloat16 values; zero rows for edges that were not sampled). */
+int hr_proposal_features(hr_scene* scene, float* feats, void* stream);
+/* Records of the last proposal pass, DEVICE outputs (each nullable):
+   z [n_views,E] logits, wq [n_views,E] u32 sampling weights (= length weights
+   under HR_PROPOSAL_LENGTH), a [n_views,E] sums of |sample contribution|,
+   dc [n_views,E,4] sums of |c- - c+| per channel and sample counts. */
+int hr_proposal_stats(hr_scene* scene, float* z, uint32_t* wq, float* a, float* dc, void* stream);
+/* The network on caller rows: X [n,16] (DEVICE float32, rounded to bfloat16
+   on input) -> z [n] (DEVICE). */
+int hr_proposal_eval(hr_scene* scene, const float* X, int32_t n, float* z, void* stream);
+/* Gradient of KL(a / sum a || q) over caller rows taken as one view: X [n,16],
+   w [n] u32 length weights (0 = not a silhouette edge), a [n] float target
+   weights, 1 <= n <= 16384 (all DEVICE); grad [HR_MLP_PARAMS] DEVICE out
+   (nullable); apply != 0 also takes the Adam step with it. */
+int hr_proposal_fit(hr_scene* scene, const float* X, const uint32_t* w, const float* a, int32_t n, float* grad,
+                    int32_t apply, void* stream);
+
 /* Diagnostics of the last backward call on this scene, copied to HOST memory
    after synchronising `stream`: per view the total quantised silhouette
    length (uint64, 1/256 px) and the number of edge samples drawn.

@@ -135,7 +135,10 @@ def kl_grad(theta, X, w, a, group, rounded=True):
     return flatten(g)
 
 
-def proposal_weights(w, z, eps=1e-3):
+EPS = float(np.float32(1e-3))   # the float32 value the device uses
+
+
+def proposal_weights(w, z, eps=EPS):
     """Integer sampling weights of one view from the length weights w (u32) and
     logits z: with E_e = exp(z_e - max z) and the length-weighted mean
     Ebar = sum w E / sum w, W_e = max(1, floor(w_e (1 + (1 - eps)(E_e / Ebar - 1))))

@@ -24,7 +24,14 @@ HR_REUSE_GEOMETRY = 4
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
            "hr_loss", "hr_backward", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
            "hr_graph_destroy", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
-           "hr_timing_enable", "hr_timing_read", "hr_last_error")
+           "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
+           "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
+           "hr_last_error")
+
+HR_PROPOSAL_LENGTH = 0
+HR_PROPOSAL_LEARNED = 1
+HR_MLP_PARAMS = 5313
+MLP_LAYOUT = (("W1", (16, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("w3", (64,)), ("b3", (1,)))
 
 
 class HRError(RuntimeError):
@@ -56,6 +63,11 @@ class AdamConfig(ctypes.Structure):
     _fields_ = [("lr_pose_root", ctypes.c_float), ("lr_pose", ctypes.c_float), ("lr_shape", ctypes.c_float),
                 ("lr_rot", ctypes.c_float), ("lr_trans", ctypes.c_float), ("lr_albedo", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class ProposalConfig(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("eps", ctypes.c_float), ("ema", ctypes.c_float), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
 
 
 class State(ctypes.Structure):
@@ -96,6 +108,14 @@ def lib():
         L.hr_set_grid.argtypes = [vp, i32, i32]
         L.hr_get_grid.argtypes = [vp, vp]
         L.hr_tune.argtypes = [vp, ctypes.POINTER(State), i32, vp, vp]
+        L.hr_proposal_set.argtypes = [vp, ctypes.POINTER(ProposalConfig), vp]
+        L.hr_proposal_get.argtypes = [vp, vp, vp]
+        L.hr_proposal_override.argtypes = [vp, vp]
+        L.hr_proposal_train.argtypes = [vp, vp]
+        L.hr_proposal_features.argtypes = [vp, vp, vp]
+        L.hr_proposal_stats.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.hr_proposal_eval.argtypes = [vp, vp, i32, vp, vp]
+        L.hr_proposal_fit.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp]
         L.hr_edge_stats.argtypes = [vp, vp, vp, vp]
         L.hr_build_hierarchy.argtypes = [vp, vp, vp]
         L.hr_set_counting.argtypes = [vp, i32]
@@ -105,7 +125,9 @@ def lib():
         L.hr_last_error.restype = ctypes.c_char_p
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step", "hr_iterate",
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats",
-                     "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read"):
+                     "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
+                     "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
+                     "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -183,6 +205,7 @@ class Scene:
         self.V, self.F, self.J = model.n_verts, model.n_faces, model.j_regressor.shape[0]
         self.spp, self.tex_h, self.tex_w = int(spp), int(tex_h), int(tex_w)
         self.P = int(lib().hr_num_pixels(h))
+        self._n_edges = int(model.n_edges)
         self.pix_off = tables["pix_off"]
 
     def __del__(self):
@@ -265,6 +288,70 @@ class Scene:
         _check(lib().hr_tune(self._h, ctypes.byref(state.c), int(reps), out.ctypes.data_as(ctypes.c_void_p),
                              _stream()), "hr_tune")
         return int(out[0]), int(out[1])
+
+    # -- learned edge-sampling proposal ----------------------------------------
+    def proposal_set(self, kind=HR_PROPOSAL_LEARNED, theta=None, eps=1e-3, ema=0.9, lr=1e-3, betas=(0.9, 0.999),
+                     adam_eps=1e-8):
+        """Select the edge proposal; theta: flat [HR_MLP_PARAMS] or a dict of the
+        MLP_LAYOUT arrays (None keeps the current network)."""
+        c = ProposalConfig()
+        c.kind, c.eps, c.ema, c.lr = int(kind), float(eps), float(ema), float(lr)
+        c.beta1, c.beta2, c.adam_eps = float(betas[0]), float(betas[1]), float(adam_eps)
+        buf = None
+        if theta is not None:
+            buf = np.ascontiguousarray(flat_mlp(theta), dtype=np.float32)
+        _check(lib().hr_proposal_set(self._h, ctypes.byref(c),
+                                     buf.ctypes.data_as(ctypes.c_void_p) if buf is not None else None),
+               "hr_proposal_set")
+        self._z_override = None
+
+    def proposal_get(self):
+        out = np.zeros(HR_MLP_PARAMS, dtype=np.float32)
+        _check(lib().hr_proposal_get(self._h, out.ctypes.data_as(ctypes.c_void_p), _stream()), "hr_proposal_get")
+        return out
+
+    def proposal_override(self, z=None):
+        """Logits [n_views,E] (CUDA float32) to use instead of the network, or None."""
+        E = self._n_edges
+        _check(lib().hr_proposal_override(self._h, _ptr(z, shape=(self.n_views, E), name="z")),
+               "hr_proposal_override")
+        self._z_override = z   # keep alive
+
+    def proposal_train(self):
+        _check(lib().hr_proposal_train(self._h, _stream()), "hr_proposal_train")
+
+    def proposal_features(self):
+        out = torch.empty(self.n_views, self._n_edges, 16, device=torch.cuda.current_device())
+        _check(lib().hr_proposal_features(self._h, _ptr(out), _stream()), "hr_proposal_features")
+        return out
+
+    def proposal_stats(self):
+        """(z, wq, a, dc) of the last proposal pass / backward records."""
+        dev = torch.cuda.current_device()
+        shp = (self.n_views, self._n_edges)
+        z = torch.empty(shp, device=dev)
+        wq = torch.empty(shp, device=dev, dtype=torch.int32)
+        a = torch.empty(shp, device=dev)
+        dc = torch.empty(*shp, 4, device=dev)
+        _check(lib().hr_proposal_stats(self._h, _ptr(z), _ptr(wq, torch.int32), _ptr(a), _ptr(dc), _stream()),
+               "hr_proposal_stats")
+        return z, wq, a, dc
+
+    def proposal_eval(self, X):
+        X = X.contiguous()
+        z = torch.empty(X.shape[0], device=X.device)
+        _check(lib().hr_proposal_eval(self._h, _ptr(X, shape=(X.shape[0], 16), name="X"), int(X.shape[0]), _ptr(z),
+                                      _stream()), "hr_proposal_eval")
+        return z
+
+    def proposal_fit(self, X, w, a, apply=False):
+        n = int(X.shape[0])
+        grad = torch.empty(HR_MLP_PARAMS, device=X.device)
+        _check(lib().hr_proposal_fit(self._h, _ptr(X.contiguous(), shape=(n, 16), name="X"),
+                                     _ptr(w.contiguous(), torch.int32, (n,), "w"),
+                                     _ptr(a.contiguous(), shape=(n,), name="a"), n, _ptr(grad), int(bool(apply)),
+                                     _stream()), "hr_proposal_fit")
+        return grad
 
     def edge_stats(self):
         tot = np.zeros(self.n_views, dtype=np.uint64)
@@ -363,3 +450,13 @@ class Graph:
         if h is not None and h.value and _lib is not None:
             _lib.hr_graph_destroy(h)
             self._h = None
+
+
+def flat_mlp(theta):
+    """Flat float32 [HR_MLP_PARAMS] from a dict of the MLP_LAYOUT arrays (or a flat array)."""
+    if isinstance(theta, dict):
+        return np.concatenate([np.asarray(theta[k], np.float32).reshape(-1) for k, _ in MLP_LAYOUT])
+    a = np.asarray(theta, np.float32).reshape(-1)
+    if a.size != HR_MLP_PARAMS:
+        raise HRError(f"expected {HR_MLP_PARAMS} network parameters, got {a.size}")
+    return a

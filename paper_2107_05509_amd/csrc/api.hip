@@ -12,6 +12,7 @@
 
 #include "../../include/handrt.h"
 #include "kernels.hip"
+#include "proposal.hip"
 #include "bvh_build.h"
 
 using namespace hr;
@@ -92,6 +93,11 @@ struct hr_scene {
     long long* edge_prefix = nullptr;
     size_t smem_prepare = 0, smem_skin = 0, smem_geom_bwd = 0;
     unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
+    // learned edge-sampling proposal (hr_proposal_*)
+    bool prop_alloc = false;
+    int prop_kind = HR_PROPOSAL_LENGTH;
+    PropDev prop{};
+    float* fit_z = nullptr;
     bool counting = false;
     // per-kernel timing (profiling aid)
     bool timing = false;
@@ -428,6 +434,7 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
     a.prefix = s->edge_prefix; a.n_views = s->n_views;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
+    a.stat_a = nullptr; a.stat_dc = nullptr;
     a.counts = s->counts + 8;
     a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
     a.delta = s->cfg.edge_delta; a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed;
@@ -536,12 +543,20 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
     if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
     if (rc) return rc;
-    const EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
+    EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
     int n_edge = 0, n_adj = 0;
     if (flags & HR_GRAD_EDGES) {
         if (!(flags & HR_REUSE_GEOMETRY)) {
             rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kThreads), 0, st, e);
             if (rc) return rc;
+        }
+        if (s->prop_kind == HR_PROPOSAL_LEARNED) {
+            // learned sampling weights replace the length weights of the CDF;
+            // the samples report per-edge statistics for training
+            rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views), dim3(256), 0, st, e, s->prop);
+            if (rc) return rc;
+            e.stat_a = s->prop.stat_a;
+            e.stat_dc = s->prop.stat_dc;
         }
         rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
                     s->n_views, s->edge_prefix);
@@ -623,6 +638,17 @@ static int check_state(const hr_state* q, const char* who)
     return HR_OK;
 }
 
+// Training step of the learned proposal on the statistics of the last
+// backward pass (no-op unless the proposal is learned and trainable).
+static int proposal_train_impl(hr_scene* s, hipStream_t st)
+{
+    if (s->prop_kind != HR_PROPOSAL_LEARNED || s->prop.z_override || !(s->prop.lr > 0.0f)) return HR_OK;
+    EdgeArgs e = edge_args(s, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
+    int rc = launch(s, "k_proposal_train", k_proposal_train, dim3(s->n_views), dim3(256), 0, st, e, s->prop);
+    if (!rc) rc = launch(s, "k_proposal_adam", k_proposal_adam, dim3(1), dim3(256), 0, st, s->prop);
+    return rc;
+}
+
 // One refinement iteration with the iteration index in device memory.
 static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cfg, uint32_t flags, hipStream_t st)
 {
@@ -635,6 +661,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
                            nullptr, st);
+    if (!rc && (flags & HR_GRAD_EDGES)) rc = proposal_train_impl(s, st);
     if (!rc)
         rc = step_impl(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
                        q->m_albedo, q->v_albedo, 1, it, cfg, st);
@@ -788,6 +815,160 @@ int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_ho
     if (rc) return rc;
     if (blocks_host) { blocks_host[0] = s->render_blocks; blocks_host[1] = s->adjoint_blocks; }
     return HR_OK;
+}
+
+int hr_proposal_set(hr_scene* s, const hr_proposal_config* cfg, const float* theta_host)
+{
+    if (!s || !cfg) return fail(HR_EINVAL, "hr_proposal_set: null argument");
+    if (cfg->kind != HR_PROPOSAL_LENGTH && cfg->kind != HR_PROPOSAL_LEARNED)
+        return fail(HR_EINVAL, "hr_proposal_set: unknown kind");
+    if (!(cfg->eps > 0.0f && cfg->eps <= 1.0f)) return fail(HR_EINVAL, "hr_proposal_set: eps must be in (0,1]");
+    if (!(cfg->ema >= 0.0f && cfg->ema < 1.0f)) return fail(HR_EINVAL, "hr_proposal_set: ema must be in [0,1)");
+    if (!(cfg->lr >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) || !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) ||
+        !(cfg->adam_eps > 0.0f))
+        return fail(HR_EINVAL, "hr_proposal_set: bad optimiser settings");
+    if (cfg->kind == HR_PROPOSAL_LEARNED && s->E > kPropMaxEdges)
+        return fail(HR_EUNSUPPORTED, "hr_proposal_set: more than %d edges", kPropMaxEdges);
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
+    PropDev& P = s->prop;
+    const size_t nve = (size_t)s->n_views * s->E;
+    if (!s->prop_alloc) {
+        int rc = HR_OK;
+        if (!rc) rc = s->upload<float>(&P.theta, nullptr, kMlpParams);
+        if (!rc) rc = s->upload<float>(&P.m, nullptr, kMlpParams);
+        if (!rc) rc = s->upload<float>(&P.v, nullptr, kMlpParams);
+        if (!rc) rc = s->upload<float>(&P.grad, nullptr, kMlpParams);
+        if (!rc) rc = s->upload<int>(&P.step, nullptr, 1);
+        if (!rc) rc = s->upload<s4v>(&P.w1p, nullptr, 4 * 64);
+        if (!rc) rc = s->upload<s4v>(&P.w2p, nullptr, 16 * 64);
+        if (!rc) rc = s->upload<s4v>(&P.w2bp, nullptr, 16 * 64);
+        if (!rc) rc = s->upload<float>(&P.fb, nullptr, kFbSize);
+        if (!rc) rc = s->upload<float>(&P.z, nullptr, nve);
+        if (!rc) rc = s->upload<s4v>(&P.feat, nullptr, nve * 4);
+        if (!rc) rc = s->upload<float>(&P.stat_a, nullptr, nve);
+        if (!rc) rc = s->upload<float>(&P.stat_dc, nullptr, nve * 4);
+        if (!rc) rc = s->upload<float>(&P.ema, nullptr, nve * 4);
+        if (!rc) rc = s->upload<float>(&s->fit_z, nullptr, kFitMaxRows);
+        if (rc) return rc;
+        s->prop_alloc = true;
+        e = hipMemset(P.theta, 0, sizeof(float) * kMlpParams);
+        if (e == hipSuccess) e = hipMemset(P.feat, 0, sizeof(s4v) * nve * 4);
+        if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
+    }
+    if (theta_host) {
+        e = hipMemcpy(P.theta, theta_host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
+    }
+    // fresh optimiser state, statistics and colour-jump averages
+    e = hipMemset(P.m, 0, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMemset(P.v, 0, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMemset(P.grad, 0, sizeof(float) * kMlpParams);
+    if (e == hipSuccess) e = hipMemset(P.step, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(P.z, 0, sizeof(float) * nve);
+    if (e == hipSuccess) e = hipMemset(P.stat_a, 0, sizeof(float) * nve);
+    if (e == hipSuccess) e = hipMemset(P.stat_dc, 0, sizeof(float) * nve * 4);
+    if (e == hipSuccess) e = hipMemset(P.ema, 0, sizeof(float) * nve * 4);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
+    P.eps = cfg->eps; P.ema_beta = cfg->ema; P.lr = cfg->lr;
+    P.beta1 = cfg->beta1; P.beta2 = cfg->beta2; P.adam_eps = cfg->adam_eps;
+    s->prop_kind = cfg->kind;
+    hipLaunchKernelGGL(k_proposal_pack, dim3(1), dim3(256), 0, (hipStream_t)0, P);
+    int rc = check_launch("hr_proposal_set");
+    if (rc) return rc;
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
+    return HR_OK;
+}
+
+static int need_prop(const hr_scene* s, const char* who)
+{
+    if (!s) return fail(HR_EINVAL, "%s: null scene", who);
+    if (!s->prop_alloc) return fail(HR_EINVAL, "%s: no proposal set on this scene (hr_proposal_set)", who);
+    return HR_OK;
+}
+
+int hr_proposal_get(hr_scene* s, float* theta_host, void* stream)
+{
+    int rc = need_prop(s, "hr_proposal_get");
+    if (rc) return rc;
+    if (!theta_host) return fail(HR_EINVAL, "hr_proposal_get: null argument");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemcpy(theta_host, s->prop.theta, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_get: %s", hipGetErrorString(e));
+    return HR_OK;
+}
+
+int hr_proposal_override(hr_scene* s, const float* z)
+{
+    int rc = need_prop(s, "hr_proposal_override");
+    if (rc) return rc;
+    s->prop.z_override = z;
+    return HR_OK;
+}
+
+int hr_proposal_train(hr_scene* s, void* stream)
+{
+    int rc = need_prop(s, "hr_proposal_train");
+    if (rc) return rc;
+    return proposal_train_impl(s, (hipStream_t)stream);
+}
+
+int hr_proposal_features(hr_scene* s, float* feats, void* stream)
+{
+    int rc = need_prop(s, "hr_proposal_features");
+    if (rc) return rc;
+    if (!feats) return fail(HR_EINVAL, "hr_proposal_features: null argument");
+    const long long rows = (long long)s->n_views * s->E;
+    return launch(s, "k_proposal_read_feat", k_proposal_read_feat,
+                  dim3((unsigned)std::min<long long>(4096, (rows * 16 + 255) / 256)), dim3(256), 0,
+                  (hipStream_t)stream, (const s4v*)s->prop.feat, (const EdgeRec*)s->edge_rec, rows, feats);
+}
+
+int hr_proposal_stats(hr_scene* s, float* z, uint32_t* wq, float* a, float* dc, void* stream)
+{
+    int rc = need_prop(s, "hr_proposal_stats");
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t rows = (size_t)s->n_views * s->E;
+    hipError_t e = hipSuccess;
+    if (z) e = hipMemcpyAsync(z, s->prop.z, sizeof(float) * rows, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && a) e = hipMemcpyAsync(a, s->prop.stat_a, sizeof(float) * rows, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && dc)
+        e = hipMemcpyAsync(dc, s->prop.stat_dc, sizeof(float) * rows * 4, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_stats: %s", hipGetErrorString(e));
+    if (wq)
+        return launch(s, "k_proposal_read_wq", k_proposal_read_wq,
+                      dim3((unsigned)std::min<size_t>(4096, (rows + 255) / 256)), dim3(256), 0, st,
+                      (const EdgeRec*)s->edge_rec, (long long)rows, wq);
+    return HR_OK;
+}
+
+int hr_proposal_eval(hr_scene* s, const float* X, int32_t n, float* z, void* stream)
+{
+    int rc = need_prop(s, "hr_proposal_eval");
+    if (rc) return rc;
+    if (n < 0 || (n > 0 && (!X || !z))) return fail(HR_EINVAL, "hr_proposal_eval: bad argument");
+    if (n == 0) return HR_OK;
+    return launch(s, "k_proposal_eval", k_proposal_eval, dim3((unsigned)((n + 63) / 64)), dim3(256), 0,
+                  (hipStream_t)stream, s->prop, X, (int)n, z);
+}
+
+int hr_proposal_fit(hr_scene* s, const float* X, const uint32_t* w, const float* a, int32_t n, float* grad,
+                    int32_t apply, void* stream)
+{
+    int rc = need_prop(s, "hr_proposal_fit");
+    if (rc) return rc;
+    if (n < 1 || n > kFitMaxRows || !X || !w || !a)
+        return fail(HR_EINVAL, "hr_proposal_fit: need 1..%d rows and non-null X, w, a", kFitMaxRows);
+    hipStream_t st = (hipStream_t)stream;
+    rc = launch(s, "k_proposal_eval", k_proposal_eval, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, s->prop, X,
+                (int)n, s->fit_z);
+    if (!rc)
+        rc = launch(s, "k_proposal_fit", k_proposal_fit, dim3(1), dim3(256), 0, st, s->prop, X, w, a,
+                    (const float*)s->fit_z, (int)n, grad, (int)(apply != 0));
+    if (!rc && apply) rc = launch(s, "k_proposal_adam", k_proposal_adam, dim3(1), dim3(256), 0, st, s->prop);
+    return rc;
 }
 
 int hr_edge_stats(hr_scene* s, uint64_t* total_host, int64_t* budget_host, void* stream)

@@ -48,7 +48,7 @@ struct alignas(16) EdgeRec {  // silhouette edge of one view (float32)
     float ax, ay, bx, by;     // projected endpoints
     float t0, t1;             // clipped parameter interval
     uint32_t w;               // quantised length, 1/256 px (0 = not sampled)
-    int pad;
+    uint32_t wq;              // sampling weight (= w for length-proportional sampling)
 };
 
 // ---------------------------------------------------------------------------

@@ -119,6 +119,8 @@ struct EdgeArgs {
     const float* background;
     const float* dimage;
     float* gacc;
+    float* stat_a;             // [n_views,E] nullable: sum of |sample contribution| per edge
+    float* stat_dc;            // [n_views,E,4] nullable: sum of |c- - c+| per channel, sample count
     unsigned long long* counts;
     int n_nodes, tex_h, tex_w;
     float delta;

@@ -815,7 +815,7 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
     for (int e = e0; e < e1; ++e) {
         EdgeRec r;
         r.ax = r.ay = r.bx = r.by = r.t0 = r.t1 = 0.0f;
-        r.w = 0; r.pad = 0;
+        r.w = 0; r.wq = 0;
         const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
         const float* pa = vh + 3 * va;
         int front[2] = {0, 0};
@@ -858,7 +858,7 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
                 float qv = floorf(ell * 256.0f);
                 uint32_t wq = qv >= 4294967295.0f ? 0xFFFFFFFFu : (uint32_t)qv;
                 if (wq == 0) wq = 1;
-                r.ax = ax; r.ay = ay; r.bx = bx; r.by = by; r.t0 = lo; r.t1 = hi; r.w = wq;
+                r.ax = ax; r.ay = ay; r.bx = bx; r.by = by; r.t0 = lo; r.t1 = hi; r.w = wq; r.wq = wq;
             }
         }
         rec[e] = r;
@@ -1019,10 +1019,18 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
         if (side != 0) continue;
         // c(x - delta n) - c(x + delta n)
         const float jump = g[0] * (o0 - col[0]) + g[1] * (o1 - col[1]) + g[2] * (o2 - col[2]);
+        float* dcs = a.stat_dc ? a.stat_dc + ((size_t)vi * E + e) * 4 : nullptr;
+        if (dcs) {   // colour-jump statistics of the edge (proposal features)
+            unsafeAtomicAdd(dcs + 0, fabsf(o0 - col[0]));
+            unsafeAtomicAdd(dcs + 1, fabsf(o1 - col[1]));
+            unsafeAtomicAdd(dcs + 2, fabsf(o2 - col[2]));
+            unsafeAtomicAdd(dcs + 3, 1.0f);
+        }
         if (jump == 0.0f) continue;
-        // weight: (stratum probability width/T) / (density (w_e/T)/len per unit length)
+        // weight: (stratum probability width/T) / (density (wq_e/T)/len per unit length)
         const float ell = len * (qe.t1 - qe.t0);
-        const float sc = jump * (ell * (float)width / (float)qe.w);
+        const float sc = jump * (ell * (float)width / (float)qe.wq);
+        if (a.stat_a) unsafeAtomicAdd(a.stat_a + (size_t)vi * E + e, fabsf(sc));
         const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
         const float* vh = a.verts + (size_t)hand * a.m.V * 3;
         float* gout = a.gacc + (size_t)hand * a.m.V * 6;

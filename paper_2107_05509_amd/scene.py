@@ -640,3 +640,20 @@ def camera_arrays(cams):
     off = np.zeros(n + 1, dtype=np.int64)
     off[1:] = np.cumsum([c.W * c.H for c in cams])
     return dict(R=R, o=o, intr=intr, wh=wh, hand=hand, pix_off=off)
+
+
+# --------------------------------------------------------------------------
+# initial parameters of the edge-proposal network (seeded; zero output layer,
+# so the initial proposal is the length-proportional one)
+# --------------------------------------------------------------------------
+
+def mlp_init(seed=0, n_in=16, n_hid=64, out_scale=0.0):
+    """Float32 arrays W1 [16,64], b1 [64], W2 [64,64], b2 [64], w3 [64], b3 [1]:
+    hidden weights N(0, 1/fan_in), zero biases, output weights N(0, out_scale^2)."""
+    r = _rng(seed, 31)
+    return {"W1": (r.normal(0, 1, (n_in, n_hid)) / np.sqrt(n_in)).astype(np.float32),
+            "b1": np.zeros(n_hid, np.float32),
+            "W2": (r.normal(0, 1, (n_hid, n_hid)) / np.sqrt(n_hid)).astype(np.float32),
+            "b2": np.zeros(n_hid, np.float32),
+            "w3": (r.normal(0, 1, n_hid) * out_scale).astype(np.float32),
+            "b3": np.zeros(1, np.float32)}

@@ -50,7 +50,7 @@ def test_render_parity(tiny):
 
 def test_loss_parity(tiny):
     c = tiny
-    img, _ = c.gpu_render(0)
+    img = f32(c.oracle_render(0))   # inputs come from the oracle side only
     rng = np.random.default_rng(1)
     target = f32(np.clip(img + rng.normal(0, 0.05, img.shape), 0, 1))
     target[::7] = img[::7]  # exact ties: sign(0) = 0
@@ -107,7 +107,7 @@ def _gpu_grads(c, dimage, flags):
 
 def test_interior_adjoint_parity(tiny):
     c = tiny
-    img, _ = c.gpu_render(0)
+    img = f32(c.oracle_render(0))   # inputs come from the oracle side only
     d = _dimage(c, img)
     g = _gpu_grads(c, d, binding.HR_GRAD_INTERIOR)
     o = _oracle_grads(c, d, binding.HR_GRAD_INTERIOR)
@@ -120,7 +120,7 @@ def test_interior_adjoint_parity(tiny):
 
 def test_edge_term_parity(tiny):
     c = tiny
-    img, _ = c.gpu_render(0)
+    img = f32(c.oracle_render(0))   # inputs come from the oracle side only
     d = _dimage(c, img)
     g = _gpu_grads(c, d, binding.HR_GRAD_EDGES)
     o = _oracle_grads(c, d, binding.HR_GRAD_EDGES)
