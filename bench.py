@@ -175,6 +175,68 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_proposal(args):
+    """Learned edge proposal against length-proportional sampling on the
+    realistic workload: (1) refinement with the proposal trained online
+    (iterations/s with and without it); (2) at the final pose, the spread of the
+    boundary term's 64-parameter gradient over 256 sample keys at the same
+    edge-sample budget (trace of the covariance; the means must agree within
+    their standard errors: unbiasedness); (3) loss trajectories of both
+    samplers from the same start."""
+    w = scene.workload_realistic(args.seed)
+    n_iter = 200
+    out = {"metric": "learned edge proposal: gradient variance ratio and refine iters/s", "unit": "ratio",
+           "config": {"workload": w.name, "iterations": n_iter, "seeds": 256}}
+    traj, refs = {}, {}
+    for kind in ("length", "learned"):
+        ref = make_refiner(w, seed=args.seed, tune=False)
+        if kind == "learned":
+            ref.scene.proposal_set(binding.HR_PROPOSAL_LEARNED, scene.mlp_init(args.seed), lr=3e-3, ema=0.9)
+        ref.run(5)
+        torch.cuda.synchronize()
+        losses = []
+        t0 = time.perf_counter()
+        for _ in range(n_iter // 10):
+            ref.run(10)
+            losses.append(float(ref.loss.item()))
+        dt = time.perf_counter() - t0
+        traj[kind] = losses
+        out[f"{kind}_iters_per_s"] = round(n_iter / dt, 2)
+        refs[kind] = ref
+        print(f"[bench] {kind}: {n_iter / dt:.1f} it/s, loss {losses[-1]:.5f}", file=sys.stderr, flush=True)
+    # gradient spread at the learned run's final state, both samplers
+    ref = refs["learned"]
+    g_learned = ref.scene
+    th, tw = w.albedo_true.shape[1:3]
+    g_length = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=1000 + args.seed)
+    q = ref.state
+    g_learned.skin(q.params, q.verts)
+    g_learned.render(q.verts, q.albedo, q.background, 0, q.image)
+    g_learned.loss(q.image, q.target, q.mask, q.loss, q.dimage)
+    d = q.dimage.clone()
+    gp = torch.empty_like(q.params)
+    ga = torch.empty_like(q.albedo)
+    res = {}
+    for kind, g in (("length", g_length), ("learned", g_learned)):
+        rows = []
+        for s in range(256):
+            g.backward(q.params, q.verts, q.albedo, q.background, d, 5000 + s, gp, ga, flags=binding.HR_GRAD_EDGES)
+            rows.append(gp[0].double().cpu().numpy())
+        res[kind] = np.array(rows)
+    mu = {k: v.mean(0) for k, v in res.items()}
+    se = {k: v.std(0, ddof=1) / np.sqrt(len(v)) for k, v in res.items()}
+    zscore = np.abs(mu["learned"] - mu["length"]) / np.sqrt(se["learned"] ** 2 + se["length"] ** 2 + 1e-300)
+    free = np.r_[3:64]
+    tr = {k: float(np.trace(np.cov(v[:, free].T))) for k, v in res.items()}
+    out["value"] = round(tr["length"] / tr["learned"], 3)
+    out["trace_cov"] = tr
+    out["variance_ratio_length_over_learned"] = out["value"]
+    out["unbiasedness_max_abs_z"] = round(float(zscore[free].max()), 2)
+    out["loss_length"] = traj["length"]
+    out["loss_learned"] = traj["learned"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,7 +250,7 @@ def main():
                     help="R,A: persistent render/adjoint grid sizes to use instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2)
-    ap.add_argument("--workload", choices=("realistic", "batched"), default="realistic",
+    ap.add_argument("--workload", choices=("realistic", "batched", "proposal"), default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
     args = ap.parse_args()
@@ -202,6 +264,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "proposal":
+        return bench_proposal(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))

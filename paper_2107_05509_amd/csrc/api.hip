@@ -98,6 +98,10 @@ struct hr_scene {
     int prop_kind = HR_PROPOSAL_LENGTH;
     PropDev prop{};
     float* fit_z = nullptr;
+    // side stream of hr_iterate: the proposal pass runs beside the loss, its
+    // training beside the geometry backward and the parameter step
+    hipStream_t side = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool counting = false;
     // per-kernel timing (profiling aid)
     bool timing = false;
@@ -177,6 +181,9 @@ void hr_scene_destroy(hr_scene* s)
     for (auto& t : s->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     for (void* p : s->allocs) (void)hipFree(p);
+    for (hipEvent_t e : s->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->side) (void)hipStreamDestroy(s->side);
     delete s;
 }
 
@@ -330,6 +337,15 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<unsigned long long>(&s->counts, nullptr, 12));
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)0, s->counts, 12);
     if (hipDeviceSynchronize() != hipSuccess) { hr_scene_destroy(s); return fail(HR_EHIP, "scene init failed"); }
+    if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EHIP, "scene init: stream");
+    }
+    for (hipEvent_t& ev : s->ev)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            hr_scene_destroy(s);
+            return fail(HR_EHIP, "scene init: event");
+        }
 #undef TRY
     s->smem_skin = sizeof(float) * 3 * V;
     s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.node_stride);
@@ -531,7 +547,8 @@ static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
 static int backward_impl(hr_scene* s, const float* params, const float* verts, const float* albedo,
                          const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
                          uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
-                         float* grad_normals, hipStream_t st)
+                         float* grad_normals, hipStream_t st, bool proposal_done = false,
+                         hipEvent_t after_trace = nullptr)
 {
     int rc;
     if (!(flags & HR_REUSE_GEOMETRY)) {
@@ -553,8 +570,11 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
         if (s->prop_kind == HR_PROPOSAL_LEARNED) {
             // learned sampling weights replace the length weights of the CDF;
             // the samples report per-edge statistics for training
-            rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views), dim3(256), 0, st, e, s->prop);
-            if (rc) return rc;
+            if (!proposal_done) {
+                rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, st, e,
+                            s->prop);
+                if (rc) return rc;
+            }
             e.stat_a = s->prop.stat_a;
             e.stat_dc = s->prop.stat_dc;
         }
@@ -581,6 +601,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
             rc = launch(s, "k_backward_trace", k_backward_trace<false>, grid, dim3(kThreads), 0, st, a, e, n_edge);
         if (rc) return rc;
     }
+    if (after_trace && hipEventRecord(after_trace, st) != hipSuccess) return fail(HR_EHIP, "hr_backward: event");
     return launch(s, "k_geom_backward", k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh,
                   params, verts, (const float*)s->gacc, (const float*)s->gface, grad_params, grad_verts,
                   grad_normals);
@@ -643,9 +664,13 @@ static int check_state(const hr_state* q, const char* who)
 static int proposal_train_impl(hr_scene* s, hipStream_t st)
 {
     if (s->prop_kind != HR_PROPOSAL_LEARNED || s->prop.z_override || !(s->prop.lr > 0.0f)) return HR_OK;
-    EdgeArgs e = edge_args(s, nullptr, nullptr, nullptr, nullptr, 0, nullptr);
-    int rc = launch(s, "k_proposal_train", k_proposal_train, dim3(s->n_views), dim3(256), 0, st, e, s->prop);
-    if (!rc) rc = launch(s, "k_proposal_adam", k_proposal_adam, dim3(1), dim3(256), 0, st, s->prop);
+    const int items = s->n_views * s->prop.split;
+    int rc = launch(s, "k_proposal_train", k_proposal_train, dim3(std::min(items, 256)), dim3(256), 0, st,
+                    (const EdgeRec*)s->edge_rec, s->E, s->n_views, s->prop);
+    const long long rows = (long long)s->n_views * s->E;
+    if (!rc)
+        rc = launch(s, "k_proposal_ema", k_proposal_ema, dim3((unsigned)std::min<long long>(2048, (rows + 255) / 256)),
+                    dim3(256), 0, st, s->prop, rows);
     return rc;
 }
 
@@ -653,19 +678,45 @@ static int proposal_train_impl(hr_scene* s, hipStream_t st)
 static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cfg, uint32_t flags, hipStream_t st)
 {
     const int* it = q->iter;
+    const bool learned = (flags & HR_GRAD_EDGES) && s->prop_kind == HR_PROPOSAL_LEARNED;
+    const bool train = learned && !s->prop.z_override && s->prop.lr > 0.0f;
+    auto fork = [&](hipEvent_t ev) -> int {
+        if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(s->side, ev, 0) != hipSuccess)
+            return fail(HR_EHIP, "hr_iterate: fork");
+        return HR_OK;
+    };
+    auto join = [&](hipEvent_t ev) -> int {
+        if (hipEventRecord(ev, s->side) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess)
+            return fail(HR_EHIP, "hr_iterate: join");
+        return HR_OK;
+    };
     int rc = launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh,
                     (const float*)q->params, q->verts, (float*)nullptr);
     if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st);
+    if (!rc && learned) {
+        // proposal pass (needs the silhouette tables of the render) beside the loss
+        const EdgeArgs e = edge_args(s, q->verts, q->albedo, q->background, nullptr, 0, it);
+        rc = fork(s->ev[0]);
+        if (!rc)
+            rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, s->side, e,
+                        s->prop);
+    }
     if (!rc) rc = loss_impl(s, q->image, q->target, q->mask, q->loss, q->dimage, st);
+    if (!rc && learned) rc = join(s->ev[1]);
+    // training (needs the records of the edge samples) beside the geometry
+    // backward and the parameter step
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st);
-    if (!rc && (flags & HR_GRAD_EDGES)) rc = proposal_train_impl(s, st);
+                           nullptr, st, learned, train ? s->ev[2] : nullptr);
+    if (!rc && train && hipStreamWaitEvent(s->side, s->ev[2], 0) != hipSuccess)
+        rc = fail(HR_EHIP, "hr_iterate: fork");
+    if (!rc && train) rc = proposal_train_impl(s, s->side);
     if (!rc)
         rc = step_impl(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
                        q->m_albedo, q->v_albedo, 1, it, cfg, st);
     if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
+    if (!rc && train) rc = join(s->ev[3]);
     return rc;
 }
 
@@ -850,10 +901,18 @@ int hr_proposal_set(hr_scene* s, const hr_proposal_config* cfg, const float* the
         if (!rc) rc = s->upload<float>(&P.stat_dc, nullptr, nve * 4);
         if (!rc) rc = s->upload<float>(&P.ema, nullptr, nve * 4);
         if (!rc) rc = s->upload<float>(&s->fit_z, nullptr, kFitMaxRows);
+        if (!rc) rc = s->upload<unsigned short>(&P.list, nullptr, nve);
+        if (!rc) rc = s->upload<int>(&P.nlist, nullptr, (size_t)s->n_views);
+        if (!rc) rc = s->upload<double>(&P.vstat, nullptr, 2 * (size_t)s->n_views);
+        if (!rc) rc = s->upload<int>(&P.vcount, nullptr, (size_t)s->n_views);
+        if (!rc) rc = s->upload<int>(&P.tcount, nullptr, 1);
         if (rc) return rc;
         s->prop_alloc = true;
         e = hipMemset(P.theta, 0, sizeof(float) * kMlpParams);
         if (e == hipSuccess) e = hipMemset(P.feat, 0, sizeof(s4v) * nve * 4);
+        if (e == hipSuccess) e = hipMemset(P.nlist, 0, sizeof(int) * s->n_views);
+        if (e == hipSuccess) e = hipMemset(P.vcount, 0, sizeof(int) * s->n_views);
+        if (e == hipSuccess) e = hipMemset(P.tcount, 0, sizeof(int));
         if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
     }
     if (theta_host) {
@@ -872,6 +931,7 @@ int hr_proposal_set(hr_scene* s, const hr_proposal_config* cfg, const float* the
     if (e != hipSuccess) return fail(HR_EHIP, "hr_proposal_set: %s", hipGetErrorString(e));
     P.eps = cfg->eps; P.ema_beta = cfg->ema; P.lr = cfg->lr;
     P.beta1 = cfg->beta1; P.beta2 = cfg->beta2; P.adam_eps = cfg->adam_eps;
+    P.split = std::max(1, std::min(8, 256 / s->n_views));
     s->prop_kind = cfg->kind;
     hipLaunchKernelGGL(k_proposal_pack, dim3(1), dim3(256), 0, (hipStream_t)0, P);
     int rc = check_launch("hr_proposal_set");

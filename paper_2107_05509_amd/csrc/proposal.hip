@@ -50,7 +50,13 @@ struct PropDev {
     float* stat_dc;      // [nV,E,4] sum of |c- - c+| per channel, sample count
     float* ema;          // [nV,E,4] colour-jump averages, [3] = 1 once measured
     const float* z_override;   // nullable [nV,E]: logits used instead of the network
+    unsigned short* list;      // [nV,E] silhouette edges of each view (edge order)
+    int* nlist;                // [nV]
+    double* vstat;             // [nV,2] max logit, sum w exp(z - max) of each view
+    int* vcount;               // [nV] finished blocks of the proposal pass (reset by the last)
+    int* tcount;               // [1] finished blocks of the training pass (reset by the last)
     float eps, ema_beta, lr, beta1, beta2, adam_eps;
+    int split;                 // blocks per view of the proposal and training passes
 };
 
 __device__ __forceinline__ unsigned short bf16_bits(float x)
@@ -138,25 +144,71 @@ __device__ __forceinline__ s4v pack_bf16(const float f[4])
     return x;
 }
 
-// Back-propagation of dL/dz of the lane's row through one tile; adds the
-// parameter gradient to `gl` (LDS, kMlpParams floats).  tA, tB: this wave's
+// Sum of v over the 16 lanes of each row (lane group), complete in the row's
+// last lane (r = 15): four DPP row shifts.
+__device__ __forceinline__ float row16_sum(float v)
+{
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xF, 0xF, true));   // row_shr:1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xF, 0xF, true));   // row_shr:2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xF, 0xF, true));   // row_shr:4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xF, 0xF, true));   // row_shr:8
+    return v;
+}
+
+// weight-gradient accumulators of one wave (MFMA accumulators kept across tiles)
+struct GradAcc {
+    f4v dw2[16];   // tile (mt input, nt output): lane holds dW2[16 mt + 4 g + i][16 nt + r]
+    f4v dw1[4];    // tile nt: lane holds dW1[4 g + i][16 nt + r]
+};
+
+__device__ __forceinline__ void grad_acc_zero(GradAcc& G)
+{
+    const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) G.dw2[t] = zero;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) G.dw1[t] = zero;
+}
+
+// add a wave's weight gradients to `gl` (LDS, kMlpParams floats)
+__device__ __forceinline__ void grad_acc_flush(const GradAcc& G, int r, int g, float* gl)
+{
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                atomicAdd(gl + kOffW2 + (16 * mt + 4 * g + i) * 64 + 16 * nt + r, G.dw2[mt * 4 + nt][i]);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(gl + kOffW1 + (4 * g + i) * 64 + 16 * nt + r, G.dw1[nt][i]);
+}
+
+// Back-propagation of dL/dz of the lane's row through one tile.  Bias and
+// output-weight gradients are summed over the tile's rows and added to `gl`
+// (LDS); the weight-matrix gradients accumulate in G.  tA, tB: this wave's
 // LDS transpose buffers (16 x 64 bfloat16 each).
-__device__ void mlp_tile_bwd(const PropDev& P, const s4v* w2b, const float* __restrict__ fb, s4v x,
-                             const TileFwd& T, float dz, int r, int g, float* gl, unsigned short* tA,
-                             unsigned short* tB)
+__device__ void mlp_tile_bwd(const s4v* w2b, const float* __restrict__ fb, s4v x, const TileFwd& T, float dz,
+                             int r, int g, float* gl, GradAcc& G, unsigned short* tA, unsigned short* tB)
 {
     const f4v zero = {0.0f, 0.0f, 0.0f, 0.0f};
     s4v da2b[4];
-    if (g == 0) atomicAdd(gl + kOffB3, dz);
+    const float dzs = row16_sum(dz);
+    if (r == 15 && g == 0) atomicAdd(gl + kOffB3, dzs);
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int h = 16 * mt + 4 * g + i;
             const float h2 = bf16_val(bf16_bits(gelu_f(T.a2[mt][i])));
-            atomicAdd(gl + kOffW3 + h, dz * h2);
             const float da2 = dz * fb[kFbW3 + h] * gelu_grad_f(T.a2[mt][i]);
-            atomicAdd(gl + kOffB2 + h, da2);
+            const float sw3 = row16_sum(dz * h2), sb2 = row16_sum(da2);
+            if (r == 15) {
+                atomicAdd(gl + kOffW3 + h, sw3);
+                atomicAdd(gl + kOffB2 + h, sb2);
+            }
             da2b[mt][i] = (short)bf16_bits(da2);
         }
     }
@@ -171,11 +223,12 @@ __device__ void mlp_tile_bwd(const PropDev& P, const s4v* w2b, const float* __re
         for (int i = 0; i < 4; ++i) {
             const int h = 16 * mt + 4 * g + i;
             const float da1 = c[i] * gelu_grad_f(T.a1[mt][i]);
-            atomicAdd(gl + kOffB1 + h, da1);
+            const float sb1 = row16_sum(da1);
+            if (r == 15) atomicAdd(gl + kOffB1 + h, sb1);
             da1b[mt][i] = (short)bf16_bits(da1);
         }
     }
-    // dW2 = H1^T dA2 (rows are the contraction): transpose both through LDS
+    // dW2 += H1^T dA2 (rows are the contraction): transpose both through LDS
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt)
 #pragma unroll
@@ -194,13 +247,11 @@ __device__ void mlp_tile_bwd(const PropDev& P, const s4v* w2b, const float* __re
             s4v B;
 #pragma unroll
             for (int i = 0; i < 4; ++i) B[i] = (short)tB[(4 * g + i) * 64 + 16 * nt + r];
-            const f4v c = mfma16(A, B, zero);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) atomicAdd(gl + kOffW2 + (16 * mt + 4 * g + i) * 64 + 16 * nt + r, c[i]);
+            G.dw2[mt * 4 + nt] = mfma16(A, B, G.dw2[mt * 4 + nt]);
         }
     }
     wave_lds_sync();
-    // dW1 = X^T dA1
+    // dW1 += X^T dA1
 #pragma unroll
     for (int i = 0; i < 4; ++i) tA[r * 16 + 4 * g + i] = (unsigned short)x[i];
 #pragma unroll
@@ -216,12 +267,9 @@ __device__ void mlp_tile_bwd(const PropDev& P, const s4v* w2b, const float* __re
         s4v B;
 #pragma unroll
         for (int i = 0; i < 4; ++i) B[i] = (short)tB[(4 * g + i) * 64 + 16 * nt + r];
-        const f4v c = mfma16(A, B, zero);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) atomicAdd(gl + kOffW1 + (4 * g + i) * 64 + 16 * nt + r, c[i]);
+        G.dw1[nt] = mfma16(A, B, G.dw1[nt]);
     }
     wave_lds_sync();
-    (void)P;
 }
 
 // operand copies of the master parameters (one block)
@@ -258,8 +306,9 @@ __device__ void pack_operands(const PropDev& P)
 
 __global__ void __launch_bounds__(256) k_proposal_pack(PropDev P) { pack_operands(P); }
 
-// Adam on the master parameters with the accumulated gradient (one block).
-__global__ void __launch_bounds__(256) k_proposal_adam(PropDev P)
+// Adam on the master parameters with the accumulated gradient, then the
+// operand copies (one block).
+__device__ void adam_and_pack(const PropDev& P)
 {
     const int t = *P.step + 1;
     __syncthreads();
@@ -277,6 +326,8 @@ __global__ void __launch_bounds__(256) k_proposal_adam(PropDev P)
     __syncthreads();
     pack_operands(P);
 }
+
+__global__ void __launch_bounds__(256) k_proposal_adam(PropDev P) { adam_and_pack(P); }
 
 // Silhouette edges of view vi (w > 0) in edge order -> list; returns the count.
 __device__ int silhouette_list(const EdgeRec* __restrict__ rec, int E, unsigned short* list, int* part)
@@ -389,10 +440,12 @@ __device__ void edge_feature4(const EdgeArgs& a, const float* __restrict__ ema, 
     f[3] = dc[0];
 }
 
-// Per view (one block of 256): features and logits of the silhouette edges,
-// integer sampling weights W_e = max(1, floor(w_e (1 + (1 - eps)(E_e/Ebar - 1))))
-// with E_e = exp(z_e - max z), Ebar = sum w E / sum w (equal logits keep the
-// length weights exactly), their inclusive prefix sums and total.
+// Block (v, sp) of grid (n_views, split): features and logits of tiles
+// sp, sp + split, ... of view v's silhouette edges.  The last block of a view
+// to finish then derives the integer sampling weights
+// W_e = max(1, floor(w_e (1 + (1 - eps)(E_e/Ebar - 1)))), E_e = exp(z_e - max z),
+// Ebar = sum w E / sum w (equal logits keep the length weights exactly), their
+// inclusive prefix sums and total, and keeps (max z, sum w E) for training.
 __global__ void __launch_bounds__(256) k_proposal(EdgeArgs a, PropDev P)
 {
     __shared__ unsigned short list[kPropMaxEdges];
@@ -400,15 +453,20 @@ __global__ void __launch_bounds__(256) k_proposal(EdgeArgs a, PropDev P)
     __shared__ int ipart[256];
     __shared__ double dpart[256];
     __shared__ unsigned long long upart[256];
-    const int vi = blockIdx.x;
+    __shared__ int last;
+    const int vi = blockIdx.x, sp = blockIdx.y, S = gridDim.y;
     const int E = a.m.E;
     EdgeRec* rec = a.rec + (size_t)vi * E;
     const int n = silhouette_list(rec, E, list, ipart);
+    if (sp == 0) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) P.list[(size_t)vi * E + j] = list[j];
+        if (threadIdx.x == 0) P.nlist[vi] = n;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
     const bool use_net = P.z_override == nullptr;
     MlpRegs R;
     if (use_net) load_mlp(P, lane, R);
-    for (int t = wave; 16 * t < n; t += 4) {
+    for (int t = 4 * sp + wave; 16 * t < n; t += 4 * S) {
         const int row = 16 * t + r;
         const int e = row < n ? (int)list[row] : -1;
         float f[4];
@@ -422,11 +480,17 @@ __global__ void __launch_bounds__(256) k_proposal(EdgeArgs a, PropDev P)
         } else {
             z = e >= 0 ? P.z_override[(size_t)vi * E + e] : 0.0f;
         }
-        if (e >= 0 && g == 0) {
-            zl[row] = z;
-            P.z[(size_t)vi * E + e] = z;
-        }
+        if (e >= 0 && g == 0) P.z[(size_t)vi * E + e] = z;
     }
+    // the last block of the view continues
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(P.vcount + vi, 1) == S - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) P.vcount[vi] = 0;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) zl[j] = P.z[(size_t)vi * E + list[j]];
     __syncthreads();
     // max logit, then sum w exp(z - max) and sum w
     float zm = -3.0e38f;
@@ -456,7 +520,12 @@ __global__ void __launch_bounds__(256) k_proposal(EdgeArgs a, PropDev P)
         }
         __syncthreads();
     }
-    const double ebar = n > 0 ? dpart[0] / (double)upart[0] : 1.0;
+    const double S1 = dpart[0];
+    const double ebar = n > 0 ? S1 / (double)upart[0] : 1.0;
+    if (threadIdx.x == 0) {
+        P.vstat[2 * vi] = zmax;
+        P.vstat[2 * vi + 1] = S1;
+    }
     __syncthreads();
     // weights of a contiguous chunk of list entries, block scan, CDF in edge order
     const int per = (n + blockDim.x - 1) / blockDim.x;
@@ -493,97 +562,104 @@ __global__ void __launch_bounds__(256) k_proposal(EdgeArgs a, PropDev P)
     if (threadIdx.x == blockDim.x - 1) a.total[vi] = upart[blockDim.x - 1];
 }
 
-// Per view (one block of 256): gradient of KL(pi || q) of the view's silhouette
-// edges, pi = a / sum a from the statistics of the last backward pass, q = w
-// exp(z) / sum w exp(z) (dL/dz = q - pi), accumulated into P.grad; then the
-// colour-jump averages are updated and the statistics cleared.
-__global__ void __launch_bounds__(256) k_proposal_train(EdgeArgs a, PropDev P)
+// Gradient of sum over views of KL(pi || q) from the records of the last
+// backward pass: pi = a / sum a, q = w exp(z) / sum w exp(z) of each view's
+// silhouette edges (dL/dz = q - pi).  Work item k = (view k / split, part
+// k % split) covers tiles part, part + split, ... of the view; a block walks
+// items blockIdx.x, blockIdx.x + gridDim.x, ... and adds its gradient to
+// P.grad once.  The last block to finish takes the Adam step.
+__global__ void __launch_bounds__(256) k_proposal_train(const EdgeRec* __restrict__ rec, int E, int n_views,
+                                                        PropDev P)
 {
     __shared__ unsigned short list[kPropMaxEdges];
     __shared__ float gl[kMlpParams];
     __shared__ unsigned short tA[4][16 * 64], tB[4][16 * 64];
-    __shared__ int ipart[256];
     __shared__ double dpart[256];
-    const int vi = blockIdx.x;
-    const int E = a.m.E;
-    const EdgeRec* rec = a.rec + (size_t)vi * E;
-    const int n = silhouette_list(rec, E, list, ipart);
+    __shared__ int last;
+    const int S = P.split;
     for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) gl[i] = 0.0f;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, r = lane & 15, g = lane >> 4;
-    const float* zv = P.z + (size_t)vi * E;
-    const float* av = P.stat_a + (size_t)vi * E;
-    // max logit, sum w exp(z - max), sum a
-    float zm = -3.0e38f;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) zm = fmaxf(zm, zv[list[j]]);
-    dpart[threadIdx.x] = zm;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) dpart[threadIdx.x] = fmax(dpart[threadIdx.x], dpart[threadIdx.x + o]);
-        __syncthreads();
-    }
-    const double zmax = dpart[0];
-    __syncthreads();
-    double s1 = 0.0, sa = 0.0;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int e = list[j];
-        s1 += (double)rec[e].w * exp((double)zv[e] - zmax);
-        sa += (double)av[e];
-    }
-    dpart[threadIdx.x] = s1;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) dpart[threadIdx.x] += dpart[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double S1 = dpart[0];
-    __syncthreads();
-    dpart[threadIdx.x] = sa;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) dpart[threadIdx.x] += dpart[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double Sa = dpart[0];
-    __syncthreads();
-    if (Sa > 0.0 && n > 0) {
-        MlpRegs R;
-        load_mlp(P, lane, R);
-        s4v w2b[16];
+    MlpRegs R;
+    load_mlp(P, lane, R);
+    s4v w2b[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) w2b[t] = P.w2bp[t * 64 + lane];
-        for (int t = wave; 16 * t < n; t += 4) {
+    for (int t = 0; t < 16; ++t) w2b[t] = P.w2bp[t * 64 + lane];
+    GradAcc G;
+    grad_acc_zero(G);
+    bool any = false;
+    for (int k = blockIdx.x; k < n_views * S; k += gridDim.x) {
+        const int vi = k / S, sp = k % S;
+        const int n = P.nlist[vi];
+        __syncthreads();
+        for (int j = threadIdx.x; j < n; j += blockDim.x) list[j] = P.list[(size_t)vi * E + j];
+        const float* zv = P.z + (size_t)vi * E;
+        const float* av = P.stat_a + (size_t)vi * E;
+        double sa = 0.0;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) sa += (double)av[list[j]];
+        dpart[threadIdx.x] = sa;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) dpart[threadIdx.x] += dpart[threadIdx.x + o];
+            __syncthreads();
+        }
+        const double Sa = dpart[0];
+        if (!(Sa > 0.0) || n == 0) continue;
+        any = true;
+        const double zmax = P.vstat[2 * vi], S1 = P.vstat[2 * vi + 1];
+        for (int t = 4 * sp + wave; 16 * t < n; t += 4 * S) {
             const int row = 16 * t + r;
             const int e = row < n ? (int)list[row] : -1;
             s4v x = {0, 0, 0, 0};
             float dz = 0.0f;
             if (e >= 0) {
                 x = P.feat[((size_t)vi * E + e) * 4 + g];
-                const double q = (double)rec[e].w * exp((double)zv[e] - zmax) / S1;
+                // the proposal pass recorded the view's normaliser sum w exp(z - max z)
+                const double q = (double)rec[(size_t)vi * E + e].w * exp((double)zv[e] - zmax) / S1;
                 dz = (float)(q - (double)av[e] / Sa);
             }
             TileFwd T;
             (void)mlp_tile_fwd(R, P.fb, x, g, T);
-            mlp_tile_bwd(P, w2b, P.fb, x, T, dz, r, g, gl, tA[wave], tB[wave]);
+            mlp_tile_bwd(w2b, P.fb, x, T, dz, r, g, gl, G, tA[wave], tB[wave]);
         }
     }
+    grad_acc_flush(G, r, g, gl);
     __syncthreads();
-    if (Sa > 0.0 && n > 0)
+    if (__syncthreads_or(any))
         for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x)
             if (gl[i] != 0.0f) unsafeAtomicAdd(P.grad + i, gl[i]);
-    // colour-jump averages of the edges sampled since the last call; statistics cleared
-    for (int e = threadIdx.x; e < E; e += blockDim.x) {
-        const size_t k = (size_t)vi * E + e;
-        float* dc = P.stat_dc + 4 * k;
-        float* em = P.ema + 4 * k;
-        if (dc[3] > 0.0f) {
-            const float inv = 1.0f / dc[3];
-            for (int ch = 0; ch < 3; ++ch) {
-                const float mean = dc[ch] * inv;
-                em[ch] = em[3] != 0.0f ? P.ema_beta * em[ch] + (1.0f - P.ema_beta) * mean : mean;
+    // the last block takes the Adam step
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(P.tcount, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) *P.tcount = 0;
+    adam_and_pack(P);
+}
+
+// Colour-jump averages of the edges sampled since the last call, statistics
+// cleared (grid-stride over all (view, edge) rows).
+__global__ void __launch_bounds__(256) k_proposal_ema(PropDev P, long long rows)
+{
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < rows;
+         k += (long long)gridDim.x * blockDim.x) {
+        float4 dc = reinterpret_cast<const float4*>(P.stat_dc)[k];
+        if (dc.w > 0.0f) {
+            float4 em = reinterpret_cast<const float4*>(P.ema)[k];
+            const float inv = 1.0f / dc.w;
+            const float m0 = dc.x * inv, m1 = dc.y * inv, m2 = dc.z * inv;
+            if (em.w != 0.0f) {
+                em.x = P.ema_beta * em.x + (1.0f - P.ema_beta) * m0;
+                em.y = P.ema_beta * em.y + (1.0f - P.ema_beta) * m1;
+                em.z = P.ema_beta * em.z + (1.0f - P.ema_beta) * m2;
+            } else {
+                em.x = m0; em.y = m1; em.z = m2;
             }
-            em[3] = 1.0f;
+            em.w = 1.0f;
+            reinterpret_cast<float4*>(P.ema)[k] = em;
         }
-        dc[0] = dc[1] = dc[2] = dc[3] = 0.0f;
+        reinterpret_cast<float4*>(P.stat_dc)[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         P.stat_a[k] = 0.0f;
     }
 }
@@ -654,6 +730,8 @@ __global__ void __launch_bounds__(256) k_proposal_fit(PropDev P, const float* __
         s4v w2b[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) w2b[t] = P.w2bp[t * 64 + lane];
+        GradAcc G;
+        grad_acc_zero(G);
         for (int t = wave; 16 * t < n; t += 4) {
             const int row = 16 * t + r;
             float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -666,8 +744,9 @@ __global__ void __launch_bounds__(256) k_proposal_fit(PropDev P, const float* __
             const s4v x = pack_bf16(f);
             TileFwd T;
             (void)mlp_tile_fwd(R, P.fb, x, g, T);
-            mlp_tile_bwd(P, w2b, P.fb, x, T, dz, r, g, gl, tA[wave], tB[wave]);
+            mlp_tile_bwd(w2b, P.fb, x, T, dz, r, g, gl, G, tA[wave], tB[wave]);
         }
+        grad_acc_flush(G, r, g, gl);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) {

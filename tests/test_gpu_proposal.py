@@ -154,3 +154,77 @@ def test_feature_parity(tiny):
     print("features: %d of %d differ by <= 1 bfloat16 step" % ((diff > 0).sum(), diff.size), flush=True)
     assert (diff <= ulp + 1e-30).all()
     assert (diff > 0).mean() < 0.01
+
+
+def _loop_scene(w, seed=4):
+    th, tw = w.albedo_true.shape[1:3]
+    g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=seed)
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to(DEV, torch.float32)
+    bg = t(f32(w.packed_background()))
+    v = torch.empty(w.n_hands, w.model.n_verts, 3, device=DEV)
+    g.skin(t(f32(w.params_true)), v)
+    target = torch.empty(g.P, 3, device=DEV)
+    g.render(v, t(f32(w.albedo_true)), bg, 77, target)
+    return g, t(f32(w.params_init)), t(f32(w.albedo_init)), bg, target
+
+
+def test_training_inside_captured_iterations():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_05509_amd import refine
+    w = scene.workload_tiny(0)
+    runs = []
+    for graph in (False, True):
+        g, p, a, bg, target = _loop_scene(w)
+        g.proposal_set(binding.HR_PROPOSAL_LEARNED, scene.mlp_init(5), lr=1e-2)
+        r = refine.Refiner(g, p, a, bg, target, None, warm=0, graph_chunk=3)
+        r.run(6, graph=graph)
+        torch.cuda.synchronize()
+        runs.append((r.params.cpu().numpy(), g.proposal_get(), int(r.state.iter.item())))
+    (pa, ta, ia), (pb, tb, ib) = runs
+    th0 = binding.flat_mlp(scene.mlp_init(5))
+    assert ia == ib == 6
+    assert np.abs(ta - th0).max() > 1e-3          # the network trained
+    assert block_rel(pb, pa) <= 1e-3 and block_rel(tb, ta) <= 1e-2
+
+
+def test_trained_proposal_is_unbiased_and_reduces_variance():
+    """Boundary-term gradient over 128 sample keys, at equal edge-sample budget:
+    the learned proposal (trained for 80 iterations on a fixed pose) and the
+    length-proportional one must agree in the mean (within 4.5 standard errors
+    per parameter) and the learned one must have the smaller spread."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = scene.workload_realistic(0, n_views=2)
+    print("case: realistic workload, 2 views, learned proposal", flush=True)
+    res = {}
+    for kind in (binding.HR_PROPOSAL_LENGTH, binding.HR_PROPOSAL_LEARNED):
+        g, p, a, bg, target = _loop_scene(w, seed=6)
+        v = torch.empty(1, w.model.n_verts, 3, device=DEV)
+        img = torch.empty(g.P, 3, device=DEV)
+        g.skin(p, v)
+        g.build_hierarchy(v)
+        g.render(v, a, bg, 0, img)
+        loss = torch.empty(1, device=DEV)
+        d = torch.empty(g.P, 3, device=DEV)
+        g.loss(img, target, None, loss, d)
+        gp = torch.empty(1, 64, device=DEV)
+        ga = torch.empty_like(a)
+        g.proposal_set(kind, scene.mlp_init(1), lr=1e-2)
+        if kind == binding.HR_PROPOSAL_LEARNED:
+            for it in range(80):
+                g.backward(p, v, a, bg, d, 1000 + it, gp, ga, flags=binding.HR_GRAD_EDGES)
+                g.proposal_train()
+        rows = []
+        for s in range(128):
+            g.backward(p, v, a, bg, d, 5000 + s, gp, ga, flags=binding.HR_GRAD_EDGES)
+            rows.append(gp[0].double().cpu().numpy())
+        res[kind] = np.array(rows)[:, 3:]
+    L, Q = res[binding.HR_PROPOSAL_LENGTH], res[binding.HR_PROPOSAL_LEARNED]
+    se = np.sqrt(L.var(0, ddof=1) / len(L) + Q.var(0, ddof=1) / len(Q)) + 1e-30
+    z = np.abs(L.mean(0) - Q.mean(0)) / se
+    ratio = np.trace(np.cov(L.T)) / np.trace(np.cov(Q.T))
+    print("max |z| %.2f over %d parameters; variance ratio length/learned %.3f" % (z.max(), z.size, ratio),
+          flush=True)
+    assert z.max() <= 4.5
+    assert ratio > 1.0
