@@ -84,6 +84,10 @@ struct hr_scene {
     Node* nodes = nullptr;
     float* gacc = nullptr;        // [hands,V,6] vertex gradient slots (edge term)
     float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
+    float* graw = nullptr;        // [hands,V,3] dL/d(raw vertex normal) (geometry backward)
+    float* skin_part = nullptr;   // [hands,skin_blocks,kSkinPart] per-block sums of the skinning backward
+    int skin_blocks = 0;
+    int* skin_count = nullptr;    // [hands] finished blocks of the skinning backward (reset by the last)
     float* loss_partial = nullptr;
     float* view_scale = nullptr;
     EdgeRec* edge_rec = nullptr;
@@ -91,7 +95,7 @@ struct hr_scene {
     unsigned long long* edge_total = nullptr;
     long long* edge_budget = nullptr;
     long long* edge_prefix = nullptr;
-    size_t smem_prepare = 0, smem_skin = 0, smem_geom_bwd = 0;
+    size_t smem_prepare = 0;
     unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
     // learned edge-sampling proposal (hr_proposal_*)
     bool prop_alloc = false;
@@ -257,6 +261,50 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             }
         TRY(s->upload(&q, off.data(), off.size())); md.vf_off = q;
         TRY(s->upload(&q, flat.data(), flat.size())); md.vf_faces = q;
+        // regressor applied to the template and to the shape directions (float64 sums)
+        std::vector<float> jt(3 * (size_t)J), jsd(3 * (size_t)J * std::max(K, 1), 0.0f);
+        for (int j = 0; j < J; ++j)
+            for (int c = 0; c < 3; ++c) {
+                double a = 0.0;
+                for (int v = 0; v < V; ++v) a += (double)m->j_regressor[(size_t)j * V + v] * m->v_template[3 * v + c];
+                jt[3 * j + c] = (float)a;
+                for (int k = 0; k < K; ++k) {
+                    double b = 0.0;
+                    for (int v = 0; v < V; ++v)
+                        b += (double)m->j_regressor[(size_t)j * V + v] * m->shapedirs[((size_t)3 * v + c) * K + k];
+                    jsd[(3 * (size_t)j + c) * K + k] = (float)b;
+                }
+            }
+        float* pf;
+        TRY(s->upload(&pf, jt.data(), jt.size())); md.jt = pf;
+        TRY(s->upload(&pf, jsd.data(), jsd.size())); md.js = pf;
+        std::vector<int> depth(J, 0);
+        int maxd = 0;
+        for (int j = 0; j < J; ++j) {
+            depth[j] = m->parents[j] < 0 ? 0 : depth[m->parents[j]] + 1;
+            maxd = std::max(maxd, depth[j]);
+        }
+        TRY(s->upload(&q, depth.data(), depth.size())); md.jdepth = q;
+        md.max_depth = maxd;
+        // non-zero skinning weights per vertex, padded to the largest count
+        int infl = 1;
+        for (int v = 0; v < V; ++v) {
+            int c = 0;
+            for (int j = 0; j < J; ++j) c += m->weights[(size_t)v * J + j] != 0.0f;
+            infl = std::max(infl, c);
+        }
+        std::vector<int> widx((size_t)V * infl, 0);
+        std::vector<float> wval((size_t)V * infl, 0.0f);
+        for (int v = 0; v < V; ++v) {
+            int c = 0;
+            for (int j = 0; j < J; ++j) {
+                const float w = m->weights[(size_t)v * J + j];
+                if (w != 0.0f) { widx[(size_t)v * infl + c] = j; wval[(size_t)v * infl + c] = w; ++c; }
+            }
+        }
+        md.infl = infl;
+        TRY(s->upload(&q, widx.data(), widx.size())); md.widx = q;
+        TRY(s->upload(&pf, wval.data(), wval.size())); md.wval = pf;
     }
     // hierarchy topology: from the rest pose until hr_build_hierarchy is called
     {
@@ -327,6 +375,14 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.node_stride));
     TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_hands * V * 6));
     TRY(s->upload<float>(&s->gface, nullptr, (size_t)n_hands * F * 18));
+    TRY(s->upload<float>(&s->graw, nullptr, (size_t)n_hands * V * 3));
+    s->skin_blocks = (V + 127) / 128;
+    TRY(s->upload<float>(&s->skin_part, nullptr, (size_t)n_hands * s->skin_blocks * kSkinPart));
+    TRY(s->upload<int>(&s->skin_count, nullptr, (size_t)n_hands));
+    if (hipMemset(s->skin_count, 0, sizeof(int) * n_hands) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EHIP, "scene init: memset");
+    }
     TRY(s->upload<float>(&s->loss_partial, nullptr, 2 * (size_t)s->n_chunks));
     TRY(s->upload<float>(&s->view_scale, nullptr, n_views));
     TRY(s->upload<EdgeRec>(&s->edge_rec, nullptr, (size_t)n_views * E));
@@ -347,9 +403,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             return fail(HR_EHIP, "scene init: event");
         }
 #undef TRY
-    s->smem_skin = sizeof(float) * 3 * V;
     s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.node_stride);
-    s->smem_geom_bwd = sizeof(float) * (3 * V * 3 + 3 * F);
     *out = s;
     return HR_OK;
 }
@@ -358,7 +412,7 @@ int hr_skin(hr_scene* s, const float* params, float* verts, float* joints, void*
 {
     if (!s || !params || !verts) return fail(HR_EINVAL, "hr_skin: null argument");
     hipStream_t st = (hipStream_t)stream;
-    return launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh, params, verts,
+    return launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh, params, verts,
                   joints);
 }
 
@@ -602,9 +656,13 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
         if (rc) return rc;
     }
     if (after_trace && hipEventRecord(after_trace, st) != hipSuccess) return fail(HR_EHIP, "hr_backward: event");
-    return launch(s, "k_geom_backward", k_geom_backward, dim3(s->n_hands), dim3(256), s->smem_geom_bwd, st, s->mesh,
-                  params, verts, (const float*)s->gacc, (const float*)s->gface, grad_params, grad_verts,
-                  grad_normals);
+    rc = launch(s, "k_normals_bwd", k_normals_bwd, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
+                verts, (const float*)s->gacc, (const float*)s->gface, s->graw, grad_normals);
+    if (!rc)
+        rc = launch(s, "k_skin_bwd", k_skin_bwd, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh, params,
+                    verts, (const float*)s->gacc, (const float*)s->gface, (const float*)s->graw, grad_verts,
+                    s->skin_part, s->skin_count, grad_params);
+    return rc;
 }
 
 int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
@@ -690,7 +748,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
             return fail(HR_EHIP, "hr_iterate: join");
         return HR_OK;
     };
-    int rc = launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh,
+    int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
                     (const float*)q->params, q->verts, (float*)nullptr);
     if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st);
     if (!rc && learned) {
@@ -818,7 +876,7 @@ int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_ho
     s->timing = false;
     // the candidates' results are discarded; the iteration index stays on the host
     auto run = [&](bool adjoint) -> int {
-        int r = launch(s, "k_skin", k_skin, dim3(s->n_hands), dim3(256), s->smem_skin, st, s->mesh,
+        int r = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
                        (const float*)q.params, q.verts, (float*)nullptr);
         if (!r) r = render_impl(s, q.verts, q.albedo, q.background, 0, nullptr, q.image, nullptr, st);
         if (!r && adjoint) {

@@ -6,6 +6,7 @@
 namespace hr {
 
 constexpr int kMaxJoints = 32;
+constexpr int kSkinPart = 12 + 12 * kMaxJoints + 16;   // per-block sums of the skinning backward
 constexpr int kLossChunk = 4096;     // pixels per loss block (never straddles views)
 
 struct MeshDev {
@@ -21,6 +22,13 @@ struct MeshDev {
     const int* edge_faces;     // [E,2]
     const int* vf_off;         // [V+1]
     const int* vf_faces;       // [3F]
+    const float* jt;           // [J,3] J_reg T: rest joints of the template
+    const float* js;           // [J,3,K] J_reg S: joint displacement per shape coefficient
+    const int* jdepth;         // [J] depth in the joint tree (root 0)
+    int max_depth;
+    int infl;                  // skinning weights per vertex (padded with weight 0)
+    const int* widx;           // [V,infl] joint of each weight
+    const float* wval;         // [V,infl]
 };
 
 // Topology of each hand's hierarchy (bounds are refit every iteration).

@@ -89,155 +89,106 @@ __device__ __forceinline__ void matTvec3(const float* A, const float* x, float* 
     for (int i = 0; i < 3; ++i) y[i] = A[i] * x[0] + A[3 + i] * x[1] + A[6 + i] * x[2];
 }
 
-// block-wide sum of `n` per-thread values (n <= 16), result broadcast in `out`
-template <int N>
-__device__ void block_sum(float* vals, float* red /* LDS [4*N] */, float* out)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        float v = wave_sum(vals[i]);
-        if (lane == 0) red[wave * N + i] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < N) {
-        float s = 0.0f;
-        for (int w = 0; w < nw; ++w) s += red[w * N + threadIdx.x];
-        red[16 * N + threadIdx.x] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < N; ++i) out[i] = red[16 * N + i];
-    __syncthreads();
-}
-
-struct SkinShared {
-    float GR[kMaxJoints * 9];
-    float Gt[kMaxJoints * 3];
-    float At[kMaxJoints * 3];
-    float J[kMaxJoints * 3];
-    float Rj[kMaxJoints * 9];
-    Rod rod[kMaxJoints + 1];     // joint rotations and the global rotation
-    float Rp[9];
-    int depth[kMaxJoints];
-    int max_depth;
-    float red[16 * 16 + 16 * 16];
+// Joint transforms of one hand, in LDS (computed by every block that needs
+// them: a few hundred flops against the latency of a second launch).
+struct JointState {
+    Rod rod[kMaxJoints + 1];      // joint rotations and the global rotation
+    float GR[kMaxJoints * 9];     // world rotation of each joint frame
+    float Gt[kMaxJoints * 3];     // world position of each joint
+    float At[kMaxJoints * 3];     // Gt - GR J: translation of the skinning transform
+    float J[kMaxJoints * 3];      // rest joint positions (shaped)
+    float Rp[9];                  // global rotation
 };
 
-// depth of joint j in the tree (root = 0)
-__device__ __forceinline__ int joint_depth(const int* parents, int j)
+// Rodrigues rotations, joint positions J = J_reg T + (J_reg S) beta (the
+// regressor applied to the template and the shape directions once, at scene
+// creation), forward kinematics one tree level at a time.  Needs blockDim.x
+// > J; every thread of the block must call it.
+__device__ void joint_state(const MeshDev& m, const float* __restrict__ p, JointState& js)
 {
-    int d = 0;
-    while (parents[j] >= 0) { j = parents[j]; ++d; }
-    return d;
-}
-
-// shaped vertices into vs (LDS), joints, joint transforms
-__device__ void skin_common(const MeshDev& m, const float* __restrict__ p, float* vs, SkinShared& sh)
-{
-    const int V = m.V, J = m.J, K = m.K;
-    const float* beta = p + 48;
-    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+    const int J = m.J, K = m.K;
+    const int j = threadIdx.x;
+    if (j <= J) rodrigues(j < J ? p + 3 * j : p + 58, js.rod[j]);
+    if (j < J)
         for (int c = 0; c < 3; ++c) {
-            float s = m.v_template[3 * v + c];
-            const float* sd = m.shapedirs + (3 * v + c) * K;
-            for (int k = 0; k < K; ++k) s += sd[k] * beta[k];
-            vs[3 * v + c] = s;
+            float x = m.jt[3 * j + c];
+            const float* sd = m.js + (3 * j + c) * K;
+            for (int k = 0; k < K; ++k) x += sd[k] * p[48 + k];
+            js.J[3 * j + c] = x;
         }
-    }
-    // rotations of all joints and of the global transform, in parallel
-    if ((int)threadIdx.x <= J) {
-        const int j = threadIdx.x;
-        rodrigues(j < J ? p + 3 * j : p + 58, sh.rod[j]);
-        if (j < J) sh.depth[j] = joint_depth(m.parents, j);
-    }
     __syncthreads();
-    // joint regression: one wave per joint, fixed reduction order
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-    for (int j = wave; j < J; j += nwv) {
-        const float* jr = m.j_regressor + (size_t)j * V;
-        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        for (int v = lane; v < V; v += 64) {
-            const float w = jr[v];
-            a0 += w * vs[3 * v]; a1 += w * vs[3 * v + 1]; a2 += w * vs[3 * v + 2];
-        }
-        a0 = wave_sum(a0); a1 = wave_sum(a1); a2 = wave_sum(a2);
-        if (lane == 0) { sh.J[3 * j] = a0; sh.J[3 * j + 1] = a1; sh.J[3 * j + 2] = a2; }
-    }
-    if (threadIdx.x == 0) {
-        int md = 0;
-        for (int j = 0; j < J; ++j) md = max(md, sh.depth[j]);
-        sh.max_depth = md;
-        for (int i = 0; i < 9; ++i) sh.Rp[i] = sh.rod[J].R[i];
-    }
-    for (int j = threadIdx.x; j < J; j += blockDim.x)
-        for (int i = 0; i < 9; ++i) sh.Rj[9 * j + i] = sh.rod[j].R[i];
-    __syncthreads();
-    // forward kinematics, one tree level at a time
-    for (int L = 0; L <= sh.max_depth; ++L) {
-        const int j = threadIdx.x;
-        if (j < J && sh.depth[j] == L) {
+    if (j < 9) js.Rp[j] = js.rod[J].R[j];
+    for (int L = 0; L <= m.max_depth; ++L) {
+        if (j < J && m.jdepth[j] == L) {
             const int par = m.parents[j];
             if (par < 0) {
-                for (int i = 0; i < 9; ++i) sh.GR[9 * j + i] = sh.Rj[9 * j + i];
-                for (int i = 0; i < 3; ++i) sh.Gt[3 * j + i] = sh.J[3 * j + i];
+                for (int i = 0; i < 9; ++i) js.GR[9 * j + i] = js.rod[j].R[i];
+                for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = js.J[3 * j + i];
             } else {
-                matmul3(sh.GR + 9 * par, sh.Rj + 9 * j, sh.GR + 9 * j);
-                float d[3] = {sh.J[3 * j] - sh.J[3 * par], sh.J[3 * j + 1] - sh.J[3 * par + 1],
-                              sh.J[3 * j + 2] - sh.J[3 * par + 2]};
+                matmul3(js.GR + 9 * par, js.rod[j].R, js.GR + 9 * j);
+                float d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
+                              js.J[3 * j + 2] - js.J[3 * par + 2]};
                 float y[3];
-                matvec3(sh.GR + 9 * par, d, y);
-                for (int i = 0; i < 3; ++i) sh.Gt[3 * j + i] = y[i] + sh.Gt[3 * par + i];
+                matvec3(js.GR + 9 * par, d, y);
+                for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = y[i] + js.Gt[3 * par + i];
             }
             float y[3];
-            matvec3(sh.GR + 9 * j, sh.J + 3 * j, y);
-            for (int i = 0; i < 3; ++i) sh.At[3 * j + i] = sh.Gt[3 * j + i] - y[i];
+            matvec3(js.GR + 9 * j, js.J + 3 * j, y);
+            for (int i = 0; i < 3; ++i) js.At[3 * j + i] = js.Gt[3 * j + i] - y[i];
         }
         __syncthreads();
     }
 }
 
-// posed (pre-global-transform) vertex v
-__device__ __forceinline__ void blend_vertex(const MeshDev& m, const float* vs, const SkinShared& sh,
-                                             int v, float* vp)
+// shaped vertex v: T_v + S_v beta
+__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* __restrict__ beta, int v, float* x)
 {
-    vp[0] = vp[1] = vp[2] = 0.0f;
-    const float* W = m.weights + (size_t)v * m.J;
-    const float x[3] = {vs[3 * v], vs[3 * v + 1], vs[3 * v + 2]};
-    for (int j = 0; j < m.J; ++j) {
-        float w = W[j];
-        if (w == 0.0f) continue;
-        float y[3];
-        matvec3(sh.GR + 9 * j, x, y);
-        for (int c = 0; c < 3; ++c) vp[c] += w * (y[c] + sh.At[3 * j + c]);
+    for (int c = 0; c < 3; ++c) {
+        float s = m.v_template[3 * v + c];
+        const float* sd = m.shapedirs + (3 * v + c) * m.K;
+        for (int k = 0; k < m.K; ++k) s += sd[k] * beta[k];
+        x[c] = s;
     }
 }
 
-__global__ void __launch_bounds__(256) k_skin(MeshDev m, const float* __restrict__ params,
+// posed (pre-global-transform) vertex: sum over the vertex's skinning weights
+__device__ __forceinline__ void blend_vertex(const MeshDev& m, const JointState& js, int v, const float* x, float* vp)
+{
+    vp[0] = vp[1] = vp[2] = 0.0f;
+    for (int q = 0; q < m.infl; ++q) {
+        const float w = m.wval[v * m.infl + q];
+        if (w == 0.0f) continue;
+        const int j = m.widx[v * m.infl + q];
+        float y[3];
+        matvec3(js.GR + 9 * j, x, y);
+        for (int c = 0; c < 3; ++c) vp[c] += w * (y[c] + js.At[3 * j + c]);
+    }
+}
+
+// Skinning, grid (vertex blocks, hands).
+__global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict__ params,
                                               float* __restrict__ verts, float* __restrict__ joints)
 {
-    extern __shared__ float dyn[];
-    __shared__ SkinShared sh;
-    const int h = blockIdx.x;
+    __shared__ JointState js;
+    const int h = blockIdx.y;
     const float* p = params + 64 * h;
-    float* vs = dyn;
-    skin_common(m, p, vs, sh);
+    joint_state(m, p, js);
     const float* tau = p + 61;
-    for (int v = threadIdx.x; v < m.V; v += blockDim.x) {
-        float vp[3], y[3];
-        blend_vertex(m, vs, sh, v, vp);
-        matvec3(sh.Rp, vp, y);
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < m.V) {
+        float x[3], vp[3], y[3];
+        shaped_vertex(m, p + 48, v, x);
+        blend_vertex(m, js, v, x, vp);
+        matvec3(js.Rp, vp, y);
         float* o = verts + ((size_t)h * m.V + v) * 3;
         o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
     }
-    if (joints) {
-        for (int j = threadIdx.x; j < m.J; j += blockDim.x) {
-            float y[3];
-            matvec3(sh.Rp, sh.Gt + 3 * j, y);
-            float* o = joints + ((size_t)h * m.J + j) * 3;
-            o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
-        }
+    if (joints && blockIdx.x == 0 && (int)threadIdx.x < m.J) {
+        const int j = threadIdx.x;
+        float y[3];
+        matvec3(js.Rp, js.Gt + 3 * j, y);
+        float* o = joints + ((size_t)h * m.J + j) * 3;
+        o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
     }
 }
 
@@ -1107,222 +1058,244 @@ __device__ __forceinline__ void vertex_grad(const MeshDev& m, const float* gvtx,
     }
 }
 
-__global__ void __launch_bounds__(256) k_geom_backward(MeshDev m, const float* __restrict__ params,
-                                                       const float* __restrict__ verts,
-                                                       const float* __restrict__ gacc,
-                                                       const float* __restrict__ gface,
-                                                       float* __restrict__ grad_params,
-                                                       float* __restrict__ grad_verts,
-                                                       float* __restrict__ grad_normals)
+// Normals backward, part 1 (grid (vertex blocks, hands)): the gradient of the
+// unit normal n = s/|s| (s = sum of the adjacent raw face normals) taken back
+// to s: graw = (gn - (gn . n) n) / |s|.
+__global__ void __launch_bounds__(128) k_normals_bwd(MeshDev m, const float* __restrict__ verts,
+                                                     const float* __restrict__ gacc,
+                                                     const float* __restrict__ gface, float* __restrict__ graw,
+                                                     float* __restrict__ grad_normals)
 {
-    extern __shared__ float dyn[];
-    __shared__ SkinShared sh;
-    __shared__ float gJ[kMaxJoints * 3];
-    __shared__ float gAt[kMaxJoints * 3];
-    __shared__ float gGt[kMaxJoints * 3];
-    __shared__ float gGR[kMaxJoints * 9];
-    __shared__ float gR[kMaxJoints * 9];
-    __shared__ float gmisc[16];
-    const int h = blockIdx.x;
-    const int V = m.V, F = m.F, J = m.J, K = m.K;
-    float* vsh = dyn;              // posed vertices [V*3]
-    float* fn = vsh + 3 * V;       // raw face normals [F*3]
-    float* graw = fn + 3 * F;      // dL/d(raw vertex normal) [V*3]
-    float* gv = graw + 3 * V;      // total dL/dv [V*3]
-    float* vs = vsh;               // shaped vertices [V*3], once the posed ones are no longer needed
-    const float* vh = verts + (size_t)h * V * 3;
-    const float* gvtx = gacc + (size_t)h * V * 6;
-    const float* gf = gface + (size_t)h * F * 18;
-    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
-    __syncthreads();
-    for (int f = threadIdx.x; f < F; f += blockDim.x) {
-        int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
-        float e1[3] = {vsh[3 * b] - vsh[3 * a], vsh[3 * b + 1] - vsh[3 * a + 1], vsh[3 * b + 2] - vsh[3 * a + 2]};
-        float e2[3] = {vsh[3 * c] - vsh[3 * a], vsh[3 * c + 1] - vsh[3 * a + 1], vsh[3 * c + 2] - vsh[3 * a + 2]};
-        fn[3 * f] = e1[1] * e2[2] - e1[2] * e2[1];
-        fn[3 * f + 1] = e1[2] * e2[0] - e1[0] * e2[2];
-        fn[3 * f + 2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const int h = blockIdx.y;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= m.V) return;
+    const float* vh = verts + (size_t)h * m.V * 3;
+    float sv[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+        const int f = m.vf_faces[k];
+        const float* a = vh + 3 * m.faces[3 * f];
+        const float* b = vh + 3 * m.faces[3 * f + 1];
+        const float* c = vh + 3 * m.faces[3 * f + 2];
+        const float e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+        const float e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+        sv[0] += e1[1] * e2[2] - e1[2] * e2[1];
+        sv[1] += e1[2] * e2[0] - e1[0] * e2[2];
+        sv[2] += e1[0] * e2[1] - e1[1] * e2[0];
+    }
+    const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+    const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
+    float gn[3];
+    vertex_grad(m, gacc + (size_t)h * m.V * 6, gface + (size_t)h * m.F * 18, v, 3, gn);
+    if (grad_normals) {
+        float* o = grad_normals + ((size_t)h * m.V + v) * 3;
+        o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
+    }
+    const float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+    float* o = graw + ((size_t)h * m.V + v) * 3;
+    for (int k = 0; k < 3; ++k) o[k] = (gn[k] - d * n[k]) * il;
+}
+
+// Skinning backward, final part (one block, js = the hand's joint state):
+// sums of the vertex blocks' partials, At_j = Gt_j - GR_j J_j, forward
+// kinematics in reverse one tree level at a time (deepest first), Rodrigues
+// backward, joint positions back to beta through J_reg S.
+__device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, const float* part, int n_blocks,
+                                const JointState& js, float* tot, float* __restrict__ gp)
+{
+    __shared__ float gJ[kMaxJoints * 3], gGt[kMaxJoints * 3], gGR[kMaxJoints * 9], gR[kMaxJoints * 9];
+    const int J = m.J, K = m.K;
+    const int n_part = 12 + 12 * J + K;
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) {
+        float t = 0.0f;
+        for (int b = 0; b < n_blocks; ++b) t += part[(size_t)b * kSkinPart + i];
+        tot[i] = t;
     }
     __syncthreads();
-    // unit normal n = s/|s|: dL/ds = (gn - (gn.n) n) / |s|
-    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-        float s[3] = {0.0f, 0.0f, 0.0f};
-        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
-            int f = m.vf_faces[k];
-            s[0] += fn[3 * f]; s[1] += fn[3 * f + 1]; s[2] += fn[3 * f + 2];
-        }
-        float len = sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-        float il = 1.0f / len;
-        float n[3] = {s[0] * il, s[1] * il, s[2] * il};
-        float gn[3];
-        vertex_grad(m, gvtx, gf, v, 3, gn);
-        if (grad_normals) {
-            float* o = grad_normals + ((size_t)h * V + v) * 3;
-            o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
-        }
-        float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
-        for (int k = 0; k < 3; ++k) graw[3 * v + k] = (gn[k] - d * n[k]) * il;
-    }
-    __syncthreads();
-    // face normal f = e1 x e2: dL/de1 = e2 x gf, dL/de2 = gf x e1, gathered per vertex
-    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-        float acc[3];
-        vertex_grad(m, gvtx, gf, v, 0, acc);
-        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
-            int f = m.vf_faces[k];
-            int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
-            float gf[3];
-            for (int q = 0; q < 3; ++q) gf[q] = graw[3 * a + q] + graw[3 * b + q] + graw[3 * c + q];
-            float e1[3] = {vsh[3 * b] - vsh[3 * a], vsh[3 * b + 1] - vsh[3 * a + 1], vsh[3 * b + 2] - vsh[3 * a + 2]};
-            float e2[3] = {vsh[3 * c] - vsh[3 * a], vsh[3 * c + 1] - vsh[3 * a + 1], vsh[3 * c + 2] - vsh[3 * a + 2]};
-            float g1[3] = {e2[1] * gf[2] - e2[2] * gf[1], e2[2] * gf[0] - e2[0] * gf[2], e2[0] * gf[1] - e2[1] * gf[0]};
-            float g2[3] = {gf[1] * e1[2] - gf[2] * e1[1], gf[2] * e1[0] - gf[0] * e1[2], gf[0] * e1[1] - gf[1] * e1[0]};
-            if (v == a) for (int q = 0; q < 3; ++q) acc[q] -= g1[q] + g2[q];
-            else if (v == b) for (int q = 0; q < 3; ++q) acc[q] += g1[q];
-            else for (int q = 0; q < 3; ++q) acc[q] += g2[q];
-        }
-        for (int q = 0; q < 3; ++q) gv[3 * v + q] = acc[q];
-        if (grad_verts) {
-            float* o = grad_verts + ((size_t)h * V + v) * 3;
-            o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2];
-        }
-    }
-    __syncthreads();
-    // ---- skinning backward ----
-    const float* p = params + 64 * h;
-    skin_common(m, p, vs, sh);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-    // global transform v = Rp vp + tau: dL/dRp = sum_v g_v vp_v^T, dL/dtau = sum_v g_v
-    {
-        float part[12];
-        for (int i = 0; i < 12; ++i) part[i] = 0.0f;
-        for (int v = threadIdx.x; v < V; v += blockDim.x) {
-            float vp[3];
-            blend_vertex(m, vs, sh, v, vp);
-            const float* g = gv + 3 * v;
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) part[3 * i + j] += g[i] * vp[j];
-            part[9] += g[0]; part[10] += g[1]; part[11] += g[2];
-        }
-        float out[12];
-        block_sum<12>(part, sh.red, out);
-        if (threadIdx.x < 12) gmisc[threadIdx.x] = out[threadIdx.x];
-    }
-    // per joint (one wave each): dL/dGR_j = sum_v W_vj gvp_v vs_v^T, dL/dAt_j = sum_v W_vj gvp_v
-    for (int j = wave; j < J; j += nwv) {
-        float part[12];
-        for (int i = 0; i < 12; ++i) part[i] = 0.0f;
-        for (int v = lane; v < V; v += 64) {
-            const float w = m.weights[(size_t)v * J + j];
-            if (w == 0.0f) continue;
-            float gvp[3];
-            matTvec3(sh.Rp, gv + 3 * v, gvp);
-            for (int i = 0; i < 3; ++i) {
-                for (int k = 0; k < 3; ++k) part[3 * i + k] += w * gvp[i] * vs[3 * v + k];
-                part[9 + i] += w * gvp[i];
-            }
-        }
-        for (int i = 0; i < 12; ++i) part[i] = wave_sum(part[i]);
-        if (lane == 0) {
-            for (int i = 0; i < 9; ++i) gGR[9 * j + i] = part[i];
-            for (int i = 0; i < 3; ++i) gAt[3 * j + i] = part[9 + i];
-        }
-    }
-    __syncthreads();
-    float* gp = grad_params + 64 * h;
-    // At_j = Gt_j - GR_j J_j (per joint, parallel)
+    // At_j = Gt_j - GR_j J_j
     for (int j = threadIdx.x; j < J; j += blockDim.x) {
+        const float* a = tot + 12 + 12 * j;
         for (int i = 0; i < 3; ++i) {
-            gGt[3 * j + i] = gAt[3 * j + i];
-            for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] -= gAt[3 * j + i] * sh.J[3 * j + k];
+            gGt[3 * j + i] = a[9 + i];
+            for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] = a[3 * i + k] - a[9 + i] * js.J[3 * j + k];
         }
         float y[3];
-        matTvec3(sh.GR + 9 * j, gAt + 3 * j, y);
+        matTvec3(js.GR + 9 * j, a + 9, y);
         for (int i = 0; i < 3; ++i) gJ[3 * j + i] = -y[i];
     }
     __syncthreads();
-    // forward kinematics in reverse, one tree level at a time (deepest first):
-    // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j.  Joints of level L
-    // finish their own terms while their parents (level L-1) pull the
-    // children's contributions.
-    for (int L = sh.max_depth; L >= 0; --L) {
+    // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j: joints of level L finish
+    // their own terms, their parents (level L-1) then pull the children's
+    for (int L = m.max_depth; L >= 0; --L) {
         const int j = threadIdx.x;
-        if (j < J && sh.depth[j] == L) {
+        if (j < J && m.jdepth[j] == L) {
             const int par = m.parents[j];
             if (par < 0) {
                 for (int i = 0; i < 9; ++i) gR[9 * j + i] = gGR[9 * j + i];
                 for (int i = 0; i < 3; ++i) gJ[3 * j + i] += gGt[3 * j + i];
             } else {
-                const float* GRp = sh.GR + 9 * par;
+                const float* GRp = js.GR + 9 * par;
                 float y[3];
                 matTvec3(GRp, gGt + 3 * j, y);
                 for (int i = 0; i < 3; ++i) gJ[3 * j + i] += y[i];
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
-                        float acc = 0.0f;
-                        for (int q = 0; q < 3; ++q) acc += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
-                        gR[9 * j + 3 * i + k] = acc;
+                        float s = 0.0f;
+                        for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
+                        gR[9 * j + 3 * i + k] = s;
                     }
             }
         }
-        const int pj = threadIdx.x - 64;   // a second wave handles the parents
-        if (pj >= 0 && pj < J && sh.depth[pj] == L - 1) {
-            const float* GRp = sh.GR + 9 * pj;
-            for (int c = pj + 1; c < J; ++c) {
-                if (m.parents[c] != pj) continue;
-                const float* Rc = sh.Rj + 9 * c;
-                const float d[3] = {sh.J[3 * c] - sh.J[3 * pj], sh.J[3 * c + 1] - sh.J[3 * pj + 1],
-                                    sh.J[3 * c + 2] - sh.J[3 * pj + 2]};
+        __syncthreads();
+        if (j < J && m.jdepth[j] == L - 1) {
+            const float* GRp = js.GR + 9 * j;
+            for (int c = j + 1; c < J; ++c) {
+                if (m.parents[c] != j) continue;
+                const float* Rc = js.rod[c].R;
+                const float d[3] = {js.J[3 * c] - js.J[3 * j], js.J[3 * c + 1] - js.J[3 * j + 1],
+                                    js.J[3 * c + 2] - js.J[3 * j + 2]};
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
-                        float acc = gGt[3 * c + i] * d[k];
-                        for (int q = 0; q < 3; ++q) acc += gGR[9 * c + 3 * i + q] * Rc[3 * k + q];
-                        gGR[9 * pj + 3 * i + k] += acc;
+                        float s = gGt[3 * c + i] * d[k];
+                        for (int q = 0; q < 3; ++q) s += gGR[9 * c + 3 * i + q] * Rc[3 * k + q];
+                        gGR[9 * j + 3 * i + k] += s;
                     }
                 float y[3];
                 matTvec3(GRp, gGt + 3 * c, y);
                 for (int i = 0; i < 3; ++i) {
-                    gJ[3 * pj + i] -= y[i];
-                    gGt[3 * pj + i] += gGt[3 * c + i];
+                    gJ[3 * j + i] -= y[i];
+                    gGt[3 * j + i] += gGt[3 * c + i];
                 }
             }
         }
         __syncthreads();
     }
-    // axis-angle gradients of the joint rotations and the global rotation (parallel)
-    if ((int)threadIdx.x <= J) {
-        const int j = threadIdx.x;
-        if (j < J) rodrigues_bwd(p + 3 * j, sh.rod[j], gR + 9 * j, gp + 3 * j);
-        else rodrigues_bwd(p + 58, sh.rod[J], gmisc, gp + 58);
+    const int t = threadIdx.x;
+    if (t < J) rodrigues_bwd(p + 3 * t, js.rod[t], gR + 9 * t, gp + 3 * t);
+    if (t == J) rodrigues_bwd(p + 58, js.rod[J], tot, gp + 58);
+    for (int j = J + t; j < 16; j += blockDim.x) gp[3 * j] = gp[3 * j + 1] = gp[3 * j + 2] = 0.0f;
+    if (t < 3) gp[61 + t] = tot[9 + t];
+    // shape: vertex part + joint part (J = J_reg T + (J_reg S) beta)
+    for (int k = t; k < 10; k += blockDim.x) {
+        float s = 0.0f;
+        if (k < K) {
+            s = tot[12 + 12 * J + k];
+            for (int j = 0; j < J; ++j)
+                for (int c = 0; c < 3; ++c) s += m.js[(3 * j + c) * K + k] * gJ[3 * j + c];
+        }
+        gp[48 + k] = s;
     }
-    for (int j = J + threadIdx.x; j < 16; j += blockDim.x) gp[3 * j] = gp[3 * j + 1] = gp[3 * j + 2] = 0.0f;
-    if (threadIdx.x == 0) { gp[61] = gmisc[9]; gp[62] = gmisc[10]; gp[63] = gmisc[11]; }
-    // shaped vertices: dL/dvs_v = sum_j W_vj GR_j^T gvp_v + sum_j Jreg_jv gJ_j; dL/dbeta
-    float part[16];
-    for (int k = 0; k < 16; ++k) part[k] = 0.0f;
-    for (int v = threadIdx.x; v < V; v += blockDim.x) {
-        float gvp[3], g[3] = {0.0f, 0.0f, 0.0f};
-        matTvec3(sh.Rp, gv + 3 * v, gvp);
-        for (int j = 0; j < J; ++j) {
-            const float w = m.weights[(size_t)v * J + j];
-            const float jr = m.j_regressor[(size_t)j * V + v];
-            if (w != 0.0f) {
-                float y[3];
-                matTvec3(sh.GR + 9 * j, gvp, y);
-                for (int c = 0; c < 3; ++c) g[c] += w * y[c];
+}
+
+// Normals backward, part 2, and skinning backward per vertex (grid (vertex
+// blocks, hands)).  The vertex gradient g_v (position slots + the raw face
+// normals f = e1 x e2: dL/de1 = e2 x gf, dL/de2 = gf x e1) is taken through
+// v = Rp vp + tau, vp = sum_j W_vj (GR_j x + At_j), x = T_v + S_v beta; each
+// block writes its sums: dL/dRp (9), dL/dtau (3), per joint dL/dGR_j (9) and
+// dL/dAt_j (3), and sum_v S_v^T sum_j W_vj GR_j^T Rp^T g_v (K).
+__global__ void __launch_bounds__(128) k_skin_bwd(MeshDev m, const float* __restrict__ params,
+                                                  const float* __restrict__ verts, const float* __restrict__ gacc,
+                                                  const float* __restrict__ gface, const float* __restrict__ graw,
+                                                  float* __restrict__ grad_verts, float* part, int* counter,
+                                                  float* __restrict__ grad_params)
+{
+    __shared__ JointState js;
+    __shared__ float acc[kSkinPart];
+    const int h = blockIdx.y;
+    const int J = m.J, K = m.K;
+    const int n_part = 12 + 12 * J + K;
+    const float* p = params + 64 * h;
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) acc[i] = 0.0f;
+    joint_state(m, p, js);
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, vp[3] = {0.0f, 0.0f, 0.0f};
+    float gvp[3] = {0.0f, 0.0f, 0.0f}, gx[3] = {0.0f, 0.0f, 0.0f};
+    if (v < m.V) {
+        const float* vh = verts + (size_t)h * m.V * 3;
+        const float* gr = graw + (size_t)h * m.V * 3;
+        vertex_grad(m, gacc + (size_t)h * m.V * 6, gface + (size_t)h * m.F * 18, v, 0, g);
+        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+            const int f = m.vf_faces[k];
+            const int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
+            float gf[3];
+            for (int q = 0; q < 3; ++q) gf[q] = gr[3 * a + q] + gr[3 * b + q] + gr[3 * c + q];
+            const float e1[3] = {vh[3 * b] - vh[3 * a], vh[3 * b + 1] - vh[3 * a + 1], vh[3 * b + 2] - vh[3 * a + 2]};
+            const float e2[3] = {vh[3 * c] - vh[3 * a], vh[3 * c + 1] - vh[3 * a + 1], vh[3 * c + 2] - vh[3 * a + 2]};
+            const float g1[3] = {e2[1] * gf[2] - e2[2] * gf[1], e2[2] * gf[0] - e2[0] * gf[2],
+                                 e2[0] * gf[1] - e2[1] * gf[0]};
+            const float g2[3] = {gf[1] * e1[2] - gf[2] * e1[1], gf[2] * e1[0] - gf[0] * e1[2],
+                                 gf[0] * e1[1] - gf[1] * e1[0]};
+            if (v == a) for (int q = 0; q < 3; ++q) g[q] -= g1[q] + g2[q];
+            else if (v == b) for (int q = 0; q < 3; ++q) g[q] += g1[q];
+            else for (int q = 0; q < 3; ++q) g[q] += g2[q];
+        }
+        if (grad_verts) {
+            float* o = grad_verts + ((size_t)h * m.V + v) * 3;
+            o[0] = g[0]; o[1] = g[1]; o[2] = g[2];
+        }
+        shaped_vertex(m, p + 48, v, x);
+        blend_vertex(m, js, v, x, vp);
+        matTvec3(js.Rp, g, gvp);
+        for (int q = 0; q < m.infl; ++q) {
+            const float w = m.wval[v * m.infl + q];
+            if (w == 0.0f) continue;
+            const int j = m.widx[v * m.infl + q];
+            float y[3];
+            matTvec3(js.GR + 9 * j, gvp, y);
+            for (int c = 0; c < 3; ++c) gx[c] += w * y[c];
+        }
+    }
+    // block sums: wave reductions first (every lane of a wave adds to the same
+    // addresses), then one LDS add per wave
+    const int lane = threadIdx.x & 63;
+    {
+        float t[12];
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) t[3 * i + k] = g[i] * vp[k];
+        for (int i = 0; i < 3; ++i) t[9 + i] = g[i];
+        for (int i = 0; i < 12; ++i) {
+            const float r = wave_sum(t[i]);
+            if (lane == 0) atomicAdd(acc + i, r);
+        }
+        float* ab = acc + 12 + 12 * J;
+        for (int k = 0; k < K; ++k) {
+            float u = 0.0f;
+            if (v < m.V)
+                u = m.shapedirs[(3 * v) * K + k] * gx[0] + m.shapedirs[(3 * v + 1) * K + k] * gx[1]
+                    + m.shapedirs[(3 * v + 2) * K + k] * gx[2];
+            const float r = wave_sum(u);
+            if (lane == 0) atomicAdd(ab + k, r);
+        }
+    }
+    for (int j = 0; j < J; ++j) {
+        float w = 0.0f;
+        if (v < m.V)
+            for (int q = 0; q < m.infl; ++q)
+                if (m.widx[v * m.infl + q] == j) w += m.wval[v * m.infl + q];
+        if (!__any(w != 0.0f)) continue;    // no vertex of this wave is bound to joint j
+        float* aj = acc + 12 + 12 * j;
+        for (int i = 0; i < 3; ++i) {
+            const float wg = w * gvp[i];
+            for (int k = 0; k < 3; ++k) {
+                const float r = wave_sum(wg * x[k]);
+                if (lane == 0) atomicAdd(aj + 3 * i + k, r);
             }
-            if (jr != 0.0f)
-                for (int c = 0; c < 3; ++c) g[c] += jr * gJ[3 * j + c];
-        }
-        for (int c = 0; c < 3; ++c) {
-            const float* sd = m.shapedirs + (3 * v + c) * K;
-            for (int k = 0; k < K; ++k) part[k] += sd[k] * g[c];
+            const float r = wave_sum(wg);
+            if (lane == 0) atomicAdd(aj + 9 + i, r);
         }
     }
-    float out[16];
-    block_sum<16>(part, sh.red, out);
-    if (threadIdx.x < K) gp[48 + threadIdx.x] = out[threadIdx.x];
-    if (threadIdx.x >= K && threadIdx.x < 10) gp[48 + threadIdx.x] = 0.0f;
+    __syncthreads();
+    float* out = part + ((size_t)h * gridDim.x + blockIdx.x) * kSkinPart;
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) out[i] = acc[i];
+    // the last block of the hand finishes (partials of all its blocks are written)
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(counter + h, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (threadIdx.x == 0) counter[h] = 0;
+    skin_bwd_finish(m, p, part + (size_t)h * gridDim.x * kSkinPart, gridDim.x, js, acc, grad_params + 64 * h);
 }
 
 // ===========================================================================
