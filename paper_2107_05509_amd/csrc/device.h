@@ -285,6 +285,94 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
     }
 }
 
+// Closest hits of the rays of one wave by a single traversal order: the wave
+// visits a node when any active lane's ray enters the node's box before that
+// lane's best hit so far (the union of the per-ray traversals), and every lane
+// keeps its own closest (t, face id).  A lane therefore tests every triangle
+// its own traversal would test (plus possibly others, which cannot beat its
+// closest hit), so each result equals the per-ray traversal's and a brute-force
+// loop's.  Meant for coherent rays (all samples of a few adjacent pixels):
+// the node and triangle addresses are wave-uniform and the stack is one per
+// wave.  Every lane of the wave must call it; inactive lanes take no part.
+// `wstack`: this wave's LDS stack (kMaxStack ints).
+template <bool COUNT = false>
+__device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
+                                           const Ray& r, bool active, int* wstack, Hit& h,
+                                           TraceCount* cnt = nullptr)
+{
+    h.face = -1;
+    h.slot = 0;
+    h.t = 0.0f;
+    float tb = active ? __builtin_inff() : -__builtin_inff();   // inactive: every box test fails
+    int fb = 0x7fffffff;
+    int sp = 0;
+    int node = 0;
+    while (true) {
+        if (COUNT && active) cnt->nodes++;
+        const Node& n = nodes[node];
+        float4 q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
+        float4 q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
+        float4 q2 = *reinterpret_cast<const float4*>(&n.lo1[2]);
+        int4 q3 = *reinterpret_cast<const int4*>(&n.child[0]);
+        float lo0[3] = {q0.x, q0.y, q0.z}, hi0[3] = {q0.w, q1.x, q1.y};
+        float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
+        const int c0 = __builtin_amdgcn_readfirstlane(q3.x), c1 = __builtin_amdgcn_readfirstlane(q3.y);
+        float t0, t1;
+        const bool h0 = slab(r, lo0, hi0, tb, t0);
+        const bool h1 = slab(r, lo1, hi1, tb, t1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int code = c == 0 ? c0 : c1;
+            const bool hit = c == 0 ? h0 : h1;
+            if (code < 0 && __any(hit)) {
+                const int lc = ~code;
+                const int start = lc >> 3, ncnt = lc & 7;
+                if (COUNT && hit) cnt->tris += ncnt;
+                for (int k = 0; k < ncnt; ++k) {
+                    const Tri& tr = tris[start + k];
+                    float4 p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
+                    float4 p1 = *reinterpret_cast<const float4*>(&tr.v[4]);
+                    float4 p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+                    if (!hit) continue;
+                    float v0[3] = {p0.x, p0.y, p0.z};
+                    float v1[3] = {p0.w, p1.x, p1.y};
+                    float v2[3] = {p1.z, p1.w, p2.x};
+                    const int face = __float_as_int(p2.y);
+                    float t, U, V, W, det;
+                    if (watertight(r, v0, v1, v2, t, U, V, W, det)) {
+                        if (t < tb || (t == tb && face < fb)) {
+                            tb = t; fb = face;
+                            h.face = face;
+                            h.slot = start + k;
+                            h.t = t;
+                        }
+                    }
+                }
+            }
+        }
+        const bool w0 = h0 && c0 >= 0 && t0 <= tb;
+        const bool w1 = h1 && c1 >= 0 && t1 <= tb;
+        const bool go0 = __any(w0), go1 = __any(w1);
+        if (go0 && go1) {
+            // nearer child first, by majority of the lanes that enter both
+            const int n01 = __popcll(__ballot(w0 && w1 && t0 <= t1));
+            const int n10 = __popcll(__ballot(w0 && w1 && t1 < t0));
+            const int nearc = n01 >= n10 ? c0 : c1;
+            const int farc = n01 >= n10 ? c1 : c0;
+            if (sp < kMaxStack) { wstack[sp] = farc; ++sp; }
+            node = nearc;
+        } else if (go0) {
+            node = c0;
+        } else if (go1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+        }
+    }
+}
+
 // float64 direction of the ray through screen point (X, Y)
 __device__ __forceinline__ void ray_dir64(const ViewDev& c, double X, double Y, double* d)
 {

@@ -380,7 +380,7 @@ template <bool COUNT>
 __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
-    int* stk = stack + threadIdx.x;
+    int* wst = stack + kMaxStack * (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
     const int s_lane = lane & (G - 1);
@@ -407,14 +407,19 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
         int misses = 0;
         for (int r = 0; r < a.ts.rounds; ++r) {
             const int s = s_lane + 64 * r;
-            if (pix_ok && s < a.spp) {
+            const bool act = pix_ok && s < a.spp;
+            float u = 0.0f, v = 0.0f;
+            if (act) {
                 const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
                 const uint64_t wd = pick(rr, s & 3);
-                const float u = u24_lo(wd), v = u24_hi(wd);
-                Ray ray;
-                ray_screen(c, (float)px + u, (float)py + v, ray);
-                Hit h;
-                trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+                u = u24_lo(wd);
+                v = u24_hi(wd);
+            }
+            Ray ray;
+            ray_screen(c, (float)px + u, (float)py + v, ray);
+            Hit h;
+            trace_wave<COUNT>(nodes, tris, ray, act, wst, h, &tc);
+            if (act) {
                 if (COUNT) ++n_rays;
                 if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
                 if (h.face >= 0) {
@@ -549,7 +554,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     float* patch = patch_base + 3 * kPatch * kPatch * (threadIdx.x >> 6);
-    int* stk = stack + threadIdx.x;
+    int* wst = stack + kMaxStack * (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
     const int s_lane = lane & (G - 1);
@@ -594,14 +599,19 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             float twt[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             int tmask = 0;
             int fi0 = 0x7fffffff, fi1 = -1, fj0 = 0x7fffffff, fj1 = -1;   // footprint rows / columns
-            if (live && s < a.spp) {
+            const bool act = live && s < a.spp;
+            float u = 0.0f, v = 0.0f;
+            if (act) {
                 const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
                 const uint64_t wd = pick(rr, s & 3);
-                const float u = u24_lo(wd), v = u24_hi(wd);
-                Ray ray;
-                ray_screen(c, (float)px + u, (float)py + v, ray);
-                Hit h;
-                trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+                u = u24_lo(wd);
+                v = u24_hi(wd);
+            }
+            Ray ray;
+            ray_screen(c, (float)px + u, (float)py + v, ray);
+            Hit h;
+            trace_wave<COUNT>(nodes, tris, ray, act, wst, h, &tc);
+            if (act) {
                 if (COUNT) ++n_rays;
                 if (h.face >= 0) {
                     if (COUNT) ++n_hit;
@@ -1011,9 +1021,10 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
 template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_render(RenderArgs a, EdgeArgs e, int n_setup)
 {
-    __shared__ int stack[kMaxStack * kThreads];
+    __shared__ unsigned long long part[kThreads];
+    __shared__ int stack[kMaxStack * (kThreads / 64)];
     if ((int)blockIdx.x < n_setup) {
-        edges_setup_view(e, blockIdx.x, reinterpret_cast<unsigned long long*>(stack));
+        edges_setup_view(e, blockIdx.x, part);
         return;
     }
     render_tiles<COUNT>(a, (int)blockIdx.x - n_setup, (int)gridDim.x - n_setup, stack);
