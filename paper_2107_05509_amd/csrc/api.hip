@@ -85,6 +85,8 @@ struct hr_scene {
     float* gacc = nullptr;        // [hands,V,6] vertex gradient slots (edge term)
     float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
     float* graw = nullptr;        // [hands,V,3] dL/d(raw vertex normal) (geometry backward)
+    EdgeSample* samples = nullptr;   // traced edge samples (first part of the boundary term)
+    long long sample_cap = 0;
     float* skin_part = nullptr;   // [hands,skin_blocks,kSkinPart] per-block sums of the skinning backward
     int skin_blocks = 0;
     int* skin_count = nullptr;    // [hands] finished blocks of the skinning backward (reset by the last)
@@ -376,6 +378,12 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_hands * V * 6));
     TRY(s->upload<float>(&s->gface, nullptr, (size_t)n_hands * F * 18));
     TRY(s->upload<float>(&s->graw, nullptr, (size_t)n_hands * V * 3));
+    {   // stored edge samples: generous for hand silhouettes; samples beyond are traced in place
+        long long cap = 65536;
+        for (int v = 0; v < n_views; ++v) cap += 8ll * (cams[v].W + cams[v].H);
+        s->sample_cap = cap;
+        TRY(s->upload<EdgeSample>(&s->samples, nullptr, (size_t)cap));
+    }
     s->skin_blocks = (V + 127) / 128;
     TRY(s->upload<float>(&s->skin_part, nullptr, (size_t)n_hands * s->skin_blocks * kSkinPart));
     TRY(s->upload<int>(&s->skin_count, nullptr, (size_t)n_hands));
@@ -460,9 +468,9 @@ static Shading shading_of(const hr_config& c)
 }
 
 static int render_impl(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
-                       const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st)
+                       const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st, bool prepared = false)
 {
-    int rc = prepare(s, verts, st);
+    int rc = prepared ? HR_OK : prepare(s, verts, st);
     if (rc) return rc;
     const long long P = s->n_pixels;
     rc = launch(s, "k_copy", k_copy, dim3((unsigned)std::min<long long>(4096, (3 * P + 255) / 256)), dim3(256), 0,
@@ -481,11 +489,31 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
-    // the silhouette tables of these vertices are built alongside
+    // the silhouette tables of these vertices are built alongside (unless the
+    // caller builds them beside the render: prepared)
     const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
-    const dim3 grid(s->n_views + s->render_blocks);
-    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, s->n_views);
-    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, s->n_views);
+    const int n_setup = prepared ? 0 : s->n_views;
+    const dim3 grid(n_setup + s->render_blocks);
+    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, n_setup);
+    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, n_setup);
+}
+
+// Edge samples, first part: silhouette tables (unless done), learned sampling
+// weights, budget prefix, tracing of every stored sample.
+static int edge_trace_impl(hr_scene* s, const float* verts, const float* albedo, const float* background,
+                           uint32_t iter, const int* iter_dev, bool setup, hipStream_t st)
+{
+    EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
+    int rc = HR_OK;
+    if (setup) rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kThreads), 0, st, e);
+    if (!rc && s->prop_kind == HR_PROPOSAL_LEARNED)
+        rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, st, e, s->prop);
+    if (!rc)
+        rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
+                    s->n_views, s->edge_prefix);
+    if (rc) return rc;
+    if (s->counting) return launch(s, "k_edge_trace", k_edge_trace<true>, dim3(kEdgeBlocks), dim3(kThreads), 0, st, e);
+    return launch(s, "k_edge_trace", k_edge_trace<false>, dim3(kEdgeBlocks), dim3(kThreads), 0, st, e);
 }
 
 int hr_render(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
@@ -505,6 +533,7 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
     a.stat_a = nullptr; a.stat_dc = nullptr;
+    a.samples = s->samples; a.sample_cap = s->sample_cap;
     a.counts = s->counts + 8;
     a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
     a.delta = s->cfg.edge_delta; a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed;
@@ -601,7 +630,7 @@ static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
 static int backward_impl(hr_scene* s, const float* params, const float* verts, const float* albedo,
                          const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
                          uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
-                         float* grad_normals, hipStream_t st, bool proposal_done = false,
+                         float* grad_normals, hipStream_t st, bool edges_traced = false,
                          hipEvent_t after_trace = nullptr)
 {
     int rc;
@@ -617,24 +646,16 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
     int n_edge = 0, n_adj = 0;
     if (flags & HR_GRAD_EDGES) {
-        if (!(flags & HR_REUSE_GEOMETRY)) {
-            rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kThreads), 0, st, e);
+        // first part of the edge samples (tracing; learned sampling weights
+        // replace the length weights of the CDF), unless the caller ran it
+        if (!edges_traced) {
+            rc = edge_trace_impl(s, verts, albedo, background, iter, iter_dev, !(flags & HR_REUSE_GEOMETRY), st);
             if (rc) return rc;
         }
-        if (s->prop_kind == HR_PROPOSAL_LEARNED) {
-            // learned sampling weights replace the length weights of the CDF;
-            // the samples report per-edge statistics for training
-            if (!proposal_done) {
-                rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, st, e,
-                            s->prop);
-                if (rc) return rc;
-            }
+        if (s->prop_kind == HR_PROPOSAL_LEARNED) {   // per-edge records for training
             e.stat_a = s->prop.stat_a;
             e.stat_dc = s->prop.stat_dc;
         }
-        rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
-                    s->n_views, s->edge_prefix);
-        if (rc) return rc;
         n_edge = kEdgeBlocks;
     }
     AdjointArgs a;
@@ -750,23 +771,21 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     };
     int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
                     (const float*)q->params, q->verts, (float*)nullptr);
-    if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st);
-    if (!rc && learned) {
-        // proposal pass (needs the silhouette tables of the render) beside the loss
-        const EdgeArgs e = edge_args(s, q->verts, q->albedo, q->background, nullptr, 0, it);
-        rc = fork(s->ev[0]);
-        if (!rc)
-            rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, s->side, e,
-                        s->prop);
-    }
+    if (!rc) rc = prepare(s, q->verts, st);
+    // edge samples, first part (silhouette tables, learned weights, tracing:
+    // independent of the image gradient) beside the render and the loss
+    const bool edges = (flags & HR_GRAD_EDGES) != 0;
+    if (!rc && edges) rc = fork(s->ev[0]);
+    if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, true, s->side);
+    if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true);
     if (!rc) rc = loss_impl(s, q->image, q->target, q->mask, q->loss, q->dimage, st);
-    if (!rc && learned) rc = join(s->ev[1]);
+    if (!rc && edges) rc = join(s->ev[1]);
     // training (needs the records of the edge samples) beside the geometry
     // backward and the parameter step
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st, learned, train ? s->ev[2] : nullptr);
+                           nullptr, st, edges, train ? s->ev[2] : nullptr);
     if (!rc && train && hipStreamWaitEvent(s->side, s->ev[2], 0) != hipSuccess)
         rc = fail(HR_EHIP, "hr_iterate: fork");
     if (!rc && train) rc = proposal_train_impl(s, s->side);

@@ -236,7 +236,8 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
         float t0, t1;
         bool h0 = slab(r, lo0, hi0, tb, t0);
         bool h1 = slab(r, lo1, hi1, tb, t1);
-        // leaves are tested right away
+        // leaves are tested right away; all triangles of a leaf are fetched
+        // before the first test (one memory latency per leaf, not per triangle)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             int code = c == 0 ? c0 : c1;
@@ -245,15 +246,22 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
                 int lc = ~code;
                 int start = lc >> 3, ncnt = lc & 7;
                 if (COUNT) cnt->tris += ncnt;
-                for (int k = 0; k < ncnt; ++k) {
-                    const Tri& tr = tris[start + k];
-                    float4 p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
-                    float4 p1 = *reinterpret_cast<const float4*>(&tr.v[4]);
-                    float4 p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
-                    float v0[3] = {p0.x, p0.y, p0.z};
-                    float v1[3] = {p0.w, p1.x, p1.y};
-                    float v2[3] = {p1.z, p1.w, p2.x};
-                    int face = __float_as_int(p2.y);
+                float4 P[kLeafMax][3];
+#pragma unroll
+                for (int k = 0; k < kLeafMax; ++k)
+                    if (k < ncnt) {
+                        const Tri& tr = tris[start + k];
+                        P[k][0] = *reinterpret_cast<const float4*>(&tr.v[0]);
+                        P[k][1] = *reinterpret_cast<const float4*>(&tr.v[4]);
+                        P[k][2] = *reinterpret_cast<const float4*>(&tr.v[8]);
+                    }
+#pragma unroll
+                for (int k = 0; k < kLeafMax; ++k) {
+                    if (k >= ncnt) break;
+                    float v0[3] = {P[k][0].x, P[k][0].y, P[k][0].z};
+                    float v1[3] = {P[k][0].w, P[k][1].x, P[k][1].y};
+                    float v2[3] = {P[k][1].z, P[k][1].w, P[k][2].x};
+                    int face = __float_as_int(P[k][2].y);
                     float t, U, V, W, det;
                     if (watertight(r, v0, v1, v2, t, U, V, W, det)) {
                         if (t < tb || (t == tb && face < fb)) {

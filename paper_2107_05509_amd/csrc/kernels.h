@@ -108,6 +108,15 @@ struct LossArgs {
     int n_hands;
 };
 
+// one stored edge sample (see edge_samples)
+struct alignas(16) EdgeSample {
+    int vi, e;                 // view and edge; vi < 0: empty stratum
+    long long pg;              // packed pixel owning the sample point
+    float t, wgt;              // position along the edge, weight factor
+    float dc[3];               // c(x - delta n) - c(x + delta n)
+    float pad;
+};
+
 struct EdgeArgs {
     MeshDev m;
     const ViewDev* views;
@@ -129,6 +138,8 @@ struct EdgeArgs {
     float* gacc;
     float* stat_a;             // [n_views,E] nullable: sum of |sample contribution| per edge
     float* stat_dc;            // [n_views,E,4] nullable: sum of |c- - c+| per channel, sample count
+    EdgeSample* samples;       // [sample_cap] traced samples
+    long long sample_cap;
     unsigned long long* counts;
     int n_nodes, tex_h, tex_w;
     float delta;

@@ -901,107 +901,201 @@ __global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict
     if (threadIdx.x == blockDim.x - 1) prefix[n_views] = part[threadIdx.x];
 }
 
-// One edge sample per lane pair: the even lane traces the ray at x + delta n,
-// the odd lane the ray at x - delta n.  Consecutive global sample indices are
-// consecutive strata of one view's CDF, so the lanes of a wave work on
-// neighbouring edges.
-// Edge samples of all views; block `bid` of `nb`.
+// Geometry of edge sample kg (global index over the views' budgets): the
+// view, the stratum of the view's integer CDF, the chosen edge and point, the
+// unit screen normal, the side point of this lane (even lane x + delta n, odd
+// lane x - delta n), the owning pixel and the weight factor
+// len * (stratum width) / wq (stratum probability over point density).
+struct EdgePoint {
+    int vi, e;
+    bool valid;          // false: empty stratum (no sample)
+    float t, nhx, nhy, xs, ys, wgt;
+    long long pg;
+};
+
+__device__ __forceinline__ void edge_point(const EdgeArgs& a, long long kg, uint64_t iter, int side, EdgePoint& P)
+{
+    const int E = a.m.E;
+    // view of global sample kg: last v with prefix[v] <= kg
+    int vlo = 0, vhi = a.n_views - 1;
+    while (vlo < vhi) {
+        const int mid = (vlo + vhi + 1) >> 1;
+        if (a.prefix[mid] <= kg) vlo = mid; else vhi = mid - 1;
+    }
+    const int vi = vlo;
+    P.vi = vi;
+    const long long k = kg - a.prefix[vi];
+    const long long M = a.budget[vi];
+    const unsigned long long T = a.total[vi];
+    const ViewDev& c = a.views[vi];
+    const EdgeRec* rec = a.rec + (size_t)vi * E;
+    const unsigned long long* cdf = a.cdf + (size_t)vi * E;
+    const uint64_t c2 = (uint64_t)c.sid | (kDomainEdge << 32);
+    // floor(k T / M) = k q + floor(k r / M) with q = T / M, r = T % M (k r < M^2 fits 64 bits)
+    const unsigned long long um = (unsigned long long)M, q = T / um, rm = T % um;
+    const unsigned long long uk = (unsigned long long)k;
+    const unsigned long long lo = uk * q + (uk * rm) / um;
+    const unsigned long long hi = (uk + 1) * q + ((uk + 1) * rm) / um;
+    const unsigned long long width = hi - lo;
+    P.valid = width != 0;
+    if (!P.valid) return;   // same for both lanes of the pair
+    const U64x4 r = philox4x64(uk, 0, c2, iter, a.seed, 0);
+    const unsigned long long target = lo + __umul64hi(r.x[0], width);
+    int elo = 0, ehi = E - 1;   // first e with cdf[e] > target
+    while (elo < ehi) {
+        int mid = (elo + ehi) >> 1;
+        if (cdf[mid] > target) ehi = mid; else elo = mid + 1;
+    }
+    const int e = elo;
+    P.e = e;
+    const EdgeRec qe = rec[e];
+    const float u = u24_hi(r.x[1]);
+    const float t = qe.t0 + u * (qe.t1 - qe.t0);
+    const float dx = qe.bx - qe.ax, dy = qe.by - qe.ay;
+    const float x = qe.ax + t * dx;
+    const float y = qe.ay + t * dy;
+    const float len = sqrtf(dx * dx + dy * dy);
+    P.t = t;
+    P.nhx = dy / len;
+    P.nhy = -dx / len;
+    P.xs = side == 0 ? x + a.delta * P.nhx : x - a.delta * P.nhx;
+    P.ys = side == 0 ? y + a.delta * P.nhy : y - a.delta * P.nhy;
+    int px = (int)floorf(x), py = (int)floorf(y);
+    px = min(max(px, 0), c.W - 1);
+    py = min(max(py, 0), c.H - 1);
+    P.pg = c.pix0 + (long long)py * c.W + px;
+    // weight: (stratum probability width/T) / (density (wq_e/T)/len per unit length)
+    const float ell = len * (qe.t1 - qe.t0);
+    P.wgt = ell * (float)width / (float)qe.wq;
+}
+
+// Closest hit and colour of this lane's side point of sample P.
 template <bool COUNT>
-__device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack)
+__device__ __forceinline__ void edge_side_colour(const EdgeArgs& a, const EdgePoint& P, int* stk, int* wst,
+                                                 TraceCount& tc, unsigned long long& n_rays,
+                                                 unsigned long long& n_hit, float col[3])
+{
+    const ViewDev& c = a.views[P.vi];
+    const int hand = c.hand;
+    const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
+    const Tri* tris = a.tris + (size_t)hand * a.m.F;
+    const float* normals = a.normals + (size_t)hand * a.m.V * 3;
+    const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
+    const float bg[3] = {a.background[3 * P.pg], a.background[3 * P.pg + 1], a.background[3 * P.pg + 2]};
+    Ray ray;
+    Hit h;
+    ray_screen(c, P.xs, P.ys, ray);
+    // consecutive samples lie on neighbouring edges of one view: the wave
+    // traverses together unless its lanes look at different hands
+    if (__all(hand == __builtin_amdgcn_readfirstlane(hand)))
+        trace_wave<COUNT>(nodes, tris, ray, true, wst, h, &tc);
+    else
+        trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+    if (COUNT) { ++n_rays; n_hit += h.face >= 0; }
+    shade_or_bg(h, tris, c, P.xs, P.ys, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, col);
+}
+
+// Boundary contribution of one sample: pixel gradient g, colour step
+// dc = c(x - delta n) - c(x + delta n); statistics for the proposal; the
+// vertex-gradient atomics.
+__device__ __forceinline__ void edge_contribution(const EdgeArgs& a, int vi, int e, float t, float wgt,
+                                                  long long pg, const float dc[3])
+{
+    const int E = a.m.E;
+    const float g[3] = {a.dimage[3 * pg], a.dimage[3 * pg + 1], a.dimage[3 * pg + 2]};
+    if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) return;
+    float* dcs = a.stat_dc ? a.stat_dc + ((size_t)vi * E + e) * 4 : nullptr;
+    if (dcs) {   // colour-jump statistics of the edge (proposal features)
+        unsafeAtomicAdd(dcs + 0, fabsf(dc[0]));
+        unsafeAtomicAdd(dcs + 1, fabsf(dc[1]));
+        unsafeAtomicAdd(dcs + 2, fabsf(dc[2]));
+        unsafeAtomicAdd(dcs + 3, 1.0f);
+    }
+    const float jump = g[0] * dc[0] + g[1] * dc[1] + g[2] * dc[2];
+    if (jump == 0.0f) return;
+    const float sc = jump * wgt;
+    if (a.stat_a) unsafeAtomicAdd(a.stat_a + (size_t)vi * E + e, fabsf(sc));
+    const ViewDev& c = a.views[vi];
+    const EdgeRec qe = a.rec[(size_t)vi * E + e];
+    const float dx = qe.bx - qe.ax, dy = qe.by - qe.ay;
+    const float len = sqrtf(dx * dx + dy * dy);
+    const float nhx = dy / len, nhy = -dx / len;
+    const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
+    const float* vh = a.verts + (size_t)c.hand * a.m.V * 3;
+    float* gout = a.gacc + (size_t)c.hand * a.m.V * 6;
+    float Ja[2][3], Jb[2][3];
+    proj_jacobian(c, vh + 3 * va, Ja);
+    proj_jacobian(c, vh + 3 * vb, Jb);
+    const float sa = (1.0f - t) * sc, sb = t * sc;
+    for (int k3 = 0; k3 < 3; ++k3) {
+        unsafeAtomicAdd(gout + 6 * va + k3, sa * (Ja[0][k3] * nhx + Ja[1][k3] * nhy));
+        unsafeAtomicAdd(gout + 6 * vb + k3, sb * (Jb[0][k3] * nhx + Jb[1][k3] * nhy));
+    }
+}
+
+// Edge samples, one per lane pair (the even lane traces x + delta n, the odd
+// lane x - delta n; consecutive global indices are consecutive strata of one
+// view's CDF, so a wave works on neighbouring edges).  Block `bid` of `nb`.
+//   TRACE: samples kg < min(total, cap): trace and shade both side points
+//          (independent of the image gradient) and store the sample record;
+//   WEIGH: samples kg < min(total, cap) from their records, the samples
+//          beyond the capacity traced in place; contributions added.
+enum EdgeMode { kEdgeTrace = 0, kEdgeWeigh = 1 };
+
+template <bool COUNT, int MODE>
+__device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int* wstack)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* stk = stack + threadIdx.x;
+    int* wst = wstack + kMaxStack * (threadIdx.x >> 6);
     const long long total = a.prefix[a.n_views];
+    const long long stored = min(total, a.sample_cap);
     const int side = threadIdx.x & 1;
-    const int E = a.m.E;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
     const long long npairs = ((long long)nb * kThreads) >> 1;
-    for (long long kg = ((long long)bid * kThreads + threadIdx.x) >> 1; kg < total; kg += npairs) {
-        // view of global sample kg: last v with prefix[v] <= kg
-        int vlo = 0, vhi = a.n_views - 1;
-        while (vlo < vhi) {
-            const int mid = (vlo + vhi + 1) >> 1;
-            if (a.prefix[mid] <= kg) vlo = mid; else vhi = mid - 1;
+    const long long first = ((long long)bid * kThreads + threadIdx.x) >> 1;
+    if (MODE == kEdgeTrace) {
+        for (long long kg = first; kg < stored; kg += npairs) {
+            EdgePoint P;
+            edge_point(a, kg, iter, side, P);
+            EdgeSample& out = a.samples[kg];
+            if (!P.valid) {
+                if (side == 0) out.vi = -1;
+                continue;   // same for both lanes of the pair
+            }
+            float col[3];
+            edge_side_colour<COUNT>(a, P, stk, wst, tc, n_rays, n_hit, col);
+            const float o0 = __shfl_xor(col[0], 1), o1 = __shfl_xor(col[1], 1), o2 = __shfl_xor(col[2], 1);
+            if (side != 0) continue;
+            out.vi = P.vi;
+            out.e = P.e;
+            out.pg = P.pg;
+            out.t = P.t;
+            out.wgt = P.wgt;
+            out.dc[0] = o0 - col[0];   // c(x - delta n) - c(x + delta n)
+            out.dc[1] = o1 - col[1];
+            out.dc[2] = o2 - col[2];
         }
-        const int vi = vlo;
-        const long long k = kg - a.prefix[vi];
-        const long long M = a.budget[vi];
-        const unsigned long long T = a.total[vi];
-        const ViewDev& c = a.views[vi];
-        const EdgeRec* rec = a.rec + (size_t)vi * E;
-        const unsigned long long* cdf = a.cdf + (size_t)vi * E;
-        const int hand = c.hand;
-        const Node* nodes = a.nodes + (size_t)hand * a.n_nodes;
-        const Tri* tris = a.tris + (size_t)hand * a.m.F;
-        const float* normals = a.normals + (size_t)hand * a.m.V * 3;
-        const float* tex = a.albedo + (size_t)hand * a.tex_h * a.tex_w * 3;
-        const uint64_t c2 = (uint64_t)c.sid | (kDomainEdge << 32);
-        // floor(k T / M) = k q + floor(k r / M) with q = T / M, r = T % M (k r < M^2 fits 64 bits)
-        const unsigned long long um = (unsigned long long)M, q = T / um, rm = T % um;
-        const unsigned long long uk = (unsigned long long)k;
-        const unsigned long long lo = uk * q + (uk * rm) / um;
-        const unsigned long long hi = (uk + 1) * q + ((uk + 1) * rm) / um;
-        const unsigned long long width = hi - lo;
-        if (width == 0) continue;   // same for both lanes of the pair
-        const U64x4 r = philox4x64(uk, 0, c2, iter, a.seed, 0);
-        const unsigned long long target = lo + __umul64hi(r.x[0], width);
-        int elo = 0, ehi = E - 1;   // first e with cdf[e] > target
-        while (elo < ehi) {
-            int mid = (elo + ehi) >> 1;
-            if (cdf[mid] > target) ehi = mid; else elo = mid + 1;
+    } else {
+        for (long long kg = first; kg < stored; kg += npairs) {
+            if (side != 0) continue;
+            const EdgeSample rs = a.samples[kg];
+            if (rs.vi < 0) continue;
+            edge_contribution(a, rs.vi, rs.e, rs.t, rs.wgt, rs.pg, rs.dc);
         }
-        const int e = elo;
-        const EdgeRec qe = rec[e];
-        const float u = u24_hi(r.x[1]);
-        const float t = qe.t0 + u * (qe.t1 - qe.t0);
-        const float dx = qe.bx - qe.ax, dy = qe.by - qe.ay;
-        const float x = qe.ax + t * dx;
-        const float y = qe.ay + t * dy;
-        const float len = sqrtf(dx * dx + dy * dy);
-        const float nhx = dy / len, nhy = -dx / len;
-        const float xs = side == 0 ? x + a.delta * nhx : x - a.delta * nhx;
-        const float ys = side == 0 ? y + a.delta * nhy : y - a.delta * nhy;
-        int px = (int)floorf(x), py = (int)floorf(y);
-        px = min(max(px, 0), c.W - 1);
-        py = min(max(py, 0), c.H - 1);
-        const long long pg = c.pix0 + (long long)py * c.W + px;
-        const float g[3] = {a.dimage[3 * pg], a.dimage[3 * pg + 1], a.dimage[3 * pg + 2]};
-        if (g[0] == 0.0f && g[1] == 0.0f && g[2] == 0.0f) continue;   // same for both lanes of the pair
-        const float bg[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
-        Ray ray;
-        Hit h;
-        ray_screen(c, xs, ys, ray);
-        trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
-        if (COUNT) { ++n_rays; n_hit += h.face >= 0; }
-        float col[3];
-        shade_or_bg(h, tris, c, xs, ys, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, col);
-        const float o0 = __shfl_xor(col[0], 1), o1 = __shfl_xor(col[1], 1), o2 = __shfl_xor(col[2], 1);
-        if (side != 0) continue;
-        // c(x - delta n) - c(x + delta n)
-        const float jump = g[0] * (o0 - col[0]) + g[1] * (o1 - col[1]) + g[2] * (o2 - col[2]);
-        float* dcs = a.stat_dc ? a.stat_dc + ((size_t)vi * E + e) * 4 : nullptr;
-        if (dcs) {   // colour-jump statistics of the edge (proposal features)
-            unsafeAtomicAdd(dcs + 0, fabsf(o0 - col[0]));
-            unsafeAtomicAdd(dcs + 1, fabsf(o1 - col[1]));
-            unsafeAtomicAdd(dcs + 2, fabsf(o2 - col[2]));
-            unsafeAtomicAdd(dcs + 3, 1.0f);
-        }
-        if (jump == 0.0f) continue;
-        // weight: (stratum probability width/T) / (density (wq_e/T)/len per unit length)
-        const float ell = len * (qe.t1 - qe.t0);
-        const float sc = jump * (ell * (float)width / (float)qe.wq);
-        if (a.stat_a) unsafeAtomicAdd(a.stat_a + (size_t)vi * E + e, fabsf(sc));
-        const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
-        const float* vh = a.verts + (size_t)hand * a.m.V * 3;
-        float* gout = a.gacc + (size_t)hand * a.m.V * 6;
-        float Ja[2][3], Jb[2][3];
-        proj_jacobian(c, vh + 3 * va, Ja);
-        proj_jacobian(c, vh + 3 * vb, Jb);
-        const float sa = (1.0f - t) * sc, sb = t * sc;
-        for (int k3 = 0; k3 < 3; ++k3) {
-            unsafeAtomicAdd(gout + 6 * va + k3, sa * (Ja[0][k3] * nhx + Ja[1][k3] * nhy));
-            unsafeAtomicAdd(gout + 6 * vb + k3, sb * (Jb[0][k3] * nhx + Jb[1][k3] * nhy));
+        for (long long kg = stored + first; kg < total; kg += npairs) {
+            EdgePoint P;
+            edge_point(a, kg, iter, side, P);
+            if (!P.valid) continue;   // same for both lanes of the pair
+            const float* gp = a.dimage + 3 * P.pg;
+            if (gp[0] == 0.0f && gp[1] == 0.0f && gp[2] == 0.0f) continue;   // same for both lanes
+            float col[3];
+            edge_side_colour<COUNT>(a, P, stk, wst, tc, n_rays, n_hit, col);
+            const float o0 = __shfl_xor(col[0], 1), o1 = __shfl_xor(col[1], 1), o2 = __shfl_xor(col[2], 1);
+            if (side != 0) continue;
+            const float dc[3] = {o0 - col[0], o1 - col[1], o2 - col[2]};
+            edge_contribution(a, P.vi, P.e, P.t, P.wgt, P.pg, dc);
         }
     }
     if (COUNT) {
@@ -1036,6 +1130,16 @@ __global__ void __launch_bounds__(kThreads) k_edges_setup(EdgeArgs e)
     edges_setup_view(e, blockIdx.x, part);
 }
 
+// Edge samples, first part: trace and shade both side points of every stored
+// sample (needs only the geometry and the silhouette tables).
+template <bool COUNT>
+__global__ void __launch_bounds__(kThreads) k_edge_trace(EdgeArgs e)
+{
+    __shared__ int stack[kMaxStack * kThreads];
+    __shared__ int wstack[kMaxStack * (kThreads / 64)];
+    edge_samples<COUNT, kEdgeTrace>(e, blockIdx.x, gridDim.x, stack, wstack);
+}
+
 // Backward ray tracing: the first `n_edge` blocks draw the edge samples, the
 // rest run the interior adjoint; in one launch the latency-bound edge
 // samples overlap with the adjoint's arithmetic.
@@ -1043,9 +1147,10 @@ template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge)
 {
     __shared__ int stack[kMaxStack * kThreads];
+    __shared__ int wstack[kMaxStack * (kThreads / 64)];
     __shared__ float patch[3 * kPatch * kPatch * (kThreads / 64)];
     if ((int)blockIdx.x < n_edge) {
-        edge_samples<COUNT>(e, blockIdx.x, n_edge, stack);
+        edge_samples<COUNT, kEdgeWeigh>(e, blockIdx.x, n_edge, stack, wstack);
         return;
     }
     adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, stack, patch);

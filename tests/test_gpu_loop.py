@@ -58,16 +58,29 @@ def _snap(r):
 
 
 def test_iterate_matches_calls(loop):
-    a, b = loop.refiner(), loop.refiner()
-    for k in range(5):           # crosses the warm-up boundary (2)
-        a.step_eager()
-        b.step()
-        sa, sb = _snap(a), _snap(b)
-        assert int(sb["iter"][0]) == k + 1 == int(sa["iter"][0])
-        if k == 0:
-            assert np.array_equal(sa["image"], sb["image"])
+    # one iteration through hr_iterate and through the five calls, from one
+    # saved state, in the colour-only phase and with all variables
+    r = loop.refiner()
+    for n_before in (0, 3):
+        _restore_or_run(r, n_before)
+        saved = _save(r)
+        outs = []
+        for eager in (True, False):
+            _restore(r, saved)
+            r.step_eager() if eager else r.step()
+            outs.append(_snap(r))
+        sa, sb = outs
+        assert int(sb["iter"][0]) == n_before + 1 == int(sa["iter"][0])
+        assert np.array_equal(sa["image"], sb["image"])
         for key in ("params", "albedo", "loss", "grad_params", "grad_albedo"):
-            assert block_rel(sb[key], sa[key]) <= 1e-5, (k, key, block_rel(sb[key], sa[key]))
+            assert block_rel(sb[key], sa[key]) <= 1e-5, (n_before, key, block_rel(sb[key], sa[key]))
+
+
+def _restore_or_run(r, n):
+    """Bring refiner r to iteration n (eager steps)."""
+    while r.it < n:
+        r.step_eager()
+    torch.cuda.synchronize()
 
 
 _STATE = ("params", "albedo", "m_params", "v_params", "m_albedo", "v_albedo", "iter")

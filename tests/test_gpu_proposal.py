@@ -169,37 +169,55 @@ def _loop_scene(w, seed=4):
 
 
 def test_training_inside_captured_iterations():
+    """hr_iterate with the learned proposal (its passes on the side stream) as
+    a captured graph and as eager calls: the first iteration's loss and
+    gradient agree (atomic-order tolerance); over several iterations the
+    network trains and the loss falls.  (Parameter trajectories are not
+    compared: Adam turns last-bit gradient differences of near-zero components
+    into steps of a learning rate.)"""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2107_05509_amd import refine
     w = scene.workload_tiny(0)
-    runs = []
+    first = []
     for graph in (False, True):
         g, p, a, bg, target = _loop_scene(w)
         g.proposal_set(binding.HR_PROPOSAL_LEARNED, scene.mlp_init(5), lr=1e-2)
         r = refine.Refiner(g, p, a, bg, target, None, warm=0, graph_chunk=3)
-        r.run(6, graph=graph)
+        r.run(1, graph=graph)
         torch.cuda.synchronize()
-        runs.append((r.params.cpu().numpy(), g.proposal_get(), int(r.state.iter.item())))
-    (pa, ta, ia), (pb, tb, ib) = runs
-    th0 = binding.flat_mlp(scene.mlp_init(5))
-    assert ia == ib == 6
-    assert np.abs(ta - th0).max() > 1e-3          # the network trained
-    assert block_rel(pb, pa) <= 1e-3 and block_rel(tb, ta) <= 1e-2
+        first.append((float(r.loss.item()), r.state.grad_params.cpu().numpy().copy()))
+        l0 = first[-1][0]
+        r.run(8, graph=graph)
+        torch.cuda.synchronize()
+        th = g.proposal_get()
+        assert int(r.state.iter.item()) == 9
+        assert np.abs(th - binding.flat_mlp(scene.mlp_init(5))).max() > 1e-3   # the network trained
+        assert np.isfinite(r.params.cpu().numpy()).all() and float(r.loss.item()) < l0
+    (la, ga), (lb, gb) = first
+    assert abs(la - lb) <= 1e-6 * abs(la)
+    assert block_rel(gb, ga) <= 1e-5
 
 
 def test_trained_proposal_is_unbiased_and_reduces_variance():
-    """Boundary-term gradient over 128 sample keys, at equal edge-sample budget:
-    the learned proposal (trained for 80 iterations on a fixed pose) and the
+    """Boundary-term gradient over 256 sample keys, at equal edge-sample budget:
+    the learned proposal (trained for 150 iterations on a fixed pose) and the
     length-proportional one must agree in the mean (within 4.5 standard errors
-    per parameter) and the learned one must have the smaller spread."""
+    per parameter), and the learned one must have the smaller spread.  The loss
+    mask keeps the left half of every image, so silhouette edges on the right
+    contribute nothing and a good proposal learns to leave them out (the
+    features include the edges' screen positions)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     w = scene.workload_realistic(0, n_views=2)
-    print("case: realistic workload, 2 views, learned proposal", flush=True)
+    print("case: realistic workload, 2 views, left-half mask, learned proposal", flush=True)
     res = {}
     for kind in (binding.HR_PROPOSAL_LENGTH, binding.HR_PROPOSAL_LEARNED):
         g, p, a, bg, target = _loop_scene(w, seed=6)
+        mask = torch.zeros(g.P, dtype=torch.uint8, device=DEV)
+        off = w.pixel_offsets()
+        for i, c in enumerate(w.cams):
+            mask[int(off[i]):int(off[i + 1])].view(c.H, c.W)[:, : c.W // 2] = 1
         v = torch.empty(1, w.model.n_verts, 3, device=DEV)
         img = torch.empty(g.P, 3, device=DEV)
         g.skin(p, v)
@@ -207,16 +225,19 @@ def test_trained_proposal_is_unbiased_and_reduces_variance():
         g.render(v, a, bg, 0, img)
         loss = torch.empty(1, device=DEV)
         d = torch.empty(g.P, 3, device=DEV)
-        g.loss(img, target, None, loss, d)
+        g.loss(img, target, mask, loss, d)
         gp = torch.empty(1, 64, device=DEV)
         ga = torch.empty_like(a)
-        g.proposal_set(kind, scene.mlp_init(1), lr=1e-2)
+        # floor 0.05: importance weights stay below 20, so that 256 keys give a
+        # usable z-test (with eps = 1e-3 the estimate is still unbiased, but its
+        # rare large weights make the sample mean heavy-tailed)
+        g.proposal_set(kind, scene.mlp_init(1), lr=1e-2, eps=0.05)
         if kind == binding.HR_PROPOSAL_LEARNED:
-            for it in range(80):
+            for it in range(150):
                 g.backward(p, v, a, bg, d, 1000 + it, gp, ga, flags=binding.HR_GRAD_EDGES)
                 g.proposal_train()
         rows = []
-        for s in range(128):
+        for s in range(256):
             g.backward(p, v, a, bg, d, 5000 + s, gp, ga, flags=binding.HR_GRAD_EDGES)
             rows.append(gp[0].double().cpu().numpy())
         res[kind] = np.array(rows)[:, 3:]
@@ -227,4 +248,4 @@ def test_trained_proposal_is_unbiased_and_reduces_variance():
     print("max |z| %.2f over %d parameters; variance ratio length/learned %.3f" % (z.max(), z.size, ratio),
           flush=True)
     assert z.max() <= 4.5
-    assert ratio > 1.0
+    assert ratio > 1.2
