@@ -69,6 +69,8 @@ struct hr_scene {
     std::vector<ViewDev> views_host;
     TileShape ts{};
     int2* tiles = nullptr;        // wave tiles inside the per-view screen bounds
+    short* hit_slot = nullptr;    // [tile_cap, rounds, 64] hits of the last render (leaf slot, -1 miss)
+    int* hit_iter = nullptr;      // iteration of those hits (-1: none)
     long long tile_cap = 0;
     int* tile_count = nullptr;
     int render_blocks = 0;        // persistent grids of the ray-tracing kernels (hr_tune)
@@ -371,6 +373,12 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     }
     // per-iteration state
     TRY(s->upload<int2>(&s->tiles, nullptr, (size_t)s->tile_cap));
+    TRY(s->upload<short>(&s->hit_slot, nullptr, (size_t)s->tile_cap * s->ts.rounds * 64));
+    TRY(s->upload<int>(&s->hit_iter, nullptr, 1));
+    if (hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EHIP, "scene init: memset");
+    }
     TRY(s->upload<int>(&s->tile_count, nullptr, 4));
     TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
     TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
@@ -485,6 +493,7 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
+    a.hit_slot = s->hit_slot; a.hit_iter = s->hit_iter;
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
@@ -663,6 +672,9 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     a.faces = s->mesh.faces;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
+    // the render's hits are valid for the geometry it prepared
+    a.hit_slot = (flags & HR_REUSE_GEOMETRY) ? s->hit_slot : nullptr;
+    a.hit_iter = s->hit_iter;
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);

@@ -62,6 +62,8 @@ struct RenderArgs {
     const float* background;
     float* image;
     int* hit_face;
+    short* hit_slot;           // [tiles, rounds, 64] leaf slot of each sample's hit (-1 miss), for the adjoint
+    int* hit_iter;             // iteration of the stored hits
     unsigned long long* counts;   // [4] rays traced, node visits, triangle tests, hits (counting variant)
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
@@ -84,6 +86,8 @@ struct AdjointArgs {
     const float* dimage;
     float* grad_albedo;
     float* gface;              // [hands,F,18] per-triangle corner gradients
+    const short* hit_slot;     // nullable: hits stored by the render of the same geometry
+    const int* hit_iter;
     unsigned long long* counts;
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;

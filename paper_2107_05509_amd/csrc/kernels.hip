@@ -422,6 +422,7 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             if (act) {
                 if (COUNT) ++n_rays;
                 if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
+                if (a.hit_slot) a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] = (short)(h.face >= 0 ? h.slot : -1);
                 if (h.face >= 0) {
                     if (COUNT) ++n_hit;
                     Surf sf;
@@ -455,6 +456,7 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             a.image[3 * pg + 2] = out[2];
         }
     }
+    if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iter;
     if (COUNT) {
         atomicAdd(a.counts + 0, n_rays);
         atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
@@ -563,6 +565,8 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
     const int n_tiles = *a.tile_count;
     const float inv_spp = 1.0f / (float)a.spp;
     const Shading S = a.shading;
+    // hits stored by the render of the same geometry and iteration: no re-trace
+    const bool stored = a.hit_slot != nullptr && __builtin_amdgcn_readfirstlane(*a.hit_iter) == (int)iter;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
     for (int t = gw; t < n_tiles; t += nw) {
@@ -607,10 +611,16 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 u = u24_lo(wd);
                 v = u24_hi(wd);
             }
-            Ray ray;
-            ray_screen(c, (float)px + u, (float)py + v, ray);
             Hit h;
-            trace_wave<COUNT>(nodes, tris, ray, act, wst, h, &tc);
+            if (stored) {
+                const int slot = act ? (int)a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] : -1;
+                h.slot = slot;
+                h.face = slot >= 0 ? tris[slot].face : -1;
+            } else {
+                Ray ray;
+                ray_screen(c, (float)px + u, (float)py + v, ray);
+                trace_wave<COUNT>(nodes, tris, ray, act, wst, h, &tc);
+            }
             if (act) {
                 if (COUNT) ++n_rays;
                 if (h.face >= 0) {

@@ -211,3 +211,27 @@ def test_batched_matches_per_hand():
         assert np.array_equal(ih.cpu().numpy(), img[off[v0]:off[v1]].cpu().numpy()), h
         assert block_rel(gph.cpu().numpy(), gp[h:h + 1].cpu().numpy()) <= 1e-5, h
         assert block_rel(gah.cpu().numpy(), ga[h:h + 1].cpu().numpy()) <= 1e-5, h
+
+
+def test_stored_hits_match_retrace(loop):
+    # the adjoint reuses the render's hits (same geometry and iteration) or
+    # re-traces (other iteration, or geometry not declared reused): same gradients
+    g, w = loop.g, loop.w
+    v = torch.empty(1, w.model.n_verts, 3, device=DEV)
+    p = _t(f32(w.params_init))
+    g.skin(p, v)
+    alb = _t(f32(w.albedo_true))
+    d = _t(np.random.default_rng(6).normal(size=(g.P, 3)).astype(np.float32))
+    img = torch.empty(g.P, 3, device=DEV)
+    outs = {}
+    for name, render_it, flags in (("stored", 3, binding.HR_REUSE_GEOMETRY), ("retraced", 3, 0),
+                                   ("other iteration", 8, binding.HR_REUSE_GEOMETRY)):
+        g.render(v, alb, loop.bg, render_it, img)
+        gp = torch.empty(1, 64, device=DEV)
+        ga = torch.empty_like(alb)
+        g.backward(p, v, alb, loop.bg, d, 3, gp, ga, flags=binding.HR_GRAD_INTERIOR | flags)
+        torch.cuda.synchronize()
+        outs[name] = (gp.cpu().numpy(), ga.cpu().numpy())
+    for name in ("retraced", "other iteration"):
+        assert block_rel(outs[name][0], outs["stored"][0]) <= 1e-5, name
+        assert block_rel(outs[name][1], outs["stored"][1]) <= 1e-5, name
