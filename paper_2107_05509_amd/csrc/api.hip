@@ -71,6 +71,7 @@ struct hr_scene {
     int2* tiles = nullptr;        // wave tiles inside the per-view screen bounds
     short* hit_slot = nullptr;    // [tile_cap, rounds, 64] hits of the last render (leaf slot, -1 miss)
     int* hit_iter = nullptr;      // iteration of those hits (-1: none)
+    int4* view_rect = nullptr;    // [n_views] pixel rectangle of each view's tiles (screen-bounds pass)
     long long tile_cap = 0;
     int* tile_count = nullptr;
     int render_blocks = 0;        // persistent grids of the ray-tracing kernels (hr_tune)
@@ -375,6 +376,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<int2>(&s->tiles, nullptr, (size_t)s->tile_cap));
     TRY(s->upload<short>(&s->hit_slot, nullptr, (size_t)s->tile_cap * s->ts.rounds * 64));
     TRY(s->upload<int>(&s->hit_iter, nullptr, 1));
+    TRY(s->upload<int4>(&s->view_rect, nullptr, (size_t)n_views));
+
     if (hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess) {
         hr_scene_destroy(s);
         return fail(HR_EHIP, "scene init: memset");
@@ -456,12 +459,10 @@ int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
 static int prepare(hr_scene* s, const float* verts, hipStream_t st)
 {
     int rc = launch(s, "k_prepare", k_prepare, dim3(s->n_hands), dim3(512), s->smem_prepare, st, s->mesh, s->bvh,
-                    verts, s->normals, s->tris, s->nodes);
-    if (rc) return rc;
-    rc = launch(s, "k_set_i32", k_set_i32, dim3(1), dim3(64), 0, st, s->tile_count, 4, 0);
+                    verts, s->normals, s->tris, s->nodes, s->tile_count);
     if (rc) return rc;
     return launch(s, "k_view_bounds", k_view_bounds, dim3(s->n_views), dim3(256), 0, st, s->mesh,
-                  (const ViewDev*)s->views, verts, s->ts, s->tiles, s->tile_count);
+                  (const ViewDev*)s->views, verts, s->ts, s->tiles, s->tile_count, s->view_rect);
 }
 
 static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
@@ -476,14 +477,12 @@ static Shading shading_of(const hr_config& c)
 }
 
 static int render_impl(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
-                       const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st, bool prepared = false)
+                       const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st, bool prepared = false,
+                       float* const* clear = nullptr, const long long* clear_n = nullptr)
 {
     int rc = prepared ? HR_OK : prepare(s, verts, st);
     if (rc) return rc;
     const long long P = s->n_pixels;
-    rc = launch(s, "k_copy", k_copy, dim3((unsigned)std::min<long long>(4096, (3 * P + 255) / 256)), dim3(256), 0,
-                st, background, image, 3 * P);
-    if (rc) return rc;
     if (hit_face) {
         rc = launch(s, "k_fill_i32", k_fill_i32, dim3((unsigned)std::min<long long>(4096, (P * s->cfg.spp + 255) / 256)),
                     dim3(256), 0, st, (int*)hit_face, P * s->cfg.spp, -1);
@@ -494,6 +493,11 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
     a.hit_slot = s->hit_slot; a.hit_iter = s->hit_iter;
+    a.view_rect = s->view_rect; a.n_views = s->n_views;
+    for (int k = 0; k < 3; ++k) {
+        a.clear[k] = clear ? clear[k] : nullptr;
+        a.clear_n[k] = clear ? clear_n[k] : 0;
+    }
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
@@ -640,18 +644,20 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
                          const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
                          uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
                          float* grad_normals, hipStream_t st, bool edges_traced = false,
-                         hipEvent_t after_trace = nullptr)
+                         hipEvent_t after_trace = nullptr, bool cleared = false)
 {
     int rc;
     if (!(flags & HR_REUSE_GEOMETRY)) {
         rc = prepare(s, verts, st);
         if (rc) return rc;
     }
-    const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
-    rc = fill(s, grad_albedo, nalb, 0.0f, st);
-    if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
-    if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
-    if (rc) return rc;
+    if (!cleared) {
+        const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
+        rc = fill(s, grad_albedo, nalb, 0.0f, st);
+        if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
+        if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
+        if (rc) return rc;
+    }
     EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
     int n_edge = 0, n_adj = 0;
     if (flags & HR_GRAD_EDGES) {
@@ -789,7 +795,10 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     const bool edges = (flags & HR_GRAD_EDGES) != 0;
     if (!rc && edges) rc = fork(s->ev[0]);
     if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, true, s->side);
-    if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true);
+    float* const clr[3] = {q->grad_albedo, s->gacc, s->gface};
+    const long long clr_n[3] = {(long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3, (long long)s->n_hands * s->V * 6,
+                                (long long)s->n_hands * s->F * 18};
+    if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true, clr, clr_n);
     if (!rc) rc = loss_impl(s, q->image, q->target, q->mask, q->loss, q->dimage, st);
     if (!rc && edges) rc = join(s->ev[1]);
     // training (needs the records of the edge samples) beside the geometry
@@ -797,7 +806,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st, edges, train ? s->ev[2] : nullptr);
+                           nullptr, st, edges, train ? s->ev[2] : nullptr, true);
     if (!rc && train && hipStreamWaitEvent(s->side, s->ev[2], 0) != hipSuccess)
         rc = fail(HR_EHIP, "hr_iterate: fork");
     if (!rc && train) rc = proposal_train_impl(s, s->side);

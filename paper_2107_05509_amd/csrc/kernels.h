@@ -64,6 +64,11 @@ struct RenderArgs {
     int* hit_face;
     short* hit_slot;           // [tiles, rounds, 64] leaf slot of each sample's hit (-1 miss), for the adjoint
     int* hit_iter;             // iteration of the stored hits
+    const int4* view_rect;     // nullable: [n_views] pixel rectangle of each view's tiles; pixels
+                               // outside it are set to the background by the render blocks
+    int n_views;
+    float* clear[3];           // nullable: buffers the render blocks zero (a following backward's accumulators)
+    long long clear_n[3];
     unsigned long long* counts;   // [4] rays traced, node visits, triangle tests, hits (counting variant)
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;

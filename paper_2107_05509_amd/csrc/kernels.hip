@@ -198,10 +198,11 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
 
 __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const float* __restrict__ verts,
                                                  float* __restrict__ normals, Tri* __restrict__ tris,
-                                                 Node* __restrict__ nodes)
+                                                 Node* __restrict__ nodes, int* __restrict__ tile_count)
 {
     extern __shared__ float dyn[];
     const int h = blockIdx.x;
+    if (h == 0 && threadIdx.x == 0) *tile_count = 0;   // the screen-bounds pass appends next
     const int V = m.V, F = m.F;
     float* vsh = dyn;                 // [V*3]
     float* fn = vsh + 3 * V;          // [F*3]
@@ -298,7 +299,8 @@ __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const floa
 // vertex is not in front of the camera.
 __global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* __restrict__ views,
                                                      const float* __restrict__ verts, TileShape ts,
-                                                     int2* __restrict__ tiles, int* __restrict__ tile_count)
+                                                     int2* __restrict__ tiles, int* __restrict__ tile_count,
+                                                     int4* __restrict__ view_rect)
 {
     __shared__ float red[4 * 4];
     __shared__ int base;
@@ -343,7 +345,14 @@ __global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* _
         }
     }
     const int count = (nx > 0 && ny > 0) ? nx * ny : 0;
-    if (threadIdx.x == 0) base = count > 0 ? atomicAdd(tile_count, count) : 0;
+    if (threadIdx.x == 0) {
+        base = count > 0 ? atomicAdd(tile_count, count) : 0;
+        // pixel rectangle covered by the view's tiles (empty if none)
+        view_rect[blockIdx.x] = count > 0 ? make_int4(tx0 << ts.tw_log2, ty0 << ts.th_log2,
+                                                       min(c.W, (tx0 + nx) << ts.tw_log2),
+                                                       min(c.H, (ty0 + ny) << ts.th_log2))
+                                          : make_int4(0, 0, 0, 0);
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < count; i += blockDim.x)
         tiles[base + i] = make_int2(blockIdx.x, (tx0 + i % nx) | ((ty0 + i / nx) << 16));
@@ -376,9 +385,40 @@ __device__ __forceinline__ void tile_pixel(const TileShape& ts, int2 e, int lane
 }
 
 // Render the listed wave tiles; this block is `bid` of `nb` blocks sharing them.
+// Pixels outside the views' tile rectangles get the background; the
+// accumulators of a following backward pass are cleared (grid-stride work of
+// the render blocks, beside the latency-bound tracing).
+__device__ void render_side_work(const RenderArgs& a, int bid, int nb)
+{
+    const long long stride = (long long)nb * blockDim.x;
+    const long long i0 = (long long)bid * blockDim.x + threadIdx.x;
+    if (a.view_rect) {
+        for (int v = 0; v < a.n_views; ++v) {
+            const ViewDev& c = a.views[v];
+            const int4 rc = a.view_rect[v];
+            const long long np = (long long)c.W * c.H;
+            for (long long pl = i0; pl < np; pl += stride) {
+                const int py = (int)(pl / c.W), px = (int)(pl - (long long)py * c.W);
+                if (px >= rc.x && px < rc.z && py >= rc.y && py < rc.w) continue;
+                const long long pg = c.pix0 + pl;
+                a.image[3 * pg] = a.background[3 * pg];
+                a.image[3 * pg + 1] = a.background[3 * pg + 1];
+                a.image[3 * pg + 2] = a.background[3 * pg + 2];
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        float* p = a.clear[k];
+        const long long n = a.clear_n[k];
+        if (!p) continue;
+        for (long long i = i0; i < n; i += stride) p[i] = 0.0f;
+    }
+}
+
 template <bool COUNT>
 __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
 {
+    render_side_work(a, bid, nb);
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* wst = stack + kMaxStack * (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
