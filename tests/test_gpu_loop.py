@@ -100,23 +100,24 @@ def _restore(r, saved):
 
 
 def test_graph_matches_iterate(loop):
-    # from one saved state, three iterations as a graph replay and as three
-    # hr_iterate calls (trajectories are compared over a few steps only:
-    # Adam's normalised steps amplify the last-bit differences of atomic sums)
+    # from one saved state: one iteration as a graph replay and as hr_iterate
+    # (tight), then three (loose: Adam's normalised steps amplify the last-bit
+    # differences of atomic sums)
     r = loop.refiner()
     r.run(4, graph=False)
     saved = _save(r)
-    outs = []
-    for graph in (True, False, True):
-        _restore(r, saved)
-        r.run(3, graph=graph)
-        outs.append(_snap(r))
-    g1, it_, g2 = outs
-    for sb in outs:
-        assert int(sb["iter"][0]) == 7
-    for key in ("params", "albedo", "loss", "grad_params"):
-        assert block_rel(g1[key], it_[key]) <= 1e-4, (key, block_rel(g1[key], it_[key]))
-        assert block_rel(g2[key], g1[key]) <= 1e-4, (key, block_rel(g2[key], g1[key]))
+    for n, tol in ((1, 1e-5), (3, 1e-3)):
+        outs = []
+        for graph in (True, False, True):
+            _restore(r, saved)
+            r.run(n, graph=graph)
+            outs.append(_snap(r))
+        g1, it_, g2 = outs
+        for sb in outs:
+            assert int(sb["iter"][0]) == 4 + n
+        for key in ("params", "albedo", "loss", "grad_params"):
+            assert block_rel(g1[key], it_[key]) <= tol, (n, key, block_rel(g1[key], it_[key]))
+            assert block_rel(g2[key], g1[key]) <= tol, (n, key, block_rel(g2[key], g1[key]))
     # the warm-up graph (colour map only) leaves the pose untouched
     r2 = loop.refiner(warm=5)
     p0 = r2.params.clone()
