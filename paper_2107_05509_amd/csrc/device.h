@@ -17,7 +17,8 @@ constexpr int kLeafMax = 4;         // triangles per leaf
 constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
 constexpr int kEdgeBlocks = 256;    // blocks of edge samples in the backward launch
 constexpr int kMaxTraceBlocks = 4096;   // largest persistent ray-tracing grid
-constexpr int kPatch = 16;          // texel patch (per wave) of the colour-map gradient
+constexpr int kWin = 16;            // texel window (per row of 16 lanes) of the colour-map gradient
+constexpr int kWaveWin = 4 * 3 * kWin * kWin;   // floats of one wave's four row windows (RGB)
 
 // ---------------------------------------------------------------------------
 // records in device memory
@@ -529,6 +530,56 @@ __device__ __forceinline__ int wave_max(int v)
 {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// The same reductions on the DPP network (lane moves inside the VALU, no LDS
+// traffic).  DPP rows are groups of 16 lanes; update_dpp with old = 0 and
+// bound_ctrl set reads 0 where the source lane is outside the row, and keeps
+// 0 in rows the row mask leaves out.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, true));
+}
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+// sum over the 64 lanes, complete in lane 63: prefix sums inside each row
+// (shifts by 1, 2, 4, 8), then lane 15 into rows 1 and 3 and lane 31 into
+// rows 2 and 3
+__device__ __forceinline__ float wave_sum63(float v)
+{
+    v += dpp_f<0x111>(v);
+    v += dpp_f<0x112>(v);
+    v += dpp_f<0x114>(v);
+    v += dpp_f<0x118>(v);
+    v += dpp_f<0x142, 0xA>(v);
+    v += dpp_f<0x143, 0xC>(v);
+    return v;
+}
+
+// min / max over each row of 16 lanes, in every lane of the row: swaps inside
+// quads (lane ^ 1, lane ^ 2), then the half-row and row mirrors
+__device__ __forceinline__ int row_min(int v)
+{
+    v = min(v, dpp_i<0xB1>(v));
+    v = min(v, dpp_i<0x4E>(v));
+    v = min(v, dpp_i<0x141>(v));
+    v = min(v, dpp_i<0x140>(v));
+    return v;
+}
+
+__device__ __forceinline__ int row_max(int v)
+{
+    v = max(v, dpp_i<0xB1>(v));
+    v = max(v, dpp_i<0x4E>(v));
+    v = max(v, dpp_i<0x141>(v));
+    v = max(v, dpp_i<0x140>(v));
     return v;
 }
 

@@ -595,7 +595,13 @@ template <bool COUNT>
 __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack, float* patch_base)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
-    float* patch = patch_base + 3 * kPatch * kPatch * (threadIdx.x >> 6);
+    // this wave's four row windows, zero between uses (the flush clears what it reads)
+    float* patch = patch_base + kWaveWin * (threadIdx.x >> 6);
+    {
+        float4* z = reinterpret_cast<float4*>(patch);
+        for (int f = threadIdx.x & 63; f < kWaveWin / 4; f += 64) z[f] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        wave_lds_sync();
+    }
     int* wst = stack + kMaxStack * (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
@@ -724,78 +730,102 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                     }
                 }
             }
-            // Colour map.  Usually the wave's samples touch at most 16x16 texels:
-            // sum them in an LDS patch and add the patch to the gradient row
-            // by row, consecutive lanes on consecutive floats (a few memory
-            // transactions per row instead of one per texel and channel).
-            const int pi0 = wave_min(fi0), pi1 = wave_max(fi1);
-            const int pj0 = wave_min(fj0), pj1 = wave_max(fj1);
-            const bool use_patch = pi1 >= pi0 && pi1 - pi0 < kPatch && pj1 - pj0 < kPatch;
-            if (use_patch) {
-                float* pch = patch;   // this wave's [kPatch][kPatch][3]
-                const int nrow = pi1 - pi0 + 1, ncol = 3 * (pj1 - pj0 + 1);
-                for (int f = lane; f < 3 * kPatch * kPatch; f += 64) pch[f] = 0.0f;
-                wave_lds_sync();
-                if (tmask) {
-                    const int ri[4] = {fi0, fi0, fi1, fi1}, rj[4] = {fj0, fj1, fj0, fj1};
-                    for (int k = 0; k < 4; ++k) {
-                        float* dst = pch + ((ri[k] - pi0) * kPatch + (rj[k] - pj0)) * 3;
-                        for (int ch = 0; ch < 3; ++ch) atomicAdd(dst + ch, g[ch] * twt[k]);
-                    }
-                    tmask = 0;
-                }
-                wave_lds_sync();
-                for (int f = lane; f < nrow * 3 * kPatch; f += 64) {
-                    const int row = f / (3 * kPatch), o = f - 3 * kPatch * row;
-                    if (o < ncol) {
-                        const float x = pch[f];
-                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * ((pi0 + row) * a.tex_w + pj0) + o, x);
-                    }
-                }
-                wave_lds_sync();
-            }
-            // Otherwise: all lanes of a pixel share dL/dI, so the gradient of
-            // texel j is dL/dI * sum of (shade * bilinear weight) over the
-            // pixel's samples touching j.  Sum per texel within the pixel's
-            // lanes; one lane per (pixel, texel) scatters.
-            {
-                const int gbase = lane & ~(G - 1);
-                const unsigned long long gmask = G == 64 ? ~0ull : ((1ull << G) - 1ull);
-                while (__any(tmask != 0)) {
-                    const unsigned long long b = __ballot(tmask != 0);
-                    const unsigned long long seg = (b >> gbase) & gmask;
-                    const int first = tmask ? tidx[__ffs(tmask) - 1] : -1;
-                    const int leader = seg ? gbase + __ffsll((long long)seg) - 1 : lane;
-                    const int tau = __shfl(first, leader);
-                    float wsum = 0.0f;
-                    if (seg) {
-                        for (int k = 0; k < 4; ++k)
-                            if (((tmask >> k) & 1) && tidx[k] == tau) { wsum += twt[k]; tmask &= ~(1 << k); }
-                    }
-                    for (int o = G >> 1; o > 0; o >>= 1) wsum += __shfl_xor(wsum, o);
-                    if (seg && lane == leader)
-                        for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * tau + ch, g[ch] * wsum);
-                }
-            }
-            // Sum the lanes' contributions per triangle (a wave's samples hit a
-            // few triangles) and let one lane scatter each sum into the
-            // triangle's slot: [corner k][dL/dv (3), dL/dn (3)].
+            // Triangles: sum the lanes' contributions per triangle (a wave's
+            // samples hit a few) and let one lane scatter each sum into the
+            // triangle's slot [corner k][dL/dv (3), dL/dn (3)].  The sums run
+            // on the DPP network and end in lane 63; lane `entry` takes
+            // entry `entry` of the slot, so one instruction writes all 18.
             unsigned long long pending = __ballot(face >= 0);
             while (pending) {
                 const int leader = __ffsll((long long)pending) - 1;
-                const int f = __shfl(face, leader);
+                const int f = __builtin_amdgcn_readlane(face, leader);
                 const bool mine = face == f;
                 pending &= ~__ballot(mine);
-                // slot entry l (corner l/6, position or normal part) from lane l:
-                // one instruction over 18 consecutive floats
                 float mine_val = 0.0f;
+#pragma unroll
                 for (int k = 0; k < 18; ++k) {
-                    const float x = wave_sum(mine ? gv[k] : 0.0f);
+                    const float x =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum63(mine ? gv[k] : 0.0f)), 63));
                     const int corner = k < 9 ? k / 3 : (k - 9) / 3;
                     const int entry = 6 * corner + (k < 9 ? k % 3 : 3 + (k - 9) % 3);
                     if (lane == entry) mine_val = x;
                 }
                 if (lane < 18) unsafeAtomicAdd(a.gface + ((size_t)hand * a.n_faces + f) * 18 + lane, mine_val);
+            }
+            // Colour map: each row of 16 lanes sums its samples' bilinear
+            // footprints into an LDS window of up to kWin x kWin texels, then
+            // adds the window's used part to the gradient, consecutive lanes
+            // on consecutive floats, clearing it for the next use.  Where the
+            // row's lanes all belong to one pixel (G >= 16) they share dL/dI
+            // and the window holds one weight per texel (dL/dI is applied in
+            // the flush); otherwise it holds RGB.  Rows whose footprint does
+            // not fit (a texture seam inside the row) scatter directly.
+            const bool scalar = G >= 16;
+            const int wr0 = row_min(fi0), wr1 = row_max(fi1);
+            const int wc0 = row_min(fj0), wc1 = row_max(fj1);
+            const bool fits = wr1 >= wr0 && wr1 - wr0 < kWin && wc1 - wc0 < kWin;   // uniform in the row
+            float* win = patch + (lane >> 4) * (3 * kWin * kWin);
+            if (tmask && fits) {
+                // start at corner (lane & 3): lanes sharing a footprint hit
+                // different LDS words in each of the four steps
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = (q + lane) & 3;
+                    const int ri = (k & 2) ? fi1 : fi0, rj = (k & 1) ? fj1 : fj0;
+                    const float wk = k == 0 ? twt[0] : k == 1 ? twt[1] : k == 2 ? twt[2] : twt[3];
+                    const int cell = (ri - wr0) * kWin + (rj - wc0);
+                    if (scalar) {
+                        atomicAdd(win + cell, wk);
+                    } else {
+                        atomicAdd(win + 3 * cell + 0, g[0] * wk);
+                        atomicAdd(win + 3 * cell + 1, g[1] * wk);
+                        atomicAdd(win + 3 * cell + 2, g[2] * wk);
+                    }
+                }
+                tmask = 0;
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int rw = 0; rw < 4; ++rw) {
+                const int src = 16 * rw;
+                if (!__builtin_amdgcn_readlane((int)fits, src)) continue;
+                const int r0 = __builtin_amdgcn_readlane(wr0, src), r1 = __builtin_amdgcn_readlane(wr1, src);
+                const int c0 = __builtin_amdgcn_readlane(wc0, src), c1 = __builtin_amdgcn_readlane(wc1, src);
+                const int ncol = 3 * (c1 - c0 + 1), n = (r1 - r0 + 1) * ncol;
+                float* wrow = patch + rw * (3 * kWin * kWin);
+                if (scalar) {
+                    const float g0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[0]), src));
+                    const float g1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[1]), src));
+                    const float g2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[2]), src));
+                    for (int f = lane; f < n; f += 64) {
+                        const int y = f / ncol, x3 = f - ncol * y;
+                        const int xt = x3 / 3, ch = x3 - 3 * xt;
+                        float* cell = wrow + y * kWin + xt;
+                        const float w = *cell;
+                        // the texel's last channel clears it (its other two
+                        // channels are read by lower f, no later)
+                        if (ch == 2) *cell = 0.0f;
+                        const float x = w * (ch == 0 ? g0 : ch == 1 ? g1 : g2);
+                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * ((r0 + y) * a.tex_w + c0) + x3, x);
+                    }
+                } else {
+                    for (int f = lane; f < n; f += 64) {
+                        const int y = f / ncol, x3 = f - ncol * y;
+                        float* cell = wrow + y * (3 * kWin) + x3;
+                        const float x = *cell;
+                        *cell = 0.0f;
+                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * ((r0 + y) * a.tex_w + c0) + x3, x);
+                    }
+                }
+            }
+            wave_lds_sync();
+            if (tmask) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int ix = k == 0 ? tidx[0] : k == 1 ? tidx[1] : k == 2 ? tidx[2] : tidx[3];
+                    const float wk = k == 0 ? twt[0] : k == 1 ? twt[1] : k == 2 ? twt[2] : twt[3];
+                    for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * ix + ch, g[ch] * wk);
+                }
             }
         }
     }
@@ -1196,14 +1226,17 @@ __global__ void __launch_bounds__(kThreads) k_edge_trace(EdgeArgs e)
 template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge)
 {
-    __shared__ int stack[kMaxStack * kThreads];
+    // edge blocks: a traversal stack per lane; adjoint blocks: the texel
+    // windows of their waves in the same memory
+    constexpr int kLds = kMaxStack * kThreads > kWaveWin * (kThreads / 64) ? kMaxStack * kThreads
+                                                                           : kWaveWin * (kThreads / 64);
+    __shared__ __align__(16) int lds[kLds];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
-    __shared__ float patch[3 * kPatch * kPatch * (kThreads / 64)];
     if ((int)blockIdx.x < n_edge) {
-        edge_samples<COUNT, kEdgeWeigh>(e, blockIdx.x, n_edge, stack, wstack);
+        edge_samples<COUNT, kEdgeWeigh>(e, blockIdx.x, n_edge, lds, wstack);
         return;
     }
-    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, stack, patch);
+    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, wstack, reinterpret_cast<float*>(lds));
 }
 
 // ===========================================================================
@@ -1515,12 +1548,6 @@ __global__ void k_advance(int* p)
 __global__ void k_set_i32(int* p, int n, int v)
 {
     if ((int)threadIdx.x < n) p[threadIdx.x] = v;
-}
-
-__global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, long long n)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        dst[i] = src[i];
 }
 
 __global__ void k_fill_i32(int* __restrict__ p, long long n, int v)

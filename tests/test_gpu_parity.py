@@ -2,6 +2,8 @@
 on identical float32 inputs: the tiny workload (4 views 64x64, 4 spp) and
 edge cases.  Bars: triangle ids of every sample bit-exact; images 1e-5
 relative; gradients 1e-4 relative per block."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -116,6 +118,29 @@ def test_interior_adjoint_parity(tiny):
         print(k, e, flush=True)
         assert e <= 1e-4, k
     _check_params(g["gp"], o["gp"])
+
+
+@pytest.mark.parametrize("spp,tex", [(16, 64), (64, 64), (4, 1024), (16, 1024)])
+def test_interior_adjoint_texture_windows(spp, tex):
+    # the colour-map gradient goes through per-row texel windows: rows of one
+    # pixel (16 spp and more) sum one weight per texel, rows of several pixels
+    # (4 spp) sum RGB; a 1024x1024 map seen in 64x64 views has pixel
+    # footprints wider than a window, which scatter directly
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"case: tiny workload (2 views), {spp} spp, albedo {tex}x{tex}", flush=True)
+    w0 = scene.workload_tiny(0)
+    alb = scene.blob_albedo(tex, tex, np.random.default_rng(7))[None]
+    w = dataclasses.replace(w0, spp=spp, albedo_true=alb, albedo_init=alb.copy())
+    c = Case(w, n_views=2)
+    img = f32(c.oracle_render(0))   # inputs come from the oracle side only
+    d = _dimage(c, img)
+    g = _gpu_grads(c, d, binding.HR_GRAD_INTERIOR)
+    o = _oracle_grads(c, d, binding.HR_GRAD_INTERIOR)
+    for k in ("ga", "gn", "gv"):
+        e = block_rel(g[k], o[k])
+        print(k, e, flush=True)
+        assert e <= 1e-4, k
 
 
 def test_edge_term_parity(tiny):
