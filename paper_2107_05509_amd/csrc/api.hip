@@ -110,7 +110,7 @@ struct hr_scene {
     // side stream of hr_iterate: the proposal pass runs beside the loss, its
     // training beside the geometry backward and the parameter step
     hipStream_t side = nullptr;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool counting = false;
     // per-kernel timing (profiling aid)
     bool timing = false;
@@ -476,9 +476,12 @@ static Shading shading_of(const hr_config& c)
     return S;
 }
 
+// `dimage` (with target, mask): the L1 loss gradient is written with the
+// image, scaled by the view_scale a preceding loss_scale_impl left
 static int render_impl(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
                        const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st, bool prepared = false,
-                       float* const* clear = nullptr, const long long* clear_n = nullptr)
+                       float* const* clear = nullptr, const long long* clear_n = nullptr,
+                       const float* target = nullptr, const uint8_t* mask = nullptr, float* dimage = nullptr)
 {
     int rc = prepared ? HR_OK : prepare(s, verts, st);
     if (rc) return rc;
@@ -494,6 +497,7 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
     a.hit_slot = s->hit_slot; a.hit_iter = s->hit_iter;
     a.view_rect = s->view_rect; a.n_views = s->n_views;
+    a.dimage = dimage; a.target = target; a.mask = mask; a.view_scale = s->view_scale;
     for (int k = 0; k < 3; ++k) {
         a.clear[k] = clear ? clear[k] : nullptr;
         a.clear_n[k] = clear ? clear_n[k] : 0;
@@ -513,12 +517,17 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
 
 // Edge samples, first part: silhouette tables (unless done), learned sampling
 // weights, budget prefix, tracing of every stored sample.
+static int edges_setup_impl(hr_scene* s, const float* verts, hipStream_t st)
+{
+    const EdgeArgs e = edge_args(s, verts, nullptr, nullptr, nullptr, 0, nullptr);
+    return launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kSetupThreads), 0, st, e);
+}
+
 static int edge_trace_impl(hr_scene* s, const float* verts, const float* albedo, const float* background,
                            uint32_t iter, const int* iter_dev, bool setup, hipStream_t st)
 {
     EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
-    int rc = HR_OK;
-    if (setup) rc = launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kThreads), 0, st, e);
+    int rc = setup ? edges_setup_impl(s, verts, st) : HR_OK;
     if (!rc && s->prop_kind == HR_PROPOSAL_LEARNED)
         rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, st, e, s->prop);
     if (!rc)
@@ -624,6 +633,34 @@ static int loss_impl(hr_scene* s, const float* image, const float* target, const
     rc = launch(s, "k_loss_final", k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
     if (rc) return rc;
     return launch(s, "k_loss_grad", k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
+}
+
+// the two halves of the loss with the gradient written by the render: the
+// views' scales from the mask alone (before the render), the loss values
+// (after it)
+static int loss_scale_impl(hr_scene* s, const uint8_t* mask, hipStream_t st)
+{
+    LossArgs a;
+    a.chunks = s->chunks; a.views = s->views; a.image = nullptr; a.target = nullptr; a.mask = mask;
+    a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
+    a.hand_views = s->hand_views; a.view_scale = s->view_scale; a.loss = nullptr; a.dimage = nullptr;
+    a.n_hands = s->n_hands;
+    int rc = launch(s, "k_loss_count", k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
+    if (rc) return rc;
+    return launch(s, "k_loss_scale", k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
+}
+
+static int loss_value_impl(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss,
+                           hipStream_t st)
+{
+    LossArgs a;
+    a.chunks = s->chunks; a.views = s->views; a.image = image; a.target = target; a.mask = mask;
+    a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
+    a.hand_views = s->hand_views; a.view_scale = nullptr; a.loss = loss; a.dimage = nullptr;
+    a.n_hands = s->n_hands;
+    int rc = launch(s, "k_loss_partial", k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
+    if (rc) return rc;
+    return launch(s, "k_loss_final", k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
 }
 
 int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss, float* dimage,
@@ -787,34 +824,51 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
             return fail(HR_EHIP, "hr_iterate: join");
         return HR_OK;
     };
+    auto mark = [&](hipEvent_t ev, hipStream_t on) -> int {
+        return hipEventRecord(ev, on) == hipSuccess ? HR_OK : fail(HR_EHIP, "hr_iterate: event");
+    };
+    auto wait = [&](hipStream_t on, hipEvent_t ev) -> int {
+        return hipStreamWaitEvent(on, ev, 0) == hipSuccess ? HR_OK : fail(HR_EHIP, "hr_iterate: wait");
+    };
     int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
                     (const float*)q->params, q->verts, (float*)nullptr);
-    if (!rc) rc = prepare(s, q->verts, st);
-    // edge samples, first part (silhouette tables, learned weights, tracing:
-    // independent of the image gradient) beside the render and the loss
+    // side stream: the views' loss scales (mask only), the silhouette tables
+    // (vertices only), then, once the hierarchy is refitted, learned weights
+    // and the tracing of the edge samples (independent of the image gradient),
+    // beside the refit, the render and its loss gradient
     const bool edges = (flags & HR_GRAD_EDGES) != 0;
-    if (!rc && edges) rc = fork(s->ev[0]);
-    if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, true, s->side);
+    if (!rc) rc = fork(s->ev[0]);
+    if (!rc) rc = loss_scale_impl(s, q->mask, s->side);
+    if (!rc) rc = mark(s->ev[6], s->side);
+    if (!rc && edges) rc = edges_setup_impl(s, q->verts, s->side);
+    if (!rc) rc = prepare(s, q->verts, st);
+    if (!rc && edges) rc = fork(s->ev[4]);
+    if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, false, s->side);
+    if (!rc && edges) rc = mark(s->ev[1], s->side);
     float* const clr[3] = {q->grad_albedo, s->gacc, s->gface};
     const long long clr_n[3] = {(long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3, (long long)s->n_hands * s->V * 6,
                                 (long long)s->n_hands * s->F * 18};
-    if (!rc) rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true, clr, clr_n);
-    if (!rc) rc = loss_impl(s, q->image, q->target, q->mask, q->loss, q->dimage, st);
-    if (!rc && edges) rc = join(s->ev[1]);
+    if (!rc) rc = wait(st, s->ev[6]);
+    if (!rc)
+        rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true, clr, clr_n,
+                         q->target, q->mask, q->dimage);
+    // the loss values beside the backward
+    if (!rc) rc = fork(s->ev[5]);
+    if (!rc) rc = loss_value_impl(s, q->image, q->target, q->mask, q->loss, s->side);
+    if (!rc && edges) rc = wait(st, s->ev[1]);
     // training (needs the records of the edge samples) beside the geometry
     // backward and the parameter step
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
                            nullptr, st, edges, train ? s->ev[2] : nullptr, true);
-    if (!rc && train && hipStreamWaitEvent(s->side, s->ev[2], 0) != hipSuccess)
-        rc = fail(HR_EHIP, "hr_iterate: fork");
+    if (!rc && train) rc = wait(s->side, s->ev[2]);
     if (!rc && train) rc = proposal_train_impl(s, s->side);
     if (!rc)
         rc = step_impl(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
                        q->m_albedo, q->v_albedo, 1, it, cfg, st);
     if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
-    if (!rc && train) rc = join(s->ev[3]);
+    if (!rc) rc = join(s->ev[3]);
     return rc;
 }
 

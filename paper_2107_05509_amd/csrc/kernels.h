@@ -69,6 +69,10 @@ struct RenderArgs {
     int n_views;
     float* clear[3];           // nullable: buffers the render blocks zero (a following backward's accumulators)
     long long clear_n[3];
+    float* dimage;             // nullable: [P,3] L1 loss gradient written with the image (needs view_rect)
+    const float* target;       // [P,3] with dimage
+    const uint8_t* mask;       // [P] nullable
+    const float* view_scale;   // [n_views] 1 / (3 * masked pixels), with dimage
     unsigned long long* counts;   // [4] rays traced, node visits, triangle tests, hits (counting variant)
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
@@ -104,15 +108,15 @@ struct AdjointArgs {
 struct LossArgs {
     const int2* chunks;        // (view, first pixel)
     const ViewDev* views;
-    const float* image;
+    const float* image;        // nullable: masked-pixel counts only
     const float* target;
     const uint8_t* mask;
     float* partial;            // [n_chunks,2]
     const int* view_chunk_off; // [n_views+1]
     const int* hand_view_off;  // [n_hands+1]
     const int* hand_views;     // [n_views]
-    float* view_scale;         // [n_views]
-    float* loss;               // [n_hands]
+    float* view_scale;         // [n_views] nullable (not written)
+    float* loss;               // [n_hands] nullable (not written)
     float* dimage;
     int n_hands;
 };

@@ -385,9 +385,21 @@ __device__ __forceinline__ void tile_pixel(const TileShape& ts, int2 e, int lane
 }
 
 // Render the listed wave tiles; this block is `bid` of `nb` blocks sharing them.
-// Pixels outside the views' tile rectangles get the background; the
-// accumulators of a following backward pass are cleared (grid-stride work of
-// the render blocks, beside the latency-bound tracing).
+// L1 loss gradient of one rendered pixel (the arithmetic of k_loss_grad)
+__device__ __forceinline__ void pixel_dimage(const RenderArgs& a, int view, long long pg, const float* img)
+{
+    const bool on = !a.mask || a.mask[pg] != 0;
+    const float sc = a.view_scale[view];
+    for (int ch = 0; ch < 3; ++ch) {
+        const float d = img[ch] - a.target[3 * pg + ch];
+        const float sg = (float)((d > 0.0f) - (d < 0.0f));
+        a.dimage[3 * pg + ch] = on ? sg * sc : 0.0f;
+    }
+}
+
+// Pixels outside the views' tile rectangles get the background (and its loss
+// gradient); the accumulators of a following backward pass are cleared
+// (grid-stride work of the render blocks, beside the latency-bound tracing).
 __device__ void render_side_work(const RenderArgs& a, int bid, int nb)
 {
     const long long stride = (long long)nb * blockDim.x;
@@ -401,9 +413,11 @@ __device__ void render_side_work(const RenderArgs& a, int bid, int nb)
                 const int py = (int)(pl / c.W), px = (int)(pl - (long long)py * c.W);
                 if (px >= rc.x && px < rc.z && py >= rc.y && py < rc.w) continue;
                 const long long pg = c.pix0 + pl;
-                a.image[3 * pg] = a.background[3 * pg];
-                a.image[3 * pg + 1] = a.background[3 * pg + 1];
-                a.image[3 * pg + 2] = a.background[3 * pg + 2];
+                const float bg[3] = {a.background[3 * pg], a.background[3 * pg + 1], a.background[3 * pg + 2]};
+                a.image[3 * pg] = bg[0];
+                a.image[3 * pg + 1] = bg[1];
+                a.image[3 * pg + 2] = bg[2];
+                if (a.dimage) pixel_dimage(a, v, pg, bg);
             }
         }
     }
@@ -494,6 +508,7 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             a.image[3 * pg] = out[0];
             a.image[3 * pg + 1] = out[1];
             a.image[3 * pg + 2] = out[2];
+            if (a.dimage) pixel_dimage(a, e.x, pg, out);
         }
     }
     if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iter;
@@ -521,8 +536,9 @@ __global__ void __launch_bounds__(256) k_loss_partial(LossArgs a)
         if (pl >= n) break;
         long long pg = c.pix0 + pl;
         if (a.mask && a.mask[pg] == 0) continue;
-        s += fabsf(a.image[3 * pg] - a.target[3 * pg]) + fabsf(a.image[3 * pg + 1] - a.target[3 * pg + 1]) +
-             fabsf(a.image[3 * pg + 2] - a.target[3 * pg + 2]);
+        if (a.image)
+            s += fabsf(a.image[3 * pg] - a.target[3 * pg]) + fabsf(a.image[3 * pg + 1] - a.target[3 * pg + 1]) +
+                 fabsf(a.image[3 * pg + 2] - a.target[3 * pg + 2]);
         cnt += 1.0f;
     }
     s = wave_sum(s);
@@ -559,12 +575,12 @@ __global__ void __launch_bounds__(256) k_loss_final(LossArgs a)
         if (threadIdx.x == 0) {
             float ts = 0.0f, tc = 0.0f;
             for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ts += red[2 * k]; tc += red[2 * k + 1]; }
-            a.view_scale[v] = tc > 0.0f ? 1.0f / (3.0f * tc) : 0.0f;
+            if (a.view_scale) a.view_scale[v] = tc > 0.0f ? 1.0f / (3.0f * tc) : 0.0f;
             if (tc > 0.0f) loss += ts / (3.0f * tc);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) a.loss[h] = loss;
+    if (threadIdx.x == 0 && a.loss) a.loss[h] = loss;
 }
 
 __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
@@ -1204,9 +1220,9 @@ __global__ void __launch_bounds__(kThreads) k_render(RenderArgs a, EdgeArgs e, i
     render_tiles<COUNT>(a, (int)blockIdx.x - n_setup, (int)gridDim.x - n_setup, stack);
 }
 
-__global__ void __launch_bounds__(kThreads) k_edges_setup(EdgeArgs e)
+__global__ void __launch_bounds__(kSetupThreads) k_edges_setup(EdgeArgs e)
 {
-    __shared__ unsigned long long part[kThreads];
+    __shared__ unsigned long long part[kSetupThreads];
     edges_setup_view(e, blockIdx.x, part);
 }
 
