@@ -320,7 +320,9 @@ def main():
     # roofline of the dominant ray-tracing kernel (the backward launch carries
     # both the interior adjoint and the edge samples)
     dom = max(("k_render", "k_backward_trace"), key=lambda k: per_kernel[k]["ms_per_step"])
-    parts = ["k_render"] if dom == "k_render" else ["k_adjoint_interior", "k_edge_sample"]
+    # the render launch also traces the edge samples' side points; the
+    # backward launch weighs them (tracing only samples beyond the stored ones)
+    parts = ["k_render", "k_edge_sample"] if dom == "k_render" else ["k_adjoint_interior"]
     rays = sum(counts[p][0] for p in parts)
     nodes = sum(counts[p][1] for p in parts)
     tris = sum(counts[p][2] for p in parts)

@@ -109,7 +109,7 @@ struct hr_scene {
     // side stream of hr_iterate: the proposal pass runs beside the loss, its
     // training beside the geometry backward and the parameter step
     hipStream_t side = nullptr;
-    hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};   // hr_iterate: after the ray-tracing backward; end of training
     bool counting = false;
     // per-kernel timing (profiling aid)
     bool timing = false;
@@ -441,7 +441,7 @@ int hr_skin(hr_scene* s, const float* params, float* verts, float* joints, void*
     if (!s || !params || !verts) return fail(HR_EINVAL, "hr_skin: null argument");
     hipStream_t st = (hipStream_t)stream;
     return launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh, params, verts,
-                  joints);
+                  joints, (int*)nullptr);
 }
 
 int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
@@ -465,17 +465,29 @@ int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
     return HR_OK;
 }
 
-static int prepare(hr_scene* s, const float* verts, hipStream_t st)
-{
-    int rc = launch(s, "k_prepare", k_prepare, dim3(s->n_hands), dim3(512), s->smem_prepare, st, s->mesh, s->bvh,
-                    verts, s->normals, s->tris, s->nodes, s->tile_count);
-    if (rc) return rc;
-    return launch(s, "k_view_bounds", k_view_bounds, dim3(s->n_views), dim3(256), 0, st, s->mesh,
-                  (const ViewDev*)s->views, verts, s->ts, s->tiles, s->tile_count, s->view_rect);
-}
-
 static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
                           const float* dimage, uint32_t iter, const int* iter_dev);
+
+// Everything the render and the backward need from the vertices, one
+// launch: refit, silhouette tables, wave tiles and (with_scale) the views'
+// loss scales from the mask.  reset_tiles: zero the tile count first (the
+// iteration folds that into its skinning launch instead).
+static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_tiles = true, bool with_scale = false,
+                   const uint8_t* mask = nullptr)
+{
+    if (reset_tiles) {
+        const int rc = launch(s, "k_set_i32", k_set_i32, dim3(1), dim3(64), 0, st, s->tile_count, 1, 0);
+        if (rc) return rc;
+    }
+    PrepArgs a;
+    a.m = s->mesh; a.b = s->bvh; a.verts = verts; a.normals = s->normals; a.tris = s->tris; a.nodes = s->nodes;
+    a.e = edge_args(s, verts, nullptr, nullptr, nullptr, 0, nullptr);
+    a.views = s->views; a.ts = s->ts; a.tiles = s->tiles; a.tile_count = s->tile_count; a.view_rect = s->view_rect;
+    a.mask = mask; a.view_scale = s->view_scale;
+    a.n_hands = s->n_hands; a.n_views = s->n_views; a.with_setup = 1; a.with_scale = with_scale;
+    const dim3 grid(s->n_hands + (2 + (with_scale ? 1 : 0)) * s->n_views);
+    return launch(s, "k_prepare", k_prepare, grid, dim3(512), s->smem_prepare, st, a);
+}
 
 static Shading shading_of(const hr_config& c)
 {
@@ -486,11 +498,15 @@ static Shading shading_of(const hr_config& c)
 }
 
 // `dimage` (with target, mask): the L1 loss gradient is written with the
-// image, scaled by the view_scale a preceding loss_scale_impl left
+// image, scaled by the view_scale a preceding prepare (with_scale) left.
+// n_edge > 0: that many blocks trace the edge samples beside the render (the
+// weights and budget prefix are built beforehand: edge_trace_impl, trace
+// false).
 static int render_impl(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
                        const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st, bool prepared = false,
                        float* const* clear = nullptr, const long long* clear_n = nullptr,
-                       const float* target = nullptr, const uint8_t* mask = nullptr, float* dimage = nullptr)
+                       const float* target = nullptr, const uint8_t* mask = nullptr, float* dimage = nullptr,
+                       int n_edge = 0)
 {
     int rc = prepared ? HR_OK : prepare(s, verts, st);
     if (rc) return rc;
@@ -515,34 +531,26 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
-    // the silhouette tables of these vertices are built alongside (unless the
-    // caller builds them beside the render: prepared)
     const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
-    const int n_setup = prepared ? 0 : s->n_views;
-    const dim3 grid(n_setup + s->render_blocks);
-    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, n_setup);
-    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, n_setup);
+    const dim3 grid(n_edge + s->render_blocks);
+    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, n_edge);
+    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, n_edge);
 }
 
 // Edge samples, first part: silhouette tables (unless done), learned sampling
 // weights, budget prefix, tracing of every stored sample.
-static int edges_setup_impl(hr_scene* s, const float* verts, hipStream_t st)
-{
-    const EdgeArgs e = edge_args(s, verts, nullptr, nullptr, nullptr, 0, nullptr);
-    return launch(s, "k_edges_setup", k_edges_setup, dim3(s->n_views), dim3(kSetupThreads), 0, st, e);
-}
 
 static int edge_trace_impl(hr_scene* s, const float* verts, const float* albedo, const float* background,
-                           uint32_t iter, const int* iter_dev, bool setup, hipStream_t st)
+                           uint32_t iter, const int* iter_dev, hipStream_t st, bool trace = true)
 {
     EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
-    int rc = setup ? edges_setup_impl(s, verts, st) : HR_OK;
+    int rc = HR_OK;
     if (!rc && s->prop_kind == HR_PROPOSAL_LEARNED)
         rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, st, e, s->prop);
     if (!rc)
         rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
                     s->n_views, s->edge_prefix);
-    if (rc) return rc;
+    if (rc || !trace) return rc;
     if (s->counting) return launch(s, "k_edge_trace", k_edge_trace<true>, dim3(kEdgeBlocks), dim3(kThreads), 0, st, e);
     return launch(s, "k_edge_trace", k_edge_trace<false>, dim3(kEdgeBlocks), dim3(kThreads), 0, st, e);
 }
@@ -644,33 +652,6 @@ static int loss_impl(hr_scene* s, const float* image, const float* target, const
     return launch(s, "k_loss_grad", k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
 }
 
-// the two halves of the loss with the gradient written by the render: the
-// views' scales from the mask alone (before the render), the loss values
-// (after it)
-static int loss_scale_impl(hr_scene* s, const uint8_t* mask, hipStream_t st)
-{
-    LossArgs a;
-    a.chunks = s->chunks; a.views = s->views; a.image = nullptr; a.target = nullptr; a.mask = mask;
-    a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
-    a.hand_views = s->hand_views; a.view_scale = s->view_scale; a.loss = nullptr; a.dimage = nullptr;
-    a.n_hands = s->n_hands;
-    int rc = launch(s, "k_loss_count", k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
-    if (rc) return rc;
-    return launch(s, "k_loss_scale", k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
-}
-
-static int loss_value_impl(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss,
-                           hipStream_t st)
-{
-    LossArgs a;
-    a.chunks = s->chunks; a.views = s->views; a.image = image; a.target = target; a.mask = mask;
-    a.partial = s->loss_partial; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
-    a.hand_views = s->hand_views; a.view_scale = nullptr; a.loss = loss; a.dimage = nullptr;
-    a.n_hands = s->n_hands;
-    int rc = launch(s, "k_loss_partial", k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
-    if (rc) return rc;
-    return launch(s, "k_loss_final", k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
-}
 
 int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss, float* dimage,
             void* stream)
@@ -684,82 +665,6 @@ static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
     if (n <= 0) return HR_OK;
     long long blocks = std::min<long long>((n + 255) / 256, 4096);
     return launch(s, "k_fill", k_fill, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
-}
-
-static int backward_impl(hr_scene* s, const float* params, const float* verts, const float* albedo,
-                         const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
-                         uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
-                         float* grad_normals, hipStream_t st, bool edges_traced = false,
-                         hipEvent_t after_trace = nullptr, bool cleared = false, const AdamArgs* adam_params = nullptr)
-{
-    int rc;
-    if (!(flags & HR_REUSE_GEOMETRY)) {
-        rc = prepare(s, verts, st);
-        if (rc) return rc;
-    }
-    if (!cleared) {
-        const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
-        rc = fill(s, grad_albedo, nalb, 0.0f, st);
-        if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
-        if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
-        if (rc) return rc;
-    }
-    EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
-    int n_edge = 0, n_adj = 0;
-    if (flags & HR_GRAD_EDGES) {
-        // first part of the edge samples (tracing; learned sampling weights
-        // replace the length weights of the CDF), unless the caller ran it
-        if (!edges_traced) {
-            rc = edge_trace_impl(s, verts, albedo, background, iter, iter_dev, !(flags & HR_REUSE_GEOMETRY), st);
-            if (rc) return rc;
-        }
-        if (s->prop_kind == HR_PROPOSAL_LEARNED) {   // per-edge records for training
-            e.stat_a = s->prop.stat_a;
-            e.stat_dc = s->prop.stat_dc;
-        }
-        n_edge = kEdgeBlocks;
-    }
-    AdjointArgs a;
-    a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
-    a.faces = s->mesh.faces;
-    a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
-    a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
-    // the render's hits are valid for the geometry it prepared
-    a.hit_slot = (flags & HR_REUSE_GEOMETRY) ? s->hit_slot : nullptr;
-    a.hit_iter = s->hit_iter;
-    a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
-    a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
-    a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-    a.counts = s->counts + 4;
-    if (flags & HR_GRAD_INTERIOR) n_adj = s->adjoint_blocks;
-    if (n_edge + n_adj > 0) {
-        const dim3 grid(n_edge + n_adj);
-        if (s->counting)
-            rc = launch(s, "k_backward_trace", k_backward_trace<true>, grid, dim3(kThreads), 0, st, a, e, n_edge);
-        else
-            rc = launch(s, "k_backward_trace", k_backward_trace<false>, grid, dim3(kThreads), 0, st, a, e, n_edge);
-        if (rc) return rc;
-    }
-    if (after_trace && hipEventRecord(after_trace, st) != hipSuccess) return fail(HR_EHIP, "hr_backward: event");
-    GeomBwdArgs g;
-    g.m = s->mesh; g.params = params; g.verts = verts; g.gacc = s->gacc; g.gface = s->gface;
-    g.grad_verts = grad_verts; g.grad_normals = grad_normals; g.grad_params = grad_params;
-    g.adam_params = adam_params != nullptr;
-    g.stage_topology = s->geom_staged;
-    if (adam_params) g.adam = *adam_params;
-    rc = launch(s, "k_geom_bwd", k_geom_bwd, dim3(s->n_hands), dim3(kGeomThreads), s->smem_geom, st, g);
-    return rc;
-}
-
-int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
-                const float* dimage, uint32_t iter, uint32_t flags, float* grad_params, float* grad_albedo,
-                float* grad_verts, float* grad_normals, void* stream)
-{
-    if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
-        return fail(HR_EINVAL, "hr_backward: null argument");
-    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY)) return fail(HR_EINVAL, "hr_backward: unknown flags");
-    return backward_impl(s, params, verts, albedo, background, dimage, iter, nullptr, flags, grad_params, grad_albedo,
-                         grad_verts, grad_normals, (hipStream_t)stream);
 }
 
 static AdamArgs adam_args(hr_scene* s, float* params, float* albedo, const float* grad_params,
@@ -787,6 +692,99 @@ static int adam_launch(hr_scene* s, const AdamArgs& a, hipStream_t st)
     const long long n = 64ll * a.n_hands + a.n_albedo / 4;
     const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(2048, (n + 255) / 256));
     return launch(s, "k_adam", k_adam, dim3(blocks), dim3(256), 0, st, a);
+}
+
+static int backward_impl(hr_scene* s, const float* params, const float* verts, const float* albedo,
+                         const float* background, const float* dimage, uint32_t iter, const int* iter_dev,
+                         uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
+                         float* grad_normals, hipStream_t st, bool edges_traced = false,
+                         hipEvent_t after_trace = nullptr, bool cleared = false, const AdamArgs* adam = nullptr,
+                         const LossArgs* loss_value = nullptr)
+{
+    int rc;
+    if (!(flags & HR_REUSE_GEOMETRY)) {
+        rc = prepare(s, verts, st);
+        if (rc) return rc;
+    }
+    if (!cleared) {
+        const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
+        rc = fill(s, grad_albedo, nalb, 0.0f, st);
+        if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
+        if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
+        if (rc) return rc;
+    }
+    EdgeArgs e = edge_args(s, verts, albedo, background, dimage, iter, iter_dev);
+    int n_edge = 0, n_adj = 0;
+    if (flags & HR_GRAD_EDGES) {
+        // first part of the edge samples (tracing; learned sampling weights
+        // replace the length weights of the CDF), unless the caller ran it
+        if (!edges_traced) {
+            rc = edge_trace_impl(s, verts, albedo, background, iter, iter_dev, st);
+            if (rc) return rc;
+        }
+        if (s->prop_kind == HR_PROPOSAL_LEARNED) {   // per-edge records for training
+            e.stat_a = s->prop.stat_a;
+            e.stat_dc = s->prop.stat_dc;
+        }
+        n_edge = kEdgeBlocks;
+    }
+    AdjointArgs a;
+    a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
+    a.faces = s->mesh.faces;
+    a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
+    a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
+    // the render's hits are valid for the geometry it prepared
+    a.hit_slot = (flags & HR_REUSE_GEOMETRY) ? s->hit_slot : nullptr;
+    a.hit_iter = s->hit_iter;
+    a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
+    a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
+    a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
+    a.counts = s->counts + 4;
+    if (flags & HR_GRAD_INTERIOR) n_adj = s->adjoint_blocks;
+    // loss_value: the loss's chunk partials ride along (summed per hand by
+    // the geometry backward)
+    const int n_loss = loss_value ? s->n_chunks : 0;
+    const LossArgs l = loss_value ? *loss_value : LossArgs{};
+    if (n_edge + n_adj + n_loss > 0) {
+        const dim3 grid(n_edge + n_adj + n_loss);
+        if (s->counting)
+            rc = launch(s, "k_backward_trace", k_backward_trace<true>, grid, dim3(kThreads), 0, st, a, e, n_edge, l,
+                        n_loss);
+        else
+            rc = launch(s, "k_backward_trace", k_backward_trace<false>, grid, dim3(kThreads), 0, st, a, e, n_edge, l,
+                        n_loss);
+        if (rc) return rc;
+    }
+    if (after_trace && hipEventRecord(after_trace, st) != hipSuccess) return fail(HR_EHIP, "hr_backward: event");
+    GeomBwdArgs g;
+    g.m = s->mesh; g.params = params; g.verts = verts; g.gacc = s->gacc; g.gface = s->gface;
+    g.grad_verts = grad_verts; g.grad_normals = grad_normals; g.grad_params = grad_params;
+    // adam: the colour map's step (its gradient is final now), then the
+    // parameters' step at the end of each hand's geometry block
+    if (adam) {
+        AdamArgs aa = *adam;
+        aa.n_hands = 0;
+        rc = adam_launch(s, aa, st);
+        if (rc) return rc;
+    }
+    g.adam_params = adam != nullptr;
+    g.stage_topology = s->geom_staged;
+    if (adam) g.adam = *adam;
+    g.with_loss = loss_value != nullptr;
+    if (loss_value) g.loss = *loss_value;
+    rc = launch(s, "k_geom_bwd", k_geom_bwd, dim3(s->n_hands), dim3(kGeomThreads), s->smem_geom, st, g);
+    return rc;
+}
+
+int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,
+                const float* dimage, uint32_t iter, uint32_t flags, float* grad_params, float* grad_albedo,
+                float* grad_verts, float* grad_normals, void* stream)
+{
+    if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
+        return fail(HR_EINVAL, "hr_backward: null argument");
+    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY)) return fail(HR_EINVAL, "hr_backward: unknown flags");
+    return backward_impl(s, params, verts, albedo, background, dimage, iter, nullptr, flags, grad_params, grad_albedo,
+                         grad_verts, grad_normals, (hipStream_t)stream);
 }
 
 static int step_impl(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
@@ -840,64 +838,43 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     const int* it = q->iter;
     const bool learned = (flags & HR_GRAD_EDGES) && s->prop_kind == HR_PROPOSAL_LEARNED;
     const bool train = learned && !s->prop.z_override && s->prop.lr > 0.0f;
-    auto fork = [&](hipEvent_t ev) -> int {
-        if (hipEventRecord(ev, st) != hipSuccess || hipStreamWaitEvent(s->side, ev, 0) != hipSuccess)
-            return fail(HR_EHIP, "hr_iterate: fork");
-        return HR_OK;
-    };
     auto join = [&](hipEvent_t ev) -> int {
         if (hipEventRecord(ev, s->side) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess)
             return fail(HR_EHIP, "hr_iterate: join");
         return HR_OK;
     };
-    auto mark = [&](hipEvent_t ev, hipStream_t on) -> int {
-        return hipEventRecord(ev, on) == hipSuccess ? HR_OK : fail(HR_EHIP, "hr_iterate: event");
-    };
-    auto wait = [&](hipStream_t on, hipEvent_t ev) -> int {
-        return hipStreamWaitEvent(on, ev, 0) == hipSuccess ? HR_OK : fail(HR_EHIP, "hr_iterate: wait");
-    };
-    int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
-                    (const float*)q->params, q->verts, (float*)nullptr);
-    // side stream: the views' loss scales (mask only), the silhouette tables
-    // (vertices only), then, once the hierarchy is refitted, learned weights
-    // and the tracing of the edge samples (independent of the image gradient),
-    // beside the refit, the render and its loss gradient
+    // one stream: skinning (emptying the tile list), one preparation launch
+    // (refit, silhouette tables, tiles, loss scales), the learned weights and
+    // budget prefix, the render with the edge samples traced beside it and
+    // the loss gradient written with the image, the ray-tracing backward with
+    // the loss partial sums beside it, the geometry backward with the loss
+    // values and both Adam steps; training of a learned proposal on the side
+    // stream beside the geometry backward
     const bool edges = (flags & HR_GRAD_EDGES) != 0;
-    if (!rc) rc = fork(s->ev[0]);
-    if (!rc) rc = loss_scale_impl(s, q->mask, s->side);
-    if (!rc) rc = mark(s->ev[6], s->side);
-    if (!rc && edges) rc = edges_setup_impl(s, q->verts, s->side);
-    if (!rc) rc = prepare(s, q->verts, st);
-    if (!rc && edges) rc = fork(s->ev[4]);
-    if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, false, s->side);
-    if (!rc && edges) rc = mark(s->ev[1], s->side);
+    int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
+                    (const float*)q->params, q->verts, (float*)nullptr, s->tile_count);
+    if (!rc) rc = prepare(s, q->verts, st, false, true, q->mask);
+    if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, st, false);
     float* const clr[3] = {q->grad_albedo, s->gacc, s->gface};
     const long long clr_n[3] = {(long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3, (long long)s->n_hands * s->V * 6,
                                 (long long)s->n_hands * s->F * 18};
-    if (!rc) rc = wait(st, s->ev[6]);
     if (!rc)
         rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true, clr, clr_n,
-                         q->target, q->mask, q->dimage);
-    // the loss values beside the backward
-    if (!rc) rc = fork(s->ev[5]);
-    if (!rc) rc = loss_value_impl(s, q->image, q->target, q->mask, q->loss, s->side);
-    if (!rc && edges) rc = wait(st, s->ev[1]);
-    // training (needs the records of the edge samples) beside the geometry
-    // backward and the parameter step
-    // the parameters' step ends the geometry backward; the colour map's
-    // (final once the ray-tracing backward is done) and the training run on
-    // the side stream beside it
-    AdamArgs adam = adam_args(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params, q->v_params,
-                              q->m_albedo, q->v_albedo, 1, it, cfg);
+                         q->target, q->mask, q->dimage, edges ? kEdgeBlocks : 0);
+    LossArgs lv;
+    lv.chunks = s->chunks; lv.views = s->views; lv.image = q->image; lv.target = q->target; lv.mask = q->mask;
+    lv.partial = s->loss_partial; lv.view_chunk_off = s->view_chunk_off; lv.hand_view_off = s->hand_view_off;
+    lv.hand_views = s->hand_views; lv.view_scale = nullptr; lv.loss = q->loss; lv.dimage = nullptr;
+    lv.n_hands = s->n_hands;
+    const AdamArgs adam = adam_args(s, q->params, q->albedo, q->grad_params, q->grad_albedo, q->m_params,
+                                    q->v_params, q->m_albedo, q->v_albedo, 1, it, cfg);
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st, edges, s->ev[2], true, &adam);
-    if (!rc) rc = wait(s->side, s->ev[2]);
-    adam.n_hands = 0;
-    if (!rc) rc = adam_launch(s, adam, s->side);
+                           nullptr, st, edges, train ? s->ev[0] : nullptr, true, &adam, &lv);
+    if (!rc && train && hipStreamWaitEvent(s->side, s->ev[0], 0) != hipSuccess) rc = fail(HR_EHIP, "hr_iterate: fork");
     if (!rc && train) rc = proposal_train_impl(s, s->side);
-    if (!rc) rc = join(s->ev[3]);
+    if (!rc && train) rc = join(s->ev[1]);
     if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
     return rc;
 }
@@ -1001,7 +978,7 @@ int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_ho
     // the candidates' results are discarded; the iteration index stays on the host
     auto run = [&](bool adjoint) -> int {
         int r = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
-                       (const float*)q.params, q.verts, (float*)nullptr);
+                       (const float*)q.params, q.verts, (float*)nullptr, (int*)nullptr);
         if (!r) r = render_impl(s, q.verts, q.albedo, q.background, 0, nullptr, q.image, nullptr, st);
         if (!r && adjoint) {
             r = loss_impl(s, q.image, q.target, q.mask, q.loss, q.dimage, st);

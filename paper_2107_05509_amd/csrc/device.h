@@ -16,7 +16,6 @@ constexpr int kMaxStack = 24;       // traversal stack entries per lane
 constexpr int kLeafMax = 4;         // triangles per leaf
 constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
 constexpr int kEdgeBlocks = 256;    // blocks of edge samples in the backward launch
-constexpr int kSetupThreads = 1024; // threads of a view's silhouette-table block
 constexpr int kMaxTraceBlocks = 4096;   // largest persistent ray-tracing grid
 constexpr int kWin = 16;            // texel window (per row of 16 lanes) of the colour-map gradient
 constexpr int kWaveWin = 4 * 3 * kWin * kWin;   // floats of one wave's four row windows (RGB)

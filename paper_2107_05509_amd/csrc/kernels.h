@@ -177,6 +177,25 @@ struct AdamArgs {
     const int* iter_dev;       // nullable: step count = *iter_dev + 1, bias corrections on the device
 };
 
+// one launch of geometry preparation (k_prepare)
+struct PrepArgs {
+    MeshDev m;
+    BvhDev b;
+    const float* verts;
+    float* normals;
+    Tri* tris;
+    Node* nodes;
+    EdgeArgs e;                // with_setup: the silhouette tables
+    const ViewDev* views;
+    TileShape ts;
+    int2* tiles;
+    int* tile_count;           // zero before the launch
+    int4* view_rect;
+    const uint8_t* mask;       // with_scale (nullable: all pixels)
+    float* view_scale;
+    int n_hands, n_views, with_setup, with_scale;
+};
+
 // geometry backward of one hand per block (k_geom_bwd)
 constexpr int kGeomThreads = 1024;
 struct GeomBwdArgs {
@@ -191,6 +210,8 @@ struct GeomBwdArgs {
     AdamArgs adam;             // with adam_params: the parameters' step
     int adam_params;
     int stage_topology;        // triangles and vertex-to-triangle lists fit in LDS
+    LossArgs loss;             // with_loss: each hand's block sums its loss value from the chunk partials
+    int with_loss;
 };
 
 }  // namespace hr

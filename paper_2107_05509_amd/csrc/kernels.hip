@@ -229,10 +229,13 @@ __device__ __forceinline__ void blend_vertex(const JointState& js, const float* 
 
 // Skinning, grid (vertex blocks, hands).
 __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict__ params,
-                                              float* __restrict__ verts, float* __restrict__ joints)
+                                              float* __restrict__ verts, float* __restrict__ joints,
+                                              int* __restrict__ tile_count)
 {
     __shared__ JointState js;
     const int h = blockIdx.y;
+    // nullable: the wave-tile list of a following refit starts empty
+    if (tile_count && blockIdx.x == 0 && h == 0 && threadIdx.x == 0) *tile_count = 0;
     const float* p = params + 64 * h;
     joint_state(m, p, js);
     const float* tau = p + 61;
@@ -262,13 +265,10 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
 // geometry preparation: vertex normals, triangles in leaf order, BVH refit
 // ===========================================================================
 
-__global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const float* __restrict__ verts,
-                                                 float* __restrict__ normals, Tri* __restrict__ tris,
-                                                 Node* __restrict__ nodes, int* __restrict__ tile_count)
+__device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __restrict__ verts,
+                           float* __restrict__ normals, Tri* __restrict__ tris, Node* __restrict__ nodes, int h,
+                           float* dyn)
 {
-    extern __shared__ float dyn[];
-    const int h = blockIdx.x;
-    if (h == 0 && threadIdx.x == 0) *tile_count = 0;   // the screen-bounds pass appends next
     const int V = m.V, F = m.F;
     float* vsh = dyn;                 // [V*3]
     float* fn = vsh + 3 * V;          // [F*3]
@@ -363,14 +363,13 @@ __global__ void __launch_bounds__(512) k_prepare(MeshDev m, BvhDev b, const floa
 // tiles (tw x th pixels, all samples of a pixel in one wave) appended to
 // `tiles` (order across views is arbitrary).  The whole view is listed if any
 // vertex is not in front of the camera.
-__global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* __restrict__ views,
-                                                     const float* __restrict__ verts, TileShape ts,
-                                                     int2* __restrict__ tiles, int* __restrict__ tile_count,
-                                                     int4* __restrict__ view_rect)
+__device__ void view_bounds(const MeshDev& m, const ViewDev* __restrict__ views, const float* __restrict__ verts,
+                            TileShape ts, int2* __restrict__ tiles, int* __restrict__ tile_count,
+                            int4* __restrict__ view_rect, int vi)
 {
-    __shared__ float red[4 * 4];
+    __shared__ float red[4 * 16];
     __shared__ int base;
-    const ViewDev c = views[blockIdx.x];
+    const ViewDev c = views[vi];
     const float* vh = verts + (size_t)c.hand * m.V * 3;
     float mnx = 3e38f, mny = 3e38f, mxx = -3e38f, mxy = -3e38f;
     int bad = 0;
@@ -414,15 +413,56 @@ __global__ void __launch_bounds__(256) k_view_bounds(MeshDev m, const ViewDev* _
     if (threadIdx.x == 0) {
         base = count > 0 ? atomicAdd(tile_count, count) : 0;
         // pixel rectangle covered by the view's tiles (empty if none)
-        view_rect[blockIdx.x] = count > 0 ? make_int4(tx0 << ts.tw_log2, ty0 << ts.th_log2,
+        view_rect[vi] = count > 0 ? make_int4(tx0 << ts.tw_log2, ty0 << ts.th_log2,
                                                        min(c.W, (tx0 + nx) << ts.tw_log2),
                                                        min(c.H, (ty0 + ny) << ts.th_log2))
                                           : make_int4(0, 0, 0, 0);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < count; i += blockDim.x)
-        tiles[base + i] = make_int2(blockIdx.x, (tx0 + i % nx) | ((ty0 + i / nx) << 16));
+        tiles[base + i] = make_int2(vi, (tx0 + i % nx) | ((ty0 + i / nx) << 16));
 }
+
+// Loss scale of view vi from its mask: 1 / (3 * masked pixels), 0 if none
+// (the value the loss kernels derive from their exact per-chunk counts).
+__device__ void mask_scale(const ViewDev* __restrict__ views, const uint8_t* __restrict__ mask,
+                           float* __restrict__ view_scale, int vi)
+{
+    __shared__ int red[16];
+    const ViewDev c = views[vi];
+    const long long n = (long long)c.W * c.H;
+    long long cnt = 0;
+    if (!mask) {
+        cnt = threadIdx.x == 0 ? n : 0;
+    } else {
+        const uint8_t* mv = mask + c.pix0;
+        // bytes up to a 16-byte boundary, then 16 at a time, then the tail
+        const long long head = min(n, (long long)((16 - ((uintptr_t)mv & 15)) & 15));
+        const long long n16 = (n - head) >> 4;
+        for (long long i = threadIdx.x; i < head; i += blockDim.x) cnt += mv[i] != 0;
+        const uint4* m16 = reinterpret_cast<const uint4*>(mv + head);
+        for (long long i = threadIdx.x; i < n16; i += blockDim.x) {
+            const uint4 q = m16[i];
+            const unsigned int w[4] = {q.x, q.y, q.z, q.w};
+            for (int k = 0; k < 4; ++k)
+                cnt += ((w[k] & 0xFFu) != 0) + ((w[k] & 0xFF00u) != 0) + ((w[k] & 0xFF0000u) != 0) +
+                       ((w[k] & 0xFF000000u) != 0);
+        }
+        for (long long i = head + 16 * n16 + threadIdx.x; i < n; i += blockDim.x) cnt += mv[i] != 0;
+    }
+    int ci = (int)cnt;
+    for (int o = 32; o > 0; o >>= 1) ci += __shfl_xor(ci, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ci;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long tot = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += red[k];
+        const float tc = (float)tot;
+        view_scale[vi] = tc > 0.0f ? 1.0f / (3.0f * tc) : 0.0f;
+    }
+}
+
+
 
 // ===========================================================================
 // render
@@ -590,10 +630,12 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
 // L1 loss
 // ===========================================================================
 
-__global__ void __launch_bounds__(256) k_loss_partial(LossArgs a)
+// partial sums of chunk ck: |image - target| over masked pixels and the
+// masked-pixel count (blocks of 256 threads)
+__device__ void loss_partial(const LossArgs& a, int chunk)
 {
     __shared__ float red[2 * 16];
-    const int2 ck = a.chunks[blockIdx.x];   // (view, first pixel in view)
+    const int2 ck = a.chunks[chunk];   // (view, first pixel in view)
     const ViewDev c = a.views[ck.x];
     const long long n = (long long)c.W * c.H;
     float s = 0.0f, cnt = 0.0f;
@@ -615,38 +657,81 @@ __global__ void __launch_bounds__(256) k_loss_partial(LossArgs a)
     if (threadIdx.x == 0) {
         float ts = 0.0f, tc = 0.0f;
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ts += red[2 * k]; tc += red[2 * k + 1]; }
-        a.partial[2 * blockIdx.x] = ts;
-        a.partial[2 * blockIdx.x + 1] = tc;
+        a.partial[2 * chunk] = ts;
+        a.partial[2 * chunk + 1] = tc;
     }
 }
 
-// one block per hand: per view, the chunk partials are summed in a fixed order
-__global__ void __launch_bounds__(256) k_loss_final(LossArgs a)
+__global__ void __launch_bounds__(256) k_loss_partial(LossArgs a)
+{
+    loss_partial(a, blockIdx.x);
+}
+
+// Hand h: per view, the chunk partials summed in a fixed order by the first
+// 256 threads (the block may be larger; all of it reaches the barriers).
+__device__ void loss_final(const LossArgs& a, int h)
 {
     __shared__ float red[2 * 4];
-    const int h = blockIdx.x;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
     float loss = 0.0f;
     for (int q = a.hand_view_off[h]; q < a.hand_view_off[h + 1]; ++q) {
         const int v = a.hand_views[q];
         float s = 0.0f, cnt = 0.0f;
-        for (int k = a.view_chunk_off[v] + threadIdx.x; k < a.view_chunk_off[v + 1]; k += blockDim.x) {
-            s += a.partial[2 * k];
-            cnt += a.partial[2 * k + 1];
-        }
+        if (t < 256)
+            for (int k = a.view_chunk_off[v] + t; k < a.view_chunk_off[v + 1]; k += 256) {
+                s += a.partial[2 * k];
+                cnt += a.partial[2 * k + 1];
+            }
         s = wave_sum(s);
         cnt = wave_sum(cnt);
-        if (lane == 0) { red[2 * w] = s; red[2 * w + 1] = cnt; }
+        if (lane == 0 && w < 4) { red[2 * w] = s; red[2 * w + 1] = cnt; }
         __syncthreads();
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             float ts = 0.0f, tc = 0.0f;
-            for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { ts += red[2 * k]; tc += red[2 * k + 1]; }
+            for (int k = 0; k < 4; ++k) { ts += red[2 * k]; tc += red[2 * k + 1]; }
             if (a.view_scale) a.view_scale[v] = tc > 0.0f ? 1.0f / (3.0f * tc) : 0.0f;
             if (tc > 0.0f) loss += ts / (3.0f * tc);
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && a.loss) a.loss[h] = loss;
+    if (t == 0 && a.loss) a.loss[h] = loss;
+}
+
+// one block (256 threads) per hand
+__global__ void __launch_bounds__(256) k_loss_final(LossArgs a)
+{
+    loss_final(a, blockIdx.x);
+}
+
+// Loss value of hand h from the chunk partials inside a larger block: one
+// wave per view (16 views per pass), the views then added in order.
+__device__ void loss_value_hand(const LossArgs& a, int h)
+{
+    __shared__ float red[2 * 16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int q0 = a.hand_view_off[h], q1 = a.hand_view_off[h + 1];
+    float loss = 0.0f;
+    for (int qb = q0; qb < q1; qb += 16) {
+        const int q = qb + w;
+        float s = 0.0f, cnt = 0.0f;
+        if (w < 16 && q < q1) {
+            const int v = a.hand_views[q];
+            for (int k = a.view_chunk_off[v] + lane; k < a.view_chunk_off[v + 1]; k += 64) {
+                s += a.partial[2 * k];
+                cnt += a.partial[2 * k + 1];
+            }
+        }
+        s = wave_sum(s);
+        cnt = wave_sum(cnt);
+        if (lane == 0 && w < 16) { red[2 * w] = s; red[2 * w + 1] = cnt; }
+        __syncthreads();
+        if (t == 0)
+            for (int k = 0; k < 16 && qb + k < q1; ++k)
+                if (red[2 * k + 1] > 0.0f) loss += red[2 * k] / (3.0f * red[2 * k + 1]);
+        __syncthreads();
+    }
+    if (t == 0) a.loss[h] = loss;
 }
 
 __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
@@ -1008,6 +1093,34 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
     }
 }
 
+// Geometry preparation in one launch: blocks [0, H) refit hand h (vertex
+// normals, triangles in leaf order, hierarchy bounds); then per view the
+// silhouette table (with_setup), the screen bounds and wave tiles (the tile
+// count is zero beforehand) and the loss scale from the mask (with_scale).
+__global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
+{
+    extern __shared__ float dyn[];
+    int bid = blockIdx.x;
+    if (bid < a.n_hands) {
+        refit_hand(a.m, a.b, a.verts, a.normals, a.tris, a.nodes, bid, dyn);
+        return;
+    }
+    bid -= a.n_hands;
+    if (a.with_setup) {
+        if (bid < a.n_views) {
+            edges_setup_view(a.e, bid, reinterpret_cast<unsigned long long*>(dyn));
+            return;
+        }
+        bid -= a.n_views;
+    }
+    if (bid < a.n_views) {
+        view_bounds(a.m, a.views, a.verts, a.ts, a.tiles, a.tile_count, a.view_rect, bid);
+        return;
+    }
+    bid -= a.n_views;
+    if (a.with_scale && bid < a.n_views) mask_scale(a.views, a.mask, a.view_scale, bid);
+}
+
 // ===========================================================================
 // edge sampling (boundary term)
 // ===========================================================================
@@ -1275,21 +1388,17 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int
 // Render; the first `n_setup` blocks build the silhouette tables of the views
 // (they need only the geometry) alongside the render blocks.
 template <bool COUNT>
-__global__ void __launch_bounds__(kThreads) k_render(RenderArgs a, EdgeArgs e, int n_setup)
+__global__ void __launch_bounds__(kThreads, 4) k_render(RenderArgs a, EdgeArgs e, int n_edge)
 {
-    __shared__ unsigned long long part[kThreads];
-    __shared__ int stack[kMaxStack * (kThreads / 64)];
-    if ((int)blockIdx.x < n_setup) {
-        edges_setup_view(e, blockIdx.x, part);
+    // edge blocks trace the edge samples' side points (a traversal stack per
+    // lane) beside the render blocks (one stack per wave)
+    __shared__ int stack[kMaxStack * kThreads];
+    __shared__ int wstack[kMaxStack * (kThreads / 64)];
+    if ((int)blockIdx.x < n_edge) {
+        edge_samples<COUNT, kEdgeTrace>(e, blockIdx.x, n_edge, stack, wstack);
         return;
     }
-    render_tiles<COUNT>(a, (int)blockIdx.x - n_setup, (int)gridDim.x - n_setup, stack);
-}
-
-__global__ void __launch_bounds__(kSetupThreads) k_edges_setup(EdgeArgs e)
-{
-    __shared__ unsigned long long part[kSetupThreads];
-    edges_setup_view(e, blockIdx.x, part);
+    render_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, wstack);
 }
 
 // Edge samples, first part: trace and shade both side points of every stored
@@ -1306,7 +1415,8 @@ __global__ void __launch_bounds__(kThreads) k_edge_trace(EdgeArgs e)
 // rest run the interior adjoint; in one launch the latency-bound edge
 // samples overlap with the adjoint's arithmetic.
 template <bool COUNT>
-__global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge)
+__global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge, LossArgs l,
+                                                             int n_loss)
 {
     // edge blocks: a traversal stack per lane; adjoint blocks: the texel
     // windows of their waves in the same memory
@@ -1318,7 +1428,13 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
         edge_samples<COUNT, kEdgeWeigh>(e, blockIdx.x, n_edge, lds, wstack);
         return;
     }
-    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, wstack, reinterpret_cast<float*>(lds));
+    // the last n_loss blocks: partial sums of the loss value (chunk per block)
+    const int n_adj = (int)gridDim.x - n_edge - n_loss;
+    if ((int)blockIdx.x >= n_edge + n_adj) {
+        loss_partial(l, (int)blockIdx.x - n_edge - n_adj);
+        return;
+    }
+    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, n_adj, wstack, reinterpret_cast<float*>(lds));
 }
 
 // ===========================================================================
@@ -1444,6 +1560,43 @@ __device__ __forceinline__ void adam_bias(const AdamArgs& a, float& bc1, float& 
 __device__ __forceinline__ float param_lr(const AdamArgs& a, int k)
 {
     return k < 3 ? a.lr[0] : k < 48 ? a.lr[1] : k < 58 ? a.lr[2] : k < 61 ? a.lr[3] : a.lr[4];
+}
+
+// Adam on the parameters (64 per hand) and on the colour map (clamped to
+// [0, 1], four entries per step), grid-stride over thread index tid of n.
+__device__ __forceinline__ void adam_params_part(const AdamArgs& a, float bc1, float bc2, long long tid,
+                                                 long long stride)
+{
+    const long long np = 64ll * a.n_hands;
+    for (long long i = tid; i < np; i += stride) {
+        const float lr = param_lr(a, (int)(i % 64));
+        if (lr != 0.0f)
+            a.params[i] = adam_update(a.params[i], a.m_params + i, a.v_params + i, a.grad_params[i], lr, a, bc1, bc2);
+    }
+}
+
+__device__ __forceinline__ void adam_albedo_part(const AdamArgs& a, float bc1, float bc2, long long tid,
+                                                 long long stride)
+{
+    const float lr = a.lr[5];
+    if (lr == 0.0f) return;
+    const long long n4 = a.n_albedo >> 2;
+    float4* x4 = reinterpret_cast<float4*>(a.albedo);
+    float4* m4 = reinterpret_cast<float4*>(a.m_albedo);
+    float4* v4 = reinterpret_cast<float4*>(a.v_albedo);
+    const float4* g4 = reinterpret_cast<const float4*>(a.grad_albedo);
+    for (long long q = tid; q < n4; q += stride) {
+        float4 x = x4[q], mm = m4[q], vv = v4[q];
+        const float4 g = g4[q];
+        x.x = fminf(fmaxf(adam_update(x.x, &mm.x, &vv.x, g.x, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x.y = fminf(fmaxf(adam_update(x.y, &mm.y, &vv.y, g.y, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x.z = fminf(fmaxf(adam_update(x.z, &mm.z, &vv.z, g.z, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x.w = fminf(fmaxf(adam_update(x.w, &mm.w, &vv.w, g.w, lr, a, bc1, bc2), 0.0f), 1.0f);
+        x4[q] = x; m4[q] = mm; v4[q] = vv;
+    }
+    for (long long j = 4 * n4 + tid; j < a.n_albedo; j += stride)
+        a.albedo[j] = fminf(fmaxf(adam_update(a.albedo[j], a.m_albedo + j, a.v_albedo + j, a.grad_albedo[j], lr, a,
+                                              bc1, bc2), 0.0f), 1.0f);
 }
 
 // sum of v over the wave added to *dst (LDS) by one lane
@@ -1602,6 +1755,7 @@ __device__ __forceinline__ void geom_vertices(const GeomBwdArgs& a, const MeshDe
 // Dynamic LDS: 9 V floats (+ 6 F + V + 1 ints when staged).
 __global__ void __launch_bounds__(kGeomThreads) k_geom_bwd(GeomBwdArgs a)
 {
+    if (a.with_loss) loss_value_hand(a.loss, blockIdx.x);
     extern __shared__ float gdyn[];
     __shared__ JointState js;
     __shared__ float acc[kSkinPart];
@@ -1650,38 +1804,14 @@ __global__ void __launch_bounds__(kGeomThreads) k_geom_bwd(GeomBwdArgs a)
     }
 }
 
-// Adam on the parameters (64 per hand) and the colour map (clamped to
-// [0, 1], four entries per step), grid-stride.
 __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 {
     float bc1, bc2;
     adam_bias(a, bc1, bc2);
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    const long long np = 64ll * a.n_hands;
-    for (long long i = tid; i < np; i += stride) {
-        const float lr = param_lr(a, (int)(i % 64));
-        if (lr != 0.0f) a.params[i] = adam_update(a.params[i], a.m_params + i, a.v_params + i, a.grad_params[i], lr, a, bc1, bc2);
-    }
-    const float lr = a.lr[5];
-    if (lr == 0.0f) return;
-    const long long n4 = a.n_albedo >> 2;
-    float4* x4 = reinterpret_cast<float4*>(a.albedo);
-    float4* m4 = reinterpret_cast<float4*>(a.m_albedo);
-    float4* v4 = reinterpret_cast<float4*>(a.v_albedo);
-    const float4* g4 = reinterpret_cast<const float4*>(a.grad_albedo);
-    for (long long q = tid; q < n4; q += stride) {
-        float4 x = x4[q], mm = m4[q], vv = v4[q];
-        const float4 g = g4[q];
-        x.x = fminf(fmaxf(adam_update(x.x, &mm.x, &vv.x, g.x, lr, a, bc1, bc2), 0.0f), 1.0f);
-        x.y = fminf(fmaxf(adam_update(x.y, &mm.y, &vv.y, g.y, lr, a, bc1, bc2), 0.0f), 1.0f);
-        x.z = fminf(fmaxf(adam_update(x.z, &mm.z, &vv.z, g.z, lr, a, bc1, bc2), 0.0f), 1.0f);
-        x.w = fminf(fmaxf(adam_update(x.w, &mm.w, &vv.w, g.w, lr, a, bc1, bc2), 0.0f), 1.0f);
-        x4[q] = x; m4[q] = mm; v4[q] = vv;
-    }
-    for (long long j = 4 * n4 + tid; j < a.n_albedo; j += stride)
-        a.albedo[j] = fminf(fmaxf(adam_update(a.albedo[j], a.m_albedo + j, a.v_albedo + j, a.grad_albedo[j], lr, a,
-                                              bc1, bc2), 0.0f), 1.0f);
+    adam_params_part(a, bc1, bc2, tid, stride);
+    adam_albedo_part(a, bc1, bc2, tid, stride);
 }
 
 __global__ void k_advance(int* p)
