@@ -98,8 +98,12 @@ struct hr_scene {
     long long* edge_budget = nullptr;
     long long* edge_prefix = nullptr;
     size_t smem_prepare = 0;
-    size_t smem_geom = 0;
-    bool geom_staged = false;
+    float* geom_gr = nullptr;     // [hands,V,3] geometry backward: raw-normal gradients
+    float* geom_gpos = nullptr;   // [hands,V,3] slot gradients
+    float* geom_part = nullptr;   // [hands,geom_blocks,kSkinPart] block rows of the skinning sums
+    int* geom_count = nullptr;    // [hands] finished blocks (reset by the last)
+    float* joint_state = nullptr; // [hands, joint state] of hr_iterate's skinning, for its backward
+    int geom_blocks = 0;
     unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
     // learned edge-sampling proposal (hr_proposal_*)
     bool prop_alloc = false;
@@ -399,6 +403,16 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload<EdgeSample>(&s->samples, nullptr, (size_t)cap));
     }
     s->skin_blocks = (V + 127) / 128;
+    s->geom_blocks = (V + 63) / 64;
+    TRY(s->upload<float>(&s->geom_gr, nullptr, (size_t)n_hands * V * 3));
+    TRY(s->upload<float>(&s->geom_gpos, nullptr, (size_t)n_hands * V * 3));
+    TRY(s->upload<float>(&s->geom_part, nullptr, (size_t)n_hands * s->geom_blocks * kSkinPart));
+    TRY(s->upload<int>(&s->geom_count, nullptr, (size_t)n_hands));
+    TRY(s->upload<float>(&s->joint_state, nullptr, (size_t)n_hands * kJointStateFloats));
+    if (hipMemset(s->geom_count, 0, sizeof(int) * n_hands) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EHIP, "scene init: memset");
+    }
     TRY(s->upload<float>(&s->loss_partial, nullptr, 2 * (size_t)s->n_chunks));
     TRY(s->upload<float>(&s->view_scale, nullptr, n_views));
     TRY(s->upload<EdgeRec>(&s->edge_rec, nullptr, (size_t)n_views * E));
@@ -420,15 +434,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         }
 #undef TRY
     s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.node_stride);
-    // the geometry backward keeps the triangles and vertex-to-triangle lists
-    // in LDS when they fit beside its per-vertex arrays
-    s->smem_geom = sizeof(float) * 9 * (size_t)V;
-    s->geom_staged = s->smem_geom + sizeof(int) * (6 * (size_t)F + V + 1) <= 96 * 1024;
-    if (s->geom_staged) s->smem_geom += sizeof(int) * (6 * (size_t)F + V + 1);
     if (hipFuncSetAttribute((const void*)k_prepare, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)s->smem_prepare) != hipSuccess ||
-        hipFuncSetAttribute((const void*)k_geom_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)s->smem_geom) != hipSuccess) {
+                            (int)s->smem_prepare) != hipSuccess) {
         hr_scene_destroy(s);
         return fail(HR_EUNSUPPORTED, "hr_scene_create: mesh needs more LDS than a workgroup has");
     }
@@ -441,7 +448,7 @@ int hr_skin(hr_scene* s, const float* params, float* verts, float* joints, void*
     if (!s || !params || !verts) return fail(HR_EINVAL, "hr_skin: null argument");
     hipStream_t st = (hipStream_t)stream;
     return launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh, params, verts,
-                  joints, (int*)nullptr);
+                  joints, (int*)nullptr, (float*)nullptr);
 }
 
 int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
@@ -699,7 +706,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
                          uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
                          float* grad_normals, hipStream_t st, bool edges_traced = false,
                          hipEvent_t after_trace = nullptr, bool cleared = false, const AdamArgs* adam = nullptr,
-                         const LossArgs* loss_value = nullptr)
+                         const LossArgs* loss_value = nullptr, const float* js_saved = nullptr)
 {
     int rc;
     if (!(flags & HR_REUSE_GEOMETRY)) {
@@ -768,11 +775,14 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
         if (rc) return rc;
     }
     g.adam_params = adam != nullptr;
-    g.stage_topology = s->geom_staged;
     if (adam) g.adam = *adam;
     g.with_loss = loss_value != nullptr;
     if (loss_value) g.loss = *loss_value;
-    rc = launch(s, "k_geom_bwd", k_geom_bwd, dim3(s->n_hands), dim3(kGeomThreads), s->smem_geom, st, g);
+    g.gr = s->geom_gr; g.gpos = s->geom_gpos; g.part = s->geom_part; g.counter = s->geom_count;
+    g.js_saved = js_saved;
+    // one more block per hand (the last) sums the loss value
+    rc = launch(s, "k_geom_p1", k_geom_p1, dim3((s->V + 255) / 256 + 1, s->n_hands), dim3(256), 0, st, g);
+    if (!rc) rc = launch(s, "k_geom_p2", k_geom_p2, dim3(s->geom_blocks, s->n_hands), dim3(64), 0, st, g);
     return rc;
 }
 
@@ -852,7 +862,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     // stream beside the geometry backward
     const bool edges = (flags & HR_GRAD_EDGES) != 0;
     int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
-                    (const float*)q->params, q->verts, (float*)nullptr, s->tile_count);
+                    (const float*)q->params, q->verts, (float*)nullptr, s->tile_count, s->joint_state);
     if (!rc) rc = prepare(s, q->verts, st, false, true, q->mask);
     if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, st, false);
     float* const clr[3] = {q->grad_albedo, s->gacc, s->gface};
@@ -871,7 +881,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st, edges, train ? s->ev[0] : nullptr, true, &adam, &lv);
+                           nullptr, st, edges, train ? s->ev[0] : nullptr, true, &adam, &lv, s->joint_state);
     if (!rc && train && hipStreamWaitEvent(s->side, s->ev[0], 0) != hipSuccess) rc = fail(HR_EHIP, "hr_iterate: fork");
     if (!rc && train) rc = proposal_train_impl(s, s->side);
     if (!rc && train) rc = join(s->ev[1]);
@@ -978,7 +988,7 @@ int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_ho
     // the candidates' results are discarded; the iteration index stays on the host
     auto run = [&](bool adjoint) -> int {
         int r = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
-                       (const float*)q.params, q.verts, (float*)nullptr, (int*)nullptr);
+                       (const float*)q.params, q.verts, (float*)nullptr, (int*)nullptr, (float*)nullptr);
         if (!r) r = render_impl(s, q.verts, q.albedo, q.background, 0, nullptr, q.image, nullptr, st);
         if (!r && adjoint) {
             r = loss_impl(s, q.image, q.target, q.mask, q.loss, q.dimage, st);

@@ -196,8 +196,7 @@ struct PrepArgs {
     int n_hands, n_views, with_setup, with_scale;
 };
 
-// geometry backward of one hand per block (k_geom_bwd)
-constexpr int kGeomThreads = 1024;
+// geometry backward (k_geom_p1, k_geom_p2)
 struct GeomBwdArgs {
     MeshDev m;
     const float* params;       // [H,64]
@@ -209,9 +208,13 @@ struct GeomBwdArgs {
     float* grad_params;        // [H,64]
     AdamArgs adam;             // with adam_params: the parameters' step
     int adam_params;
-    int stage_topology;        // triangles and vertex-to-triangle lists fit in LDS
-    LossArgs loss;             // with_loss: each hand's block sums its loss value from the chunk partials
+    LossArgs loss;             // with_loss: the hand's loss value from the chunk partials
     int with_loss;
+    float* gr;                 // [H,V,3] dL/d(raw vertex normal) (first launch -> second)
+    float* gpos;               // [H,V,3] dL/dv from the slots
+    float* part;               // [H, vertex blocks, kSkinPart] block rows of the skinning sums
+    int* counter;              // [H] finished blocks (zero between launches)
+    const float* js_saved;     // nullable: [H, joint state] left by the skinning of the same parameters
 };
 
 }  // namespace hr

@@ -99,6 +99,7 @@ struct JointState {
     float J[kMaxJoints * 3];      // rest joint positions (shaped)
     float Rp[9];                  // global rotation
 };
+constexpr int kJointStateFloats = sizeof(JointState) / sizeof(float);
 
 // Small per-vertex and per-joint tables are read into registers with loads
 // that do not depend on a branch (indices clamped into range, the surplus
@@ -230,7 +231,7 @@ __device__ __forceinline__ void blend_vertex(const JointState& js, const float* 
 // Skinning, grid (vertex blocks, hands).
 __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict__ params,
                                               float* __restrict__ verts, float* __restrict__ joints,
-                                              int* __restrict__ tile_count)
+                                              int* __restrict__ tile_count, float* __restrict__ js_out)
 {
     __shared__ JointState js;
     const int h = blockIdx.y;
@@ -238,6 +239,12 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
     if (tile_count && blockIdx.x == 0 && h == 0 && threadIdx.x == 0) *tile_count = 0;
     const float* p = params + 64 * h;
     joint_state(m, p, js);
+    // nullable: the joint state of these parameters for the backward
+    if (js_out && blockIdx.x == 0) {
+        const float* src = reinterpret_cast<const float*>(&js);
+        for (int i = threadIdx.x; i < kJointStateFloats; i += blockDim.x)
+            js_out[(size_t)h * kJointStateFloats + i] = src[i];
+    }
     const float* tau = p + 61;
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     float bk[kMaxShape];
@@ -704,18 +711,19 @@ __global__ void __launch_bounds__(256) k_loss_final(LossArgs a)
     loss_final(a, blockIdx.x);
 }
 
-// Loss value of hand h from the chunk partials inside a larger block: one
-// wave per view (16 views per pass), the views then added in order.
+// Loss value of hand h from the chunk partials inside a block of up to 16
+// waves: one wave per view, the views then added in order.
 __device__ void loss_value_hand(const LossArgs& a, int h)
 {
     __shared__ float red[2 * 16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int nw = min((int)(blockDim.x >> 6), 16);
     const int q0 = a.hand_view_off[h], q1 = a.hand_view_off[h + 1];
     float loss = 0.0f;
-    for (int qb = q0; qb < q1; qb += 16) {
+    for (int qb = q0; qb < q1; qb += nw) {
         const int q = qb + w;
         float s = 0.0f, cnt = 0.0f;
-        if (w < 16 && q < q1) {
+        if (w < nw && q < q1) {
             const int v = a.hand_views[q];
             for (int k = a.view_chunk_off[v] + lane; k < a.view_chunk_off[v + 1]; k += 64) {
                 s += a.partial[2 * k];
@@ -724,10 +732,10 @@ __device__ void loss_value_hand(const LossArgs& a, int h)
         }
         s = wave_sum(s);
         cnt = wave_sum(cnt);
-        if (lane == 0 && w < 16) { red[2 * w] = s; red[2 * w + 1] = cnt; }
+        if (lane == 0 && w < nw) { red[2 * w] = s; red[2 * w + 1] = cnt; }
         __syncthreads();
         if (t == 0)
-            for (int k = 0; k < 16 && qb + k < q1; ++k)
+            for (int k = 0; k < nw && qb + k < q1; ++k)
                 if (red[2 * k + 1] > 0.0f) loss += red[2 * k] / (3.0f * red[2 * k + 1]);
         __syncthreads();
     }
@@ -1599,208 +1607,220 @@ __device__ __forceinline__ void adam_albedo_part(const AdamArgs& a, float bc1, f
                                               bc1, bc2), 0.0f), 1.0f);
 }
 
-// sum of v over the wave added to *dst (LDS) by one lane
-__device__ __forceinline__ void wave_add_lds(float* dst, float v)
+// sum of v over the wave stored to *dst (LDS) by one lane (blocks of one
+// wave: each entry is written once)
+__device__ __forceinline__ void wave_store_lds(float* dst, float v)
 {
     const float r = wave_sum63(v);
-    if ((threadIdx.x & 63) == 63) atomicAdd(dst, r);
+    if ((threadIdx.x & 63) == 63) *dst = r;
 }
 
-// Per-vertex part of the geometry backward (the topology arrays faces,
-// vf_off, vf_faces in LDS or in memory): the corner slots and the raw vertex
-// normals, then dL/dv and the skinning sums into acc.
-__device__ __forceinline__ void geom_vertices(const GeomBwdArgs& a, const MeshDev& m, const JointState& js,
-                                              const float* vsh, float* gr, float* gpos, float* acc,
-                                              const int* faces, const int* vf_off, const int* vf_faces)
+// Geometry backward in two launches.
+//
+// k_geom_p1, grid (vertex blocks, hands): per vertex, its own slot and the
+// triangle-corner slots it occupies (position and normal parts), the raw
+// normal s (the forward's face cross products in the same order) and the
+// normalisation backward dL/ds = (gn - (gn . n) n) / |s|.  The block past
+// the vertex blocks sums the hand's loss value from the chunk partials.
+__global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
 {
-    const int h = blockIdx.x, t = threadIdx.x;
-    const int V = m.V, J = m.J, K = m.K;
-    // corner slots (position and normal parts) and the raw normal of each
-    // vertex (the face cross products of the forward, in the same order)
+    const MeshDev& m = a.m;
+    const int h = blockIdx.y, V = m.V;
+    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+        if (a.with_loss) loss_value_hand(a.loss, h);
+        return;
+    }
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    const float* vh = a.verts + (size_t)h * V * 3;
     const float* ga = a.gacc + (size_t)h * V * 6;
     const float* gf = a.gface + (size_t)h * m.F * 18;
-    for (int v = t; v < V; v += blockDim.x) {
-        float g[3] = {ga[6 * v], ga[6 * v + 1], ga[6 * v + 2]};
-        float gn[3] = {ga[6 * v + 3], ga[6 * v + 4], ga[6 * v + 5]};
-        float sv[3] = {0.0f, 0.0f, 0.0f};
+    float g[3] = {ga[6 * v], ga[6 * v + 1], ga[6 * v + 2]};
+    float gn[3] = {ga[6 * v + 3], ga[6 * v + 4], ga[6 * v + 5]};
+    float sv[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll 4
-        for (int k = vf_off[v]; k < vf_off[v + 1]; ++k) {
-            const int f = vf_faces[k];
-            const int i0 = faces[3 * f], i1 = faces[3 * f + 1], i2 = faces[3 * f + 2];
-            const int corner = i0 == v ? 0 : (i1 == v ? 1 : 2);
-            const float* sl = gf + 18 * f + 6 * corner;
-            for (int q = 0; q < 3; ++q) { g[q] += sl[q]; gn[q] += sl[3 + q]; }
-            const float* a0 = vsh + 3 * i0;
-            const float* a1 = vsh + 3 * i1;
-            const float* a2 = vsh + 3 * i2;
-            const float e1[3] = {a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]};
-            const float e2[3] = {a2[0] - a0[0], a2[1] - a0[1], a2[2] - a0[2]};
-            sv[0] += e1[1] * e2[2] - e1[2] * e2[1];
-            sv[1] += e1[2] * e2[0] - e1[0] * e2[2];
-            sv[2] += e1[0] * e2[1] - e1[1] * e2[0];
-        }
-        const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
-        const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
-        if (a.grad_normals) {
-            float* o = a.grad_normals + ((size_t)h * V + v) * 3;
-            o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
-        }
-        const float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
-        for (int q = 0; q < 3; ++q) {
-            gr[3 * v + q] = (gn[q] - d * n[q]) * il;
-            gpos[3 * v + q] = g[q];
-        }
+    for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+        const int f = m.vf_faces[k];
+        const int i0 = m.faces[3 * f], i1 = m.faces[3 * f + 1], i2 = m.faces[3 * f + 2];
+        const int corner = i0 == v ? 0 : (i1 == v ? 1 : 2);
+        const float* sl = gf + 18 * f + 6 * corner;
+        for (int q = 0; q < 3; ++q) { g[q] += sl[q]; gn[q] += sl[3 + q]; }
+        const float* a0 = vh + 3 * i0;
+        const float* a1 = vh + 3 * i1;
+        const float* a2 = vh + 3 * i2;
+        const float e1[3] = {a1[0] - a0[0], a1[1] - a0[1], a1[2] - a0[2]};
+        const float e2[3] = {a2[0] - a0[0], a2[1] - a0[1], a2[2] - a0[2]};
+        sv[0] += e1[1] * e2[2] - e1[2] * e2[1];
+        sv[1] += e1[2] * e2[0] - e1[0] * e2[2];
+        sv[2] += e1[0] * e2[1] - e1[1] * e2[0];
     }
-    __syncthreads();
-    // raw normal = sum over faces of (b - a) x (c - a): its gradient to the
-    // vertices, then the skinning backward with block sums (whole waves)
-    float bk[kMaxShape];
-    load_beta(m, a.params + 64 * h + 48, bk);
-    for (int v0 = 0; v0 < V; v0 += blockDim.x) {
-        const int v = v0 + t;
-        float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, vp[3] = {0.0f, 0.0f, 0.0f};
-        float gvp[3] = {0.0f, 0.0f, 0.0f}, gx[3] = {0.0f, 0.0f, 0.0f};
-        unsigned int jmask = 0u;   // joints this vertex is bound to
-        float wq[kMaxInfl];
-        int jq[kMaxInfl];
-        if (v < V) {
-            load_weights(m, v, wq, jq);
-            shaped_vertex(m, bk, v, x);
-            for (int q = 0; q < 3; ++q) g[q] = gpos[3 * v + q];
-#pragma unroll 4
-            for (int k = vf_off[v]; k < vf_off[v + 1]; ++k) {
-                const int f = vf_faces[k];
-                const int ia = faces[3 * f], ib = faces[3 * f + 1], ic = faces[3 * f + 2];
-                float gfs[3];
-                for (int q = 0; q < 3; ++q) gfs[q] = gr[3 * ia + q] + gr[3 * ib + q] + gr[3 * ic + q];
-                const float e1[3] = {vsh[3 * ib] - vsh[3 * ia], vsh[3 * ib + 1] - vsh[3 * ia + 1],
-                                     vsh[3 * ib + 2] - vsh[3 * ia + 2]};
-                const float e2[3] = {vsh[3 * ic] - vsh[3 * ia], vsh[3 * ic + 1] - vsh[3 * ia + 1],
-                                     vsh[3 * ic + 2] - vsh[3 * ia + 2]};
-                const float g1[3] = {e2[1] * gfs[2] - e2[2] * gfs[1], e2[2] * gfs[0] - e2[0] * gfs[2],
-                                     e2[0] * gfs[1] - e2[1] * gfs[0]};
-                const float g2[3] = {gfs[1] * e1[2] - gfs[2] * e1[1], gfs[2] * e1[0] - gfs[0] * e1[2],
-                                     gfs[0] * e1[1] - gfs[1] * e1[0]};
-                if (v == ia) for (int q = 0; q < 3; ++q) g[q] -= g1[q] + g2[q];
-                else if (v == ib) for (int q = 0; q < 3; ++q) g[q] += g1[q];
-                else for (int q = 0; q < 3; ++q) g[q] += g2[q];
-            }
-            if (a.grad_verts) {
-                float* o = a.grad_verts + ((size_t)h * V + v) * 3;
-                o[0] = g[0]; o[1] = g[1]; o[2] = g[2];
-            }
-            blend_vertex(js, wq, jq, x, vp);
-            matTvec3(js.Rp, g, gvp);
-#pragma unroll
-            for (int q = 0; q < kMaxInfl; ++q) {
-                const float w = wq[q];
-                if (w == 0.0f) continue;
-                const int j = jq[q];
-                jmask |= 1u << j;
-                float y[3];
-                matTvec3(js.GR + 9 * j, gvp, y);
-                for (int c = 0; c < 3; ++c) gx[c] += w * y[c];
-            }
-        }
-        // global rotation (g vp^T) and translation (g)
-        for (int i = 0; i < 3; ++i) {
-            for (int k = 0; k < 3; ++k) wave_add_lds(acc + 3 * i + k, g[i] * vp[k]);
-            wave_add_lds(acc + 9 + i, g[i]);
-        }
-        // shape through the vertex offsets
-        {
-            const float* sd = m.shapedirs + (size_t)3 * (v < V ? v : 0) * K;
-            float u[kMaxShape];
-#pragma unroll
-            for (int k = 0; k < kMaxShape; ++k) {
-                const int kk = k < K ? k : K - 1;
-                const float s0 = K > 0 ? sd[kk] : 0.0f, s1 = K > 0 ? sd[K + kk] : 0.0f;
-                const float s2 = K > 0 ? sd[2 * K + kk] : 0.0f;
-                u[k] = v < V ? s0 * gx[0] + s1 * gx[1] + s2 * gx[2] : 0.0f;
-            }
-#pragma unroll
-            for (int k = 0; k < kMaxShape; ++k)
-                if (k < K) wave_add_lds(acc + 12 + 12 * J + k, u[k]);
-        }
-        // per joint bound to a vertex of this wave: [dL/dGR_j as w gvp x^T (9),
-        // dL/dAt_j as w gvp (3)]
-        unsigned int wmask = jmask;
-        wmask |= __shfl_xor(wmask, 1);
-        for (int o = 2; o < 64; o <<= 1) wmask |= __shfl_xor(wmask, o);
-        wmask = __builtin_amdgcn_readfirstlane(wmask);
-        for (; wmask; wmask &= wmask - 1u) {
-            const int j = __builtin_ctz(wmask);
-            float w = 0.0f;
-            if ((jmask >> j) & 1u)
-#pragma unroll
-                for (int q = 0; q < kMaxInfl; ++q)
-                    if (q < m.infl && jq[q] == j) w += wq[q];
-            float* aj = acc + 12 + 12 * j;
-            for (int i = 0; i < 3; ++i) {
-                const float wg = w * gvp[i];
-                for (int k = 0; k < 3; ++k) wave_add_lds(aj + 3 * i + k, wg * x[k]);
-                wave_add_lds(aj + 9 + i, wg);
-            }
-        }
+    const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
+    const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
+    if (a.grad_normals) {
+        float* o = a.grad_normals + ((size_t)h * V + v) * 3;
+        o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
+    }
+    const float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+    float* gr = a.gr + ((size_t)h * V + v) * 3;
+    float* gp = a.gpos + ((size_t)h * V + v) * 3;
+    for (int q = 0; q < 3; ++q) {
+        gr[q] = (gn[q] - d * n[q]) * il;
+        gp[q] = g[q];
     }
 }
 
-// Geometry backward of one hand per block (all of its vertices, so no sums
-// across blocks): dL/dv from the triangle-corner slots and the vertex-normal
-// gradients (through the normalisation and the face cross products), then
-// through the skinning to the pose, shape and global parameters, and
-// optionally the parameters' Adam step.  The block first copies the small
-// tables it walks (joint tree, and with stage_topology the triangles and the
-// vertex-to-triangle lists) into LDS, so the walks wait on LDS, not memory.
-// Dynamic LDS: 9 V floats (+ 6 F + V + 1 ints when staged).
-__global__ void __launch_bounds__(kGeomThreads) k_geom_bwd(GeomBwdArgs a)
+// k_geom_p2, grid (vertex blocks of one wave, hands): the raw normals'
+// gradient to the vertices through the face cross products, dL/dv, then the
+// skinning backward with the block's sums (DPP wave sums) written as one
+// row of partials; the last block of the hand adds the rows in block order,
+// takes them through the joint tree and, with adam_params, steps the
+// parameters.
+__global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
 {
-    if (a.with_loss) loss_value_hand(a.loss, blockIdx.x);
-    extern __shared__ float gdyn[];
     __shared__ JointState js;
     __shared__ float acc[kSkinPart];
-    __shared__ float ljt[3 * kMaxJoints], ljs[3 * kMaxJoints * kMaxShape];
-    __shared__ int lpar[kMaxJoints], ldep[kMaxJoints];
-    MeshDev m = a.m;
-    const int h = blockIdx.x, t = threadIdx.x;
-    const int V = m.V, F = m.F, J = m.J, K = m.K;
+    __shared__ int last;
+    const MeshDev& m = a.m;
+    const int h = blockIdx.y, t = threadIdx.x;
+    const int V = m.V, J = m.J, K = m.K;
     const int n_part = 12 + 12 * J + K;
-    float* vsh = gdyn;            // [V,3] vertices
-    float* gr = vsh + 3 * V;      // [V,3] dL/d(raw vertex normal)
-    float* gpos = gr + 3 * V;     // [V,3] dL/dv from the corner slots
-    int* lf = reinterpret_cast<int*>(gpos + 3 * V);   // staged: [F,3] triangles
-    int* lvo = lf + 3 * F;                               //         [V+1] list offsets
-    int* lvf = lvo + V + 1;                              //         [3F] triangles of each vertex
     const float* p = a.params + 64 * h;
-    const float* vh = a.verts + (size_t)h * V * 3;
-    for (int i = t; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
-    for (int i = t; i < n_part; i += blockDim.x) acc[i] = 0.0f;
-    for (int i = t; i < 3 * J; i += blockDim.x) ljt[i] = m.jt[i];
-    for (int i = t; i < 3 * J * K; i += blockDim.x) ljs[i] = m.js[i];
-    if (t < J) { lpar[t] = m.parents[t]; ldep[t] = m.jdepth[t]; }
-    if (a.stage_topology) {
-        for (int i = t; i < 3 * F; i += blockDim.x) { lf[i] = m.faces[i]; lvf[i] = m.vf_faces[i]; }
-        for (int i = t; i <= V; i += blockDim.x) lvo[i] = m.vf_off[i];
+    for (int i = t; i < n_part; i += 64) acc[i] = 0.0f;
+    if (a.js_saved) {
+        // the skinning launch of these parameters left the joint state
+        const float* src = a.js_saved + (size_t)h * kJointStateFloats;
+        float* dst = reinterpret_cast<float*>(&js);
+        for (int i = t; i < kJointStateFloats; i += 64) dst[i] = src[i];
+        __syncthreads();
+    } else {
+        joint_state(m, p, js);   // ends with a barrier
     }
-    m.jt = ljt; m.js = ljs; m.parents = lpar; m.jdepth = ldep;
+    const float* vh = a.verts + (size_t)h * V * 3;
+    const float* grh = a.gr + (size_t)h * V * 3;
+    float bk[kMaxShape];
+    load_beta(m, p + 48, bk);
+    const int v = blockIdx.x * 64 + t;
+    float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, vp[3] = {0.0f, 0.0f, 0.0f};
+    float gvp[3] = {0.0f, 0.0f, 0.0f}, gx[3] = {0.0f, 0.0f, 0.0f};
+    unsigned int jmask = 0u;   // joints this vertex is bound to
+    float wq[kMaxInfl];
+    int jq[kMaxInfl];
+    if (v < V) {
+        load_weights(m, v, wq, jq);
+        shaped_vertex(m, bk, v, x);
+        for (int q = 0; q < 3; ++q) g[q] = a.gpos[((size_t)h * V + v) * 3 + q];
+#pragma unroll 4
+        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+            const int f = m.vf_faces[k];
+            const int ia = m.faces[3 * f], ib = m.faces[3 * f + 1], ic = m.faces[3 * f + 2];
+            float gfs[3];
+            for (int q = 0; q < 3; ++q) gfs[q] = grh[3 * ia + q] + grh[3 * ib + q] + grh[3 * ic + q];
+            const float e1[3] = {vh[3 * ib] - vh[3 * ia], vh[3 * ib + 1] - vh[3 * ia + 1],
+                                 vh[3 * ib + 2] - vh[3 * ia + 2]};
+            const float e2[3] = {vh[3 * ic] - vh[3 * ia], vh[3 * ic + 1] - vh[3 * ia + 1],
+                                 vh[3 * ic + 2] - vh[3 * ia + 2]};
+            const float g1[3] = {e2[1] * gfs[2] - e2[2] * gfs[1], e2[2] * gfs[0] - e2[0] * gfs[2],
+                                 e2[0] * gfs[1] - e2[1] * gfs[0]};
+            const float g2[3] = {gfs[1] * e1[2] - gfs[2] * e1[1], gfs[2] * e1[0] - gfs[0] * e1[2],
+                                 gfs[0] * e1[1] - gfs[1] * e1[0]};
+            if (v == ia) for (int q = 0; q < 3; ++q) g[q] -= g1[q] + g2[q];
+            else if (v == ib) for (int q = 0; q < 3; ++q) g[q] += g1[q];
+            else for (int q = 0; q < 3; ++q) g[q] += g2[q];
+        }
+        if (a.grad_verts) {
+            float* o = a.grad_verts + ((size_t)h * V + v) * 3;
+            o[0] = g[0]; o[1] = g[1]; o[2] = g[2];
+        }
+        blend_vertex(js, wq, jq, x, vp);
+        matTvec3(js.Rp, g, gvp);
+#pragma unroll
+        for (int q = 0; q < kMaxInfl; ++q) {
+            const float w = wq[q];
+            if (w == 0.0f) continue;
+            const int j = jq[q];
+            jmask |= 1u << j;
+            float y[3];
+            matTvec3(js.GR + 9 * j, gvp, y);
+            for (int c = 0; c < 3; ++c) gx[c] += w * y[c];
+        }
+    }
+    // global rotation (g vp^T) and translation (g)
+    for (int i = 0; i < 3; ++i) {
+        for (int k = 0; k < 3; ++k) wave_store_lds(acc + 3 * i + k, g[i] * vp[k]);
+        wave_store_lds(acc + 9 + i, g[i]);
+    }
+    // shape through the vertex offsets
+    {
+        const float* sd = m.shapedirs + (size_t)3 * (v < V ? v : 0) * K;
+        float u[kMaxShape];
+#pragma unroll
+        for (int k = 0; k < kMaxShape; ++k) {
+            const int kk = k < K ? k : K - 1;
+            const float s0 = K > 0 ? sd[kk] : 0.0f, s1 = K > 0 ? sd[K + kk] : 0.0f;
+            const float s2 = K > 0 ? sd[2 * K + kk] : 0.0f;
+            u[k] = v < V ? s0 * gx[0] + s1 * gx[1] + s2 * gx[2] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxShape; ++k)
+            if (k < K) wave_store_lds(acc + 12 + 12 * J + k, u[k]);
+    }
+    // per joint bound to a vertex of this wave: [dL/dGR_j as w gvp x^T (9),
+    // dL/dAt_j as w gvp (3)]
+    unsigned int wmask = jmask;
+    for (int o = 1; o < 64; o <<= 1) wmask |= __shfl_xor(wmask, o);
+    wmask = __builtin_amdgcn_readfirstlane(wmask);
+    for (; wmask; wmask &= wmask - 1u) {
+        const int j = __builtin_ctz(wmask);
+        float w = 0.0f;
+        if ((jmask >> j) & 1u)
+#pragma unroll
+            for (int q = 0; q < kMaxInfl; ++q)
+                if (q < m.infl && jq[q] == j) w += wq[q];
+        float* aj = acc + 12 + 12 * j;
+        for (int i = 0; i < 3; ++i) {
+            const float wg = w * gvp[i];
+            for (int k = 0; k < 3; ++k) wave_store_lds(aj + 3 * i + k, wg * x[k]);
+            wave_store_lds(aj + 9 + i, wg);
+        }
+    }
     __syncthreads();
-    joint_state(m, p, js);   // ends with a barrier
-    if (a.stage_topology) geom_vertices(a, m, js, vsh, gr, gpos, acc, lf, lvo, lvf);
-    else geom_vertices(a, m, js, vsh, gr, gpos, acc, m.faces, m.vf_off, m.vf_faces);
+    float* row = a.part + ((size_t)h * gridDim.x + blockIdx.x) * kSkinPart;
+    for (int i = t; i < n_part; i += 64) row[i] = acc[i];
+    // the last block of the hand finishes (every row is written)
+    __threadfence();
+    __syncthreads();
+    if (t == 0) last = atomicAdd(a.counter + h, 1) == (int)gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    if (t == 0) a.counter[h] = 0;
+    const float* rows = a.part + (size_t)h * gridDim.x * kSkinPart;
+    const int nb = gridDim.x;
+    for (int i = t; i < n_part; i += 64) {
+        // rows in block order, eight loads in flight
+        float sum = 0.0f;
+        for (int b0 = 0; b0 < nb; b0 += 8) {
+            float x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = b0 + q < nb ? rows[(size_t)(b0 + q) * kSkinPart + i] : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (b0 + q < nb) sum += x[q];
+        }
+        acc[i] = sum;
+    }
     __syncthreads();
     float* gp = a.grad_params + 64 * h;
     skin_bwd_finish(m, p, acc, js, gp);
     if (!a.adam_params) return;
     __syncthreads();   // the finish has read the parameters and written gp
-    if (t < 64) {
-        const float lr = param_lr(a.adam, t);
-        if (lr != 0.0f) {
-            float bc1, bc2;
-            adam_bias(a.adam, bc1, bc2);
-            const size_t i = (size_t)64 * h + t;
-            a.adam.params[i] =
-                adam_update(a.adam.params[i], a.adam.m_params + i, a.adam.v_params + i, gp[t], lr, a.adam, bc1, bc2);
-        }
+    const float lr = param_lr(a.adam, t);
+    if (lr != 0.0f) {
+        float bc1, bc2;
+        adam_bias(a.adam, bc1, bc2);
+        const size_t i = (size_t)64 * h + t;
+        a.adam.params[i] =
+            adam_update(a.adam.params[i], a.adam.m_params + i, a.adam.v_params + i, gp[t], lr, a.adam, bc1, bc2);
     }
 }
 
