@@ -85,7 +85,7 @@ struct hr_scene {
     float* normals = nullptr;
     Tri* tris = nullptr;
     Node* nodes = nullptr;
-    float* gacc = nullptr;        // [hands,V,6] vertex gradient slots (edge term)
+    float* gacc = nullptr;        // [views,V,6] vertex gradient slots of each view (edge term)
     float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
     EdgeSample* samples = nullptr;   // traced edge samples (first part of the boundary term)
     long long sample_cap = 0;
@@ -394,7 +394,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
     TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
     TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.node_stride));
-    TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_hands * V * 6));
+    TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_views * V * 6));
     TRY(s->upload<float>(&s->gface, nullptr, (size_t)n_hands * F * 18));
     {   // stored edge samples: generous for hand silhouettes; samples beyond are traced in place
         long long cap = 65536;
@@ -716,7 +716,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     if (!cleared) {
         const long long nalb = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3;
         rc = fill(s, grad_albedo, nalb, 0.0f, st);
-        if (!rc) rc = fill(s, s->gacc, (long long)s->n_hands * s->V * 6, 0.0f, st);
+        if (!rc) rc = fill(s, s->gacc, (long long)s->n_views * s->V * 6, 0.0f, st);
         if (!rc) rc = fill(s, s->gface, (long long)s->n_hands * s->F * 18, 0.0f, st);
         if (rc) return rc;
     }
@@ -765,6 +765,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     if (after_trace && hipEventRecord(after_trace, st) != hipSuccess) return fail(HR_EHIP, "hr_backward: event");
     GeomBwdArgs g;
     g.m = s->mesh; g.params = params; g.verts = verts; g.gacc = s->gacc; g.gface = s->gface;
+    g.hand_view_off = s->hand_view_off; g.hand_views = s->hand_views;
     g.grad_verts = grad_verts; g.grad_normals = grad_normals; g.grad_params = grad_params;
     // adam: the colour map's step (its gradient is final now), then the
     // parameters' step at the end of each hand's geometry block
@@ -866,7 +867,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     if (!rc) rc = prepare(s, q->verts, st, false, true, q->mask);
     if (!rc && edges) rc = edge_trace_impl(s, q->verts, q->albedo, q->background, 0, it, st, false);
     float* const clr[3] = {q->grad_albedo, s->gacc, s->gface};
-    const long long clr_n[3] = {(long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3, (long long)s->n_hands * s->V * 6,
+    const long long clr_n[3] = {(long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3, (long long)s->n_views * s->V * 6,
                                 (long long)s->n_hands * s->F * 18};
     if (!rc)
         rc = render_impl(s, q->verts, q->albedo, q->background, 0, it, q->image, nullptr, st, true, clr, clr_n,

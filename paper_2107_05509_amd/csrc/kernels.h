@@ -201,7 +201,9 @@ struct GeomBwdArgs {
     MeshDev m;
     const float* params;       // [H,64]
     const float* verts;        // [H,V,3]
-    const float* gacc;         // [H,V,6] per-vertex slots (edge term)
+    const float* gacc;         // [views,V,6] per-vertex slots of each view (edge term)
+    const int* hand_view_off;  // [H+1] views of each hand
+    const int* hand_views;
     const float* gface;        // [H,F,18] triangle-corner slots (interior term)
     float* grad_verts;         // nullable [H,V,3]
     float* grad_normals;       // nullable [H,V,3]

@@ -1305,7 +1305,9 @@ __device__ __forceinline__ void edge_contribution(const EdgeArgs& a, int vi, int
     const float nhx = dy / len, nhy = -dx / len;
     const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
     const float* vh = a.verts + (size_t)c.hand * a.m.V * 3;
-    float* gout = a.gacc + (size_t)c.hand * a.m.V * 6;
+    // one slot array per view: the samples of a view share few vertices, so
+    // the memory-side atomics of different views never queue on one address
+    float* gout = a.gacc + (size_t)vi * a.m.V * 6;
     float Ja[2][3], Jb[2][3];
     proj_jacobian(c, vh + 3 * va, Ja);
     proj_jacobian(c, vh + 3 * vb, Jb);
@@ -1633,10 +1635,13 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
     const float* vh = a.verts + (size_t)h * V * 3;
-    const float* ga = a.gacc + (size_t)h * V * 6;
     const float* gf = a.gface + (size_t)h * m.F * 18;
-    float g[3] = {ga[6 * v], ga[6 * v + 1], ga[6 * v + 2]};
-    float gn[3] = {ga[6 * v + 3], ga[6 * v + 4], ga[6 * v + 5]};
+    // the edge term's slots of the hand's views, in view order
+    float g[3] = {0.0f, 0.0f, 0.0f}, gn[3] = {0.0f, 0.0f, 0.0f};
+    for (int q = a.hand_view_off[h]; q < a.hand_view_off[h + 1]; ++q) {
+        const float* ga = a.gacc + ((size_t)a.hand_views[q] * V + v) * 6;
+        for (int k = 0; k < 3; ++k) { g[k] += ga[k]; gn[k] += ga[3 + k]; }
+    }
     float sv[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll 4
     for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
@@ -1690,7 +1695,13 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
         // the skinning launch of these parameters left the joint state
         const float* src = a.js_saved + (size_t)h * kJointStateFloats;
         float* dst = reinterpret_cast<float*>(&js);
-        for (int i = t; i < kJointStateFloats; i += 64) dst[i] = src[i];
+        constexpr int kPer = (kJointStateFloats + 63) / 64;
+        float x[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) x[q] = src[min(t + 64 * q, kJointStateFloats - 1)];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q)
+            if (t + 64 * q < kJointStateFloats) dst[t + 64 * q] = x[q];
         __syncthreads();
     } else {
         joint_state(m, p, js);   // ends with a barrier
