@@ -103,6 +103,7 @@ struct hr_scene {
     float* geom_part = nullptr;   // [hands,geom_blocks,kSkinPart] block rows of the skinning sums
     int* geom_count = nullptr;    // [hands] finished blocks (reset by the last)
     float* joint_state = nullptr; // [hands, joint state] of hr_iterate's skinning, for its backward
+    int* hand_counter = nullptr;  // [1] hands finished in the geometry backward (reset by the last)
     int geom_blocks = 0;
     unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
     // learned edge-sampling proposal (hr_proposal_*)
@@ -409,6 +410,11 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<float>(&s->geom_part, nullptr, (size_t)n_hands * s->geom_blocks * kSkinPart));
     TRY(s->upload<int>(&s->geom_count, nullptr, (size_t)n_hands));
     TRY(s->upload<float>(&s->joint_state, nullptr, (size_t)n_hands * kJointStateFloats));
+    TRY(s->upload<int>(&s->hand_counter, nullptr, 1));
+    if (hipMemset(s->hand_counter, 0, sizeof(int)) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EHIP, "scene init: memset");
+    }
     if (hipMemset(s->geom_count, 0, sizeof(int) * n_hands) != hipSuccess) {
         hr_scene_destroy(s);
         return fail(HR_EHIP, "scene init: memset");
@@ -706,7 +712,8 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
                          uint32_t flags, float* grad_params, float* grad_albedo, float* grad_verts,
                          float* grad_normals, hipStream_t st, bool edges_traced = false,
                          hipEvent_t after_trace = nullptr, bool cleared = false, const AdamArgs* adam = nullptr,
-                         const LossArgs* loss_value = nullptr, const float* js_saved = nullptr)
+                         const LossArgs* loss_value = nullptr, const float* js_saved = nullptr,
+                         int* iter_advance = nullptr)
 {
     int rc;
     if (!(flags & HR_REUSE_GEOMETRY)) {
@@ -767,22 +774,23 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     g.m = s->mesh; g.params = params; g.verts = verts; g.gacc = s->gacc; g.gface = s->gface;
     g.hand_view_off = s->hand_view_off; g.hand_views = s->hand_views;
     g.grad_verts = grad_verts; g.grad_normals = grad_normals; g.grad_params = grad_params;
-    // adam: the colour map's step (its gradient is final now), then the
-    // parameters' step at the end of each hand's geometry block
-    if (adam) {
-        AdamArgs aa = *adam;
-        aa.n_hands = 0;
-        rc = adam_launch(s, aa, st);
-        if (rc) return rc;
-    }
+    // adam: the colour map's step (its gradient is final now) in blocks of
+    // the first launch, the parameters' step at the end of each hand's
+    // second launch; iter_advance: the counter advances after both
     g.adam_params = adam != nullptr;
     if (adam) g.adam = *adam;
     g.with_loss = loss_value != nullptr;
     if (loss_value) g.loss = *loss_value;
     g.gr = s->geom_gr; g.gpos = s->geom_gpos; g.part = s->geom_part; g.counter = s->geom_count;
     g.js_saved = js_saved;
-    // one more block per hand (the last) sums the loss value
-    rc = launch(s, "k_geom_p1", k_geom_p1, dim3((s->V + 255) / 256 + 1, s->n_hands), dim3(256), 0, st, g);
+    g.n_hands = s->n_hands;
+    g.p1_blocks = (s->V + 255) / 256;
+    g.iter_advance = iter_advance;
+    g.hand_counter = s->hand_counter;
+    // per hand one more block sums the loss value
+    const long long n4 = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3 / 4;
+    const int n_adam = adam ? (int)std::min<long long>(1024, std::max<long long>(1, (n4 + 255) / 256)) : 0;
+    rc = launch(s, "k_geom_p1", k_geom_p1, dim3(s->n_hands * (g.p1_blocks + 1) + n_adam), dim3(256), 0, st, g);
     if (!rc) rc = launch(s, "k_geom_p2", k_geom_p2, dim3(s->geom_blocks, s->n_hands), dim3(64), 0, st, g);
     return rc;
 }
@@ -882,11 +890,13 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     if (!rc)
         rc = backward_impl(s, q->params, q->verts, q->albedo, q->background, q->dimage, 0, it,
                            (flags & HR_GRAD_ALL) | HR_REUSE_GEOMETRY, q->grad_params, q->grad_albedo, nullptr,
-                           nullptr, st, edges, train ? s->ev[0] : nullptr, true, &adam, &lv, s->joint_state);
+                           nullptr, st, edges, train ? s->ev[0] : nullptr, true, &adam, &lv, s->joint_state,
+                           train ? nullptr : q->iter);
     if (!rc && train && hipStreamWaitEvent(s->side, s->ev[0], 0) != hipSuccess) rc = fail(HR_EHIP, "hr_iterate: fork");
     if (!rc && train) rc = proposal_train_impl(s, s->side);
     if (!rc && train) rc = join(s->ev[1]);
-    if (!rc) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
+    // with training the side stream still reads the counter: advance after the join
+    if (!rc && train) rc = launch(s, "k_advance", k_advance, dim3(1), dim3(64), 0, st, q->iter);
     return rc;
 }
 

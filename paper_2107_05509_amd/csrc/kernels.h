@@ -217,6 +217,10 @@ struct GeomBwdArgs {
     float* part;               // [H, vertex blocks, kSkinPart] block rows of the skinning sums
     int* counter;              // [H] finished blocks (zero between launches)
     const float* js_saved;     // nullable: [H, joint state] left by the skinning of the same parameters
+    int n_hands;
+    int p1_blocks;             // vertex blocks per hand of the first launch
+    int* iter_advance;         // nullable: iteration counter, incremented once every hand has finished
+    int* hand_counter;         // [1] finished hands (zero between launches)
 };
 
 }  // namespace hr

@@ -1627,12 +1627,25 @@ __device__ __forceinline__ void wave_store_lds(float* dst, float v)
 __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
 {
     const MeshDev& m = a.m;
-    const int h = blockIdx.y, V = m.V;
-    if ((int)blockIdx.x == (int)gridDim.x - 1) {
+    const int V = m.V;
+    // blocks [0, H * per_hand): per hand, vertex blocks and the loss block;
+    // the rest: the colour map's Adam step (with adam_albedo)
+    const int per_hand = a.p1_blocks + 1;
+    const int bid = blockIdx.x;
+    if (bid >= a.n_hands * per_hand) {
+        float bc1, bc2;
+        adam_bias(a.adam, bc1, bc2);
+        const long long nb = (long long)gridDim.x - (long long)a.n_hands * per_hand;
+        adam_albedo_part(a.adam, bc1, bc2, (long long)(bid - a.n_hands * per_hand) * blockDim.x + threadIdx.x,
+                         nb * blockDim.x);
+        return;
+    }
+    const int h = bid / per_hand, bx = bid - h * per_hand;
+    if (bx == a.p1_blocks) {
         if (a.with_loss) loss_value_hand(a.loss, h);
         return;
     }
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = bx * blockDim.x + threadIdx.x;
     if (v >= V) return;
     const float* vh = a.verts + (size_t)h * V * 3;
     const float* gf = a.gface + (size_t)h * m.F * 18;
@@ -1832,6 +1845,18 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
         const size_t i = (size_t)64 * h + t;
         a.adam.params[i] =
             adam_update(a.adam.params[i], a.adam.m_params + i, a.adam.v_params + i, gp[t], lr, a.adam, bc1, bc2);
+    }
+    if (!a.iter_advance) return;
+    // the last hand to finish advances the iteration counter: every read of
+    // it in this iteration (the Adam steps above and in the previous
+    // launches) has happened
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();
+        if (atomicAdd(a.hand_counter, 1) == a.n_hands - 1) {
+            *a.hand_counter = 0;
+            *a.iter_advance += 1;
+        }
     }
 }
 
