@@ -137,8 +137,11 @@ struct hr_graph {
     int n_iters = 0;
 };
 
-// Copy one hand's hierarchy topology to the device (synchronous).
-static int upload_hierarchy(hr_scene* s, int h, const HostBvh& hb)
+// Copy one hand's hierarchy topology to the device (synchronous).  Internal
+// nodes are renumbered by height, the root first (index 0, where traversal
+// starts) and the nodes of each height contiguous: the refit walks a height
+// as one index range.  With it go the vertex ids of each leaf slot's triangle.
+static int upload_hierarchy(hr_scene* s, int h, const HostBvh& hb, const int* faces)
 {
     BvhDev& b = s->bvh;
     const int n = (int)hb.child.size() / 2;
@@ -146,13 +149,29 @@ static int upload_hierarchy(hr_scene* s, int h, const HostBvh& hb)
     if (hb.depth + 1 > kMaxStack || nl + 1 > b.level_stride)
         return fail(HR_EUNSUPPORTED, "hierarchy too deep (%d levels)", hb.depth);
     if (n > b.node_stride) return fail(HR_EUNSUPPORTED, "hierarchy too large (%d nodes)", n);
-    hipError_t e = hipMemcpy((int*)b.child + (size_t)h * b.node_stride * 2, hb.child.data(),
-                             sizeof(int) * hb.child.size(), hipMemcpyHostToDevice);
+    if ((int)hb.order.size() != n || hb.level_off[nl] != n) return fail(HR_EINVAL, "hierarchy: bad level order");
+    std::vector<int> renum(n), child(2 * (size_t)n);
+    for (int q = 0; q < n; ++q) renum[hb.order[q]] = n - 1 - q;
+    if (renum[0] != 0) return fail(HR_EINVAL, "hierarchy: the root is not the highest node");
+    for (int old = 0; old < n; ++old)
+        for (int c = 0; c < 2; ++c) {
+            const int code = hb.child[2 * (size_t)old + c];
+            child[2 * (size_t)renum[old] + c] = code >= 0 ? renum[code] : code;
+        }
+    std::vector<int> order(n), sv((size_t)s->F * 3);
+    for (int q = 0; q < n; ++q) order[q] = n - 1 - q;
+    for (int i = 0; i < s->F; ++i)
+        for (int k = 0; k < 3; ++k) sv[3 * (size_t)i + k] = faces[3 * (size_t)hb.perm[i] + k];
+    hipError_t e = hipMemcpy((int*)b.child + (size_t)h * b.node_stride * 2, child.data(),
+                             sizeof(int) * child.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy((int*)b.perm + (size_t)h * s->F, hb.perm.data(), sizeof(int) * hb.perm.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy((int*)b.order + (size_t)h * b.node_stride, hb.order.data(), sizeof(int) * hb.order.size(),
+        e = hipMemcpy((int*)b.order + (size_t)h * b.node_stride, order.data(), sizeof(int) * order.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((int*)b.slot_verts + (size_t)h * s->F * 3, sv.data(), sizeof(int) * sv.size(),
                       hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy((int*)b.level_off + (size_t)h * b.level_stride, hb.level_off.data(),
@@ -331,8 +350,9 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * F)); b.perm = q;
         TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.node_stride)); b.order = q;
         TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.level_stride)); b.level_off = q;
+        TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * F * 3)); b.slot_verts = q;
         HostBvh hb = build_bvh(m->v_template, m->faces, F, kLeafMax);
-        for (int h = 0; h < n_hands; ++h) TRY(upload_hierarchy(s, h, hb));
+        for (int h = 0; h < n_hands; ++h) TRY(upload_hierarchy(s, h, hb, m->faces));
     }
     // views, work lists
     {
@@ -439,7 +459,10 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             return fail(HR_EHIP, "scene init: event");
         }
 #undef TRY
-    s->smem_prepare = sizeof(float) * (3 * V + 3 * F + 6 * s->bvh.node_stride);
+    // refit: vertices, node bounds (face normals before them), child codes
+    // and the leaf slots' vertex ids
+    s->smem_prepare = sizeof(float) * (3 * V + std::max(6 * s->bvh.node_stride, 3 * F)) +
+                      sizeof(int) * (2 * s->bvh.node_stride + 3 * F);
     if (hipFuncSetAttribute((const void*)k_prepare, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)s->smem_prepare) != hipSuccess) {
         hr_scene_destroy(s);
@@ -472,7 +495,7 @@ int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
         if (!std::isfinite(hv[i])) return fail(HR_EINVAL, "hr_build_hierarchy: non-finite vertex");
     for (int h = 0; h < s->n_hands; ++h) {
         HostBvh hb = build_bvh(hv.data() + (size_t)h * s->V * 3, faces.data(), s->F, kLeafMax);
-        int rc = upload_hierarchy(s, h, hb);
+        int rc = upload_hierarchy(s, h, hb, faces.data());
         if (rc) return rc;
     }
     return HR_OK;

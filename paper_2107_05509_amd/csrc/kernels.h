@@ -41,8 +41,10 @@ struct BvhDev {
     const int* n_levels;       // [H]
     const int* child;          // [H, node_stride, 2] child codes
     const int* perm;           // [H, F] face of each leaf slot
-    const int* order;          // [H, node_stride] internal nodes sorted by height
+    const int* order;          // [H, node_stride] internal nodes sorted by height (the traversal's
+                               // numbering puts them at n - 1 - position: the root is 0)
     const int* level_off;      // [H, level_stride] offsets into order per height
+    const int* slot_verts;     // [H, F, 3] vertex ids of each leaf slot's triangle
 };
 
 // wave tiles: a tile of 2^tw_log2 x 2^th_log2 pixels, 2^spp_log2 lanes per

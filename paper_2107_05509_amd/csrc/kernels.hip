@@ -276,17 +276,24 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
                            float* __restrict__ normals, Tri* __restrict__ tris, Node* __restrict__ nodes, int h,
                            float* dyn)
 {
-    const int V = m.V, F = m.F;
-    float* vsh = dyn;                 // [V*3]
-    float* fn = vsh + 3 * V;          // [F*3]
-    float* nb = fn + 3 * F;           // [node_stride*6] node bounds
-    const int* child = b.child + (size_t)h * b.node_stride * 2;
+    const int V = m.V, F = m.F, NS = b.node_stride;
+    // LDS: vertices, node bounds (the raw face normals first), child codes,
+    // vertex ids of the leaf slots: every refit level reads LDS only
+    float* vsh = dyn;                                        // [V*3]
+    float* nb = vsh + 3 * V;                                 // [NS*6] node bounds
+    float* fn = nb;                                          // [F*3] before the refit
+    int* lchild = reinterpret_cast<int*>(nb + max(6 * NS, 3 * F));   // [NS*2]
+    int* lsv = lchild + 2 * NS;                              // [F*3]
+    const int* child = b.child + (size_t)h * NS * 2;
     const int* perm = b.perm + (size_t)h * F;
-    const int* order = b.order + (size_t)h * b.node_stride;
+    const int* sv = b.slot_verts + (size_t)h * F * 3;
     const int* level_off = b.level_off + (size_t)h * b.level_stride;
     const int n_levels = b.n_levels[h];
+    const int n_nodes = level_off[n_levels];
     const float* vh = verts + (size_t)h * V * 3;
     for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
+    for (int i = threadIdx.x; i < 2 * n_nodes; i += blockDim.x) lchild[i] = child[i];
+    for (int i = threadIdx.x; i < 3 * F; i += blockDim.x) lsv[i] = sv[i];
     __syncthreads();
     for (int f = threadIdx.x; f < F; f += blockDim.x) {
         int a = m.faces[3 * f], bb = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
@@ -309,33 +316,33 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
     }
     Tri* th = tris + (size_t)h * F;
     for (int i = threadIdx.x; i < F; i += blockDim.x) {
-        int f = perm[i];
         Tri t;
-        int id[3] = {m.faces[3 * f], m.faces[3 * f + 1], m.faces[3 * f + 2]};
+        const int id[3] = {lsv[3 * i], lsv[3 * i + 1], lsv[3 * i + 2]};
         for (int k = 0; k < 3; ++k)
             for (int c = 0; c < 3; ++c) t.v[3 * k + c] = vsh[3 * id[k] + c];
-        t.face = f; t.i0 = id[0]; t.i1 = id[1]; t.i2 = id[2];
+        t.face = perm[i]; t.i0 = id[0]; t.i1 = id[1]; t.i2 = id[2];
         t.pad[0] = t.pad[1] = t.pad[2] = 0;
         th[i] = t;
     }
-    // refit, level by level from the leaves up
-    Node* nd = nodes + (size_t)h * b.node_stride;
+    __syncthreads();   // the face normals' LDS becomes the node bounds
+    // refit, level by level from the leaves up; the nodes at position q of
+    // the height order are numbered n_nodes - 1 - q
+    Node* nd = nodes + (size_t)h * NS;
     for (int L = 0; L < n_levels; ++L) {
         for (int q = level_off[L] + threadIdx.x; q < level_off[L + 1]; q += blockDim.x) {
-            int n = order[q];
+            const int n = n_nodes - 1 - q;
             Node out;
             float own[6] = {3e38f, 3e38f, 3e38f, -3e38f, -3e38f, -3e38f};
             for (int c = 0; c < 2; ++c) {
-                int code = child[2 * n + c];
+                int code = lchild[2 * n + c];
                 float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
                 if (code >= 0) {
                     for (int k = 0; k < 3; ++k) { lo[k] = nb[6 * code + k]; hi[k] = nb[6 * code + 3 + k]; }
                 } else {
                     int lc = ~code, start = lc >> 3, cnt = lc & 7;
                     for (int i = 0; i < cnt; ++i) {
-                        int f = perm[start + i];
                         for (int k = 0; k < 3; ++k) {
-                            int vid = m.faces[3 * f + k];
+                            int vid = lsv[3 * (start + i) + k];
                             for (int cc = 0; cc < 3; ++cc) {
                                 float x = vsh[3 * vid + cc];
                                 lo[cc] = fminf(lo[cc], x);
