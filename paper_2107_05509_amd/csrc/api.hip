@@ -279,6 +279,19 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload(&q, m->faces, 3 * (size_t)F)); md.faces = q;
         TRY(s->upload(&q, m->edges, 2 * (size_t)E)); md.edges = q;
         TRY(s->upload(&q, m->edge_faces, 2 * (size_t)E)); md.edge_faces = q;
+        // per edge: its vertices, then the vertices of its faces in face
+        // order (-1 for a missing second face): one table read per edge
+        std::vector<int> et((size_t)E * 8, -1);
+        for (int e = 0; e < E; ++e) {
+            et[8 * (size_t)e] = m->edges[2 * e];
+            et[8 * (size_t)e + 1] = m->edges[2 * e + 1];
+            for (int k = 0; k < 2; ++k) {
+                const int f = m->edge_faces[2 * e + k];
+                if (f < 0) continue;
+                for (int c = 0; c < 3; ++c) et[8 * (size_t)e + 2 + 3 * k + c] = m->faces[3 * f + c];
+            }
+        }
+        TRY(s->upload(&q, et.data(), et.size())); md.edge_verts = reinterpret_cast<const int4*>(q);
         std::vector<int> off(V + 1, 0), cnt(V, 0), flat(3 * F);
         for (int i = 0; i < 3 * F; ++i) off[m->faces[i] + 1]++;
         for (int v = 0; v < V; ++v) off[v + 1] += off[v];
@@ -463,6 +476,9 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     // and the leaf slots' vertex ids
     s->smem_prepare = sizeof(float) * (3 * V + std::max(6 * s->bvh.node_stride, 3 * F)) +
                       sizeof(int) * (2 * s->bvh.node_stride + 3 * F);
+    // silhouette-table blocks: scan buffer, vertices, edge weights
+    s->smem_prepare = std::max(s->smem_prepare, sizeof(unsigned long long) * 512 + sizeof(float) * 3 * V +
+                                                    sizeof(uint32_t) * E);
     if (hipFuncSetAttribute((const void*)k_prepare, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)s->smem_prepare) != hipSuccess) {
         hr_scene_destroy(s);

@@ -22,6 +22,7 @@ struct MeshDev {
     const float* uv;           // [V,2]
     const int* edges;          // [E,2]
     const int* edge_faces;     // [E,2]
+    const int4* edge_verts;    // [E,2] (va, vb, face 0's vertices, face 1's vertices or -1)
     const int* vf_off;         // [V+1]
     const int* vf_faces;       // [3F]
     const float* jt;           // [J,3] J_reg T: rest joints of the template

@@ -1027,10 +1027,15 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
 __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* part)
 {
     const ViewDev c = a.views[vi];
-    const float* vh = a.verts + (size_t)c.hand * a.m.V * 3;
-    const int E = a.m.E;
+    const float* vg = a.verts + (size_t)c.hand * a.m.V * 3;
+    const int E = a.m.E, V = a.m.V;
     EdgeRec* rec = a.rec + (size_t)vi * E;
     unsigned long long* cdf = a.cdf + (size_t)vi * E;
+    // LDS after the scan buffer: the hand's vertices, then each edge's weight
+    float* vh = reinterpret_cast<float*>(part + blockDim.x);
+    uint32_t* wl = reinterpret_cast<uint32_t*>(vh + 3 * V);
+    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vh[i] = vg[i];
+    __syncthreads();
     const int per = (E + blockDim.x - 1) / blockDim.x;
     const int e0 = threadIdx.x * per;
     const int e1 = min(E, e0 + per);
@@ -1039,15 +1044,16 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
         EdgeRec r;
         r.ax = r.ay = r.bx = r.by = r.t0 = r.t1 = 0.0f;
         r.w = 0; r.wq = 0;
-        const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
+        const int4 t0 = a.m.edge_verts[2 * e], t1 = a.m.edge_verts[2 * e + 1];
+        const int va = t0.x, vb = t0.y;
+        const int fv[2][3] = {{t0.z, t0.w, t1.x}, {t1.y, t1.z, t1.w}};
         const float* pa = vh + 3 * va;
         int front[2] = {0, 0};
-        const int nf = a.m.edge_faces[2 * e + 1] < 0 ? 1 : 2;
+        const int nf = fv[1][0] < 0 ? 1 : 2;
         for (int k = 0; k < nf; ++k) {
-            const int f = a.m.edge_faces[2 * e + k];
-            const float* p0 = vh + 3 * a.m.faces[3 * f];
-            const float* p1 = vh + 3 * a.m.faces[3 * f + 1];
-            const float* p2 = vh + 3 * a.m.faces[3 * f + 2];
+            const float* p0 = vh + 3 * fv[k][0];
+            const float* p1 = vh + 3 * fv[k][1];
+            const float* p2 = vh + 3 * fv[k][2];
             float u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
             float w[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
             float n0 = u[1] * w[2] - u[2] * w[1];
@@ -1085,6 +1091,7 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
             }
         }
         rec[e] = r;
+        wl[e] = r.w;
         local += r.w;
     }
     part[threadIdx.x] = local;
@@ -1098,7 +1105,7 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
     }
     unsigned long long run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0ull;
     for (int e = e0; e < e1; ++e) {
-        run += rec[e].w;
+        run += wl[e];
         cdf[e] = run;
     }
     if (threadIdx.x == blockDim.x - 1) {
