@@ -472,10 +472,11 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             return fail(HR_EHIP, "scene init: event");
         }
 #undef TRY
-    // refit: vertices, node bounds (face normals before them), child codes
-    // and the leaf slots' vertex ids
-    s->smem_prepare = sizeof(float) * (3 * V + std::max(6 * s->bvh.node_stride, 3 * F)) +
+    // refit: vertices, node bounds, slot bounds, child codes and the leaf
+    // slots' vertex ids; normals: vertices and face normals
+    s->smem_prepare = sizeof(float) * (3 * V + 6 * s->bvh.node_stride + 6 * F) +
                       sizeof(int) * (2 * s->bvh.node_stride + 3 * F);
+    s->smem_prepare = std::max(s->smem_prepare, sizeof(float) * (3 * V + 3 * F));
     // silhouette-table blocks: scan buffer, vertices, edge weights
     s->smem_prepare = std::max(s->smem_prepare, sizeof(unsigned long long) * 512 + sizeof(float) * 3 * V +
                                                     sizeof(uint32_t) * E);
@@ -537,7 +538,7 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_t
     a.views = s->views; a.ts = s->ts; a.tiles = s->tiles; a.tile_count = s->tile_count; a.view_rect = s->view_rect;
     a.mask = mask; a.view_scale = s->view_scale;
     a.n_hands = s->n_hands; a.n_views = s->n_views; a.with_setup = 1; a.with_scale = with_scale;
-    const dim3 grid(s->n_hands + (2 + (with_scale ? 1 : 0)) * s->n_views);
+    const dim3 grid(2 * s->n_hands + (2 + (with_scale ? 1 : 0)) * s->n_views);
     return launch(s, "k_prepare", k_prepare, grid, dim3(512), s->smem_prepare, st, a);
 }
 

@@ -272,28 +272,14 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
 // geometry preparation: vertex normals, triangles in leaf order, BVH refit
 // ===========================================================================
 
-__device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __restrict__ verts,
-                           float* __restrict__ normals, Tri* __restrict__ tris, Node* __restrict__ nodes, int h,
-                           float* dyn)
+__device__ void normals_hand(const MeshDev& m, const float* __restrict__ verts, float* __restrict__ normals, int h,
+                             float* dyn)
 {
-    const int V = m.V, F = m.F, NS = b.node_stride;
-    // LDS: vertices, node bounds (the raw face normals first), child codes,
-    // vertex ids of the leaf slots: every refit level reads LDS only
-    float* vsh = dyn;                                        // [V*3]
-    float* nb = vsh + 3 * V;                                 // [NS*6] node bounds
-    float* fn = nb;                                          // [F*3] before the refit
-    int* lchild = reinterpret_cast<int*>(nb + max(6 * NS, 3 * F));   // [NS*2]
-    int* lsv = lchild + 2 * NS;                              // [F*3]
-    const int* child = b.child + (size_t)h * NS * 2;
-    const int* perm = b.perm + (size_t)h * F;
-    const int* sv = b.slot_verts + (size_t)h * F * 3;
-    const int* level_off = b.level_off + (size_t)h * b.level_stride;
-    const int n_levels = b.n_levels[h];
-    const int n_nodes = level_off[n_levels];
+    const int V = m.V, F = m.F;
+    float* vsh = dyn;          // [V*3]
+    float* fn = vsh + 3 * V;   // [F*3] raw face normals (area weighted)
     const float* vh = verts + (size_t)h * V * 3;
     for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
-    for (int i = threadIdx.x; i < 2 * n_nodes; i += blockDim.x) lchild[i] = child[i];
-    for (int i = threadIdx.x; i < 3 * F; i += blockDim.x) lsv[i] = sv[i];
     __syncthreads();
     for (int f = threadIdx.x; f < F; f += blockDim.x) {
         int a = m.faces[3 * f], bb = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
@@ -314,6 +300,31 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
         float inv = 1.0f / sqrtf(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
         nh[3 * v] = s[0] * inv; nh[3 * v + 1] = s[1] * inv; nh[3 * v + 2] = s[2] * inv;
     }
+}
+
+__device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __restrict__ verts,
+                           Tri* __restrict__ tris, Node* __restrict__ nodes, int h, float* dyn)
+{
+    const int V = m.V, F = m.F, NS = b.node_stride;
+    // LDS: vertices, node bounds, child codes, vertex ids of the leaf slots,
+    // each slot's triangle bounds: every refit level reads LDS only
+    float* vsh = dyn;                                        // [V*3]
+    float* nb = vsh + 3 * V;                                 // [NS*6] node bounds
+    float* sb = nb + 6 * NS;                                 // [F*6] slot bounds
+    int* lchild = reinterpret_cast<int*>(sb + 6 * F);        // [NS*2]
+    int* lsv = lchild + 2 * NS;                              // [F*3]
+    const int* child = b.child + (size_t)h * NS * 2;
+    const int* perm = b.perm + (size_t)h * F;
+    const int* sv = b.slot_verts + (size_t)h * F * 3;
+    const int* level_off = b.level_off + (size_t)h * b.level_stride;
+    const int n_levels = b.n_levels[h];
+    const int n_nodes = level_off[n_levels];
+    const float* vh = verts + (size_t)h * V * 3;
+    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
+    for (int i = threadIdx.x; i < 2 * n_nodes; i += blockDim.x) lchild[i] = child[i];
+    for (int i = threadIdx.x; i < 3 * F; i += blockDim.x) lsv[i] = sv[i];
+    __syncthreads();
+    // triangles in leaf order and their bounds
     Tri* th = tris + (size_t)h * F;
     for (int i = threadIdx.x; i < F; i += blockDim.x) {
         Tri t;
@@ -323,8 +334,12 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
         t.face = perm[i]; t.i0 = id[0]; t.i1 = id[1]; t.i2 = id[2];
         t.pad[0] = t.pad[1] = t.pad[2] = 0;
         th[i] = t;
+        for (int c = 0; c < 3; ++c) {
+            sb[6 * i + c] = fminf(fminf(t.v[c], t.v[3 + c]), t.v[6 + c]);
+            sb[6 * i + 3 + c] = fmaxf(fmaxf(t.v[c], t.v[3 + c]), t.v[6 + c]);
+        }
     }
-    __syncthreads();   // the face normals' LDS becomes the node bounds
+    __syncthreads();
     // refit, level by level from the leaves up; the nodes at position q of
     // the height order are numbered n_nodes - 1 - q
     Node* nd = nodes + (size_t)h * NS;
@@ -342,12 +357,8 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
                     int lc = ~code, start = lc >> 3, cnt = lc & 7;
                     for (int i = 0; i < cnt; ++i) {
                         for (int k = 0; k < 3; ++k) {
-                            int vid = lsv[3 * (start + i) + k];
-                            for (int cc = 0; cc < 3; ++cc) {
-                                float x = vsh[3 * vid + cc];
-                                lo[cc] = fminf(lo[cc], x);
-                                hi[cc] = fmaxf(hi[cc], x);
-                            }
+                            lo[k] = fminf(lo[k], sb[6 * (start + i) + k]);
+                            hi[k] = fmaxf(hi[k], sb[6 * (start + i) + 3 + k]);
                         }
                     }
                     // conservative padding: the float32 watertight test accepts
@@ -1115,8 +1126,8 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
     }
 }
 
-// Geometry preparation in one launch: blocks [0, H) refit hand h (vertex
-// normals, triangles in leaf order, hierarchy bounds); then per view the
+// Geometry preparation in one launch: blocks [0, H) refit hand h (triangles
+// in leaf order, hierarchy bounds), blocks [H, 2H) its vertex normals; then per view the
 // silhouette table (with_setup), the screen bounds and wave tiles (the tile
 // count is zero beforehand) and the loss scale from the mask (with_scale).
 __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
@@ -1124,7 +1135,12 @@ __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
     extern __shared__ float dyn[];
     int bid = blockIdx.x;
     if (bid < a.n_hands) {
-        refit_hand(a.m, a.b, a.verts, a.normals, a.tris, a.nodes, bid, dyn);
+        refit_hand(a.m, a.b, a.verts, a.tris, a.nodes, bid, dyn);
+        return;
+    }
+    bid -= a.n_hands;
+    if (bid < a.n_hands) {
+        normals_hand(a.m, a.verts, a.normals, bid, dyn);
         return;
     }
     bid -= a.n_hands;
