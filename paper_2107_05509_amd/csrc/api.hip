@@ -97,6 +97,7 @@ struct hr_scene {
     unsigned long long* edge_total = nullptr;
     long long* edge_budget = nullptr;
     long long* edge_prefix = nullptr;
+    int* setup_done = nullptr;
     size_t smem_prepare = 0;
     float* geom_gr = nullptr;     // [hands,V,3] geometry backward: raw-normal gradients
     float* geom_gpos = nullptr;   // [hands,V,3] slot gradients
@@ -177,6 +178,17 @@ static int upload_hierarchy(hr_scene* s, int h, const HostBvh& hb, const int* fa
         e = hipMemcpy((int*)b.level_off + (size_t)h * b.level_stride, hb.level_off.data(),
                       sizeof(int) * hb.level_off.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy((int*)b.n_levels + h, &nl, sizeof(int), hipMemcpyHostToDevice);
+    // the triangles' face and vertex ids (the refit writes their corners)
+    std::vector<Tri> tri(s->F);
+    for (int i = 0; i < s->F; ++i) {
+        Tri& t = tri[i];
+        std::fill(t.v, t.v + 9, 0.0f);
+        t.face = hb.perm[i];
+        t.i0 = sv[3 * (size_t)i]; t.i1 = sv[3 * (size_t)i + 1]; t.i2 = sv[3 * (size_t)i + 2];
+        t.pad[0] = t.pad[1] = t.pad[2] = 0;
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(s->tris + (size_t)h * s->F, tri.data(), sizeof(Tri) * tri.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(HR_EHIP, "hierarchy upload: %s", hipGetErrorString(e));
     return HR_OK;
 }
@@ -364,6 +376,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.node_stride)); b.order = q;
         TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * b.level_stride)); b.level_off = q;
         TRY(s->upload<int>(&q, nullptr, (size_t)n_hands * F * 3)); b.slot_verts = q;
+        TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
         HostBvh hb = build_bvh(m->v_template, m->faces, F, kLeafMax);
         for (int h = 0; h < n_hands; ++h) TRY(upload_hierarchy(s, h, hb, m->faces));
     }
@@ -426,7 +439,6 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     }
     TRY(s->upload<int>(&s->tile_count, nullptr, 4));
     TRY(s->upload<float>(&s->normals, nullptr, (size_t)n_hands * V * 3));
-    TRY(s->upload<Tri>(&s->tris, nullptr, (size_t)n_hands * F));
     TRY(s->upload<Node>(&s->nodes, nullptr, (size_t)n_hands * s->bvh.node_stride));
     TRY(s->upload<float>(&s->gacc, nullptr, (size_t)n_views * V * 6));
     TRY(s->upload<float>(&s->gface, nullptr, (size_t)n_hands * F * 18));
@@ -444,7 +456,9 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<int>(&s->geom_count, nullptr, (size_t)n_hands));
     TRY(s->upload<float>(&s->joint_state, nullptr, (size_t)n_hands * kJointStateFloats));
     TRY(s->upload<int>(&s->hand_counter, nullptr, 1));
-    if (hipMemset(s->hand_counter, 0, sizeof(int)) != hipSuccess) {
+    TRY(s->upload<int>(&s->setup_done, nullptr, 1));
+    if (hipMemset(s->hand_counter, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(s->setup_done, 0, sizeof(int)) != hipSuccess) {
         hr_scene_destroy(s);
         return fail(HR_EHIP, "scene init: memset");
     }
@@ -475,11 +489,11 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     // refit: vertices, node bounds, slot bounds, child codes and the leaf
     // slots' vertex ids; normals: vertices and face normals
     s->smem_prepare = sizeof(float) * (3 * V + 6 * s->bvh.node_stride + 6 * F) +
-                      sizeof(int) * (2 * s->bvh.node_stride + 3 * F);
+                      sizeof(int) * (2 * s->bvh.node_stride + 3 * F + s->bvh.level_stride);
     s->smem_prepare = std::max(s->smem_prepare, sizeof(float) * (3 * V + 3 * F));
-    // silhouette-table blocks: scan buffer, vertices, edge weights
-    s->smem_prepare = std::max(s->smem_prepare, sizeof(unsigned long long) * 512 + sizeof(float) * 3 * V +
-                                                    sizeof(uint32_t) * E);
+    // silhouette-table blocks: scan buffer, edge table, vertices, edge weights
+    s->smem_prepare = std::max(s->smem_prepare, sizeof(unsigned long long) * 16 + sizeof(int) * 8 * E +
+                                                    sizeof(float) * 3 * V + sizeof(uint32_t) * E);
     if (hipFuncSetAttribute((const void*)k_prepare, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)s->smem_prepare) != hipSuccess) {
         hr_scene_destroy(s);
@@ -536,7 +550,7 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_t
     a.m = s->mesh; a.b = s->bvh; a.verts = verts; a.normals = s->normals; a.tris = s->tris; a.nodes = s->nodes;
     a.e = edge_args(s, verts, nullptr, nullptr, nullptr, 0, nullptr);
     a.views = s->views; a.ts = s->ts; a.tiles = s->tiles; a.tile_count = s->tile_count; a.view_rect = s->view_rect;
-    a.mask = mask; a.view_scale = s->view_scale;
+    a.mask = mask; a.view_scale = s->view_scale; a.setup_done = s->setup_done;
     a.n_hands = s->n_hands; a.n_views = s->n_views; a.with_setup = 1; a.with_scale = with_scale;
     const dim3 grid(2 * s->n_hands + (2 + (with_scale ? 1 : 0)) * s->n_views);
     return launch(s, "k_prepare", k_prepare, grid, dim3(512), s->smem_prepare, st, a);
@@ -600,7 +614,9 @@ static int edge_trace_impl(hr_scene* s, const float* verts, const float* albedo,
     int rc = HR_OK;
     if (!rc && s->prop_kind == HR_PROPOSAL_LEARNED)
         rc = launch(s, "k_proposal", k_proposal, dim3(s->n_views, s->prop.split), dim3(256), 0, st, e, s->prop);
-    if (!rc)
+    // the preparation launch wrote the prefix of the length budgets; the
+    // learned proposal's budgets need their own
+    if (!rc && s->prop_kind == HR_PROPOSAL_LEARNED)
         rc = launch(s, "k_edge_prefix", k_edge_prefix, dim3(1), dim3(256), 0, st, (const long long*)s->edge_budget,
                     s->n_views, s->edge_prefix);
     if (rc || !trace) return rc;

@@ -591,4 +591,28 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Block-wide copy of n elements from global memory into LDS, eight loads in
+// flight per thread (a staging loop that waits on each load in turn costs a
+// memory round trip per element and thread).  The caller synchronises.
+template <typename T>
+__device__ __forceinline__ void lds_stage(T* dst, const T* __restrict__ src, int n)
+{
+    const int s = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + 7 * s < n; i += 8 * s) {
+        T r[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r[k] = src[i + k * s];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dst[i + k * s] = r[k];
+    }
+    T r[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (i + k * s < n) r[k] = src[i + k * s];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (i + k * s < n) dst[i + k * s] = r[k];
+}
+
 }  // namespace hr

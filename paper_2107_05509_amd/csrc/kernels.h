@@ -196,6 +196,7 @@ struct PrepArgs {
     int4* view_rect;
     const uint8_t* mask;       // with_scale (nullable: all pixels)
     float* view_scale;
+    int* setup_done;           // with_setup: finished silhouette tables (zero between launches)
     int n_hands, n_views, with_setup, with_scale;
 };
 

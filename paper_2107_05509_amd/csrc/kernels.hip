@@ -278,8 +278,7 @@ __device__ void normals_hand(const MeshDev& m, const float* __restrict__ verts, 
     const int V = m.V, F = m.F;
     float* vsh = dyn;          // [V*3]
     float* fn = vsh + 3 * V;   // [F*3] raw face normals (area weighted)
-    const float* vh = verts + (size_t)h * V * 3;
-    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
+    lds_stage(vsh, verts + (size_t)h * V * 3, 3 * V);
     __syncthreads();
     for (int f = threadIdx.x; f < F; f += blockDim.x) {
         int a = m.faces[3 * f], bb = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
@@ -307,36 +306,61 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
 {
     const int V = m.V, F = m.F, NS = b.node_stride;
     // LDS: vertices, node bounds, child codes, vertex ids of the leaf slots,
-    // each slot's triangle bounds: every refit level reads LDS only
+    // each slot's triangle bounds, the level offsets: every refit level reads
+    // LDS only (a global load in the level loop would also wait for the
+    // previous level's node stores)
     float* vsh = dyn;                                        // [V*3]
     float* nb = vsh + 3 * V;                                 // [NS*6] node bounds
     float* sb = nb + 6 * NS;                                 // [F*6] slot bounds
     int* lchild = reinterpret_cast<int*>(sb + 6 * F);        // [NS*2]
     int* lsv = lchild + 2 * NS;                              // [F*3]
-    const int* child = b.child + (size_t)h * NS * 2;
-    const int* perm = b.perm + (size_t)h * F;
-    const int* sv = b.slot_verts + (size_t)h * F * 3;
-    const int* level_off = b.level_off + (size_t)h * b.level_stride;
+    int* loff = lsv + 3 * F;                                 // [level_stride]
     const int n_levels = b.n_levels[h];
-    const int n_nodes = level_off[n_levels];
-    const float* vh = verts + (size_t)h * V * 3;
-    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vsh[i] = vh[i];
-    for (int i = threadIdx.x; i < 2 * n_nodes; i += blockDim.x) lchild[i] = child[i];
-    for (int i = threadIdx.x; i < 3 * F; i += blockDim.x) lsv[i] = sv[i];
+    lds_stage(vsh, verts + (size_t)h * V * 3, 3 * V);
+    lds_stage(lchild, b.child + (size_t)h * NS * 2, 2 * NS);
+    lds_stage(lsv, b.slot_verts + (size_t)h * F * 3, 3 * F);
+    lds_stage(loff, b.level_off + (size_t)h * b.level_stride, b.level_stride);
     __syncthreads();
-    // triangles in leaf order and their bounds
+    const int n_nodes = loff[n_levels];
+    // triangles in leaf order (their face and vertex ids are written with
+    // the topology) and their bounds
     Tri* th = tris + (size_t)h * F;
     for (int i = threadIdx.x; i < F; i += blockDim.x) {
-        Tri t;
-        const int id[3] = {lsv[3 * i], lsv[3 * i + 1], lsv[3 * i + 2]};
-        for (int k = 0; k < 3; ++k)
-            for (int c = 0; c < 3; ++c) t.v[3 * k + c] = vsh[3 * id[k] + c];
-        t.face = perm[i]; t.i0 = id[0]; t.i1 = id[1]; t.i2 = id[2];
-        t.pad[0] = t.pad[1] = t.pad[2] = 0;
-        th[i] = t;
+        const int i0 = lsv[3 * i], i1 = lsv[3 * i + 1], i2 = lsv[3 * i + 2];
+        const float v[9] = {vsh[3 * i0], vsh[3 * i0 + 1], vsh[3 * i0 + 2], vsh[3 * i1], vsh[3 * i1 + 1],
+                            vsh[3 * i1 + 2], vsh[3 * i2], vsh[3 * i2 + 1], vsh[3 * i2 + 2]};
+        float4* dst = reinterpret_cast<float4*>(th + i);
+        dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+        dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+        reinterpret_cast<float*>(dst + 2)[0] = v[8];
         for (int c = 0; c < 3; ++c) {
-            sb[6 * i + c] = fminf(fminf(t.v[c], t.v[3 + c]), t.v[6 + c]);
-            sb[6 * i + 3 + c] = fmaxf(fmaxf(t.v[c], t.v[3 + c]), t.v[6 + c]);
+            sb[6 * i + c] = fminf(fminf(v[c], v[3 + c]), v[6 + c]);
+            sb[6 * i + 3 + c] = fmaxf(fmaxf(v[c], v[3 + c]), v[6 + c]);
+        }
+    }
+    __syncthreads();
+    // leaf bounds: the union of the leaf's slots, padded, written over the
+    // bounds of its first slot (the leaves' slot ranges are disjoint)
+    for (int i = threadIdx.x; i < 2 * n_nodes; i += blockDim.x) {
+        const int code = lchild[i];
+        if (code >= 0) continue;
+        const int lc = ~code, start = lc >> 3, cnt = lc & 7;
+        float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+#pragma unroll
+        for (int j = 0; j < kLeafMax; ++j) {
+            if (j < cnt) {
+                for (int k = 0; k < 3; ++k) {
+                    lo[k] = fminf(lo[k], sb[6 * (start + j) + k]);
+                    hi[k] = fmaxf(hi[k], sb[6 * (start + j) + 3 + k]);
+                }
+            }
+        }
+        // conservative padding: the float32 watertight test accepts rays a
+        // few ulps outside the exact triangle
+        for (int k = 0; k < 3; ++k) {
+            const float pad = 1e-5f + 1e-6f * fmaxf(fabsf(lo[k]), fabsf(hi[k]));
+            sb[6 * start + k] = lo[k] - pad;
+            sb[6 * start + 3 + k] = hi[k] + pad;
         }
     }
     __syncthreads();
@@ -344,41 +368,23 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
     // the height order are numbered n_nodes - 1 - q
     Node* nd = nodes + (size_t)h * NS;
     for (int L = 0; L < n_levels; ++L) {
-        for (int q = level_off[L] + threadIdx.x; q < level_off[L + 1]; q += blockDim.x) {
+        for (int q = loff[L] + threadIdx.x; q < loff[L + 1]; q += blockDim.x) {
             const int n = n_nodes - 1 - q;
+            const int c0 = lchild[2 * n], c1 = lchild[2 * n + 1];
+            const float* b0 = c0 >= 0 ? nb + 6 * c0 : sb + 6 * ((~c0) >> 3);
+            const float* b1 = c1 >= 0 ? nb + 6 * c1 : sb + 6 * ((~c1) >> 3);
             Node out;
-            float own[6] = {3e38f, 3e38f, 3e38f, -3e38f, -3e38f, -3e38f};
-            for (int c = 0; c < 2; ++c) {
-                int code = lchild[2 * n + c];
-                float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
-                if (code >= 0) {
-                    for (int k = 0; k < 3; ++k) { lo[k] = nb[6 * code + k]; hi[k] = nb[6 * code + 3 + k]; }
-                } else {
-                    int lc = ~code, start = lc >> 3, cnt = lc & 7;
-                    for (int i = 0; i < cnt; ++i) {
-                        for (int k = 0; k < 3; ++k) {
-                            lo[k] = fminf(lo[k], sb[6 * (start + i) + k]);
-                            hi[k] = fmaxf(hi[k], sb[6 * (start + i) + 3 + k]);
-                        }
-                    }
-                    // conservative padding: the float32 watertight test accepts
-                    // rays a few ulps outside the exact triangle
-                    for (int cc = 0; cc < 3; ++cc) {
-                        float pad = 1e-5f + 1e-6f * fmaxf(fabsf(lo[cc]), fabsf(hi[cc]));
-                        lo[cc] -= pad; hi[cc] += pad;
-                    }
-                }
-                float* dl = c == 0 ? out.lo0 : out.lo1;
-                float* dh = c == 0 ? out.hi0 : out.hi1;
-                for (int k = 0; k < 3; ++k) {
-                    dl[k] = lo[k]; dh[k] = hi[k];
-                    own[k] = fminf(own[k], lo[k]); own[3 + k] = fmaxf(own[3 + k], hi[k]);
-                }
-                out.child[c] = code;
+            for (int k = 0; k < 3; ++k) {
+                out.lo0[k] = b0[k]; out.hi0[k] = b0[3 + k];
+                out.lo1[k] = b1[k]; out.hi1[k] = b1[3 + k];
             }
+            out.child[0] = c0; out.child[1] = c1;
             out.pad[0] = out.pad[1] = 0;
             nd[n] = out;
-            for (int k = 0; k < 6; ++k) nb[6 * n + k] = own[k];
+            for (int k = 0; k < 3; ++k) {
+                nb[6 * n + k] = fminf(out.lo0[k], out.lo1[k]);
+                nb[6 * n + 3 + k] = fmaxf(out.hi0[k], out.hi1[k]);
+            }
         }
         __syncthreads();
     }
@@ -448,6 +454,17 @@ __device__ void view_bounds(const MeshDev& m, const ViewDev* __restrict__ views,
         tiles[base + i] = make_int2(vi, (tx0 + i % nx) | ((ty0 + i / nx) << 16));
 }
 
+// number of non-zero bytes of a 16-byte word: bit 7 of each byte of
+// ((w & 0x7F..) + 0x7F..) | w is set exactly when that byte is non-zero
+__device__ __forceinline__ int nonzero_bytes(uint4 q)
+{
+    const unsigned int w[4] = {q.x, q.y, q.z, q.w};
+    int c = 0;
+    for (int k = 0; k < 4; ++k)
+        c += __popc((((w[k] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w[k]) & 0x80808080u);
+    return c;
+}
+
 // Loss scale of view vi from its mask: 1 / (3 * masked pixels), 0 if none
 // (the value the loss kernels derive from their exact per-chunk counts).
 __device__ void mask_scale(const ViewDev* __restrict__ views, const uint8_t* __restrict__ mask,
@@ -466,13 +483,14 @@ __device__ void mask_scale(const ViewDev* __restrict__ views, const uint8_t* __r
         const long long n16 = (n - head) >> 4;
         for (long long i = threadIdx.x; i < head; i += blockDim.x) cnt += mv[i] != 0;
         const uint4* m16 = reinterpret_cast<const uint4*>(mv + head);
-        for (long long i = threadIdx.x; i < n16; i += blockDim.x) {
-            const uint4 q = m16[i];
-            const unsigned int w[4] = {q.x, q.y, q.z, q.w};
-            for (int k = 0; k < 4; ++k)
-                cnt += ((w[k] & 0xFFu) != 0) + ((w[k] & 0xFF00u) != 0) + ((w[k] & 0xFF0000u) != 0) +
-                       ((w[k] & 0xFF000000u) != 0);
+        // four 16-byte loads in flight per thread
+        const long long s = blockDim.x;
+        long long i = threadIdx.x;
+        for (; i + 3 * s < n16; i += 4 * s) {
+            const uint4 q[4] = {m16[i], m16[i + s], m16[i + 2 * s], m16[i + 3 * s]};
+            for (int k = 0; k < 4; ++k) cnt += nonzero_bytes(q[k]);
         }
+        for (; i < n16; i += s) cnt += nonzero_bytes(m16[i]);
         for (long long i = head + 16 * n16 + threadIdx.x; i < n; i += blockDim.x) cnt += mv[i] != 0;
     }
     int ci = (int)cnt;
@@ -1034,44 +1052,94 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
 // silhouette edges: classification, quantised weights, prefix sums
 // ===========================================================================
 
-// Silhouette table of view `vi` (one block of 256 threads; `part` is LDS [256]).
-__device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* part)
+// Inclusive prefix sum over the block (blockDim a multiple of 64, at most
+// 1024); `wtot` is LDS [16].  Every thread of the block must call it.
+__device__ __forceinline__ unsigned long long block_scan_u64(unsigned long long x, unsigned long long* wtot)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    unsigned long long off = 0;
+    for (int k = 0; k < w; ++k) off += wtot[k];
+    __syncthreads();
+    return x + off;
+}
+
+// Exclusive prefix of the views' edge-sample budgets, prefix[n_views] the
+// total (one block; budgets read past the L1, since other blocks of the same
+// launch may have written them).
+__device__ void budget_prefix(const long long* budget, int n_views, long long* prefix, unsigned long long* wtot)
+{
+    const int per = (n_views + blockDim.x - 1) / blockDim.x;
+    const int v0 = min(n_views, (int)threadIdx.x * per), v1 = min(n_views, v0 + per);
+    long long s = 0;
+    for (int v = v0; v < v1; ++v) s += __hip_atomic_load(budget + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long incl = (long long)block_scan_u64((unsigned long long)s, wtot);
+    long long run = incl - s;
+    for (int v = v0; v < v1; ++v) {
+        prefix[v] = run;
+        run += __hip_atomic_load(budget + v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == blockDim.x - 1) prefix[n_views] = incl;
+}
+
+// exclusive prefix of the per-view edge-sample budgets (one block)
+__global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict__ budget, int n_views,
+                                                     long long* __restrict__ prefix)
+{
+    __shared__ unsigned long long wtot[16];
+    budget_prefix(budget, n_views, prefix, wtot);
+}
+
+// Silhouette table of view `vi` (one block; LDS from `part`: [16] scan
+// buffer, the hand's vertices, each edge's weight).  The block that finishes
+// last also writes the budget prefix over the views (`done` counts finished
+// views and is left at zero).
+__device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* part, int* done)
 {
     const ViewDev c = a.views[vi];
     const float* vg = a.verts + (size_t)c.hand * a.m.V * 3;
     const int E = a.m.E, V = a.m.V;
     EdgeRec* rec = a.rec + (size_t)vi * E;
     unsigned long long* cdf = a.cdf + (size_t)vi * E;
-    // LDS after the scan buffer: the hand's vertices, then each edge's weight
-    float* vh = reinterpret_cast<float*>(part + blockDim.x);
+    float* vh = reinterpret_cast<float*>(part + 16);
     uint32_t* wl = reinterpret_cast<uint32_t*>(vh + 3 * V);
-    for (int i = threadIdx.x; i < 3 * V; i += blockDim.x) vh[i] = vg[i];
+    __shared__ int last;
+    lds_stage(vh, vg, 3 * V);
     __syncthreads();
-    const int per = (E + blockDim.x - 1) / blockDim.x;
-    const int e0 = threadIdx.x * per;
-    const int e1 = min(E, e0 + per);
-    unsigned long long local = 0;
-    for (int e = e0; e < e1; ++e) {
+    // weights, one edge per thread and pass (the next pass's table entry
+    // fetched ahead)
+    int4 n0 = make_int4(0, 0, 0, 0), n1 = n0;
+    if ((int)threadIdx.x < E) { n0 = a.m.edge_verts[2 * threadIdx.x]; n1 = a.m.edge_verts[2 * threadIdx.x + 1]; }
+    for (int e = threadIdx.x; e < E; e += blockDim.x) {
+        const int4 t0 = n0, t1 = n1;
+        const int en = e + blockDim.x;
+        if (en < E) { n0 = a.m.edge_verts[2 * en]; n1 = a.m.edge_verts[2 * en + 1]; }
         EdgeRec r;
         r.ax = r.ay = r.bx = r.by = r.t0 = r.t1 = 0.0f;
         r.w = 0; r.wq = 0;
-        const int4 t0 = a.m.edge_verts[2 * e], t1 = a.m.edge_verts[2 * e + 1];
         const int va = t0.x, vb = t0.y;
         const int fv[2][3] = {{t0.z, t0.w, t1.x}, {t1.y, t1.z, t1.w}};
         const float* pa = vh + 3 * va;
         int front[2] = {0, 0};
         const int nf = fv[1][0] < 0 ? 1 : 2;
-        for (int k = 0; k < nf; ++k) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (k >= nf) break;
             const float* p0 = vh + 3 * fv[k][0];
             const float* p1 = vh + 3 * fv[k][1];
             const float* p2 = vh + 3 * fv[k][2];
             float u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
             float w[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
-            float n0 = u[1] * w[2] - u[2] * w[1];
-            float n1 = u[2] * w[0] - u[0] * w[2];
-            float n2 = u[0] * w[1] - u[1] * w[0];
+            float n0x = u[1] * w[2] - u[2] * w[1];
+            float n1x = u[2] * w[0] - u[0] * w[2];
+            float n2x = u[0] * w[1] - u[1] * w[0];
             float w0 = c.o[0] - pa[0], w1 = c.o[1] - pa[1], w2 = c.o[2] - pa[2];
-            float dd = (n0 * w0 + n1 * w1) + n2 * w2;
+            float dd = (n0x * w0 + n1x * w1) + n2x * w2;
             front[k] = dd > 0.0f;
         }
         const bool sil = nf == 1 || front[0] != front[1];
@@ -1103,32 +1171,37 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
         }
         rec[e] = r;
         wl[e] = r.w;
-        local += r.w;
     }
-    part[threadIdx.x] = local;
     __syncthreads();
-    // inclusive scan of the per-thread totals (Hillis-Steele)
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        unsigned long long x = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0ull;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
-    }
-    unsigned long long run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0ull;
+    // integer CDF: contiguous runs of edges per thread, block scan of the
+    // runs' sums
+    const int per = (E + blockDim.x - 1) / blockDim.x;
+    const int e0 = min(E, (int)threadIdx.x * per);
+    const int e1 = min(E, e0 + per);
+    unsigned long long local = 0;
+    for (int e = e0; e < e1; ++e) local += wl[e];
+    const unsigned long long incl = block_scan_u64(local, part);
+    unsigned long long run = incl - local;
     for (int e = e0; e < e1; ++e) {
         run += wl[e];
         cdf[e] = run;
     }
     if (threadIdx.x == blockDim.x - 1) {
-        const unsigned long long T = part[threadIdx.x];
-        a.total[vi] = T;
-        a.budget[vi] = (long long)((T + 255ull) / 256ull);
+        a.total[vi] = incl;
+        a.budget[vi] = (long long)((incl + 255ull) / 256ull);
+        __threadfence();
+        last = atomicAdd(done, 1) == a.n_views - 1;
     }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    budget_prefix(a.budget, a.n_views, a.prefix, part);
+    if (threadIdx.x == 0) *done = 0;
 }
 
 // Geometry preparation in one launch: blocks [0, H) refit hand h (triangles
 // in leaf order, hierarchy bounds), blocks [H, 2H) its vertex normals; then per view the
-// silhouette table (with_setup), the screen bounds and wave tiles (the tile
+// silhouette table (with_setup; the last one also the budget prefix), the screen bounds and wave tiles (the tile
 // count is zero beforehand) and the loss scale from the mask (with_scale).
 __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
 {
@@ -1146,7 +1219,7 @@ __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
     bid -= a.n_hands;
     if (a.with_setup) {
         if (bid < a.n_views) {
-            edges_setup_view(a.e, bid, reinterpret_cast<unsigned long long*>(dyn));
+            edges_setup_view(a.e, bid, reinterpret_cast<unsigned long long*>(dyn), a.setup_done);
             return;
         }
         bid -= a.n_views;
@@ -1187,31 +1260,6 @@ __device__ __forceinline__ void proj_jacobian(const ViewDev& c, const float* v, 
     float d[2][3] = {{c.fx * iz, 0.0f, -c.fx * xc[0] * iz * iz}, {0.0f, c.fy * iz, -c.fy * xc[1] * iz * iz}};
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k) J[r][k] = d[r][0] * c.R[k] + d[r][1] * c.R[3 + k] + d[r][2] * c.R[6 + k];
-}
-
-// exclusive prefix of the per-view edge-sample budgets (one block)
-__global__ void __launch_bounds__(256) k_edge_prefix(const long long* __restrict__ budget, int n_views,
-                                                     long long* __restrict__ prefix)
-{
-    __shared__ long long part[256];
-    const int per = (n_views + blockDim.x - 1) / blockDim.x;
-    const int v0 = threadIdx.x * per, v1 = min(n_views, v0 + per);
-    long long s = 0;
-    for (int v = v0; v < v1; ++v) s += budget[v];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        long long x = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0ll;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
-    }
-    long long run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0ll;
-    for (int v = v0; v < v1; ++v) {
-        prefix[v] = run;
-        run += budget[v];
-    }
-    if (threadIdx.x == blockDim.x - 1) prefix[n_views] = part[threadIdx.x];
 }
 
 // Geometry of edge sample kg (global index over the views' budgets): the
