@@ -39,6 +39,10 @@ struct alignas(16) Node {   // internal node: bounds of both children
     int pad[2];
 };
 
+// read-only global data addressed as constant memory: wave-uniform loads of
+// it become scalar loads
+typedef const __attribute__((address_space(4))) float ConstF;
+
 struct alignas(16) Tri {    // triangle in leaf order
     float v[9];
     int face, i0, i1, i2;
@@ -303,8 +307,12 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
 // loop's.  Meant for coherent rays (all samples of a few adjacent pixels):
 // the node and triangle addresses are wave-uniform and the stack is one per
 // wave.  Every lane of the wave must call it; inactive lanes take no part.
-// `wstack`: this wave's LDS stack (kMaxStack ints).
-template <bool COUNT = false>
+// `wstack`: this wave's LDS stack (kMaxStack ints).  SFETCH: nodes and
+// triangles are fetched through the scalar data cache (reads only; the
+// hierarchy is not written during the launch), which suits packets whose
+// node sequence is short and shared by many waves (camera rays); incoherent
+// packets (silhouette side points) keep vector fetches.
+template <bool COUNT = false, bool SFETCH = false>
 __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
                                            const Ray& r, bool active, int* wstack, Hit& h,
                                            TraceCount* cnt = nullptr)
@@ -318,11 +326,21 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
     int node = 0;
     while (true) {
         if (COUNT && active) cnt->nodes++;
-        const Node& n = nodes[node];
-        float4 q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
-        float4 q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
-        float4 q2 = *reinterpret_cast<const float4*>(&n.lo1[2]);
-        int4 q3 = *reinterpret_cast<const int4*>(&n.child[0]);
+        float4 q0, q1, q2;
+        int4 q3;
+        if (SFETCH) {
+            const ConstF* np = (const ConstF*)(nodes + node);
+            q0 = make_float4(np[0], np[1], np[2], np[3]);
+            q1 = make_float4(np[4], np[5], np[6], np[7]);
+            q2 = make_float4(np[8], np[9], np[10], np[11]);
+            q3 = make_int4(__float_as_int(np[12]), __float_as_int(np[13]), 0, 0);
+        } else {
+            const Node& n = nodes[node];
+            q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
+            q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
+            q2 = *reinterpret_cast<const float4*>(&n.lo1[2]);
+            q3 = *reinterpret_cast<const int4*>(&n.child[0]);
+        }
         float lo0[3] = {q0.x, q0.y, q0.z}, hi0[3] = {q0.w, q1.x, q1.y};
         float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
         const int c0 = __builtin_amdgcn_readfirstlane(q3.x), c1 = __builtin_amdgcn_readfirstlane(q3.y);
@@ -338,10 +356,18 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
                 const int start = lc >> 3, ncnt = lc & 7;
                 if (COUNT && hit) cnt->tris += ncnt;
                 for (int k = 0; k < ncnt; ++k) {
-                    const Tri& tr = tris[start + k];
-                    float4 p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
-                    float4 p1 = *reinterpret_cast<const float4*>(&tr.v[4]);
-                    float4 p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+                    float4 p0, p1, p2;
+                    if (SFETCH) {
+                        const ConstF* tp = (const ConstF*)(tris + start + k);
+                        p0 = make_float4(tp[0], tp[1], tp[2], tp[3]);
+                        p1 = make_float4(tp[4], tp[5], tp[6], tp[7]);
+                        p2 = make_float4(tp[8], tp[9], tp[10], tp[11]);
+                    } else {
+                        const Tri& tr = tris[start + k];
+                        p0 = *reinterpret_cast<const float4*>(&tr.v[0]);
+                        p1 = *reinterpret_cast<const float4*>(&tr.v[4]);
+                        p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+                    }
                     if (!hit) continue;
                     float v0[3] = {p0.x, p0.y, p0.z};
                     float v1[3] = {p0.w, p1.x, p1.y};

@@ -621,7 +621,7 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             Ray ray;
             ray_screen(c, (float)px + u, (float)py + v, ray);
             Hit h;
-            trace_wave<COUNT>(nodes, tris, ray, act, wst, h, &tc);
+            trace_wave<COUNT, true>(nodes, tris, ray, act, wst, h, &tc);
             if (act) {
                 if (COUNT) ++n_rays;
                 if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
@@ -876,7 +876,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             } else {
                 Ray ray;
                 ray_screen(c, (float)px + u, (float)py + v, ray);
-                trace_wave<COUNT>(nodes, tris, ray, act, wst, h, &tc);
+                trace_wave<COUNT, true>(nodes, tris, ray, act, wst, h, &tc);
             }
             if (act) {
                 if (COUNT) ++n_rays;
