@@ -96,6 +96,7 @@ struct Ray {
     int kx, ky, kz;
     float Sx, Sy, Sz;
     float inv[3];           // 1/d for the slab test (|d| clamped away from 0)
+    float oi[3];            // o * inv: a slab plane's t is one fused multiply-add
 };
 
 __device__ __forceinline__ float comp(const float* a, int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
@@ -118,6 +119,7 @@ __device__ __forceinline__ void ray_setup(Ray& r)
         float dk = r.d[k];
         if (fabsf(dk) < 1e-20f) dk = dk < 0.0f ? -1e-20f : 1e-20f;
         r.inv[k] = 1.0f / dk;
+        r.oi[k] = r.o[k] * r.inv[k];
     }
 }
 
@@ -201,9 +203,12 @@ struct Surf {
 __device__ __forceinline__ bool slab(const Ray& r, const float* lo, const float* hi, float tmax_in,
                                      float& tmin_out)
 {
-    float tx0 = (lo[0] - r.o[0]) * r.inv[0], tx1 = (hi[0] - r.o[0]) * r.inv[0];
-    float ty0 = (lo[1] - r.o[1]) * r.inv[1], ty1 = (hi[1] - r.o[1]) * r.inv[1];
-    float tz0 = (lo[2] - r.o[2]) * r.inv[2], tz1 = (hi[2] - r.o[2]) * r.inv[2];
+    // t of the plane x = lo as lo / d - o / d: the error of the rounded o / d
+    // (half an ulp of it) stays far below the bounds' padding (1e-5 + 1e-6 |x|
+    // in x, i.e. (1e-5 + 1e-6 |x|) / |d| in t) for origins within metres
+    float tx0 = __builtin_fmaf(lo[0], r.inv[0], -r.oi[0]), tx1 = __builtin_fmaf(hi[0], r.inv[0], -r.oi[0]);
+    float ty0 = __builtin_fmaf(lo[1], r.inv[1], -r.oi[1]), ty1 = __builtin_fmaf(hi[1], r.inv[1], -r.oi[1]);
+    float tz0 = __builtin_fmaf(lo[2], r.inv[2], -r.oi[2]), tz1 = __builtin_fmaf(hi[2], r.inv[2], -r.oi[2]);
     float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
     float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tmax_in));
     tmin_out = tmin;
