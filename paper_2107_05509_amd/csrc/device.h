@@ -99,7 +99,14 @@ struct Ray {
     float oi[3];            // o * inv: a slab plane's t is one fused multiply-add
 };
 
-__device__ __forceinline__ float comp(const float* a, int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
+// component k of a: two selects, never a branch (lanes of a wave may differ
+// in k, and a branch per component costs a run of exec-mask instructions)
+__device__ __forceinline__ float comp(const float* a, int k)
+{
+    const float a0 = a[0], a1 = a[1], a2 = a[2];
+    const float r = k == 1 ? a1 : a0;
+    return k == 2 ? a2 : r;
+}
 
 __device__ __forceinline__ void ray_setup(Ray& r)
 {
