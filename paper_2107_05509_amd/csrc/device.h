@@ -324,6 +324,19 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
 // hierarchy is not written during the launch), which suits packets whose
 // node sequence is short and shared by many waves (camera rays); incoherent
 // packets (silhouette side points) keep vector fetches.
+// lane mask of a predicate over the wave (inactive lanes 0)
+__device__ __forceinline__ uint64_t wave_mask(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// a wave-uniform pointer held in scalar registers
+template <typename T>
+__device__ __forceinline__ const T* uniform_ptr(const T* p)
+{
+    const uint64_t u = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return reinterpret_cast<const T*>(((uint64_t)hi << 32) | lo);
+}
+
 template <bool COUNT = false, bool SFETCH = false>
 __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
                                            const Ray& r, bool active, int* wstack, Hit& h,
@@ -336,6 +349,8 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
     int fb = 0x7fffffff;
     int sp = 0;
     int node = 0;
+    nodes = uniform_ptr(nodes);
+    tris = uniform_ptr(tris);
     while (true) {
         if (COUNT && active) cnt->nodes++;
         float4 q0, q1, q2;
@@ -363,7 +378,7 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
         for (int c = 0; c < 2; ++c) {
             const int code = c == 0 ? c0 : c1;
             const bool hit = c == 0 ? h0 : h1;
-            if (code < 0 && __any(hit)) {
+            if (code < 0 && wave_mask(hit) != 0) {
                 const int lc = ~code;
                 const int start = lc >> 3, ncnt = lc & 7;
                 if (COUNT && hit) cnt->tris += ncnt;
@@ -397,13 +412,15 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
                 }
             }
         }
-        const bool w0 = h0 && c0 >= 0 && t0 <= tb;
-        const bool w1 = h1 && c1 >= 0 && t1 <= tb;
-        const bool go0 = __any(w0), go1 = __any(w1);
+        const uint64_t m0 = c0 >= 0 ? wave_mask(h0 && t0 <= tb) : 0ull;
+        const uint64_t m1 = c1 >= 0 ? wave_mask(h1 && t1 <= tb) : 0ull;
+        const bool go0 = m0 != 0, go1 = m1 != 0;
         if (go0 && go1) {
             // nearer child first, by majority of the lanes that enter both
-            const int n01 = __popcll(__ballot(w0 && w1 && t0 <= t1));
-            const int n10 = __popcll(__ballot(w0 && w1 && t1 < t0));
+            // (the rest of those lanes have t1 < t0: slab entries are not NaN)
+            const uint64_t both = m0 & m1;
+            const int n01 = __popcll(both & wave_mask(t0 <= t1));
+            const int n10 = __popcll(both) - n01;
             const int nearc = n01 >= n10 ? c0 : c1;
             const int farc = n01 >= n10 ? c1 : c0;
             if (sp < kMaxStack) { wstack[sp] = farc; ++sp; }

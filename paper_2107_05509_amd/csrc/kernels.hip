@@ -594,7 +594,8 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
     for (int t = gw; t < n_tiles; t += nw) {
-        const int2 e = a.tiles[t];
+        const int2 et = a.tiles[t];   // t is wave-uniform
+        const int2 e = make_int2(__builtin_amdgcn_readfirstlane(et.x), __builtin_amdgcn_readfirstlane(et.y));
         const ViewDev& c = a.views[e.x];
         int px, py;
         tile_pixel(a.ts, e, lane, px, py);
@@ -827,7 +828,8 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
     for (int t = gw; t < n_tiles; t += nw) {
-        const int2 e = a.tiles[t];
+        const int2 et = a.tiles[t];   // t is wave-uniform
+        const int2 e = make_int2(__builtin_amdgcn_readfirstlane(et.x), __builtin_amdgcn_readfirstlane(et.y));
         const ViewDev& c = a.views[e.x];
         int px, py;
         tile_pixel(a.ts, e, lane, px, py);
