@@ -24,6 +24,11 @@ constexpr int kWaveWin = 4 * 3 * kWin * kWin;   // floats of one wave's four row
 // records in device memory
 // ---------------------------------------------------------------------------
 
+// read-only global data addressed as constant memory: wave-uniform loads of
+// it become scalar loads
+typedef const __attribute__((address_space(4))) float ConstF;
+typedef const __attribute__((address_space(4))) int ConstI;
+
 struct ViewDev {            // one camera (see hr_camera)
     float R[9];
     float o[3];
@@ -32,6 +37,17 @@ struct ViewDev {            // one camera (see hr_camera)
     uint32_t sid;           // sample-stream id (Philox counter word of the view)
     long long pix0;         // first pixel in packed buffers
 };
+// A view's record through the scalar cache (views are never written by a
+// launch; the index must be wave-uniform).
+__device__ __forceinline__ ViewDev load_view(const ViewDev* views, int i)
+{
+    ViewDev v;
+    const ConstI* src = (const ConstI*)(views + i);
+    int* dst = reinterpret_cast<int*>(&v);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(ViewDev) / 4); ++k) dst[k] = src[k];
+    return v;
+}
 
 struct alignas(16) Node {   // internal node: bounds of both children
     float lo0[3], hi0[3], lo1[3], hi1[3];
@@ -39,9 +55,6 @@ struct alignas(16) Node {   // internal node: bounds of both children
     int pad[2];
 };
 
-// read-only global data addressed as constant memory: wave-uniform loads of
-// it become scalar loads
-typedef const __attribute__((address_space(4))) float ConstF;
 
 struct alignas(16) Tri {    // triangle in leaf order
     float v[9];

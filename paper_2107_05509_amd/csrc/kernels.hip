@@ -827,9 +827,14 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
     const bool stored = a.hit_slot != nullptr && __builtin_amdgcn_readfirstlane(*a.hit_iter) == (int)iter;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
+    // wave-uniform tile entries through the scalar cache, the next one
+    // fetched while the current tile is worked on
+    const ConstI* tl = (const ConstI*)a.tiles;
+    int2 e_nx = make_int2(0, 0);
+    if (gw < n_tiles) e_nx = make_int2(tl[2 * gw], tl[2 * gw + 1]);
     for (int t = gw; t < n_tiles; t += nw) {
-        const int2 et = a.tiles[t];   // t is wave-uniform
-        const int2 e = make_int2(__builtin_amdgcn_readfirstlane(et.x), __builtin_amdgcn_readfirstlane(et.y));
+        const int2 e = e_nx;
+        if (t + nw < n_tiles) e_nx = make_int2(tl[2 * (t + nw)], tl[2 * (t + nw) + 1]);
         const ViewDev& c = a.views[e.x];
         int px, py;
         tile_pixel(a.ts, e, lane, px, py);
@@ -863,16 +868,14 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             int tmask = 0;
             int fi0 = 0x7fffffff, fi1 = -1, fj0 = 0x7fffffff, fj1 = -1;   // footprint rows / columns
             const bool act = live && s < a.spp;
-            float u = 0.0f, v = 0.0f;
-            if (act) {
-                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
-                const uint64_t wd = pick(rr, s & 3);
-                u = u24_lo(wd);
-                v = u24_hi(wd);
-            }
+            // the stored hit is fetched before the sample's random numbers
+            // are computed (for every lane: no branch between them)
+            const int slot = stored && act ? (int)a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] : -1;
+            const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
+            const uint64_t wd = pick(rr, s & 3);
+            const float u = act ? u24_lo(wd) : 0.0f, v = act ? u24_hi(wd) : 0.0f;
             Hit h;
             if (stored) {
-                const int slot = act ? (int)a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] : -1;
                 h.slot = slot;
                 h.face = slot >= 0 ? tris[slot].face : -1;
             } else {
