@@ -101,7 +101,7 @@ struct hr_scene {
     size_t smem_prepare = 0;
     float* geom_gr = nullptr;     // [hands,V,3] geometry backward: raw-normal gradients
     float* geom_gpos = nullptr;   // [hands,V,3] slot gradients
-    float* geom_part = nullptr;   // [hands,geom_blocks,kSkinPart] block rows of the skinning sums
+    float* geom_part = nullptr;   // [hands,kSkinPart] skinning sums (zero between launches)
     int* geom_count = nullptr;    // [hands] finished blocks (reset by the last)
     float* joint_state = nullptr; // [hands, joint state] of hr_iterate's skinning, for its backward
     int* hand_counter = nullptr;  // [1] hands finished in the geometry backward (reset by the last)
@@ -314,6 +314,20 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             }
         TRY(s->upload(&q, off.data(), off.size())); md.vf_off = q;
         TRY(s->upload(&q, flat.data(), flat.size())); md.vf_faces = q;
+        // the same lists as vertex triples, kVfSlots per vertex, padded with
+        // (v, v, v): a degenerate face adds nothing to the normal backward
+        std::vector<int> vc(4 * (size_t)V * kVfSlots, 0);
+        for (int v = 0; v < V; ++v)
+            for (int k = 0; k < kVfSlots; ++k) {
+                int* d = &vc[4 * ((size_t)v * kVfSlots + k)];
+                if (off[v] + k < off[v + 1]) {
+                    const int f = flat[off[v] + k];
+                    for (int c = 0; c < 3; ++c) d[c] = m->faces[3 * f + c];
+                } else {
+                    d[0] = d[1] = d[2] = v;
+                }
+            }
+        TRY(s->upload(&q, vc.data(), vc.size())); md.vf_corner = reinterpret_cast<const int4*>(q);
         // regressor applied to the template and to the shape directions (float64 sums)
         std::vector<float> jt(3 * (size_t)J), jsd(3 * (size_t)J * std::max(K, 1), 0.0f);
         for (int j = 0; j < J; ++j)
@@ -452,7 +466,11 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     s->geom_blocks = (V + 63) / 64;
     TRY(s->upload<float>(&s->geom_gr, nullptr, (size_t)n_hands * V * 3));
     TRY(s->upload<float>(&s->geom_gpos, nullptr, (size_t)n_hands * V * 3));
-    TRY(s->upload<float>(&s->geom_part, nullptr, (size_t)n_hands * s->geom_blocks * kSkinPart));
+    TRY(s->upload<float>(&s->geom_part, nullptr, (size_t)n_hands * kSkinPart));
+    if (hipMemset(s->geom_part, 0, sizeof(float) * n_hands * kSkinPart) != hipSuccess) {
+        hr_scene_destroy(s);
+        return fail(HR_EHIP, "scene init: memset");
+    }
     TRY(s->upload<int>(&s->geom_count, nullptr, (size_t)n_hands));
     TRY(s->upload<float>(&s->joint_state, nullptr, (size_t)n_hands * kJointStateFloats));
     TRY(s->upload<int>(&s->hand_counter, nullptr, 1));

@@ -631,6 +631,25 @@ __device__ __forceinline__ float wave_sum63(float v)
     return v;
 }
 
+// wave_sum63 of N values at once, step by step over all of them (the DPP
+// steps of different values interleave instead of waiting on each other)
+template <int N>
+__device__ __forceinline__ void wave_sum63_n(float* v)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_f<0x111>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_f<0x112>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_f<0x114>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_f<0x118>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_f<0x142, 0xA>(v[k]);
+#pragma unroll
+    for (int k = 0; k < N; ++k) v[k] += dpp_f<0x143, 0xC>(v[k]);
+}
+
 // min / max over each row of 16 lanes, in every lane of the row: swaps inside
 // quads (lane ^ 1, lane ^ 2), then the half-row and row mirrors
 __device__ __forceinline__ int row_min(int v)

@@ -8,7 +8,8 @@ namespace hr {
 constexpr int kMaxJoints = 32;
 constexpr int kMaxShape = 16;
 constexpr int kMaxInfl = 8;     // skinning weights per vertex
-constexpr int kSkinPart = 12 + 12 * kMaxJoints + 16;   // per-block sums of the skinning backward
+constexpr int kSkinPart = 12 + 12 * kMaxJoints + 16;   // per-hand sums of the skinning backward
+constexpr int kVfSlots = 12;    // faces per vertex in the corner table (more: the CSR list)
 constexpr int kLossChunk = 4096;     // pixels per loss block (never straddles views)
 
 struct MeshDev {
@@ -25,6 +26,8 @@ struct MeshDev {
     const int4* edge_verts;    // [E,2] (va, vb, face 0's vertices, face 1's vertices or -1)
     const int* vf_off;         // [V+1]
     const int* vf_faces;       // [3F]
+    const int4* vf_corner;     // [V,kVfSlots] the first kVfSlots faces around each vertex as
+                               // (a, b, c, 0) vertex triples, padded with (v, v, v, 0)
     const float* jt;           // [J,3] J_reg T: rest joints of the template
     const float* js;           // [J,3,K] J_reg S: joint displacement per shape coefficient
     const int* jdepth;         // [J] depth in the joint tree (root 0)
@@ -218,7 +221,7 @@ struct GeomBwdArgs {
     int with_loss;
     float* gr;                 // [H,V,3] dL/d(raw vertex normal) (first launch -> second)
     float* gpos;               // [H,V,3] dL/dv from the slots
-    float* part;               // [H, vertex blocks, kSkinPart] block rows of the skinning sums
+    float* part;               // [H, kSkinPart] the skinning sums (atomic; zero between launches)
     int* counter;              // [H] finished blocks (zero between launches)
     const float* js_saved;     // nullable: [H, joint state] left by the skinning of the same parameters
     int n_hands;

@@ -1692,13 +1692,6 @@ __device__ __forceinline__ void adam_albedo_part(const AdamArgs& a, float bc1, f
                                               bc1, bc2), 0.0f), 1.0f);
 }
 
-// sum of v over the wave stored to *dst (LDS) by one lane (blocks of one
-// wave: each entry is written once)
-__device__ __forceinline__ void wave_store_lds(float* dst, float v)
-{
-    const float r = wave_sum63(v);
-    if ((threadIdx.x & 63) == 63) *dst = r;
-}
 
 // Geometry backward in two launches.
 //
@@ -1776,6 +1769,26 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
 // row of partials; the last block of the hand adds the rows in block order,
 // takes them through the joint tree and, with adam_params, steps the
 // parameters.
+// Gradient at vertex v (a corner of face (ia, ib, ic)) of the face's raw
+// normal (b - a) x (c - a), given dL/d(raw face normal) as the sum of its
+// corners' raw-vertex-normal gradients.  A face (v, v, v) adds exact zeros.
+__device__ __forceinline__ void normal_corner_grad(int v, int ia, int ib, int ic, const float* __restrict__ vh,
+                                                   const float* __restrict__ grh, float* g)
+{
+    float gfs[3];
+    for (int q = 0; q < 3; ++q) gfs[q] = grh[3 * ia + q] + grh[3 * ib + q] + grh[3 * ic + q];
+    const float e1[3] = {vh[3 * ib] - vh[3 * ia], vh[3 * ib + 1] - vh[3 * ia + 1], vh[3 * ib + 2] - vh[3 * ia + 2]};
+    const float e2[3] = {vh[3 * ic] - vh[3 * ia], vh[3 * ic + 1] - vh[3 * ia + 1], vh[3 * ic + 2] - vh[3 * ia + 2]};
+    const float g1[3] = {e2[1] * gfs[2] - e2[2] * gfs[1], e2[2] * gfs[0] - e2[0] * gfs[2],
+                         e2[0] * gfs[1] - e2[1] * gfs[0]};
+    const float g2[3] = {gfs[1] * e1[2] - gfs[2] * e1[1], gfs[2] * e1[0] - gfs[0] * e1[2],
+                         gfs[0] * e1[1] - gfs[1] * e1[0]};
+    for (int q = 0; q < 3; ++q) {
+        const float d = v == ia ? -(g1[q] + g2[q]) : (v == ib ? g1[q] : g2[q]);
+        g[q] += d;
+    }
+}
+
 __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
 {
     __shared__ JointState js;
@@ -1816,23 +1829,18 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
         load_weights(m, v, wq, jq);
         shaped_vertex(m, bk, v, x);
         for (int q = 0; q < 3; ++q) g[q] = a.gpos[((size_t)h * V + v) * 3 + q];
-#pragma unroll 4
-        for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
+        // faces around v: the padded corner table with all its loads in
+        // flight together, then the faces beyond it (rare) from the CSR list
+        const int k0 = m.vf_off[v], k1 = m.vf_off[v + 1];
+        int4 cq[kVfSlots];
+#pragma unroll
+        for (int k = 0; k < kVfSlots; ++k) cq[k] = m.vf_corner[(size_t)v * kVfSlots + k];
+#pragma unroll
+        for (int k = 0; k < kVfSlots; ++k)
+            if (k < k1 - k0) normal_corner_grad(v, cq[k].x, cq[k].y, cq[k].z, vh, grh, g);
+        for (int k = k0 + kVfSlots; k < k1; ++k) {
             const int f = m.vf_faces[k];
-            const int ia = m.faces[3 * f], ib = m.faces[3 * f + 1], ic = m.faces[3 * f + 2];
-            float gfs[3];
-            for (int q = 0; q < 3; ++q) gfs[q] = grh[3 * ia + q] + grh[3 * ib + q] + grh[3 * ic + q];
-            const float e1[3] = {vh[3 * ib] - vh[3 * ia], vh[3 * ib + 1] - vh[3 * ia + 1],
-                                 vh[3 * ib + 2] - vh[3 * ia + 2]};
-            const float e2[3] = {vh[3 * ic] - vh[3 * ia], vh[3 * ic + 1] - vh[3 * ia + 1],
-                                 vh[3 * ic + 2] - vh[3 * ia + 2]};
-            const float g1[3] = {e2[1] * gfs[2] - e2[2] * gfs[1], e2[2] * gfs[0] - e2[0] * gfs[2],
-                                 e2[0] * gfs[1] - e2[1] * gfs[0]};
-            const float g2[3] = {gfs[1] * e1[2] - gfs[2] * e1[1], gfs[2] * e1[0] - gfs[0] * e1[2],
-                                 gfs[0] * e1[1] - gfs[1] * e1[0]};
-            if (v == ia) for (int q = 0; q < 3; ++q) g[q] -= g1[q] + g2[q];
-            else if (v == ib) for (int q = 0; q < 3; ++q) g[q] += g1[q];
-            else for (int q = 0; q < 3; ++q) g[q] += g2[q];
+            normal_corner_grad(v, m.faces[3 * f], m.faces[3 * f + 1], m.faces[3 * f + 2], vh, grh, g);
         }
         if (a.grad_verts) {
             float* o = a.grad_verts + ((size_t)h * V + v) * 3;
@@ -1851,25 +1859,28 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
             for (int c = 0; c < 3; ++c) gx[c] += w * y[c];
         }
     }
-    // global rotation (g vp^T) and translation (g)
-    for (int i = 0; i < 3; ++i) {
-        for (int k = 0; k < 3; ++k) wave_store_lds(acc + 3 * i + k, g[i] * vp[k]);
-        wave_store_lds(acc + 9 + i, g[i]);
-    }
-    // shape through the vertex offsets
+    // global rotation (g vp^T) and translation (g), shape through the vertex
+    // offsets: all wave sums interleaved, then stored by lane 63
     {
+        float sv[12 + kMaxShape];
+        for (int i = 0; i < 3; ++i) {
+            for (int k = 0; k < 3; ++k) sv[3 * i + k] = g[i] * vp[k];
+            sv[9 + i] = g[i];
+        }
         const float* sd = m.shapedirs + (size_t)3 * (v < V ? v : 0) * K;
-        float u[kMaxShape];
 #pragma unroll
         for (int k = 0; k < kMaxShape; ++k) {
             const int kk = k < K ? k : K - 1;
             const float s0 = K > 0 ? sd[kk] : 0.0f, s1 = K > 0 ? sd[K + kk] : 0.0f;
             const float s2 = K > 0 ? sd[2 * K + kk] : 0.0f;
-            u[k] = v < V ? s0 * gx[0] + s1 * gx[1] + s2 * gx[2] : 0.0f;
+            sv[12 + k] = v < V ? s0 * gx[0] + s1 * gx[1] + s2 * gx[2] : 0.0f;
         }
-#pragma unroll
-        for (int k = 0; k < kMaxShape; ++k)
-            if (k < K) wave_store_lds(acc + 12 + 12 * J + k, u[k]);
+        wave_sum63_n<12 + kMaxShape>(sv);
+        if (t == 63) {
+            for (int k = 0; k < 12; ++k) acc[k] = sv[k];
+            for (int k = 0; k < kMaxShape; ++k)
+                if (k < K) acc[12 + 12 * J + k] = sv[12 + k];
+        }
     }
     // per joint bound to a vertex of this wave: [dL/dGR_j as w gvp x^T (9),
     // dL/dAt_j as w gvp (3)]
@@ -1883,17 +1894,22 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
 #pragma unroll
             for (int q = 0; q < kMaxInfl; ++q)
                 if (q < m.infl && jq[q] == j) w += wq[q];
-        float* aj = acc + 12 + 12 * j;
+        float sv[12];
         for (int i = 0; i < 3; ++i) {
             const float wg = w * gvp[i];
-            for (int k = 0; k < 3; ++k) wave_store_lds(aj + 3 * i + k, wg * x[k]);
-            wave_store_lds(aj + 9 + i, wg);
+            for (int k = 0; k < 3; ++k) sv[3 * i + k] = wg * x[k];
+            sv[9 + i] = wg;
         }
+        wave_sum63_n<12>(sv);
+        if (t == 63)
+            for (int k = 0; k < 12; ++k) acc[12 + 12 * j + k] = sv[k];
     }
     __syncthreads();
-    float* row = a.part + ((size_t)h * gridDim.x + blockIdx.x) * kSkinPart;
-    for (int i = t; i < n_part; i += 64) row[i] = acc[i];
-    // the last block of the hand finishes (every row is written)
+    // the hand's sums: each block adds its own (memory-side atomics), the
+    // last block to finish reads them and leaves zeros
+    float* sums = a.part + (size_t)h * kSkinPart;
+    for (int i = t; i < n_part; i += 64)
+        if (acc[i] != 0.0f) unsafeAtomicAdd(sums + i, acc[i]);
     __threadfence();
     __syncthreads();
     if (t == 0) last = atomicAdd(a.counter + h, 1) == (int)gridDim.x - 1;
@@ -1901,20 +1917,9 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
     if (!last) return;
     __threadfence();
     if (t == 0) a.counter[h] = 0;
-    const float* rows = a.part + (size_t)h * gridDim.x * kSkinPart;
-    const int nb = gridDim.x;
     for (int i = t; i < n_part; i += 64) {
-        // rows in block order, eight loads in flight
-        float sum = 0.0f;
-        for (int b0 = 0; b0 < nb; b0 += 8) {
-            float x[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = b0 + q < nb ? rows[(size_t)(b0 + q) * kSkinPart + i] : 0.0f;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (b0 + q < nb) sum += x[q];
-        }
-        acc[i] = sum;
+        acc[i] = __hip_atomic_load(sums + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sums[i] = 0.0f;
     }
     __syncthreads();
     float* gp = a.grad_params + 64 * h;
