@@ -193,10 +193,11 @@ __device__ void joint_state(const MeshDev& m, const float* __restrict__ p, Joint
 }
 
 // shaped vertex v: T_v + S_v beta (bk from load_beta)
-__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x)
+// (sd: the vertex's shape directions, entries past K repeat entry K - 1)
+__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x,
+                                              float (&sd)[3][kMaxShape])
 {
     const int K = m.K;
-    float sd[3][kMaxShape];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -229,6 +230,12 @@ __device__ __forceinline__ void blend_vertex(const JointState& js, const float* 
 }
 
 // Skinning, grid (vertex blocks, hands).
+__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x)
+{
+    float sd[3][kMaxShape];
+    shaped_vertex(m, bk, v, x, sd);
+}
+
 __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict__ params,
                                               float* __restrict__ verts, float* __restrict__ joints,
                                               int* __restrict__ tile_count, float* __restrict__ js_out)
@@ -1548,6 +1555,16 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
     const int J = m.J, K = m.K;
     const int j = threadIdx.x;
     if (j >= 64) return;
+    // rows j and j + 64 of J_reg S (joint coordinate row / 3, row % 3 per
+    // shape coefficient), fetched now for the shape gradient at the end
+    float jsr[2][kMaxShape];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < kMaxShape; ++k) {
+            const int row = min(j + 64 * h, 3 * J - 1), kk = k < K ? k : K - 1;
+            jsr[h][k] = K > 0 && J > 0 ? m.js[row * K + kk] : 0.0f;
+        }
     const int dj = j < J ? m.jdepth[j] : -1, par = j < J ? m.parents[j] : -1;
     if (j < J) kids[j] = 0u;
     wave_lds_sync();
@@ -1567,46 +1584,55 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
     // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j: joints of level L finish
     // their own terms and leave those of their parent, which (level L-1) adds
     // them in child order
+    // (each lane works on register copies: its LDS reads go out together
+    // and every value is written once per level)
     for (int L = m.max_depth; L >= 0; --L) {
         if (dj == L) {
+            float oGR[9], oGt[3], oJ[3];
+            for (int i = 0; i < 9; ++i) oGR[i] = gGR[9 * j + i];
+            for (int i = 0; i < 3; ++i) { oGt[i] = gGt[3 * j + i]; oJ[i] = gJ[3 * j + i]; }
             if (par < 0) {
-                for (int i = 0; i < 9; ++i) gR[9 * j + i] = gGR[9 * j + i];
-                for (int i = 0; i < 3; ++i) gJ[3 * j + i] += gGt[3 * j + i];
+                for (int i = 0; i < 9; ++i) gR[9 * j + i] = oGR[i];
+                for (int i = 0; i < 3; ++i) gJ[3 * j + i] = oJ[i] + oGt[i];
             } else {
-                const float* GRp = js.GR + 9 * par;
+                float GRp[9], Rc[9], d[3];
+                for (int i = 0; i < 9; ++i) { GRp[i] = js.GR[9 * par + i]; Rc[i] = js.rod[j].R[i]; }
+                for (int i = 0; i < 3; ++i) d[i] = js.J[3 * j + i] - js.J[3 * par + i];
                 float y[3];
-                matTvec3(GRp, gGt + 3 * j, y);
+                matTvec3(GRp, oGt, y);
                 for (int i = 0; i < 3; ++i) {
-                    gJ[3 * j + i] += y[i];
+                    gJ[3 * j + i] = oJ[i] + y[i];
                     cJ[3 * j + i] = y[i];
                 }
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
                         float s = 0.0f;
-                        for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * gGR[9 * j + 3 * q + k];
+                        for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * oGR[3 * q + k];
                         gR[9 * j + 3 * i + k] = s;
                     }
-                const float* Rc = js.rod[j].R;
-                const float d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
-                                    js.J[3 * j + 2] - js.J[3 * par + 2]};
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
-                        float s = gGt[3 * j + i] * d[k];
-                        for (int q = 0; q < 3; ++q) s += gGR[9 * j + 3 * i + q] * Rc[3 * k + q];
+                        float s = oGt[i] * d[k];
+                        for (int q = 0; q < 3; ++q) s += oGR[3 * i + q] * Rc[3 * k + q];
                         cGR[9 * j + 3 * i + k] = s;
                     }
             }
         }
         wave_lds_sync();
         if (j < J && dj == L - 1) {
+            float aGR[9], aJ[3], aGt[3];
+            for (int i = 0; i < 9; ++i) aGR[i] = gGR[9 * j + i];
+            for (int i = 0; i < 3; ++i) { aJ[i] = gJ[3 * j + i]; aGt[i] = gGt[3 * j + i]; }
             for (unsigned int bits = kids[j]; bits; bits &= bits - 1u) {
                 const int c = __builtin_ctz(bits);
-                for (int i = 0; i < 9; ++i) gGR[9 * j + i] += cGR[9 * c + i];
+                for (int i = 0; i < 9; ++i) aGR[i] += cGR[9 * c + i];
                 for (int i = 0; i < 3; ++i) {
-                    gJ[3 * j + i] -= cJ[3 * c + i];
-                    gGt[3 * j + i] += gGt[3 * c + i];
+                    aJ[i] -= cJ[3 * c + i];
+                    aGt[i] += gGt[3 * c + i];
                 }
             }
+            for (int i = 0; i < 9; ++i) gGR[9 * j + i] = aGR[i];
+            for (int i = 0; i < 3; ++i) { gJ[3 * j + i] = aJ[i]; gGt[3 * j + i] = aGt[i]; }
         }
         wave_lds_sync();
     }
@@ -1614,16 +1640,16 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
     if (j == J) rodrigues_bwd(p + 58, js.rod[J], tot, gp + 58);
     for (int q = J + j; q < 16; q += 64) gp[3 * q] = gp[3 * q + 1] = gp[3 * q + 2] = 0.0f;
     if (j < 3) gp[61 + j] = tot[9 + j];
-    // shape: vertex part + joint part (J = J_reg T + (J_reg S) beta)
-    if (j < 10) {
-        float s = 0.0f;
-        if (j < K) {
-            s = tot[12 + 12 * J + j];
-            for (int q = 0; q < J; ++q)
-                for (int c = 0; c < 3; ++c) s += m.js[(3 * q + c) * K + j] * gJ[3 * q + c];
-        }
-        gp[48 + j] = s;
-    }
+    // shape: vertex part + joint part (J = J_reg T + (J_reg S) beta), the
+    // joint part as lane j's row times dL/dJ[j], summed over the wave
+    float sj[kMaxShape];
+    const float gj0 = j < 3 * J ? gJ[j] : 0.0f, gj1 = j + 64 < 3 * J ? gJ[j + 64] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < kMaxShape; ++k) sj[k] = jsr[0][k] * gj0 + jsr[1][k] * gj1;
+    wave_sum63_n<kMaxShape>(sj);
+    if (j == 63)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) gp[48 + k] = k < K ? tot[12 + 12 * J + k] + sj[k] : 0.0f;
 }
 
 // One Adam update (bias corrections bc1, bc2), the arithmetic of every
@@ -1825,9 +1851,10 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
     unsigned int jmask = 0u;   // joints this vertex is bound to
     float wq[kMaxInfl];
     int jq[kMaxInfl];
+    float sd[3][kMaxShape] = {};
     if (v < V) {
         load_weights(m, v, wq, jq);
-        shaped_vertex(m, bk, v, x);
+        shaped_vertex(m, bk, v, x, sd);
         for (int q = 0; q < 3; ++q) g[q] = a.gpos[((size_t)h * V + v) * 3 + q];
         // faces around v: the padded corner table with all its loads in
         // flight together, then the faces beyond it (rare) from the CSR list
@@ -1867,14 +1894,9 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
             for (int k = 0; k < 3; ++k) sv[3 * i + k] = g[i] * vp[k];
             sv[9 + i] = g[i];
         }
-        const float* sd = m.shapedirs + (size_t)3 * (v < V ? v : 0) * K;
 #pragma unroll
-        for (int k = 0; k < kMaxShape; ++k) {
-            const int kk = k < K ? k : K - 1;
-            const float s0 = K > 0 ? sd[kk] : 0.0f, s1 = K > 0 ? sd[K + kk] : 0.0f;
-            const float s2 = K > 0 ? sd[2 * K + kk] : 0.0f;
-            sv[12 + k] = v < V ? s0 * gx[0] + s1 * gx[1] + s2 * gx[2] : 0.0f;
-        }
+        for (int k = 0; k < kMaxShape; ++k)
+            sv[12 + k] = v < V ? sd[0][k] * gx[0] + sd[1][k] * gx[1] + sd[2][k] * gx[2] : 0.0f;
         wave_sum63_n<12 + kMaxShape>(sv);
         if (t == 63) {
             for (int k = 0; k < 12; ++k) acc[k] = sv[k];
