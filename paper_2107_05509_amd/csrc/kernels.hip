@@ -964,11 +964,14 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 const int f = __builtin_amdgcn_readlane(face, leader);
                 const bool mine = face == f;
                 pending &= ~__ballot(mine);
+                float sv[18];
+#pragma unroll
+                for (int k = 0; k < 18; ++k) sv[k] = mine ? gv[k] : 0.0f;
+                wave_sum63_n<18>(sv);   // the 18 sums interleaved
                 float mine_val = 0.0f;
 #pragma unroll
                 for (int k = 0; k < 18; ++k) {
-                    const float x =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum63(mine ? gv[k] : 0.0f)), 63));
+                    const float x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sv[k]), 63));
                     const int corner = k < 9 ? k / 3 : (k - 9) / 3;
                     const int entry = 6 * corner + (k < 9 ? k % 3 : 3 + (k - 9) % 3);
                     if (lane == entry) mine_val = x;
@@ -1008,37 +1011,34 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 tmask = 0;
             }
             wave_lds_sync();
-#pragma unroll
-            for (int rw = 0; rw < 4; ++rw) {
-                const int src = 16 * rw;
-                if (!__builtin_amdgcn_readlane((int)fits, src)) continue;
-                const int r0 = __builtin_amdgcn_readlane(wr0, src), r1 = __builtin_amdgcn_readlane(wr1, src);
-                const int c0 = __builtin_amdgcn_readlane(wc0, src), c1 = __builtin_amdgcn_readlane(wc1, src);
-                const int ncol = 3 * (c1 - c0 + 1), n = (r1 - r0 + 1) * ncol;
-                float* wrow = patch + rw * (3 * kWin * kWin);
-                if (scalar) {
-                    const float g0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[0]), src));
-                    const float g1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[1]), src));
-                    const float g2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(g[2]), src));
-                    for (int f = lane; f < n; f += 64) {
-                        const int y = f / ncol, x3 = f - ncol * y;
+            // flush: each row's 16 lanes walk its window's used part (the
+            // row's lanes hold the same bounds and, with G >= 16, the same
+            // dL/dI); row y, float x3 of the window from f via a float
+            // reciprocal, exact here (f < 3 kWin^2, distance to the next
+            // integer at least 1/(2 ncol))
+            if (fits) {
+                const int ncol = 3 * (wc1 - wc0 + 1), n = (wr1 - wr0 + 1) * ncol;
+                const float rn = 1.0f / (float)ncol;
+                float* wrow = patch + (lane >> 4) * (3 * kWin * kWin);
+                float* grow = gtex + 3 * ((size_t)wr0 * a.tex_w + wc0);
+                for (int f = lane & 15; f < n; f += 16) {
+                    const int y = (int)(((float)f + 0.5f) * rn);
+                    const int x3 = f - ncol * y;
+                    float x;
+                    if (scalar) {
                         const int xt = x3 / 3, ch = x3 - 3 * xt;
                         float* cell = wrow + y * kWin + xt;
                         const float w = *cell;
                         // the texel's last channel clears it (its other two
                         // channels are read by lower f, no later)
                         if (ch == 2) *cell = 0.0f;
-                        const float x = w * (ch == 0 ? g0 : ch == 1 ? g1 : g2);
-                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * ((r0 + y) * a.tex_w + c0) + x3, x);
-                    }
-                } else {
-                    for (int f = lane; f < n; f += 64) {
-                        const int y = f / ncol, x3 = f - ncol * y;
+                        x = w * (ch == 0 ? g[0] : ch == 1 ? g[1] : g[2]);
+                    } else {
                         float* cell = wrow + y * (3 * kWin) + x3;
-                        const float x = *cell;
+                        x = *cell;
                         *cell = 0.0f;
-                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * ((r0 + y) * a.tex_w + c0) + x3, x);
                     }
+                    if (x != 0.0f) unsafeAtomicAdd(grow + (size_t)y * 3 * a.tex_w + x3, x);
                 }
             }
             wave_lds_sync();
