@@ -878,6 +878,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             // the stored hit is fetched before the sample's random numbers
             // are computed (for every lane: no branch between them)
             const int slot = stored && act ? (int)a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] : -1;
+            if (stored && !__any(slot >= 0)) continue;   // no hit in this round of the tile
             const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
             const uint64_t wd = pick(rr, s & 3);
             const float u = act ? u24_lo(wd) : 0.0f, v = act ? u24_hi(wd) : 0.0f;
