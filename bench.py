@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 from paper_2107_05509_amd import binding, refine, scene  # noqa: E402
 
 METRIC = "fwd+bwd diff-render Mrays/s + refine iters/s (8 views 334x512, 16 spp)"
+CAL_FLOATS = 1 << 27   # calibration copy: 512 MiB in, 512 MiB out
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 128 lanes x 2 x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 
@@ -277,9 +278,10 @@ def main():
     ref.run(args.warmup, graph=graph)
     torch.cuda.synchronize()
     print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-    # a plain device copy of known size (P x 3 float32 in and out): profiler
-    # runs of this command scale their HBM byte counters by what they read for it
-    cal_src = torch.rand(w.n_pixels * 3, device="cuda")
+    # a plain device copy of known size (CAL_FLOATS float32 in and out, far
+    # beyond the L2 and last-level caches): profiler runs of this command
+    # scale their HBM byte counters by what they read for it
+    cal_src = torch.rand(CAL_FLOATS, device="cuda")
     cal_dst = torch.empty_like(cal_src)
     for _ in range(3):
         cal_dst.copy_(cal_src)

@@ -980,18 +980,19 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 if (lane < 18) unsafeAtomicAdd(a.gface + ((size_t)hand * a.n_faces + f) * 18 + lane, mine_val);
             }
             // Colour map: each row of 16 lanes sums its samples' bilinear
-            // footprints into an LDS window of up to kWin x kWin texels, then
+            // footprints into an LDS window of up to W x W texels, then
             // adds the window's used part to the gradient, consecutive lanes
             // on consecutive floats, clearing it for the next use.  Where the
             // row's lanes all belong to one pixel (G >= 16) they share dL/dI
             // and the window holds one weight per texel (dL/dI is applied in
-            // the flush); otherwise it holds RGB.  Rows whose footprint does
+            // the flush, W = kWin); otherwise it holds RGB (W = kWinRGB).  Rows whose footprint does
             // not fit (a texture seam inside the row) scatter directly.
             const bool scalar = G >= 16;
             const int wr0 = row_min(fi0), wr1 = row_max(fi1);
             const int wc0 = row_min(fj0), wc1 = row_max(fj1);
-            const bool fits = wr1 >= wr0 && wr1 - wr0 < kWin && wc1 - wc0 < kWin;   // uniform in the row
-            float* win = patch + (lane >> 4) * (3 * kWin * kWin);
+            const int W = scalar ? kWin : kWinRGB;
+            const bool fits = wr1 >= wr0 && wr1 - wr0 < W && wc1 - wc0 < W;   // uniform in the row
+            float* win = patch + (lane >> 4) * (kWin * kWin);
             if (tmask && fits) {
                 // start at corner (lane & 3): lanes sharing a footprint hit
                 // different LDS words in each of the four steps
@@ -1000,7 +1001,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                     const int k = (q + lane) & 3;
                     const int ri = (k & 2) ? fi1 : fi0, rj = (k & 1) ? fj1 : fj0;
                     const float wk = k == 0 ? twt[0] : k == 1 ? twt[1] : k == 2 ? twt[2] : twt[3];
-                    const int cell = (ri - wr0) * kWin + (rj - wc0);
+                    const int cell = (ri - wr0) * W + (rj - wc0);
                     if (scalar) {
                         atomicAdd(win + cell, wk);
                     } else {
@@ -1020,7 +1021,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             if (fits) {
                 const int ncol = 3 * (wc1 - wc0 + 1), n = (wr1 - wr0 + 1) * ncol;
                 const float rn = 1.0f / (float)ncol;
-                float* wrow = patch + (lane >> 4) * (3 * kWin * kWin);
+                float* wrow = patch + (lane >> 4) * (kWin * kWin);
                 float* grow = gtex + 3 * ((size_t)wr0 * a.tex_w + wc0);
                 for (int f = lane & 15; f < n; f += 16) {
                     const int y = (int)(((float)f + 0.5f) * rn);
@@ -1035,7 +1036,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                         if (ch == 2) *cell = 0.0f;
                         x = w * (ch == 0 ? g[0] : ch == 1 ? g[1] : g[2]);
                     } else {
-                        float* cell = wrow + y * (3 * kWin) + x3;
+                        float* cell = wrow + y * (3 * kWinRGB) + x3;
                         x = *cell;
                         *cell = 0.0f;
                     }
