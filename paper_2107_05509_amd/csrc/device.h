@@ -16,7 +16,7 @@ constexpr int kMaxStack = 24;       // traversal stack entries per lane
 constexpr int kLeafMax = 4;         // triangles per leaf
 constexpr int kThreads = 256;       // threads per block of the ray-tracing kernels
 constexpr int kEdgeBlocks = 256;    // blocks of edge samples in the backward launch
-constexpr int kMaxTraceBlocks = 4096;   // largest persistent ray-tracing grid
+constexpr int kMaxTraceBlocks = 16384;  // largest ray-tracing grid
 constexpr int kWin = 16;            // texel window (per row of 16 lanes) of the colour-map gradient: kWin^2 weights
 constexpr int kWinRGB = 9;          // ... or kWinRGB^2 RGB texels (3 kWinRGB^2 <= kWin^2)
 constexpr int kWaveWin = 4 * kWin * kWin;   // floats of one wave's four row windows
