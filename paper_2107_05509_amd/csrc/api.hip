@@ -314,8 +314,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             }
         TRY(s->upload(&q, off.data(), off.size())); md.vf_off = q;
         TRY(s->upload(&q, flat.data(), flat.size())); md.vf_faces = q;
-        // the same lists as vertex triples, kVfSlots per vertex, padded with
-        // (v, v, v): a degenerate face adds nothing to the normal backward
+        // the same lists as (vertex triple, face), kVfSlots per vertex, padded
+        // with (v, v, v, 0): a degenerate face adds nothing to the normal backward
         std::vector<int> vc(4 * (size_t)V * kVfSlots, 0);
         for (int v = 0; v < V; ++v)
             for (int k = 0; k < kVfSlots; ++k) {
@@ -323,8 +323,10 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
                 if (off[v] + k < off[v + 1]) {
                     const int f = flat[off[v] + k];
                     for (int c = 0; c < 3; ++c) d[c] = m->faces[3 * f + c];
+                    d[3] = f;
                 } else {
                     d[0] = d[1] = d[2] = v;
+                    d[3] = 0;
                 }
             }
         TRY(s->upload(&q, vc.data(), vc.size())); md.vf_corner = reinterpret_cast<const int4*>(q);

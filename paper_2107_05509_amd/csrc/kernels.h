@@ -27,7 +27,7 @@ struct MeshDev {
     const int* vf_off;         // [V+1]
     const int* vf_faces;       // [3F]
     const int4* vf_corner;     // [V,kVfSlots] the first kVfSlots faces around each vertex as
-                               // (a, b, c, 0) vertex triples, padded with (v, v, v, 0)
+                               // (a, b, c, face), padded with (v, v, v, 0)
     const float* jt;           // [J,3] J_reg T: rest joints of the template
     const float* js;           // [J,3,K] J_reg S: joint displacement per shape coefficient
     const int* jdepth;         // [J] depth in the joint tree (root 0)

@@ -1760,10 +1760,13 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
         for (int k = 0; k < 3; ++k) { g[k] += ga[k]; gn[k] += ga[3 + k]; }
     }
     float sv[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll 4
-    for (int k = m.vf_off[v]; k < m.vf_off[v + 1]; ++k) {
-        const int f = m.vf_faces[k];
-        const int i0 = m.faces[3 * f], i1 = m.faces[3 * f + 1], i2 = m.faces[3 * f + 2];
+    // faces around v: the corner table's entries with all their loads in
+    // flight, then any faces beyond it from the CSR list, in list order
+    const int k0 = m.vf_off[v], k1 = m.vf_off[v + 1];
+    int4 cq[kVfSlots];
+#pragma unroll
+    for (int k = 0; k < kVfSlots; ++k) cq[k] = m.vf_corner[(size_t)v * kVfSlots + k];
+    auto face_terms = [&](int f, int i0, int i1, int i2) {
         const int corner = i0 == v ? 0 : (i1 == v ? 1 : 2);
         const float* sl = gf + 18 * f + 6 * corner;
         for (int q = 0; q < 3; ++q) { g[q] += sl[q]; gn[q] += sl[3 + q]; }
@@ -1775,6 +1778,13 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
         sv[0] += e1[1] * e2[2] - e1[2] * e2[1];
         sv[1] += e1[2] * e2[0] - e1[0] * e2[2];
         sv[2] += e1[0] * e2[1] - e1[1] * e2[0];
+    };
+#pragma unroll
+    for (int k = 0; k < kVfSlots; ++k)
+        if (k < k1 - k0) face_terms(cq[k].w, cq[k].x, cq[k].y, cq[k].z);
+    for (int k = k0 + kVfSlots; k < k1; ++k) {
+        const int f = m.vf_faces[k];
+        face_terms(f, m.faces[3 * f], m.faces[3 * f + 1], m.faces[3 * f + 2]);
     }
     const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
     const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
