@@ -586,9 +586,9 @@ static Shading shading_of(const hr_config& c)
 
 // `dimage` (with target, mask): the L1 loss gradient is written with the
 // image, scaled by the view_scale a preceding prepare (with_scale) left.
-// n_edge > 0: that many blocks trace the edge samples beside the render (the
-// weights and budget prefix are built beforehand: edge_trace_impl, trace
-// false).
+// n_edge > 0: the render blocks also trace the edge samples, each its share
+// after its tiles (the weights and budget prefix are built beforehand:
+// edge_trace_impl, trace false).
 static int render_impl(hr_scene* s, const float* verts, const float* albedo, const float* background, uint32_t iter,
                        const int* iter_dev, float* image, int32_t* hit_face, hipStream_t st, bool prepared = false,
                        float* const* clear = nullptr, const long long* clear_n = nullptr,
@@ -619,9 +619,10 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
     const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
-    const dim3 grid(n_edge + s->render_blocks);
-    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, n_edge);
-    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, n_edge);
+    const dim3 grid(s->render_blocks);
+    const int with_edges = n_edge > 0 ? 1 : 0;
+    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, with_edges);
+    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
 }
 
 // Edge samples, first part: silhouette tables (unless done), learned sampling

@@ -1487,20 +1487,17 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int
 // launches of the ray-tracing work
 // ===========================================================================
 
-// Render; the first `n_setup` blocks build the silhouette tables of the views
-// (they need only the geometry) alongside the render blocks.
+// Render: every block renders its share of the wave tiles (one traversal
+// stack per wave), then, with edges, traces its share of the edge samples'
+// side points (a traversal stack per lane), so no block slot idles while work
+// of either kind remains.
 template <bool COUNT>
-__global__ void __launch_bounds__(kThreads, 4) k_render(RenderArgs a, EdgeArgs e, int n_edge)
+__global__ void __launch_bounds__(kThreads, 4) k_render(RenderArgs a, EdgeArgs e, int with_edges)
 {
-    // edge blocks trace the edge samples' side points (a traversal stack per
-    // lane) beside the render blocks (one stack per wave)
     __shared__ int stack[kMaxStack * kThreads];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
-    if ((int)blockIdx.x < n_edge) {
-        edge_samples<COUNT, kEdgeTrace>(e, blockIdx.x, n_edge, stack, wstack);
-        return;
-    }
-    render_tiles<COUNT>(a, (int)blockIdx.x - n_edge, (int)gridDim.x - n_edge, wstack);
+    render_tiles<COUNT>(a, (int)blockIdx.x, (int)gridDim.x, wstack);
+    if (with_edges) edge_samples<COUNT, kEdgeTrace>(e, (int)blockIdx.x, (int)gridDim.x, stack, wstack);
 }
 
 // Edge samples, first part: trace and shade both side points of every stored
