@@ -193,23 +193,39 @@ __device__ void joint_state(const MeshDev& m, const float* __restrict__ p, Joint
 }
 
 // shaped vertex v: T_v + S_v beta (bk from load_beta)
-// (sd: the vertex's shape directions, entries past K repeat entry K - 1)
-__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x,
-                                              float (&sd)[3][kMaxShape])
+// the vertex's rest data: template position and shape directions (sd
+// entries past K repeat entry K - 1)
+__device__ __forceinline__ void load_shape(const MeshDev& m, int v, float* tpl, float (&sd)[3][kMaxShape])
 {
     const int K = m.K;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int c = 0; c < 3; ++c) {
+        tpl[c] = m.v_template[3 * v + c];
 #pragma unroll
         for (int k = 0; k < kMaxShape; ++k) sd[c][k] = K > 0 ? m.shapedirs[(3 * v + c) * K + (k < K ? k : K - 1)] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void shape_vertex(const MeshDev& m, const float* bk, const float* tpl,
+                                             const float (&sd)[3][kMaxShape], float* x)
+{
+    const int K = m.K;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float s = m.v_template[3 * v + c];
+        float s = tpl[c];
 #pragma unroll
         for (int k = 0; k < kMaxShape; ++k)
             if (k < K) s += sd[c][k] * bk[k];
         x[c] = s;
     }
+}
+
+__device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x,
+                                              float (&sd)[3][kMaxShape])
+{
+    float tpl[3];
+    load_shape(m, v, tpl, sd);
+    shape_vertex(m, bk, tpl, sd, x);
 }
 
 // posed (pre-global-transform) vertex: sum over the vertex's skinning
@@ -229,13 +245,13 @@ __device__ __forceinline__ void blend_vertex(const JointState& js, const float* 
     }
 }
 
-// Skinning, grid (vertex blocks, hands).
 __device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk, int v, float* x)
 {
     float sd[3][kMaxShape];
     shaped_vertex(m, bk, v, x, sd);
 }
 
+// Skinning, grid (vertex blocks, hands).
 __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict__ params,
                                               float* __restrict__ verts, float* __restrict__ joints,
                                               int* __restrict__ tile_count, float* __restrict__ js_out)
@@ -245,6 +261,15 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
     // nullable: the wave-tile list of a following refit starts empty
     if (tile_count && blockIdx.x == 0 && h == 0 && threadIdx.x == 0) *tile_count = 0;
     const float* p = params + 64 * h;
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    // the vertex's tables first: their loads are in flight with the joint
+    // state's
+    float tpl[3] = {0.0f, 0.0f, 0.0f}, sd[3][kMaxShape] = {}, wq[kMaxInfl] = {};
+    int jq[kMaxInfl] = {};
+    if (v < m.V) {
+        load_weights(m, v, wq, jq);
+        load_shape(m, v, tpl, sd);
+    }
     joint_state(m, p, js);
     // nullable: the joint state of these parameters for the backward
     if (js_out && blockIdx.x == 0) {
@@ -253,14 +278,11 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
             js_out[(size_t)h * kJointStateFloats + i] = src[i];
     }
     const float* tau = p + 61;
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
     float bk[kMaxShape];
     load_beta(m, p + 48, bk);
     if (v < m.V) {
-        float x[3], vp[3], y[3], wq[kMaxInfl];
-        int jq[kMaxInfl];
-        load_weights(m, v, wq, jq);
-        shaped_vertex(m, bk, v, x);
+        float x[3], vp[3], y[3];
+        shape_vertex(m, bk, tpl, sd, x);
         blend_vertex(js, wq, jq, x, vp);
         matvec3(js.Rp, vp, y);
         float* o = verts + ((size_t)h * m.V + v) * 3;
@@ -1834,6 +1856,15 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
     const int V = m.V, J = m.J, K = m.K;
     const int n_part = 12 + 12 * J + K;
     const float* p = a.params + 64 * h;
+    const int v = blockIdx.x * 64 + t;
+    // the vertex's tables first: their loads are in flight with the joint
+    // state's
+    float tpl[3] = {0.0f, 0.0f, 0.0f}, sd[3][kMaxShape] = {}, wq[kMaxInfl] = {};
+    int jq[kMaxInfl] = {};
+    if (v < V) {
+        load_weights(m, v, wq, jq);
+        load_shape(m, v, tpl, sd);
+    }
     for (int i = t; i < n_part; i += 64) acc[i] = 0.0f;
     if (a.js_saved) {
         // the skinning launch of these parameters left the joint state
@@ -1854,16 +1885,11 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
     const float* grh = a.gr + (size_t)h * V * 3;
     float bk[kMaxShape];
     load_beta(m, p + 48, bk);
-    const int v = blockIdx.x * 64 + t;
     float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, vp[3] = {0.0f, 0.0f, 0.0f};
     float gvp[3] = {0.0f, 0.0f, 0.0f}, gx[3] = {0.0f, 0.0f, 0.0f};
     unsigned int jmask = 0u;   // joints this vertex is bound to
-    float wq[kMaxInfl];
-    int jq[kMaxInfl];
-    float sd[3][kMaxShape] = {};
     if (v < V) {
-        load_weights(m, v, wq, jq);
-        shaped_vertex(m, bk, v, x, sd);
+        shape_vertex(m, bk, tpl, sd, x);
         for (int q = 0; q < 3; ++q) g[q] = a.gpos[((size_t)h * V + v) * 3 + q];
         // faces around v: the padded corner table with all its loads in
         // flight together, then the faces beyond it (rare) from the CSR list
