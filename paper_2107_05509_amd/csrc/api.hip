@@ -69,7 +69,7 @@ struct hr_scene {
     std::vector<ViewDev> views_host;
     TileShape ts{};
     int2* tiles = nullptr;        // wave tiles inside the per-view screen bounds
-    short* hit_slot = nullptr;    // [tile_cap, rounds, 64] hits of the last render (leaf slot, -1 miss)
+    uint64_t* hit_rec = nullptr;  // [tile_cap, rounds, 64] samples of the last render (random word, leaf slot)
     int* hit_iter = nullptr;      // iteration of those hits (-1: none)
     int4* view_rect = nullptr;    // [n_views] pixel rectangle of each view's tiles (screen-bounds pass)
     long long tile_cap = 0;
@@ -445,7 +445,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     }
     // per-iteration state
     TRY(s->upload<int2>(&s->tiles, nullptr, (size_t)s->tile_cap));
-    TRY(s->upload<short>(&s->hit_slot, nullptr, (size_t)s->tile_cap * s->ts.rounds * 64));
+    TRY(s->upload<uint64_t>(&s->hit_rec, nullptr, (size_t)s->tile_cap * s->ts.rounds * 64));
     TRY(s->upload<int>(&s->hit_iter, nullptr, 1));
     TRY(s->upload<int4>(&s->view_rect, nullptr, (size_t)n_views));
 
@@ -607,7 +607,7 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.tiles = s->tiles; a.tile_count = s->tile_count; a.ts = s->ts; a.views = s->views;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.image = image; a.hit_face = hit_face;
-    a.hit_slot = s->hit_slot; a.hit_iter = s->hit_iter;
+    a.hit_rec = s->hit_rec; a.hit_iter = s->hit_iter;
     a.view_rect = s->view_rect; a.n_views = s->n_views;
     a.dimage = dimage; a.target = target; a.mask = mask; a.view_scale = s->view_scale;
     for (int k = 0; k < 3; ++k) {
@@ -825,7 +825,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.dimage = dimage; a.grad_albedo = grad_albedo; a.gface = s->gface;
     // the render's hits are valid for the geometry it prepared
-    a.hit_slot = (flags & HR_REUSE_GEOMETRY) ? s->hit_slot : nullptr;
+    a.hit_rec = (flags & HR_REUSE_GEOMETRY) ? s->hit_rec : nullptr;
     a.hit_iter = s->hit_iter;
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;

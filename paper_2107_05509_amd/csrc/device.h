@@ -98,6 +98,20 @@ __device__ __forceinline__ U64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c
 __device__ __forceinline__ float u24_lo(uint64_t r) { return (float)((uint32_t)r >> 8) * 0x1p-24f; }
 __device__ __forceinline__ float u24_hi(uint64_t r) { return (float)(r >> 40) * 0x1p-24f; }
 
+// A stored camera sample: its random word (bits 8..31 and 40..63 are u and
+// v) with the hit's leaf slot (int16, -1 miss) in the bits u and v leave out
+// (0..7 low byte, 32..39 high byte).
+__device__ __forceinline__ uint64_t hit_record(uint64_t wd, int slot)
+{
+    const uint64_t s16 = (uint64_t)(uint16_t)slot;
+    return (wd & 0xFFFFFF00FFFFFF00ull) | (s16 & 0xFFu) | ((s16 >> 8) << 32);
+}
+
+__device__ __forceinline__ int hit_record_slot(uint64_t rec)
+{
+    return (int)(int16_t)(uint16_t)((rec & 0xFFu) | ((rec >> 24) & 0xFF00u));
+}
+
 constexpr uint64_t kDomainCamera = 0;
 constexpr uint64_t kDomainEdge = 1;
 

@@ -70,7 +70,7 @@ struct RenderArgs {
     const float* background;
     float* image;
     int* hit_face;
-    short* hit_slot;           // [tiles, rounds, 64] leaf slot of each sample's hit (-1 miss), for the adjoint
+    uint64_t* hit_rec;         // [tiles, rounds, 64] each sample's random word and hit leaf slot (hit_record), for the adjoint
     int* hit_iter;             // iteration of the stored hits
     const int4* view_rect;     // nullable: [n_views] pixel rectangle of each view's tiles; pixels
                                // outside it are set to the background by the render blocks
@@ -103,7 +103,7 @@ struct AdjointArgs {
     const float* dimage;
     float* grad_albedo;
     float* gface;              // [hands,F,18] per-triangle corner gradients
-    const short* hit_slot;     // nullable: hits stored by the render of the same geometry
+    const uint64_t* hit_rec;   // nullable: sample records stored by the render of the same geometry
     const int* hit_iter;
     unsigned long long* counts;
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;

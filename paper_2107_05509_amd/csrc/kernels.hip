@@ -642,9 +642,10 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             const int s = s_lane + 64 * r;
             const bool act = pix_ok && s < a.spp;
             float u = 0.0f, v = 0.0f;
+            uint64_t wd = 0;
             if (act) {
                 const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
-                const uint64_t wd = pick(rr, s & 3);
+                wd = pick(rr, s & 3);
                 u = u24_lo(wd);
                 v = u24_hi(wd);
             }
@@ -655,7 +656,7 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             if (act) {
                 if (COUNT) ++n_rays;
                 if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
-                if (a.hit_slot) a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] = (short)(h.face >= 0 ? h.slot : -1);
+                if (a.hit_rec) a.hit_rec[((size_t)t * a.ts.rounds + r) * 64 + lane] = hit_record(wd, h.face >= 0 ? h.slot : -1);
                 if (h.face >= 0) {
                     if (COUNT) ++n_hit;
                     Surf sf;
@@ -853,7 +854,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
     const float inv_spp = 1.0f / (float)a.spp;
     const Shading S = a.shading;
     // hits stored by the render of the same geometry and iteration: no re-trace
-    const bool stored = a.hit_slot != nullptr && __builtin_amdgcn_readfirstlane(*a.hit_iter) == (int)iter;
+    const bool stored = a.hit_rec != nullptr && __builtin_amdgcn_readfirstlane(*a.hit_iter) == (int)iter;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
     // wave-uniform tile entries through the scalar cache, the next one
@@ -897,12 +898,16 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             int tmask = 0;
             int fi0 = 0x7fffffff, fi1 = -1, fj0 = 0x7fffffff, fj1 = -1;   // footprint rows / columns
             const bool act = live && s < a.spp;
-            // the stored hit is fetched before the sample's random numbers
-            // are computed (for every lane: no branch between them)
-            const int slot = stored && act ? (int)a.hit_slot[((size_t)t * a.ts.rounds + r) * 64 + lane] : -1;
+            // a stored hit record carries the sample's random word: no
+            // Philox here; re-traced samples draw it again
+            const uint64_t rec = stored && act ? a.hit_rec[((size_t)t * a.ts.rounds + r) * 64 + lane] : 0ull;
+            const int slot = stored && act ? hit_record_slot(rec) : -1;
             if (stored && !__any(slot >= 0)) continue;   // no hit in this round of the tile
-            const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
-            const uint64_t wd = pick(rr, s & 3);
+            uint64_t wd = rec;
+            if (!stored) {
+                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
+                wd = pick(rr, s & 3);
+            }
             const float u = act ? u24_lo(wd) : 0.0f, v = act ? u24_hi(wd) : 0.0f;
             Hit h;
             if (stored) {
