@@ -228,6 +228,7 @@ struct Hit {
 // exact sample ray: the float32 test decides the triangle, float64 gives the
 // position on it (well conditioned even at grazing incidence).
 struct Surf {
+    int face;         // face id of the triangle
     int i0, i1, i2;
     float b0, b1, b2;
     double tu, tv;    // texture coordinates (float64: texel positions stay exact)
@@ -485,6 +486,7 @@ __device__ __forceinline__ void surface(const Tri* __restrict__ tris, const floa
     float4 p2 = *reinterpret_cast<const float4*>(&tr.v[8]);
     s.v[0] = p0.x; s.v[1] = p0.y; s.v[2] = p0.z; s.v[3] = p0.w; s.v[4] = p1.x;
     s.v[5] = p1.y; s.v[6] = p1.z; s.v[7] = p1.w; s.v[8] = p2.x;
+    s.face = __float_as_int(p2.y);
     s.i0 = __float_as_int(p2.z); s.i1 = __float_as_int(p2.w); s.i2 = tr.i2;
     ray_dir64(c, X, Y, s.d);
     double e1[3], e2[3], q[3], pv[3], sv[3];

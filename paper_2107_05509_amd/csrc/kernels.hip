@@ -912,7 +912,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
             Hit h;
             if (stored) {
                 h.slot = slot;
-                h.face = slot >= 0 ? tris[slot].face : -1;
+                h.face = slot;   // >= 0 for a hit; the face id comes with the triangle below
             } else {
                 Ray ray;
                 ray_screen(c, (float)px + u, (float)py + v, ray);
@@ -922,9 +922,9 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 if (COUNT) ++n_rays;
                 if (h.face >= 0) {
                     if (COUNT) ++n_hit;
-                    face = h.face;
                     Surf sf;
                     surface(tris, a.uv, h.slot, c, px + (double)u, py + (double)v, sf);
+                    face = sf.face;
                     Shade sd;
                     shade_hit(sf, normals, a.uv, tex, a.tex_h, a.tex_w, S, sd);
                     for (int k = 0; k < 4; ++k) {
