@@ -80,7 +80,7 @@ def make_refiner(w, dev="cuda:0", seed=0, tune=True, cover_spp=64):
     mask = refine.coverage_mask(hits, w.cams, w.pixel_offsets(), 9)
     del hits, gt, alb_true
     r = refine.Refiner(g, t(w.params_init.astype(np.float32)), t(w.albedo_init.astype(np.float32)), bg, target,
-                       mask, warm=50, graph_chunk=10)
+                       mask, warm=50, graph_chunk=50)
     r.build_hierarchy()
     if tune:
         r.tune(reps=3)
