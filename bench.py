@@ -83,7 +83,7 @@ def make_refiner(w, dev="cuda:0", seed=0, tune=True, cover_spp=64):
                        mask, warm=50, graph_chunk=50)
     r.build_hierarchy()
     if tune:
-        r.tune(reps=3)
+        r.tune(reps=10)
     return r
 
 

@@ -1096,7 +1096,7 @@ int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_ho
         if (!r) (void)hipEventElapsedTime(ms, e0, e1);
         return r;
     };
-    static const int kCand[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192, 12288, 16384};
+    static const int kCand[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096};
     float best = 0.0f;
     int best_r = s->render_blocks, best_a = s->adjoint_blocks;
     for (int pass = 0; pass < 2 && !rc; ++pass) {
