@@ -98,10 +98,12 @@ def cpu_baseline(w, ref, views=1):
     om = oracle.Model(w.model)
     P = int(tab["pix_off"][-1])
     p = torch.as_tensor(w.params_init.astype(np.float32).astype(np.float64))
-    bg = ref.state.background[:P].cpu().numpy().astype(np.float64)
+    # host inputs only (nothing the GPU computed): the views' backgrounds,
+    # a seeded target of the same shape, every pixel in the mask
+    bg = np.asarray(w.packed_background(), np.float64)[:P]
     alb = w.albedo_init.astype(np.float64)
-    target = ref.state.target[:P].cpu().numpy().astype(np.float64)
-    mask = ref.state.mask[:P].cpu().numpy()
+    target = np.clip(bg + np.random.default_rng(7).normal(0.0, 0.1, bg.shape), 0.0, 1.0)
+    mask = np.ones(P, np.uint8)
     t0 = time.perf_counter()
     v, _ = oracle.skin(om, p)
     n = oracle.vertex_normals(v, om.faces)
