@@ -234,6 +234,8 @@ struct Surf {
     double tu, tv;    // texture coordinates (float64: texel positions stay exact)
     float v[9];       // triangle vertices
     double d[3];      // float64 ray direction (unnormalised, camera depth scale)
+    double pv[3];     // d x (v2 - v0) and 1 / det of the solve (reused by the adjoint)
+    double idet;
 };
 
 __device__ __forceinline__ bool slab(const Ray& r, const float* lo, const float* hi, float tmax_in,
@@ -503,8 +505,11 @@ __device__ __forceinline__ void surface(const Tri* __restrict__ tris, const floa
     q[0] = sv[1] * e1[2] - sv[2] * e1[1];
     q[1] = sv[2] * e1[0] - sv[0] * e1[2];
     q[2] = sv[0] * e1[1] - sv[1] * e1[0];
-    double b1 = (sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2]) / det;
-    double b2 = (s.d[0] * q[0] + s.d[1] * q[1] + s.d[2] * q[2]) / det;
+    const double idet = 1.0 / det;
+    double b1 = (sv[0] * pv[0] + sv[1] * pv[1] + sv[2] * pv[2]) * idet;
+    double b2 = (s.d[0] * q[0] + s.d[1] * q[1] + s.d[2] * q[2]) * idet;
+    s.idet = idet;
+    s.pv[0] = pv[0]; s.pv[1] = pv[1]; s.pv[2] = pv[2];
     const double b0 = 1.0 - b1 - b2;
     s.b0 = (float)b0;
     s.b1 = (float)b1;

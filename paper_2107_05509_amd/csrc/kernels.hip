@@ -960,19 +960,18 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                             gb2 += gr * (n2[k] - n0[k]);
                         }
                     }
-                    // hit point: y = M^{-T} [gb1, gb2, 0], M = [v1-v0, v2-v0, -d] (float64)
-                    double e1[3], e2[3], md[3];
+                    // hit point: y = M^{-T} [gb1, gb2, 0], M = [v1-v0, v2-v0, -d] (float64);
+                    // M's cofactor column (v2-v0) x (-d) = d x (v2-v0) and 1/det M
+                    // come with the surface point's solve
+                    double e1[3], md[3];
                     for (int k = 0; k < 3; ++k) {
                         e1[k] = (double)sf.v[3 + k] - (double)sf.v[k];
-                        e2[k] = (double)sf.v[6 + k] - (double)sf.v[k];
                         md[k] = -sf.d[k];
                     }
-                    const double c23[3] = {e2[1] * md[2] - e2[2] * md[1], e2[2] * md[0] - e2[0] * md[2],
-                                           e2[0] * md[1] - e2[1] * md[0]};
+                    const double* c23 = sf.pv;
                     const double c31[3] = {md[1] * e1[2] - md[2] * e1[1], md[2] * e1[0] - md[0] * e1[2],
                                            md[0] * e1[1] - md[1] * e1[0]};
-                    const double det = e1[0] * c23[0] + e1[1] * c23[1] + e1[2] * c23[2];
-                    const double idet = 1.0 / det;
+                    const double idet = sf.idet;
                     for (int k = 0; k < 3; ++k) {
                         const float y = (float)(((double)gb1 * c23[k] + (double)gb2 * c31[k]) * idet);
                         gv[k] = -sf.b0 * y;
