@@ -941,7 +941,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     };
     // one stream: skinning (emptying the tile list), one preparation launch
     // (refit, silhouette tables, tiles, loss scales), the learned weights and
-    // budget prefix, the render with the edge samples traced beside it and
+    // budget prefix, the render with the edge samples traced by its blocks and
     // the loss gradient written with the image, the ray-tracing backward with
     // the loss partial sums beside it, the geometry backward with the loss
     // values and both Adam steps; training of a learned proposal on the side
