@@ -271,6 +271,17 @@ def skin(m: Model, params):
     return verts, joints
 
 
+def joint_prior(joints, target, lam, gamma):
+    """lambda E2 per hand (Section 3.3, the prior term of the objective
+    E = E1 + lambda E2): over joints [H,J,3] and their coordinates, the smooth
+    L1 distance to the target joints with threshold gamma, d^2 / (2 gamma)
+    where |d| < gamma and |d| - gamma / 2 elsewhere."""
+    d = joints - torch.as_tensor(np.asarray(target, dtype=np.float64))
+    ad = d.abs()
+    f = torch.where(ad < gamma, 0.5 * d * d / gamma, ad - 0.5 * gamma)
+    return lam * f.sum(dim=(1, 2))
+
+
 def vertex_normals(verts, faces):
     """Unit vertex normals: normalised sum of the incident faces' (v1-v0)x(v2-v0)."""
     v0 = verts[:, faces[:, 0]]
@@ -330,9 +341,10 @@ def adam_step(x, g, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, lo=None, hi=N
 # --------------------------------------------------------------------------
 
 def gradient(model: Model, sc: Scene, params, albedo, background, target, mask, spp, seed, it,
-             delta=1e-3, edges=True, interior=True):
+             delta=1e-3, edges=True, interior=True, prior=None):
     """Loss per hand and its gradient w.r.t. params [H,64] and albedo, plus the
-    intermediate arrays (for stage-by-stage comparisons)."""
+    intermediate arrays (for stage-by-stage comparisons).  prior: optional
+    (target joints [H,J,3], lambda, gamma) of the joint prior, added to both."""
     p = torch.as_tensor(np.asarray(params, dtype=np.float64)).clone().requires_grad_(True)
     verts, joints = skin(model, p)
     normals = vertex_normals(verts, model.faces)
@@ -348,7 +360,13 @@ def gradient(model: Model, sc: Scene, params, albedo, background, target, mask, 
         gv = gv + gv_i
     if edges:
         gv = gv + backward_edges(sc, v_np, n_np, albedo, background, dimg, seed, it, delta)
-    torch.autograd.backward([verts, normals], [torch.as_tensor(gv), torch.as_tensor(gn)])
+    outs, grads = [verts, normals], [torch.as_tensor(gv), torch.as_tensor(gn)]
+    if prior is not None:
+        e2 = joint_prior(joints, *prior)
+        loss = loss + e2.detach().numpy()
+        outs.append(e2.sum())
+        grads.append(None)
+    torch.autograd.backward(outs, grads)
     return dict(loss=loss, grad_params=p.grad.numpy().copy(), grad_albedo=ga, image=img,
                 dimage=dimg, verts=v_np, normals=n_np, joints=joints.detach().numpy(),
                 g_verts=gv, g_normals=gn)

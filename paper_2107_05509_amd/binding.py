@@ -22,7 +22,7 @@ HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
-           "hr_loss", "hr_backward", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
+           "hr_loss", "hr_backward", "hr_set_joint_prior", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
            "hr_graph_destroy", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
@@ -98,6 +98,7 @@ def lib():
         L.hr_render.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp]
         L.hr_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
+        L.hr_set_joint_prior.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float]
         L.hr_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(AdamConfig), vp]
         L.hr_iterate.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(AdamConfig), u32, vp]
         L.hr_graph_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(State), ctypes.POINTER(AdamConfig), u32,
@@ -123,7 +124,8 @@ def lib():
         L.hr_timing_enable.argtypes = [vp, i32]
         L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.hr_last_error.restype = ctypes.c_char_p
-        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_step", "hr_iterate",
+        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_set_joint_prior",
+                     "hr_step", "hr_iterate",
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats",
                      "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
                      "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
@@ -249,6 +251,14 @@ class Scene:
             _ptr(grad_albedo, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="grad_albedo"),
             _ptr(grad_verts, shape=(self.n_hands, self.V, 3), name="grad_verts"),
             _ptr(grad_normals, shape=(self.n_hands, self.V, 3), name="grad_normals"), _stream()), "hr_backward")
+
+    def set_joint_prior(self, target_joints=None, lam=0.0, gamma=0.005):
+        """Joint prior lambda E2 (Section 3.3) for the backwards enqueued from now
+        on: target_joints a CUDA float32 tensor [n_hands,J,3] (the scene keeps a
+        reference: the library reads it at every backward), None to switch off."""
+        ptr = _ptr(target_joints, shape=(self.n_hands, self.J, 3), name="target_joints")
+        _check(lib().hr_set_joint_prior(self._h, ptr, float(lam), float(gamma)), "hr_set_joint_prior")
+        self._prior_target = target_joints
 
     def step(self, params, albedo, grad_params, grad_albedo, m_p, v_p, m_a, v_a, t, lrs, betas=(0.9, 0.999),
              eps=1e-8):

@@ -84,6 +84,9 @@ struct hr_scene {
     int* hand_views = nullptr;
     float* normals = nullptr;
     Tri* tris = nullptr;
+    // joint prior (hr_set_joint_prior): caller-owned target joints, weight, threshold
+    const float* prior_target = nullptr;
+    float prior_lambda = 0.0f, prior_gamma = 1.0f;
     Node* nodes = nullptr;
     float* gacc = nullptr;        // [views,V,6] vertex gradient slots of each view (edge term)
     float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
@@ -864,12 +867,25 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     g.p1_blocks = (s->V + 255) / 256;
     g.iter_advance = iter_advance;
     g.hand_counter = s->hand_counter;
+    g.prior_target = s->prior_target; g.prior_lambda = s->prior_lambda; g.prior_gamma = s->prior_gamma;
     // per hand one more block sums the loss value
     const long long n4 = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3 / 4;
     const int n_adam = adam ? (int)std::min<long long>(1024, std::max<long long>(1, (n4 + 255) / 256)) : 0;
     rc = launch(s, "k_geom_p1", k_geom_p1, dim3(s->n_hands * (g.p1_blocks + 1) + n_adam), dim3(256), 0, st, g);
     if (!rc) rc = launch(s, "k_geom_p2", k_geom_p2, dim3(s->geom_blocks, s->n_hands), dim3(64), 0, st, g);
     return rc;
+}
+
+int hr_set_joint_prior(hr_scene* s, const float* target_joints, float lambda, float gamma)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_joint_prior: null scene");
+    if (!(lambda >= 0.0f) || !std::isfinite(lambda) || !(gamma > 0.0f) || !std::isfinite(gamma))
+        return fail(HR_EINVAL, "hr_set_joint_prior: need lambda >= 0 and gamma > 0 (finite)");
+    const bool on = target_joints != nullptr && lambda > 0.0f;
+    s->prior_target = on ? target_joints : nullptr;
+    s->prior_lambda = on ? lambda : 0.0f;
+    s->prior_gamma = gamma;
+    return HR_OK;
 }
 
 int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,

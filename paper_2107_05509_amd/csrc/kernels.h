@@ -228,6 +228,9 @@ struct GeomBwdArgs {
     int p1_blocks;             // vertex blocks per hand of the first launch
     int* iter_advance;         // nullable: iteration counter, incremented once every hand has finished
     int* hand_counter;         // [1] finished hands (zero between launches)
+    const float* prior_target; // nullable: [H,J,3] target joints of the joint prior
+    float prior_lambda;        // its weight
+    float prior_gamma;         // its smooth-L1 threshold (model units)
 };
 
 }  // namespace hr

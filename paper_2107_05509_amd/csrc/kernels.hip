@@ -1572,7 +1572,7 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
 // wave does the work (the levels synchronise the wave only); the caller's
 // next block barrier orders its results for the other waves.
 __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, const float* tot,
-                                const JointState& js, float* __restrict__ gp)
+                                const JointState& js, float* __restrict__ gp, const float* xGt)
 {
     __shared__ float gJ[kMaxJoints * 3], gGt[kMaxJoints * 3], gGR[kMaxJoints * 9], gR[kMaxJoints * 9];
     __shared__ float cGR[kMaxJoints * 9], cJ[kMaxJoints * 3];   // each joint's terms for its parent
@@ -1598,7 +1598,7 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
     if (j < J) {
         const float* a = tot + 12 + 12 * j;
         for (int i = 0; i < 3; ++i) {
-            gGt[3 * j + i] = a[9 + i];
+            gGt[3 * j + i] = a[9 + i] + (xGt ? xGt[3 * j + i] : 0.0f);
             for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] = a[3 * i + k] - a[9 + i] * js.J[3 * j + k];
         }
         float y[3];
@@ -1675,6 +1675,50 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
     if (j == 63)
 #pragma unroll
         for (int k = 0; k < 10; ++k) gp[48 + k] = k < K ? tot[12 + 12 * J + k] + sj[k] : 0.0f;
+}
+
+// Joint prior (Section 3.3): lambda times the coordinate-wise smooth L1
+// distance, with threshold gamma, between the posed joints Rp Gt_j + tau and
+// the target joints (quadratic d^2 / (2 gamma) below gamma, |d| - gamma / 2
+// above).  One wave, lane j for joint j.  Its gradient g_j with respect to the
+// posed joint enters the global rotation and translation sums (tot[0..8] as
+// g_j Gt_j^T, tot[9..11] as g_j) and, as Rp^T g_j, dL/dGt_j (xGt, LDS);
+// lambda E2 is added to *loss when it is given.
+__device__ void joint_prior(const MeshDev& m, const JointState& js, const float* __restrict__ p,
+                            const float* __restrict__ target, float lambda, float gamma, float* tot,
+                            float* xGt, float* loss)
+{
+    const int j = threadIdx.x;
+    float g[3] = {0.0f, 0.0f, 0.0f}, x[3] = {0.0f, 0.0f, 0.0f}, e = 0.0f;
+    if (j < m.J) {
+        for (int i = 0; i < 3; ++i) x[i] = js.Gt[3 * j + i];
+        float y[3];
+        matvec3(js.Rp, x, y);
+        for (int i = 0; i < 3; ++i) {
+            const float d = (y[i] + p[61 + i]) - target[3 * j + i];
+            const float ad = fabsf(d);
+            if (ad < gamma) {
+                e += 0.5f * d * d / gamma;
+                g[i] = lambda * d / gamma;
+            } else {
+                e += ad - 0.5f * gamma;
+                g[i] = d > 0.0f ? lambda : -lambda;
+            }
+        }
+        matTvec3(js.Rp, g, xGt + 3 * j);
+    }
+    float sv[13];
+    for (int i = 0; i < 3; ++i) {
+        for (int k = 0; k < 3; ++k) sv[3 * i + k] = g[i] * x[k];
+        sv[9 + i] = g[i];
+    }
+    sv[12] = lambda * e;
+    wave_sum63_n<13>(sv);
+    if (j == 63) {
+        for (int k = 0; k < 12; ++k) tot[k] += sv[k];
+        if (loss) *loss += sv[12];
+    }
+    wave_lds_sync();
 }
 
 // One Adam update (bias corrections bc1, bc2), the arithmetic of every
@@ -1984,7 +2028,11 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
     }
     __syncthreads();
     float* gp = a.grad_params + 64 * h;
-    skin_bwd_finish(m, p, acc, js, gp);
+    __shared__ float xGt[kMaxJoints * 3];
+    if (a.prior_target)
+        joint_prior(m, js, p, a.prior_target + (size_t)h * J * 3, a.prior_lambda, a.prior_gamma, acc, xGt,
+                    a.with_loss && a.loss.loss ? a.loss.loss + h : nullptr);
+    skin_bwd_finish(m, p, acc, js, gp, a.prior_target ? xGt : nullptr);
     if (!a.adam_params) return;
     __syncthreads();   // the finish has read the parameters and written gp
     const float lr = param_lr(a.adam, t);
