@@ -181,10 +181,12 @@ int hr_backward(hr_scene* scene, const float* params, const float* verts, const 
    distance f2(d) = d^2 / (2 gamma) for |d| < gamma, |d| - gamma / 2
    otherwise, between the posed joints (those hr_skin returns) and
    target_joints (DEVICE [n_hands,J,3] float32, caller-owned, read by every
-   later backward until the next call: it must stay valid that long).
+   later backward until the next call, and by every launch of a graph
+   captured meanwhile: it must stay valid that long).
    gamma is in the model's units (the paper's 5 mm is 0.005 for a model in
    metres).  From the next enqueued call on, hr_backward, hr_iterate and
-   graphs created afterwards add lambda dE2/dparams to grad_params, and the
+   graphs created afterwards (a graph keeps the setting it was captured
+   with) add lambda dE2/dparams to grad_params, and the
    loss that hr_iterate writes becomes E1 + lambda E2 per hand (hr_loss stays
    E1).  target_joints NULL or lambda 0 switches the prior off.
    HR_EINVAL: null scene, lambda < 0, gamma <= 0 or either not finite. */

@@ -254,11 +254,13 @@ class Scene:
 
     def set_joint_prior(self, target_joints=None, lam=0.0, gamma=0.005):
         """Joint prior lambda E2 (Section 3.3) for the backwards enqueued from now
-        on: target_joints a CUDA float32 tensor [n_hands,J,3] (the scene keeps a
-        reference: the library reads it at every backward), None to switch off."""
+        on: target_joints a CUDA float32 tensor [n_hands,J,3], None to switch off.
+        The scene keeps a reference to every target it was given: backwards and
+        graphs captured while it was set read it."""
         ptr = _ptr(target_joints, shape=(self.n_hands, self.J, 3), name="target_joints")
         _check(lib().hr_set_joint_prior(self._h, ptr, float(lam), float(gamma)), "hr_set_joint_prior")
-        self._prior_target = target_joints
+        if target_joints is not None:
+            self._keep.append(target_joints)
 
     def step(self, params, albedo, grad_params, grad_albedo, m_p, v_p, m_a, v_a, t, lrs, betas=(0.9, 0.999),
              eps=1e-8):

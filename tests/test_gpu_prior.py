@@ -99,3 +99,40 @@ def test_prior_argument_errors(case):
             c.gsc.set_joint_prior(c.t(c.jtarget), lam, gamma)
     with pytest.raises(binding.HRError):
         c.gsc.set_joint_prior(c.t(c.jtarget[:, :4]), 1.0, 0.005)   # wrong shape
+
+
+def test_prior_in_graphs():
+    # a graph captured after hr_set_joint_prior carries the prior: one
+    # iteration replayed from a saved state equals hr_iterate with the prior,
+    # and differs from the prior-free iteration
+    from test_gpu_loop import Loop, _restore, _save, _snap
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("case: tiny workload, joint prior in graphs", flush=True)
+    lp = Loop(scene.workload_tiny(0))
+    g = lp.g
+    v = torch.empty(1, lp.w.model.n_verts, 3, device=DEV)
+    j = torch.empty(1, g.J, 3, device=DEV)
+    g.skin(torch.as_tensor(f32(lp.w.params_init)).to(DEV), v, j)
+    target = (j + 0.01).contiguous()
+    g.set_joint_prior(target, LAM, GAMMA)
+    try:
+        r = lp.refiner(warm=0)
+        r.run(2, graph=False)
+        saved = _save(r)
+        outs = []
+        for graph in (True, False):
+            _restore(r, saved)
+            r.run(1, graph=graph)
+            outs.append(_snap(r))
+    finally:
+        g.set_joint_prior(None)
+    _restore(r, saved)
+    r.run(1, graph=False)
+    off = _snap(r)
+    for key in ("params", "loss", "grad_params"):
+        e = block_rel(outs[0][key], outs[1][key])
+        print(key, e, flush=True)
+        assert e <= 1e-5, key
+    assert block_rel(off["grad_params"], outs[1]["grad_params"]) > 1e-2
+    assert outs[1]["loss"][0] > off["loss"][0]
