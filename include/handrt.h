@@ -176,6 +176,21 @@ int hr_backward(hr_scene* scene, const float* params, const float* verts, const 
                 float* grad_params, float* grad_albedo, float* grad_verts, float* grad_normals,
                 void* stream);
 
+/* Camera coverage (Section 5, camera coverage; Eq. 6).  hr_face_visibility:
+   visible [n_views,F] int32 out (DEVICE): 1 where some camera sample of the
+   view hit the face, from hit_face [pixels,spp] as hr_render writes it (the
+   coverage of a view is the set of triangles its samples see), else 0.
+   hr_camera_order: per hand, its views in greedy order, each next view the
+   one adding the most faces not seen by those before it (ties: the earlier
+   view of the hand in the camera list), so the coverage of the first i views
+   never decreases with i.  order [n_views] int32 out (DEVICE): view indices
+   in hand segments (hand 0's views first, then hand 1's, ...; position k of
+   a segment is step k); covered [n_views] int32 out (DEVICE), same layout:
+   faces seen by the hand's first k + 1 views.  HR_EINVAL: null argument; HR_EUNSUPPORTED:
+   more than 131072 faces or 256 views of one hand. */
+int hr_face_visibility(hr_scene* scene, const int32_t* hit_face, int32_t* visible, void* stream);
+int hr_camera_order(hr_scene* scene, const int32_t* visible, int32_t* order, int32_t* covered, void* stream);
+
 /* Joint prior of the objective E = E1 + lambda E2 (Section 3.3): E2 sums,
    over the hands' joints and their three coordinates, the smooth L1
    distance f2(d) = d^2 / (2 gamma) for |d| < gamma, |d| - gamma / 2

@@ -123,6 +123,40 @@ def render(sc: Scene, verts, normals, albedo, background, spp, seed, it, want_hi
     return (img, hits) if want_hits else img
 
 
+def face_visibility(hits, pix_off, F):
+    """visible [N,F] bool: view i sees face f when one of its camera samples hit
+    f (Section 5, camera coverage: the surface a view makes visible, counted in
+    triangles).  hits [P,spp] per-sample face ids (-1 miss), views packed by
+    pix_off [N+1]."""
+    N = len(pix_off) - 1
+    vis = np.zeros((N, F), dtype=bool)
+    for i in range(N):
+        h = np.asarray(hits[pix_off[i]:pix_off[i + 1]]).ravel()
+        vis[i, h[h >= 0]] = True
+    return vis
+
+
+def camera_order(visible, hand_views):
+    """Greedy order of each hand's views (Section 5, camera coverage, Eq. 6):
+    each step takes the view that adds the most faces not seen by the views
+    taken before (ties: the earlier view of the hand's list).  Returns (order,
+    covered), concatenated over the hands: view indices, and the faces seen by
+    the first k + 1 views."""
+    order, covered = [], []
+    for views in hand_views:
+        seen = np.zeros(visible.shape[1], dtype=bool)
+        left, total = list(views), 0
+        while left:
+            gains = [int((visible[v] & ~seen).sum()) for v in left]
+            k = int(np.argmax(gains))   # the first maximum: the earliest view
+            v = left.pop(k)
+            seen |= visible[v]
+            total += gains[k]
+            order.append(v)
+            covered.append(total)
+    return np.array(order, dtype=np.int64), np.array(covered, dtype=np.int64)
+
+
 def backward_interior(sc: Scene, verts, normals, albedo, dimage, spp, seed, it):
     """(g_albedo, g_verts, g_normals) of sum(dimage * I) at fixed samples."""
     verts = _c(verts, np.float64).reshape(-1, sc.V, 3)

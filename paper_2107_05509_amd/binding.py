@@ -22,7 +22,7 @@ HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
-           "hr_loss", "hr_backward", "hr_set_joint_prior", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
+           "hr_loss", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
            "hr_graph_destroy", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
@@ -99,6 +99,8 @@ def lib():
         L.hr_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
         L.hr_set_joint_prior.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float]
+        L.hr_face_visibility.argtypes = [vp, vp, vp, vp]
+        L.hr_camera_order.argtypes = [vp, vp, vp, vp, vp]
         L.hr_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, ctypes.POINTER(AdamConfig), vp]
         L.hr_iterate.argtypes = [vp, ctypes.POINTER(State), ctypes.POINTER(AdamConfig), u32, vp]
         L.hr_graph_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(State), ctypes.POINTER(AdamConfig), u32,
@@ -125,6 +127,7 @@ def lib():
         L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.hr_last_error.restype = ctypes.c_char_p
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_set_joint_prior",
+                     "hr_face_visibility", "hr_camera_order",
                      "hr_step", "hr_iterate",
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats",
                      "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
@@ -251,6 +254,19 @@ class Scene:
             _ptr(grad_albedo, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="grad_albedo"),
             _ptr(grad_verts, shape=(self.n_hands, self.V, 3), name="grad_verts"),
             _ptr(grad_normals, shape=(self.n_hands, self.V, 3), name="grad_normals"), _stream()), "hr_backward")
+
+    def face_visibility(self, hit_face, visible):
+        """visible [n_views,F] int32 <- faces hit by each view's samples (hit_face [P,spp])."""
+        _check(lib().hr_face_visibility(self._h, _ptr(hit_face, torch.int32, (self.P, self.spp), "hit_face"),
+                                        _ptr(visible, torch.int32, (self.n_views, self.F), "visible"), _stream()),
+               "hr_face_visibility")
+
+    def camera_order(self, visible, order, covered):
+        """Greedy coverage order of each hand's views (order, covered: [n_views] int32)."""
+        _check(lib().hr_camera_order(self._h, _ptr(visible, torch.int32, (self.n_views, self.F), "visible"),
+                                     _ptr(order, torch.int32, (self.n_views,), "order"),
+                                     _ptr(covered, torch.int32, (self.n_views,), "covered"), _stream()),
+               "hr_camera_order")
 
     def set_joint_prior(self, target_joints=None, lam=0.0, gamma=0.005):
         """Joint prior lambda E2 (Section 3.3) for the backwards enqueued from now

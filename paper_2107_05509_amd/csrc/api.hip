@@ -82,6 +82,7 @@ struct hr_scene {
     int* view_chunk_off = nullptr;
     int* hand_view_off = nullptr;
     int* hand_views = nullptr;
+    int max_views_per_hand = 0;
     float* normals = nullptr;
     Tri* tris = nullptr;
     // joint prior (hr_set_joint_prior): caller-owned target joints, weight, threshold
@@ -439,6 +440,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             for (int v = 0; v < n_views; ++v)
                 if (cams[v].hand == h) hv.push_back(v);
             hvo[h + 1] = (int)hv.size();
+            s->max_views_per_hand = std::max(s->max_views_per_hand, hvo[h + 1] - hvo[h]);
         }
         TRY(s->upload(&s->views, s->views_host.data(), s->views_host.size()));
         TRY(s->upload(&s->chunks, chunks.data(), chunks.size()));
@@ -886,6 +888,28 @@ int hr_set_joint_prior(hr_scene* s, const float* target_joints, float lambda, fl
     s->prior_lambda = on ? lambda : 0.0f;
     s->prior_gamma = gamma;
     return HR_OK;
+}
+
+int hr_face_visibility(hr_scene* s, const int32_t* hit_face, int32_t* visible, void* stream)
+{
+    if (!s || !hit_face || !visible) return fail(HR_EINVAL, "hr_face_visibility: null argument");
+    const hipStream_t st = (hipStream_t)stream;
+    const long long n = (long long)s->n_views * s->F;
+    int rc = launch(s, "k_fill_i32", k_fill_i32, dim3((unsigned)std::min<long long>(1024, (n + 255) / 256)), dim3(256),
+                    0, st, (int*)visible, n, 0);
+    if (rc) return rc;
+    return launch(s, "k_face_visibility", k_face_visibility, dim3(64, s->n_views), dim3(256), 0, st, s->views,
+                  (const int*)hit_face, s->cfg.spp, s->F, (int*)visible);
+}
+
+int hr_camera_order(hr_scene* s, const int32_t* visible, int32_t* order, int32_t* covered, void* stream)
+{
+    if (!s || !visible || !order || !covered) return fail(HR_EINVAL, "hr_camera_order: null argument");
+    if (s->F > 32 * kCoverWords) return fail(HR_EUNSUPPORTED, "hr_camera_order: more than %d faces", 32 * kCoverWords);
+    if (s->max_views_per_hand > kCoverViews)
+        return fail(HR_EUNSUPPORTED, "hr_camera_order: more than %d views of one hand", kCoverViews);
+    return launch(s, "k_camera_order", k_camera_order, dim3(s->n_hands), dim3(256), 0, (hipStream_t)stream,
+                  (const int*)visible, s->hand_view_off, s->hand_views, s->F, (int*)order, (int*)covered);
 }
 
 int hr_backward(hr_scene* s, const float* params, const float* verts, const float* albedo, const float* background,

@@ -2077,6 +2077,82 @@ __global__ void k_set_i32(int* p, int n, int v)
     if ((int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
+// ===========================================================================
+// camera coverage: faces seen per view, greedy camera order
+// ===========================================================================
+
+constexpr int kCoverWords = 4096;   // faces up to 32 * kCoverWords
+constexpr int kCoverViews = 256;    // views per hand
+
+// visible[v, f] = 1 when a camera sample of view v hit face f (hit_face as the
+// render writes it, [pixels, spp]); grid (chunks, views); `visible` is zero
+// before the launch.
+__global__ void __launch_bounds__(256) k_face_visibility(const ViewDev* __restrict__ views,
+                                                         const int* __restrict__ hit_face, int spp, int F,
+                                                         int* __restrict__ visible)
+{
+    const ViewDev& c = views[blockIdx.y];
+    const long long n = (long long)c.W * c.H * spp;
+    const int* hf = hit_face + c.pix0 * spp;
+    int* out = visible + (size_t)blockIdx.y * F;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int f = hf[i];
+        if (f >= 0 && f < F) out[f] = 1;
+    }
+}
+
+// Greedy order of each hand's views by coverage (one block per hand): step k
+// takes the view that adds the most faces not seen by the views taken
+// before (ties: the earlier view in the hand's list); order[off + k] is its
+// view index, covered[off + k] the faces seen by the first k + 1 views.
+__global__ void __launch_bounds__(256) k_camera_order(const int* __restrict__ visible,
+                                                      const int* __restrict__ hand_view_off,
+                                                      const int* __restrict__ hand_views, int F,
+                                                      int* __restrict__ order, int* __restrict__ covered)
+{
+    __shared__ unsigned int seen[kCoverWords];
+    __shared__ int gain[kCoverViews];
+    __shared__ int taken[kCoverViews];
+    __shared__ int best;
+    const int h = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    const int off = hand_view_off[h], nv = hand_view_off[h + 1] - off;
+    const int nwords = (F + 31) >> 5;
+    for (int i = t; i < nwords; i += blockDim.x) seen[i] = 0u;
+    for (int i = t; i < nv; i += blockDim.x) taken[i] = 0;
+    __syncthreads();
+    int total = 0;
+    for (int k = 0; k < nv; ++k) {
+        // new faces of every view not yet taken, one wave per view
+        for (int c = w; c < nv; c += nw) {
+            int cnt = 0;
+            if (!taken[c]) {
+                const int* vis = visible + (size_t)hand_views[off + c] * F;
+                for (int f = lane; f < F; f += 64)
+                    cnt += (vis[f] != 0 && !((seen[f >> 5] >> (f & 31)) & 1u)) ? 1 : 0;
+            }
+            for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+            if (lane == 0) gain[c] = taken[c] ? -1 : cnt;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int b = -1;
+            for (int c = 0; c < nv; ++c)
+                if (gain[c] >= 0 && (b < 0 || gain[c] > gain[b])) b = c;
+            best = b;
+            taken[b] = 1;
+            total += gain[b];
+            order[off + k] = hand_views[off + b];
+            covered[off + k] = total;
+        }
+        __syncthreads();
+        const int* vis = visible + (size_t)hand_views[off + best] * F;
+        for (int f = t; f < F; f += blockDim.x)
+            if (vis[f] != 0) atomicOr(seen + (f >> 5), 1u << (f & 31));
+        __syncthreads();
+    }
+}
+
 __global__ void k_fill_i32(int* __restrict__ p, long long n, int v)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
