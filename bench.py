@@ -240,6 +240,57 @@ def bench_proposal(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_coverage(args):
+    """Camera-coverage ordering (Eq. 6) on 40 views 334x512 at 16 spp: faces seen
+    per view from the render's hit ids, then each hand's greedy view order."""
+    w = scene.workload_realistic(args.seed, n_views=40)
+    print(f"[bench] workload: coverage, {len(w.cams)} views, {w.n_pixels} pixels", file=sys.stderr, flush=True)
+    dev = "cuda:0"
+    th, tw = w.albedo_true.shape[1:3]
+    g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=args.seed)
+    t = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)
+    verts = torch.empty(w.n_hands, w.model.n_verts, 3, device=dev)
+    g.skin(t(w.params_init), verts)
+    img = torch.empty(g.P, 3, device=dev)
+    hits = torch.empty(g.P, w.spp, dtype=torch.int32, device=dev)
+    g.render(verts, t(w.albedo_true), t(w.packed_background()), 0, img, hits)
+    vis = torch.empty(len(w.cams), g.F, dtype=torch.int32, device=dev)
+    order = torch.empty(len(w.cams), dtype=torch.int32, device=dev)
+    covered = torch.empty_like(order)
+
+    def once():
+        g.face_visibility(hits, vis)
+        g.camera_order(vis, order, covered)
+
+    for _ in range(3):
+        once()
+    reps = max(1, min(args.steps, 50))
+    g.timing_enable(True)
+    g.timing_read()
+    ms = timed(lambda: [once() for _ in range(reps)]) / reps
+    k = g.timing_read()
+    g.timing_enable(False)
+    per = {n: round(v / max(c, 1) * 1e3, 2) for n, (v, c) in k.items()}
+    samples = g.P * w.spp
+    vis_us = per.get("k_face_visibility", float("nan"))
+    achieved = samples * 4 / (vis_us * 1e-6) / 1e9
+    cov = covered.cpu().numpy()
+    out = {
+        "metric": "camera-coverage ordering time (40 views 334x512, 16 spp)",
+        "value": round(ms, 4), "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 3, "ms_per_step": round(ms, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": "coverage: 1 hand, 40 views 334x512, 16 spp hit ids (109.4 M samples)",
+                   "views": len(w.cams), "samples": int(samples)},
+        "kernels": per, "kernels_unit": "us per launch",
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4), "traffic": None, "kernel": "k_face_visibility",
+                     "bytes_per_launch": int(samples * 4)},
+        "order": order.cpu().numpy().tolist(), "covered": cov.tolist(),
+        "faces_seen_by_7": int(cov[6]), "faces_seen_by_all": int(cov[-1]),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,7 +304,7 @@ def main():
                     help="R,A: persistent render/adjoint grid sizes to use instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=int, default=2)
-    ap.add_argument("--workload", choices=("realistic", "batched", "proposal"), default="realistic",
+    ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage"), default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
     args = ap.parse_args()
@@ -269,6 +320,8 @@ def main():
         return bench_batched(args)
     if args.workload == "proposal":
         return bench_proposal(args)
+    if args.workload == "coverage":
+        return bench_coverage(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))

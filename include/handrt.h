@@ -186,8 +186,10 @@ int hr_backward(hr_scene* scene, const float* params, const float* verts, const 
    never decreases with i.  order [n_views] int32 out (DEVICE): view indices
    in hand segments (hand 0's views first, then hand 1's, ...; position k of
    a segment is step k); covered [n_views] int32 out (DEVICE), same layout:
-   faces seen by the hand's first k + 1 views.  HR_EINVAL: null argument; HR_EUNSUPPORTED:
-   more than 131072 faces or 256 views of one hand. */
+   faces seen by the hand's first k + 1 views.  HR_EINVAL: null argument;
+   HR_EUNSUPPORTED: a face bitmap (ceil(F / 32) words) or, for the order, the
+   bitmaps of one hand's views (views x ceil(F / 32) words + 2 per view)
+   beyond 64 KiB. */
 int hr_face_visibility(hr_scene* scene, const int32_t* hit_face, int32_t* visible, void* stream);
 int hr_camera_order(hr_scene* scene, const int32_t* visible, int32_t* order, int32_t* covered, void* stream);
 

@@ -898,17 +898,21 @@ int hr_face_visibility(hr_scene* s, const int32_t* hit_face, int32_t* visible, v
     int rc = launch(s, "k_fill_i32", k_fill_i32, dim3((unsigned)std::min<long long>(1024, (n + 255) / 256)), dim3(256),
                     0, st, (int*)visible, n, 0);
     if (rc) return rc;
-    return launch(s, "k_face_visibility", k_face_visibility, dim3(64, s->n_views), dim3(256), 0, st, s->views,
+    const size_t smem = sizeof(unsigned int) * (size_t)((s->F + 31) / 32);
+    if (smem > (size_t)kCoverLdsBytes) return fail(HR_EUNSUPPORTED, "hr_face_visibility: too many faces");
+    return launch(s, "k_face_visibility", k_face_visibility, dim3(64, s->n_views), dim3(256), smem, st, s->views,
                   (const int*)hit_face, s->cfg.spp, s->F, (int*)visible);
 }
 
 int hr_camera_order(hr_scene* s, const int32_t* visible, int32_t* order, int32_t* covered, void* stream)
 {
     if (!s || !visible || !order || !covered) return fail(HR_EINVAL, "hr_camera_order: null argument");
-    if (s->F > 32 * kCoverWords) return fail(HR_EUNSUPPORTED, "hr_camera_order: more than %d faces", 32 * kCoverWords);
-    if (s->max_views_per_hand > kCoverViews)
-        return fail(HR_EUNSUPPORTED, "hr_camera_order: more than %d views of one hand", kCoverViews);
-    return launch(s, "k_camera_order", k_camera_order, dim3(s->n_hands), dim3(256), 0, (hipStream_t)stream,
+    const size_t nwords = (size_t)(s->F + 31) / 32, nv = (size_t)s->max_views_per_hand;
+    const size_t smem = sizeof(unsigned int) * (nv * nwords + nwords + 2 * nv);
+    if (smem > (size_t)kCoverLdsBytes)
+        return fail(HR_EUNSUPPORTED, "hr_camera_order: the views' face bitmaps (%zu B) exceed %d B of LDS", smem,
+                    kCoverLdsBytes);
+    return launch(s, "k_camera_order", k_camera_order, dim3(s->n_hands), dim3(256), smem, (hipStream_t)stream,
                   (const int*)visible, s->hand_view_off, s->hand_views, s->F, (int*)order, (int*)covered);
 }
 

@@ -2081,58 +2081,82 @@ __global__ void k_set_i32(int* p, int n, int v)
 // camera coverage: faces seen per view, greedy camera order
 // ===========================================================================
 
-constexpr int kCoverWords = 4096;   // faces up to 32 * kCoverWords
-constexpr int kCoverViews = 256;    // views per hand
+constexpr int kCoverLdsBytes = 65536;   // bitmaps of the order kernel
 
 // visible[v, f] = 1 when a camera sample of view v hit face f (hit_face as the
-// render writes it, [pixels, spp]); grid (chunks, views); `visible` is zero
-// before the launch.
+// render writes it, [pixels, spp]); grid (chunks, views), dynamic LDS: a bitmap
+// of the faces (the block's hits are gathered there, then written once);
+// `visible` is zero before the launch.
 __global__ void __launch_bounds__(256) k_face_visibility(const ViewDev* __restrict__ views,
                                                          const int* __restrict__ hit_face, int spp, int F,
                                                          int* __restrict__ visible)
 {
+    extern __shared__ unsigned int bits[];
+    const int nwords = (F + 31) >> 5;
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) bits[i] = 0u;
+    __syncthreads();
     const ViewDev& c = views[blockIdx.y];
-    const long long n = (long long)c.W * c.H * spp;
-    const int* hf = hit_face + c.pix0 * spp;
-    int* out = visible + (size_t)blockIdx.y * F;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const int f = hf[i];
-        if (f >= 0 && f < F) out[f] = 1;
+    const long long n = (long long)c.W * c.H * spp, first = c.pix0 * spp;
+    const int* hf = hit_face + first;
+    auto mark = [&](int f) {
+        if (f >= 0 && f < F && !((bits[f >> 5] >> (f & 31)) & 1u)) atomicOr(bits + (f >> 5), 1u << (f & 31));
+    };
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    long long done = 0;
+    if ((reinterpret_cast<uintptr_t>(hf) & 15) == 0) {
+        // four ids per load
+        const int4* h4 = reinterpret_cast<const int4*>(hf);
+        const long long n4 = n >> 2;
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+            const int4 q = h4[i];
+            mark(q.x); mark(q.y); mark(q.z); mark(q.w);
+        }
+        done = n4 << 2;
     }
+    for (long long i = done + (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) mark(hf[i]);
+    __syncthreads();
+    int* out = visible + (size_t)blockIdx.y * F;
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x)
+        for (unsigned int b = bits[i]; b; b &= b - 1u) out[32 * i + __builtin_ctz(b)] = 1;
 }
 
-// Greedy order of each hand's views by coverage (one block per hand): step k
-// takes the view that adds the most faces not seen by the views taken
-// before (ties: the earlier view in the hand's list); order[off + k] is its
-// view index, covered[off + k] the faces seen by the first k + 1 views.
+// Greedy order of each hand's views by coverage (one block per hand, a thread
+// per view): step k takes the view that adds the most faces not seen by the
+// views taken before (ties: the earlier view in the hand's list);
+// order[off + k] is its view index, covered[off + k] the faces seen by the
+// first k + 1 views.  Dynamic LDS: the views' face bitmaps, the seen bitmap,
+// gains, taken flags.
 __global__ void __launch_bounds__(256) k_camera_order(const int* __restrict__ visible,
                                                       const int* __restrict__ hand_view_off,
                                                       const int* __restrict__ hand_views, int F,
                                                       int* __restrict__ order, int* __restrict__ covered)
 {
-    __shared__ unsigned int seen[kCoverWords];
-    __shared__ int gain[kCoverViews];
-    __shared__ int taken[kCoverViews];
+    extern __shared__ unsigned int cs[];
     __shared__ int best;
-    const int h = blockIdx.x, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+    const int h = blockIdx.x, t = threadIdx.x;
     const int off = hand_view_off[h], nv = hand_view_off[h + 1] - off;
     const int nwords = (F + 31) >> 5;
+    unsigned int* vb = cs;                                    // [nv * nwords]
+    unsigned int* seen = vb + (size_t)nv * nwords;            // [nwords]
+    int* gain = reinterpret_cast<int*>(seen + nwords);        // [nv]
+    int* taken = gain + nv;                                   // [nv]
+    for (int i = t; i < nv * nwords; i += blockDim.x) {
+        const int c = i / nwords, wd = i - c * nwords;
+        const int* v = visible + (size_t)hand_views[off + c] * F + 32 * wd;
+        const int nb = min(32, F - 32 * wd);
+        unsigned int m = 0u;
+        for (int b = 0; b < nb; ++b) m |= (v[b] != 0 ? 1u : 0u) << b;
+        vb[i] = m;
+    }
     for (int i = t; i < nwords; i += blockDim.x) seen[i] = 0u;
     for (int i = t; i < nv; i += blockDim.x) taken[i] = 0;
     __syncthreads();
     int total = 0;
     for (int k = 0; k < nv; ++k) {
-        // new faces of every view not yet taken, one wave per view
-        for (int c = w; c < nv; c += nw) {
+        for (int c = t; c < nv; c += blockDim.x) {
             int cnt = 0;
-            if (!taken[c]) {
-                const int* vis = visible + (size_t)hand_views[off + c] * F;
-                for (int f = lane; f < F; f += 64)
-                    cnt += (vis[f] != 0 && !((seen[f >> 5] >> (f & 31)) & 1u)) ? 1 : 0;
-            }
-            for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
-            if (lane == 0) gain[c] = taken[c] ? -1 : cnt;
+            for (int wd = 0; wd < nwords; ++wd) cnt += __popc(vb[(size_t)c * nwords + wd] & ~seen[wd]);
+            gain[c] = taken[c] ? -1 : cnt;
         }
         __syncthreads();
         if (t == 0) {
@@ -2146,9 +2170,7 @@ __global__ void __launch_bounds__(256) k_camera_order(const int* __restrict__ vi
             covered[off + k] = total;
         }
         __syncthreads();
-        const int* vis = visible + (size_t)hand_views[off + best] * F;
-        for (int f = t; f < F; f += blockDim.x)
-            if (vis[f] != 0) atomicOr(seen + (f >> 5), 1u << (f & 31));
+        for (int wd = t; wd < nwords; wd += blockDim.x) seen[wd] |= vb[(size_t)best * nwords + wd];
         __syncthreads();
     }
 }
