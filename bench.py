@@ -303,6 +303,8 @@ def main():
     ap.add_argument("--grids", default=None,
                     help="R,A: persistent render/adjoint grid sizes to use instead of tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--joint-prior", action="store_true",
+                    help="add the joint prior (lambda 1, gamma 5 mm) against the true joints plus 5 mm noise")
     ap.add_argument("--cpu-views", type=int, default=2)
     ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage"), default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
@@ -326,6 +328,14 @@ def main():
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))
     g = ref.scene
+    if args.joint_prior:
+        # target joints: the true pose's joints with seeded 5 mm noise (an initial joint estimate)
+        jt = torch.empty(w.n_hands, g.J, 3, device="cuda:0")
+        g.skin(torch.as_tensor(w.params_true, dtype=torch.float32).to("cuda:0").contiguous(),
+               torch.empty(w.n_hands, g.V, 3, device="cuda:0"), jt)
+        gen = torch.Generator().manual_seed(args.seed + 17)
+        jt += (0.005 * torch.randn(jt.shape, generator=gen)).to(jt.device)
+        g.set_joint_prior(jt.contiguous(), 1.0, 0.005)
     if args.grids:
         g.set_grid(*[int(x) for x in args.grids.split(",")])
     print(f"[bench] launch grids (render, adjoint): {g.grids()}", file=sys.stderr, flush=True)
@@ -407,7 +417,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "realistic: 1 hand (778 verts, 1538 tris), 8 views 334x512, 16 spp, "
-                               "512x512 albedo, L1 over hand masks, Adam on 64 params + albedo",
+                               "512x512 albedo, L1 over hand masks, Adam on 64 params + albedo"
+                               + (", joint prior (lambda 1, gamma 5 mm)" if args.joint_prior else ""),
                    "views": len(w.cams), "W": 334, "H": 512, "spp": w.spp, "tex": 512,
                    "camera_samples_per_step": cam_samples},
         "mode": args.mode,
