@@ -13,7 +13,7 @@ sampling, normals + skinning backward) -> Adam.  Inputs are resident in HBM
 before the timed region.  Steps 0..49 optimise the colour map only (warm-up
 phase of the paper's schedule); the timed steps follow with all variables.
 
-Prints one JSON line (see the design doc for the metric and roofline definitions).
+Prints one JSON line: the metric, per-kernel times, the roofline of the render launch and the CPU baseline.
 """
 import argparse
 import hashlib
@@ -35,7 +35,7 @@ CAL_FLOATS = 1 << 27   # calibration copy: 512 MiB in, 512 MiB out
 PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 128 lanes x 2 x 2.4 GHz)
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic operations per unit of traversal work (FP32-equivalent)
+# Algorithmic operations per unit of traversal work (FP32-equivalent: per ray, node visit, triangle test, hit)
 OPS_PER_RAY = 90       # ray generation (Philox share + camera transform) and set-up
 OPS_PER_NODE = 50      # two slab tests and the near/far order
 OPS_PER_TRI = 47       # watertight ray/triangle test
@@ -312,7 +312,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how the workload would shard)", file=sys.stderr)
+              "(the workload would shard by hand or by view, one all-reduce of the gradients per iteration)", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
