@@ -10,8 +10,10 @@ hand masks, Adam on the 64 hand parameters and the colour map.
 A step is one full iteration: skin -> render (vertex normals, BVH refit, screen
 bounds, ray tracing) -> L1 loss -> backward (interior adjoint, silhouette edge
 sampling, normals + skinning backward) -> Adam.  Inputs are resident in HBM
-before the timed region.  Steps 0..49 optimise the colour map only (warm-up
-phase of the paper's schedule); the timed steps follow with all variables.
+before the timed region.  Iterations 0..49 optimise the colour map only (the
+warm-up phase of the paper's schedule) and always run untimed, whatever
+--warmup asks for (more if it asks for more), so the timed steps are
+iterations of the all-variables phase.
 
 Prints one JSON line: the metric, per-kernel times, the roofline of the render launch and the CPU baseline.
 """
@@ -32,14 +34,24 @@ from paper_2107_05509_amd import binding, refine, scene  # noqa: E402
 
 METRIC = "fwd+bwd diff-render Mrays/s + refine iters/s (8 views 334x512, 16 spp)"
 CAL_FLOATS = 1 << 27   # calibration copy: 512 MiB in, 512 MiB out
-PEAK_FP32_TFLOPS = 157.3   # MI355X vector FP32 (256 CUs x 128 lanes x 2 x 2.4 GHz)
+# Published MI355X FP32 vector peak.  It counts packed FP32: 256 CUs x 64 lanes
+# (4 SIMDs of 16 lanes, a wave64 instruction every 4 cycles) x 2 FMAs per lane
+# and cycle (v_pk_fma_f32) x 2 FLOP x 2.4 GHz.  This library is compiled without
+# packed FP32, so its own ceiling is half of it (78.6 TFLOP/s of FMAs, or 39.3 T
+# lane operations/s of any other VALU instruction); the fraction is reported
+# against the published figure.
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
-# Algorithmic operations per unit of traversal work (FP32-equivalent: per ray, node visit, triangle test, hit)
-OPS_PER_RAY = 90       # ray generation (Philox share + camera transform) and set-up
-OPS_PER_NODE = 50      # two slab tests and the near/far order
-OPS_PER_TRI = 47       # watertight ray/triangle test
-OPS_PER_HIT = {"k_render": 150, "k_adjoint_interior": 300, "k_edge_sample": 150}
+# Algorithmic FLOP per unit of ray-tracing work, the per-unit figures of the
+# hot-path measurement plan: per ray (Philox share and ray set-up), per node
+# visit of the ray's own traversal (two child slab tests), per ray/triangle
+# test of the ray's own traversal (watertight test), per hit (shading; the
+# interior adjoint adds 100 for the hit-point derivative and the chain rule)
+OPS_PER_RAY = 20
+OPS_PER_NODE = 24
+OPS_PER_TRI = 40
+OPS_PER_HIT = {"k_render": 70, "k_adjoint_interior": 170, "k_edge_sample": 70}
 
 
 def kernel_source_hash():
@@ -87,9 +99,11 @@ def make_refiner(w, dev="cuda:0", seed=0, tune=True, cover_spp=64):
     return r
 
 
-def cpu_baseline(w, ref, views=1):
+def cpu_baseline(w, views=1):
     """The oracle (float64, brute force, OpenMP) on the first `views` views of the
-    same workload: forward render + loss + interior adjoint + edge term."""
+    same workload: forward render + loss + interior adjoint + edge term, and
+    the per-iteration time that extrapolates to all views (and to the 200
+    iterations of a refinement), labelled as an extrapolation."""
     import oracle
     oracle.build(force=False)
     cams = w.cams[:views]
@@ -114,10 +128,14 @@ def cpu_baseline(w, ref, views=1):
     oracle.backward_edges(osc, v, n, alb, bg, dimg, 1000, 60)
     dt = time.perf_counter() - t0
     samples = P * w.spp
+    s_iter = dt * len(w.cams) / views
     return {"value": samples / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{views} of {len(w.cams)} views ({cams[0].W}x{cams[0].H}), {w.spp} spp: forward render, "
                       f"loss, interior adjoint and edge term, float64 brute force; {dt:.1f} s",
-            "seconds": dt}
+            "seconds": dt,
+            "extrapolated_s_per_iteration": round(s_iter, 2),
+            "extrapolated_min_per_200_iterations": round(s_iter * 200 / 60, 1),
+            "extrapolation": f"linear in views: {views} measured -> {len(w.cams)}"}
 
 
 def timed(fn):
@@ -291,6 +309,28 @@ def bench_coverage(args):
     print(json.dumps(out), flush=True)
 
 
+def dense_iteration(args):
+    """fwd+bwd time of one iteration of the dense workload (one hand, 40 views
+    334x512, 4 spp, 1024x1024 colour map): graph-replayed iterations of the
+    all-variables phase, fixed launch grids (untuned, the benchmark's own)."""
+    w = scene.workload_dense(args.seed)
+    ref = make_refiner(w, seed=args.seed, tune=False, cover_spp=4)
+    g = ref.scene
+    g.set_grid(4096, 4096)
+    ref.run(ref.warm)
+    steps = 20
+    ref.prepare_graphs(steps)
+    ms = timed(lambda: ref.run(steps)) / steps
+    samples = sum(c.W * c.H for c in w.cams) * w.spp
+    out = {"workload": "dense: 1 hand, 40 views 334x512, 4 spp, 1024x1024 albedo", "steps": steps,
+           "ms_per_iteration": round(ms, 4), "refine_iters_per_s": round(1e3 / ms, 2),
+           "camera_samples_per_step": int(samples), "camera_msamples_per_s": round(samples / (ms * 1e-3) / 1e6, 1),
+           "launch_grids": list(g.grids())}
+    del ref, g
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -306,6 +346,8 @@ def main():
     ap.add_argument("--joint-prior", action="store_true",
                     help="add the joint prior (lambda 1, gamma 5 mm) against the true joints plus 5 mm noise")
     ap.add_argument("--cpu-views", type=int, default=2)
+    ap.add_argument("--no-dense", action="store_true",
+                    help="skip the dense-workload iteration time (40 views, 4 spp, 1024x1024 albedo)")
     ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage"), default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
@@ -340,9 +382,12 @@ def main():
         g.set_grid(*[int(x) for x in args.grids.split(",")])
     print(f"[bench] launch grids (render, adjoint): {g.grids()}", file=sys.stderr, flush=True)
     graph = args.mode == "graph"
-    ref.run(args.warmup, graph=graph)
+    # the colour-only phase (iterations 0..warm-1) always runs untimed
+    n_warm = max(args.warmup, ref.warm)
+    ref.run(n_warm, graph=graph)
     torch.cuda.synchronize()
-    print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
+    print(f"[bench] warmup done ({n_warm} iterations; timed: iterations {n_warm}..{n_warm + args.steps - 1}, "
+          f"all variables)", file=sys.stderr, flush=True)
     # a plain device copy of known size (CAL_FLOATS float32 in and out, far
     # beyond the L2 and last-level caches): profiler runs of this command
     # scale their HBM byte counters by what they read for it
@@ -378,6 +423,9 @@ def main():
     torch.cuda.synchronize()
 
     cam_samples = sum(c.W * c.H for c in w.cams) * w.spp
+    # rays that enter a hierarchy: camera rays of the render, both side rays of
+    # every edge sample, rays the adjoint traces again (none: it reads the
+    # render's stored hits)
     traced = sum(int(counts[k][0]) for k in counts)
     n_it = args.steps
     per_kernel = {k: {"ms_per_launch": v[0] / v[1], "launches": v[1], "ms_per_step": v[0] / n_it}
@@ -394,6 +442,9 @@ def main():
     nodes = sum(counts[p][1] for p in parts)
     tris = sum(counts[p][2] for p in parts)
     hits = sum(counts[p][3] for p in parts)
+    nodes_w = sum(counts[p][4] for p in parts)
+    tris_w = sum(counts[p][5] for p in parts)
+    # the adjoint's samples are counted by their hits (it traces no ray)
     ops = sum(counts[p][0] * OPS_PER_RAY + counts[p][1] * OPS_PER_NODE + counts[p][2] * OPS_PER_TRI
               + counts[p][3] * OPS_PER_HIT[p] for p in parts)
     ach = ops / (per_kernel[dom]["ms_per_launch"] * 1e-3) / 1e12
@@ -407,12 +458,19 @@ def main():
             "frac": round(ach / PEAK_FP32_TFLOPS, 4), "traffic": traffic, "kernel": dom,
             "kernel_us": round(per_kernel[dom]["ms_per_launch"] * 1e3, 2),
             "ops_per_launch": int(ops), "rays": int(rays), "node_visits": int(nodes), "tri_tests": int(tris),
-            "hits": int(hits)}
+            "hits": int(hits),
+            "flop_per_unit": {"ray": OPS_PER_RAY, "node": OPS_PER_NODE, "tri": OPS_PER_TRI,
+                              "hit": {p: OPS_PER_HIT[p] for p in parts}},
+            # lane utilisation of the wave-packet traversal: the rays' own
+            # node visits / triangle tests over those executed per active lane
+            "packet_node_visits": int(nodes_w), "packet_tri_tests": int(tris_w),
+            "lane_util_nodes": round(nodes / max(nodes_w, 1), 4),
+            "lane_util_tris": round(tris / max(tris_w, 1), 4)}
     out = {
         "metric": METRIC,
         "value": round(cam_samples / (ms * 1e-3) / 1e6, 2),
         "unit": "Mrays/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "n_gpus": 1, "steps": args.steps, "warmup": n_warm, "warmup_requested": args.warmup,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -428,14 +486,20 @@ def main():
         "edge_samples_per_step": int(bud.sum()),
         "eager_ms_per_step": None if eager_ms is None else round(eager_ms, 4),
         "kernels": {k: round(v["ms_per_launch"] * 1e3, 2) for k, v in per_kernel.items()},
-        "work_counts": {k: {"rays": int(v[0]), "node_visits": int(v[1]), "tri_tests": int(v[2]), "hits": int(v[3])}
+        "work_counts": {k: {"rays": int(v[0]), "node_visits": int(v[1]), "tri_tests": int(v[2]), "hits": int(v[3]),
+                            "packet_node_visits": int(v[4]), "packet_tri_tests": int(v[5])}
                         for k, v in counts.items()},
         "kernels_unit": "us per launch",
         "roofline": roof,
     }
+    if not args.no_dense:
+        print("[bench] dense workload (40 views, 4 spp) ...", file=sys.stderr, flush=True)
+        del ref, g
+        out["dense"] = dense_iteration(args)
+        print(f"[bench] dense: {out['dense']['ms_per_iteration']:.4f} ms/iteration", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, ref, args.cpu_views)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_views)
     print(json.dumps(out), flush=True)
 
 

@@ -353,10 +353,15 @@ int hr_edge_stats(hr_scene* scene, uint64_t* total_host, int64_t* budget_host, v
 
 /* Work counting (profiling aid).  While enabled, hr_render and hr_backward
    launch variants of their ray-tracing kernels that count their work.
-   hr_read_counts synchronises `stream`, copies 12 uint64 to counts_host
+   hr_read_counts synchronises `stream`, copies 18 uint64 to counts_host
    (HOST) and resets them: for the render, interior-adjoint and edge-sampling
-   kernels in turn, (rays traced, BVH nodes visited, ray/triangle tests, rays
-   that hit). */
+   kernels in turn, six counts:
+     rays traced; node visits of the rays' own traversals (nodes whose box the
+     ray enters); ray/triangle tests of the rays' own traversals (triangles of
+     leaves whose box the ray enters); rays that hit; node visits and
+     triangle tests executed by the wave packets, counted once per active
+     lane (the union of the wave's traversals: the own counts over these are
+     the lane utilisation of the traversal). */
 int hr_set_counting(hr_scene* scene, int32_t enable);
 int hr_read_counts(hr_scene* scene, uint64_t* counts_host, void* stream);
 

@@ -393,10 +393,12 @@ class Scene:
         _check(lib().hr_set_counting(self._h, int(bool(enable))), "hr_set_counting")
 
     def read_counts(self):
-        """{kernel: (rays, nodes, triangle tests, hits)} since the last read."""
-        c = np.zeros(12, dtype=np.uint64)
+        """{kernel: (rays, nodes, triangle tests, hits, packet node visits,
+        packet triangle tests)} since the last read (per-ray counts, then the
+        wave packets' counts per active lane)."""
+        c = np.zeros(18, dtype=np.uint64)
         _check(lib().hr_read_counts(self._h, c.ctypes.data_as(ctypes.c_void_p), _stream()), "hr_read_counts")
-        c = c.reshape(3, 4).astype(np.int64)
+        c = c.reshape(3, 6).astype(np.int64)
         return {"k_render": tuple(c[0]), "k_adjoint_interior": tuple(c[1]), "k_edge_sample": tuple(c[2])}
 
     def timing_enable(self, enable):

@@ -110,7 +110,7 @@ struct hr_scene {
     float* joint_state = nullptr; // [hands, joint state] of hr_iterate's skinning, for its backward
     int* hand_counter = nullptr;  // [1] hands finished in the geometry backward (reset by the last)
     int geom_blocks = 0;
-    unsigned long long* counts = nullptr;   // [3][4] work counters (render, interior adjoint, edges)
+    unsigned long long* counts = nullptr;   // [3][6] work counters (render, interior adjoint, edges)
     // learned edge-sampling proposal (hr_proposal_*)
     bool prop_alloc = false;
     int prop_kind = HR_PROPOSAL_LENGTH;
@@ -498,8 +498,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<unsigned long long>(&s->edge_total, nullptr, n_views));
     TRY(s->upload<long long>(&s->edge_budget, nullptr, n_views));
     TRY(s->upload<long long>(&s->edge_prefix, nullptr, (size_t)n_views + 1));
-    TRY(s->upload<unsigned long long>(&s->counts, nullptr, 12));
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)0, s->counts, 12);
+    TRY(s->upload<unsigned long long>(&s->counts, nullptr, kCounts));
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, (hipStream_t)0, s->counts, kCounts);
     if (hipDeviceSynchronize() != hipSuccess) { hr_scene_destroy(s); return fail(HR_EHIP, "scene init failed"); }
     if (hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking) != hipSuccess) {
         hr_scene_destroy(s);
@@ -668,7 +668,7 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
     a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
     a.stat_a = nullptr; a.stat_dc = nullptr;
     a.samples = s->samples; a.sample_cap = s->sample_cap;
-    a.counts = s->counts + 8;
+    a.counts = s->counts + 12;
     a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
     a.delta = s->cfg.edge_delta; a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed;
     a.shading = shading_of(s->cfg);
@@ -687,9 +687,9 @@ int hr_read_counts(hr_scene* s, uint64_t* counts_host, void* stream)
     if (!s || !counts_host) return fail(HR_EINVAL, "hr_read_counts: null argument");
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = hipMemcpy(counts_host, s->counts, 12 * sizeof(uint64_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(counts_host, s->counts, kCounts * sizeof(uint64_t), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(HR_EHIP, "hr_read_counts: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, s->counts, 12);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, s->counts, kCounts);
     return check_launch("hr_read_counts");
 }
 
@@ -835,7 +835,7 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     a.n_nodes = s->bvh.node_stride; a.n_faces = s->F; a.n_verts = s->V;
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
-    a.counts = s->counts + 4;
+    a.counts = s->counts + 6;
     if (flags & HR_GRAD_INTERIOR) n_adj = s->adjoint_blocks;
     // loss_value: the loss's chunk partials ride along (summed per hand by
     // the geometry backward)

@@ -262,7 +262,10 @@ __device__ __forceinline__ bool slab(const Ray& r, const float* lo, const float*
 // `stack` points at this lane's column of an LDS array (stride `sstride`).
 // Work counters of one traversal (only maintained when COUNT is true).
 struct TraceCount {
-    unsigned nodes = 0, tris = 0;
+    unsigned nodes = 0, tris = 0;       // the ray's own work: nodes whose box it enters, triangles of
+                                        // leaves whose box it enters
+    unsigned nodes_w = 0, tris_w = 0;   // packet traversal: node visits and triangle tests executed
+                                        // while this lane was active (the union of the wave's rays)
 };
 
 template <bool COUNT = false>
@@ -275,7 +278,7 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
     int sp = 0;
     int node = 0;
     while (true) {
-        if (COUNT) cnt->nodes++;
+        if (COUNT) { cnt->nodes++; cnt->nodes_w++; }
         const Node& n = nodes[node];
         float4 q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
         float4 q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
@@ -296,7 +299,7 @@ __device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri*
             if (hit && code < 0) {
                 int lc = ~code;
                 int start = lc >> 3, ncnt = lc & 7;
-                if (COUNT) cnt->tris += ncnt;
+                if (COUNT) { cnt->tris += ncnt; cnt->tris_w += ncnt; }
                 float4 P[kLeafMax][3];
 #pragma unroll
                 for (int k = 0; k < kLeafMax; ++k)
@@ -385,8 +388,16 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
     int node = 0;
     nodes = uniform_ptr(nodes);
     tris = uniform_ptr(tris);
+    // counting: the lanes whose ray entered the current node's box (from the
+    // parent's test; the root: every active lane), with a mask per stack entry
+    __shared__ uint64_t mstack[COUNT ? kThreads / 64 : 1][COUNT ? kMaxStack : 1];
+    const int lane_id = (int)(threadIdx.x & 63);
+    uint64_t need = COUNT ? wave_mask(active) : 0ull;
     while (true) {
-        if (COUNT && active) cnt->nodes++;
+        if (COUNT) {
+            if (active) cnt->nodes_w++;
+            if ((need >> lane_id) & 1ull) cnt->nodes++;
+        }
         float4 q0, q1, q2;
         int4 q3;
         if (SFETCH) {
@@ -416,6 +427,7 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
                 const int lc = ~code;
                 const int start = lc >> 3, ncnt = lc & 7;
                 if (COUNT && hit) cnt->tris += ncnt;
+                if (COUNT && active) cnt->tris_w += ncnt;
                 for (int k = 0; k < ncnt; ++k) {
                     float4 p0, p1, p2;
                     if (SFETCH) {
@@ -457,16 +469,21 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
             const int n10 = __popcll(both) - n01;
             const int nearc = n01 >= n10 ? c0 : c1;
             const int farc = n01 >= n10 ? c1 : c0;
+            if (COUNT && sp < kMaxStack) mstack[threadIdx.x >> 6][sp] = n01 >= n10 ? m1 : m0;
+            if (COUNT) need = n01 >= n10 ? m0 : m1;
             if (sp < kMaxStack) { wstack[sp] = farc; ++sp; }
             node = nearc;
         } else if (go0) {
             node = c0;
+            if (COUNT) need = m0;
         } else if (go1) {
             node = c1;
+            if (COUNT) need = m1;
         } else {
             if (sp == 0) break;
             --sp;
             node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+            if (COUNT) need = mstack[threadIdx.x >> 6][sp];
         }
     }
 }

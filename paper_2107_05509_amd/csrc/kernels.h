@@ -11,6 +11,7 @@ constexpr int kMaxInfl = 8;     // skinning weights per vertex
 constexpr int kSkinPart = 12 + 12 * kMaxJoints + 16;   // per-hand sums of the skinning backward
 constexpr int kVfSlots = 12;    // faces per vertex in the corner table (more: the CSR list)
 constexpr int kLossChunk = 4096;     // pixels per loss block (never straddles views)
+constexpr int kCounts = 18;          // work counters: 6 per ray-tracing kernel (render, interior adjoint, edges)
 
 struct MeshDev {
     int V, F, J, K, E;
@@ -81,7 +82,8 @@ struct RenderArgs {
     const float* target;       // [P,3] with dimage
     const uint8_t* mask;       // [P] nullable
     const float* view_scale;   // [n_views] 1 / (3 * masked pixels), with dimage
-    unsigned long long* counts;   // [4] rays traced, node visits, triangle tests, hits (counting variant)
+    unsigned long long* counts;   // [6] counting variant: rays traced, node visits, triangle tests, hits,
+                                  // packet node visits and packet triangle tests (TraceCount)
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
     const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`

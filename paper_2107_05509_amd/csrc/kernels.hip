@@ -697,6 +697,8 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
         atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
         atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
         atomicAdd(a.counts + 3, n_hit);
+        atomicAdd(a.counts + 4, (unsigned long long)tc.nodes_w);
+        atomicAdd(a.counts + 5, (unsigned long long)tc.tris_w);
     }
 }
 
@@ -919,7 +921,7 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 trace_wave<COUNT, true>(nodes, tris, ray, act, wst, h, &tc);
             }
             if (act) {
-                if (COUNT) ++n_rays;
+                if (COUNT && !stored) ++n_rays;   // rays traced again (stored hits are read, not traced)
                 if (h.face >= 0) {
                     if (COUNT) ++n_hit;
                     Surf sf;
@@ -1085,6 +1087,8 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
         atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
         atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
         atomicAdd(a.counts + 3, n_hit);
+        atomicAdd(a.counts + 4, (unsigned long long)tc.nodes_w);
+        atomicAdd(a.counts + 5, (unsigned long long)tc.tris_w);
     }
 }
 
@@ -1506,6 +1510,8 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int
         atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
         atomicAdd(a.counts + 2, (unsigned long long)tc.tris);
         atomicAdd(a.counts + 3, n_hit);
+        atomicAdd(a.counts + 4, (unsigned long long)tc.nodes_w);
+        atomicAdd(a.counts + 5, (unsigned long long)tc.tris_w);
     }
 }
 

@@ -98,3 +98,77 @@ def camera_sample_offsets(philox, seed, it, view, pix, spp):
     u = ((r & np.uint64(0xFFFFFFFF)) >> np.uint64(8)).astype(np.float64) / 2 ** 24
     v = (r >> np.uint64(40)).astype(np.float64) / 2 ** 24
     return u, v
+
+
+def convex_hull(pts):
+    """Counter-clockwise convex hull of 2-D points (monotone chain)."""
+    pts = sorted(map(tuple, np.asarray(pts, np.float64)))
+
+    def cross(o, a, b):
+        return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+
+    lower, upper = [], []
+    for p in pts:
+        while len(lower) >= 2 and cross(lower[-2], lower[-1], p) <= 0:
+            lower.pop()
+        lower.append(p)
+    for p in reversed(pts):
+        while len(upper) >= 2 and cross(upper[-2], upper[-1], p) <= 0:
+            upper.pop()
+        upper.append(p)
+    return np.array(lower[:-1] + upper[:-1])
+
+
+def clip_to_convex(poly, hull):
+    """Intersect a convex polygon with a counter-clockwise convex polygon."""
+    n = len(hull)
+    for i in range(n):
+        p, q = hull[i], hull[(i + 1) % n]
+        a, b = -(q[1] - p[1]), (q[0] - p[0])
+        c = -(a * p[0] + b * p[1])
+        poly = clip_poly(poly, a, b, c)
+        if len(poly) == 0:
+            break
+    return poly
+
+
+def polygon_pixel_areas(poly, W, H):
+    """Exact area of (convex polygon) ∩ pixel for every pixel: [H,W]."""
+    A = np.zeros((H, W))
+    if len(poly) < 3:
+        return A
+    lo = np.floor(poly.min(0)).astype(int)
+    hi = np.ceil(poly.max(0)).astype(int)
+    for y in range(max(lo[1], 0), min(hi[1], H)):
+        for x in range(max(lo[0], 0), min(hi[0], W)):
+            A[y, x] = poly_area(clip_to_box(poly, x, y, x + 1, y + 1))
+    return A
+
+
+def triangulated_cube(half, rot, centre):
+    """Closed cube of half-size `half`, rotated by `rot` [3,3] about its centre
+    and moved to `centre`: 8 vertices, 12 triangles wound counter-clockwise
+    seen from outside (two per square face, split along a diagonal)."""
+    corners = np.array([[x, y, z] for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)], np.float64)
+    quads = []
+    for axis in range(3):
+        for sgn in (-1, 1):
+            q = [i for i, c in enumerate(corners) if c[axis] == sgn]
+            # order the face's corners around its normal
+            u, v = [a for a in range(3) if a != axis]
+            ctr = corners[q].mean(0)
+            ang = [np.arctan2(corners[i][v] - ctr[v], corners[i][u] - ctr[u]) for i in q]
+            q = [q[k] for k in np.argsort(ang)]
+            n = np.zeros(3)
+            n[axis] = sgn
+            tri = (q[0], q[1], q[2])
+            e = np.cross(corners[tri[1]] - corners[tri[0]], corners[tri[2]] - corners[tri[0]])
+            if np.dot(e, n) < 0:
+                q = q[::-1]
+            quads.append(q)
+    faces = []
+    for q in quads:
+        faces.append((q[0], q[1], q[2]))
+        faces.append((q[0], q[2], q[3]))
+    verts = (corners * half) @ np.asarray(rot).T + np.asarray(centre)
+    return verts, np.array(faces, np.int32)
