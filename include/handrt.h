@@ -59,6 +59,9 @@ extern "C" {
 #define HR_GRAD_ALL 3u
 #define HR_REUSE_GEOMETRY 4u    /* normals/BVH already prepared from `verts`
                                    by the previous hr_render on this scene */
+#define HR_SKIP_PRIOR 8u        /* leave the joint prior's gradient out even when
+                                   hr_set_joint_prior has set one (gradient of
+                                   the data term alone) */
 
 typedef struct hr_scene hr_scene;
 typedef struct hr_graph hr_graph;
@@ -166,7 +169,9 @@ int hr_loss(hr_scene* scene, const float* image, const float* target, const uint
 
 /* Gradient of L = sum_p dimage[p] . image[p] (with the samples of hr_render
    at the same iter) with respect to the hand parameters and the colour map.
-   flags: HR_GRAD_* terms to include, plus HR_REUSE_GEOMETRY.
+   flags: HR_GRAD_* terms to include, plus HR_REUSE_GEOMETRY and HR_SKIP_PRIOR.
+   With a joint prior set (hr_set_joint_prior) and without HR_SKIP_PRIOR,
+   grad_params also holds lambda dE2/dparams.
    grad_params [n_hands,64] out; grad_albedo [n_hands,tex_h,tex_w,3] out;
    grad_verts [n_hands,V,3] out (nullable): dL/dvertex before skinning
    backward, all terms; grad_normals [n_hands,V,3] out (nullable): dL/d(unit
@@ -176,7 +181,7 @@ int hr_backward(hr_scene* scene, const float* params, const float* verts, const 
                 float* grad_params, float* grad_albedo, float* grad_verts, float* grad_normals,
                 void* stream);
 
-/* Camera coverage (Section 5, camera coverage; Eq. 6).  hr_face_visibility:
+/* Camera coverage (Section 4.2.3, camera coverage; Eq. 6).  hr_face_visibility:
    visible [n_views,F] int32 out (DEVICE): 1 where some camera sample of the
    view hit the face, from hit_face [pixels,spp] as hr_render writes it (the
    coverage of a view is the set of triangles its samples see), else 0.
@@ -193,7 +198,7 @@ int hr_backward(hr_scene* scene, const float* params, const float* verts, const 
 int hr_face_visibility(hr_scene* scene, const int32_t* hit_face, int32_t* visible, void* stream);
 int hr_camera_order(hr_scene* scene, const int32_t* visible, int32_t* order, int32_t* covered, void* stream);
 
-/* Joint prior of the objective E = E1 + lambda E2 (Section 3.3): E2 sums,
+/* Joint prior of the objective E = E1 + lambda E2 (Section 3.2, Eq. 5): E2 sums,
    over the hands' joints and their three coordinates, the smooth L1
    distance f2(d) = d^2 / (2 gamma) for |d| < gamma, |d| - gamma / 2
    otherwise, between the posed joints (those hr_skin returns) and
@@ -231,7 +236,8 @@ typedef struct {
     float* verts;             /* [n_hands,V,3] out: vertices of the iteration */
     float* image;             /* [P,3] out: rendered images */
     float* dimage;            /* [P,3] out: dE1/dimage */
-    float* loss;              /* [n_hands] out: E1 of the iteration (before its step) */
+    float* loss;              /* [n_hands] out: the objective of the iteration (before its
+                                 step): E1, or E1 + lambda E2 while a joint prior is set */
     float* grad_params;       /* [n_hands,64] out */
     float* grad_albedo;       /* [n_hands,tex_h,tex_w,3] out */
     int32_t* iter;            /* [1] int32 iteration index, read when the work

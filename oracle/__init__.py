@@ -9,7 +9,7 @@ colour difference D_c of Eq. 4, the optimiser is Adam, Section 3.3):
 * skin         -- linear blend skinning of the hand model: shape blend, joint
                   regression, per-joint Rodrigues rotations, forward kinematics,
                   blend of joint transforms, global rotation and translation
-                  (the model G_v / G_J of Section 3.1 and Eq. 5).  float64 torch.
+                  (G_v of Section 3.1; G_J of Section 3.2, Eq. 5).  float64 torch.
 * normals      -- area-weighted unit vertex normals.  float64 torch.
 * render       -- Monte Carlo pixel integrals (Section 3: each rendered pixel is
                   an integral of samples); brute-force closest hit.  C, float64.
@@ -125,7 +125,7 @@ def render(sc: Scene, verts, normals, albedo, background, spp, seed, it, want_hi
 
 def face_visibility(hits, pix_off, F):
     """visible [N,F] bool: view i sees face f when one of its camera samples hit
-    f (Section 5, camera coverage: the surface a view makes visible, counted in
+    f (Section 4.2.3, camera coverage: the surface a view makes visible, counted in
     triangles).  hits [P,spp] per-sample face ids (-1 miss), views packed by
     pix_off [N+1]."""
     N = len(pix_off) - 1
@@ -137,7 +137,7 @@ def face_visibility(hits, pix_off, F):
 
 
 def camera_order(visible, hand_views):
-    """Greedy order of each hand's views (Section 5, camera coverage, Eq. 6):
+    """Greedy order of each hand's views (Section 4.2.3, camera coverage, Eq. 6):
     each step takes the view that adds the most faces not seen by the views
     taken before (ties: the earlier view of the hand's list).  Returns (order,
     covered), concatenated over the hands: view indices, and the faces seen by
@@ -306,7 +306,7 @@ def skin(m: Model, params):
 
 
 def joint_prior(joints, target, lam, gamma):
-    """lambda E2 per hand (Section 3.3, the prior term of the objective
+    """lambda E2 per hand (Section 3.2, Eq. 5: the prior term of the objective
     E = E1 + lambda E2): over joints [H,J,3] and their coordinates, the smooth
     L1 distance to the target joints with threshold gamma, d^2 / (2 gamma)
     where |d| < gamma and |d| - gamma / 2 elsewhere."""

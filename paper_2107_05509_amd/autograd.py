@@ -5,6 +5,8 @@ colour map: its backward hands the incoming image gradient to hr_backward,
 which re-traces the forward's samples from their counters (nothing per sample
 is stored) and adds the silhouette-edge term.  `photometric_loss` fuses render
 and the L1 data term (Eq. 3 with D_c of Eq. 4) and returns the per-hand loss.
+Both differentiate exactly what they return: a joint prior set on the scene
+(part of hr_iterate's objective) stays out of their gradients.
 """
 from __future__ import annotations
 
@@ -41,7 +43,8 @@ class _RenderImages(torch.autograd.Function):
         scene.skin(params, verts)   # recomputed; hr_backward re-prepares the geometry
         gp = torch.empty_like(params)
         ga = torch.empty_like(albedo)
-        scene.backward(params, verts, albedo, background, grad_image.contiguous(), ctx.it, gp, ga)
+        scene.backward(params, verts, albedo, background, grad_image.contiguous(), ctx.it, gp, ga,
+                       flags=binding.HR_GRAD_ALL | binding.HR_SKIP_PRIOR)
         return gp, ga, None, None, None
 
 
@@ -74,7 +77,8 @@ class _PhotometricLoss(torch.autograd.Function):
         d = (dimage * grad_loss[pixel_hand][:, None]).contiguous()
         gp = torch.empty_like(params)
         ga = torch.empty_like(albedo)
-        scene.backward(params, verts, albedo, background, d, ctx.it, gp, ga)
+        scene.backward(params, verts, albedo, background, d, ctx.it, gp, ga,
+                       flags=binding.HR_GRAD_ALL | binding.HR_SKIP_PRIOR)
         return gp, ga, None, None, None, None, None, None
 
 

@@ -20,6 +20,7 @@ HR_GRAD_INTERIOR = 1
 HR_GRAD_EDGES = 2
 HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
+HR_SKIP_PRIOR = 8
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
            "hr_loss", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
@@ -269,7 +270,7 @@ class Scene:
                "hr_camera_order")
 
     def set_joint_prior(self, target_joints=None, lam=0.0, gamma=0.005):
-        """Joint prior lambda E2 (Section 3.3) for the backwards enqueued from now
+        """Joint prior lambda E2 (Section 3.2, Eq. 5) for the backwards enqueued from now
         on: target_joints a CUDA float32 tensor [n_hands,J,3], None to switch off.
         The scene keeps a reference to every target it was given: backwards and
         graphs captured while it was set read it."""

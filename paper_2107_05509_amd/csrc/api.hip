@@ -89,7 +89,8 @@ struct hr_scene {
     const float* prior_target = nullptr;
     float prior_lambda = 0.0f, prior_gamma = 1.0f;
     Node* nodes = nullptr;
-    float* gacc = nullptr;        // [views,V,6] vertex gradient slots of each view (edge term)
+    float* gacc = nullptr;        // [views,V,3] float64 vertex gradient slots of each view (edge term),
+                                  // zeroed as 6 floats per vertex
     float* gface = nullptr;       // [hands,F,18] triangle corner slots (interior term)
     EdgeSample* samples = nullptr;   // traced edge samples (first part of the boundary term)
     long long sample_cap = 0;
@@ -869,7 +870,9 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
     g.p1_blocks = (s->V + 255) / 256;
     g.iter_advance = iter_advance;
     g.hand_counter = s->hand_counter;
-    g.prior_target = s->prior_target; g.prior_lambda = s->prior_lambda; g.prior_gamma = s->prior_gamma;
+    const bool prior = !(flags & HR_SKIP_PRIOR);
+    g.prior_target = prior ? s->prior_target : nullptr;
+    g.prior_lambda = s->prior_lambda; g.prior_gamma = s->prior_gamma;
     // per hand one more block sums the loss value
     const long long n4 = (long long)s->n_hands * s->cfg.tex_h * s->cfg.tex_w * 3 / 4;
     const int n_adam = adam ? (int)std::min<long long>(1024, std::max<long long>(1, (n4 + 255) / 256)) : 0;
@@ -922,7 +925,7 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
 {
     if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
         return fail(HR_EINVAL, "hr_backward: null argument");
-    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY)) return fail(HR_EINVAL, "hr_backward: unknown flags");
+    if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY | HR_SKIP_PRIOR)) return fail(HR_EINVAL, "hr_backward: unknown flags");
     return backward_impl(s, params, verts, albedo, background, dimage, iter, nullptr, flags, grad_params, grad_albedo,
                          grad_verts, grad_normals, (hipStream_t)stream);
 }

@@ -135,7 +135,7 @@ struct LossArgs {
 struct alignas(16) EdgeSample {
     int vi, e;                 // view and edge; vi < 0: empty stratum
     long long pg;              // packed pixel owning the sample point
-    float t, wgt;              // position along the edge, weight factor
+    float t, wgt;              // position along the edge, stratum width over sampling weight
     float dc[3];               // c(x - delta n) - c(x + delta n)
     float pad;
 };
@@ -158,7 +158,7 @@ struct EdgeArgs {
     const float* albedo;
     const float* background;
     const float* dimage;
-    float* gacc;
+    float* gacc;               // [views,V,3] float64 vertex-gradient slots (6 floats of storage per vertex)
     float* stat_a;             // [n_views,E] nullable: sum of |sample contribution| per edge
     float* stat_dc;            // [n_views,E,4] nullable: sum of |c- - c+| per channel, sample count
     EdgeSample* samples;       // [sample_cap] traced samples
@@ -210,7 +210,7 @@ struct GeomBwdArgs {
     MeshDev m;
     const float* params;       // [H,64]
     const float* verts;        // [H,V,3]
-    const float* gacc;         // [views,V,6] per-vertex slots of each view (edge term)
+    const float* gacc;         // [views,V,3] float64 per-vertex slots of each view (edge term)
     const int* hand_view_off;  // [H+1] views of each hand
     const int* hand_views;
     const float* gface;        // [H,F,18] triangle-corner slots (interior term)

@@ -1295,22 +1295,29 @@ __device__ __forceinline__ void shade_or_bg(const Hit& h, const Tri* tris, const
     }
 }
 
-__device__ __forceinline__ void proj_jacobian(const ViewDev& c, const float* v, float J[2][3])
+// float64 projection of a vertex to the screen and its Jacobian d(px,py)/dv
+__device__ __forceinline__ void project64(const ViewDev& c, const float* v, double p[2], double J[2][3])
 {
-    float q[3] = {v[0] - c.o[0], v[1] - c.o[1], v[2] - c.o[2]};
-    float xc[3];
-    matvec3(c.R, q, xc);
-    float iz = 1.0f / xc[2];
-    float d[2][3] = {{c.fx * iz, 0.0f, -c.fx * xc[0] * iz * iz}, {0.0f, c.fy * iz, -c.fy * xc[1] * iz * iz}};
+    const double q[3] = {(double)v[0] - (double)c.o[0], (double)v[1] - (double)c.o[1], (double)v[2] - (double)c.o[2]};
+    double xc[3];
+    for (int r = 0; r < 3; ++r)
+        xc[r] = (double)c.R[3 * r] * q[0] + (double)c.R[3 * r + 1] * q[1] + (double)c.R[3 * r + 2] * q[2];
+    const double z = xc[2];
+    p[0] = (double)c.fx * xc[0] / z + (double)c.cx;
+    p[1] = (double)c.fy * xc[1] / z + (double)c.cy;
+    const double d[2][3] = {{(double)c.fx / z, 0.0, -(double)c.fx * xc[0] / (z * z)},
+                            {0.0, (double)c.fy / z, -(double)c.fy * xc[1] / (z * z)}};
     for (int r = 0; r < 2; ++r)
-        for (int k = 0; k < 3; ++k) J[r][k] = d[r][0] * c.R[k] + d[r][1] * c.R[3 + k] + d[r][2] * c.R[6 + k];
+        for (int k = 0; k < 3; ++k)
+            J[r][k] = d[r][0] * (double)c.R[k] + d[r][1] * (double)c.R[3 + k] + d[r][2] * (double)c.R[6 + k];
 }
 
 // Geometry of edge sample kg (global index over the views' budgets): the
 // view, the stratum of the view's integer CDF, the chosen edge and point, the
 // unit screen normal, the side point of this lane (even lane x + delta n, odd
-// lane x - delta n), the owning pixel and the weight factor
-// len * (stratum width) / wq (stratum probability over point density).
+// lane x - delta n), the owning pixel and the weight factor (stratum width) /
+// wq: the sample's weight is the edge's clipped length times it (stratum
+// probability over point density).
 struct EdgePoint {
     int vi, e;
     bool valid;          // false: empty stratum (no sample)
@@ -1369,9 +1376,9 @@ __device__ __forceinline__ void edge_point(const EdgeArgs& a, long long kg, uint
     px = min(max(px, 0), c.W - 1);
     py = min(max(py, 0), c.H - 1);
     P.pg = c.pix0 + (long long)py * c.W + px;
-    // weight: (stratum probability width/T) / (density (wq_e/T)/len per unit length)
-    const float ell = len * (qe.t1 - qe.t0);
-    P.wgt = ell * (float)width / (float)qe.wq;
+    // weight: (stratum probability width/T) / (density (wq_e/T)/len per unit length),
+    // the clipped length taken in float64 with the contribution
+    P.wgt = (float)width / (float)qe.wq;
 }
 
 // Closest hit and colour of this lane's side point of sample P.
@@ -1416,27 +1423,31 @@ __device__ __forceinline__ void edge_contribution(const EdgeArgs& a, int vi, int
         unsafeAtomicAdd(dcs + 2, fabsf(dc[2]));
         unsafeAtomicAdd(dcs + 3, 1.0f);
     }
-    const float jump = g[0] * dc[0] + g[1] * dc[1] + g[2] * dc[2];
-    if (jump == 0.0f) return;
-    const float sc = jump * wgt;
-    if (a.stat_a) unsafeAtomicAdd(a.stat_a + (size_t)vi * E + e, fabsf(sc));
+    const double jump = (double)g[0] * dc[0] + (double)g[1] * dc[1] + (double)g[2] * dc[2];
+    if (jump == 0.0) return;
     const ViewDev& c = a.views[vi];
     const EdgeRec qe = a.rec[(size_t)vi * E + e];
-    const float dx = qe.bx - qe.ax, dy = qe.by - qe.ay;
-    const float len = sqrtf(dx * dx + dy * dy);
-    const float nhx = dy / len, nhy = -dx / len;
     const int va = a.m.edges[2 * e], vb = a.m.edges[2 * e + 1];
     const float* vh = a.verts + (size_t)c.hand * a.m.V * 3;
+    // the edge's screen normal, clipped length and projection Jacobians in
+    // float64 from the float32 vertices (the float32 endpoints of the edge
+    // record only placed the sample)
+    double pa[2], pb[2], Ja[2][3], Jb[2][3];
+    project64(c, vh + 3 * va, pa, Ja);
+    project64(c, vh + 3 * vb, pb, Jb);
+    const double dx = pb[0] - pa[0], dy = pb[1] - pa[1];
+    const double len = sqrt(dx * dx + dy * dy);
+    const double nhx = dy / len, nhy = -dx / len;
+    const double sc = jump * (len * ((double)qe.t1 - (double)qe.t0)) * (double)wgt;
+    if (a.stat_a) unsafeAtomicAdd(a.stat_a + (size_t)vi * E + e, (float)fabs(sc));
     // one slot array per view: the samples of a view share few vertices, so
-    // the memory-side atomics of different views never queue on one address
-    float* gout = a.gacc + (size_t)vi * a.m.V * 6;
-    float Ja[2][3], Jb[2][3];
-    proj_jacobian(c, vh + 3 * va, Ja);
-    proj_jacobian(c, vh + 3 * vb, Jb);
-    const float sa = (1.0f - t) * sc, sb = t * sc;
+    // the memory-side atomics of different views never queue on one address;
+    // float64 sums (a vertex's samples come with both signs)
+    double* gout = reinterpret_cast<double*>(a.gacc) + (size_t)vi * a.m.V * 3;
+    const double sa = (1.0 - (double)t) * sc, sb = (double)t * sc;
     for (int k3 = 0; k3 < 3; ++k3) {
-        unsafeAtomicAdd(gout + 6 * va + k3, sa * (Ja[0][k3] * nhx + Ja[1][k3] * nhy));
-        unsafeAtomicAdd(gout + 6 * vb + k3, sb * (Jb[0][k3] * nhx + Jb[1][k3] * nhy));
+        unsafeAtomicAdd(gout + 3 * va + k3, sa * (Ja[0][k3] * nhx + Ja[1][k3] * nhy));
+        unsafeAtomicAdd(gout + 3 * vb + k3, sb * (Jb[0][k3] * nhx + Jb[1][k3] * nhy));
     }
 }
 
@@ -1683,7 +1694,7 @@ __device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, c
         for (int k = 0; k < 10; ++k) gp[48 + k] = k < K ? tot[12 + 12 * J + k] + sj[k] : 0.0f;
 }
 
-// Joint prior (Section 3.3): lambda times the coordinate-wise smooth L1
+// Joint prior (Section 3.2, Eq. 5): lambda times the coordinate-wise smooth L1
 // distance, with threshold gamma, between the posed joints Rp Gt_j + tau and
 // the target joints (quadratic d^2 / (2 gamma) below gamma, |d| - gamma / 2
 // above).  One wave, lane j for joint j.  Its gradient g_j with respect to the
@@ -1826,11 +1837,12 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
     if (v >= V) return;
     const float* vh = a.verts + (size_t)h * V * 3;
     const float* gf = a.gface + (size_t)h * m.F * 18;
-    // the edge term's slots of the hand's views, in view order
-    float g[3] = {0.0f, 0.0f, 0.0f}, gn[3] = {0.0f, 0.0f, 0.0f};
+    // the edge term's float64 slots of the hand's views, in view order; the
+    // sums of the vertex run in float64
+    double g[3] = {0.0, 0.0, 0.0}, gn[3] = {0.0, 0.0, 0.0};
     for (int q = a.hand_view_off[h]; q < a.hand_view_off[h + 1]; ++q) {
-        const float* ga = a.gacc + ((size_t)a.hand_views[q] * V + v) * 6;
-        for (int k = 0; k < 3; ++k) { g[k] += ga[k]; gn[k] += ga[3 + k]; }
+        const double* ga = reinterpret_cast<const double*>(a.gacc) + ((size_t)a.hand_views[q] * V + v) * 3;
+        for (int k = 0; k < 3; ++k) g[k] += ga[k];
     }
     float sv[3] = {0.0f, 0.0f, 0.0f};
     // faces around v: the corner table's entries with all their loads in
@@ -1842,7 +1854,7 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
     auto face_terms = [&](int f, int i0, int i1, int i2) {
         const int corner = i0 == v ? 0 : (i1 == v ? 1 : 2);
         const float* sl = gf + 18 * f + 6 * corner;
-        for (int q = 0; q < 3; ++q) { g[q] += sl[q]; gn[q] += sl[3 + q]; }
+        for (int q = 0; q < 3; ++q) { g[q] += (double)sl[q]; gn[q] += (double)sl[3 + q]; }
         const float* a0 = vh + 3 * i0;
         const float* a1 = vh + 3 * i1;
         const float* a2 = vh + 3 * i2;
@@ -1861,16 +1873,17 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
     }
     const float il = 1.0f / sqrtf(sv[0] * sv[0] + sv[1] * sv[1] + sv[2] * sv[2]);
     const float n[3] = {sv[0] * il, sv[1] * il, sv[2] * il};
+    const float gnf[3] = {(float)gn[0], (float)gn[1], (float)gn[2]};
     if (a.grad_normals) {
         float* o = a.grad_normals + ((size_t)h * V + v) * 3;
-        o[0] = gn[0]; o[1] = gn[1]; o[2] = gn[2];
+        o[0] = gnf[0]; o[1] = gnf[1]; o[2] = gnf[2];
     }
-    const float d = gn[0] * n[0] + gn[1] * n[1] + gn[2] * n[2];
+    const float d = gnf[0] * n[0] + gnf[1] * n[1] + gnf[2] * n[2];
     float* gr = a.gr + ((size_t)h * V + v) * 3;
     float* gp = a.gpos + ((size_t)h * V + v) * 3;
     for (int q = 0; q < 3; ++q) {
-        gr[q] = (gn[q] - d * n[q]) * il;
-        gp[q] = g[q];
+        gr[q] = (gnf[q] - d * n[q]) * il;
+        gp[q] = (float)g[q];
     }
 }
 

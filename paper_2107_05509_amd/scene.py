@@ -422,8 +422,11 @@ def make_hand_model(seed: int = 0) -> HandModel:
     uv = np.clip(uv, 0.0, 1.0)
 
     edges, efaces, offs, flat = _edge_tables(faces, V)
-    return HandModel(v_template=verts, shapedirs=shapedirs, j_regressor=jreg, weights=W,
-                     parents=parents, faces=faces.astype(np.int32), uv=uv, edges=edges,
+    # the model's real arrays hold float32 values (kept as float64 arrays), so
+    # that every consumer, float32 or float64, reads exactly the same numbers
+    f32v = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    return HandModel(v_template=f32v(verts), shapedirs=f32v(shapedirs), j_regressor=f32v(jreg), weights=f32v(W),
+                     parents=parents, faces=faces.astype(np.int32), uv=f32v(uv), edges=edges,
                      edge_faces=efaces, vf_offsets=offs, vf_faces=flat, layout2d=lay)
 
 
@@ -614,6 +617,25 @@ def workload_batched(seed=0, n_hands=64, spp=8):
     albs = np.array(albs)
     return Workload(f"batched {n_hands} hands {spp}spp", model, cams, n_hands, np.array(pts),
                     np.array(pis), albs, np.full_like(albs, 0.5), bgs, spp, 200, seed)
+
+
+def workload_mixed(seed=0, spp=4):
+    """A small batch for parity against the oracle: 3 hands with 3, 1 and 2
+    views of 64x64, 48x32 and 96x64 pixels (f = 80 W / 64, 0.6 m sphere),
+    the hands' views interleaved in the camera list, 64x64 albedo, 4 spp."""
+    model = make_hand_model(0)
+    r = _rng(seed, 31)
+    layout = [(0, 64, 64), (2, 96, 64), (0, 64, 64), (1, 48, 32), (2, 96, 64), (0, 64, 64)]
+    pts = [true_params(r, 0.3, shape=True, global_rot=True) for _ in range(3)]
+    pis = [perturb_params(p, r, 0.1, 5.0) for p in pts]
+    albs = np.array([blob_albedo(64, 64, _rng(seed * 1000 + h, 32)) for h in range(3)])
+    cams = []
+    for k, (h, W, H) in enumerate(layout):
+        cams.extend(camera_rig(1, W, H, 80.0 * W / 64.0, 0.6, _rng(seed * 1000 + k, 33), hand=h))
+    bgr = _rng(seed, 34)
+    bgs = [uniform_background(c.H, c.W, bgr) for c in cams]
+    return Workload(f"mixed 3 hands {spp}spp", model, cams, 3, np.array(pts), np.array(pis), albs,
+                    albs.copy(), bgs, spp, 10, seed)
 
 
 # --------------------------------------------------------------------------

@@ -63,3 +63,22 @@ def block_rel(a, b):
     b = np.asarray(b, np.float64).ravel()
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / max(nb, 1e-30)
+
+
+def elem_excess(a, b, rtol=1e-4, floor=1e-3):
+    """Largest element-wise error of `a` against the oracle's `b`, in units of
+    the bar rtol * max(|b_i|, floor * max|b|) (<= 1 passes)."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    scale = np.maximum(np.abs(b), floor * np.abs(b).max())
+    return float((np.abs(a - b) / (rtol * np.maximum(scale, 1e-300))).max())
+
+
+def check_grad(name, a, b, block_tol=1e-4, rtol=1e-4, floor=1e-3):
+    """Block norm ||a - b|| / ||b|| <= block_tol and every element within
+    rtol * max(|b_i|, floor * max|b|)."""
+    e = block_rel(a, b)
+    x = elem_excess(a, b, rtol, floor)
+    print(f"{name}: block {e:.3g}, element-wise {x:.3g} of the bar", flush=True)
+    assert e <= block_tol, (name, e)
+    assert x <= 1.0, (name, x)

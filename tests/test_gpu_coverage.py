@@ -1,4 +1,4 @@
-"""Camera coverage (paper Section 5, Eq. 6) on the HIP path, through the C ABI,
+"""Camera coverage (paper Section 4.2.3, Eq. 6) on the HIP path, through the C ABI,
 against the oracle: faces seen per view from the render's hit ids, and the
 greedy camera order.  Bar: bit-exact (integer work)."""
 import numpy as np

@@ -3,9 +3,13 @@ edge gradients, Adam with the root rotation frozen) on the tiny workload, run
 independently by the HIP path and by the oracle from the same float32 inputs
 (target images rendered by the oracle from the true parameters at 64 samples
 per pixel with an independent key).  The first three iterations must agree
-tightly (loss 1e-5 relative, parameters 1e-4); afterwards the trajectories
-may drift apart by Adam's amplification of rounding differences (loss within
-2%, parameters within two learning rates), and the loss must fall on both."""
+tightly (loss 1e-5 relative, parameters 1e-4).  Afterwards each side skins
+its own parameters (float32 against float64) and Adam's normalised steps
+amplify the rounding differences of near-zero gradient components; should
+a quantised silhouette length or a grazing hit fall differently, the two
+sides would from then on draw different edge samples.  The band: loss
+within 2% and every parameter within a quarter of a learning rate at the
+end; the loss must fall on both."""
 import numpy as np
 import pytest
 import torch
@@ -82,11 +86,9 @@ def test_refinement_trajectory():
             assert dl <= 1e-5, it
             assert dp <= 1e-4, it
         else:
-            # later on, Adam's normalised steps amplify float32-vs-float64 (and
-            # atomic-order) differences of near-zero gradient components into
-            # steps of up to one learning rate: a drift band only
+            # later on, a drift band only (see above)
             assert dl <= 2e-2, it
     drift = np.abs(g_params[-1] - o_params[-1])
     print("largest final drift at parameter %d: %.2e" % (int(drift.argmax()), drift.max()), flush=True)
-    assert drift.max() <= 2e-2
+    assert drift.max() <= 2.5e-3   # a quarter of the 1e-2 learning rate
     assert g_loss[-1] < g_loss[0] and o_loss[-1] < o_loss[0]

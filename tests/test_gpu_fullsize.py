@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import DEV, Case, block_rel, f32, rel_err
+from gpu_util import DEV, Case, check_grad, f32, rel_err
 from paper_2107_05509_amd import binding, scene
 from test_gpu_parity import _check_params, _dimage, _gpu_grads, _oracle_grads
 
@@ -52,7 +52,5 @@ def test_fullsize_gradient_parity(full):
     _, _, tot_o, bud_o = oracle.edge_weights(c.osc, c.v32.astype(np.float64))
     assert np.array_equal(tot, tot_o) and np.array_equal(bud, bud_o)
     for k in ("ga", "gn", "gv"):
-        e = block_rel(g[k], o[k])
-        print(k, e, flush=True)
-        assert e <= 1e-4, k
+        check_grad(k, g[k], o[k])
     _check_params(g["gp"], o["gp"])

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import DEV, Case, block_rel, f32, rel_err
+from gpu_util import DEV, Case, block_rel, check_grad, f32, rel_err
 from paper_2107_05509_amd import binding, scene
 
 pytestmark = pytest.mark.gpu
@@ -114,9 +114,7 @@ def test_interior_adjoint_parity(tiny):
     g = _gpu_grads(c, d, binding.HR_GRAD_INTERIOR)
     o = _oracle_grads(c, d, binding.HR_GRAD_INTERIOR)
     for k in ("ga", "gn", "gv"):
-        e = block_rel(g[k], o[k])
-        print(k, e, flush=True)
-        assert e <= 1e-4, k
+        check_grad(k, g[k], o[k])
     _check_params(g["gp"], o["gp"])
 
 
@@ -138,9 +136,7 @@ def test_interior_adjoint_texture_windows(spp, tex):
     g = _gpu_grads(c, d, binding.HR_GRAD_INTERIOR)
     o = _oracle_grads(c, d, binding.HR_GRAD_INTERIOR)
     for k in ("ga", "gn", "gv"):
-        e = block_rel(g[k], o[k])
-        print(k, e, flush=True)
-        assert e <= 1e-4, k
+        check_grad(k, g[k], o[k])
 
 
 def test_edge_term_parity(tiny):
@@ -153,18 +149,14 @@ def test_edge_term_parity(tiny):
     w, cdf, tot_o, bud_o = oracle.edge_weights(c.osc, c.v32.astype(np.float64))
     assert np.array_equal(tot, tot_o) and np.array_equal(bud, bud_o)
     assert bud.min() > 10
-    e = block_rel(g["gv"], o["gv"])
-    print("gv", e, flush=True)
-    assert e <= 1e-4
+    check_grad("gv", g["gv"], o["gv"])
     _check_params(g["gp"], o["gp"])
 
 
 def _check_params(gp, op):
     blocks = {"pose": slice(0, 48), "shape": slice(48, 58), "global": slice(58, 64)}
     for name, sl in blocks.items():
-        e = block_rel(gp[:, sl], op[:, sl])
-        print(name, e, flush=True)
-        assert e <= 1e-4, name
+        check_grad(name, gp[:, sl], op[:, sl])
 
 
 def test_adam_parity(tiny):

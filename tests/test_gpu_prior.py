@@ -1,4 +1,4 @@
-"""The joint prior lambda E2 (paper Section 3.3) on the HIP path, through the
+"""The joint prior lambda E2 (paper Section 3.2, Eq. 5) on the HIP path, through the
 C ABI, against the oracle: its gradient with respect to the hand parameters
 (the difference of two backwards, with and without the prior, on the same
 inputs) and its value in the loss of a whole iteration.  Bars: 1e-4 relative

@@ -1,4 +1,4 @@
-"""Pins of the oracle's camera-coverage ordering (paper Section 5, camera
+"""Pins of the oracle's camera-coverage ordering (paper Section 4.2.3, camera
 coverage, Eq. 6): a worked example, the tie rule, the coverage bound every
 greedy maximum-coverage order meets against brute force over all subsets, and
 visibility recounted from hit ids by plain loops."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's joint prior (paper Section 3.3, the prior term E2 of
+"""Pins of the oracle's joint prior (paper Section 3.2, Eq. 5: the prior term E2 of
 the objective E = E1 + lambda E2): the smooth L1 function against the library
 routine that defines the same function, its two regimes and their meeting
 point, and the gradient through the skinning against central differences."""
