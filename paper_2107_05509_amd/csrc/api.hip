@@ -337,21 +337,27 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         TRY(s->upload(&q, vc.data(), vc.size())); md.vf_corner = reinterpret_cast<const int4*>(q);
         // regressor applied to the template and to the shape directions (float64 sums)
         std::vector<float> jt(3 * (size_t)J), jsd(3 * (size_t)J * std::max(K, 1), 0.0f);
+        std::vector<double> jt64(jt.size()), jsd64(jsd.size(), 0.0);
         for (int j = 0; j < J; ++j)
             for (int c = 0; c < 3; ++c) {
                 double a = 0.0;
                 for (int v = 0; v < V; ++v) a += (double)m->j_regressor[(size_t)j * V + v] * m->v_template[3 * v + c];
                 jt[3 * j + c] = (float)a;
+                jt64[3 * j + c] = a;
                 for (int k = 0; k < K; ++k) {
                     double b = 0.0;
                     for (int v = 0; v < V; ++v)
                         b += (double)m->j_regressor[(size_t)j * V + v] * m->shapedirs[((size_t)3 * v + c) * K + k];
                     jsd[(3 * (size_t)j + c) * K + k] = (float)b;
+                    jsd64[(3 * (size_t)j + c) * K + k] = b;
                 }
             }
         float* pf;
         TRY(s->upload(&pf, jt.data(), jt.size())); md.jt = pf;
         TRY(s->upload(&pf, jsd.data(), jsd.size())); md.js = pf;
+        double* pd;
+        TRY(s->upload(&pd, jt64.data(), jt64.size())); md.jt64 = pd;
+        TRY(s->upload(&pd, jsd64.data(), jsd64.size())); md.js64 = pd;
         std::vector<int> depth(J, 0);
         int maxd = 0;
         for (int j = 0; j < J; ++j) {

@@ -31,6 +31,8 @@ struct MeshDev {
                                // (a, b, c, face), padded with (v, v, v, 0)
     const float* jt;           // [J,3] J_reg T: rest joints of the template
     const float* js;           // [J,3,K] J_reg S: joint displacement per shape coefficient
+    const double* jt64;        // the same two tables in float64 (the forward skinning)
+    const double* js64;
     const int* jdepth;         // [J] depth in the joint tree (root 0)
     int max_depth;
     int infl;                  // skinning weights per vertex (padded with weight 0)

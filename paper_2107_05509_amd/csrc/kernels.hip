@@ -251,12 +251,123 @@ __device__ __forceinline__ void shaped_vertex(const MeshDev& m, const float* bk,
     shaped_vertex(m, bk, v, x, sd);
 }
 
+// ---------------------------------------------------------------------------
+// Forward skinning in float64.  The model's real tables hold float32 values,
+// whose float64 conversions are exact, so the vertices are the float32
+// roundings of a float64 evaluation of the skinning: the same float32 values
+// a float64 evaluation elsewhere rounds to (bar ties), which keeps every
+// float32 decision downstream (hits, silhouettes) identical.  The joint state
+// handed to the float32 backward is the rounding of the float64 one.
+// ---------------------------------------------------------------------------
+
+struct Rod64 {
+    double R[9];
+    double a, b, ad, bd;
+};
+
+struct JointState64 {              // JointState's layout with float64 members
+    Rod64 rod[kMaxJoints + 1];
+    double GR[kMaxJoints * 9];
+    double Gt[kMaxJoints * 3];
+    double At[kMaxJoints * 3];
+    double J[kMaxJoints * 3];
+    double Rp[9];
+};
+static_assert(sizeof(JointState64) == 2 * sizeof(JointState), "joint state layouts differ");
+
+__device__ void rodrigues64(const double* r, Rod64& o)
+{
+    const double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    const double t = sqrt(t2);
+    if (t < 1e-4) {
+        o.a = 1.0 - t2 / 6.0;
+        o.b = 0.5 - t2 / 24.0;
+    } else {
+        const double sh = sin(0.5 * t);
+        o.a = sin(t) / t;
+        o.b = 2.0 * sh * sh / t2;
+    }
+    // derivative factors of the backward (float32 there)
+    if (t < 0.3) {
+        o.ad = -1.0 / 3.0 + t2 / 30.0 - t2 * t2 / 840.0;
+        o.bd = -1.0 / 12.0 + t2 / 180.0 - t2 * t2 / 6720.0;
+    } else {
+        const double s = sin(t), c = cos(t), sh = sin(0.5 * t);
+        o.ad = (t * c - s) / (t2 * t);
+        o.bd = (t * s - 4.0 * sh * sh) / (t2 * t2);
+    }
+    const double K[9] = {0.0, -r[2], r[1], r[2], 0.0, -r[0], -r[1], r[0], 0.0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const double k2 = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+            o.R[3 * i + j] = o.a * K[3 * i + j] + o.b * k2 + (i == j ? 1.0 : 0.0);
+        }
+}
+
+__device__ __forceinline__ void matmul3d(const double* A, const double* B, double* C)
+{
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+__device__ __forceinline__ void matvec3d(const double* A, const double* x, double* y)
+{
+    for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
+}
+
+// joint_state in float64 (same structure: the first wave, one tree level at a
+// time; ends with a block barrier)
+__device__ void joint_state64(const MeshDev& m, const float* __restrict__ p, JointState64& js)
+{
+    const int J = m.J, K = m.K;
+    const int j = threadIdx.x;
+    if (j < 64) {
+        double bk[kMaxShape];
+#pragma unroll
+        for (int k = 0; k < kMaxShape; ++k) bk[k] = k < K ? (double)p[48 + k] : 0.0;
+        const int dj = j < J ? m.jdepth[j] : -1, par = j < J ? m.parents[j] : -1;
+        const int jr = j < J ? j : J;
+        const float* pr = j < J ? p + 3 * j : p + 58;
+        const double r[3] = {(double)pr[0], (double)pr[1], (double)pr[2]};
+        if (j <= J) rodrigues64(r, js.rod[jr]);
+        if (j < J)
+            for (int c = 0; c < 3; ++c) {
+                double x = m.jt64[3 * j + c];
+                for (int k = 0; k < K; ++k) x += m.js64[(3 * j + c) * K + k] * bk[k];
+                js.J[3 * j + c] = x;
+            }
+        wave_lds_sync();
+        if (j < 9) js.Rp[j] = js.rod[J].R[j];
+        for (int L = 0; L <= m.max_depth; ++L) {
+            if (dj == L) {
+                if (par < 0) {
+                    for (int i = 0; i < 9; ++i) js.GR[9 * j + i] = js.rod[j].R[i];
+                    for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = js.J[3 * j + i];
+                } else {
+                    matmul3d(js.GR + 9 * par, js.rod[j].R, js.GR + 9 * j);
+                    const double d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
+                                         js.J[3 * j + 2] - js.J[3 * par + 2]};
+                    double y[3];
+                    matvec3d(js.GR + 9 * par, d, y);
+                    for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = y[i] + js.Gt[3 * par + i];
+                }
+                double y[3];
+                matvec3d(js.GR + 9 * j, js.J + 3 * j, y);
+                for (int i = 0; i < 3; ++i) js.At[3 * j + i] = js.Gt[3 * j + i] - y[i];
+            }
+            wave_lds_sync();
+        }
+    }
+    __syncthreads();
+}
+
 // Skinning, grid (vertex blocks, hands).
 __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict__ params,
                                               float* __restrict__ verts, float* __restrict__ joints,
                                               int* __restrict__ tile_count, float* __restrict__ js_out)
 {
-    __shared__ JointState js;
+    __shared__ JointState64 js;
     const int h = blockIdx.y;
     // nullable: the wave-tile list of a following refit starts empty
     if (tile_count && blockIdx.x == 0 && h == 0 && threadIdx.x == 0) *tile_count = 0;
@@ -270,30 +381,44 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
         load_weights(m, v, wq, jq);
         load_shape(m, v, tpl, sd);
     }
-    joint_state(m, p, js);
-    // nullable: the joint state of these parameters for the backward
+    joint_state64(m, p, js);
+    // nullable: the joint state of these parameters for the backward (float32)
     if (js_out && blockIdx.x == 0) {
-        const float* src = reinterpret_cast<const float*>(&js);
+        const double* src = reinterpret_cast<const double*>(&js);
         for (int i = threadIdx.x; i < kJointStateFloats; i += blockDim.x)
-            js_out[(size_t)h * kJointStateFloats + i] = src[i];
+            js_out[(size_t)h * kJointStateFloats + i] = (float)src[i];
     }
     const float* tau = p + 61;
-    float bk[kMaxShape];
-    load_beta(m, p + 48, bk);
     if (v < m.V) {
-        float x[3], vp[3], y[3];
-        shape_vertex(m, bk, tpl, sd, x);
-        blend_vertex(js, wq, jq, x, vp);
-        matvec3(js.Rp, vp, y);
+        double x[3], vp[3] = {0.0, 0.0, 0.0}, y[3];
+        for (int c = 0; c < 3; ++c) {
+            double sv = (double)tpl[c];
+            for (int k = 0; k < m.K; ++k) sv += (double)sd[c][k] * (double)p[48 + k];
+            x[c] = sv;
+        }
+#pragma unroll
+        for (int q = 0; q < kMaxInfl; ++q) {
+            const double w = (double)wq[q];
+            if (w == 0.0) continue;
+            const int j = jq[q];
+            double g[3];
+            matvec3d(js.GR + 9 * j, x, g);
+            for (int c = 0; c < 3; ++c) vp[c] += w * (g[c] + js.At[3 * j + c]);
+        }
+        matvec3d(js.Rp, vp, y);
         float* o = verts + ((size_t)h * m.V + v) * 3;
-        o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
+        o[0] = (float)(y[0] + (double)tau[0]);
+        o[1] = (float)(y[1] + (double)tau[1]);
+        o[2] = (float)(y[2] + (double)tau[2]);
     }
     if (joints && blockIdx.x == 0 && (int)threadIdx.x < m.J) {
         const int j = threadIdx.x;
-        float y[3];
-        matvec3(js.Rp, js.Gt + 3 * j, y);
+        double y[3];
+        matvec3d(js.Rp, js.Gt + 3 * j, y);
         float* o = joints + ((size_t)h * m.J + j) * 3;
-        o[0] = y[0] + tau[0]; o[1] = y[1] + tau[1]; o[2] = y[2] + tau[2];
+        o[0] = (float)(y[0] + (double)tau[0]);
+        o[1] = (float)(y[1] + (double)tau[1]);
+        o[2] = (float)(y[2] + (double)tau[2]);
     }
 }
 

@@ -7,8 +7,9 @@ packed pixel offsets, per-hand colour maps and parameters) is exercised.
 Through the separate calls (render, loss, backward) both sides take the same
 float32 vertices (the oracle's skinning rounded): hit ids bit-exact, images
 1e-5 relative, gradients 1e-4 per block and element-wise.  Through
-hr_iterate the GPU skins the hand itself (float32 arithmetic, a few ulps from
-the oracle's rounded float64), so a ray grazing an edge may pick the other
+hr_iterate the GPU skins the hand itself (float64 arithmetic rounded to
+float32: the oracle's vertices rounded, bar a rare tie that moves a
+coordinate by one ulp), so a ray grazing an edge could pick the other
 triangle: at most 1e-4 of the samples may differ, the loss within the L1
 effect of the differing pixels, and the interior gradient within 1e-4 per
 block plus what those samples and the vertices' rounding move the oracle's
@@ -142,9 +143,13 @@ def test_iterate_interior_against_oracle(mixed):
     torch.cuda.synchronize()
     r = oracle.gradient(c.om, c.osc, c.params.astype(np.float64), c.albedo.astype(np.float64), c.bg, target, mask,
                         c.w.spp, c.seed, 0, edges=False)
-    # the GPU's own float32 skinning
+    # the GPU's own skinning (float64 arithmetic rounded to float32): the
+    # oracle's float64 vertices rounded, bar a rare tie
     verts = st.verts.cpu().numpy()
     assert np.abs(verts - r["verts"]).max() <= 1e-5 * np.abs(r["verts"]).max()
+    n_off = int((verts != f32(r["verts"])).sum())
+    print("vertex coordinates off the oracle's rounding:", n_off, flush=True)
+    assert n_off <= 2
     # samples: at most 1e-4 of them may take another triangle (rays grazing
     # an edge, the vertices a few ulps apart)
     img = st.image.cpu().numpy()
