@@ -167,6 +167,22 @@ int hr_render(hr_scene* scene, const float* verts, const float* albedo, const fl
 int hr_loss(hr_scene* scene, const float* image, const float* target, const uint8_t* mask,
             float* loss, float* dimage, void* stream);
 
+/* hr_loss for callers that cannot allocate device memory (code under HIP
+   graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+   same outputs as hr_loss (bit for bit), with its scratch (the chunk partial
+   sums and the views' loss scales) in a fixed array of the library instead
+   of the scene's buffers.  Allocates nothing and calls no allocating routine;
+   the array (64 KiB, 16384 floats, one copy per device, held until the
+   process ends) is looked up by hr_scene_create.  Limit: 2 * chunks + views
+   <= 16384 floats, chunks = sum over views of ceil(W*H / 4096) (about 33 M
+   pixels in total); larger scenes get HR_EUNSUPPORTED and nothing is
+   enqueued.  Every call on a device shares that device's array, which keeps
+   the last call's values: calls that overlap on one device (concurrent
+   streams, other host threads) race and must be ordered by the caller.
+   Arguments and errors as hr_loss. */
+int hr_loss_noalloc(hr_scene* scene, const float* image, const float* target, const uint8_t* mask,
+                    float* loss, float* dimage, void* stream);
+
 /* Gradient of L = sum_p dimage[p] . image[p] (with the samples of hr_render
    at the same iter) with respect to the hand parameters and the colour map.
    flags: HR_GRAD_* terms to include, plus HR_REUSE_GEOMETRY and HR_SKIP_PRIOR.

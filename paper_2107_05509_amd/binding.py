@@ -23,7 +23,7 @@ HR_REUSE_GEOMETRY = 4
 HR_SKIP_PRIOR = 8
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
-           "hr_loss", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
+           "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
            "hr_graph_destroy", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
@@ -98,6 +98,7 @@ def lib():
         L.hr_skin.argtypes = [vp, vp, vp, vp, vp]
         L.hr_render.argtypes = [vp, vp, vp, vp, u32, vp, vp, vp]
         L.hr_loss.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.hr_loss_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.hr_backward.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, vp, vp, vp, vp, vp]
         L.hr_set_joint_prior.argtypes = [vp, vp, ctypes.c_float, ctypes.c_float]
         L.hr_face_visibility.argtypes = [vp, vp, vp, vp]
@@ -127,7 +128,7 @@ def lib():
         L.hr_timing_enable.argtypes = [vp, i32]
         L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
         L.hr_last_error.restype = ctypes.c_char_p
-        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_backward", "hr_set_joint_prior",
+        for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior",
                      "hr_face_visibility", "hr_camera_order",
                      "hr_step", "hr_iterate",
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats",
@@ -243,6 +244,14 @@ class Scene:
                              _ptr(mask, torch.uint8, (self.P,), "mask"),
                              _ptr(loss, shape=(self.n_hands,), name="loss"),
                              _ptr(dimage, shape=(self.P, 3), name="dimage"), _stream()), "hr_loss")
+
+    def loss_noalloc(self, image, target, mask, loss, dimage):
+        """hr_loss with its scratch in the library's fixed array (allocates nothing)."""
+        _check(lib().hr_loss_noalloc(self._h, _ptr(image, shape=(self.P, 3), name="image"),
+                                     _ptr(target, shape=(self.P, 3), name="target"),
+                                     _ptr(mask, torch.uint8, (self.P,), "mask"),
+                                     _ptr(loss, shape=(self.n_hands,), name="loss"),
+                                     _ptr(dimage, shape=(self.P, 3), name="dimage"), _stream()), "hr_loss_noalloc")
 
     def backward(self, params, verts, albedo, background, dimage, it, grad_params, grad_albedo,
                  grad_verts=None, grad_normals=None, flags=HR_GRAD_ALL):

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -50,6 +51,39 @@ int dev_upload(T** dst, const T* src, size_t n)
         e = hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail(HR_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
     }
+    return HR_OK;
+}
+
+}  // namespace
+
+// Scratch of hr_loss_noalloc (chunk partial sums, then the views' loss
+// scales): a fixed array of the library, one copy per device, held until the
+// process ends.  Host code reaches a device's copy only through the address
+// hipGetSymbolAddress returns on that device (the symbol's name is a host
+// stand-in, not a device address).
+constexpr int kScratchFloats = 1 << 14;   // 64 KiB
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices] = {};
+
+// this device's copy of `scratch`, looked up once per device (with `dev` current)
+int scratch_address(int dev, float** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return fail(HR_EUNSUPPORTED, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HR_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
     return HR_OK;
 }
 
@@ -281,6 +315,10 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     (void)hipGetDevice(&s->device);
     int rc = HR_OK;
 #define TRY(x) do { rc = (x); if (rc != HR_OK) { hr_scene_destroy(s); return rc; } } while (0)
+    {
+        float* sp;   // hr_loss_noalloc's scratch on this device (looked up here, once per device)
+        TRY(scratch_address(s->device, &sp));
+    }
     // mesh tables
     MeshDev& md = s->mesh;
     md.V = V; md.F = F; md.J = J; md.K = K; md.E = E;
@@ -760,6 +798,31 @@ int hr_loss(hr_scene* s, const float* image, const float* target, const uint8_t*
 {
     if (!s || !image || !target || !loss || !dimage) return fail(HR_EINVAL, "hr_loss: null argument");
     return loss_impl(s, image, target, mask, loss, dimage, (hipStream_t)stream);
+}
+
+int hr_loss_noalloc(hr_scene* s, const float* image, const float* target, const uint8_t* mask, float* loss,
+                    float* dimage, void* stream)
+{
+    if (!s || !image || !target || !loss || !dimage) return fail(HR_EINVAL, "hr_loss_noalloc: null argument");
+    const long long need = 2LL * s->n_chunks + s->n_views;
+    if (need > kScratchFloats)
+        return fail(HR_EUNSUPPORTED,
+                    "hr_loss_noalloc: the scene needs %lld scratch floats (%d chunks of %d pixels, %d views), "
+                    "the fixed array holds %d", need, s->n_chunks, kLossChunk, s->n_views, kScratchFloats);
+    float* sp = nullptr;
+    const int rc = scratch_address(s->device, &sp);   // set at scene creation: a table read
+    if (rc) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    LossArgs a;
+    a.chunks = s->chunks; a.views = s->views; a.image = image; a.target = target; a.mask = mask;
+    a.partial = sp; a.view_chunk_off = s->view_chunk_off; a.hand_view_off = s->hand_view_off;
+    a.hand_views = s->hand_views; a.view_scale = sp + 2 * (size_t)s->n_chunks; a.loss = loss; a.dimage = dimage;
+    a.n_hands = s->n_hands;
+    // every value is written before it is read (partials, then scales): nothing to clear
+    hipLaunchKernelGGL(k_loss_partial, dim3(s->n_chunks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_loss_final, dim3(s->n_hands), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_loss_grad, dim3(s->n_chunks), dim3(256), 0, st, a);
+    return check_launch("hr_loss_noalloc");
 }
 
 static int fill(hr_scene* s, float* p, long long n, float v, hipStream_t st)
