@@ -292,6 +292,20 @@ void hr_graph_destroy(hr_graph* graph);
    Synchronises `stream`; not for use under graph capture.  Graphs created
    before a change keep the grids they were captured with. */
 int hr_set_grid(hr_scene* scene, int32_t render_blocks, int32_t adjoint_blocks);
+
+/* Acceleration of the camera rays (speed only: hits and images are identical
+   either way).  HR_ACCEL_AUTO (default): per-view screen bins of 16 x 16
+   pixels list the triangles whose padded screen bounds touch them (camera
+   rays all start at the camera centre), with the bounding-volume hierarchy
+   for views where binning does not apply (a vertex within 1 mm of the camera
+   plane, more than 8192 bins, more than 16 F entries) and for the edge
+   samples' side rays; HR_ACCEL_HIERARCHY: the hierarchy for every ray.  Takes
+   effect with the next preparation (hr_render, hr_backward without
+   HR_REUSE_GEOMETRY, hr_iterate); graphs keep the mode they were captured
+   with.  HR_EINVAL: unknown mode. */
+#define HR_ACCEL_AUTO 0
+#define HR_ACCEL_HIERARCHY 1
+int hr_set_accel(hr_scene* scene, int32_t mode);
 int hr_get_grid(const hr_scene* scene, int32_t* blocks_host);   /* (render, adjoint) */
 int hr_tune(hr_scene* scene, const hr_state* state, int32_t reps, int32_t* blocks_host, void* stream);
 

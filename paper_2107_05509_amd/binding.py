@@ -21,10 +21,12 @@ HR_GRAD_EDGES = 2
 HR_GRAD_ALL = 3
 HR_REUSE_GEOMETRY = 4
 HR_SKIP_PRIOR = 8
+HR_ACCEL_AUTO = 0
+HR_ACCEL_HIERARCHY = 1
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
            "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
-           "hr_graph_destroy", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
+           "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
            "hr_last_error")
@@ -111,6 +113,7 @@ def lib():
         L.hr_graph_destroy.argtypes = [vp]
         L.hr_graph_destroy.restype = None
         L.hr_set_grid.argtypes = [vp, i32, i32]
+        L.hr_set_accel.argtypes = [vp, i32]
         L.hr_get_grid.argtypes = [vp, vp]
         L.hr_tune.argtypes = [vp, ctypes.POINTER(State), i32, vp, vp]
         L.hr_proposal_set.argtypes = [vp, ctypes.POINTER(ProposalConfig), vp]
@@ -131,7 +134,7 @@ def lib():
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior",
                      "hr_face_visibility", "hr_camera_order",
                      "hr_step", "hr_iterate",
-                     "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_get_grid", "hr_tune", "hr_edge_stats",
+                     "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_set_accel", "hr_get_grid", "hr_tune", "hr_edge_stats",
                      "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
                      "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
                      "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit"):
@@ -313,6 +316,10 @@ class Scene:
 
     def set_grid(self, render_blocks=0, adjoint_blocks=0):
         _check(lib().hr_set_grid(self._h, int(render_blocks), int(adjoint_blocks)), "hr_set_grid")
+
+    def set_accel(self, mode):
+        """HR_ACCEL_AUTO (screen bins for the camera rays) or HR_ACCEL_HIERARCHY."""
+        _check(lib().hr_set_accel(self._h, int(mode)), "hr_set_accel")
 
     def grids(self):
         """(render blocks, adjoint blocks) of the persistent ray-tracing grids."""

@@ -106,6 +106,9 @@ struct hr_scene {
     uint64_t* hit_rec = nullptr;  // [tile_cap, rounds, 64] samples of the last render (random word, leaf slot)
     int* hit_iter = nullptr;      // iteration of those hits (-1: none)
     int4* view_rect = nullptr;    // [n_views] pixel rectangle of each view's tiles (screen-bounds pass)
+    BinDev bins{};                // screen bins of the camera rays (built by the preparation launch)
+    int n_bins = 0;
+    int accel = HR_ACCEL_AUTO;
     long long tile_cap = 0;
     int* tile_count = nullptr;
     int render_blocks = 0;        // persistent grids of the ray-tracing kernels (hr_tune)
@@ -467,6 +470,9 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
             d.W = c.W; d.H = c.H; d.hand = c.hand;
             d.sid = cfg->view_base + (uint32_t)v;
+            d.bin0 = s->n_bins;
+            d.nbx = (c.W + (1 << kBinLog2) - 1) >> kBinLog2;
+            s->n_bins += d.nbx * ((c.H + (1 << kBinLog2) - 1) >> kBinLog2);
             d.pix0 = pix;
             s->tile_cap += (long long)((c.W + (1 << ts.tw_log2) - 1) >> ts.tw_log2) *
                            ((c.H + (1 << ts.th_log2) - 1) >> ts.th_log2);
@@ -498,6 +504,19 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     TRY(s->upload<uint64_t>(&s->hit_rec, nullptr, (size_t)s->tile_cap * s->ts.rounds * 64));
     TRY(s->upload<int>(&s->hit_iter, nullptr, 1));
     TRY(s->upload<int4>(&s->view_rect, nullptr, (size_t)n_views));
+    {   // screen bins: entries for each triangle in up to 16 bins per view on average
+        BinDev& bd = s->bins;
+        bd.cap = 16 * F;
+        TRY(s->upload<int>(&bd.count, nullptr, (size_t)s->n_bins));
+        TRY(s->upload<int>(&bd.off, nullptr, (size_t)s->n_bins));
+        TRY(s->upload<uint16_t>(&bd.entries, nullptr, (size_t)n_views * bd.cap));
+        TRY(s->upload<float4>(&bd.box, nullptr, (size_t)n_views * F));
+        TRY(s->upload<int>(&bd.binned, nullptr, (size_t)n_views));
+        if (hipMemset(bd.binned, 0, sizeof(int) * n_views) != hipSuccess) {
+            hr_scene_destroy(s);
+            return fail(HR_EHIP, "scene init: memset");
+        }
+    }
 
     if (hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess) {
         hr_scene_destroy(s);
@@ -564,6 +583,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     // silhouette-table blocks: scan buffer, edge table, vertices, edge weights
     s->smem_prepare = std::max(s->smem_prepare, sizeof(unsigned long long) * 16 + sizeof(int) * 8 * E +
                                                     sizeof(float) * 3 * V + sizeof(uint32_t) * E);
+    // bin blocks: projected vertices, two counters per (bin, depth band) cell
+    s->smem_prepare = std::max(s->smem_prepare, sizeof(float) * 3 * V + sizeof(int) * 2 * kMaxBinCells);
     if (hipFuncSetAttribute((const void*)k_prepare, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)s->smem_prepare) != hipSuccess) {
         hr_scene_destroy(s);
@@ -621,8 +642,10 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_t
     a.e = edge_args(s, verts, nullptr, nullptr, nullptr, 0, nullptr);
     a.views = s->views; a.ts = s->ts; a.tiles = s->tiles; a.tile_count = s->tile_count; a.view_rect = s->view_rect;
     a.mask = mask; a.view_scale = s->view_scale; a.setup_done = s->setup_done;
+    a.bins = s->bins;
+    a.with_bins = s->accel == HR_ACCEL_AUTO ? 1 : 0;
     a.n_hands = s->n_hands; a.n_views = s->n_views; a.with_setup = 1; a.with_scale = with_scale;
-    const dim3 grid(2 * s->n_hands + (2 + (with_scale ? 1 : 0)) * s->n_views);
+    const dim3 grid(2 * s->n_hands + (3 + (with_scale ? 1 : 0)) * s->n_views);
     return launch(s, "k_prepare", k_prepare, grid, dim3(512), s->smem_prepare, st, a);
 }
 
@@ -668,6 +691,7 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w; a.spp = s->cfg.spp;
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
+    a.bins = s->bins;
     const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
     const dim3 grid(s->render_blocks);
     const int with_edges = n_edge > 0 ? 1 : 0;
@@ -1165,6 +1189,14 @@ int hr_set_grid(hr_scene* s, int32_t render_blocks, int32_t adjoint_blocks)
     if (render_blocks < 0 || adjoint_blocks < 0) return fail(HR_EINVAL, "hr_set_grid: negative block count");
     if (render_blocks) s->render_blocks = std::min(render_blocks, s->max_blocks);
     if (adjoint_blocks) s->adjoint_blocks = std::min(adjoint_blocks, s->max_blocks);
+    return HR_OK;
+}
+
+int hr_set_accel(hr_scene* s, int32_t mode)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_accel: null scene");
+    if (mode != HR_ACCEL_AUTO && mode != HR_ACCEL_HIERARCHY) return fail(HR_EINVAL, "hr_set_accel: unknown mode %d", mode);
+    s->accel = mode;
     return HR_OK;
 }
 

@@ -36,8 +36,14 @@ struct ViewDev {            // one camera (see hr_camera)
     float fx, fy, cx, cy;
     int W, H, hand;
     uint32_t sid;           // sample-stream id (Philox counter word of the view)
+    int bin0, nbx;          // first screen bin of the view in the scene's bin arrays, bins per row
     long long pix0;         // first pixel in packed buffers
 };
+
+constexpr int kBinLog2 = 4;         // screen bins of 16 x 16 pixels (wave tiles never straddle one)
+constexpr int kMaxBinsLds = 8192;   // bins of a view counted in LDS (larger views traverse the hierarchy)
+constexpr int kMaxBands = 16;       // depth bands per bin (fewer for views with many bins)
+constexpr int kMaxBinCells = 8192;  // (bin, band) cells counted in LDS
 // A view's record through the scalar cache (views are never written by a
 // launch; the index must be wave-uniform).
 __device__ __forceinline__ ViewDev load_view(const ViewDev* views, int i)
@@ -484,6 +490,88 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
             --sp;
             node = __builtin_amdgcn_readfirstlane(wstack[sp]);
             if (COUNT) need = mstack[threadIdx.x >> 6][sp];
+        }
+    }
+}
+
+// Closest hits of the camera rays of one wave tile from its screen bin: `ent`
+// lists `cnt` leaf slots, `box` holds each slot's padded screen bounds, and
+// the tile's rays pass through screen points in [x0, x1] x [y0, y1].  Every
+// triangle that a ray of the tile can hit is listed and touches that
+// rectangle, and the closest hit is the minimum of (t, face id) over them:
+// the result equals a brute-force loop over all triangles.  Before its
+// watertight test a triangle is skipped by the wave when no lane can find
+// it nearer than its best hit so far: the test computes t as a weighted mean
+// of the three vertices' (v[kz] - o[kz]) Sz with non-negative weights, so t
+// is at least their minimum, which is computed here with the same rounding
+// (times 1 - 1e-6 for the rounding of the mean); a skip therefore never
+// drops a hit at or before the lane's best, ties included.  The lanes that
+// call it share the list (each loads every n-th entry, n = the calling
+// lanes); `active` selects the lanes whose rays are traced.
+template <bool COUNT = false>
+__device__ __forceinline__ void trace_bins(const Tri* __restrict__ tris, const uint16_t* __restrict__ ent, int cnt,
+                                           const float4* __restrict__ box, float x0, float y0, float x1, float y1,
+                                           const Ray& r, bool active, Hit& h, TraceCount* tc = nullptr)
+{
+    h.face = -1;
+    h.slot = 0;
+    h.t = 0.0f;
+    float tb = active ? __builtin_inff() : -__builtin_inff();
+    int fb = 0x7fffffff;
+    tris = uniform_ptr(tris);
+    // the calling lanes load the list together: lane of rank k takes entries
+    // c0 + k, c0 advancing by their number
+    const uint64_t exec = wave_mask(true);
+    const int ncall = __popcll(exec);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(exec >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)exec, 0u));
+    const float okz = comp(r.o, r.kz);
+    // lane-parallel loads of a chunk of entries: each lane fetches its
+    // entry's bounds and triangle at once (no dependent fetch per triangle),
+    // the loop then broadcasts the touching ones lane by lane
+    for (int c0 = 0; c0 < cnt; c0 += ncall) {
+        int slot = 0;
+        bool touch = false;
+        float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0, q2 = q0;
+        if (c0 + rank < cnt) {
+            slot = ent[c0 + rank];
+            const Tri& tr = tris[slot];
+            q0 = *reinterpret_cast<const float4*>(&tr.v[0]);
+            q1 = *reinterpret_cast<const float4*>(&tr.v[4]);
+            q2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+            const float4 b = box[slot];
+            touch = b.x <= x1 && b.z >= x0 && b.y <= y1 && b.w >= y0;
+        }
+        uint64_t m = wave_mask(touch);
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const int s = __builtin_amdgcn_readlane(slot, l);
+            auto rl = [l](float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); };
+            const float v0[3] = {rl(q0.x), rl(q0.y), rl(q0.z)};
+            const float v1[3] = {rl(q0.w), rl(q1.x), rl(q1.y)};
+            const float v2[3] = {rl(q1.z), rl(q1.w), rl(q2.x)};
+            const int face = __builtin_amdgcn_readlane(__float_as_int(q2.y), l);
+            const float a0 = comp(v0, r.kz), a1 = comp(v1, r.kz), a2 = comp(v2, r.kz);
+            const float near = r.Sz > 0.0f ? fminf(fminf(a0, a1), a2) : fmaxf(fmaxf(a0, a1), a2);
+            const float bound = r.Sz * (near - okz);
+            const bool need = active && !(bound * (1.0f - 1e-6f) > tb);
+            if (COUNT && active) { tc->nodes++; tc->nodes_w++; }
+            const uint64_t mn = wave_mask(need);
+            if (mn == 0) continue;
+            if (COUNT) {
+                if (need) tc->tris++;
+                if (active) tc->tris_w++;
+            }
+            float t, U, V, W, det;
+            if (watertight(r, v0, v1, v2, t, U, V, W, det)) {
+                if (t < tb || (t == tb && face < fb)) {
+                    tb = t; fb = face;
+                    h.face = face;
+                    h.slot = s;
+                    h.t = t;
+                }
+            }
         }
     }
 }

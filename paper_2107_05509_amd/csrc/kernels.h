@@ -54,6 +54,20 @@ struct BvhDev {
     const int* slot_verts;     // [H, F, 3] vertex ids of each leaf slot's triangle
 };
 
+// Per-view screen bins of the camera rays: each 16 x 16-pixel bin lists the
+// leaf slots of the triangles whose padded screen bounds touch it.  Camera
+// rays all start at the camera centre, so a ray through a screen point can
+// only hit triangles listed in that point's bin: the lists replace the
+// hierarchy for them (views whose bins are incomplete keep the hierarchy).
+struct BinDev {
+    int* count;                // [bins of all views] triangles listed per bin
+    int* off;                  // [bins of all views] first entry of the bin in its view's entries
+    uint16_t* entries;         // [n_views, cap] leaf slots, bin after bin
+    float4* box;               // [n_views, F] padded screen bounds (x0, y0, x1, y1) per leaf slot
+    int* binned;               // [n_views] 1: the view's bins are complete and valid
+    int cap;                   // entries per view
+};
+
 // wave tiles: a tile of 2^tw_log2 x 2^th_log2 pixels, 2^spp_log2 lanes per
 // pixel (64 lanes per wave); spp > 64 takes `rounds` passes of 64 samples
 struct TileShape {
@@ -86,6 +100,7 @@ struct RenderArgs {
     const float* view_scale;   // [n_views] 1 / (3 * masked pixels), with dimage
     unsigned long long* counts;   // [6] counting variant: rays traced, node visits, triangle tests, hits,
                                   // packet node visits and packet triangle tests (TraceCount)
+    BinDev bins;               // screen bins of the camera rays
     int n_nodes, n_faces, n_verts, tex_h, tex_w, spp;
     uint32_t iter;
     const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`
@@ -204,6 +219,8 @@ struct PrepArgs {
     const uint8_t* mask;       // with_scale (nullable: all pixels)
     float* view_scale;
     int* setup_done;           // with_setup: finished silhouette tables (zero between launches)
+    BinDev bins;               // the views' screen bins (built every launch)
+    int with_bins;             // 0: every view marked unbinned (hierarchy only)
     int n_hands, n_views, with_setup, with_scale;
 };
 

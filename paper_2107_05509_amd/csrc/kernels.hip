@@ -323,18 +323,31 @@ __device__ void joint_state64(const MeshDev& m, const float* __restrict__ p, Joi
     const int J = m.J, K = m.K;
     const int j = threadIdx.x;
     if (j < 64) {
-        double bk[kMaxShape];
-#pragma unroll
-        for (int k = 0; k < kMaxShape; ++k) bk[k] = k < K ? (double)p[48 + k] : 0.0;
+        // every load first, with clamped indices (one round trip to memory)
+        float bkf[kMaxShape];
+        load_beta(m, p + 48, bkf);
         const int dj = j < J ? m.jdepth[j] : -1, par = j < J ? m.parents[j] : -1;
         const int jr = j < J ? j : J;
         const float* pr = j < J ? p + 3 * j : p + 58;
         const double r[3] = {(double)pr[0], (double)pr[1], (double)pr[2]};
+        const int jj = j < J ? j : J - 1;
+        double jt[3], jsd[3][kMaxShape];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            jt[c] = m.jt64[3 * jj + c];
+#pragma unroll
+            for (int k = 0; k < kMaxShape; ++k) {
+                const double d = K > 0 ? m.js64[(3 * jj + c) * K + (k < K ? k : K - 1)] : 0.0;
+                jsd[c][k] = k < K ? d : 0.0;
+            }
+        }
         if (j <= J) rodrigues64(r, js.rod[jr]);
         if (j < J)
             for (int c = 0; c < 3; ++c) {
-                double x = m.jt64[3 * j + c];
-                for (int k = 0; k < K; ++k) x += m.js64[(3 * j + c) * K + k] * bk[k];
+                double x = jt[c];
+#pragma unroll
+                for (int k = 0; k < kMaxShape; ++k)
+                    if (k < K) x += jsd[c][k] * (double)bkf[k];
                 js.J[3 * j + c] = x;
             }
         wave_lds_sync();
@@ -375,12 +388,14 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     // the vertex's tables first: their loads are in flight with the joint
     // state's
-    float tpl[3] = {0.0f, 0.0f, 0.0f}, sd[3][kMaxShape] = {}, wq[kMaxInfl] = {};
+    float tpl[3] = {0.0f, 0.0f, 0.0f}, sd[3][kMaxShape] = {}, wq[kMaxInfl] = {}, bk[kMaxShape];
     int jq[kMaxInfl] = {};
     if (v < m.V) {
         load_weights(m, v, wq, jq);
         load_shape(m, v, tpl, sd);
     }
+    load_beta(m, p + 48, bk);
+    const float tau[3] = {p[61], p[62], p[63]};
     joint_state64(m, p, js);
     // nullable: the joint state of these parameters for the backward (float32)
     if (js_out && blockIdx.x == 0) {
@@ -388,12 +403,13 @@ __global__ void __launch_bounds__(128) k_skin(MeshDev m, const float* __restrict
         for (int i = threadIdx.x; i < kJointStateFloats; i += blockDim.x)
             js_out[(size_t)h * kJointStateFloats + i] = (float)src[i];
     }
-    const float* tau = p + 61;
     if (v < m.V) {
         double x[3], vp[3] = {0.0, 0.0, 0.0}, y[3];
         for (int c = 0; c < 3; ++c) {
             double sv = (double)tpl[c];
-            for (int k = 0; k < m.K; ++k) sv += (double)sd[c][k] * (double)p[48 + k];
+#pragma unroll
+            for (int k = 0; k < kMaxShape; ++k)
+                if (k < m.K) sv += (double)sd[c][k] * (double)bk[k];
             x[c] = sv;
         }
 #pragma unroll
@@ -608,6 +624,145 @@ __device__ void view_bounds(const MeshDev& m, const ViewDev* __restrict__ views,
         tiles[base + i] = make_int2(vi, (tx0 + i % nx) | ((ty0 + i / nx) << 16));
 }
 
+// Inclusive prefix sum over the block (blockDim a multiple of 64, at most
+// 1024); `wtot` is LDS [16].  Every thread of the block must call it.
+__device__ __forceinline__ unsigned long long block_scan_u64(unsigned long long x, unsigned long long* wtot)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    unsigned long long off = 0;
+    for (int k = 0; k < w; ++k) off += wtot[k];
+    __syncthreads();
+    return x + off;
+}
+
+// Screen bins of view vi (one block, LDS `dyn`: the projected vertices, two
+// counters per cell).  Every leaf slot's triangle gets padded screen bounds;
+// triangles whose bounds touch the image are listed in every bin they touch.
+// A bin's list runs from near to far in depth bands (the triangle's nearest
+// vertex, bands spanning the hand's depth range in this view; inside a band
+// the order is arbitrary), so a ray usually meets its hit early and skips the
+// triangles behind it.  Lists are counted per (bin, band) cell, scanned, then
+// filled by LDS cursors.  A view with a vertex less than 1 mm in front of the
+// camera, more than kMaxBinsLds bins or more entries than the capacity is
+// marked unbinned: its camera rays traverse the hierarchy.
+__device__ void bin_view(const PrepArgs& a, int vi, float* dyn)
+{
+    __shared__ int bad;
+    __shared__ float zred[2 * 16];
+    __shared__ unsigned long long wtot[16];
+    const ViewDev c = load_view(a.views, vi);
+    const int V = a.m.V, F = a.m.F;
+    const int nbx = c.nbx, nby = (c.H + (1 << kBinLog2) - 1) >> kBinLog2, nb = nbx * nby;
+    if (nb > kMaxBinsLds || !a.with_bins) {   // uniform over the block
+        if (threadIdx.x == 0) a.bins.binned[vi] = 0;
+        return;
+    }
+    int nband = kMaxBands;
+    while (nband > 1 && nb * nband > kMaxBinCells) nband >>= 1;
+    const int ncell = nb * nband;
+    float* pxy = dyn;                                   // [V][3] px, py (screen), camera depth
+    int* cnt = reinterpret_cast<int*>(pxy + 3 * V);     // [ncell] bin-major, band-minor
+    int* cur = cnt + ncell;                             // [ncell]
+    for (int k = threadIdx.x; k < ncell; k += blockDim.x) cnt[k] = 0;
+    const float* vg = a.verts + (size_t)c.hand * V * 3;
+    int my_bad = 0;
+    float zlo = 3e38f, zhi = -3e38f;
+    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+        const float q0 = vg[3 * v] - c.o[0], q1 = vg[3 * v + 1] - c.o[1], q2 = vg[3 * v + 2] - c.o[2];
+        const float xc = (c.R[0] * q0 + c.R[1] * q1) + c.R[2] * q2;
+        const float yc = (c.R[3] * q0 + c.R[4] * q1) + c.R[5] * q2;
+        const float zc = (c.R[6] * q0 + c.R[7] * q1) + c.R[8] * q2;
+        if (!(zc > 1e-3f)) my_bad = 1;
+        pxy[3 * v] = (c.fx * xc) / zc + c.cx;
+        pxy[3 * v + 1] = (c.fy * yc) / zc + c.cy;
+        pxy[3 * v + 2] = zc;
+        zlo = fminf(zlo, zc);
+        zhi = fmaxf(zhi, zc);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        zlo = fminf(zlo, __shfl_xor(zlo, o));
+        zhi = fmaxf(zhi, __shfl_xor(zhi, o));
+    }
+    if ((threadIdx.x & 63) == 0) { zred[2 * (threadIdx.x >> 6)] = zlo; zred[2 * (threadIdx.x >> 6) + 1] = zhi; }
+    if (__syncthreads_or(my_bad)) {
+        if (threadIdx.x == 0) a.bins.binned[vi] = 0;
+        return;
+    }
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { zlo = fminf(zlo, zred[2 * k]); zhi = fmaxf(zhi, zred[2 * k + 1]); }
+    const float zscale = (float)nband / fmaxf(zhi - zlo, 1e-6f);
+    // padded bounds: far beyond the float32 rounding of the projections and
+    // of the ray test (below 1e-3 px), and beyond the largest rounding of a
+    // sample point onto a pixel's far edge
+    const float pad = 1.0f / 16.0f;
+    const int* sv = a.b.slot_verts + (size_t)c.hand * F * 3;
+    float4* box = a.bins.box + (size_t)vi * F;
+    auto bounds = [&](int i, float4& bx, int& x0, int& y0, int& x1, int& y1, int& band) -> bool {
+        const float* p0 = pxy + 3 * sv[3 * i];
+        const float* p1 = pxy + 3 * sv[3 * i + 1];
+        const float* p2 = pxy + 3 * sv[3 * i + 2];
+        bx.x = fminf(fminf(p0[0], p1[0]), p2[0]) - pad;
+        bx.y = fminf(fminf(p0[1], p1[1]), p2[1]) - pad;
+        bx.z = fmaxf(fmaxf(p0[0], p1[0]), p2[0]) + pad;
+        bx.w = fmaxf(fmaxf(p0[1], p1[1]), p2[1]) + pad;
+        band = min(nband - 1, max(0, (int)((fminf(fminf(p0[2], p1[2]), p2[2]) - zlo) * zscale)));
+        if (bx.z < 0.0f || bx.w < 0.0f || bx.x > (float)c.W || bx.y > (float)c.H) return false;
+        x0 = max(0, (int)floorf(bx.x)) >> kBinLog2;
+        y0 = max(0, (int)floorf(bx.y)) >> kBinLog2;
+        x1 = min(c.W - 1, (int)floorf(bx.z)) >> kBinLog2;
+        y1 = min(c.H - 1, (int)floorf(bx.w)) >> kBinLog2;
+        return true;
+    };
+    for (int i = threadIdx.x; i < F; i += blockDim.x) {
+        float4 bx;
+        int x0, y0, x1, y1, band;
+        const bool in = bounds(i, bx, x0, y0, x1, y1, band);
+        box[i] = bx;
+        if (!in) continue;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) atomicAdd(cnt + (y * nbx + x) * nband + band, 1);
+    }
+    __syncthreads();
+    // exclusive offsets of the cells: contiguous runs per thread, block scan of the runs
+    const int per = (ncell + blockDim.x - 1) / blockDim.x;
+    const int k0 = min(ncell, (int)threadIdx.x * per), k1 = min(ncell, k0 + per);
+    unsigned long long local = 0;
+    for (int k = k0; k < k1; ++k) local += (unsigned long long)cnt[k];
+    const unsigned long long incl = block_scan_u64(local, wtot);
+    unsigned long long run = incl - local;
+    for (int k = k0; k < k1; ++k) {
+        cur[k] = (int)run;
+        run += (unsigned long long)cnt[k];
+    }
+    if (threadIdx.x == blockDim.x - 1) bad = incl > (unsigned long long)a.bins.cap;
+    __syncthreads();
+    if (bad) {
+        if (threadIdx.x == 0) a.bins.binned[vi] = 0;
+        return;
+    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int first = cur[b * nband];
+        const int last = cur[(b + 1) * nband - 1] + cnt[(b + 1) * nband - 1];
+        a.bins.off[c.bin0 + b] = first;
+        a.bins.count[c.bin0 + b] = last - first;
+    }
+    __syncthreads();   // the offsets are read before the cursors move
+    uint16_t* ent = a.bins.entries + (size_t)vi * a.bins.cap;
+    for (int i = threadIdx.x; i < F; i += blockDim.x) {
+        float4 bx;
+        int x0, y0, x1, y1, band;
+        if (!bounds(i, bx, x0, y0, x1, y1, band)) continue;
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) ent[atomicAdd(cur + (y * nbx + x) * nband + band, 1)] = (uint16_t)i;
+    }
+    if (threadIdx.x == 0) a.bins.binned[vi] = 1;
+}
+
 // number of non-zero bytes of a 16-byte word: bit 7 of each byte of
 // ((w & 0x7F..) + 0x7F..) | w is set exactly when that byte is non-zero
 __device__ __forceinline__ int nonzero_bytes(uint4 q)
@@ -761,6 +916,21 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
         const float* normals = a.normals + (size_t)c.hand * a.n_verts * 3;
         const float* tex = a.albedo + (size_t)c.hand * a.tex_h * a.tex_w * 3;
         const uint64_t c2 = (uint64_t)c.sid | (kDomainCamera << 32);
+        // the tile's screen bin (all wave-uniform): an empty bin means every
+        // sample of the tile misses, without a ray
+        const int tx0 = (e.y & 0xffff) << a.ts.tw_log2, ty0 = (e.y >> 16) << a.ts.th_log2;
+        const bool binned = __builtin_amdgcn_readfirstlane(a.bins.binned[e.x]) != 0;
+        int bcnt = 0;
+        const uint16_t* bent = nullptr;
+        if (binned) {
+            const int bb = c.bin0 + (tx0 >> kBinLog2) + (ty0 >> kBinLog2) * c.nbx;
+            bcnt = __builtin_amdgcn_readfirstlane(a.bins.count[bb]);
+            bent = a.bins.entries + (size_t)e.x * a.bins.cap + __builtin_amdgcn_readfirstlane(a.bins.off[bb]);
+        }
+        const bool empty = binned && bcnt == 0;
+        const float4* bbox = a.bins.box + (size_t)e.x * a.n_faces;
+        const float rx0 = (float)tx0, ry0 = (float)ty0;
+        const float rx1 = (float)(tx0 + (1 << a.ts.tw_log2)), ry1 = (float)(ty0 + (1 << a.ts.th_log2));
         float acc[3] = {0.0f, 0.0f, 0.0f};
         int misses = 0;
         for (int r = 0; r < a.ts.rounds; ++r) {
@@ -768,18 +938,25 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             const bool act = pix_ok && s < a.spp;
             float u = 0.0f, v = 0.0f;
             uint64_t wd = 0;
-            if (act) {
+            if (act && !empty) {
                 const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
                 wd = pick(rr, s & 3);
                 u = u24_lo(wd);
                 v = u24_hi(wd);
             }
-            Ray ray;
-            ray_screen(c, (float)px + u, (float)py + v, ray);
             Hit h;
-            trace_wave<COUNT, true>(nodes, tris, ray, act, wst, h, &tc);
+            h.face = -1;
+            h.slot = 0;
+            if (!empty) {
+                Ray ray;
+                ray_screen(c, (float)px + u, (float)py + v, ray);
+                if (binned)
+                    trace_bins<COUNT>(tris, bent, bcnt, bbox, rx0, ry0, rx1, ry1, ray, act, h, &tc);
+                else
+                    trace_wave<COUNT, true>(nodes, tris, ray, act, wst, h, &tc);
+            }
             if (act) {
-                if (COUNT) ++n_rays;
+                if (COUNT && !empty) ++n_rays;
                 if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
                 if (a.hit_rec) a.hit_rec[((size_t)t * a.ts.rounds + r) * 64 + lane] = hit_record(wd, h.face >= 0 ? h.slot : -1);
                 if (h.face >= 0) {
@@ -1221,23 +1398,6 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
 // silhouette edges: classification, quantised weights, prefix sums
 // ===========================================================================
 
-// Inclusive prefix sum over the block (blockDim a multiple of 64, at most
-// 1024); `wtot` is LDS [16].  Every thread of the block must call it.
-__device__ __forceinline__ unsigned long long block_scan_u64(unsigned long long x, unsigned long long* wtot)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wtot[w] = x;
-    __syncthreads();
-    unsigned long long off = 0;
-    for (int k = 0; k < w; ++k) off += wtot[k];
-    __syncthreads();
-    return x + off;
-}
-
 // Exclusive prefix of the views' edge-sample budgets, prefix[n_views] the
 // total (one block; budgets read past the L1, since other blocks of the same
 // launch may have written them).
@@ -1371,7 +1531,7 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
 // Geometry preparation in one launch: blocks [0, H) refit hand h (triangles
 // in leaf order, hierarchy bounds), blocks [H, 2H) its vertex normals; then per view the
 // silhouette table (with_setup; the last one also the budget prefix), the screen bounds and wave tiles (the tile
-// count is zero beforehand) and the loss scale from the mask (with_scale).
+// count is zero beforehand), the screen bins and the loss scale from the mask (with_scale).
 __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
 {
     extern __shared__ float dyn[];
@@ -1395,6 +1555,11 @@ __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
     }
     if (bid < a.n_views) {
         view_bounds(a.m, a.views, a.verts, a.ts, a.tiles, a.tile_count, a.view_rect, bid);
+        return;
+    }
+    bid -= a.n_views;
+    if (bid < a.n_views) {
+        bin_view(a, bid, dyn);
         return;
     }
     bid -= a.n_views;
@@ -1523,7 +1688,8 @@ __device__ __forceinline__ void edge_side_colour(const EdgeArgs& a, const EdgePo
     Hit h;
     ray_screen(c, P.xs, P.ys, ray);
     // consecutive samples lie on neighbouring edges of one view: the wave
-    // traverses together unless its lanes look at different hands
+    // traverses together unless its lanes look at different hands (the
+    // side points are spread along silhouettes, over many screen bins)
     if (__all(hand == __builtin_amdgcn_readfirstlane(hand)))
         trace_wave<COUNT>(nodes, tris, ray, true, wst, h, &tc);
     else

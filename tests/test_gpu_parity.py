@@ -210,3 +210,20 @@ def test_hierarchy_topology_does_not_change_results(tiny):
     torch.cuda.synchronize()
     assert np.array_equal(hf.cpu().numpy(), hit0)
     assert np.array_equal(img.cpu().numpy(), img0)
+
+
+@pytest.mark.parametrize("workload", ["tiny", "mixed"])
+def test_screen_bins_match_hierarchy(workload):
+    # camera rays through screen bins (the default) and through the
+    # hierarchy: the same closest hits, hence identical images and records
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"case: {workload} workload, screen bins against the hierarchy", flush=True)
+    c = Case(scene.workload_tiny(0) if workload == "tiny" else scene.workload_mixed(0))
+    out = []
+    for mode in (binding.HR_ACCEL_HIERARCHY, binding.HR_ACCEL_AUTO):
+        c.gsc.set_accel(mode)
+        out.append(c.gpu_render(5, hits=True))
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][0], out[1][0])
+    assert (out[1][1] >= 0).mean() > 0.02
