@@ -381,6 +381,64 @@ int hr_proposal_eval(hr_scene* scene, const float* X, int32_t n, float* z, void*
 int hr_proposal_fit(hr_scene* scene, const float* X, const uint32_t* w, const float* a, int32_t n, float* grad,
                     int32_t apply, void* stream);
 
+/* ---- the paper's full data term ---------------------------------------
+   Eq. 3 compares each observed image O_i with T_i R_i, the rendering under a
+   per-camera 3x3 colour transform T_i (Section 3.1, "Rendering"), through
+   f1 = D_c + D_e of Eq. 4: the L1 colour difference and the L1 difference of
+   edge maps B(Canny(.)), Canny edges blurred by an 11x11 Gaussian of sigma 5
+   (Section 3.1, "Render-and-compare").  Per view:
+     E1_i = mean over masked pixels and channels |O - T R|
+          + w_edge mean over masked pixels |B(Canny(O)) - B(Canny(T R))|.
+   Canny: luma 0.299 R + 0.587 G + 0.114 B, 5x5 Gaussian smoothing (sigma 1),
+   Sobel filters / 8, magnitude sqrt(gx^2 + gy^2 + 1e-6), suppression of
+   pixels below either neighbour along the gradient direction quantised to 0,
+   45, 90, 135 degrees, thresholds low / high on the magnitude, one
+   8-neighbour hysteresis step (a pixel above low is kept next to one above
+   high); Canny(x) = the magnitude at the kept pixels.  Filters read
+   clamped-to-edge pixels of their input.  Computed in float64; the kept set
+   is held fixed in the derivative (it is piecewise constant), which flows
+   through the magnitude.
+
+   hr_data_term_set allocates the buffers on its first call (10 float64
+   values per pixel; synchronises the device) and sets w_edge, low, high.
+   HR_EINVAL: w_edge < 0, not 0 <= low <= high, not finite. */
+typedef struct {
+    float w_edge;        /* weight of D_e (the paper: 1) */
+    float low, high;     /* Canny thresholds on the magnitude (0.1, 0.2) */
+} hr_data_term;
+
+int hr_data_term_set(hr_scene* scene, const hr_data_term* cfg);
+
+/* B(Canny(T image)) of every view: image [P,3], T [n_views,9] row-major
+   (nullable = identity), edge_map [P] out (all DEVICE).  Used once for the
+   observed images.  HR_EINVAL: before hr_data_term_set. */
+int hr_edge_map(hr_scene* scene, const float* image, const float* T, float* edge_map, void* stream);
+
+/* The full data term of each hand (sum over its views of E1_i above) and
+   its gradients: image = R [P,3] (what hr_render returns), T [n_views,9]
+   (nullable = identity), target = O [P,3], target_edges = B(Canny(O)) [P]
+   (from hr_edge_map), mask [P] (nullable = all pixels); loss [n_hands] out,
+   dimage = dE1/dR [P,3] out (hand it to hr_backward), grad_T [n_views,9] out
+   (nullable), edge_map = B(Canny(T R)) [P] out (nullable).  All DEVICE. */
+int hr_loss_full(hr_scene* scene, const float* image, const float* T, const float* target,
+                 const float* target_edges, const uint8_t* mask, float* loss, float* dimage, float* grad_T,
+                 float* edge_map, void* stream);
+
+/* Two-level colour map (Section 3.1, "Colour mapping"): albedo = high +
+   low nearest-upsampled, low [n_hands,L,L,3], high and albedo
+   [n_hands,tex_h,tex_w,3]; hr_albedo_low_grad sums dE/dalbedo over each low
+   texel's block into grad_low [n_hands,L,L,3].  HR_ESHAPE: L does not divide
+   tex_h and tex_w. */
+int hr_compose_albedo(hr_scene* scene, const float* low, int32_t L, const float* high, float* albedo, void* stream);
+int hr_albedo_low_grad(hr_scene* scene, const float* grad_albedo, int32_t L, float* grad_low, void* stream);
+
+/* One Adam step on n float32 values x (gradient g, moments m, v; t >= 1
+   counts steps) with learning rate lr and cfg's betas and epsilon, the
+   result clamped to [lo, hi] (the colour transforms and the low colour map).
+   HR_EINVAL: n < 0, t < 1, lo > hi. */
+int hr_adam(hr_scene* scene, float* x, const float* g, float* m, float* v, int64_t n, int32_t t, float lr,
+            float lo, float hi, const hr_adam_config* cfg, void* stream);
+
 /* Diagnostics of the last backward call on this scene, copied to HOST memory
    after synchronising `stream`: per view the total quantised silhouette
    length (uint64, 1/256 px) and the number of edge samples drawn.

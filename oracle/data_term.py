@@ -105,17 +105,17 @@ def select(gx, gy, M, low=LOW, high=HIGH):
     return strong | (weak & near)
 
 
-def canny(img):
+def canny(img, low=LOW, high=HIGH):
     """Canny(x) of an RGB image [H,W,3]: magnitude at the selected pixels.
     Returns (edges, selection)."""
     gx, gy, M = gradients(grey(img))
-    S = select(gx, gy, M)
+    S = select(gx, gy, M, low, high)
     return np.where(S, M, 0.0), S
 
 
-def edge_map(img):
+def edge_map(img, low=LOW, high=HIGH):
     """B(Canny(x)) [H,W]: the edge map blurred by the 11x11, sigma 5 Gaussian."""
-    e, _ = canny(img)
+    e, _ = canny(img, low, high)
     return correlate(e, gaussian_kernel(BLUR_SIZE, BLUR_SIGMA))
 
 
@@ -142,12 +142,12 @@ def colour_transform(image, T, pix_off):
     return out
 
 
-def edge_maps(image, wh, pix_off):
+def edge_maps(image, wh, pix_off, low=LOW, high=HIGH):
     """B(Canny(view)) of every view, packed [P]."""
     image = np.asarray(image, np.float64)
     out = np.empty(image.shape[0])
     for v, sl, img in _views(image, wh, pix_off, 3):
-        out[sl] = edge_map(img).reshape(-1)
+        out[sl] = edge_map(img, low, high).reshape(-1)
     return out
 
 
@@ -169,7 +169,8 @@ def _edge_term_torch(rp, S, Bo, m, n):
     return (torch.abs(torch.as_tensor(Bo) - B) * torch.as_tensor(m, dtype=torch.float64)).sum() / n
 
 
-def data_term(render, T, target, target_edges, mask, wh, pix_off, view_hand, n_hands, w_e=1.0):
+def data_term(render, T, target, target_edges, mask, wh, pix_off, view_hand, n_hands, w_e=1.0, low=LOW,
+              high=HIGH):
     """E1 per hand of Eq. 3 with f1 = D_c + w_e D_e (Eq. 4) and its gradients.
 
     render R [P,3] (what the renderer returns), T [n_views,9], target O [P,3],
@@ -192,7 +193,7 @@ def data_term(render, T, target, target_edges, mask, wh, pix_off, view_hand, n_h
         m = mask[sl]
         n = int(m.sum())
         gx, gy, M = gradients(grey(img))
-        S = select(gx, gy, M)
+        S = select(gx, gy, M, low, high)
         sel[sl] = S.reshape(-1)
         b_r[sl] = correlate(np.where(S, M, 0.0), gaussian_kernel(BLUR_SIZE, BLUR_SIGMA)).reshape(-1)
         if n == 0:

@@ -29,6 +29,7 @@ EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "h
            "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
+           "hr_data_term_set", "hr_edge_map", "hr_loss_full", "hr_compose_albedo", "hr_albedo_low_grad", "hr_adam",
            "hr_last_error")
 
 HR_PROPOSAL_LENGTH = 0
@@ -71,6 +72,10 @@ class AdamConfig(ctypes.Structure):
 class ProposalConfig(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("eps", ctypes.c_float), ("ema", ctypes.c_float), ("lr", ctypes.c_float),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float)]
+
+
+class DataTerm(ctypes.Structure):
+    _fields_ = [("w_edge", ctypes.c_float), ("low", ctypes.c_float), ("high", ctypes.c_float)]
 
 
 class State(ctypes.Structure):
@@ -130,6 +135,13 @@ def lib():
         L.hr_read_counts.argtypes = [vp, vp, vp]
         L.hr_timing_enable.argtypes = [vp, i32]
         L.hr_timing_read.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+        L.hr_data_term_set.argtypes = [vp, ctypes.POINTER(DataTerm)]
+        L.hr_edge_map.argtypes = [vp, vp, vp, vp, vp]
+        L.hr_loss_full.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.hr_compose_albedo.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.hr_albedo_low_grad.argtypes = [vp, vp, i32, vp, vp]
+        L.hr_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.POINTER(AdamConfig), vp]
         L.hr_last_error.restype = ctypes.c_char_p
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior",
                      "hr_face_visibility", "hr_camera_order",
@@ -137,7 +149,9 @@ def lib():
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_set_accel", "hr_get_grid", "hr_tune", "hr_edge_stats",
                      "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
                      "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
-                     "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit"):
+                     "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
+                     "hr_data_term_set", "hr_edge_map", "hr_loss_full", "hr_compose_albedo", "hr_albedo_low_grad",
+                     "hr_adam"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -316,6 +330,51 @@ class Scene:
 
     def set_grid(self, render_blocks=0, adjoint_blocks=0):
         _check(lib().hr_set_grid(self._h, int(render_blocks), int(adjoint_blocks)), "hr_set_grid")
+
+    # -- the full data term (colour transforms, blurred-Canny edge term, two-level colour map) --
+    def data_term_set(self, w_edge=1.0, low=0.1, high=0.2):
+        c = DataTerm()
+        c.w_edge, c.low, c.high = float(w_edge), float(low), float(high)
+        _check(lib().hr_data_term_set(self._h, ctypes.byref(c)), "hr_data_term_set")
+
+    def edge_map(self, image, T, out):
+        """B(Canny(T image)) [P] of every view (T [n_views,9] or None)."""
+        _check(lib().hr_edge_map(self._h, _ptr(image, shape=(self.P, 3), name="image"),
+                                 _ptr(T, shape=(self.n_views, 9), name="T"),
+                                 _ptr(out, shape=(self.P,), name="edge_map"), _stream()), "hr_edge_map")
+
+    def loss_full(self, image, T, target, target_edges, mask, loss, dimage, grad_T=None, edge_map=None):
+        _check(lib().hr_loss_full(self._h, _ptr(image, shape=(self.P, 3), name="image"),
+                                  _ptr(T, shape=(self.n_views, 9), name="T"),
+                                  _ptr(target, shape=(self.P, 3), name="target"),
+                                  _ptr(target_edges, shape=(self.P,), name="target_edges"),
+                                  _ptr(mask, torch.uint8, (self.P,), "mask"),
+                                  _ptr(loss, shape=(self.n_hands,), name="loss"),
+                                  _ptr(dimage, shape=(self.P, 3), name="dimage"),
+                                  _ptr(grad_T, shape=(self.n_views, 9), name="grad_T"),
+                                  _ptr(edge_map, shape=(self.P,), name="edge_map"), _stream()), "hr_loss_full")
+
+    def compose_albedo(self, low, high, out):
+        L = int(low.shape[1])
+        _check(lib().hr_compose_albedo(self._h, _ptr(low, shape=(self.n_hands, L, L, 3), name="low"), L,
+                                       _ptr(high, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="high"),
+                                       _ptr(out, shape=(self.n_hands, self.tex_h, self.tex_w, 3), name="albedo"),
+                                       _stream()), "hr_compose_albedo")
+
+    def albedo_low_grad(self, grad_albedo, grad_low):
+        L = int(grad_low.shape[1])
+        _check(lib().hr_albedo_low_grad(self._h, _ptr(grad_albedo, shape=(self.n_hands, self.tex_h, self.tex_w, 3),
+                                                      name="grad_albedo"), L,
+                                        _ptr(grad_low, shape=(self.n_hands, L, L, 3), name="grad_low"), _stream()),
+               "hr_albedo_low_grad")
+
+    def adam(self, x, g, m, v, t, lr, lo=-3.4e38, hi=3.4e38, betas=(0.9, 0.999), eps=1e-8):
+        """One Adam step on the float32 tensor x in place (clamped to [lo, hi])."""
+        n = int(x.numel())
+        c = adam_config((0.0,) * 6, betas, eps)
+        _check(lib().hr_adam(self._h, _ptr(x, shape=tuple(x.shape), name="x"), _ptr(g, shape=tuple(x.shape), name="g"),
+                             _ptr(m, shape=tuple(x.shape), name="m"), _ptr(v, shape=tuple(x.shape), name="v"), n,
+                             int(t), float(lr), float(lo), float(hi), ctypes.byref(c), _stream()), "hr_adam")
 
     def set_accel(self, mode):
         """HR_ACCEL_AUTO (screen bins for the camera rays) or HR_ACCEL_HIERARCHY."""

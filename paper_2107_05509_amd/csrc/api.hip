@@ -14,6 +14,7 @@
 #include "../../include/handrt.h"
 #include "kernels.hip"
 #include "proposal.hip"
+#include "dataterm.hip"
 #include "bvh_build.h"
 
 using namespace hr;
@@ -149,6 +150,9 @@ struct hr_scene {
     int* hand_counter = nullptr;  // [1] hands finished in the geometry backward (reset by the last)
     int geom_blocks = 0;
     unsigned long long* counts = nullptr;   // [3][6] work counters (render, interior adjoint, edges)
+    // full data term (hr_data_term_set, hr_edge_map, hr_loss_full)
+    bool dt_alloc = false;
+    DataTermDev dt{};
     // learned edge-sampling proposal (hr_proposal_*)
     bool prop_alloc = false;
     int prop_kind = HR_PROPOSAL_LENGTH;
@@ -1434,6 +1438,148 @@ int hr_proposal_fit(hr_scene* s, const float* X, const uint32_t* w, const float*
                     (const float*)s->fit_z, (int)n, grad, (int)(apply != 0));
     if (!rc && apply) rc = launch(s, "k_proposal_adam", k_proposal_adam, dim3(1), dim3(256), 0, st, s->prop);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// full data term
+// ---------------------------------------------------------------------------
+
+int hr_data_term_set(hr_scene* s, const hr_data_term* cfg)
+{
+    if (!s || !cfg) return fail(HR_EINVAL, "hr_data_term_set: null argument");
+    if (!(cfg->w_edge >= 0.0f) || !std::isfinite(cfg->w_edge) || !(cfg->low >= 0.0f) || !(cfg->high >= cfg->low) ||
+        !std::isfinite(cfg->high))
+        return fail(HR_EINVAL, "hr_data_term_set: need w_edge >= 0 and 0 <= low <= high (finite)");
+    DataTermDev& d = s->dt;
+    if (!s->dt_alloc) {
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return fail(HR_EHIP, "hr_data_term_set: %s", hipGetErrorString(e));
+        const size_t P = (size_t)s->n_pixels;
+        int rc = HR_OK;
+        if (!rc) rc = s->upload<double>(&d.w5, nullptr, 25);
+        if (!rc) rc = s->upload<double>(&d.w11, nullptr, 121);
+        double* bufs[10];
+        for (int k = 0; k < 10 && !rc; ++k) rc = s->upload<double>(&bufs[k], nullptr, P);
+        if (!rc) rc = s->upload<uint8_t>(&d.flags, nullptr, P);
+        if (!rc) rc = s->upload<double>(&d.vsum, nullptr, 2 * (size_t)s->n_views);
+        if (!rc) rc = s->upload<double>(&d.gT, nullptr, 9 * (size_t)s->n_views);
+        if (rc) return rc;
+        d.grey = bufs[0]; d.sm = bufs[1]; d.gx = bufs[2]; d.gy = bufs[3]; d.mag = bufs[4];
+        d.edge = bufs[5]; d.blur = bufs[6]; d.g1 = bufs[7]; d.g2 = bufs[8];
+        // normalised Gaussian weights exp(-(i^2 + j^2) / (2 sigma^2))
+        auto gauss = [](int size, double sigma, double* host) {
+            const double c = (size - 1) / 2.0;
+            double sum = 0.0;
+            for (int i = 0; i < size; ++i)
+                for (int j = 0; j < size; ++j) {
+                    const double di = i - c, dj = j - c;
+                    host[size * i + j] = std::exp(-(di * di + dj * dj) / (2.0 * sigma * sigma));
+                    sum += host[size * i + j];
+                }
+            for (int k = 0; k < size * size; ++k) host[k] /= sum;
+        };
+        double w5[25], w11[121];
+        gauss(5, 1.0, w5);
+        gauss(11, 5.0, w11);
+        hipError_t e2 = hipMemcpy(d.w5, w5, sizeof(w5), hipMemcpyHostToDevice);
+        if (e2 == hipSuccess) e2 = hipMemcpy(d.w11, w11, sizeof(w11), hipMemcpyHostToDevice);
+        if (e2 != hipSuccess) return fail(HR_EHIP, "hr_data_term_set: %s", hipGetErrorString(e2));
+        s->dt_alloc = true;
+    }
+    d.w_e = cfg->w_edge;
+    d.low = cfg->low;
+    d.high = cfg->high;
+    return HR_OK;
+}
+
+static DtArgs dt_args(hr_scene* s, const float* image, const float* T)
+{
+    DtArgs a;
+    a.chunks = s->chunks; a.views = s->views; a.image = image; a.T = T;
+    a.target = nullptr; a.target_edges = nullptr; a.mask = nullptr; a.view_scale = s->view_scale;
+    a.d = s->dt;
+    return a;
+}
+
+// stages of B(Canny(T R)) up to the blur
+static int dt_canny(hr_scene* s, const DtArgs& a, hipStream_t st)
+{
+    const dim3 g(s->n_chunks), b(256);
+    int rc = launch(s, "k_dt_grey", k_dt_grey, g, b, 0, st, a);
+    if (!rc) rc = launch(s, "k_dt_smooth", k_dt_smooth, g, b, 0, st, a);
+    if (!rc) rc = launch(s, "k_dt_grad", k_dt_grad, g, b, 0, st, a);
+    if (!rc) rc = launch(s, "k_dt_suppress", k_dt_suppress, g, b, 0, st, a);
+    if (!rc) rc = launch(s, "k_dt_hyst", k_dt_hyst, g, b, 0, st, a);
+    return rc;
+}
+
+int hr_edge_map(hr_scene* s, const float* image, const float* T, float* edge_map, void* stream)
+{
+    if (!s || !image || !edge_map) return fail(HR_EINVAL, "hr_edge_map: null argument");
+    if (!s->dt_alloc) return fail(HR_EINVAL, "hr_edge_map: call hr_data_term_set first");
+    const hipStream_t st = (hipStream_t)stream;
+    const DtArgs a = dt_args(s, image, T);
+    int rc = dt_canny(s, a, st);
+    if (!rc) rc = launch(s, "k_dt_blur", k_dt_blur<false>, dim3(s->n_chunks), dim3(256), 0, st, a, edge_map);
+    return rc;
+}
+
+int hr_loss_full(hr_scene* s, const float* image, const float* T, const float* target, const float* target_edges,
+                 const uint8_t* mask, float* loss, float* dimage, float* grad_T, float* edge_map, void* stream)
+{
+    if (!s || !image || !target || !target_edges || !loss || !dimage)
+        return fail(HR_EINVAL, "hr_loss_full: null argument");
+    if (!s->dt_alloc) return fail(HR_EINVAL, "hr_loss_full: call hr_data_term_set first");
+    const hipStream_t st = (hipStream_t)stream;
+    DtArgs a = dt_args(s, image, T);
+    a.target = target; a.target_edges = target_edges; a.mask = mask;
+    int rc = launch(s, "k_dt_zero", k_dt_zero, dim3(1), dim3(256), 0, st, s->dt.vsum, 2 * s->n_views);
+    if (!rc) rc = launch(s, "k_dt_zero", k_dt_zero, dim3(1), dim3(256), 0, st, s->dt.gT, 9 * s->n_views);
+    if (!rc) rc = launch(s, "k_dt_scale", k_dt_scale, dim3(s->n_views), dim3(256), 0, st, (const ViewDev*)s->views, mask,
+                         s->view_scale);
+    if (!rc) rc = dt_canny(s, a, st);
+    const dim3 g(s->n_chunks), b(256);
+    if (!rc) rc = launch(s, "k_dt_blur", k_dt_blur<true>, g, b, 0, st, a, edge_map);
+    if (!rc) rc = launch(s, "k_dt_bwd_edge", k_dt_bwd_edge, g, b, 0, st, a);
+    if (!rc) rc = launch(s, "k_dt_bwd_sobel", k_dt_bwd_sobel, g, b, 0, st, a, s->dt.sm);
+    if (!rc) rc = launch(s, "k_dt_bwd_final", k_dt_bwd_final, g, b, 0, st, a, (const double*)s->dt.sm, dimage);
+    if (!rc)
+        rc = launch(s, "k_dt_finish", k_dt_finish, dim3(1), dim3(256), 0, st, a, (const int*)s->hand_view_off,
+                    (const int*)s->hand_views, s->n_hands, s->n_views, loss, grad_T);
+    return rc;
+}
+
+int hr_compose_albedo(hr_scene* s, const float* low, int32_t L, const float* high, float* albedo, void* stream)
+{
+    if (!s || !low || !high || !albedo) return fail(HR_EINVAL, "hr_compose_albedo: null argument");
+    const int th = s->cfg.tex_h, tw = s->cfg.tex_w;
+    if (L < 1 || th % L || tw % L) return fail(HR_ESHAPE, "hr_compose_albedo: %d does not divide %d x %d", L, th, tw);
+    const long long n = (long long)s->n_hands * th * tw * 3;
+    const unsigned blocks = (unsigned)std::min<long long>(4096, (n + 255) / 256);
+    return launch(s, "k_compose_albedo", k_compose_albedo, dim3(blocks), dim3(256), 0, (hipStream_t)stream, low, L, high,
+                  albedo, th, tw, n);
+}
+
+int hr_albedo_low_grad(hr_scene* s, const float* grad_albedo, int32_t L, float* grad_low, void* stream)
+{
+    if (!s || !grad_albedo || !grad_low) return fail(HR_EINVAL, "hr_albedo_low_grad: null argument");
+    const int th = s->cfg.tex_h, tw = s->cfg.tex_w;
+    if (L < 1 || th % L || tw % L) return fail(HR_ESHAPE, "hr_albedo_low_grad: %d does not divide %d x %d", L, th, tw);
+    return launch(s, "k_albedo_low_grad", k_albedo_low_grad, dim3(s->n_hands * L * L), dim3(256), 0, (hipStream_t)stream,
+                  grad_albedo, L, th, tw, grad_low);
+}
+
+int hr_adam(hr_scene* s, float* x, const float* g, float* m, float* v, int64_t n, int32_t t, float lr, float lo,
+            float hi, const hr_adam_config* cfg, void* stream)
+{
+    if (!s || !x || !g || !m || !v || !cfg) return fail(HR_EINVAL, "hr_adam: null argument");
+    if (n < 0 || t < 1 || !(lo <= hi)) return fail(HR_EINVAL, "hr_adam: need n >= 0, t >= 1, lo <= hi");
+    if (n == 0) return HR_OK;
+    const float bc1 = (float)(1.0 - std::pow((double)cfg->beta1, (double)t));
+    const float bc2 = (float)(1.0 - std::pow((double)cfg->beta2, (double)t));
+    const unsigned blocks = (unsigned)std::min<long long>(4096, (n + 255) / 256);
+    return launch(s, "k_adam_plain", k_adam_plain, dim3(blocks), dim3(256), 0, (hipStream_t)stream, x, g, m, v,
+                  (long long)n, lr, cfg->beta1, cfg->beta2, cfg->eps, bc1, bc2, lo, hi);
 }
 
 int hr_edge_stats(hr_scene* s, uint64_t* total_host, int64_t* budget_host, void* stream)

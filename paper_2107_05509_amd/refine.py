@@ -119,3 +119,70 @@ class Refiner:
         for phase, n in self._plan(n_iters):
             self._graph(phase, n).launch()
             self.it += n
+
+
+class FullRefiner:
+    """Refinement with the paper's full data term (Section 3.1 and Eq. 4):
+    per-camera colour transforms T_i, the two-level colour map V = V_high +
+    V_low (L x L, nearest-upsampled) and the blurred-Canny edge term beside
+    the colour term.  Schedule of Section 3.3: a warm-up of `warm`
+    iterations on {T, V_low} only, then every variable.  Each iteration
+    enqueues: colour map, skinning, render, full data term (hr_loss_full),
+    backward, the low map's gradient, and Adam steps (hr_adam for T, V_low
+    and V_high, hr_step for the hand parameters); no host synchronisation.
+
+    T starts at the identity (clamped to [-2, 2]), V_low at `low_init`
+    (clamped to [0, 1]), V_high at zero (clamped to [-1, 1])."""
+
+    def __init__(self, scene: binding.Scene, params, background, target, mask=None, L=8, low_init=0.5, warm=50,
+                 w_edge=1.0, low=0.02, high=0.04, lr_T=1e-3, lr_low=1e-2, lr_high=1e-2, lr_params=LR_ALL[:5],
+                 flags=binding.HR_GRAD_ALL):
+        g = self.scene = scene
+        dev = params.device
+        H, th, tw, V = g.n_hands, g.tex_h, g.tex_w, g.V
+        z = lambda *shape: torch.zeros(*shape, device=dev)
+        self.params = params
+        self.T = torch.eye(3, device=dev).reshape(1, 9).repeat(g.n_views, 1).contiguous()
+        self.low = torch.full((H, L, L, 3), float(low_init), device=dev)
+        self.high = z(H, th, tw, 3)
+        self.albedo = z(H, th, tw, 3)
+        self.background, self.target, self.mask = background, target, mask
+        self.m = {k: z(*t.shape) for k, t in (("T", self.T), ("low", self.low), ("high", self.high))}
+        self.v = {k: z(*t.shape) for k, t in (("T", self.T), ("low", self.low), ("high", self.high))}
+        self.mp, self.vp = z(H, 64), z(H, 64)
+        self.verts = z(H, V, 3)
+        self.image = z(g.P, 3)
+        self.dimage = z(g.P, 3)
+        self.loss = z(H)
+        self.gT = z(g.n_views, 9)
+        self.gp = z(H, 64)
+        self.galb = z(H, th, tw, 3)
+        self.glow = z(H, L, L, 3)
+        self.warm, self.flags = int(warm), int(flags)
+        self.lr_T, self.lr_low, self.lr_high, self.lr_params = lr_T, lr_low, lr_high, tuple(lr_params)
+        self.it = 0
+        g.data_term_set(w_edge, low, high)
+        self.target_edges = z(g.P)
+        g.edge_map(target, None, self.target_edges)
+
+    def step(self):
+        g, it = self.scene, self.it
+        g.compose_albedo(self.low, self.high, self.albedo)
+        g.skin(self.params, self.verts)
+        g.render(self.verts, self.albedo, self.background, it, self.image)
+        g.loss_full(self.image, self.T, self.target, self.target_edges, self.mask, self.loss, self.dimage, self.gT)
+        g.backward(self.params, self.verts, self.albedo, self.background, self.dimage, it, self.gp, self.galb,
+                   flags=self.flags | binding.HR_REUSE_GEOMETRY)
+        g.albedo_low_grad(self.galb, self.glow)
+        g.adam(self.T, self.gT, self.m["T"], self.v["T"], it + 1, self.lr_T, -2.0, 2.0)
+        g.adam(self.low, self.glow, self.m["low"], self.v["low"], it + 1, self.lr_low, 0.0, 1.0)
+        if it >= self.warm:
+            t = it - self.warm + 1
+            g.adam(self.high, self.galb, self.m["high"], self.v["high"], t, self.lr_high, -1.0, 1.0)
+            g.step(self.params, self.albedo, self.gp, self.galb, self.mp, self.vp, self.m["high"], self.v["high"], t,
+                   self.lr_params + (0.0,))
+        self.it += 1
+
+    def run(self, n):
+        for _ in range(int(n)):
+            self.step()
