@@ -309,6 +309,39 @@ def bench_coverage(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_full(args):
+    """The paper's full data term on the realistic workload: colour transforms,
+    two-level colour map, blurred-Canny edge term beside the colour term
+    (refine.FullRefiner, eager enqueue); iterations of the all-variables
+    phase timed after the 50-iteration warm-up on {T, V_low}."""
+    w = scene.workload_realistic(args.seed)
+    print(f"[bench] workload: full data term, {w.name}", file=sys.stderr, flush=True)
+    base = make_refiner(w, seed=args.seed, tune=not args.no_tune)
+    g = base.scene
+    st = base.state
+    r = refine.FullRefiner(g, st.params, st.background, st.target, st.mask, warm=50)
+    n_warm = max(args.warmup, r.warm)
+    r.run(n_warm)
+    torch.cuda.synchronize()
+    steps = min(args.steps, 50)
+    g.timing_enable(True)
+    g.timing_read()
+    ms = timed(lambda: r.run(steps)) / steps
+    kern = g.timing_read()
+    g.timing_enable(False)
+    per = {k: round(v[0] / v[1] * 1e3, 2) for k, v in kern.items()}
+    cam = sum(c.W * c.H for c in w.cams) * w.spp
+    out = {"metric": "full data term refine iteration (8 views 334x512, 16 spp, colour transforms, "
+                     "8x8 + 512x512 colour map, blurred-Canny edge term)",
+           "value": round(1e3 / ms, 2), "unit": "iters/s", "n_gpus": 1, "steps": steps, "warmup": n_warm,
+           "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 render, f64 data term", "data": "synthetic",
+           "config": {"workload": "realistic with the full data term", "camera_samples_per_step": cam},
+           "kernels_us": per, "loss": [round(float(x), 5) for x in r.loss.cpu()],
+           "data_term_us": round(sum(v for k, v in per.items() if k.startswith("k_dt_")), 1)}
+    print(json.dumps(out), flush=True)
+
+
 def dense_iteration(args):
     """fwd+bwd time of one iteration of the dense workload (one hand, 40 views
     334x512, 4 spp, 1024x1024 colour map): graph-replayed iterations of the
@@ -348,7 +381,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=2)
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-workload iteration time (40 views, 4 spp, 1024x1024 albedo)")
-    ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage"), default="realistic",
+    ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage", "full"), default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
     args = ap.parse_args()
@@ -366,6 +399,8 @@ def main():
         return bench_proposal(args)
     if args.workload == "coverage":
         return bench_coverage(args)
+    if args.workload == "full":
+        return bench_full(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))

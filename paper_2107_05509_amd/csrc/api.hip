@@ -1458,6 +1458,7 @@ int hr_data_term_set(hr_scene* s, const hr_data_term* cfg)
         int rc = HR_OK;
         if (!rc) rc = s->upload<double>(&d.w5, nullptr, 25);
         if (!rc) rc = s->upload<double>(&d.w11, nullptr, 121);
+        if (!rc) rc = s->upload<double>(&d.w11s, nullptr, 11);
         double* bufs[10];
         for (int k = 0; k < 10 && !rc; ++k) rc = s->upload<double>(&bufs[k], nullptr, P);
         if (!rc) rc = s->upload<uint8_t>(&d.flags, nullptr, P);
@@ -1465,7 +1466,7 @@ int hr_data_term_set(hr_scene* s, const hr_data_term* cfg)
         if (!rc) rc = s->upload<double>(&d.gT, nullptr, 9 * (size_t)s->n_views);
         if (rc) return rc;
         d.grey = bufs[0]; d.sm = bufs[1]; d.gx = bufs[2]; d.gy = bufs[3]; d.mag = bufs[4];
-        d.edge = bufs[5]; d.blur = bufs[6]; d.g1 = bufs[7]; d.g2 = bufs[8];
+        d.edge = bufs[5]; d.blur = bufs[6]; d.g1 = bufs[7]; d.g2 = bufs[8]; d.gb = bufs[9];
         // normalised Gaussian weights exp(-(i^2 + j^2) / (2 sigma^2))
         auto gauss = [](int size, double sigma, double* host) {
             const double c = (size - 1) / 2.0;
@@ -1478,11 +1479,18 @@ int hr_data_term_set(hr_scene* s, const hr_data_term* cfg)
                 }
             for (int k = 0; k < size * size; ++k) host[k] /= sum;
         };
-        double w5[25], w11[121];
+        double w5[25], w11[121], w11s[11], sum1 = 0.0;
         gauss(5, 1.0, w5);
         gauss(11, 5.0, w11);
+        // the blur's factor: w11[i][j] = w11s[i] w11s[j]
+        for (int k = 0; k < 11; ++k) {
+            w11s[k] = std::exp(-(double)((k - 5) * (k - 5)) / 50.0);
+            sum1 += w11s[k];
+        }
+        for (int k = 0; k < 11; ++k) w11s[k] /= sum1;
         hipError_t e2 = hipMemcpy(d.w5, w5, sizeof(w5), hipMemcpyHostToDevice);
         if (e2 == hipSuccess) e2 = hipMemcpy(d.w11, w11, sizeof(w11), hipMemcpyHostToDevice);
+        if (e2 == hipSuccess) e2 = hipMemcpy(d.w11s, w11s, sizeof(w11s), hipMemcpyHostToDevice);
         if (e2 != hipSuccess) return fail(HR_EHIP, "hr_data_term_set: %s", hipGetErrorString(e2));
         s->dt_alloc = true;
     }
@@ -1520,7 +1528,10 @@ int hr_edge_map(hr_scene* s, const float* image, const float* T, float* edge_map
     const hipStream_t st = (hipStream_t)stream;
     const DtArgs a = dt_args(s, image, T);
     int rc = dt_canny(s, a, st);
-    if (!rc) rc = launch(s, "k_dt_blur", k_dt_blur<false>, dim3(s->n_chunks), dim3(256), 0, st, a, edge_map);
+    if (!rc) rc = launch(s, "k_dt_blur_col", k_dt_blur_col, dim3(s->n_chunks), dim3(256), 0, st, a, s->dt.g1);
+    if (!rc)
+        rc = launch(s, "k_dt_blur", k_dt_blur<false>, dim3(s->n_chunks), dim3(256), 0, st, a, (const double*)s->dt.g1,
+                    edge_map);
     return rc;
 }
 
@@ -1539,8 +1550,12 @@ int hr_loss_full(hr_scene* s, const float* image, const float* T, const float* t
                          s->view_scale);
     if (!rc) rc = dt_canny(s, a, st);
     const dim3 g(s->n_chunks), b(256);
-    if (!rc) rc = launch(s, "k_dt_blur", k_dt_blur<true>, g, b, 0, st, a, edge_map);
-    if (!rc) rc = launch(s, "k_dt_bwd_edge", k_dt_bwd_edge, g, b, 0, st, a);
+    // the column pass writes g1 (free until the backward); the backward's
+    // row pass writes the edge map's buffer (no longer read)
+    if (!rc) rc = launch(s, "k_dt_blur_col", k_dt_blur_col, g, b, 0, st, a, s->dt.g1);
+    if (!rc) rc = launch(s, "k_dt_blur", k_dt_blur<true>, g, b, 0, st, a, (const double*)s->dt.g1, edge_map);
+    if (!rc) rc = launch(s, "k_dt_bwd_blur_row", k_dt_bwd_blur_row, g, b, 0, st, a, s->dt.edge);
+    if (!rc) rc = launch(s, "k_dt_bwd_edge", k_dt_bwd_edge, g, b, 0, st, a, (const double*)s->dt.edge);
     if (!rc) rc = launch(s, "k_dt_bwd_sobel", k_dt_bwd_sobel, g, b, 0, st, a, s->dt.sm);
     if (!rc) rc = launch(s, "k_dt_bwd_final", k_dt_bwd_final, g, b, 0, st, a, (const double*)s->dt.sm, dimage);
     if (!rc)

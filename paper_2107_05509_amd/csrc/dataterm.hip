@@ -25,6 +25,7 @@ namespace hr {
 struct DataTermDev {
     double* w5;          // [25] smoothing weights, row-major
     double* w11;         // [121] blur weights
+    double* w11s;        // [11] the blur's 1-D factor (the blur runs as a column then a row pass)
     double* grey;        // [P] luma of r' = T R
     double* sm;          // [P] smoothed luma
     double* gx;          // [P]
@@ -34,7 +35,8 @@ struct DataTermDev {
     double* edge;        // [P] Canny: magnitude at selected pixels
     double* blur;        // [P] B(Canny(r'))
     double* g1;          // [P] backward scratch (dE/dgx)
-    double* g2;          // [P] backward scratch (dE/dgy, then dE/dsmoothed)
+    double* g2;          // [P] backward scratch (dE/dgy)
+    double* gb;          // [P] dE/dB(Canny(r')) of the edge term (0 off the mask)
     double* vsum;        // [n_views, 2] sums of |O - r'| and |B(C(O)) - B(C(r'))| over masked pixels
     double* gT;          // [n_views, 9] dE/dT
     float w_e;           // weight of the edge term
@@ -61,10 +63,10 @@ __device__ __forceinline__ bool dt_pixel(const DtArgs& a, int k, ViewDev& c, int
 {
     const int2 ck = a.chunks[blockIdx.x];
     c = load_view(a.views, ck.x);
-    const long long pl = (long long)ck.y + k;
-    if (pl >= (long long)c.W * c.H) return false;
-    y = (int)(pl / c.W);
-    x = (int)(pl - (long long)y * c.W);
+    const int pl = ck.y + k;   // a view holds at most 4096 x 4096 pixels
+    if (pl >= c.W * c.H) return false;
+    y = pl / c.W;
+    x = pl - y * c.W;
     pg = c.pix0 + pl;
     return true;
 }
@@ -177,9 +179,23 @@ __global__ void __launch_bounds__(256) k_dt_hyst(DtArgs a)
     }
 }
 
-// stage 6: 11x11 blur; with the loss: per-view sums of the colour and edge differences
+// stage 6: the 11x11 blur, separable: a column pass into `tmp`, then a row
+// pass; with the loss: per-view sums of the colour and edge differences and
+// dE/dB of the edge term.  With the loss only masked pixels need the blurred
+// map (unless it is an output).
+__global__ void __launch_bounds__(256) k_dt_blur_col(DtArgs a, double* tmp)
+{
+    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+        ViewDev c; int x, y; long long pg;
+        if (!dt_pixel(a, k, c, x, y, pg)) break;
+        double acc = 0.0;
+        for (int i = 0; i < 11; ++i) acc = acc + a.d.w11s[i] * a.d.edge[dt_at(c, x, y + i - 5)];
+        tmp[pg] = acc;
+    }
+}
+
 template <bool LOSS>
-__global__ void __launch_bounds__(256) k_dt_blur(DtArgs a, float* edge_out)
+__global__ void __launch_bounds__(256) k_dt_blur(DtArgs a, const double* tmp, float* edge_out)
 {
     __shared__ double red[2 * 4];
     const int view = a.chunks[blockIdx.x].x;
@@ -187,16 +203,24 @@ __global__ void __launch_bounds__(256) k_dt_blur(DtArgs a, float* edge_out)
     for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
+        const bool on = !a.mask || a.mask[pg] != 0;
         double acc = 0.0;
-        for (int i = 0; i < 11; ++i)
-            for (int j = 0; j < 11; ++j) acc = acc + a.d.w11[11 * i + j] * a.d.edge[dt_at(c, x + j - 5, y + i - 5)];
+        if (!LOSS || edge_out || on)
+            for (int j = 0; j < 11; ++j) acc = acc + a.d.w11s[j] * tmp[dt_at(c, x + j - 5, y)];
         a.d.blur[pg] = acc;
         if (edge_out) edge_out[pg] = (float)acc;
-        if (LOSS && (!a.mask || a.mask[pg] != 0)) {
-            double rp[3];
-            dt_transform(a, view, pg, rp);
-            for (int ch = 0; ch < 3; ++ch) sc += fabs((double)a.target[3 * pg + ch] - rp[ch]);
-            se += fabs((double)a.target_edges[pg] - acc);
+        if (LOSS) {
+            double gb = 0.0;
+            if (on) {
+                double rp[3];
+                dt_transform(a, view, pg, rp);
+                for (int ch = 0; ch < 3; ++ch) sc += fabs((double)a.target[3 * pg + ch] - rp[ch]);
+                const double d = acc - (double)a.target_edges[pg];
+                se += fabs(d);
+                // dE/dB: w_e sign(B - B_O) / n, with 1 / n = 3 view_scale
+                gb = (double)a.d.w_e * (double)((d > 0.0) - (d < 0.0)) * (3.0 * (double)a.view_scale[view]);
+            }
+            a.d.gb[pg] = gb;
         }
     }
     if (!LOSS) return;
@@ -221,39 +245,78 @@ __device__ __forceinline__ bool dt_taps(int p, int q, int r, int n, int& lo, int
     return lo >= -r && lo <= r;
 }
 
-// dE/dB(Canny(r')) of the edge term at pixel pg (masked pixels of the view)
-__device__ __forceinline__ double dt_gblur(const DtArgs& a, int view, long long pg)
+// Transposed clamped (2r+1)-tap filter at output pixel (x, y) of a view:
+// sum over the input positions p that read (x, y) and their taps of
+// w[tap] * g[p].  Far from the border a tap reads (x, y) from p = (x, y) -
+// tap only; near it the clamped taps of several positions fold onto it.
+template <int R>
+__device__ __forceinline__ double dt_adjoint(const ViewDev& c, int x, int y, const double* __restrict__ w,
+                                             const double* __restrict__ g)
 {
-    if (a.mask && a.mask[pg] == 0) return 0.0;
-    const double d = a.d.blur[pg] - (double)a.target_edges[pg];
-    const double s = (double)((d > 0.0) - (d < 0.0));
-    // 1 / masked pixels = 3 view_scale
-    return (double)a.d.w_e * s * (3.0 * (double)a.view_scale[view]);
+    constexpr int N = 2 * R + 1;
+    double acc = 0.0;
+    if (x >= R && y >= R && x < c.W - R && y < c.H - R) {
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                acc += w[N * i + j] * g[c.pix0 + (long long)(y - (i - R)) * c.W + (x - (j - R))];
+        return acc;
+    }
+    for (int py = max(0, y - R); py <= min(c.H - 1, y + R); ++py) {
+        int ylo, yhi;
+        if (!dt_taps(py, y, R, c.H, ylo, yhi)) continue;
+        for (int px = max(0, x - R); px <= min(c.W - 1, x + R); ++px) {
+            int xlo, xhi;
+            if (!dt_taps(px, x, R, c.W, xlo, xhi)) continue;
+            double ws = 0.0;
+            for (int ty = ylo; ty <= yhi; ++ty)
+                for (int tx = xlo; tx <= xhi; ++tx) ws += w[N * (ty + R) + tx + R];
+            acc += ws * g[c.pix0 + (long long)py * c.W + px];
+        }
+    }
+    return acc;
 }
 
-// backward 1: through the blur (its transpose, clamped) and the magnitude at
-// selected pixels: dE/dgx, dE/dgy
-__global__ void __launch_bounds__(256) k_dt_bwd_edge(DtArgs a)
+// transposed clamped (2R+1)-tap filter along one axis (AXIS 0: rows of the
+// image, i.e. along x; 1: columns, along y) at output pixel (x, y)
+template <int R, int AXIS>
+__device__ __forceinline__ double dt_adjoint1(const ViewDev& c, int x, int y, const double* __restrict__ w,
+                                              const double* __restrict__ g)
 {
-    const int view = a.chunks[blockIdx.x].x;
+    const int q = AXIS == 0 ? x : y, n = AXIS == 0 ? c.W : c.H;
+    auto at = [&](int p) { return AXIS == 0 ? c.pix0 + (long long)y * c.W + p : c.pix0 + (long long)p * c.W + x; };
+    double acc = 0.0;
+    if (q >= R && q < n - R) {
+        for (int t = 0; t <= 2 * R; ++t) acc += w[t] * g[at(q - (t - R))];
+        return acc;
+    }
+    for (int p = max(0, q - R); p <= min(n - 1, q + R); ++p) {
+        int lo, hi;
+        if (!dt_taps(p, q, R, n, lo, hi)) continue;
+        double ws = 0.0;
+        for (int t = lo; t <= hi; ++t) ws += w[t + R];
+        acc += ws * g[at(p)];
+    }
+    return acc;
+}
+
+// backward of the blur's row pass (transposed): into `tmp`
+__global__ void __launch_bounds__(256) k_dt_bwd_blur_row(DtArgs a, double* tmp)
+{
     for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
-        double gc = 0.0;
-        if (a.d.flags[pg] & 4) {
-            for (int py = max(0, y - 5); py <= min(c.H - 1, y + 5); ++py) {
-                int ylo, yhi;
-                if (!dt_taps(py, y, 5, c.H, ylo, yhi)) continue;
-                for (int px = max(0, x - 5); px <= min(c.W - 1, x + 5); ++px) {
-                    int xlo, xhi;
-                    if (!dt_taps(px, x, 5, c.W, xlo, xhi)) continue;
-                    double w = 0.0;
-                    for (int ty = ylo; ty <= yhi; ++ty)
-                        for (int tx = xlo; tx <= xhi; ++tx) w += a.d.w11[11 * (ty + 5) + tx + 5];
-                    gc += w * dt_gblur(a, view, c.pix0 + (long long)py * c.W + px);
-                }
-            }
-        }
+        tmp[pg] = dt_adjoint1<5, 0>(c, x, y, a.d.w11s, a.d.gb);
+    }
+}
+
+// backward 1: through the blur's column pass (transposed, from `tmp`) and the
+// magnitude at selected pixels: dE/dgx, dE/dgy
+__global__ void __launch_bounds__(256) k_dt_bwd_edge(DtArgs a, const double* tmp)
+{
+    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+        ViewDev c; int x, y; long long pg;
+        if (!dt_pixel(a, k, c, x, y, pg)) break;
+        const double gc = (a.d.flags[pg] & 4) ? dt_adjoint1<5, 1>(c, x, y, a.d.w11s, tmp) : 0.0;
         const double M = a.d.mag[pg];
         a.d.g1[pg] = gc * a.d.gx[pg] / M;
         a.d.g2[pg] = gc * a.d.gy[pg] / M;
@@ -268,24 +331,7 @@ __global__ void __launch_bounds__(256) k_dt_bwd_sobel(DtArgs a, double* out)
     for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
-        double g = 0.0;
-        for (int py = max(0, y - 1); py <= min(c.H - 1, y + 1); ++py) {
-            int ylo, yhi;
-            if (!dt_taps(py, y, 1, c.H, ylo, yhi)) continue;
-            for (int px = max(0, x - 1); px <= min(c.W - 1, x + 1); ++px) {
-                int xlo, xhi;
-                if (!dt_taps(px, x, 1, c.W, xlo, xhi)) continue;
-                double wx = 0.0, wy = 0.0;
-                for (int ty = ylo; ty <= yhi; ++ty)
-                    for (int tx = xlo; tx <= xhi; ++tx) {
-                        wx += sx[3 * (ty + 1) + tx + 1];
-                        wy += sy[3 * (ty + 1) + tx + 1];
-                    }
-                const long long pp = c.pix0 + (long long)py * c.W + px;
-                g += wx * a.d.g1[pp] + wy * a.d.g2[pp];
-            }
-        }
-        out[pg] = g;
+        out[pg] = dt_adjoint<1>(c, x, y, sx, a.d.g1) + dt_adjoint<1>(c, x, y, sy, a.d.g2);
     }
 }
 
@@ -300,19 +346,7 @@ __global__ void __launch_bounds__(256) k_dt_bwd_final(DtArgs a, const double* gs
     for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
-        double g = 0.0;
-        for (int py = max(0, y - 2); py <= min(c.H - 1, y + 2); ++py) {
-            int ylo, yhi;
-            if (!dt_taps(py, y, 2, c.H, ylo, yhi)) continue;
-            for (int px = max(0, x - 2); px <= min(c.W - 1, x + 2); ++px) {
-                int xlo, xhi;
-                if (!dt_taps(px, x, 2, c.W, xlo, xhi)) continue;
-                double w = 0.0;
-                for (int ty = ylo; ty <= yhi; ++ty)
-                    for (int tx = xlo; tx <= xhi; ++tx) w += a.d.w5[5 * (ty + 2) + tx + 2];
-                g += w * gs[c.pix0 + (long long)py * c.W + px];
-            }
-        }
+        const double g = dt_adjoint<2>(c, x, y, a.d.w5, gs);
         double grp[3] = {kGrey0 * g, kGrey1 * g, kGrey2 * g};
         if (!a.mask || a.mask[pg] != 0) {
             double rp[3];
