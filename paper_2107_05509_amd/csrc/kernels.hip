@@ -887,17 +887,15 @@ __device__ void render_side_work(const RenderArgs& a, int bid, int nb)
     }
 }
 
+// Wave tiles gw, gw + nw, ... (wave-uniform gw).
 template <bool COUNT>
-__device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
+__device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
 {
-    render_side_work(a, bid, nb);
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* wst = stack + kMaxStack * (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int G = 1 << a.ts.spp_log2;
     const int s_lane = lane & (G - 1);
-    const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
-    const int nw = (int)((nb * kThreads) >> 6);
     const int n_tiles = *a.tile_count;
     const float inv_spp = 1.0f / (float)a.spp;
     TraceCount tc;
@@ -993,7 +991,6 @@ __device__ void render_tiles(const RenderArgs& a, int bid, int nb, int* stack)
             if (a.dimage) pixel_dimage(a, e.x, pg, out);
         }
     }
-    if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iter;
     if (COUNT) {
         atomicAdd(a.counts + 0, n_rays);
         atomicAdd(a.counts + 1, (unsigned long long)tc.nodes);
@@ -1691,7 +1688,7 @@ __device__ __forceinline__ void edge_side_colour(const EdgeArgs& a, const EdgePo
     // traverses together unless its lanes look at different hands (the
     // side points are spread along silhouettes, over many screen bins)
     if (__all(hand == __builtin_amdgcn_readfirstlane(hand)))
-        trace_wave<COUNT>(nodes, tris, ray, true, wst, h, &tc);
+        trace_wave<COUNT, true>(nodes, tris, ray, true, wst, h, &tc);
     else
         trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
     if (COUNT) { ++n_rays; n_hit += h.face >= 0; }
@@ -1744,7 +1741,7 @@ __device__ __forceinline__ void edge_contribution(const EdgeArgs& a, int vi, int
 
 // Edge samples, one per lane pair (the even lane traces x + delta n, the odd
 // lane x - delta n; consecutive global indices are consecutive strata of one
-// view's CDF, so a wave works on neighbouring edges).  Block `bid` of `nb`.
+// view's CDF).  This lane pair takes samples first, first + npairs, ...
 //   TRACE: samples kg < min(total, cap): trace and shade both side points
 //          (independent of the image gradient) and store the sample record;
 //   WEIGH: samples kg < min(total, cap) from their records, the samples
@@ -1752,7 +1749,7 @@ __device__ __forceinline__ void edge_contribution(const EdgeArgs& a, int vi, int
 enum EdgeMode { kEdgeTrace = 0, kEdgeWeigh = 1 };
 
 template <bool COUNT, int MODE>
-__device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int* wstack)
+__device__ void edge_samples(const EdgeArgs& a, long long first, long long npairs, int* stack, int* wstack)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* stk = stack + threadIdx.x;
@@ -1762,8 +1759,6 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int
     const int side = threadIdx.x & 1;
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
-    const long long npairs = ((long long)nb * kThreads) >> 1;
-    const long long first = ((long long)bid * kThreads + threadIdx.x) >> 1;
     if (MODE == kEdgeTrace) {
         for (long long kg = first; kg < stored; kg += npairs) {
             EdgePoint P;
@@ -1821,17 +1816,35 @@ __device__ void edge_samples(const EdgeArgs& a, int bid, int nb, int* stack, int
 // launches of the ray-tracing work
 // ===========================================================================
 
-// Render: every block renders its share of the wave tiles (one traversal
-// stack per wave), then, with edges, traces its share of the edge samples'
-// side points (a traversal stack per lane), so no block slot idles while work
-// of either kind remains.
+// Render: every block writes its share of the pixels outside the views'
+// tiled rectangles; with edges, the first waves trace the edge samples' side
+// points (a wave packet, or a traversal stack per lane where a wave's lanes
+// look at different hands) while the others render the wave tiles (one
+// traversal stack per wave).
 template <bool COUNT>
 __global__ void __launch_bounds__(kThreads, 4) k_render(RenderArgs a, EdgeArgs e, int with_edges)
 {
     __shared__ int stack[kMaxStack * kThreads];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
-    render_tiles<COUNT>(a, (int)blockIdx.x, (int)gridDim.x, wstack);
-    if (with_edges) edge_samples<COUNT, kEdgeTrace>(e, (int)blockIdx.x, (int)gridDim.x, stack, wstack);
+    const int bid = (int)blockIdx.x, nb = (int)gridDim.x;
+    render_side_work(a, bid, nb);
+    if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iteration(a.iter_dev, a.iter);
+    const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
+    const int nw = (int)((nb * kThreads) >> 6);
+    // the first n_ew waves trace the edge samples (32 lane pairs each), from
+    // the start: their traversals are long dependent chains; the other waves
+    // render the tiles
+    int n_ew = 0;
+    if (with_edges) {
+        const long long stored = min(e.prefix[e.n_views], e.sample_cap);
+        n_ew = (int)min((stored + 31) / 32, (long long)max(1, nw / 2));
+    }
+    if (gw < n_ew) {
+        const long long first = (long long)gw * 32 + ((threadIdx.x & 63) >> 1);
+        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * 32, stack, wstack);
+    } else {
+        render_tiles<COUNT>(a, gw - n_ew, nw - n_ew, wstack);
+    }
 }
 
 // Edge samples, first part: trace and shade both side points of every stored
@@ -1841,7 +1854,8 @@ __global__ void __launch_bounds__(kThreads) k_edge_trace(EdgeArgs e)
 {
     __shared__ int stack[kMaxStack * kThreads];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
-    edge_samples<COUNT, kEdgeTrace>(e, blockIdx.x, gridDim.x, stack, wstack);
+    edge_samples<COUNT, kEdgeTrace>(e, ((long long)blockIdx.x * kThreads + threadIdx.x) >> 1,
+                                    ((long long)gridDim.x * kThreads) >> 1, stack, wstack);
 }
 
 // Backward ray tracing: the first `n_edge` blocks draw the edge samples, the
@@ -1858,7 +1872,8 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
     __shared__ __align__(16) int lds[kLds];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
     if ((int)blockIdx.x < n_edge) {
-        edge_samples<COUNT, kEdgeWeigh>(e, blockIdx.x, n_edge, lds, wstack);
+        edge_samples<COUNT, kEdgeWeigh>(e, ((long long)blockIdx.x * kThreads + threadIdx.x) >> 1,
+                                        ((long long)n_edge * kThreads) >> 1, lds, wstack);
         return;
     }
     // the last n_loss blocks: partial sums of the loss value (chunk per block)
