@@ -18,7 +18,6 @@ iterations of the all-variables phase.
 Prints one JSON line: the metric, per-kernel times, the roofline of the render launch and the CPU baseline.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -55,12 +54,8 @@ OPS_PER_HIT = {"k_render": 70, "k_adjoint_interior": 170, "k_edge_sample": 70}
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2107_05509_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".h", ".hip")):
-            h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_2107_05509_amd.build import source_hash
+    return source_hash()
 
 
 def make_refiner(w, dev="cuda:0", seed=0, tune=True, cover_spp=64):

@@ -1,4 +1,5 @@
 """Build the handrt HIP library for gfx950 (in-tree: paper_2107_05509_amd/libhandrt.so)."""
+import hashlib
 import os
 import subprocess
 import sys
@@ -14,6 +15,15 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
+
+
+def source_hash():
+    """Hash of the HIP sources (ties profiler summaries to the kernels they measured)."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def build(verbose=False):
