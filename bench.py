@@ -410,7 +410,8 @@ def main():
         g.set_joint_prior(jt.contiguous(), 1.0, 0.005)
     if args.grids:
         g.set_grid(*[int(x) for x in args.grids.split(",")])
-    print(f"[bench] launch grids (render, adjoint): {g.grids()}", file=sys.stderr, flush=True)
+    print(f"[bench] launch grids (render, adjoint): {g.grids()}, tiles (w, h, bin) log2: {g.tiles()}",
+          file=sys.stderr, flush=True)
     graph = args.mode == "graph"
     # the colour-only phase (iterations 0..warm-1) always runs untimed
     n_warm = max(args.warmup, ref.warm)
@@ -511,6 +512,7 @@ def main():
                    "camera_samples_per_step": cam_samples},
         "mode": args.mode,
         "launch_grids": list(g.grids()),
+        "launch_tiles": dict(zip(("tile_w_log2", "tile_h_log2", "bin_log2"), g.tiles())),
         "refine_iters_per_s": round(1e3 / ms, 2),
         "traced_mrays_per_s": round(traced / (ms * 1e-3) / 1e6, 2),
         "edge_samples_per_step": int(bud.sum()),

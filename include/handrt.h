@@ -284,13 +284,15 @@ void hr_graph_destroy(hr_graph* graph);
    images are identical for any choice (each pixel sums its samples in a fixed
    order), gradients agree up to the order of floating-point atomic sums.
    hr_set_grid sets them (0 keeps a value; values are capped at one block per
-   four wave tiles of the views), hr_get_grid reads them.  hr_tune times candidate grids on `state`'s
-   buffers (it runs skin, render, loss and the interior adjoint `reps` times
-   per candidate, overwriting verts, image, dimage, loss and the gradient
-   outputs, never params, albedo, moments or iter), keeps the fastest and
-   writes (render blocks, adjoint blocks) to blocks_host (HOST, nullable).
-   Synchronises `stream`; not for use under graph capture.  Graphs created
-   before a change keep the grids they were captured with. */
+   four wave tiles of the views), hr_get_grid reads them.  hr_tune times
+   candidates on `state`'s buffers (it runs skin, render, loss and the
+   interior adjoint `reps` times per candidate, overwriting verts, image,
+   dimage, loss and the gradient outputs, never params, albedo, moments or
+   iter): first every wave-tile shape and screen-bin size (hr_set_tiles),
+   then the render grid, then the adjoint grid; it keeps the fastest of each
+   and writes (render blocks, adjoint blocks) to blocks_host (HOST,
+   nullable).  Synchronises the device; not for use under graph capture.
+   Graphs created before a change keep the grids they were captured with. */
 int hr_set_grid(hr_scene* scene, int32_t render_blocks, int32_t adjoint_blocks);
 
 /* Acceleration of the camera rays (speed only: hits and images are identical
@@ -307,6 +309,21 @@ int hr_set_grid(hr_scene* scene, int32_t render_blocks, int32_t adjoint_blocks);
 #define HR_ACCEL_HIERARCHY 1
 int hr_set_accel(hr_scene* scene, int32_t mode);
 int hr_get_grid(const hr_scene* scene, int32_t* blocks_host);   /* (render, adjoint) */
+
+/* Work layout of the camera samples (speed only: the samples, each pixel's
+   sum and so the images are bit-identical for every choice).  A wave takes
+   all samples of 2^spp_log2 lanes per pixel for a tile of 2^a x 2^b pixels,
+   a + b = 6 - spp_log2 (spp_log2 = ceil(log2 spp), at most 6); screen bins
+   are 2^bin_log2 pixels square, 3 <= bin_log2 <= 5, and a tile lies inside
+   one bin (a, b <= bin_log2).  hr_set_tiles(scene, a, bin_log2) synchronises
+   the device, rewrites the views' bin layout and drops the render's stored
+   samples (a following hr_backward with HR_REUSE_GEOMETRY prepares and
+   traces again);
+   graphs captured before a change must be captured again.  hr_get_tiles
+   writes (a, b, bin_log2) to out_host (HOST, 3 ints).  HR_EINVAL: a shape or
+   bin size outside these rules. */
+int hr_set_tiles(hr_scene* scene, int32_t tile_w_log2, int32_t bin_log2);
+int hr_get_tiles(const hr_scene* scene, int32_t* out_host);
 int hr_tune(hr_scene* scene, const hr_state* state, int32_t reps, int32_t* blocks_host, void* stream);
 
 /* ---- learned edge-sampling proposal (project addition) -----------------

@@ -26,7 +26,7 @@ HR_ACCEL_HIERARCHY = 1
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
            "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
-           "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
+           "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
            "hr_data_term_set", "hr_edge_map", "hr_loss_full", "hr_compose_albedo", "hr_albedo_low_grad", "hr_adam",
@@ -146,7 +146,8 @@ def lib():
         for name in ("hr_scene_create", "hr_skin", "hr_render", "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior",
                      "hr_face_visibility", "hr_camera_order",
                      "hr_step", "hr_iterate",
-                     "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_set_accel", "hr_get_grid", "hr_tune", "hr_edge_stats",
+                     "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles",
+                     "hr_get_grid", "hr_tune", "hr_edge_stats",
                      "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
                      "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
                      "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
@@ -380,6 +381,17 @@ class Scene:
         """HR_ACCEL_AUTO (screen bins for the camera rays) or HR_ACCEL_HIERARCHY."""
         _check(lib().hr_set_accel(self._h, int(mode)), "hr_set_accel")
 
+    def set_tiles(self, tile_w_log2, bin_log2):
+        """Wave tiles of 2^tile_w_log2 pixels across (the height follows from the
+        samples per pixel) and screen bins of 2^bin_log2 pixels; images never change."""
+        _check(lib().hr_set_tiles(self._h, int(tile_w_log2), int(bin_log2)), "hr_set_tiles")
+
+    def tiles(self):
+        """(tile width log2, tile height log2, bin size log2)."""
+        out = np.zeros(3, dtype=np.int32)
+        _check(lib().hr_get_tiles(self._h, out.ctypes.data_as(ctypes.c_void_p)), "hr_get_tiles")
+        return int(out[0]), int(out[1]), int(out[2])
+
     def grids(self):
         """(render blocks, adjoint blocks) of the persistent ray-tracing grids."""
         out = np.zeros(2, dtype=np.int32)
@@ -387,7 +399,8 @@ class Scene:
         return int(out[0]), int(out[1])
 
     def tune(self, state, reps=3):
-        """Time candidate persistent grids; returns (render blocks, adjoint blocks)."""
+        """Time candidate tile shapes and bin sizes, then persistent grids; returns
+        (render blocks, adjoint blocks) (the tile choice: tiles())."""
         out = np.zeros(2, dtype=np.int32)
         _check(lib().hr_tune(self._h, ctypes.byref(state.c), int(reps), out.ctypes.data_as(ctypes.c_void_p),
                              _stream()), "hr_tune")

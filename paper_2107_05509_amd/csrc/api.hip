@@ -108,7 +108,9 @@ struct hr_scene {
     int* hit_iter = nullptr;      // iteration of those hits (-1: none)
     int4* view_rect = nullptr;    // [n_views] pixel rectangle of each view's tiles (screen-bounds pass)
     BinDev bins{};                // screen bins of the camera rays (built by the preparation launch)
-    int n_bins = 0;
+    int bin_log2 = kBinLog2;      // bins of 2^bin_log2 pixels square
+    bool layout_changed = false;  // hr_set_tiles since the last preparation
+    long long bin_cap = 0;        // bins of all views at the smallest bin size
     int accel = HR_ACCEL_AUTO;
     long long tile_cap = 0;
     int* tile_count = nullptr;
@@ -278,6 +280,18 @@ void hr_scene_destroy(hr_scene* s)
 }
 
 int64_t hr_num_pixels(const hr_scene* s) { return s ? s->n_pixels : -1; }
+
+// First bin and bins per row of every view for the scene's bin size (host copy).
+static void layout_bins(hr_scene* s)
+{
+    const int lb = s->bin_log2;
+    long long n = 0;
+    for (ViewDev& d : s->views_host) {
+        d.bin0 = (int)n;
+        d.nbx = (d.W + (1 << lb) - 1) >> lb;
+        n += (long long)d.nbx * ((d.H + (1 << lb) - 1) >> lb);
+    }
+}
 
 int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, const hr_camera* cams,
                     int32_t n_views, const hr_config* cfg)
@@ -465,7 +479,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         ts.rounds = (cfg->spp + 63) / 64;
         std::vector<int2> chunks;
         std::vector<int> vco(1, 0);
-        long long pix = 0;
+        long long pix = 0, bin_cap = 0;
         for (int v = 0; v < n_views; ++v) {
             const hr_camera& c = cams[v];
             ViewDev d;
@@ -474,12 +488,14 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
             d.W = c.W; d.H = c.H; d.hand = c.hand;
             d.sid = cfg->view_base + (uint32_t)v;
-            d.bin0 = s->n_bins;
-            d.nbx = (c.W + (1 << kBinLog2) - 1) >> kBinLog2;
-            s->n_bins += d.nbx * ((c.H + (1 << kBinLog2) - 1) >> kBinLog2);
+            // bins: room for the smallest bin size; tiles: for the shape with the most tiles
+            bin_cap += ((c.W + (1 << kMinBinLog2) - 1) >> kMinBinLog2) * ((c.H + (1 << kMinBinLog2) - 1) >> kMinBinLog2);
             d.pix0 = pix;
-            s->tile_cap += (long long)((c.W + (1 << ts.tw_log2) - 1) >> ts.tw_log2) *
-                           ((c.H + (1 << ts.th_log2) - 1) >> ts.th_log2);
+            long long tmax = 0;
+            for (int tw = 0; tw <= ppw_log2; ++tw)
+                tmax = std::max(tmax, (long long)((c.W + (1 << tw) - 1) >> tw) *
+                                          ((c.H + (1 << (ppw_log2 - tw)) - 1) >> (ppw_log2 - tw)));
+            s->tile_cap += tmax;
             const long long np = (long long)c.W * c.H;
             for (long long p0 = 0; p0 < np; p0 += kLossChunk) chunks.push_back(make_int2(v, (int)p0));
             vco.push_back((int)chunks.size());
@@ -487,6 +503,8 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             s->views_host.push_back(d);
         }
         s->n_pixels = pix;
+        s->bin_cap = bin_cap;
+        layout_bins(s);
         s->n_chunks = (int)chunks.size();
         s->max_blocks = (int)std::max<long long>(1, std::min<long long>(kMaxTraceBlocks, (s->tile_cap + 3) / 4));
         s->render_blocks = s->adjoint_blocks = std::min(2048, s->max_blocks);
@@ -511,8 +529,9 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     {   // screen bins: entries for each triangle in up to 16 bins per view on average
         BinDev& bd = s->bins;
         bd.cap = 16 * F;
-        TRY(s->upload<int>(&bd.count, nullptr, (size_t)s->n_bins));
-        TRY(s->upload<int>(&bd.off, nullptr, (size_t)s->n_bins));
+        bd.log2 = s->bin_log2;
+        TRY(s->upload<int>(&bd.count, nullptr, (size_t)s->bin_cap));
+        TRY(s->upload<int>(&bd.off, nullptr, (size_t)s->bin_cap));
         TRY(s->upload<uint16_t>(&bd.entries, nullptr, (size_t)n_views * bd.cap));
         TRY(s->upload<float4>(&bd.box, nullptr, (size_t)n_views * F));
         TRY(s->upload<int>(&bd.binned, nullptr, (size_t)n_views));
@@ -637,6 +656,7 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
 static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_tiles = true, bool with_scale = false,
                    const uint8_t* mask = nullptr)
 {
+    s->layout_changed = false;
     if (reset_tiles) {
         const int rc = launch(s, "k_set_i32", k_set_i32, dim3(1), dim3(64), 0, st, s->tile_count, 1, 0);
         if (rc) return rc;
@@ -896,7 +916,8 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
                          int* iter_advance = nullptr)
 {
     int rc;
-    if (!(flags & HR_REUSE_GEOMETRY)) {
+    // reuse needs a preparation with the current work layout
+    if (!(flags & HR_REUSE_GEOMETRY) || s->layout_changed) {
         rc = prepare(s, verts, st);
         if (rc) return rc;
     }
@@ -1204,6 +1225,49 @@ int hr_set_accel(hr_scene* s, int32_t mode)
     return HR_OK;
 }
 
+// Wave-tile shape and screen-bin size.  Neither changes which samples are
+// drawn or how a pixel's samples are summed, so images are bit-identical for
+// every choice; the render's stored samples (kept by tile) are dropped.
+static int set_tiles(hr_scene* s, int tw_log2, int bin_log2)
+{
+    const int ppw = s->ts.tw_log2 + s->ts.th_log2;   // pixels per wave, log2
+    const int th_log2 = ppw - tw_log2;
+    if (tw_log2 < 0 || th_log2 < 0 || bin_log2 < kMinBinLog2 || bin_log2 > kMaxBinLog2 || tw_log2 > bin_log2 ||
+        th_log2 > bin_log2)
+        return fail(HR_EINVAL, "hr_set_tiles: tile 2^%d x 2^%d pixels in bins of 2^%d pixels is not available "
+                    "(tile sides 2^a x 2^b with a + b = %d, bins 2^%d .. 2^%d, a tile inside one bin)",
+                    tw_log2, th_log2, bin_log2, ppw, kMinBinLog2, kMaxBinLog2);
+    if (tw_log2 == s->ts.tw_log2 && bin_log2 == s->bin_log2) return HR_OK;
+    // work already enqueued reads the views' bin layout and the stored samples
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HR_EHIP, "hr_set_tiles: synchronize");
+    s->ts.tw_log2 = tw_log2;
+    s->ts.th_log2 = th_log2;
+    s->bin_log2 = bin_log2;
+    s->bins.log2 = bin_log2;
+    s->layout_changed = true;
+    layout_bins(s);
+    if (hipMemcpy(s->views, s->views_host.data(), sizeof(ViewDev) * s->views_host.size(), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess)
+        return fail(HR_EHIP, "hr_set_tiles: upload");
+    return HR_OK;
+}
+
+int hr_set_tiles(hr_scene* s, int32_t tile_w_log2, int32_t bin_log2)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_tiles: null scene");
+    return set_tiles(s, tile_w_log2, bin_log2);
+}
+
+int hr_get_tiles(const hr_scene* s, int32_t* out_host)
+{
+    if (!s || !out_host) return fail(HR_EINVAL, "hr_get_tiles: null argument");
+    out_host[0] = s->ts.tw_log2;
+    out_host[1] = s->ts.th_log2;
+    out_host[2] = s->bin_log2;
+    return HR_OK;
+}
+
 int hr_get_grid(const hr_scene* s, int32_t* blocks_host)
 {
     if (!s || !blocks_host) return fail(HR_EINVAL, "hr_get_grid: null argument");
@@ -1248,6 +1312,21 @@ int hr_tune(hr_scene* s, const hr_state* state, int32_t reps, int32_t* blocks_ho
         if (!r) (void)hipEventElapsedTime(ms, e0, e1);
         return r;
     };
+    // first the wave-tile shape and the bin size (render + adjoint at the
+    // current grids), then the render grid, then the adjoint grid
+    {
+        const int ppw = s->ts.tw_log2 + s->ts.th_log2;
+        int best_tw = s->ts.tw_log2, best_lb = s->bin_log2;
+        float best_ms = 3.4e38f;
+        for (int lb = kMinBinLog2; lb <= kMaxBinLog2 && !rc; ++lb)
+            for (int tw = std::max(0, ppw - lb); tw <= std::min(ppw, lb) && !rc; ++tw) {
+                rc = set_tiles(s, tw, lb);
+                float ms = 0.0f;
+                if (!rc) rc = measure(true, &ms);
+                if (!rc && ms < best_ms) { best_ms = ms; best_tw = tw; best_lb = lb; }
+            }
+        if (!rc) rc = set_tiles(s, best_tw, best_lb);
+    }
     static const int kCand[] = {256, 384, 512, 768, 1024, 1536, 2048, 3072, 4096};
     float best = 0.0f;
     int best_r = s->render_blocks, best_a = s->adjoint_blocks;

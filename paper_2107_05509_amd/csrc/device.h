@@ -40,7 +40,8 @@ struct ViewDev {            // one camera (see hr_camera)
     long long pix0;         // first pixel in packed buffers
 };
 
-constexpr int kBinLog2 = 4;         // screen bins of 16 x 16 pixels (wave tiles never straddle one)
+constexpr int kBinLog2 = 4;         // default screen bins of 16 x 16 pixels (wave tiles never straddle one)
+constexpr int kMinBinLog2 = 3, kMaxBinLog2 = 5;   // bin sizes the tuner may choose (8 .. 32 pixels)
 constexpr int kMaxBinsLds = 8192;   // bins of a view counted in LDS (larger views traverse the hierarchy)
 constexpr int kMaxBands = 16;       // depth bands per bin (fewer for views with many bins)
 constexpr int kMaxBinCells = 8192;  // (bin, band) cells counted in LDS

@@ -66,6 +66,7 @@ struct BinDev {
     float4* box;               // [n_views, F] padded screen bounds (x0, y0, x1, y1) per leaf slot
     int* binned;               // [n_views] 1: the view's bins are complete and valid
     int cap;                   // entries per view
+    int log2;                  // bins of 2^log2 x 2^log2 pixels (kMinBinLog2 .. kMaxBinLog2)
 };
 
 // wave tiles: a tile of 2^tw_log2 x 2^th_log2 pixels, 2^spp_log2 lanes per

@@ -658,7 +658,8 @@ __device__ void bin_view(const PrepArgs& a, int vi, float* dyn)
     __shared__ unsigned long long wtot[16];
     const ViewDev c = load_view(a.views, vi);
     const int V = a.m.V, F = a.m.F;
-    const int nbx = c.nbx, nby = (c.H + (1 << kBinLog2) - 1) >> kBinLog2, nb = nbx * nby;
+    const int lb = a.bins.log2;
+    const int nbx = c.nbx, nby = (c.H + (1 << lb) - 1) >> lb, nb = nbx * nby;
     if (nb > kMaxBinsLds || !a.with_bins) {   // uniform over the block
         if (threadIdx.x == 0) a.bins.binned[vi] = 0;
         return;
@@ -712,10 +713,10 @@ __device__ void bin_view(const PrepArgs& a, int vi, float* dyn)
         bx.w = fmaxf(fmaxf(p0[1], p1[1]), p2[1]) + pad;
         band = min(nband - 1, max(0, (int)((fminf(fminf(p0[2], p1[2]), p2[2]) - zlo) * zscale)));
         if (bx.z < 0.0f || bx.w < 0.0f || bx.x > (float)c.W || bx.y > (float)c.H) return false;
-        x0 = max(0, (int)floorf(bx.x)) >> kBinLog2;
-        y0 = max(0, (int)floorf(bx.y)) >> kBinLog2;
-        x1 = min(c.W - 1, (int)floorf(bx.z)) >> kBinLog2;
-        y1 = min(c.H - 1, (int)floorf(bx.w)) >> kBinLog2;
+        x0 = max(0, (int)floorf(bx.x)) >> lb;
+        y0 = max(0, (int)floorf(bx.y)) >> lb;
+        x1 = min(c.W - 1, (int)floorf(bx.z)) >> lb;
+        y1 = min(c.H - 1, (int)floorf(bx.w)) >> lb;
         return true;
     };
     for (int i = threadIdx.x; i < F; i += blockDim.x) {
@@ -921,7 +922,7 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
         int bcnt = 0;
         const uint16_t* bent = nullptr;
         if (binned) {
-            const int bb = c.bin0 + (tx0 >> kBinLog2) + (ty0 >> kBinLog2) * c.nbx;
+            const int bb = c.bin0 + (tx0 >> a.bins.log2) + (ty0 >> a.bins.log2) * c.nbx;
             bcnt = __builtin_amdgcn_readfirstlane(a.bins.count[bb]);
             bent = a.bins.entries + (size_t)e.x * a.bins.cap + __builtin_amdgcn_readfirstlane(a.bins.off[bb]);
         }
