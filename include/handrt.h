@@ -323,6 +323,28 @@ int hr_get_grid(const hr_scene* scene, int32_t* blocks_host);   /* (render, adjo
    writes (a, b, bin_log2) to out_host (HOST, 3 ints).  HR_EINVAL: a shape or
    bin size outside these rules. */
 int hr_set_tiles(hr_scene* scene, int32_t tile_w_log2, int32_t bin_log2);
+
+/* Renderer of the camera samples.  HR_RENDERER_RAY (default): the Monte Carlo
+   ray tracer above.  HR_RENDERER_RASTER: hard rasterisation, the comparison
+   renderer of Section 4.2.2 ("Ray tracing vs rasterization"): each pixel
+   takes the colour of the nearest triangle covering its centre (edge
+   functions of the projected vertices, either orientation, all >= 0 or all
+   <= 0 with a non-zero sum; nearest = the largest perspective-correct 1/z
+   rounded to float32, ties to the smaller triangle index; triangles with a
+   vertex less than 1 mm in front of the camera are dropped; float64
+   projection, edge functions and 1/z), or its background; the shading is
+   the ray tracer's at the pixel centre.  Its gradient flows through the
+   covering triangles' interpolation only: hr_backward and hr_iterate ignore
+   HR_GRAD_EDGES (coverage is piecewise constant), and hr_backward without
+   HR_REUSE_GEOMETRY renders the covering triangles first (into a scratch
+   image of the scene).  hit_face of hr_render holds each pixel's covering
+   triangle.  The raster mode needs a scene of spp = 1 (HR_EUNSUPPORTED
+   otherwise); the first switch to it allocates the scratch image.
+   Synchronises the device; graphs keep the renderer they were captured
+   with.  HR_EINVAL: unknown mode. */
+#define HR_RENDERER_RAY 0
+#define HR_RENDERER_RASTER 1
+int hr_set_renderer(hr_scene* scene, int32_t mode);
 int hr_get_tiles(const hr_scene* scene, int32_t* out_host);
 int hr_tune(hr_scene* scene, const hr_state* state, int32_t reps, int32_t* blocks_host, void* stream);
 

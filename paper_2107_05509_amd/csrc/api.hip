@@ -110,6 +110,8 @@ struct hr_scene {
     BinDev bins{};                // screen bins of the camera rays (built by the preparation launch)
     int bin_log2 = kBinLog2;      // bins of 2^bin_log2 pixels square
     bool layout_changed = false;  // hr_set_tiles since the last preparation
+    int renderer = HR_RENDERER_RAY;
+    float* raster_image = nullptr;   // [P,3] hard rasterisation: image of a stand-alone backward's render
     long long bin_cap = 0;        // bins of all views at the smallest bin size
     int accel = HR_ACCEL_AUTO;
     long long tile_cap = 0;
@@ -716,9 +718,10 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
     a.bins = s->bins;
+    a.raster = s->renderer == HR_RENDERER_RASTER ? 1 : 0;
     const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
     const dim3 grid(s->render_blocks);
-    const int with_edges = n_edge > 0 ? 1 : 0;
+    const int with_edges = n_edge > 0 && !a.raster ? 1 : 0;
     if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, with_edges);
     return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
 }
@@ -916,6 +919,17 @@ static int backward_impl(hr_scene* s, const float* params, const float* verts, c
                          int* iter_advance = nullptr)
 {
     int rc;
+    if (s->renderer == HR_RENDERER_RASTER) {
+        // hard rasterisation: no visibility (edge) term; the covering triangles
+        // come from a render of these vertices (into the scene's scratch image
+        // unless the caller's render of the same geometry is reused)
+        flags &= ~HR_GRAD_EDGES;
+        if (!(flags & HR_REUSE_GEOMETRY) || s->layout_changed) {
+            rc = render_impl(s, verts, albedo, background, iter, iter_dev, s->raster_image, nullptr, st);
+            if (rc) return rc;
+            flags |= HR_REUSE_GEOMETRY;
+        }
+    }
     // reuse needs a preparation with the current work layout
     if (!(flags & HR_REUSE_GEOMETRY) || s->layout_changed) {
         rc = prepare(s, verts, st);
@@ -1097,7 +1111,8 @@ static int proposal_train_impl(hr_scene* s, hipStream_t st)
 static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cfg, uint32_t flags, hipStream_t st)
 {
     const int* it = q->iter;
-    const bool learned = (flags & HR_GRAD_EDGES) && s->prop_kind == HR_PROPOSAL_LEARNED;
+    const bool raster = s->renderer == HR_RENDERER_RASTER;
+    const bool learned = (flags & HR_GRAD_EDGES) && !raster && s->prop_kind == HR_PROPOSAL_LEARNED;
     const bool train = learned && !s->prop.z_override && s->prop.lr > 0.0f;
     auto join = [&](hipEvent_t ev) -> int {
         if (hipEventRecord(ev, s->side) != hipSuccess || hipStreamWaitEvent(st, ev, 0) != hipSuccess)
@@ -1111,7 +1126,7 @@ static int iterate_impl(hr_scene* s, const hr_state* q, const hr_adam_config* cf
     // the loss partial sums beside it, the geometry backward with the loss
     // values and both Adam steps; training of a learned proposal on the side
     // stream beside the geometry backward
-    const bool edges = (flags & HR_GRAD_EDGES) != 0;
+    const bool edges = (flags & HR_GRAD_EDGES) != 0 && !raster;   // hard rasterisation has no edge term
     int rc = launch(s, "k_skin", k_skin, dim3(s->skin_blocks, s->n_hands), dim3(128), 0, st, s->mesh,
                     (const float*)q->params, q->verts, (float*)nullptr, s->tile_count, s->joint_state);
     if (!rc) rc = prepare(s, q->verts, st, false, true, q->mask);
@@ -1250,6 +1265,24 @@ static int set_tiles(hr_scene* s, int tw_log2, int bin_log2)
             hipSuccess ||
         hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess)
         return fail(HR_EHIP, "hr_set_tiles: upload");
+    return HR_OK;
+}
+
+int hr_set_renderer(hr_scene* s, int32_t mode)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_renderer: null scene");
+    if (mode != HR_RENDERER_RAY && mode != HR_RENDERER_RASTER) return fail(HR_EINVAL, "hr_set_renderer: unknown mode %d", mode);
+    if (mode == HR_RENDERER_RASTER && s->cfg.spp != 1)
+        return fail(HR_EUNSUPPORTED, "hr_set_renderer: hard rasterisation takes one sample per pixel (spp %d)", s->cfg.spp);
+    if (mode == s->renderer) return HR_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(HR_EHIP, "hr_set_renderer: synchronize");
+    if (mode == HR_RENDERER_RASTER && !s->raster_image) {
+        const int rc = s->upload<float>(&s->raster_image, nullptr, (size_t)s->n_pixels * 3);
+        if (rc) return rc;
+    }
+    s->renderer = mode;
+    // the stored samples belong to the other renderer
+    if (hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess) return fail(HR_EHIP, "hr_set_renderer: memset");
     return HR_OK;
 }
 

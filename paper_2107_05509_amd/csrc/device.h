@@ -586,6 +586,108 @@ __device__ __forceinline__ void ray_dir64(const ViewDev& c, double X, double Y, 
     for (int k = 0; k < 3; ++k) d[k] = (double)c.R[k] * dcx + (double)c.R[3 + k] * dcy + (double)c.R[6 + k];
 }
 
+// Hard rasterisation (the comparison renderer of Section 4.2.2, "Ray tracing
+// vs rasterization"): one sample at the pixel centre, the triangle covering it
+// with the largest perspective-correct 1/z wins.  Coverage: the edge functions
+// E(a, b, p) = (b.x - a.x)(p.y - a.y) - (b.y - a.y)(p.x - a.x) of the edges
+// (v1, v2), (v2, v0), (v0, v1) are all >= 0 or all <= 0 with a non-zero sum
+// (no culling; a centre on a shared edge is covered by both triangles);
+// triangles with a vertex less than 1 mm in front of the camera are dropped;
+// 1/z = (E0/z0 + E1/z1 + E2/z2) / (E0 + E1 + E2), compared rounded to
+// float32, ties to the smaller triangle index.  Projection, edge functions and
+// 1/z in float64 from the float32 vertices, each expression in one fixed
+// order (no contraction), so the covering triangle is reproducible exactly.
+constexpr uint64_t kCentreWord = 0x8000000080000000ull;   // sample word with u = v = 1/2
+constexpr double kRasterNear = 1e-3;
+
+__device__ __forceinline__ void raster_project(const ViewDev& c, const float v[3], double& px, double& py,
+                                               double& z)
+{
+    const double q0 = (double)v[0] - (double)c.o[0], q1 = (double)v[1] - (double)c.o[1];
+    const double q2 = (double)v[2] - (double)c.o[2];
+    const double x = ((double)c.R[0] * q0 + (double)c.R[1] * q1) + (double)c.R[2] * q2;
+    const double y = ((double)c.R[3] * q0 + (double)c.R[4] * q1) + (double)c.R[5] * q2;
+    z = ((double)c.R[6] * q0 + (double)c.R[7] * q1) + (double)c.R[8] * q2;
+    px = ((double)c.fx * x) / z + (double)c.cx;
+    py = ((double)c.fy * y) / z + (double)c.cy;
+}
+
+__device__ __forceinline__ double raster_edge(double ax, double ay, double bx, double by, double px, double py)
+{
+    return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+// Covering triangle of pixel centre (X, Y) among `cnt` listed leaf slots
+// (`ent`, or slots 0 .. cnt-1 when null; `box` the slots' padded screen bounds
+// against the tile rectangle [x0, x1] x [y0, y1], or no bound test when
+// null).  The calling lanes load the list together, as trace_bins does.
+template <bool COUNT>
+__device__ __forceinline__ void raster_list(const Tri* __restrict__ tris, const uint16_t* __restrict__ ent, int cnt,
+                                            const float4* __restrict__ box, float x0, float y0, float x1, float y1,
+                                            const ViewDev& c, double X, double Y, bool active, Hit& h,
+                                            TraceCount* tc = nullptr)
+{
+    h.face = -1;
+    h.slot = 0;
+    h.t = 0.0f;
+    uint32_t bk = 0u;   // float32 bits of the best 1/z (0: none)
+    int bf = 0x7fffffff;
+    tris = uniform_ptr(tris);
+    const uint64_t exec = wave_mask(true);
+    const int ncall = __popcll(exec);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(exec >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)exec, 0u));
+    for (int c0 = 0; c0 < cnt; c0 += ncall) {
+        int slot = 0;
+        bool touch = false;
+        float4 q0 = make_float4(0.0f, 0.0f, 0.0f, 0.0f), q1 = q0, q2 = q0;
+        if (c0 + rank < cnt) {
+            slot = ent ? (int)ent[c0 + rank] : c0 + rank;
+            const Tri& tr = tris[slot];
+            q0 = *reinterpret_cast<const float4*>(&tr.v[0]);
+            q1 = *reinterpret_cast<const float4*>(&tr.v[4]);
+            q2 = *reinterpret_cast<const float4*>(&tr.v[8]);
+            touch = true;
+            if (box) {
+                const float4 b = box[slot];
+                touch = b.x <= x1 && b.z >= x0 && b.y <= y1 && b.w >= y0;
+            }
+        }
+        uint64_t m = wave_mask(touch);
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            const int s = __builtin_amdgcn_readlane(slot, l);
+            auto rl = [l](float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); };
+            const float v0[3] = {rl(q0.x), rl(q0.y), rl(q0.z)};
+            const float v1[3] = {rl(q0.w), rl(q1.x), rl(q1.y)};
+            const float v2[3] = {rl(q1.z), rl(q1.w), rl(q2.x)};
+            const int face = __builtin_amdgcn_readlane(__float_as_int(q2.y), l);
+            if (COUNT && active) { tc->nodes++; tc->nodes_w++; tc->tris++; tc->tris_w++; }
+            double ax, ay, az, bx, by, bz, cx, cy, cz;
+            raster_project(c, v0, ax, ay, az);
+            raster_project(c, v1, bx, by, bz);
+            raster_project(c, v2, cx, cy, cz);
+            if (!(az > kRasterNear && bz > kRasterNear && cz > kRasterNear)) continue;   // uniform
+            const double e0 = raster_edge(bx, by, cx, cy, X, Y);
+            const double e1 = raster_edge(cx, cy, ax, ay, X, Y);
+            const double e2 = raster_edge(ax, ay, bx, by, X, Y);
+            const double area = (e0 + e1) + e2;
+            const bool in = ((e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) || (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0)) &&
+                            area != 0.0;
+            if (!(active && in)) continue;
+            const double zinv = ((e0 / az + e1 / bz) + e2 / cz) / area;
+            const uint32_t key = __float_as_uint((float)zinv);
+            if (key > bk || (key == bk && face < bf)) {
+                bk = key;
+                bf = face;
+                h.face = face;
+                h.slot = s;
+            }
+        }
+    }
+}
+
 // barycentrics of the hit on triangle `slot` for the float64 ray (o, d):
 // o + t d = (1-b1-b2) v0 + b1 v1 + b2 v2 by Cramer's rule
 __device__ __forceinline__ void surface(const Tri* __restrict__ tris, const float* __restrict__ uv, int slot,

@@ -107,6 +107,7 @@ struct RenderArgs {
     const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`
     uint64_t seed;
     Shading shading;
+    int raster;                // 1: hard rasterisation (one sample at each pixel centre, no edge samples)
 };
 
 struct AdjointArgs {

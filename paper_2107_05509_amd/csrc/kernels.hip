@@ -938,15 +938,22 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
             float u = 0.0f, v = 0.0f;
             uint64_t wd = 0;
             if (act && !empty) {
-                const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
-                wd = pick(rr, s & 3);
+                if (a.raster) {
+                    wd = kCentreWord;
+                } else {
+                    const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
+                    wd = pick(rr, s & 3);
+                }
                 u = u24_lo(wd);
                 v = u24_hi(wd);
             }
             Hit h;
             h.face = -1;
             h.slot = 0;
-            if (!empty) {
+            if (!empty && a.raster) {
+                raster_list<COUNT>(tris, binned ? bent : nullptr, binned ? bcnt : a.n_faces, binned ? bbox : nullptr,
+                                   rx0, ry0, rx1, ry1, c, (double)px + 0.5, (double)py + 0.5, act, h, &tc);
+            } else if (!empty) {
                 Ray ray;
                 ray_screen(c, (float)px + u, (float)py + v, ray);
                 if (binned)
