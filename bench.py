@@ -194,18 +194,25 @@ def bench_batched(args):
 def bench_proposal(args):
     """Learned edge proposal against length-proportional sampling on the
     realistic workload: (1) refinement with the proposal trained online
-    (iterations/s with and without it); (2) at the final pose, the spread of the
-    boundary term's 64-parameter gradient over 256 sample keys at the same
-    edge-sample budget (trace of the covariance; the means must agree within
-    their standard errors: unbiasedness); (3) loss trajectories of both
-    samplers from the same start."""
+    (iterations/s), for the learned proposal also at half the edge-sample
+    budget (one sample per two pixels of silhouette); (2) at the learned run's
+    final pose, the spread of the boundary term's 64-parameter gradient over
+    256 sample keys (trace of the covariance over the 61 free parameters; the
+    means must agree within their standard errors: unbiasedness), for length
+    sampling at the full budget and the learned proposal at the full and at
+    half the budget; (3) loss trajectories.  Refine/s at equal variance:
+    the learned proposal at the budget whose covariance matches length
+    sampling's at the full budget."""
     w = scene.workload_realistic(args.seed)
     n_iter = 200
     out = {"metric": "learned edge proposal: gradient variance ratio and refine iters/s", "unit": "ratio",
            "config": {"workload": w.name, "iterations": n_iter, "seeds": 256}}
+    runs = (("length", 256), ("learned", 256), ("learned", 512))
     traj, refs = {}, {}
-    for kind in ("length", "learned"):
+    for kind, div in runs:
+        name = kind if div == 256 else f"{kind}_half_budget"
         ref = make_refiner(w, seed=args.seed, tune=False)
+        ref.scene.set_edge_budget(div)
         if kind == "learned":
             ref.scene.proposal_set(binding.HR_PROPOSAL_LEARNED, scene.mlp_init(args.seed), lr=3e-3, ema=0.9)
         ref.run(5)
@@ -216,11 +223,11 @@ def bench_proposal(args):
             ref.run(10)
             losses.append(float(ref.loss.item()))
         dt = time.perf_counter() - t0
-        traj[kind] = losses
-        out[f"{kind}_iters_per_s"] = round(n_iter / dt, 2)
-        refs[kind] = ref
-        print(f"[bench] {kind}: {n_iter / dt:.1f} it/s, loss {losses[-1]:.5f}", file=sys.stderr, flush=True)
-    # gradient spread at the learned run's final state, both samplers
+        traj[name] = losses
+        out[f"{name}_iters_per_s"] = round(n_iter / dt, 2)
+        refs[name] = ref
+        print(f"[bench] {name}: {n_iter / dt:.1f} it/s, loss {losses[-1]:.5f}", file=sys.stderr, flush=True)
+    # gradient spread at the learned run's final state
     ref = refs["learned"]
     g_learned = ref.scene
     th, tw = w.albedo_true.shape[1:3]
@@ -233,23 +240,28 @@ def bench_proposal(args):
     gp = torch.empty_like(q.params)
     ga = torch.empty_like(q.albedo)
     res = {}
-    for kind, g in (("length", g_length), ("learned", g_learned)):
+    for name, g, div in (("length", g_length, 256), ("learned", g_learned, 256), ("learned_half_budget", g_learned, 512)):
+        g.set_edge_budget(div)
         rows = []
         for s in range(256):
             g.backward(q.params, q.verts, q.albedo, q.background, d, 5000 + s, gp, ga, flags=binding.HR_GRAD_EDGES)
             rows.append(gp[0].double().cpu().numpy())
-        res[kind] = np.array(rows)
+        res[name] = np.array(rows)
+    g_learned.set_edge_budget(256)
+    free = np.r_[3:64]
     mu = {k: v.mean(0) for k, v in res.items()}
     se = {k: v.std(0, ddof=1) / np.sqrt(len(v)) for k, v in res.items()}
-    zscore = np.abs(mu["learned"] - mu["length"]) / np.sqrt(se["learned"] ** 2 + se["length"] ** 2 + 1e-300)
-    free = np.r_[3:64]
     tr = {k: float(np.trace(np.cov(v[:, free].T))) for k, v in res.items()}
+    zs = {k: float((np.abs(mu[k] - mu["length"]) / np.sqrt(se[k] ** 2 + se["length"] ** 2 + 1e-300))[free].max())
+          for k in ("learned", "learned_half_budget")}
     out["value"] = round(tr["length"] / tr["learned"], 3)
     out["trace_cov"] = tr
     out["variance_ratio_length_over_learned"] = out["value"]
-    out["unbiasedness_max_abs_z"] = round(float(zscore[free].max()), 2)
-    out["loss_length"] = traj["length"]
-    out["loss_learned"] = traj["learned"]
+    out["variance_ratio_length_over_learned_half_budget"] = round(tr["length"] / tr["learned_half_budget"], 3)
+    out["unbiasedness_max_abs_z"] = {k: round(v, 2) for k, v in zs.items()}
+    out["equal_variance_iters_per_s"] = {"length_full_budget": out["length_iters_per_s"],
+                                         "learned_half_budget": out["learned_half_budget_iters_per_s"]}
+    out["loss"] = traj
     print(json.dumps(out), flush=True)
 
 

@@ -342,6 +342,15 @@ int hr_set_tiles(hr_scene* scene, int32_t tile_w_log2, int32_t bin_log2);
    otherwise); the first switch to it allocates the scratch image.
    Synchronises the device; graphs keep the renderer they were captured
    with.  HR_EINVAL: unknown mode. */
+/* Edge-sample budget (Section 4.2.2): each view draws ceil(T / units)
+   samples, T its total quantised silhouette length in 1/256 pixel; the
+   default units = 256 draws one sample per pixel of silhouette.  Every
+   budget gives an unbiased estimate (stratified samples, each weighted by
+   its stratum); fewer samples, more variance.  Takes effect with the next
+   preparation; graphs keep the budget they were captured with.  HR_EINVAL:
+   units outside 1 .. 2^20. */
+int hr_set_edge_budget(hr_scene* scene, int32_t units_per_sample);
+
 #define HR_RENDERER_RAY 0
 #define HR_RENDERER_RASTER 1
 int hr_set_renderer(hr_scene* scene, int32_t mode);

@@ -111,6 +111,7 @@ struct hr_scene {
     int bin_log2 = kBinLog2;      // bins of 2^bin_log2 pixels square
     bool layout_changed = false;  // hr_set_tiles since the last preparation
     int renderer = HR_RENDERER_RAY;
+    int edge_div = 256;           // quantised silhouette length (1/256 px) per edge sample
     float* raster_image = nullptr;   // [P,3] hard rasterisation: image of a stand-alone backward's render
     long long bin_cap = 0;        // bins of all views at the smallest bin size
     int accel = HR_ACCEL_AUTO;
@@ -759,7 +760,7 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
     EdgeArgs a;
     a.m = s->mesh; a.views = s->views; a.verts = verts;
     a.rec = s->edge_rec; a.cdf = s->edge_cdf; a.total = s->edge_total; a.budget = s->edge_budget;
-    a.prefix = s->edge_prefix; a.n_views = s->n_views;
+    a.prefix = s->edge_prefix; a.n_views = s->n_views; a.budget_div = s->edge_div;
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
     a.stat_a = nullptr; a.stat_dc = nullptr;
@@ -1265,6 +1266,15 @@ static int set_tiles(hr_scene* s, int tw_log2, int bin_log2)
             hipSuccess ||
         hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess)
         return fail(HR_EHIP, "hr_set_tiles: upload");
+    return HR_OK;
+}
+
+int hr_set_edge_budget(hr_scene* s, int32_t units_per_sample)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_edge_budget: null scene");
+    if (units_per_sample < 1 || units_per_sample > (1 << 20))
+        return fail(HR_EINVAL, "hr_set_edge_budget: %d outside 1 .. 2^20", units_per_sample);
+    s->edge_div = units_per_sample;
     return HR_OK;
 }
 

@@ -167,6 +167,7 @@ struct EdgeArgs {
     unsigned long long* cdf;   // [n_views,E]
     unsigned long long* total; // [n_views]
     long long* budget;         // [n_views]
+    int budget_div;            // quantised length (1/256 px) per edge sample: budget = ceil(total / budget_div)
     long long* prefix;         // [n_views+1] exclusive prefix of budgets
     int n_views;
 

@@ -1522,7 +1522,8 @@ __device__ void edges_setup_view(const EdgeArgs& a, int vi, unsigned long long* 
     }
     if (threadIdx.x == blockDim.x - 1) {
         a.total[vi] = incl;
-        a.budget[vi] = (long long)((incl + 255ull) / 256ull);
+        const unsigned long long div = (unsigned long long)a.budget_div;
+        a.budget[vi] = (long long)((incl + div - 1ull) / div);
         __threadfence();
         last = atomicAdd(done, 1) == a.n_views - 1;
     }

@@ -153,6 +153,46 @@ def test_edge_term_parity(tiny):
     _check_params(g["gp"], o["gp"])
 
 
+def test_edge_budget(tiny):
+    # hr_set_edge_budget: ceil(T / units) samples per view with the oracle's
+    # totals T; the estimate stays unbiased: the means over sample keys at
+    # the full budget and at a quarter of it agree within their standard errors
+    c = tiny
+    img = f32(c.oracle_render(0))
+    d = _dimage(c, img)
+    _, _, tot_o, _ = oracle.edge_weights(c.osc, c.v32.astype(np.float64))
+    gv = torch.empty(1, c.model.n_verts, 3, device=DEV)
+    gp = torch.empty(1, 64, device=DEV)
+    ga = torch.empty(1, c.th, c.tw, 3, device=DEV)
+
+    def draws(units, n):
+        c.gsc.set_edge_budget(units)
+        rows = []
+        for k in range(n):
+            c.gsc.backward(c.t(c.params), c.t(c.v32), c.t(c.albedo), c.t(c.bg), c.t(d), 100 + k, gp, ga, gv, None,
+                           binding.HR_GRAD_EDGES)
+            torch.cuda.synchronize()
+            rows.append(gv.cpu().numpy().ravel().astype(np.float64))
+        tot, bud = c.gsc.edge_stats()
+        assert np.array_equal(tot, tot_o)
+        assert np.array_equal(bud, (tot_o.astype(np.int64) + units - 1) // units)
+        return np.array(rows)
+
+    try:
+        full = draws(256, 48)
+        quarter = draws(1024, 96)
+        with pytest.raises(binding.HRError):
+            c.gsc.set_edge_budget(0)
+    finally:
+        c.gsc.set_edge_budget(256)
+    mf, mq = full.mean(0), quarter.mean(0)
+    se = np.sqrt(full.var(0, ddof=1) / len(full) + quarter.var(0, ddof=1) / len(quarter))
+    big = np.abs(mf) > 0.05 * np.abs(mf).max()
+    z = np.abs(mq - mf)[big] / (se[big] + 1e-12 * np.abs(mf).max())
+    print("quarter vs full budget: max |z| over %d large entries %.2f" % (big.sum(), z.max()), flush=True)
+    assert big.sum() > 10 and z.max() < 5.0
+
+
 def _check_params(gp, op):
     blocks = {"pose": slice(0, 48), "shape": slice(48, 58), "global": slice(58, 64)}
     for name, sl in blocks.items():
