@@ -1043,12 +1043,12 @@ int hr_face_visibility(hr_scene* s, const int32_t* hit_face, int32_t* visible, v
 int hr_camera_order(hr_scene* s, const int32_t* visible, int32_t* order, int32_t* covered, void* stream)
 {
     if (!s || !visible || !order || !covered) return fail(HR_EINVAL, "hr_camera_order: null argument");
-    const size_t nwords = (size_t)(s->F + 31) / 32, nv = (size_t)s->max_views_per_hand;
-    const size_t smem = sizeof(unsigned int) * (nv * nwords + nwords + 2 * nv);
+    const size_t nwords = (size_t)(s->F + 31) / 32, nwp = (nwords + 3) & ~(size_t)3, nv = (size_t)s->max_views_per_hand;
+    const size_t smem = sizeof(unsigned int) * (nv * nwp + nwp + nv);
     if (smem > (size_t)kCoverLdsBytes)
         return fail(HR_EUNSUPPORTED, "hr_camera_order: the views' face bitmaps (%zu B) exceed %d B of LDS", smem,
                     kCoverLdsBytes);
-    return launch(s, "k_camera_order", k_camera_order, dim3(s->n_hands), dim3(256), smem, (hipStream_t)stream,
+    return launch(s, "k_camera_order", k_camera_order, dim3(s->n_hands), dim3(1024), smem, (hipStream_t)stream,
                   (const int*)visible, s->hand_view_off, s->hand_views, s->F, (int*)order, (int*)covered);
 }
 

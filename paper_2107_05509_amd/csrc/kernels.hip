@@ -2454,58 +2454,83 @@ __global__ void __launch_bounds__(256) k_face_visibility(const ViewDev* __restri
         for (unsigned int b = bits[i]; b; b &= b - 1u) out[32 * i + __builtin_ctz(b)] = 1;
 }
 
-// Greedy order of each hand's views by coverage (one block per hand, a thread
-// per view): step k takes the view that adds the most faces not seen by the
-// views taken before (ties: the earlier view in the hand's list);
-// order[off + k] is its view index, covered[off + k] the faces seen by the
-// first k + 1 views.  Dynamic LDS: the views' face bitmaps, the seen bitmap,
-// gains, taken flags.
-__global__ void __launch_bounds__(256) k_camera_order(const int* __restrict__ visible,
-                                                      const int* __restrict__ hand_view_off,
-                                                      const int* __restrict__ hand_views, int F,
-                                                      int* __restrict__ order, int* __restrict__ covered)
+// Greedy order of each hand's views by coverage (one block per hand): step k
+// takes the view that adds the most faces not seen by the views taken before
+// (ties: the earlier view in the hand's list); order[off + k] is its view
+// index, covered[off + k] the faces seen by the first k + 1 views.  The whole
+// block turns the views' face flags into LDS bitmaps (8-byte loads, many in
+// flight); then one wave runs the steps: a lane per candidate view counts its
+// new faces by popcounts against the seen bitmap, the wave maximum of
+// (gain, earlier view) picks the view, and the seen bitmap takes its bits, with
+// no block barrier inside the loop.  Dynamic LDS: the views' bitmaps, the seen
+// bitmap, taken flags.
+__global__ void __launch_bounds__(1024) k_camera_order(const int* __restrict__ visible,
+                                                       const int* __restrict__ hand_view_off,
+                                                       const int* __restrict__ hand_views, int F,
+                                                       int* __restrict__ order, int* __restrict__ covered)
 {
-    extern __shared__ unsigned int cs[];
-    __shared__ int best;
+    extern __shared__ __align__(16) unsigned int cs[];
     const int h = blockIdx.x, t = threadIdx.x;
     const int off = hand_view_off[h], nv = hand_view_off[h + 1] - off;
-    const int nwords = (F + 31) >> 5;
-    unsigned int* vb = cs;                                    // [nv * nwords]
-    unsigned int* seen = vb + (size_t)nv * nwords;            // [nwords]
-    int* gain = reinterpret_cast<int*>(seen + nwords);        // [nv]
-    int* taken = gain + nv;                                   // [nv]
-    for (int i = t; i < nv * nwords; i += blockDim.x) {
-        const int c = i / nwords, wd = i - c * nwords;
-        const int* v = visible + (size_t)hand_views[off + c] * F + 32 * wd;
-        const int nb = min(32, F - 32 * wd);
+    const int nwords = (F + 31) >> 5, nwp = (nwords + 3) & ~3;   // rows padded to 16 bytes
+    unsigned int* vb = cs;                                    // [nv * nwp]
+    unsigned int* seen = vb + (size_t)nv * nwp;               // [nwp]
+    int* taken = reinterpret_cast<int*>(seen + nwp);          // [nv]
+    // word wd of view c: faces 32 wd .. 32 wd + 31, read as pairs (a view's
+    // row starts at a multiple of 8 bytes when F is even; odd F reads singles)
+    for (int i = t; i < nv * nwp; i += blockDim.x) {
+        const int c = i / nwp, wd = i - c * nwp;
         unsigned int m = 0u;
-        for (int b = 0; b < nb; ++b) m |= (v[b] != 0 ? 1u : 0u) << b;
+        if (wd < nwords) {
+            const int* v = visible + (size_t)hand_views[off + c] * F + 32 * wd;
+            const int nb = min(32, F - 32 * wd);
+            if ((F & 1) == 0 && nb == 32) {
+                int2 q[16];
+#pragma unroll
+                for (int b = 0; b < 16; ++b) q[b] = reinterpret_cast<const int2*>(v)[b];
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    m |= (q[b].x != 0 ? 1u : 0u) << (2 * b) | (q[b].y != 0 ? 1u : 0u) << (2 * b + 1);
+            } else {
+                for (int b = 0; b < nb; ++b) m |= (v[b] != 0 ? 1u : 0u) << b;
+            }
+        }
         vb[i] = m;
     }
-    for (int i = t; i < nwords; i += blockDim.x) seen[i] = 0u;
+    for (int i = t; i < nwp; i += blockDim.x) seen[i] = 0u;
     for (int i = t; i < nv; i += blockDim.x) taken[i] = 0;
     __syncthreads();
+    if (t >= 64) return;   // one wave from here on
+    const int lane = t;
+    const uint4* vb4 = reinterpret_cast<const uint4*>(vb);
+    const uint4* seen4 = reinterpret_cast<const uint4*>(seen);
+    const int nq = nwp >> 2;
     int total = 0;
     for (int k = 0; k < nv; ++k) {
-        for (int c = t; c < nv; c += blockDim.x) {
+        // best key (gain << 16 | 0xffff - view) of the lane's candidates
+        // (gain < 2^15, views < 2^16), then the wave's on the DPP network
+        int key = -1;
+        for (int c = lane; c < nv; c += 64) {
+            if (taken[c]) continue;
             int cnt = 0;
-            for (int wd = 0; wd < nwords; ++wd) cnt += __popc(vb[(size_t)c * nwords + wd] & ~seen[wd]);
-            gain[c] = taken[c] ? -1 : cnt;
+            for (int q = 0; q < nq; ++q) {
+                const uint4 x = vb4[(size_t)c * nq + q], y = seen4[q];
+                cnt += __popc(x.x & ~y.x) + __popc(x.y & ~y.y) + __popc(x.z & ~y.z) + __popc(x.w & ~y.w);
+            }
+            key = max(key, (cnt << 16) | (0xffff - c));
         }
-        __syncthreads();
-        if (t == 0) {
-            int b = -1;
-            for (int c = 0; c < nv; ++c)
-                if (gain[c] >= 0 && (b < 0 || gain[c] > gain[b])) b = c;
-            best = b;
+        key = row_max(key);
+        key = max(max(__builtin_amdgcn_readlane(key, 0), __builtin_amdgcn_readlane(key, 16)),
+                  max(__builtin_amdgcn_readlane(key, 32), __builtin_amdgcn_readlane(key, 48)));
+        const int b = 0xffff - (key & 0xffff);
+        total += key >> 16;
+        if (lane == 0) {
             taken[b] = 1;
-            total += gain[b];
             order[off + k] = hand_views[off + b];
             covered[off + k] = total;
         }
-        __syncthreads();
-        for (int wd = t; wd < nwords; wd += blockDim.x) seen[wd] |= vb[(size_t)best * nwords + wd];
-        __syncthreads();
+        for (int wd = lane; wd < nwp; wd += 64) seen[wd] |= vb[(size_t)b * nwp + wd];
+        wave_lds_sync();   // the next step reads seen and taken
     }
 }
 
