@@ -159,6 +159,14 @@ int hr_build_hierarchy(hr_scene* scene, const float* verts, void* stream);
 int hr_render(hr_scene* scene, const float* verts, const float* albedo, const float* background,
               uint32_t iter, float* image, int32_t* hit_face, void* stream);
 
+/* While enabled (default off), hr_render also traces the edge samples' side
+   rays of its iteration (Section 4.2.2; they depend on the geometry only),
+   in the same launch, and a following hr_backward with HR_REUSE_GEOMETRY at
+   the same iter weighs them instead of tracing them again.  Worth it when
+   the backward follows each render (a loop with its own loss, such as the
+   full data term); hr_iterate does the same by itself. */
+int hr_set_render_edges(hr_scene* scene, int32_t enable);
+
 /* Photometric loss, per hand: E1 = sum over the hand's views of the mean of
    |image - target| over the view's masked pixels and the 3 channels
    (Eq. 3 with D_c of Eq. 4); dimage = dE1/dimage = sign(image - target) /

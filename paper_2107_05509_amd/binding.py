@@ -26,7 +26,7 @@ HR_ACCEL_HIERARCHY = 1
 
 EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
            "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
-           "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles", "hr_set_renderer", "hr_set_edge_budget", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
+           "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles", "hr_set_renderer", "hr_set_edge_budget", "hr_set_render_edges", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
            "hr_proposal_train", "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
            "hr_data_term_set", "hr_edge_map", "hr_loss_full", "hr_compose_albedo", "hr_albedo_low_grad", "hr_adam",
@@ -149,7 +149,7 @@ def lib():
                      "hr_face_visibility", "hr_camera_order",
                      "hr_step", "hr_iterate",
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles",
-                     "hr_set_renderer", "hr_set_edge_budget", "hr_get_grid", "hr_tune", "hr_edge_stats",
+                     "hr_set_renderer", "hr_set_edge_budget", "hr_set_render_edges", "hr_get_grid", "hr_tune", "hr_edge_stats",
                      "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
                      "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
                      "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
@@ -382,6 +382,10 @@ class Scene:
     def set_accel(self, mode):
         """HR_ACCEL_AUTO (screen bins for the camera rays) or HR_ACCEL_HIERARCHY."""
         _check(lib().hr_set_accel(self._h, int(mode)), "hr_set_accel")
+
+    def set_render_edges(self, enable):
+        """hr_render also traces the edge samples for a following reusing backward."""
+        _check(lib().hr_set_render_edges(self._h, int(bool(enable))), "hr_set_render_edges")
 
     def set_edge_budget(self, units_per_sample=256):
         """Edge samples per view = ceil(quantised silhouette length / units) (256: one per pixel)."""

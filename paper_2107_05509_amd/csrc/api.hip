@@ -112,6 +112,9 @@ struct hr_scene {
     bool layout_changed = false;  // hr_set_tiles since the last preparation
     int renderer = HR_RENDERER_RAY;
     int edge_div = 256;           // quantised silhouette length (1/256 px) per edge sample
+    bool render_edges = false;    // hr_render also traces the edge samples (hr_set_render_edges)
+    bool edges_valid = false;     // ... and has done so for the current preparation, at iteration edges_iter
+    uint32_t edges_iter = 0;
     float* raster_image = nullptr;   // [P,3] hard rasterisation: image of a stand-alone backward's render
     long long bin_cap = 0;        // bins of all views at the smallest bin size
     int accel = HR_ACCEL_AUTO;
@@ -660,6 +663,7 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_t
                    const uint8_t* mask = nullptr)
 {
     s->layout_changed = false;
+    s->edges_valid = false;   // a new geometry: the traced edge samples are stale
     if (reset_tiles) {
         const int rc = launch(s, "k_set_i32", k_set_i32, dim3(1), dim3(64), 0, st, s->tile_count, 1, 0);
         if (rc) return rc;
@@ -751,7 +755,28 @@ int hr_render(hr_scene* s, const float* verts, const float* albedo, const float*
               float* image, int32_t* hit_face, void* stream)
 {
     if (!s || !verts || !albedo || !background || !image) return fail(HR_EINVAL, "hr_render: null argument");
-    return render_impl(s, verts, albedo, background, iter, nullptr, image, hit_face, (hipStream_t)stream);
+    hipStream_t st = (hipStream_t)stream;
+    if (!s->render_edges || s->renderer == HR_RENDERER_RASTER)
+        return render_impl(s, verts, albedo, background, iter, nullptr, image, hit_face, st);
+    // the edge samples' side rays traced by the render launch, for a
+    // following hr_backward with HR_REUSE_GEOMETRY at the same iteration
+    int rc = prepare(s, verts, st);
+    if (!rc) rc = edge_trace_impl(s, verts, albedo, background, iter, nullptr, st, false);
+    if (!rc)
+        rc = render_impl(s, verts, albedo, background, iter, nullptr, image, hit_face, st, true, nullptr, nullptr,
+                         nullptr, nullptr, nullptr, kEdgeBlocks);
+    if (!rc) {
+        s->edges_valid = true;
+        s->edges_iter = iter;
+    }
+    return rc;
+}
+
+int hr_set_render_edges(hr_scene* s, int32_t enable)
+{
+    if (!s) return fail(HR_EINVAL, "hr_set_render_edges: null scene");
+    s->render_edges = enable != 0;
+    return HR_OK;
 }
 
 static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, const float* background,
@@ -1059,8 +1084,10 @@ int hr_backward(hr_scene* s, const float* params, const float* verts, const floa
     if (!s || !params || !verts || !albedo || !background || !dimage || !grad_params || !grad_albedo)
         return fail(HR_EINVAL, "hr_backward: null argument");
     if (flags & ~(HR_GRAD_ALL | HR_REUSE_GEOMETRY | HR_SKIP_PRIOR)) return fail(HR_EINVAL, "hr_backward: unknown flags");
+    // edge samples traced by the last hr_render (hr_set_render_edges) of this geometry and iteration
+    const bool traced = (flags & HR_REUSE_GEOMETRY) && s->edges_valid && s->edges_iter == iter && !s->layout_changed;
     return backward_impl(s, params, verts, albedo, background, dimage, iter, nullptr, flags, grad_params, grad_albedo,
-                         grad_verts, grad_normals, (hipStream_t)stream);
+                         grad_verts, grad_normals, (hipStream_t)stream, traced);
 }
 
 static int step_impl(hr_scene* s, float* params, float* albedo, const float* grad_params, const float* grad_albedo,
@@ -1634,7 +1661,7 @@ static DtArgs dt_args(hr_scene* s, const float* image, const float* T)
 // stages of B(Canny(T R)) up to the blur
 static int dt_canny(hr_scene* s, const DtArgs& a, hipStream_t st)
 {
-    const dim3 g(s->n_chunks), b(256);
+    const dim3 g(s->n_chunks, kDtSplit), b(256);
     int rc = launch(s, "k_dt_grey", k_dt_grey, g, b, 0, st, a);
     if (!rc) rc = launch(s, "k_dt_smooth", k_dt_smooth, g, b, 0, st, a);
     if (!rc) rc = launch(s, "k_dt_grad", k_dt_grad, g, b, 0, st, a);
@@ -1650,9 +1677,9 @@ int hr_edge_map(hr_scene* s, const float* image, const float* T, float* edge_map
     const hipStream_t st = (hipStream_t)stream;
     const DtArgs a = dt_args(s, image, T);
     int rc = dt_canny(s, a, st);
-    if (!rc) rc = launch(s, "k_dt_blur_col", k_dt_blur_col, dim3(s->n_chunks), dim3(256), 0, st, a, s->dt.g1);
+    if (!rc) rc = launch(s, "k_dt_blur_col", k_dt_blur_col, dim3(s->n_chunks, kDtSplit), dim3(256), 0, st, a, s->dt.g1);
     if (!rc)
-        rc = launch(s, "k_dt_blur", k_dt_blur<false>, dim3(s->n_chunks), dim3(256), 0, st, a, (const double*)s->dt.g1,
+        rc = launch(s, "k_dt_blur", k_dt_blur<false>, dim3(s->n_chunks, kDtSplit), dim3(256), 0, st, a, (const double*)s->dt.g1,
                     edge_map);
     return rc;
 }
@@ -1671,7 +1698,7 @@ int hr_loss_full(hr_scene* s, const float* image, const float* T, const float* t
     if (!rc) rc = launch(s, "k_dt_scale", k_dt_scale, dim3(s->n_views), dim3(256), 0, st, (const ViewDev*)s->views, mask,
                          s->view_scale);
     if (!rc) rc = dt_canny(s, a, st);
-    const dim3 g(s->n_chunks), b(256);
+    const dim3 g(s->n_chunks, kDtSplit), b(256);
     // the column pass writes g1 (free until the backward); the backward's
     // row pass writes the edge map's buffer (no longer read)
     if (!rc) rc = launch(s, "k_dt_blur_col", k_dt_blur_col, g, b, 0, st, a, s->dt.g1);

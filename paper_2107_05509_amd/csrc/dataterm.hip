@@ -43,6 +43,14 @@ struct DataTermDev {
     double low, high;    // thresholds
 };
 
+// The per-pixel kernels take a 4096-pixel chunk of a view per blockIdx.x
+// and split it over gridDim.y = kDtSplit blocks (one pixel per thread at 256
+// threads), so a whole image fills the GPU.
+#ifndef HR_DT_SPLIT
+#define HR_DT_SPLIT 8
+#endif
+constexpr int kDtSplit = HR_DT_SPLIT;
+
 struct DtArgs {
     const int2* chunks;        // (view, first pixel of the chunk in the view)
     const ViewDev* views;
@@ -94,7 +102,7 @@ __device__ __forceinline__ void dt_transform(const DtArgs& a, int view, long lon
 // stage 1: luma of r' = T R
 __global__ void __launch_bounds__(256) k_dt_grey(DtArgs a)
 {
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         double rp[3];
@@ -106,7 +114,7 @@ __global__ void __launch_bounds__(256) k_dt_grey(DtArgs a)
 // stage 2: 5x5 smoothing
 __global__ void __launch_bounds__(256) k_dt_smooth(DtArgs a)
 {
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         double acc = 0.0;
@@ -121,7 +129,7 @@ __global__ void __launch_bounds__(256) k_dt_grad(DtArgs a)
 {
     const double sx[9] = {-0.125, 0.0, 0.125, -0.25, 0.0, 0.25, -0.125, 0.0, 0.125};
     const double sy[9] = {-0.125, -0.25, -0.125, 0.0, 0.0, 0.0, 0.125, 0.25, 0.125};
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         double gx = 0.0, gy = 0.0;
@@ -141,7 +149,7 @@ __global__ void __launch_bounds__(256) k_dt_grad(DtArgs a)
 __global__ void __launch_bounds__(256) k_dt_suppress(DtArgs a)
 {
     const double tan1 = sqrt(2.0) - 1.0, tan2 = sqrt(2.0) + 1.0;
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         const double gx = a.d.gx[pg], gy = a.d.gy[pg], M = a.d.mag[pg];
@@ -160,7 +168,7 @@ __global__ void __launch_bounds__(256) k_dt_suppress(DtArgs a)
 // stage 5: one hysteresis step and the edge map
 __global__ void __launch_bounds__(256) k_dt_hyst(DtArgs a)
 {
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         const int f = a.d.flags[pg];
@@ -185,7 +193,7 @@ __global__ void __launch_bounds__(256) k_dt_hyst(DtArgs a)
 // map (unless it is an output).
 __global__ void __launch_bounds__(256) k_dt_blur_col(DtArgs a, double* tmp)
 {
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         double acc = 0.0;
@@ -200,7 +208,7 @@ __global__ void __launch_bounds__(256) k_dt_blur(DtArgs a, const double* tmp, fl
     __shared__ double red[2 * 4];
     const int view = a.chunks[blockIdx.x].x;
     double sc = 0.0, se = 0.0;
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         const bool on = !a.mask || a.mask[pg] != 0;
@@ -302,7 +310,7 @@ __device__ __forceinline__ double dt_adjoint1(const ViewDev& c, int x, int y, co
 // backward of the blur's row pass (transposed): into `tmp`
 __global__ void __launch_bounds__(256) k_dt_bwd_blur_row(DtArgs a, double* tmp)
 {
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         tmp[pg] = dt_adjoint1<5, 0>(c, x, y, a.d.w11s, a.d.gb);
@@ -313,7 +321,7 @@ __global__ void __launch_bounds__(256) k_dt_bwd_blur_row(DtArgs a, double* tmp)
 // magnitude at selected pixels: dE/dgx, dE/dgy
 __global__ void __launch_bounds__(256) k_dt_bwd_edge(DtArgs a, const double* tmp)
 {
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         const double gc = (a.d.flags[pg] & 4) ? dt_adjoint1<5, 1>(c, x, y, a.d.w11s, tmp) : 0.0;
@@ -328,7 +336,7 @@ __global__ void __launch_bounds__(256) k_dt_bwd_sobel(DtArgs a, double* out)
 {
     const double sx[9] = {-0.125, 0.0, 0.125, -0.25, 0.0, 0.25, -0.125, 0.0, 0.125};
     const double sy[9] = {-0.125, -0.25, -0.125, 0.0, 0.0, 0.0, 0.125, 0.25, 0.125};
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         out[pg] = dt_adjoint<1>(c, x, y, sx, a.d.g1) + dt_adjoint<1>(c, x, y, sy, a.d.g2);
@@ -343,7 +351,7 @@ __global__ void __launch_bounds__(256) k_dt_bwd_final(DtArgs a, const double* gs
     __shared__ double red[9 * 4];
     const int view = a.chunks[blockIdx.x].x;
     double gT[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = threadIdx.x; k < kLossChunk; k += blockDim.x) {
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
         const double g = dt_adjoint<2>(c, x, y, a.d.w5, gs);

@@ -162,6 +162,8 @@ class FullRefiner:
         self.lr_T, self.lr_low, self.lr_high, self.lr_params = lr_T, lr_low, lr_high, tuple(lr_params)
         self.it = 0
         g.data_term_set(w_edge, low, high)
+        # the render traces the edge samples that the reusing backward weighs
+        g.set_render_edges(True)
         self.target_edges = z(g.P)
         g.edge_map(target, None, self.target_edges)
 

@@ -267,3 +267,39 @@ def test_screen_bins_match_hierarchy(workload):
     assert np.array_equal(out[0][1], out[1][1])
     assert np.array_equal(out[0][0], out[1][0])
     assert (out[1][1] >= 0).mean() > 0.02
+
+
+def test_render_traced_edges_are_reused(tiny):
+    # hr_set_render_edges: hr_render traces the edge samples and a reusing
+    # backward at the same iteration weighs them: the same samples as the
+    # backward's own tracing, so the same gradient (float64 slots: equal up to
+    # the order of the atomic sums); a reusing backward at another iteration
+    # traces its own samples
+    c = tiny
+    img = f32(c.oracle_render(0))
+    d = _dimage(c, img)
+    flags = binding.HR_GRAD_EDGES | binding.HR_REUSE_GEOMETRY
+
+    def run(render_edges, it_render, it_backward):
+        c.gsc.set_render_edges(render_edges)
+        out = torch.empty(c.P, 3, device=DEV)
+        c.gsc.render(c.t(c.v32), c.t(c.albedo), c.t(c.bg), it_render, out)
+        gp = torch.empty(1, 64, device=DEV)
+        ga = torch.empty(1, c.th, c.tw, 3, device=DEV)
+        gv = torch.empty(1, c.model.n_verts, 3, device=DEV)
+        c.gsc.backward(c.t(c.params), c.t(c.v32), c.t(c.albedo), c.t(c.bg), c.t(d), it_backward, gp, ga, gv, None,
+                       flags)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), gv.cpu().numpy()
+
+    try:
+        img0, g0 = run(False, 3, 3)
+        img1, g1 = run(True, 3, 3)
+        _, g2 = run(True, 4, 3)      # the render's samples belong to iteration 4: traced again for 3
+        _, g4 = run(False, 4, 4)
+    finally:
+        c.gsc.set_render_edges(False)
+    assert np.array_equal(img0, img1)
+    assert block_rel(g1, g0) <= 1e-6
+    assert block_rel(g2, g0) <= 1e-6
+    assert block_rel(g4, g0) > 1e-3   # another iteration draws other samples
