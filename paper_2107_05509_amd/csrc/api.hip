@@ -1608,6 +1608,7 @@ int hr_data_term_set(hr_scene* s, const hr_data_term* cfg)
         if (!rc) rc = s->upload<double>(&d.w5, nullptr, 25);
         if (!rc) rc = s->upload<double>(&d.w11, nullptr, 121);
         if (!rc) rc = s->upload<double>(&d.w11s, nullptr, 11);
+        if (!rc) rc = s->upload<double>(&d.w5s, nullptr, 5);
         double* bufs[10];
         for (int k = 0; k < 10 && !rc; ++k) rc = s->upload<double>(&bufs[k], nullptr, P);
         if (!rc) rc = s->upload<uint8_t>(&d.flags, nullptr, P);
@@ -1637,9 +1638,17 @@ int hr_data_term_set(hr_scene* s, const hr_data_term* cfg)
             sum1 += w11s[k];
         }
         for (int k = 0; k < 11; ++k) w11s[k] /= sum1;
+        // the smoothing's factor: w5[i][j] = w5s[i] w5s[j]
+        double w5s[5], sum5 = 0.0;
+        for (int k = 0; k < 5; ++k) {
+            w5s[k] = std::exp(-(double)((k - 2) * (k - 2)) / 2.0);
+            sum5 += w5s[k];
+        }
+        for (int k = 0; k < 5; ++k) w5s[k] /= sum5;
         hipError_t e2 = hipMemcpy(d.w5, w5, sizeof(w5), hipMemcpyHostToDevice);
         if (e2 == hipSuccess) e2 = hipMemcpy(d.w11, w11, sizeof(w11), hipMemcpyHostToDevice);
         if (e2 == hipSuccess) e2 = hipMemcpy(d.w11s, w11s, sizeof(w11s), hipMemcpyHostToDevice);
+        if (e2 == hipSuccess) e2 = hipMemcpy(d.w5s, w5s, sizeof(w5s), hipMemcpyHostToDevice);
         if (e2 != hipSuccess) return fail(HR_EHIP, "hr_data_term_set: %s", hipGetErrorString(e2));
         s->dt_alloc = true;
     }
@@ -1706,7 +1715,9 @@ int hr_loss_full(hr_scene* s, const float* image, const float* T, const float* t
     if (!rc) rc = launch(s, "k_dt_bwd_blur_row", k_dt_bwd_blur_row, g, b, 0, st, a, s->dt.edge);
     if (!rc) rc = launch(s, "k_dt_bwd_edge", k_dt_bwd_edge, g, b, 0, st, a, (const double*)s->dt.edge);
     if (!rc) rc = launch(s, "k_dt_bwd_sobel", k_dt_bwd_sobel, g, b, 0, st, a, s->dt.sm);
-    if (!rc) rc = launch(s, "k_dt_bwd_final", k_dt_bwd_final, g, b, 0, st, a, (const double*)s->dt.sm, dimage);
+    // the smoothing's transpose: row pass into the Canny map's buffer (free by now), column pass in the final kernel
+    if (!rc) rc = launch(s, "k_dt_bwd_smooth_row", k_dt_bwd_smooth_row, g, b, 0, st, a, (const double*)s->dt.sm, s->dt.edge);
+    if (!rc) rc = launch(s, "k_dt_bwd_final", k_dt_bwd_final, g, b, 0, st, a, (const double*)s->dt.edge, dimage);
     if (!rc)
         rc = launch(s, "k_dt_finish", k_dt_finish, dim3(1), dim3(256), 0, st, a, (const int*)s->hand_view_off,
                     (const int*)s->hand_views, s->n_hands, s->n_views, loss, grad_T);

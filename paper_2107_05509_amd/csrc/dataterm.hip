@@ -24,6 +24,7 @@ namespace hr {
 
 struct DataTermDev {
     double* w5;          // [25] smoothing weights, row-major
+    double* w5s;         // [5] the smoothing's 1-D factor (its transpose runs as a row then a column pass)
     double* w11;         // [121] blur weights
     double* w11s;        // [11] the blur's 1-D factor (the blur runs as a column then a row pass)
     double* grey;        // [P] luma of r' = T R
@@ -343,9 +344,19 @@ __global__ void __launch_bounds__(256) k_dt_bwd_sobel(DtArgs a, double* out)
     }
 }
 
-// backward 3: through the smoothing (transposed, clamped) and the luma to
-// dE/dr', plus the colour term; then dE/dR = T^T dE/dr' and the per-view
-// sums of dE/dT = sum_p dE/dr'_p R_p^T
+// backward 3a: the smoothing's row pass, transposed: into `tmp`
+__global__ void __launch_bounds__(256) k_dt_bwd_smooth_row(DtArgs a, const double* gs, double* tmp)
+{
+    for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
+        ViewDev c; int x, y; long long pg;
+        if (!dt_pixel(a, k, c, x, y, pg)) break;
+        tmp[pg] = dt_adjoint1<2, 0>(c, x, y, a.d.w5s, gs);
+    }
+}
+
+// backward 3b: through the smoothing's column pass (transposed, from `gs`,
+// the row pass's output) and the luma to dE/dr', plus the colour term; then
+// dE/dR = T^T dE/dr' and the per-view sums of dE/dT = sum_p dE/dr'_p R_p^T
 __global__ void __launch_bounds__(256) k_dt_bwd_final(DtArgs a, const double* gs, float* dimage)
 {
     __shared__ double red[9 * 4];
@@ -354,7 +365,7 @@ __global__ void __launch_bounds__(256) k_dt_bwd_final(DtArgs a, const double* gs
     for (int k = blockIdx.y * blockDim.x + threadIdx.x; k < kLossChunk; k += blockDim.x * gridDim.y) {
         ViewDev c; int x, y; long long pg;
         if (!dt_pixel(a, k, c, x, y, pg)) break;
-        const double g = dt_adjoint<2>(c, x, y, a.d.w5, gs);
+        const double g = dt_adjoint1<2, 1>(c, x, y, a.d.w5s, gs);
         double grp[3] = {kGrey0 * g, kGrey1 * g, kGrey2 * g};
         if (!a.mask || a.mask[pg] != 0) {
             double rp[3];
