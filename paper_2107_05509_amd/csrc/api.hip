@@ -723,12 +723,16 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
     a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed; a.shading = shading_of(s->cfg);
     a.counts = s->counts;
     a.bins = s->bins;
-    a.raster = s->renderer == HR_RENDERER_RASTER ? 1 : 0;
+    const bool raster = s->renderer == HR_RENDERER_RASTER;   // hard rasterisation: its own kernel instantiation
     const EdgeArgs e = edge_args(s, verts, albedo, background, nullptr, iter, iter_dev);
     const dim3 grid(s->render_blocks);
-    const int with_edges = n_edge > 0 && !a.raster ? 1 : 0;
-    if (s->counting) return launch(s, "k_render", k_render<true>, grid, dim3(kThreads), 0, st, a, e, with_edges);
-    return launch(s, "k_render", k_render<false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
+    const int with_edges = n_edge > 0 && !raster ? 1 : 0;
+    if (raster) {
+        if (s->counting) return launch(s, "k_render", k_render<true, true>, grid, dim3(kThreads), 0, st, a, e, 0);
+        return launch(s, "k_render", k_render<false, true>, grid, dim3(kThreads), 0, st, a, e, 0);
+    }
+    if (s->counting) return launch(s, "k_render", k_render<true, false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
+    return launch(s, "k_render", k_render<false, false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
 }
 
 // Edge samples, first part: silhouette tables (unless done), learned sampling

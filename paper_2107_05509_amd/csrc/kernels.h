@@ -107,7 +107,6 @@ struct RenderArgs {
     const int* iter_dev;       // nullable: iteration index read on the device instead of `iter`
     uint64_t seed;
     Shading shading;
-    int raster;                // 1: hard rasterisation (one sample at each pixel centre, no edge samples)
 };
 
 struct AdjointArgs {

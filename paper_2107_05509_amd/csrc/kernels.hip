@@ -888,8 +888,10 @@ __device__ void render_side_work(const RenderArgs& a, int bid, int nb)
     }
 }
 
-// Wave tiles gw, gw + nw, ... (wave-uniform gw).
-template <bool COUNT>
+// Wave tiles gw, gw + nw, ... (wave-uniform gw).  RASTER: hard rasterisation
+// (a separate instantiation, so the ray tracer's register allocation does not
+// carry the rasteriser's float64 state).
+template <bool COUNT, bool RASTER>
 __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
@@ -938,7 +940,7 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
             float u = 0.0f, v = 0.0f;
             uint64_t wd = 0;
             if (act && !empty) {
-                if (a.raster) {
+                if (RASTER) {
                     wd = kCentreWord;
                 } else {
                     const U64x4 rr = philox4x64((uint64_t)pl, (uint64_t)(s >> 2), c2, iter, a.seed, 0);
@@ -950,10 +952,10 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
             Hit h;
             h.face = -1;
             h.slot = 0;
-            if (!empty && a.raster) {
+            if (RASTER && !empty) {
                 raster_list<COUNT>(tris, binned ? bent : nullptr, binned ? bcnt : a.n_faces, binned ? bbox : nullptr,
                                    rx0, ry0, rx1, ry1, c, (double)px + 0.5, (double)py + 0.5, act, h, &tc);
-            } else if (!empty) {
+            } else if (!RASTER && !empty) {
                 Ray ray;
                 ray_screen(c, (float)px + u, (float)py + v, ray);
                 if (binned)
@@ -1830,8 +1832,8 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
 // points (a wave packet, or a traversal stack per lane where a wave's lanes
 // look at different hands) while the others render the wave tiles (one
 // traversal stack per wave).
-template <bool COUNT>
-__global__ void __launch_bounds__(kThreads, 4) k_render(RenderArgs a, EdgeArgs e, int with_edges)
+template <bool COUNT, bool RASTER>
+__global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e, int with_edges)
 {
     __shared__ int stack[kMaxStack * kThreads];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
@@ -1852,7 +1854,7 @@ __global__ void __launch_bounds__(kThreads, 4) k_render(RenderArgs a, EdgeArgs e
         const long long first = (long long)gw * 32 + ((threadIdx.x & 63) >> 1);
         edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * 32, stack, wstack);
     } else {
-        render_tiles<COUNT>(a, gw - n_ew, nw - n_ew, wstack);
+        render_tiles<COUNT, RASTER>(a, gw - n_ew, nw - n_ew, wstack);
     }
 }
 
