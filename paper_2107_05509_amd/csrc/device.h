@@ -263,10 +263,6 @@ __device__ __forceinline__ bool slab(const Ray& r, const float* lo, const float*
     return tmin <= tmax;
 }
 
-// Closest hit by stack traversal of a binary BVH with padded (conservative)
-// bounds.  The closest hit is the minimum of (t, face id): independent of the
-// visiting order, hence equal to a brute-force loop over all triangles.
-// `stack` points at this lane's column of an LDS array (stride `sstride`).
 // Work counters of one traversal (only maintained when COUNT is true).
 struct TraceCount {
     unsigned nodes = 0, tris = 0;       // the ray's own work: nodes whose box it enters, triangles of
@@ -274,85 +270,6 @@ struct TraceCount {
     unsigned nodes_w = 0, tris_w = 0;   // packet traversal: node visits and triangle tests executed
                                         // while this lane was active (the union of the wave's rays)
 };
-
-template <bool COUNT = false>
-__device__ __forceinline__ void trace(const Node* __restrict__ nodes, const Tri* __restrict__ tris,
-                                      const Ray& r, int* stack, int sstride, Hit& h, TraceCount* cnt = nullptr)
-{
-    h.face = -1;
-    float tb = __builtin_inff();
-    int fb = 0x7fffffff;
-    int sp = 0;
-    int node = 0;
-    while (true) {
-        if (COUNT) { cnt->nodes++; cnt->nodes_w++; }
-        const Node& n = nodes[node];
-        float4 q0 = *reinterpret_cast<const float4*>(&n.lo0[0]);
-        float4 q1 = *reinterpret_cast<const float4*>(&n.hi0[1]);
-        float4 q2 = *reinterpret_cast<const float4*>(&n.lo1[2]);
-        int4 q3 = *reinterpret_cast<const int4*>(&n.child[0]);
-        float lo0[3] = {q0.x, q0.y, q0.z}, hi0[3] = {q0.w, q1.x, q1.y};
-        float lo1[3] = {q1.z, q1.w, q2.x}, hi1[3] = {q2.y, q2.z, q2.w};
-        int c0 = q3.x, c1 = q3.y;
-        float t0, t1;
-        bool h0 = slab(r, lo0, hi0, tb, t0);
-        bool h1 = slab(r, lo1, hi1, tb, t1);
-        // leaves are tested right away; all triangles of a leaf are fetched
-        // before the first test (one memory latency per leaf, not per triangle)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            int code = c == 0 ? c0 : c1;
-            bool hit = c == 0 ? h0 : h1;
-            if (hit && code < 0) {
-                int lc = ~code;
-                int start = lc >> 3, ncnt = lc & 7;
-                if (COUNT) { cnt->tris += ncnt; cnt->tris_w += ncnt; }
-                float4 P[kLeafMax][3];
-#pragma unroll
-                for (int k = 0; k < kLeafMax; ++k)
-                    if (k < ncnt) {
-                        const Tri& tr = tris[start + k];
-                        P[k][0] = *reinterpret_cast<const float4*>(&tr.v[0]);
-                        P[k][1] = *reinterpret_cast<const float4*>(&tr.v[4]);
-                        P[k][2] = *reinterpret_cast<const float4*>(&tr.v[8]);
-                    }
-#pragma unroll
-                for (int k = 0; k < kLeafMax; ++k) {
-                    if (k >= ncnt) break;
-                    float v0[3] = {P[k][0].x, P[k][0].y, P[k][0].z};
-                    float v1[3] = {P[k][0].w, P[k][1].x, P[k][1].y};
-                    float v2[3] = {P[k][1].z, P[k][1].w, P[k][2].x};
-                    int face = __float_as_int(P[k][2].y);
-                    float t, U, V, W, det;
-                    if (watertight(r, v0, v1, v2, t, U, V, W, det)) {
-                        if (t < tb || (t == tb && face < fb)) {
-                            tb = t; fb = face;
-                            h.face = face;
-                            h.slot = start + k;
-                            h.t = t;
-                        }
-                    }
-                }
-            }
-        }
-        bool go0 = h0 && c0 >= 0 && t0 <= tb;
-        bool go1 = h1 && c1 >= 0 && t1 <= tb;
-        if (go0 && go1) {
-            int nearc = t0 <= t1 ? c0 : c1;
-            int farc = t0 <= t1 ? c1 : c0;
-            if (sp < kMaxStack) { stack[sp * sstride] = farc; ++sp; }
-            node = nearc;
-        } else if (go0) {
-            node = c0;
-        } else if (go1) {
-            node = c1;
-        } else {
-            if (sp == 0) break;
-            --sp;
-            node = stack[sp * sstride];
-        }
-    }
-}
 
 // Closest hits of the rays of one wave by a single traversal order: the wave
 // visits a node when any active lane's ray enters the node's box before that

@@ -1681,7 +1681,7 @@ __device__ __forceinline__ void edge_point(const EdgeArgs& a, long long kg, uint
 
 // Closest hit and colour of this lane's side point of sample P.
 template <bool COUNT>
-__device__ __forceinline__ void edge_side_colour(const EdgeArgs& a, const EdgePoint& P, int* stk, int* wst,
+__device__ __forceinline__ void edge_side_colour(const EdgeArgs& a, const EdgePoint& P, int* wst,
                                                  TraceCount& tc, unsigned long long& n_rays,
                                                  unsigned long long& n_hit, float col[3])
 {
@@ -1695,13 +1695,27 @@ __device__ __forceinline__ void edge_side_colour(const EdgeArgs& a, const EdgePo
     Ray ray;
     Hit h;
     ray_screen(c, P.xs, P.ys, ray);
-    // consecutive samples lie on neighbouring edges of one view: the wave
-    // traverses together unless its lanes look at different hands (the
-    // side points are spread along silhouettes, over many screen bins)
-    if (__all(hand == __builtin_amdgcn_readfirstlane(hand)))
+    // the wave traverses as one packet (the side points are spread along
+    // silhouettes, over many screen bins); lanes of several hands (at the
+    // hands' boundaries in the sample order) take one packet per hand, the
+    // other lanes inactive
+    if (__all(hand == __builtin_amdgcn_readfirstlane(hand))) {
         trace_wave<COUNT, true>(nodes, tris, ray, true, wst, h, &tc);
-    else
-        trace<COUNT>(nodes, tris, ray, stk, kThreads, h, &tc);
+    } else {
+        h.face = -1;
+        h.slot = 0;
+        h.t = 0.0f;
+        uint64_t todo = wave_mask(true);
+        while (todo) {
+            const int hl = __builtin_amdgcn_readlane(hand, __ffsll((long long)todo) - 1);
+            const bool mine = hand == hl;
+            todo &= ~wave_mask(mine);
+            Hit hh;
+            trace_wave<COUNT, true>(a.nodes + (size_t)hl * a.n_nodes, a.tris + (size_t)hl * a.m.F, ray, mine, wst,
+                                    hh, &tc);
+            if (mine) h = hh;
+        }
+    }
     if (COUNT) { ++n_rays; n_hit += h.face >= 0; }
     shade_or_bg(h, tris, c, P.xs, P.ys, normals, a.uv, tex, a.tex_h, a.tex_w, a.shading, bg, col);
 }
@@ -1760,10 +1774,9 @@ __device__ __forceinline__ void edge_contribution(const EdgeArgs& a, int vi, int
 enum EdgeMode { kEdgeTrace = 0, kEdgeWeigh = 1 };
 
 template <bool COUNT, int MODE>
-__device__ void edge_samples(const EdgeArgs& a, long long first, long long npairs, int* stack, int* wstack)
+__device__ void edge_samples(const EdgeArgs& a, long long first, long long npairs, int* wstack)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
-    int* stk = stack + threadIdx.x;
     int* wst = wstack + kMaxStack * (threadIdx.x >> 6);
     const long long total = a.prefix[a.n_views];
     const long long stored = min(total, a.sample_cap);
@@ -1779,15 +1792,18 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
                 if (side == 0) out.vi = -1;
                 continue;   // same for both lanes of the pair
             }
+            // the record's geometry first: none of it is live across the trace
+            if (side == 0) {
+                out.vi = P.vi;
+                out.e = P.e;
+                out.pg = P.pg;
+                out.t = P.t;
+                out.wgt = P.wgt;
+            }
             float col[3];
-            edge_side_colour<COUNT>(a, P, stk, wst, tc, n_rays, n_hit, col);
+            edge_side_colour<COUNT>(a, P, wst, tc, n_rays, n_hit, col);
             const float o0 = __shfl_xor(col[0], 1), o1 = __shfl_xor(col[1], 1), o2 = __shfl_xor(col[2], 1);
             if (side != 0) continue;
-            out.vi = P.vi;
-            out.e = P.e;
-            out.pg = P.pg;
-            out.t = P.t;
-            out.wgt = P.wgt;
             out.dc[0] = o0 - col[0];   // c(x - delta n) - c(x + delta n)
             out.dc[1] = o1 - col[1];
             out.dc[2] = o2 - col[2];
@@ -1806,7 +1822,7 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
             const float* gp = a.dimage + 3 * P.pg;
             if (gp[0] == 0.0f && gp[1] == 0.0f && gp[2] == 0.0f) continue;   // same for both lanes
             float col[3];
-            edge_side_colour<COUNT>(a, P, stk, wst, tc, n_rays, n_hit, col);
+            edge_side_colour<COUNT>(a, P, wst, tc, n_rays, n_hit, col);
             const float o0 = __shfl_xor(col[0], 1), o1 = __shfl_xor(col[1], 1), o2 = __shfl_xor(col[2], 1);
             if (side != 0) continue;
             const float dc[3] = {o0 - col[0], o1 - col[1], o2 - col[2]};
@@ -1835,7 +1851,6 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
 template <bool COUNT, bool RASTER>
 __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e, int with_edges)
 {
-    __shared__ int stack[kMaxStack * kThreads];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
     const int bid = (int)blockIdx.x, nb = (int)gridDim.x;
     render_side_work(a, bid, nb);
@@ -1852,7 +1867,7 @@ __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e
     }
     if (gw < n_ew) {
         const long long first = (long long)gw * 32 + ((threadIdx.x & 63) >> 1);
-        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * 32, stack, wstack);
+        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * 32, wstack);
     } else {
         render_tiles<COUNT, RASTER>(a, gw - n_ew, nw - n_ew, wstack);
     }
@@ -1863,10 +1878,9 @@ __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e
 template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_edge_trace(EdgeArgs e)
 {
-    __shared__ int stack[kMaxStack * kThreads];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
     edge_samples<COUNT, kEdgeTrace>(e, ((long long)blockIdx.x * kThreads + threadIdx.x) >> 1,
-                                    ((long long)gridDim.x * kThreads) >> 1, stack, wstack);
+                                    ((long long)gridDim.x * kThreads) >> 1, wstack);
 }
 
 // Backward ray tracing: the first `n_edge` blocks draw the edge samples, the
@@ -1876,15 +1890,12 @@ template <bool COUNT>
 __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, EdgeArgs e, int n_edge, LossArgs l,
                                                              int n_loss)
 {
-    // edge blocks: a traversal stack per lane; adjoint blocks: the texel
-    // windows of their waves in the same memory
-    constexpr int kLds = kMaxStack * kThreads > kWaveWin * (kThreads / 64) ? kMaxStack * kThreads
-                                                                           : kWaveWin * (kThreads / 64);
-    __shared__ __align__(16) int lds[kLds];
+    // adjoint blocks: the texel windows of their waves
+    __shared__ __align__(16) int lds[kWaveWin * (kThreads / 64)];
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
     if ((int)blockIdx.x < n_edge) {
         edge_samples<COUNT, kEdgeWeigh>(e, ((long long)blockIdx.x * kThreads + threadIdx.x) >> 1,
-                                        ((long long)n_edge * kThreads) >> 1, lds, wstack);
+                                        ((long long)n_edge * kThreads) >> 1, wstack);
         return;
     }
     // the last n_loss blocks: partial sums of the loss value (chunk per block)
