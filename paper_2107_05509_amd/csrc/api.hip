@@ -351,8 +351,19 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     md.V = V; md.F = F; md.J = J; md.K = K; md.E = E;
     {
         float* p;
-        TRY(s->upload(&p, m->v_template, 3 * (size_t)V)); md.v_template = p;
-        TRY(s->upload(&p, m->shapedirs, 3 * (size_t)V * std::max(K, 1))); md.shapedirs = p;
+        // per-vertex tables vertex-minor ([..][V]): a wave's 64 vertices read
+        // one contiguous run per entry
+        {
+            std::vector<float> tt(3 * (size_t)V), st(3 * (size_t)V * std::max(K, 1), 0.0f);
+            for (int v = 0; v < V; ++v)
+                for (int c = 0; c < 3; ++c) {
+                    tt[(size_t)c * V + v] = m->v_template[3 * (size_t)v + c];
+                    for (int k = 0; k < K; ++k)
+                        st[((size_t)k * 3 + c) * V + v] = m->shapedirs[(3 * (size_t)v + c) * K + k];
+                }
+            TRY(s->upload(&p, tt.data(), tt.size())); md.v_template = p;
+            TRY(s->upload(&p, st.data(), st.size())); md.shapedirs = p;
+        }
         TRY(s->upload(&p, m->j_regressor, (size_t)J * V)); md.j_regressor = p;
         TRY(s->upload(&p, m->weights, (size_t)V * J)); md.weights = p;
         TRY(s->upload(&p, m->uv, 2 * (size_t)V)); md.uv = p;
@@ -389,7 +400,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         std::vector<int> vc(4 * (size_t)V * kVfSlots, 0);
         for (int v = 0; v < V; ++v)
             for (int k = 0; k < kVfSlots; ++k) {
-                int* d = &vc[4 * ((size_t)v * kVfSlots + k)];
+                int* d = &vc[4 * ((size_t)k * V + v)];
                 if (off[v] + k < off[v + 1]) {
                     const int f = flat[off[v] + k];
                     for (int c = 0; c < 3; ++c) d[c] = m->faces[3 * f + c];
@@ -444,7 +455,7 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
             int c = 0;
             for (int j = 0; j < J; ++j) {
                 const float w = m->weights[(size_t)v * J + j];
-                if (w != 0.0f) { widx[(size_t)v * infl + c] = j; wval[(size_t)v * infl + c] = w; ++c; }
+                if (w != 0.0f) { widx[(size_t)c * V + v] = j; wval[(size_t)c * V + v] = w; ++c; }
             }
         }
         if (infl > kMaxInfl) {

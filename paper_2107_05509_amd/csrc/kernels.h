@@ -15,8 +15,8 @@ constexpr int kCounts = 18;          // work counters: 6 per ray-tracing kernel 
 
 struct MeshDev {
     int V, F, J, K, E;
-    const float* v_template;   // [V,3]
-    const float* shapedirs;    // [V,3,K]
+    const float* v_template;   // [3,V]
+    const float* shapedirs;    // [K,3,V]
     const float* j_regressor;  // [J,V]
     const float* weights;      // [V,J]
     const int* parents;        // [J]
@@ -27,7 +27,7 @@ struct MeshDev {
     const int4* edge_verts;    // [E,2] (va, vb, face 0's vertices, face 1's vertices or -1)
     const int* vf_off;         // [V+1]
     const int* vf_faces;       // [3F]
-    const int4* vf_corner;     // [V,kVfSlots] the first kVfSlots faces around each vertex as
+    const int4* vf_corner;     // [kVfSlots,V] the first kVfSlots faces around each vertex as
                                // (a, b, c, face), padded with (v, v, v, 0)
     const float* jt;           // [J,3] J_reg T: rest joints of the template
     const float* js;           // [J,3,K] J_reg S: joint displacement per shape coefficient
@@ -36,8 +36,8 @@ struct MeshDev {
     const int* jdepth;         // [J] depth in the joint tree (root 0)
     int max_depth;
     int infl;                  // skinning weights per vertex (padded with weight 0)
-    const int* widx;           // [V,infl] joint of each weight
-    const float* wval;         // [V,infl]
+    const int* widx;           // [infl,V] joint of each weight
+    const float* wval;         // [infl,V]
 };
 
 // Topology of each hand's hierarchy (bounds are refit every iteration).

@@ -124,8 +124,8 @@ __device__ __forceinline__ void load_weights(const MeshDev& m, int v, float* wq,
 #pragma unroll
     for (int q = 0; q < kMaxInfl; ++q) {
         const int qq = q < n ? q : n - 1;
-        const float w = m.wval[v * n + qq];
-        jq[q] = m.widx[v * n + qq];
+        const float w = m.wval[(size_t)qq * m.V + v];
+        jq[q] = m.widx[(size_t)qq * m.V + v];
         wq[q] = q < n ? w : 0.0f;
     }
 }
@@ -200,9 +200,10 @@ __device__ __forceinline__ void load_shape(const MeshDev& m, int v, float* tpl, 
     const int K = m.K;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        tpl[c] = m.v_template[3 * v + c];
+        tpl[c] = m.v_template[(size_t)c * m.V + v];
 #pragma unroll
-        for (int k = 0; k < kMaxShape; ++k) sd[c][k] = K > 0 ? m.shapedirs[(3 * v + c) * K + (k < K ? k : K - 1)] : 0.0f;
+        for (int k = 0; k < kMaxShape; ++k)
+            sd[c][k] = K > 0 ? m.shapedirs[((size_t)(k < K ? k : K - 1) * 3 + c) * m.V + v] : 0.0f;
     }
 }
 
@@ -279,12 +280,14 @@ __device__ void rodrigues64(const double* r, Rod64& o)
 {
     const double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
     const double t = sqrt(t2);
+    // the three circular functions once, for every lane: the lanes of a wave
+    // take different branches below, which would otherwise each evaluate them
+    const double s = sin(t), c = cos(t), sh = sin(0.5 * t);
     if (t < 1e-4) {
         o.a = 1.0 - t2 / 6.0;
         o.b = 0.5 - t2 / 24.0;
     } else {
-        const double sh = sin(0.5 * t);
-        o.a = sin(t) / t;
+        o.a = s / t;
         o.b = 2.0 * sh * sh / t2;
     }
     // derivative factors of the backward (float32 there)
@@ -292,7 +295,6 @@ __device__ void rodrigues64(const double* r, Rod64& o)
         o.ad = -1.0 / 3.0 + t2 / 30.0 - t2 * t2 / 840.0;
         o.bd = -1.0 / 12.0 + t2 / 180.0 - t2 * t2 / 6720.0;
     } else {
-        const double s = sin(t), c = cos(t), sh = sin(0.5 * t);
         o.ad = (t * c - s) / (t2 * t);
         o.bd = (t * s - 4.0 * sh * sh) / (t2 * t2);
     }
@@ -316,8 +318,12 @@ __device__ __forceinline__ void matvec3d(const double* A, const double* x, doubl
     for (int i = 0; i < 3; ++i) y[i] = A[3 * i] * x[0] + A[3 * i + 1] * x[1] + A[3 * i + 2] * x[2];
 }
 
-// joint_state in float64 (same structure: the first wave, one tree level at a
-// time; ends with a block barrier)
+// joint_state in float64, in the first wave: lane j < J for joint j, lane J
+// for the global rotation.  The tree is walked one level at a time from the
+// roots with each lane's global rotation and translation in registers: a
+// lane of level L reads its parent's (final since level L - 1) from the
+// parent's lane, so no level waits on LDS.  The products are those of
+// joint_state, in the same order.  Ends with a block barrier.
 __device__ void joint_state64(const MeshDev& m, const float* __restrict__ p, JointState64& js)
 {
     const int J = m.J, K = m.K;
@@ -341,35 +347,49 @@ __device__ void joint_state64(const MeshDev& m, const float* __restrict__ p, Joi
                 jsd[c][k] = k < K ? d : 0.0;
             }
         }
-        if (j <= J) rodrigues64(r, js.rod[jr]);
-        if (j < J)
-            for (int c = 0; c < 3; ++c) {
-                double x = jt[c];
+        Rod64 rd;
+        rodrigues64(r, rd);
+        if (j <= J) js.rod[jr] = rd;
+        if (j == J)
+            for (int i = 0; i < 9; ++i) js.Rp[i] = rd.R[i];
+        double x[3];
+        for (int c = 0; c < 3; ++c) {
+            x[c] = jt[c];
 #pragma unroll
-                for (int k = 0; k < kMaxShape; ++k)
-                    if (k < K) x += jsd[c][k] * (double)bkf[k];
-                js.J[3 * j + c] = x;
-            }
-        wave_lds_sync();
-        if (j < 9) js.Rp[j] = js.rod[J].R[j];
-        for (int L = 0; L <= m.max_depth; ++L) {
+            for (int k = 0; k < kMaxShape; ++k)
+                if (k < K) x[c] += jsd[c][k] * (double)bkf[k];
+        }
+        if (j < J)
+            for (int c = 0; c < 3; ++c) js.J[3 * j + c] = x[c];
+        // roots: GR = R, Gt = J; lane `src` is the parent (itself for roots
+        // and lanes past the joints)
+        const int src = par >= 0 ? par : j;
+        double GR[9], Gt[3], pJ[3];
+        for (int i = 0; i < 9; ++i) GR[i] = rd.R[i];
+        for (int c = 0; c < 3; ++c) {
+            Gt[c] = x[c];
+            pJ[c] = __shfl(x[c], src);
+        }
+        for (int L = 1; L <= m.max_depth; ++L) {
+            double pG[9], pt[3];
+            for (int i = 0; i < 9; ++i) pG[i] = __shfl(GR[i], src);
+            for (int i = 0; i < 3; ++i) pt[i] = __shfl(Gt[i], src);
             if (dj == L) {
-                if (par < 0) {
-                    for (int i = 0; i < 9; ++i) js.GR[9 * j + i] = js.rod[j].R[i];
-                    for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = js.J[3 * j + i];
-                } else {
-                    matmul3d(js.GR + 9 * par, js.rod[j].R, js.GR + 9 * j);
-                    const double d[3] = {js.J[3 * j] - js.J[3 * par], js.J[3 * j + 1] - js.J[3 * par + 1],
-                                         js.J[3 * j + 2] - js.J[3 * par + 2]};
-                    double y[3];
-                    matvec3d(js.GR + 9 * par, d, y);
-                    for (int i = 0; i < 3; ++i) js.Gt[3 * j + i] = y[i] + js.Gt[3 * par + i];
-                }
+                matmul3d(pG, rd.R, GR);
+                const double d[3] = {x[0] - pJ[0], x[1] - pJ[1], x[2] - pJ[2]};
                 double y[3];
-                matvec3d(js.GR + 9 * j, js.J + 3 * j, y);
-                for (int i = 0; i < 3; ++i) js.At[3 * j + i] = js.Gt[3 * j + i] - y[i];
+                matvec3d(pG, d, y);
+                for (int i = 0; i < 3; ++i) Gt[i] = y[i] + pt[i];
             }
-            wave_lds_sync();
+        }
+        if (j < J) {
+            double y[3];
+            matvec3d(GR, x, y);
+            for (int i = 0; i < 9; ++i) js.GR[9 * j + i] = GR[i];
+            for (int i = 0; i < 3; ++i) {
+                js.Gt[3 * j + i] = Gt[i];
+                js.At[3 * j + i] = Gt[i] - y[i];
+            }
         }
     }
     __syncthreads();
@@ -1914,108 +1934,137 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
 // The sums over the vertices (`tot`: global rotation and translation, per
 // joint dL/dGR_j and dL/dAt_j, shape) taken through the joint tree, one level
 // at a time from the leaves, and the Rodrigues maps to dL/dparams.  The first
-// wave does the work (the levels synchronise the wave only); the caller's
-// next block barrier orders its results for the other waves.
-__device__ void skin_bwd_finish(const MeshDev& m, const float* __restrict__ p, const float* tot,
-                                const JointState& js, float* __restrict__ gp, const float* xGt)
-{
-    __shared__ float gJ[kMaxJoints * 3], gGt[kMaxJoints * 3], gGR[kMaxJoints * 9], gR[kMaxJoints * 9];
-    __shared__ float cGR[kMaxJoints * 9], cJ[kMaxJoints * 3];   // each joint's terms for its parent
-    __shared__ unsigned int kids[kMaxJoints];                   // bit c: joint c is a child
-    const int J = m.J, K = m.K;
-    const int j = threadIdx.x;
-    if (j >= 64) return;
-    // rows j and j + 64 of J_reg S (joint coordinate row / 3, row % 3 per
-    // shape coefficient), fetched now for the shape gradient at the end
+// wave does the work, lane j for joint j; the caller's next block barrier
+// orders its results for the other waves.
+// What lane j of the finish reads from global memory, loaded ahead (the
+// finish runs in whichever block of the hand ends last): rows j and j + 64
+// of J_reg S (joint coordinate row / 3, row % 3 per shape coefficient) for
+// the shape gradient, the lane's rotation parameters, its joint's depth and
+// parent.
+struct FinishIn {
     float jsr[2][kMaxShape];
+    float r[3];
+    int dj, par;
+};
+
+__device__ __forceinline__ void finish_load(const MeshDev& m, const float* __restrict__ p, FinishIn& in)
+{
+    const int J = m.J, K = m.K;
+    const int j = threadIdx.x & 63;
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int k = 0; k < kMaxShape; ++k) {
             const int row = min(j + 64 * h, 3 * J - 1), kk = k < K ? k : K - 1;
-            jsr[h][k] = K > 0 && J > 0 ? m.js[row * K + kk] : 0.0f;
+            in.jsr[h][k] = K > 0 && J > 0 ? m.js[row * K + kk] : 0.0f;
         }
-    const int dj = j < J ? m.jdepth[j] : -1, par = j < J ? m.parents[j] : -1;
-    if (j < J) kids[j] = 0u;
-    wave_lds_sync();
-    if (par >= 0) atomicOr(kids + par, 1u << j);
+    const float* pr = j < J ? p + 3 * j : p + 58;
+    for (int c = 0; c < 3; ++c) in.r[c] = pr[c];
+    in.dj = j < J ? m.jdepth[j] : -1;
+    in.par = j < J ? m.parents[j] : -1;
+}
+
+__device__ void skin_bwd_finish(const MeshDev& m, const FinishIn& in, const float* tot, const JointState& js,
+                                float* __restrict__ gp, const float* xGt)
+{
+    __shared__ float gJs[kMaxJoints * 3];   // dL/dJ for the shape rows at the end
+    const int J = m.J, K = m.K;
+    const int j = threadIdx.x;
+    if (j >= 64) return;
+    const float* r = in.r;
+    const int dj = in.dj, par = in.par;
+    // children of joint j (bit c: joint c), from the parents' lanes
+    unsigned int kids = 0u;
+    for (int c = 0; c < J; ++c)
+        if (__builtin_amdgcn_readlane(par, c) == j) kids |= 1u << c;
+    // the joint's state, read once: GR_j, GR_parent, R_j, J_j - J_parent
+    const int jl = j < J ? j : 0, pl = par >= 0 ? par : 0;
+    float GRj[9], GRp[9], Rc[9], d[3];
+    for (int i = 0; i < 9; ++i) {
+        GRj[i] = js.GR[9 * jl + i];
+        GRp[i] = js.GR[9 * pl + i];
+        Rc[i] = js.rod[jl].R[i];
+    }
+    for (int i = 0; i < 3; ++i) d[i] = js.J[3 * jl + i] - js.J[3 * pl + i];
     // At_j = Gt_j - GR_j J_j
-    if (j < J) {
-        const float* a = tot + 12 + 12 * j;
+    float gGR[9], gGt[3], gJ[3];
+    {
+        const float* a = tot + 12 + 12 * jl;
         for (int i = 0; i < 3; ++i) {
-            gGt[3 * j + i] = a[9 + i] + (xGt ? xGt[3 * j + i] : 0.0f);
-            for (int k = 0; k < 3; ++k) gGR[9 * j + 3 * i + k] = a[3 * i + k] - a[9 + i] * js.J[3 * j + k];
+            gGt[i] = a[9 + i] + (xGt ? xGt[3 * jl + i] : 0.0f);
+            for (int k = 0; k < 3; ++k) gGR[3 * i + k] = a[3 * i + k] - a[9 + i] * js.J[3 * jl + k];
         }
         float y[3];
-        matTvec3(js.GR + 9 * j, a + 9, y);
-        for (int i = 0; i < 3; ++i) gJ[3 * j + i] = -y[i];
+        matTvec3(GRj, a + 9, y);
+        for (int i = 0; i < 3; ++i) gJ[i] = -y[i];
     }
-    wave_lds_sync();
-    // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j: joints of level L finish
-    // their own terms and leave those of their parent, which (level L-1) adds
-    // them in child order
-    // (each lane works on register copies: its LDS reads go out together
-    // and every value is written once per level)
+    // Gt_j = GR_p (J_j - J_p) + Gt_p, GR_j = GR_p R_j: the joints of level L
+    // finish their own terms and leave those of their parent in registers;
+    // the parents (level L - 1) read them from the children's lanes and add
+    // them in child order.  Every value stays in its lane's registers.
+    float gR[9], cGR[9], cJ[3];
+    for (int i = 0; i < 9; ++i) gR[i] = cGR[i] = 0.0f;
+    for (int i = 0; i < 3; ++i) cJ[i] = 0.0f;
     for (int L = m.max_depth; L >= 0; --L) {
         if (dj == L) {
-            float oGR[9], oGt[3], oJ[3];
-            for (int i = 0; i < 9; ++i) oGR[i] = gGR[9 * j + i];
-            for (int i = 0; i < 3; ++i) { oGt[i] = gGt[3 * j + i]; oJ[i] = gJ[3 * j + i]; }
             if (par < 0) {
-                for (int i = 0; i < 9; ++i) gR[9 * j + i] = oGR[i];
-                for (int i = 0; i < 3; ++i) gJ[3 * j + i] = oJ[i] + oGt[i];
+                for (int i = 0; i < 9; ++i) gR[i] = gGR[i];
+                for (int i = 0; i < 3; ++i) gJ[i] = gJ[i] + gGt[i];
             } else {
-                float GRp[9], Rc[9], d[3];
-                for (int i = 0; i < 9; ++i) { GRp[i] = js.GR[9 * par + i]; Rc[i] = js.rod[j].R[i]; }
-                for (int i = 0; i < 3; ++i) d[i] = js.J[3 * j + i] - js.J[3 * par + i];
                 float y[3];
-                matTvec3(GRp, oGt, y);
+                matTvec3(GRp, gGt, y);
                 for (int i = 0; i < 3; ++i) {
-                    gJ[3 * j + i] = oJ[i] + y[i];
-                    cJ[3 * j + i] = y[i];
+                    gJ[i] = gJ[i] + y[i];
+                    cJ[i] = y[i];
                 }
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
                         float s = 0.0f;
-                        for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * oGR[3 * q + k];
-                        gR[9 * j + 3 * i + k] = s;
+                        for (int q = 0; q < 3; ++q) s += GRp[3 * q + i] * gGR[3 * q + k];
+                        gR[3 * i + k] = s;
                     }
                 for (int i = 0; i < 3; ++i)
                     for (int k = 0; k < 3; ++k) {
-                        float s = oGt[i] * d[k];
-                        for (int q = 0; q < 3; ++q) s += oGR[3 * i + q] * Rc[3 * k + q];
-                        cGR[9 * j + 3 * i + k] = s;
+                        float s = gGt[i] * d[k];
+                        for (int q = 0; q < 3; ++q) s += gGR[3 * i + q] * Rc[3 * k + q];
+                        cGR[3 * i + k] = s;
                     }
             }
         }
-        wave_lds_sync();
-        if (j < J && dj == L - 1) {
-            float aGR[9], aJ[3], aGt[3];
-            for (int i = 0; i < 9; ++i) aGR[i] = gGR[9 * j + i];
-            for (int i = 0; i < 3; ++i) { aJ[i] = gJ[3 * j + i]; aGt[i] = gGt[3 * j + i]; }
-            for (unsigned int bits = kids[j]; bits; bits &= bits - 1u) {
-                const int c = __builtin_ctz(bits);
-                for (int i = 0; i < 9; ++i) aGR[i] += cGR[9 * c + i];
-                for (int i = 0; i < 3; ++i) {
-                    aJ[i] -= cJ[3 * c + i];
-                    aGt[i] += gGt[3 * c + i];
-                }
+        // the parents of level L - 1: one child per round (the loop and its
+        // lane reads run on the whole wave)
+        unsigned int rem = j < J && dj == L - 1 ? kids : 0u;
+        while (__any(rem != 0u)) {
+            const int c = rem ? __builtin_ctz(rem) : j;
+            float xGR[9], xJ[3], xT[3];
+            for (int i = 0; i < 9; ++i) xGR[i] = __shfl(cGR[i], c);
+            for (int i = 0; i < 3; ++i) {
+                xJ[i] = __shfl(cJ[i], c);
+                xT[i] = __shfl(gGt[i], c);
             }
-            for (int i = 0; i < 9; ++i) gGR[9 * j + i] = aGR[i];
-            for (int i = 0; i < 3; ++i) { gJ[3 * j + i] = aJ[i]; gGt[3 * j + i] = aGt[i]; }
+            if (rem) {
+                for (int i = 0; i < 9; ++i) gGR[i] += xGR[i];
+                for (int i = 0; i < 3; ++i) {
+                    gJ[i] -= xJ[i];
+                    gGt[i] += xT[i];
+                }
+                rem &= rem - 1u;
+            }
         }
-        wave_lds_sync();
     }
-    if (j < J) rodrigues_bwd(p + 3 * j, js.rod[j], gR + 9 * j, gp + 3 * j);
-    if (j == J) rodrigues_bwd(p + 58, js.rod[J], tot, gp + 58);
+    if (j < J) rodrigues_bwd(r, js.rod[j], gR, gp + 3 * j);
+    if (j == J) rodrigues_bwd(r, js.rod[J], tot, gp + 58);
     for (int q = J + j; q < 16; q += 64) gp[3 * q] = gp[3 * q + 1] = gp[3 * q + 2] = 0.0f;
     if (j < 3) gp[61 + j] = tot[9 + j];
     // shape: vertex part + joint part (J = J_reg T + (J_reg S) beta), the
     // joint part as lane j's row times dL/dJ[j], summed over the wave
+    if (j < J)
+        for (int i = 0; i < 3; ++i) gJs[3 * j + i] = gJ[i];
+    wave_lds_sync();
     float sj[kMaxShape];
-    const float gj0 = j < 3 * J ? gJ[j] : 0.0f, gj1 = j + 64 < 3 * J ? gJ[j + 64] : 0.0f;
+    const float gj0 = j < 3 * J ? gJs[j] : 0.0f, gj1 = j + 64 < 3 * J ? gJs[j + 64] : 0.0f;
 #pragma unroll
-    for (int k = 0; k < kMaxShape; ++k) sj[k] = jsr[0][k] * gj0 + jsr[1][k] * gj1;
+    for (int k = 0; k < kMaxShape; ++k) sj[k] = in.jsr[0][k] * gj0 + in.jsr[1][k] * gj1;
     wave_sum63_n<kMaxShape>(sj);
     if (j == 63)
 #pragma unroll
@@ -2178,7 +2227,7 @@ __global__ void __launch_bounds__(256) k_geom_p1(GeomBwdArgs a)
     const int k0 = m.vf_off[v], k1 = m.vf_off[v + 1];
     int4 cq[kVfSlots];
 #pragma unroll
-    for (int k = 0; k < kVfSlots; ++k) cq[k] = m.vf_corner[(size_t)v * kVfSlots + k];
+    for (int k = 0; k < kVfSlots; ++k) cq[k] = m.vf_corner[(size_t)k * V + v];
     auto face_terms = [&](int f, int i0, int i1, int i2) {
         const int corner = i0 == v ? 0 : (i1 == v ? 1 : 2);
         const float* sl = gf + 18 * f + 6 * corner;
@@ -2261,6 +2310,17 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
         load_shape(m, v, tpl, sd);
     }
     for (int i = t; i < n_part; i += 64) acc[i] = 0.0f;
+    // the finish's reads and the parameters' Adam state, in case this block
+    // ends last
+    FinishIn fin;
+    finish_load(m, p, fin);
+    float ax = 0.0f, am = 0.0f, av = 0.0f;
+    if (a.adam_params) {
+        const size_t i = (size_t)64 * h + t;
+        ax = a.adam.params[i];
+        am = a.adam.m_params[i];
+        av = a.adam.v_params[i];
+    }
     if (a.js_saved) {
         // the skinning launch of these parameters left the joint state
         const float* src = a.js_saved + (size_t)h * kJointStateFloats;
@@ -2291,7 +2351,7 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
         const int k0 = m.vf_off[v], k1 = m.vf_off[v + 1];
         int4 cq[kVfSlots];
 #pragma unroll
-        for (int k = 0; k < kVfSlots; ++k) cq[k] = m.vf_corner[(size_t)v * kVfSlots + k];
+        for (int k = 0; k < kVfSlots; ++k) cq[k] = m.vf_corner[(size_t)k * V + v];
 #pragma unroll
         for (int k = 0; k < kVfSlots; ++k)
             if (k < k1 - k0) normal_corner_grad(v, cq[k].x, cq[k].y, cq[k].z, vh, grh, g);
@@ -2379,7 +2439,7 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
     if (a.prior_target)
         joint_prior(m, js, p, a.prior_target + (size_t)h * J * 3, a.prior_lambda, a.prior_gamma, acc, xGt,
                     a.with_loss && a.loss.loss ? a.loss.loss + h : nullptr);
-    skin_bwd_finish(m, p, acc, js, gp, a.prior_target ? xGt : nullptr);
+    skin_bwd_finish(m, fin, acc, js, gp, a.prior_target ? xGt : nullptr);
     if (!a.adam_params) return;
     __syncthreads();   // the finish has read the parameters and written gp
     const float lr = param_lr(a.adam, t);
@@ -2387,8 +2447,9 @@ __global__ void __launch_bounds__(64) k_geom_p2(GeomBwdArgs a)
         float bc1, bc2;
         adam_bias(a.adam, bc1, bc2);
         const size_t i = (size_t)64 * h + t;
-        a.adam.params[i] =
-            adam_update(a.adam.params[i], a.adam.m_params + i, a.adam.v_params + i, gp[t], lr, a.adam, bc1, bc2);
+        a.adam.params[i] = adam_update(ax, &am, &av, gp[t], lr, a.adam, bc1, bc2);
+        a.adam.m_params[i] = am;
+        a.adam.v_params[i] = av;
     }
     if (!a.iter_advance) return;
     // the last hand to finish advances the iteration counter: every read of
