@@ -124,9 +124,11 @@ def traffic(fetch_csv, write_csv, title, cmd):
     js = {"source_hash": source_hash(), "units": "bytes per launch (counter values scaled by the copy kernel)",
           "scale": {"fetch": fs, "write": ws}, "kernels": {}, "detail": {}}
     for k in sorted(set(f) | set(w)):
-        if not (k.startswith("k_") and "<true>" not in k):
+        # the counting instantiations (<true ...>) are not launched in the
+        # timed region; the others keep their plain name
+        if not (k.startswith("k_") and "<true" not in k):
             continue
-        kk = k.replace("<false>", "")
+        kk = k.replace("<false>", "").replace("<false, false>", "")
         rb, wb = f.get(k, 0.0) * 1024.0 * fs, w.get(k, 0.0) * 1024.0 * ws
         out.append(f"{kk},{f.get(k, 0.0):.1f},{w.get(k, 0.0):.1f},{rb / 1e6:.2f},{wb / 1e6:.2f},{(rb + wb) / 1e6:.2f}")
         js["kernels"][kk] = int(rb + wb)
