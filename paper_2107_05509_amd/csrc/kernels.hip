@@ -1865,9 +1865,8 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
 
 // Render: every block writes its share of the pixels outside the views'
 // tiled rectangles; with edges, the first waves trace the edge samples' side
-// points (a wave packet, or a traversal stack per lane where a wave's lanes
-// look at different hands) while the others render the wave tiles (one
-// traversal stack per wave).
+// points (a wave packet per hand the wave's samples look at) while the
+// others render the wave tiles (one traversal stack per wave).
 template <bool COUNT, bool RASTER>
 __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e, int with_edges)
 {
