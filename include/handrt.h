@@ -147,6 +147,17 @@ int hr_skin(hr_scene* scene, const float* params, float* verts, float* joints, v
    graph capture.  The scene starts with a hierarchy of the rest pose. */
 int hr_build_hierarchy(hr_scene* scene, const float* verts, void* stream);
 
+/* Quality of each hand's hierarchy as last refit (by hr_render, hr_iterate
+   or any call that prepares the geometry), so that a caller can decide when
+   to call hr_build_hierarchy again: the sum over the internal nodes of their
+   two child boxes' surface areas divided by the root box's surface area
+   (the expected number of child-box tests of a ray crossing the root box, the
+   measure the surface-area heuristic minimises).  It grows as the pose
+   drifts from the one the topology was built around; 0 before the first
+   refit.  cost_host [n_hands] float, host memory, written.  Synchronises the
+   device; not for use under graph capture. */
+int hr_hierarchy_cost(hr_scene* scene, float* cost_host);
+
 /* Render all views: pixel = (1/spp) sum over samples of the colour of the
    first surface hit by the ray through a uniformly drawn point of the pixel,
    or the pixel's background colour (Section 3, Eq. 3).  Also prepares the

@@ -24,7 +24,8 @@ HR_SKIP_PRIOR = 8
 HR_ACCEL_AUTO = 0
 HR_ACCEL_HIERARCHY = 1
 
-EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy", "hr_render",
+EXPORTS = ("hr_scene_create", "hr_scene_destroy", "hr_num_pixels", "hr_skin", "hr_build_hierarchy",
+           "hr_hierarchy_cost", "hr_render",
            "hr_loss", "hr_loss_noalloc", "hr_backward", "hr_set_joint_prior", "hr_face_visibility", "hr_camera_order", "hr_step", "hr_iterate", "hr_graph_create", "hr_graph_launch",
            "hr_graph_destroy", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles", "hr_set_renderer", "hr_set_edge_budget", "hr_set_render_edges", "hr_get_grid", "hr_tune", "hr_edge_stats", "hr_set_counting", "hr_read_counts",
            "hr_timing_enable", "hr_timing_read", "hr_proposal_set", "hr_proposal_get", "hr_proposal_override",
@@ -133,6 +134,7 @@ def lib():
         L.hr_proposal_fit.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp]
         L.hr_edge_stats.argtypes = [vp, vp, vp, vp]
         L.hr_build_hierarchy.argtypes = [vp, vp, vp]
+        L.hr_hierarchy_cost.argtypes = [vp, vp]
         L.hr_set_counting.argtypes = [vp, i32]
         L.hr_read_counts.argtypes = [vp, vp, vp]
         L.hr_timing_enable.argtypes = [vp, i32]
@@ -150,7 +152,7 @@ def lib():
                      "hr_step", "hr_iterate",
                      "hr_graph_create", "hr_graph_launch", "hr_set_grid", "hr_set_accel", "hr_set_tiles", "hr_get_tiles",
                      "hr_set_renderer", "hr_set_edge_budget", "hr_set_render_edges", "hr_get_grid", "hr_tune", "hr_edge_stats",
-                     "hr_build_hierarchy", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
+                     "hr_build_hierarchy", "hr_hierarchy_cost", "hr_set_counting", "hr_read_counts", "hr_timing_enable", "hr_timing_read",
                      "hr_proposal_set", "hr_proposal_get", "hr_proposal_override", "hr_proposal_train",
                      "hr_proposal_features", "hr_proposal_stats", "hr_proposal_eval", "hr_proposal_fit",
                      "hr_data_term_set", "hr_edge_map", "hr_loss_full", "hr_compose_albedo", "hr_albedo_low_grad",
@@ -250,6 +252,13 @@ class Scene:
     def build_hierarchy(self, verts):
         _check(lib().hr_build_hierarchy(self._h, _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),
                                         _stream()), "hr_build_hierarchy")
+
+    def hierarchy_cost(self):
+        """Each hand's hierarchy cost as last refit (numpy float32 [n_hands];
+        synchronises the device)."""
+        out = np.zeros(self.n_hands, np.float32)
+        _check(lib().hr_hierarchy_cost(self._h, out.ctypes.data_as(ctypes.c_void_p)), "hr_hierarchy_cost")
+        return out
 
     def render(self, verts, albedo, background, it, image, hit_face=None):
         _check(lib().hr_render(self._h, _ptr(verts, shape=(self.n_hands, self.V, 3), name="verts"),

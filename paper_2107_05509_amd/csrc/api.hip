@@ -155,6 +155,7 @@ struct hr_scene {
     float* geom_part = nullptr;   // [hands,kSkinPart] skinning sums (zero between launches)
     int* geom_count = nullptr;    // [hands] finished blocks (reset by the last)
     float* joint_state = nullptr; // [hands, joint state] of hr_iterate's skinning, for its backward
+    float* bvh_cost = nullptr;    // [hands] traversal cost of the last refitted hierarchy
     int* hand_counter = nullptr;  // [1] hands finished in the geometry backward (reset by the last)
     int geom_blocks = 0;
     unsigned long long* counts = nullptr;   // [3][6] work counters (render, interior adjoint, edges)
@@ -584,6 +585,10 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
     }
     TRY(s->upload<int>(&s->geom_count, nullptr, (size_t)n_hands));
     TRY(s->upload<float>(&s->joint_state, nullptr, (size_t)n_hands * kJointStateFloats));
+    {
+        const std::vector<float> zero((size_t)n_hands, 0.0f);   // 0 until the first refit
+        TRY(s->upload(&s->bvh_cost, zero.data(), zero.size()));
+    }
     TRY(s->upload<int>(&s->hand_counter, nullptr, 1));
     TRY(s->upload<int>(&s->setup_done, nullptr, 1));
     if (hipMemset(s->hand_counter, 0, sizeof(int)) != hipSuccess ||
@@ -660,6 +665,21 @@ int hr_build_hierarchy(hr_scene* s, const float* verts, void* stream)
         int rc = upload_hierarchy(s, h, hb, faces.data());
         if (rc) return rc;
     }
+    // the stored samples of an earlier render name leaf slots of the old
+    // topology: a backward reusing them prepares and traces again
+    s->layout_changed = true;
+    s->edges_valid = false;
+    if (hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess)
+        return fail(HR_EHIP, "hr_build_hierarchy: memset");
+    return HR_OK;
+}
+
+int hr_hierarchy_cost(hr_scene* s, float* cost_host)
+{
+    if (!s || !cost_host) return fail(HR_EINVAL, "hr_hierarchy_cost: null argument");
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(cost_host, s->bvh_cost, sizeof(float) * s->n_hands, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(HR_EHIP, "hr_hierarchy_cost: %s", hipGetErrorString(e));
     return HR_OK;
 }
 
@@ -686,6 +706,7 @@ static int prepare(hr_scene* s, const float* verts, hipStream_t st, bool reset_t
     a.mask = mask; a.view_scale = s->view_scale; a.setup_done = s->setup_done;
     a.bins = s->bins;
     a.with_bins = s->accel == HR_ACCEL_AUTO ? 1 : 0;
+    a.bvh_cost = s->bvh_cost;
     a.n_hands = s->n_hands; a.n_views = s->n_views; a.with_setup = 1; a.with_scale = with_scale;
     const dim3 grid(2 * s->n_hands + (3 + (with_scale ? 1 : 0)) * s->n_views);
     return launch(s, "k_prepare", k_prepare, grid, dim3(512), s->smem_prepare, st, a);

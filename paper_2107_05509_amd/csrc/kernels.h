@@ -224,6 +224,7 @@ struct PrepArgs {
     BinDev bins;               // the views' screen bins (built every launch)
     int with_bins;             // 0: every view marked unbinned (hierarchy only)
     int n_hands, n_views, with_setup, with_scale;
+    float* bvh_cost;           // [H] the refitted hierarchy's traversal cost (see refit_hand)
 };
 
 // geometry backward (k_geom_p1, k_geom_p2)

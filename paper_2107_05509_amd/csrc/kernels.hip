@@ -491,8 +491,20 @@ __device__ void normals_hand(const MeshDev& m, const float* __restrict__ verts, 
     }
 }
 
+__device__ __forceinline__ float box_area(const float* lo, const float* hi)
+{
+    const float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    return 2.0f * (dx * dy + dy * dz + dz * dx);
+}
+
+// Refit of hand h's hierarchy; with cost, also its quality: the sum over
+// the internal nodes of their two child boxes' surface areas over the root
+// box's (the expected number of child-box tests of a ray through the root
+// box, the surface-area measure a topology build minimises).  It grows as
+// the pose drifts from the one the topology was built for.
 __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __restrict__ verts,
-                           Tri* __restrict__ tris, Node* __restrict__ nodes, int h, float* dyn)
+                           Tri* __restrict__ tris, Node* __restrict__ nodes, int h, float* dyn,
+                           float* __restrict__ cost)
 {
     const int V = m.V, F = m.F, NS = b.node_stride;
     // LDS: vertices, node bounds, child codes, vertex ids of the leaf slots,
@@ -557,6 +569,7 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
     // refit, level by level from the leaves up; the nodes at position q of
     // the height order are numbered n_nodes - 1 - q
     Node* nd = nodes + (size_t)h * NS;
+    float area = 0.0f;   // this thread's nodes' child-box areas
     for (int L = 0; L < n_levels; ++L) {
         for (int q = loff[L] + threadIdx.x; q < loff[L + 1]; q += blockDim.x) {
             const int n = n_nodes - 1 - q;
@@ -575,8 +588,21 @@ __device__ void refit_hand(const MeshDev& m, const BvhDev& b, const float* __res
                 nb[6 * n + k] = fminf(out.lo0[k], out.lo1[k]);
                 nb[6 * n + 3 + k] = fmaxf(out.hi0[k], out.hi1[k]);
             }
+            if (cost) area += box_area(out.lo0, out.hi0) + box_area(out.lo1, out.hi1);
         }
         __syncthreads();
+    }
+    if (!cost) return;
+    // block sum: waves, then the first thread (the root's box is node 0's)
+    __shared__ float wsum[16];
+    area = wave_sum(area);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = area;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float tot = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += wsum[w];
+        const float ra = n_nodes > 0 ? box_area(nb, nb + 3) : 0.0f;
+        cost[h] = ra > 0.0f ? tot / ra : 0.0f;
     }
 }
 
@@ -1565,7 +1591,7 @@ __global__ void __launch_bounds__(512) k_prepare(PrepArgs a)
     extern __shared__ float dyn[];
     int bid = blockIdx.x;
     if (bid < a.n_hands) {
-        refit_hand(a.m, a.b, a.verts, a.tris, a.nodes, bid, dyn);
+        refit_hand(a.m, a.b, a.verts, a.tris, a.nodes, bid, dyn, a.bvh_cost);
         return;
     }
     bid -= a.n_hands;

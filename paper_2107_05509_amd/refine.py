@@ -41,12 +41,19 @@ class Refiner:
     against `target` images under `mask`."""
 
     def __init__(self, scene: binding.Scene, params, albedo, background, target, mask=None, warm=50,
-                 graph_chunk=10, flags=binding.HR_GRAD_ALL):
+                 graph_chunk=10, flags=binding.HR_GRAD_ALL, rebuild_ratio=None):
+        """rebuild_ratio: after every `graph_chunk` iterations (a host
+        synchronisation), rebuild the hierarchy topology around the current
+        pose once a hand's hierarchy cost (hr_hierarchy_cost) exceeds
+        rebuild_ratio times its value after the last build; None: never."""
         self.scene = scene
         self.state = scene.make_state(params, albedo, background, target, mask)
         self.warm, self.chunk, self.flags = int(warm), int(graph_chunk), int(flags)
         self.it = 0            # host mirror of state.iter
         self._graphs = {}
+        self.rebuild_ratio = rebuild_ratio
+        self.rebuilds = 0
+        self._cost0 = None     # the costs first seen after the last build
 
     @property
     def params(self):
@@ -64,6 +71,18 @@ class Refiner:
         """Rebuild the hierarchy topology around the current pose (host work, synchronising)."""
         self.scene.skin(self.state.params, self.state.verts)
         self.scene.build_hierarchy(self.state.verts)
+        self._cost0 = None
+
+    def _check_hierarchy(self):
+        """With rebuild_ratio: rebuild once a hand's hierarchy has degraded."""
+        if self.rebuild_ratio is None:
+            return
+        cost = self.scene.hierarchy_cost()
+        if self._cost0 is None:
+            self._cost0 = cost
+        elif (cost > self.rebuild_ratio * self._cost0).any():
+            self.build_hierarchy()
+            self.rebuilds += 1
 
     def tune(self, reps=3):
         return self.scene.tune(self.state, reps)
@@ -111,14 +130,18 @@ class Refiner:
 
     def run(self, n_iters, graph=True):
         """Enqueue n_iters iterations (graph replays of `graph_chunk` iterations
-        where the schedule allows); no host synchronisation."""
+        where the schedule allows); no host synchronisation unless
+        rebuild_ratio is set (then one per `graph_chunk` iterations)."""
         if not graph:
             for _ in range(int(n_iters)):
                 self.step()
+                if self.rebuild_ratio is not None and self.it % self.chunk == 0:
+                    self._check_hierarchy()
             return
         for phase, n in self._plan(n_iters):
             self._graph(phase, n).launch()
             self.it += n
+            self._check_hierarchy()
 
 
 class FullRefiner:

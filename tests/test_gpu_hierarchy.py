@@ -1,0 +1,105 @@
+"""The hierarchy's quality measure (hr_hierarchy_cost) and rebuilds
+(hr_build_hierarchy) on the HIP path, through the C ABI.  The topology only
+changes speed: images and hit ids must be bit-identical whichever topology
+the refit starts from, and a refinement that rebuilds must agree with one that
+does not within the loop's atomic-order tolerance.  The measure (the internal
+nodes' child-box surface areas over the root box's) has no counterpart in the
+paper or the oracle; its checks are properties: it is positive and
+reproducible, it grows when the pose moves away from the one the topology was
+built for, and a rebuild at the new pose lowers it again."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, block_rel, f32
+from paper_2107_05509_amd import binding, refine, scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+class Hier:
+    def __init__(self, w, seed=3):
+        self.w = w
+        th, tw = w.albedo_true.shape[1:3]
+        self.g = binding.Scene(w.model, w.cams, w.n_hands, w.spp, th, tw, seed=seed)
+        self.bg = _t(f32(w.packed_background()))
+        self.albedo = _t(f32(w.albedo_true))
+
+    def verts(self, params):
+        v = torch.empty(self.w.n_hands, self.w.model.n_verts, 3, device=DEV)
+        self.g.skin(_t(f32(params)), v)
+        return v
+
+    def render(self, v):
+        img = torch.empty(self.g.P, 3, device=DEV)
+        hit = torch.empty(self.g.P, self.w.spp, device=DEV, dtype=torch.int32)
+        self.g.render(v, self.albedo, self.bg, 0, img, hit)
+        torch.cuda.synchronize()
+        return img.cpu().numpy(), hit.cpu().numpy(), self.g.hierarchy_cost()
+
+
+@pytest.fixture(scope="module")
+def hier():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("case: tiny workload, hierarchy cost and rebuilds", flush=True)
+    return Hier(scene.workload_tiny(0))
+
+
+def test_cost_grows_with_drift_and_rebuild_restores(hier):
+    h = hier
+    p0 = np.asarray(h.w.params_init, np.float32)
+    # a far pose: every finger joint bent by a further 0.6 rad (seeded)
+    rng = np.random.default_rng(17)
+    p1 = np.stack([scene.perturb_params(p, rng, pose_sigma=0.6, trans_mm=0.0) for p in p0]).astype(np.float32)
+    v0, v1 = h.verts(p0), h.verts(p1)
+    h.g.build_hierarchy(v0)
+    img0, hit0, c0 = h.render(v0)
+    img0b, hit0b, c0b = h.render(v0)
+    print("cost built at the start pose", c0, flush=True)
+    assert np.all(np.isfinite(c0)) and np.all(c0 > 0.0)
+    assert np.array_equal(c0, c0b) and np.array_equal(img0, img0b)
+    img1, hit1, c1 = h.render(v1)          # refit of the start pose's topology
+    h.g.build_hierarchy(v1)
+    img1r, hit1r, c1r = h.render(v1)       # topology built for the far pose
+    print("far pose: refit", c1, "rebuilt", c1r, flush=True)
+    assert np.all(c1 > c0)
+    assert np.all(c1r < c1)
+    # the topology never changes a result
+    assert np.array_equal(hit1, hit1r)
+    assert np.array_equal(img1, img1r)
+    h.g.build_hierarchy(v0)
+    img0c, hit0c, c0c = h.render(v0)
+    assert np.array_equal(hit0c, hit0) and np.array_equal(img0c, img0)
+    assert np.allclose(c0c, c0, rtol=1e-6)
+
+
+def test_refiner_rebuilds_keep_the_loop(hier):
+    # rebuild_ratio 0: every second check rebuilds (the first after a build
+    # records the cost); the loop must end where one that never rebuilds
+    # ends, up to the order of the atomic sums
+    w = hier.w
+    img = torch.empty(hier.g.P, 3, device=DEV)
+    hier.g.render(hier.verts(w.params_true), hier.albedo, hier.bg, 99, img)
+    target = img.clone()
+    outs = []
+    for ratio in (None, 0.0):
+        hier.g.build_hierarchy(hier.verts(w.params_init))
+        r = refine.Refiner(hier.g, _t(f32(w.params_init)), _t(f32(w.albedo_init)), hier.bg, target, None,
+                           warm=2, graph_chunk=3, rebuild_ratio=ratio)
+        r.run(12)
+        torch.cuda.synchronize()
+        outs.append((r.rebuilds, r.state.params.cpu().numpy().copy(), r.state.loss.cpu().numpy().copy()))
+    print("rebuilds", outs[1][0], "loss", outs[0][2], outs[1][2], flush=True)
+    assert outs[0][0] == 0 and outs[1][0] == 2
+    assert block_rel(outs[1][1], outs[0][1]) <= 1e-3
+    assert np.allclose(outs[1][2], outs[0][2], rtol=1e-3)
+
+
+def test_cost_argument_errors(hier):
+    with pytest.raises(binding.HRError):
+        binding._check(binding.lib().hr_hierarchy_cost(hier.g._h, None), "hr_hierarchy_cost")
