@@ -18,6 +18,7 @@ iterations of the all-variables phase.
 Prints one JSON line: the metric, per-kernel times, the roofline of the render launch and the CPU baseline.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -384,6 +385,43 @@ def bench_coverage(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_adam(args):
+    """The colour-map Adam step as a streaming pass (hr_step, k_adam): 4 hands
+    x 2048 x 2048 x 3 entries, each step reading the map, its gradient and
+    both moments and writing the map and the moments (28 B per entry)."""
+    w = scene.workload_tiny(args.seed)
+    H, T = 4, 2048
+    cams = []
+    for h in range(H):
+        c = dataclasses.replace(w.cams[0], hand=h)
+        cams.append(c)
+    g = binding.Scene(w.model, cams, H, 1, T, T, seed=0)
+    gen = torch.Generator(device="cuda").manual_seed(args.seed)
+    p = torch.zeros(H, 64, device="cuda")
+    gp = torch.rand(H, 64, device="cuda", generator=gen)
+    mp, vp = torch.zeros_like(p), torch.zeros_like(p)
+    a = torch.rand(H, T, T, 3, device="cuda", generator=gen)
+    ga = torch.rand(H, T, T, 3, device="cuda", generator=gen) - 0.5
+    ma, va = torch.zeros_like(a), torch.zeros_like(a)
+    lrs = (1e-2,) * 6
+    for i in range(5):
+        g.step(p, a, gp, ga, mp, vp, ma, va, i + 1, lrs)
+    reps = max(1, min(args.steps, 100))
+    ms = timed(lambda: [g.step(p, a, gp, ga, mp, vp, ma, va, i + 6, lrs) for i in range(reps)]) / reps
+    nbytes = a.numel() * 28 + 64 * H * 28
+    out = {
+        "metric": "colour-map Adam streaming pass (4 hands x 2048x2048x3)",
+        "value": round(nbytes / (ms * 1e-3) / 1e9, 1), "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 5,
+        "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "adam: 4 hands, 2048x2048x3 colour map each (50.3 M entries)", "entries": a.numel()},
+        "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms * 1e-3) / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(nbytes / (ms * 1e-3) / 1e9 / 8000.0, 4), "traffic": None, "kernel": "k_adam",
+                     "bytes_per_launch": int(nbytes)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_full(args):
     """The paper's full data term on the realistic workload: colour transforms,
     two-level colour map, blurred-Canny edge term beside the colour term
@@ -456,7 +494,8 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=2)
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-workload iteration time (40 views, 4 spp, 1024x1024 albedo)")
-    ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage", "full", "raster"), default="realistic",
+    ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage", "full", "raster", "adam"),
+                    default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
     args = ap.parse_args()
@@ -478,6 +517,8 @@ def main():
         return bench_full(args)
     if args.workload == "raster":
         return bench_raster(args)
+    if args.workload == "adam":
+        return bench_adam(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))
