@@ -385,6 +385,104 @@ def bench_coverage(args):
     print(json.dumps(out), flush=True)
 
 
+def oracle_phases(w, iters=10):
+    """The oracle's refinement of the small case, `iters` iterations from the
+    initial parameters, each timed per phase (skinning with vertex normals,
+    render, loss, backward: interior and edge terms and the chain through the
+    normals and the skinning, Adam step); host-made inputs only (target: the
+    oracle's own render of the true parameters at 16 samples per pixel)."""
+    import oracle
+    oracle.build(force=False)
+    tab = scene.camera_arrays(w.cams)
+    osc = oracle.Scene(w.model.faces, w.model.uv, tab, scene.SHADING, w.model.edges, w.model.edge_faces)
+    om = oracle.Model(w.model)
+    P = int(tab["pix_off"][-1])
+    bg = np.asarray(w.packed_background(), np.float64)
+    vt, _ = oracle.skin(om, torch.as_tensor(w.params_true.astype(np.float64)))
+    vt = vt.numpy()
+    target = oracle.render(osc, vt, oracle.vertex_normals(torch.as_tensor(vt), om.faces).numpy(),
+                           w.albedo_true.astype(np.float64), bg, 16, 7000, 0)
+    mask = np.ones(P, np.uint8)
+    params = w.params_init.astype(np.float32).astype(np.float64)
+    alb = w.albedo_init.astype(np.float64)
+    mp, vp, ma, va = np.zeros_like(params), np.zeros_like(params), np.zeros_like(alb), np.zeros_like(alb)
+    lr = np.zeros(64)
+    lr[0:3], lr[3:48], lr[48:58], lr[58:61], lr[61:64] = refine.LR_ALL[:5]
+    ph = {k: 0.0 for k in ("skin", "render", "loss", "backward", "step")}
+    for it in range(iters):
+        t0 = time.perf_counter()
+        p = torch.as_tensor(params).requires_grad_(True)
+        verts, _ = oracle.skin(om, p)
+        normals = oracle.vertex_normals(verts, om.faces)
+        v_np, n_np = verts.detach().numpy(), normals.detach().numpy()
+        t1 = time.perf_counter()
+        img = oracle.render(osc, v_np, n_np, alb, bg, w.spp, 1000, it)
+        t2 = time.perf_counter()
+        _, dimg = oracle.l1_loss(img, target, mask, tab["pix_off"], tab["hand"], w.n_hands)
+        t3 = time.perf_counter()
+        ga, gv, gn = oracle.backward_interior(osc, v_np, n_np, alb, dimg, w.spp, 1000, it)
+        gv = gv + oracle.backward_edges(osc, v_np, n_np, alb, bg, dimg, 1000, it)
+        torch.autograd.backward([verts, normals], [torch.as_tensor(gv), torch.as_tensor(gn)])
+        gp = p.grad.numpy()
+        t4 = time.perf_counter()
+        params, mp, vp = oracle.adam_step(params, gp, mp, vp, it + 1, lr)
+        alb, ma, va = oracle.adam_step(alb, ga, ma, va, it + 1, refine.LR_ALL[5], lo=0.0, hi=1.0)
+        t5 = time.perf_counter()
+        for k, a, b in (("skin", t0, t1), ("render", t1, t2), ("loss", t2, t3), ("backward", t3, t4),
+                        ("step", t4, t5)):
+            ph[k] += b - a
+    total = sum(ph.values())
+    return {"value": round(iters / total, 3), "unit": "iters/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"all {iters} iterations of the small case, float64 brute force; {total:.2f} s",
+            "seconds": round(total, 3), "seconds_per_phase": {k: round(v, 4) for k, v in ph.items()}}
+
+
+def bench_tiny(args):
+    """The small case (1 hand, 4 views 64x64, 4 spp, 64x64 colour map; a
+    refinement of 10 iterations): the GPU's time for the 10 iterations (one
+    graph launch, every variable from the first iteration, repeated from the
+    initial state) beside the oracle's 10 iterations timed per phase on the
+    host cores."""
+    w = scene.workload_tiny(args.seed)
+    print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
+    ref = make_refiner(w, seed=args.seed, tune=False, cover_spp=64)
+    ref.warm = 0
+    ref.chunk = 10
+    q = ref.state
+    start = {k: getattr(q, k).clone() for k in ("params", "albedo")}
+
+    def restart():
+        # every timed refinement starts from the initial state
+        for k, v in start.items():
+            getattr(q, k).copy_(v)
+        for t in (q.m_params, q.v_params, q.m_albedo, q.v_albedo, q.iter):
+            t.zero_()
+        ref.it = 0
+
+    ref.run(10)                         # captures the graph
+    reps = max(1, min(args.steps, 100))
+    ms = []
+    for _ in range(reps + 2):
+        restart()
+        ms.append(timed(lambda: ref.run(10)))
+    ms10 = float(np.mean(ms[2:]))
+    samples = w.n_pixels * w.spp
+    out = {
+        "metric": "small case: refine iterations/s (4 views 64x64, 4 spp, 10 iterations)",
+        "value": round(10 / (ms10 * 1e-3), 1), "unit": "iters/s", "n_gpus": 1, "steps": 10 * reps, "warmup": 30,
+        "ms_per_step": round(ms10 / 10, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "tiny: 1 hand, 4 views 64x64, 4 spp, 64x64 albedo", "views": len(w.cams),
+                   "camera_samples_per_step": int(samples)},
+        "ms_per_10_iterations": round(ms10, 4), "repetitions": reps,
+        "camera_msamples_per_s": round(samples / (ms10 / 10 * 1e-3) / 1e6, 1),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] oracle: 10 iterations, per phase ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = oracle_phases(w, 10)
+    print(json.dumps(out), flush=True)
+
+
 def bench_adam(args):
     """The colour-map Adam step as a streaming pass (hr_step, k_adam): 4 hands
     x 2048 x 2048 x 3 entries, each step reading the map, its gradient and
@@ -494,7 +592,8 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=2)
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-workload iteration time (40 views, 4 spp, 1024x1024 albedo)")
-    ap.add_argument("--workload", choices=("realistic", "batched", "proposal", "coverage", "full", "raster", "adam"),
+    ap.add_argument("--workload",
+                    choices=("realistic", "batched", "proposal", "coverage", "full", "raster", "adam", "tiny"),
                     default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
@@ -519,6 +618,8 @@ def main():
         return bench_raster(args)
     if args.workload == "adam":
         return bench_adam(args)
+    if args.workload == "tiny":
+        return bench_tiny(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))
