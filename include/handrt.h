@@ -315,8 +315,8 @@ void hr_graph_destroy(hr_graph* graph);
 int hr_set_grid(hr_scene* scene, int32_t render_blocks, int32_t adjoint_blocks);
 
 /* Acceleration of the camera rays (speed only: hits and images are identical
-   either way).  HR_ACCEL_AUTO (default): per-view screen bins of 16 x 16
-   pixels list the triangles whose padded screen bounds touch them (camera
+   either way).  HR_ACCEL_AUTO (default): per-view screen bins (16 x 16
+   pixels unless hr_set_tiles or hr_tune chose 8 or 32) list the triangles whose padded screen bounds touch them (camera
    rays all start at the camera centre), with the bounding-volume hierarchy
    for views where binning does not apply (a vertex within 1 mm of the camera
    plane, more than 8192 bins, more than 16 F entries) and for the edge

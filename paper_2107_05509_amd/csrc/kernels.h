@@ -54,8 +54,9 @@ struct BvhDev {
     const int* slot_verts;     // [H, F, 3] vertex ids of each leaf slot's triangle
 };
 
-// Per-view screen bins of the camera rays: each 16 x 16-pixel bin lists the
-// leaf slots of the triangles whose padded screen bounds touch it.  Camera
+// Per-view screen bins of the camera rays: each bin of 2^log2 x 2^log2
+// pixels (16 x 16 by default) lists the leaf slots of the triangles whose
+// padded screen bounds touch it.  Camera
 // rays all start at the camera centre, so a ray through a screen point can
 // only hit triangles listed in that point's bin: the lists replace the
 // hierarchy for them (views whose bins are incomplete keep the hierarchy).
