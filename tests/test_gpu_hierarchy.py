@@ -80,24 +80,35 @@ def test_cost_grows_with_drift_and_rebuild_restores(hier):
 
 def test_refiner_rebuilds_keep_the_loop(hier):
     # rebuild_ratio 0: every second check rebuilds (the first after a build
-    # records the cost); the loop must end where one that never rebuilds
-    # ends, up to the order of the atomic sums
+    # records the cost), so four one-iteration chunks rebuild twice.  The
+    # loop must end where one that never rebuilds ends, up to the order of
+    # the atomic sums: Adam's normalised steps amplify last-bit differences,
+    # so the bar is the spread between two runs that never rebuild (times 3),
+    # and no tighter than 2e-3 (parameters) and 2e-2 (the last iterate's loss,
+    # which magnifies the parameters' differences near the optimum; over 12
+    # iterations runs have differed by 2.1e-3 and 1.3e-2)
     w = hier.w
     img = torch.empty(hier.g.P, 3, device=DEV)
     hier.g.render(hier.verts(w.params_true), hier.albedo, hier.bg, 99, img)
     target = img.clone()
     outs = []
-    for ratio in (None, 0.0):
+    for ratio in (None, None, 0.0):
         hier.g.build_hierarchy(hier.verts(w.params_init))
         r = refine.Refiner(hier.g, _t(f32(w.params_init)), _t(f32(w.albedo_init)), hier.bg, target, None,
-                           warm=2, graph_chunk=3, rebuild_ratio=ratio)
-        r.run(12)
+                           warm=0, graph_chunk=1, rebuild_ratio=ratio)
+        r.run(4)
         torch.cuda.synchronize()
         outs.append((r.rebuilds, r.state.params.cpu().numpy().copy(), r.state.loss.cpu().numpy().copy()))
-    print("rebuilds", outs[1][0], "loss", outs[0][2], outs[1][2], flush=True)
-    assert outs[0][0] == 0 and outs[1][0] == 2
-    assert block_rel(outs[1][1], outs[0][1]) <= 1e-3
-    assert np.allclose(outs[1][2], outs[0][2], rtol=1e-3)
+    (n0, p0, l0), (n1, p1, l1), (n2, p2, l2) = outs
+    noise_p = block_rel(p1, p0)
+    noise_l = float(np.max(np.abs(l1 - l0) / np.abs(l0)))
+    err_p = block_rel(p2, p0)
+    err_l = float(np.max(np.abs(l2 - l0) / np.abs(l0)))
+    print("rebuilds", n0, n1, n2, "params", noise_p, err_p, "loss", noise_l, err_l, flush=True)
+    assert n0 == 0 and n1 == 0 and n2 == 2
+    assert np.all(np.isfinite(p2)) and np.all(np.isfinite(l2))
+    assert err_p <= max(3.0 * noise_p, 2e-3)
+    assert err_l <= max(3.0 * noise_l, 2e-2)
 
 
 def test_cost_argument_errors(hier):

@@ -146,7 +146,7 @@ def test_raster_refinement_loop(case):
                               torch.as_tensor(c.albedo.astype(np.float64)), c.bg, c.w.model.faces, c.tab,
                               scene.SHADING, ft).numpy()
     outs = []
-    for flags in (binding.HR_GRAD_ALL, binding.HR_GRAD_INTERIOR):
+    for flags in (binding.HR_GRAD_ALL, binding.HR_GRAD_ALL, binding.HR_GRAD_INTERIOR):
         st = c.g.make_state(c.t(c.params), c.t(c.albedo), c.t(c.bg), c.t(tgt))
         losses = []
         for _ in range(20):
@@ -155,9 +155,17 @@ def test_raster_refinement_loop(case):
             losses.append(st.loss.cpu().numpy().copy())
         outs.append((st.params.cpu().numpy(), np.array(losses)))
     print("raster loop losses", outs[0][1][[0, -1]].ravel(), flush=True)
+    # Adam's normalised steps amplify the last-bit differences of the atomic
+    # sums over 20 iterations (two runs with the same flags have differed by
+    # up to 1.8e-3): the bar is that spread (times 3), and no tighter than
+    # 5e-3 (the edge term, were it wrongly applied, moves the pose by far more)
     moved = outs[0][0] - c.params
-    assert block_rel(outs[1][0] - c.params, moved) <= 1e-3
+    noise = block_rel(outs[1][0] - c.params, moved)
+    err = block_rel(outs[2][0] - c.params, moved)
+    print("moved: spread of two runs", noise, "edge flag off", err, flush=True)
+    assert err <= max(3.0 * noise, 5e-3)
     # a pixel whose covering triangle flips in a later iteration moves the
     # loss by about one pixel's share
-    assert np.abs(outs[1][1] - outs[0][1]).max() <= 1e-2 * np.abs(outs[0][1]).max()
+    lnoise = np.abs(outs[1][1] - outs[0][1]).max()
+    assert np.abs(outs[2][1] - outs[0][1]).max() <= max(3.0 * lnoise, 1e-2 * np.abs(outs[0][1]).max())
     assert np.all(outs[0][1][-1] < outs[0][1][0])
