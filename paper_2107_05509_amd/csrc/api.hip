@@ -159,6 +159,7 @@ struct hr_scene {
     int* hand_counter = nullptr;  // [1] hands finished in the geometry backward (reset by the last)
     int geom_blocks = 0;
     unsigned long long* counts = nullptr;   // [3][6] work counters (render, interior adjoint, edges)
+    int n_cu = 0;                 // compute units of the scene's device
     // full data term (hr_data_term_set, hr_edge_map, hr_loss_full)
     bool dt_alloc = false;
     DataTermDev dt{};
@@ -559,6 +560,14 @@ int hr_scene_create(hr_scene** out, const hr_mesh_desc* m, int32_t n_hands, cons
         }
     }
 
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&s->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            hr_scene_destroy(s);
+            return fail(HR_EHIP, "scene init: device attributes");
+        }
+    }
     if (hipMemset(s->hit_iter, 0xFF, sizeof(int)) != hipSuccess) {
         hr_scene_destroy(s);
         return fail(HR_EHIP, "scene init: memset");
@@ -825,7 +834,7 @@ static EdgeArgs edge_args(hr_scene* s, const float* verts, const float* albedo, 
     a.nodes = s->nodes; a.tris = s->tris; a.normals = s->normals; a.uv = s->mesh.uv;
     a.albedo = albedo; a.background = background; a.dimage = dimage; a.gacc = s->gacc;
     a.stat_a = nullptr; a.stat_dc = nullptr;
-    a.samples = s->samples; a.sample_cap = s->sample_cap;
+    a.samples = s->samples; a.sample_cap = s->sample_cap; a.few_waves = s->n_cu;
     a.counts = s->counts + 12;
     a.n_nodes = s->bvh.node_stride; a.tex_h = s->cfg.tex_h; a.tex_w = s->cfg.tex_w;
     a.delta = s->cfg.edge_delta; a.iter = iter; a.iter_dev = iter_dev; a.seed = s->cfg.seed;

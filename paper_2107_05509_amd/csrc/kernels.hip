@@ -1902,17 +1902,23 @@ __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e
     if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iteration(a.iter_dev, a.iter);
     const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
     const int nw = (int)((nb * kThreads) >> 6);
-    // the first n_ew waves trace the edge samples (32 lane pairs each), from
-    // the start: their traversals are long dependent chains; the other waves
-    // render the tiles
-    int n_ew = 0;
+    // the first n_ew waves trace the edge samples, from the start: their
+    // traversals are long dependent chains; the other waves render the
+    // tiles.  A wave takes pw lane pairs (one sample per pair), 32 while the
+    // samples are many; when they are few, smaller packets (down to 8 pairs)
+    // give more and shorter chains (an incoherent packet walks the union of
+    // its rays' paths), as long as the edge waves stay at most one per
+    // compute unit
+    int n_ew = 0, pw = 32;
     if (with_edges) {
         const long long stored = min(e.prefix[e.n_views], e.sample_cap);
-        n_ew = (int)min((stored + 31) / 32, (long long)max(1, nw / 2));
+        while (pw > 8 && (stored + pw / 2 - 1) / (pw / 2) <= e.few_waves) pw >>= 1;
+        n_ew = (int)min((stored + pw - 1) / pw, (long long)max(1, nw / 2));
     }
     if (gw < n_ew) {
-        const long long first = (long long)gw * 32 + ((threadIdx.x & 63) >> 1);
-        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * 32, wstack);
+        const int pr = (threadIdx.x & 63) >> 1;   // the lane's pair; pairs past pw idle
+        const long long first = pr < pw ? (long long)gw * pw + pr : (1LL << 62);
+        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * pw, wstack);
     } else {
         render_tiles<COUNT, RASTER>(a, gw - n_ew, nw - n_ew, wstack);
     }
