@@ -772,6 +772,12 @@ static int render_impl(hr_scene* s, const float* verts, const float* albedo, con
         if (s->counting) return launch(s, "k_render", k_render<true, true>, grid, dim3(kThreads), 0, st, a, e, 0);
         return launch(s, "k_render", k_render<false, true>, grid, dim3(kThreads), 0, st, a, e, 0);
     }
+    // few tiles: the tiles of all views at most one wave per SIMD (4 per CU)
+    if (s->tile_cap <= 4LL * s->n_cu && grid.x >= 2) {
+        if (s->counting)
+            return launch(s, "k_render", k_render_few<true>, grid, dim3(kThreads), 0, st, a, e, with_edges);
+        return launch(s, "k_render", k_render_few<false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
+    }
     if (s->counting) return launch(s, "k_render", k_render<true, false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
     return launch(s, "k_render", k_render<false, false>, grid, dim3(kThreads), 0, st, a, e, with_edges);
 }

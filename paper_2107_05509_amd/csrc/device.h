@@ -417,7 +417,9 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
 // the tile's rays pass through screen points in [x0, x1] x [y0, y1].  Every
 // triangle that a ray of the tile can hit is listed and touches that
 // rectangle, and the closest hit is the minimum of (t, face id) over them:
-// the result equals a brute-force loop over all triangles.  Before its
+// the result equals a brute-force loop over all triangles.  With NP > 1 the
+// calling wave takes only the touching triangles whose rank in the list is
+// part mod NP (the minimum over the NP parts is the whole list's).  Before its
 // watertight test a triangle is skipped by the wave when no lane can find
 // it nearer than its best hit so far: the test computes t as a weighted mean
 // of the three vertices' (v[kz] - o[kz]) Sz with non-negative weights, so t
@@ -426,10 +428,11 @@ __device__ __forceinline__ void trace_wave(const Node* __restrict__ nodes, const
 // drops a hit at or before the lane's best, ties included.  The lanes that
 // call it share the list (each loads every n-th entry, n = the calling
 // lanes); `active` selects the lanes whose rays are traced.
-template <bool COUNT = false>
+template <bool COUNT = false, int NP = 1>
 __device__ __forceinline__ void trace_bins(const Tri* __restrict__ tris, const uint16_t* __restrict__ ent, int cnt,
                                            const float4* __restrict__ box, float x0, float y0, float x1, float y1,
-                                           const Ray& r, bool active, Hit& h, TraceCount* tc = nullptr)
+                                           const Ray& r, bool active, Hit& h, TraceCount* tc = nullptr,
+                                           int part = 0)
 {
     h.face = -1;
     h.slot = 0;
@@ -444,6 +447,7 @@ __device__ __forceinline__ void trace_bins(const Tri* __restrict__ tris, const u
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(exec >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)exec, 0u));
     const float okz = comp(r.o, r.kz);
+    int rank_t = 0;   // touching triangles seen (NP > 1)
     // lane-parallel loads of a chunk of entries: each lane fetches its
     // entry's bounds and triangle at once (no dependent fetch per triangle),
     // the loop then broadcasts the touching ones lane by lane
@@ -464,6 +468,7 @@ __device__ __forceinline__ void trace_bins(const Tri* __restrict__ tris, const u
         while (m) {
             const int l = __builtin_ctzll(m);
             m &= m - 1;
+            if (NP > 1 && (rank_t++ % NP) != part) continue;
             const int s = __builtin_amdgcn_readlane(slot, l);
             auto rl = [l](float x) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); };
             const float v0[3] = {rl(q0.x), rl(q0.y), rl(q0.z)};

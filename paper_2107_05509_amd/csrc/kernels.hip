@@ -936,9 +936,15 @@ __device__ void render_side_work(const RenderArgs& a, int bid, int nb)
 
 // Wave tiles gw, gw + nw, ... (wave-uniform gw).  RASTER: hard rasterisation
 // (a separate instantiation, so the ray tracer's register allocation does not
-// carry the rasteriser's float64 state).
-template <bool COUNT, bool RASTER>
-__device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
+// carry the rasteriser's float64 state).  SPLIT > 1 (few tiles, ray tracing
+// only): the SPLIT waves of a block render the same tiles, gw and nw then
+// counting blocks; each walks every SPLIT-th touching triangle of the tile's
+// screen bin, the partial closest hits meet in LDS (`xch`: two halves of
+// SPLIT x 64 (t, face, slot) records, alternating per round, so that one
+// barrier per round suffices) and the block's first wave takes their
+// minimum, shades and writes the tile while the others go on.
+template <bool COUNT, bool RASTER, int SPLIT = 1>
+__device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack, float* xch = nullptr)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     int* wst = stack + kMaxStack * (threadIdx.x >> 6);
@@ -947,6 +953,8 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
     const int s_lane = lane & (G - 1);
     const int n_tiles = *a.tile_count;
     const float inv_spp = 1.0f / (float)a.spp;
+    const int wv = SPLIT > 1 ? (int)(threadIdx.x >> 6) : 0;   // the wave's part of each bin
+    int xr = 0;                                               // exchanges so far (the LDS half)
     TraceCount tc;
     unsigned long long n_rays = 0, n_hit = 0;
     for (int t = gw; t < n_tiles; t += nw) {
@@ -1005,10 +1013,39 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
                 Ray ray;
                 ray_screen(c, (float)px + u, (float)py + v, ray);
                 if (binned)
-                    trace_bins<COUNT>(tris, bent, bcnt, bbox, rx0, ry0, rx1, ry1, ray, act, h, &tc);
-                else
+                    trace_bins<COUNT, SPLIT>(tris, bent, bcnt, bbox, rx0, ry0, rx1, ry1, ray, act, h, &tc, wv);
+                else if (wv == 0)
                     trace_wave<COUNT, true>(nodes, tris, ray, act, wst, h, &tc);
             }
+            if (SPLIT > 1 && !empty) {
+                // the block's partial hits (the tile, hence `empty`, is the
+                // block's): lexicographic minimum of (t, face)
+                float* x = xch + (size_t)(xr & 1) * SPLIT * 64 * 3;
+                ++xr;
+                float bt = h.face >= 0 ? h.t : __builtin_inff();
+                int bf = h.face >= 0 ? h.face : 0x7fffffff, bs = h.slot;
+                float* mine = x + (wv * 64 + lane) * 3;
+                mine[0] = bt;
+                mine[1] = __int_as_float(bf);
+                mine[2] = __int_as_float(bs);
+                __syncthreads();
+                if (wv == 0) {
+                    for (int k = 1; k < SPLIT; ++k) {
+                        const float* o = x + (k * 64 + lane) * 3;
+                        const float ot = o[0];
+                        const int of = __float_as_int(o[1]);
+                        if (ot < bt || (ot == bt && of < bf)) {
+                            bt = ot;
+                            bf = of;
+                            bs = __float_as_int(o[2]);
+                        }
+                    }
+                    h.face = bf == 0x7fffffff ? -1 : bf;
+                    h.slot = bs;
+                    h.t = bt;
+                }
+            }
+            if (SPLIT > 1 && wv != 0) continue;   // shading and writes: the block's first wave
             if (act) {
                 if (COUNT && !empty) ++n_rays;
                 if (a.hit_face) a.hit_face[pg * a.spp + s] = h.face;
@@ -1025,6 +1062,7 @@ __device__ void render_tiles(const RenderArgs& a, int gw, int nw, int* stack)
                 }
             }
         }
+        if (SPLIT > 1 && wv != 0) continue;
         // sum over the G lanes of the pixel (fixed butterfly order)
         for (int o = G >> 1; o > 0; o >>= 1) {
             acc[0] += __shfl_xor(acc[0], o);
@@ -1889,6 +1927,30 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
 // launches of the ray-tracing work
 // ===========================================================================
 
+// The render's edge waves: the first n_ew waves trace the edge samples,
+// from the start: their traversals are long dependent chains; the other
+// waves render the tiles.  A wave takes pw lane pairs (one sample per pair),
+// 32 while the samples are many; when they are few, smaller packets (down to
+// 8 pairs) give more and shorter chains (an incoherent packet walks the
+// union of its rays' paths), as long as the edge waves stay at most one per
+// compute unit.  Returns n_ew (at most half the waves).
+__device__ __forceinline__ int edge_waves(const EdgeArgs& e, int with_edges, int nw, int& pw)
+{
+    pw = 32;
+    if (!with_edges) return 0;
+    const long long stored = min(e.prefix[e.n_views], e.sample_cap);
+    while (pw > 8 && (stored + pw / 2 - 1) / (pw / 2) <= e.few_waves) pw >>= 1;
+    return (int)min((stored + pw - 1) / pw, (long long)max(1, nw / 2));
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void render_edge_wave(const EdgeArgs& e, int gw, int n_ew, int pw, int* wstack)
+{
+    const int pr = (threadIdx.x & 63) >> 1;   // the lane's pair; pairs past pw idle
+    const long long first = pr < pw ? (long long)gw * pw + pr : (1LL << 62);
+    edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * pw, wstack);
+}
+
 // Render: every block writes its share of the pixels outside the views'
 // tiled rectangles; with edges, the first waves trace the edge samples' side
 // points (a wave packet per hand the wave's samples look at) while the
@@ -1902,26 +1964,37 @@ __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e
     if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iteration(a.iter_dev, a.iter);
     const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
     const int nw = (int)((nb * kThreads) >> 6);
-    // the first n_ew waves trace the edge samples, from the start: their
-    // traversals are long dependent chains; the other waves render the
-    // tiles.  A wave takes pw lane pairs (one sample per pair), 32 while the
-    // samples are many; when they are few, smaller packets (down to 8 pairs)
-    // give more and shorter chains (an incoherent packet walks the union of
-    // its rays' paths), as long as the edge waves stay at most one per
-    // compute unit
-    int n_ew = 0, pw = 32;
-    if (with_edges) {
-        const long long stored = min(e.prefix[e.n_views], e.sample_cap);
-        while (pw > 8 && (stored + pw / 2 - 1) / (pw / 2) <= e.few_waves) pw >>= 1;
-        n_ew = (int)min((stored + pw - 1) / pw, (long long)max(1, nw / 2));
-    }
-    if (gw < n_ew) {
-        const int pr = (threadIdx.x & 63) >> 1;   // the lane's pair; pairs past pw idle
-        const long long first = pr < pw ? (long long)gw * pw + pr : (1LL << 62);
-        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * pw, wstack);
-    } else {
+    int pw;
+    const int n_ew = edge_waves(e, with_edges, nw, pw);
+    if (gw < n_ew)
+        render_edge_wave<COUNT>(e, gw, n_ew, pw, wstack);
+    else
         render_tiles<COUNT, RASTER>(a, gw - n_ew, nw - n_ew, wstack);
-    }
+}
+
+// The same render for scenes with few tiles (the tiles of all views at most
+// one per SIMD, ray tracing only; grid of at least two blocks): most SIMDs
+// would idle, and a tile's bin walk is one wave's chain of triangle tests,
+// so the waves of a block share each tile (render_tiles with SPLIT); the
+// edge waves take whole blocks, leaving at least one block to the tiles.
+template <bool COUNT>
+__global__ void __launch_bounds__(kThreads, 5) k_render_few(RenderArgs a, EdgeArgs e, int with_edges)
+{
+    constexpr int kSplit = kThreads / 64;
+    __shared__ int wstack[kMaxStack * kSplit];
+    __shared__ float xch[2 * kThreads * 3];   // the waves' partial hits
+    const int bid = (int)blockIdx.x, nb = (int)gridDim.x;
+    render_side_work(a, bid, nb);
+    if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iteration(a.iter_dev, a.iter);
+    const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
+    const int nw = (int)((nb * kThreads) >> 6);
+    int pw;
+    int n_ew = edge_waves(e, with_edges, nw, pw);
+    n_ew = min((n_ew + kSplit - 1) / kSplit * kSplit, (nb - 1) * kSplit);
+    if (gw < n_ew)
+        render_edge_wave<COUNT>(e, gw, n_ew, pw, wstack);
+    else
+        render_tiles<COUNT, false, kSplit>(a, bid - n_ew / kSplit, nb - n_ew / kSplit, wstack, xch);
 }
 
 // Edge samples, first part: trace and shade both side points of every stored
