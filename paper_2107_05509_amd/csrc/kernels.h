@@ -183,8 +183,8 @@ struct EdgeArgs {
     float* stat_dc;            // [n_views,E,4] nullable: sum of |c- - c+| per channel, sample count
     EdgeSample* samples;       // [sample_cap] traced samples
     long long sample_cap;
-    int few_waves;             // the device's compute units: the render's edge packets shrink while
-                               // their waves stay at most this many
+    int few_waves;             // the device's compute units: the few-tile render's edge packets shrink
+                               // while their waves stay at most this many
     unsigned long long* counts;
     int n_nodes, tex_h, tex_w;
     float delta;

@@ -1927,19 +1927,17 @@ __device__ void edge_samples(const EdgeArgs& a, long long first, long long npair
 // launches of the ray-tracing work
 // ===========================================================================
 
-// The render's edge waves: the first n_ew waves trace the edge samples,
-// from the start: their traversals are long dependent chains; the other
-// waves render the tiles.  A wave takes pw lane pairs (one sample per pair),
-// 32 while the samples are many; when they are few, smaller packets (down to
-// 8 pairs) give more and shorter chains (an incoherent packet walks the
-// union of its rays' paths), as long as the edge waves stay at most one per
-// compute unit.  Returns n_ew (at most half the waves).
-__device__ __forceinline__ int edge_waves(const EdgeArgs& e, int with_edges, int nw, int& pw)
+// The few-tile render's edge waves: a wave takes pw lane pairs (one sample
+// per pair), 32 while the samples are many; when they are few, smaller
+// packets (down to 2 pairs) give more and shorter chains (an incoherent
+// packet walks the union of its rays' paths), as long as the edge waves stay
+// at most one per compute unit.  Returns their number (at most half the waves).
+__device__ __forceinline__ int edge_waves_adaptive(const EdgeArgs& e, int with_edges, int nw, int& pw)
 {
     pw = 32;
     if (!with_edges) return 0;
     const long long stored = min(e.prefix[e.n_views], e.sample_cap);
-    while (pw > 8 && (stored + pw / 2 - 1) / (pw / 2) <= e.few_waves) pw >>= 1;
+    while (pw > 2 && (stored + pw / 2 - 1) / (pw / 2) <= e.few_waves) pw >>= 1;
     return (int)min((stored + pw - 1) / pw, (long long)max(1, nw / 2));
 }
 
@@ -1964,12 +1962,21 @@ __global__ void __launch_bounds__(kThreads, 5) k_render(RenderArgs a, EdgeArgs e
     if (a.hit_iter && bid == 0 && threadIdx.x == 0) *a.hit_iter = (int)iteration(a.iter_dev, a.iter);
     const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
     const int nw = (int)((nb * kThreads) >> 6);
-    int pw;
-    const int n_ew = edge_waves(e, with_edges, nw, pw);
-    if (gw < n_ew)
-        render_edge_wave<COUNT>(e, gw, n_ew, pw, wstack);
-    else
+    // the first n_ew waves trace the edge samples (32 lane pairs each), from
+    // the start: their traversals are long dependent chains; the other waves
+    // render the tiles.  (The few-tile render's adaptive packet size costs
+    // this kernel's tile path scalar registers and time.)
+    int n_ew = 0;
+    if (with_edges) {
+        const long long stored = min(e.prefix[e.n_views], e.sample_cap);
+        n_ew = (int)min((stored + 31) / 32, (long long)max(1, nw / 2));
+    }
+    if (gw < n_ew) {
+        const long long first = (long long)gw * 32 + ((threadIdx.x & 63) >> 1);
+        edge_samples<COUNT, kEdgeTrace>(e, first, (long long)n_ew * 32, wstack);
+    } else {
         render_tiles<COUNT, RASTER>(a, gw - n_ew, nw - n_ew, wstack);
+    }
 }
 
 // The same render for scenes with few tiles (the tiles of all views at most
@@ -1989,7 +1996,7 @@ __global__ void __launch_bounds__(kThreads, 5) k_render_few(RenderArgs a, EdgeAr
     const int gw = __builtin_amdgcn_readfirstlane((int)((bid * kThreads + threadIdx.x) >> 6));
     const int nw = (int)((nb * kThreads) >> 6);
     int pw;
-    int n_ew = edge_waves(e, with_edges, nw, pw);
+    int n_ew = edge_waves_adaptive(e, with_edges, nw, pw);
     n_ew = min((n_ew + kSplit - 1) / kSplit * kSplit, (nb - 1) * kSplit);
     if (gw < n_ew)
         render_edge_wave<COUNT>(e, gw, n_ew, pw, wstack);
