@@ -128,6 +128,10 @@ def test_graph_matches_iterate(loop):
 
 
 def test_grid_does_not_change_images(loop):
+    # this small scene's tiles are few (all views' tiles at most one per
+    # SIMD): grids of two blocks or more render with k_render_few (the waves
+    # of a block share each tile, edge packets shrink), a one-block grid with
+    # k_render (a wave per tile): the images must agree bit for bit
     g = loop.g
     w = loop.w
     v = torch.empty(1, w.model.n_verts, 3, device=DEV)
