@@ -302,7 +302,11 @@ void hr_graph_destroy(hr_graph* graph);
    grids that walk the wave-tile list; their block counts change speed only:
    images are identical for any choice (each pixel sums its samples in a fixed
    order), gradients agree up to the order of floating-point atomic sums.
-   hr_set_grid sets them (0 keeps a value; values are capped at one block per
+   Scenes whose views hold at most one wave tile per SIMD of the device (4
+   per compute unit) render, with a grid of two blocks or more, with the
+   four waves of a block sharing each tile (each walks a quarter of the
+   tile's screen-bin list) and smaller edge-sample packets: the same images
+   and hits, fewer idle SIMDs.  hr_set_grid sets them (0 keeps a value; values are capped at one block per
    four wave tiles of the views), hr_get_grid reads them.  hr_tune times
    candidates on `state`'s buffers (it runs skin, render, loss and the
    interior adjoint `reps` times per candidate, overwriting verts, image,
