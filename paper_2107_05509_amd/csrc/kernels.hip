@@ -1227,9 +1227,11 @@ __global__ void __launch_bounds__(256) k_loss_grad(LossArgs a)
 // interior adjoint
 // ===========================================================================
 
+constexpr int kStageW = 11;   // staged scatter of one sample's colour-map footprint: 4 texels, 4 weights, RGB
+
 // Interior adjoint over the listed wave tiles; block `bid` of `nb`.
 template <bool COUNT>
-__device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack, float* patch_base)
+__device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack, float* patch_base, float* stage)
 {
     const uint64_t iter = iteration(a.iter_dev, a.iter);
     // this wave's four row windows, zero between uses (the flush clears what it reads)
@@ -1465,13 +1467,43 @@ __device__ void adjoint_tiles(const AdjointArgs& a, int bid, int nb, int* stack,
                 }
             }
             wave_lds_sync();
-            if (tmask) {
+            // Footprints that did not fit their row's window (minified maps:
+            // a few spp per pixel spread over many texels): a sample's twelve
+            // values are two texel rows of two texels x RGB, six consecutive
+            // floats when the columns are adjacent.  Staged in LDS, they are
+            // scattered six lanes to a texel row, so that each atomic
+            // instruction's lanes fall on a few cache lines (a lane per
+            // sample puts each of twelve instructions on up to 64 lines).
+            const uint64_t smask = __ballot(tmask != 0);
+            if (smask) {
+                float* st = stage + (threadIdx.x >> 6) * (64 * kStageW);
+                if (tmask) {
+                    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(smask >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)smask, 0u));
+                    float* e = st + rank * kStageW;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int ix = k == 0 ? tidx[0] : k == 1 ? tidx[1] : k == 2 ? tidx[2] : tidx[3];
-                    const float wk = k == 0 ? twt[0] : k == 1 ? twt[1] : k == 2 ? twt[2] : twt[3];
-                    for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(gtex + 3 * ix + ch, g[ch] * wk);
+                    for (int k = 0; k < 4; ++k) {
+                        e[k] = __int_as_float(tidx[k]);
+                        e[4 + k] = twt[k];
+                    }
+                    e[8] = g[0];
+                    e[9] = g[1];
+                    e[10] = g[2];
                 }
+                wave_lds_sync();
+                const int njobs = 2 * __popcll(smask);   // (sample, texel row)
+                const int jq = lane / 6, el = lane - 6 * jq;
+                const int k_el = el >= 3 ? 1 : 0, ch = el - 3 * k_el;
+                for (int q0 = 0; q0 < njobs; q0 += 10) {
+                    const int q = q0 + jq;
+                    if (jq < 10 && q < njobs) {
+                        const float* e = st + (q >> 1) * kStageW;
+                        const int k = 2 * (q & 1) + k_el;
+                        const float x = e[8 + ch] * e[4 + k];
+                        if (x != 0.0f) unsafeAtomicAdd(gtex + 3 * (size_t)__float_as_int(e[k]) + ch, x);
+                    }
+                }
+                wave_lds_sync();   // the stage is written again by the next round
             }
         }
     }
@@ -2023,6 +2055,7 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
 {
     // adjoint blocks: the texel windows of their waves
     __shared__ __align__(16) int lds[kWaveWin * (kThreads / 64)];
+    __shared__ float stage[64 * kStageW * (kThreads / 64)];   // adjoint blocks: staged texel scatters
     __shared__ int wstack[kMaxStack * (kThreads / 64)];
     if ((int)blockIdx.x < n_edge) {
         edge_samples<COUNT, kEdgeWeigh>(e, ((long long)blockIdx.x * kThreads + threadIdx.x) >> 1,
@@ -2035,7 +2068,7 @@ __global__ void __launch_bounds__(kThreads) k_backward_trace(AdjointArgs a, Edge
         loss_partial(l, (int)blockIdx.x - n_edge - n_adj);
         return;
     }
-    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, n_adj, wstack, reinterpret_cast<float*>(lds));
+    adjoint_tiles<COUNT>(a, (int)blockIdx.x - n_edge, n_adj, wstack, reinterpret_cast<float*>(lds), stage);
 }
 
 // ===========================================================================
