@@ -123,7 +123,8 @@ def test_interior_adjoint_texture_windows(spp, tex):
     # the colour-map gradient goes through per-row texel windows: rows of one
     # pixel (16 spp and more) sum one weight per texel, rows of several pixels
     # (4 spp) sum RGB; a 1024x1024 map seen in 64x64 views has pixel
-    # footprints wider than a window, which scatter directly
+    # footprints wider than a window, which go through the staged scatter
+    # (each sample's footprint in LDS, six lanes per texel row)
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     print(f"case: tiny workload (2 views), {spp} spp, albedo {tex}x{tex}", flush=True)
