@@ -575,6 +575,21 @@ def dense_iteration(args):
     return out
 
 
+def bench_dense(args):
+    """The dense workload alone (1 hand, 40 views 334x512, 4 spp, 1024x1024
+    colour map): one JSON line with its iteration time."""
+    print("[bench] workload: dense, 40 views 334x512, 4 spp", file=sys.stderr, flush=True)
+    d = dense_iteration(args)
+    ms = d["ms_per_iteration"]
+    out = {"metric": "dense: fwd+bwd refine iterations/s (40 views 334x512, 4 spp, 1024x1024 albedo)",
+           "value": d["refine_iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": d["steps"], "warmup": 50,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic", "config": {"workload": d["workload"], "views": 40, "spp": 4,
+                                           "camera_samples_per_step": d["camera_samples_per_step"]},
+           "camera_msamples_per_s": d["camera_msamples_per_s"], "launch_grids": d["launch_grids"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -593,13 +608,13 @@ def main():
     ap.add_argument("--no-dense", action="store_true",
                     help="skip the dense-workload iteration time (40 views, 4 spp, 1024x1024 albedo)")
     ap.add_argument("--workload",
-                    choices=("realistic", "batched", "proposal", "coverage", "full", "raster", "adam", "tiny"),
+                    choices=("realistic", "batched", "proposal", "coverage", "full", "raster", "adam", "tiny", "dense"),
                     default="realistic",
                     help="batched: 64 hands, 4-40 views each at 128x128/256x256/334x512, 8 spp "
                          "(per-iteration latency percentiles; not the headline metric)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the workload would shard by hand or by view, one all-reduce of the gradients per iteration)", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
@@ -620,6 +635,8 @@ def main():
         return bench_adam(args)
     if args.workload == "tiny":
         return bench_tiny(args)
+    if args.workload == "dense":
+        return bench_dense(args)
     w = scene.workload_realistic(args.seed)
     print(f"[bench] workload: {w.name}, {w.n_pixels} pixels", file=sys.stderr, flush=True)
     ref = make_refiner(w, seed=args.seed, tune=not (args.no_tune or args.grids))
